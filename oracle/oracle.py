@@ -1,0 +1,314 @@
+"""Python driver for the FP64 CPU oracle (megs_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline use it; the renderer never does. It imports nothing from the renderer
+package; its inputs are the seeded scenes (as float64 planes holding the exact
+stored values) and cameras.
+
+The C file does the arithmetic; this module builds and loads it, marshals
+arrays, and composes the per-view steps into a whole multi-view render and its
+gradient, plus a central finite-difference harness.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "megs_oracle.c")
+LIB = os.path.join(HERE, "libmegs_oracle.so")
+
+PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
+          "base", "axis", "sharp", "amp", "lmask_logit")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class OScene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("pad", ctypes.c_int32)] + \
+               [(p, _dp) for p in PLANES]
+
+
+class OCam(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3),
+                ("znear", ctypes.c_double), ("bg", ctypes.c_double * 3)]
+
+
+class OGrad(ctypes.Structure):
+    _fields_ = [(p, _dp) for p in PLANES]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-std=c11", "-Wall", "-shared", "-fPIC", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        vp = ctypes.c_void_p
+        L.oracle_project.argtypes = [ctypes.POINTER(OScene), ctypes.POINTER(OCam), ctypes.c_int32, vp, vp]
+        L.oracle_sg_color.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+        L.oracle_sg_color_many.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_int64, vp, vp]
+        L.oracle_pairs.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                   ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
+        L.oracle_pairs.restype = ctypes.c_int64
+        L.oracle_blend.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                   vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.oracle_blend.restype = ctypes.c_int64
+        L.oracle_bruteforce.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64, vp,
+                                        vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.oracle_blend_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                            vp, vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp,
+                                            ctypes.c_int32, vp]
+        L.oracle_project_backward.argtypes = [ctypes.POINTER(OScene), ctypes.POINTER(OCam), ctypes.c_int32,
+                                              vp, ctypes.POINTER(OGrad)]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_oscene(planes: dict, k: int):
+    """planes: float64 arrays (exact stored values). Returns (struct, keepalive)."""
+    keep = {p: _c64(planes.get(p)) for p in PLANES}
+    n = keep["op_logit"].shape[0]
+    s = OScene(n=n, k=k, pad=0)
+    for p in PLANES:
+        setattr(s, p, None if keep[p] is None else keep[p].ctypes.data_as(_dp))
+    return s, keep
+
+
+def make_ocam(cam) -> OCam:
+    c = OCam()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = np.asarray(cam.R, np.float64).reshape(9)
+    for i in range(9):
+        c.R[i] = R[i]
+    for i in range(3):
+        c.t[i] = float(np.asarray(cam.t, np.float64)[i])
+        c.bg[i] = float(cam.bg[i])
+    c.znear = float(cam.znear)
+    return c
+
+
+def project(planes: dict, k: int, cam, tile: int) -> dict:
+    """FP64 records of all Gaussians in one view."""
+    s, keep = make_oscene(planes, k)
+    n = s.n
+    f = np.zeros((n, 10), np.float64)
+    i = np.zeros((n, 7), np.int32)
+    c = make_ocam(cam)
+    lib().oracle_project(ctypes.byref(s), ctypes.byref(c), tile, _ptr(f), _ptr(i))
+    return {"u": f[:, 0].copy(), "v": f[:, 1].copy(), "depth": f[:, 2].copy(),
+            "conic": f[:, 3:6].copy(), "o": f[:, 6].copy(), "rgb": f[:, 7:10].copy(),
+            "valid": i[:, 0].copy(), "radius": i[:, 1].copy(), "rect": i[:, 2:6].copy(),
+            "ntiles": i[:, 6].copy()}
+
+
+def sg_color(base, axis, sharp, amp, direction, mask=None) -> np.ndarray:
+    base = _c64(base); axis = _c64(axis); sharp = _c64(sharp); amp = _c64(amp)
+    direction = _c64(direction)
+    mask = _c64(mask)
+    out = np.zeros(3, np.float64)
+    lib().oracle_sg_color(len(sharp), _ptr(base), _ptr(axis), _ptr(sharp), _ptr(amp), _ptr(mask),
+                          _ptr(direction), _ptr(out))
+    return out
+
+
+def sg_color_many(base, axis, sharp, amp, directions, mask=None) -> np.ndarray:
+    """SG colour for many directions [m][3] -> [m][3]."""
+    base = _c64(base); axis = _c64(axis); sharp = _c64(sharp); amp = _c64(amp)
+    d = _c64(directions)
+    mask = _c64(mask)
+    out = np.zeros((len(d), 3), np.float64)
+    lib().oracle_sg_color_many(len(sharp), _ptr(base), _ptr(axis), _ptr(sharp), _ptr(amp), _ptr(mask),
+                               len(d), _ptr(d), _ptr(out))
+    return out
+
+
+def tile_layout(cams: Sequence, tile: int):
+    """Per-view tile counts and the global tile offset of each view."""
+    counts = [((c.width + tile - 1) // tile) * ((c.height + tile - 1) // tile) for c in cams]
+    off = np.zeros(len(cams) + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    return off
+
+
+def pairs(u, v, depth_f32, radius, valid, rec_view, cams, tile: int):
+    """Sorted key table over records of several views.
+
+    u, v: float64 means; depth_f32: float32 depths; radius, valid, rec_view: int32.
+    Returns keys (uint64), vals (uint32), ranges ([T][2] uint32), tile offsets.
+    """
+    u = _c64(u); v = _c64(v)
+    d = np.ascontiguousarray(depth_f32, np.float32)
+    r = np.ascontiguousarray(radius, np.int32)
+    va = np.ascontiguousarray(valid, np.int32)
+    rv = np.ascontiguousarray(rec_view, np.int32)
+    w = np.array([c.width for c in cams], np.int32)
+    h = np.array([c.height for c in cams], np.int32)
+    off = tile_layout(cams, tile)
+    total = int(off[-1])
+    L = lib()
+    n = len(u)
+    cnt = L.oracle_pairs(n, _ptr(u), _ptr(v), _ptr(d), _ptr(r), _ptr(va), _ptr(rv), _ptr(w), _ptr(h),
+                         _ptr(off), tile, total, None, None, None)
+    keys = np.zeros(max(cnt, 1), np.uint64)
+    vals = np.zeros(max(cnt, 1), np.uint32)
+    ranges = np.zeros((total, 2), np.uint32)
+    L.oracle_pairs(n, _ptr(u), _ptr(v), _ptr(d), _ptr(r), _ptr(va), _ptr(rv), _ptr(w), _ptr(h),
+                   _ptr(off), tile, total, _ptr(keys), _ptr(vals), _ptr(ranges))
+    return keys[:cnt], vals[:cnt], ranges, off
+
+
+def _recs(rec):
+    return (_c64(rec["u"]), _c64(rec["v"]), _c64(rec["conic"]), _c64(rec["o"]), _c64(rec["rgb"]))
+
+
+def blend(cam, tile: int, rec: dict, vals, ranges_view):
+    """Tiled forward blend of one view. ranges_view: the view's [T_v][2] slice."""
+    u, v, conic, o, rgb = _recs(rec)
+    w, h = cam.width, cam.height
+    bg = np.asarray(cam.bg, np.float64)
+    image = np.zeros((3, h, w), np.float64)
+    T = np.zeros((h, w), np.float64)
+    last = np.zeros((h, w), np.int32)
+    flag = np.zeros((h, w), np.int32)
+    sig = np.zeros((h, w), np.int64)
+    vals = np.ascontiguousarray(vals, np.uint32)
+    rv = np.ascontiguousarray(ranges_view, np.uint32)
+    nfrag = lib().oracle_blend(w, h, tile, _ptr(bg), _ptr(u), _ptr(v), _ptr(conic), _ptr(o), _ptr(rgb),
+                               _ptr(vals), _ptr(rv), _ptr(image), _ptr(T), _ptr(last), _ptr(flag), _ptr(sig))
+    return {"image": image, "T": T, "last": last, "flag": flag, "sig": sig, "nfrag": int(nfrag)}
+
+
+def bruteforce(cam, rec: dict, valid):
+    u, v, conic, o, rgb = _recs(rec)
+    depth = _c64(rec["depth"])
+    va = np.ascontiguousarray(valid, np.int32)
+    w, h = cam.width, cam.height
+    bg = np.asarray(cam.bg, np.float64)
+    image = np.zeros((3, h, w), np.float64)
+    T = np.zeros((h, w), np.float64)
+    last = np.zeros((h, w), np.int32)
+    flag = np.zeros((h, w), np.int32)
+    lib().oracle_bruteforce(w, h, _ptr(bg), len(u), _ptr(va), _ptr(depth), _ptr(u), _ptr(v), _ptr(conic),
+                            _ptr(o), _ptr(rgb), _ptr(image), _ptr(T), _ptr(last), _ptr(flag))
+    return {"image": image, "T": T, "last": last, "flag": flag}
+
+
+def blend_backward(cam, tile: int, rec: dict, vals, ranges_view, dl, direct: bool = False, grad2d=None):
+    """Per-record 2D gradients [n][9] for one view (added into grad2d if given)."""
+    u, v, conic, o, rgb = _recs(rec)
+    n = len(u)
+    if grad2d is None:
+        grad2d = np.zeros((n, 9), np.float64)
+    bg = np.asarray(cam.bg, np.float64)
+    vals = np.ascontiguousarray(vals, np.uint32)
+    rv = np.ascontiguousarray(ranges_view, np.uint32)
+    dl = _c64(dl)
+    lib().oracle_blend_backward(cam.width, cam.height, tile, _ptr(bg), _ptr(u), _ptr(v), _ptr(conic), _ptr(o),
+                                _ptr(rgb), _ptr(vals), _ptr(rv), len(vals), _ptr(dl), int(direct), _ptr(grad2d))
+    return grad2d
+
+
+def zero_grads(planes: dict) -> dict:
+    return {p: (None if planes.get(p) is None else np.zeros_like(_c64(planes[p]))) for p in PLANES}
+
+
+def project_backward(planes: dict, k: int, cam, tile: int, grad2d, grads: dict):
+    """Adds one view's raw-parameter gradients into grads (float64 planes)."""
+    s, keep = make_oscene(planes, k)
+    g = OGrad()
+    for p in PLANES:
+        setattr(g, p, None if grads[p] is None else grads[p].ctypes.data_as(_dp))
+    c = make_ocam(cam)
+    g2 = _c64(grad2d)
+    lib().oracle_project_backward(ctypes.byref(s), ctypes.byref(c), tile, _ptr(g2), ctypes.byref(g))
+    return grads
+
+
+def render(planes: dict, k: int, cams: Sequence, tile: int) -> dict:
+    """Whole FP64 multi-view forward: per-view records, key table, blend."""
+    n = len(planes["op_logit"])
+    recs = [project(planes, k, c, tile) for c in cams]
+    cat = lambda key: np.concatenate([r[key] for r in recs])
+    rec_all = {key: cat(key) for key in ("u", "v", "depth", "conic", "o", "rgb", "valid", "radius", "ntiles")}
+    rec_view = np.repeat(np.arange(len(cams), dtype=np.int32), n)
+    keys, vals, ranges, off = pairs(rec_all["u"], rec_all["v"], rec_all["depth"].astype(np.float32),
+                                    rec_all["radius"], rec_all["valid"], rec_view, cams, tile)
+    views = []
+    for vi, c in enumerate(cams):
+        views.append(blend(c, tile, rec_all, vals, ranges[off[vi]:off[vi + 1]]))
+    return {"records": rec_all, "per_view_records": recs, "keys": keys, "vals": vals, "ranges": ranges,
+            "tile_off": off, "views": views, "images": [vw["image"] for vw in views]}
+
+
+def render_backward(planes: dict, k: int, cams: Sequence, tile: int, dl_images: Sequence, fwd: dict = None):
+    """Gradients of L = sum(dl_images[v] * image_v) with respect to every raw plane."""
+    if fwd is None:
+        fwd = render(planes, k, cams, tile)
+    n = len(planes["op_logit"])
+    grads = zero_grads(planes)
+    grad2d = np.zeros((n * len(cams), 9), np.float64)
+    off = fwd["tile_off"]
+    for vi, c in enumerate(cams):
+        blend_backward(c, tile, fwd["records"], fwd["vals"], fwd["ranges"][off[vi]:off[vi + 1]],
+                       dl_images[vi], grad2d=grad2d)
+    for vi, c in enumerate(cams):
+        project_backward(planes, k, c, tile, grad2d[vi * n:(vi + 1) * n], grads)
+    return grads, grad2d
+
+
+def loss(planes: dict, k: int, cams, tile: int, weights) -> tuple:
+    fwd = render(planes, k, cams, tile)
+    L = sum(float(np.sum(w.astype(np.float64) * img)) for w, img in zip(weights, fwd["images"]))
+    sig = tuple(np.concatenate([vw["sig"].ravel() for vw in fwd["views"]]).tolist())
+    return L, hash(sig)
+
+
+def fd_gradient(planes: dict, k: int, cams, tile: int, weights, plane: str, flat_indices, rel_h: float = 1e-6):
+    """Central differences of L for chosen entries of one plane.
+
+    Returns (fd values, mask of entries whose +-h perturbation kept every per-pixel
+    decision -- the included fragment set and clamp states -- unchanged)."""
+    _, sig0 = loss(planes, k, cams, tile, weights)
+    out = np.zeros(len(flat_indices))
+    ok = np.ones(len(flat_indices), bool)
+    for j, fi in enumerate(flat_indices):
+        base = {p: (None if planes.get(p) is None else np.array(planes[p], np.float64, copy=True)) for p in PLANES}
+        arr = base[plane].reshape(-1)
+        x0 = arr[fi]
+        h = rel_h * max(1.0, abs(x0))
+        arr[fi] = x0 + h
+        Lp, sp = loss(base, k, cams, tile, weights)
+        arr[fi] = x0 - h
+        Lm, sm = loss(base, k, cams, tile, weights)
+        out[j] = (Lp - Lm) / (2 * h)
+        ok[j] = (sp == sig0) and (sm == sig0)
+    return out, ok
