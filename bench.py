@@ -1,0 +1,305 @@
+#!/usr/bin/env python3
+"""Forward+backward throughput (Mpixel/s) and peak VRAM of the SG-splatting renderer on one MI355X.
+
+Workload (synthetic, seeded): 1M clustered Gaussians with 4 SG lobes and soft primitive/lobe
+masks. Two forms are measured:
+  * headline `value`: parameters stored in FP16 (amplitudes in BF16), 8 views at 1920x1080 on a
+    ring of radius 6, forward+backward of all views captured once in a hipGraph and replayed;
+  * `plain_fp32`: the same scene in FP32, one 1920x1080 view, eager launches.
+A step is one whole forward+backward of the workload's views. Inputs are resident in HBM before
+the timed region. Each stage's kernels are also timed live with HIP events (eager calls of the
+same workload); the slowest stage gives the roofline line. The FP64 CPU oracle is timed on a
+bounded tile sample of the plain view.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (packed); the unpacked FMA ceiling is half of it
+
+# Algorithmic FP32 operations per fragment (FMA = 2, add/mul/compare/exp = 1):
+#   alpha test of an evaluated fragment (offsets, quadratic form, exp, opacity, clamp, threshold): 15
+#   forward blend of an included fragment (transmittance, weight, colour accumulate): 10
+#   backward of an included fragment (transmittance recovery, colour/alpha/conic/mean/opacity
+#   gradients, background recursion, summation over pixels): 58
+FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 58
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000, help="Gaussians (default: the 1M workload)")
+    ap.add_argument("--views", type=int, default=8)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--autotune", action="store_true", help="pick tile/batch with the library's autotuner")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=float, default=0.02, help="fraction of tiles the oracle blends")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def fragment_counts(R, ds, cams, cfg):
+    """(blended, evaluated, replayed) fragments of one forward, counted by the stats instance."""
+    import torch
+    from paper_2509_07021_amd import _lib as L
+    c = R.Config(cfg.tile, cfg.batch, cfg.flags | L.MEGS_FLAG_STATS, 0)
+    fr = R.forward(ds, cams, c)
+    torch.cuda.synchronize()
+    st = fr.buffer("device_status", 8, torch.int32).cpu().numpy()
+    blended = int(st[4:6].view("uint64")[0])
+    evaluated = int(st[6:8].view("uint64")[0])
+    replayed = int(fr.buffer("last", fr.state.n_pixels, torch.int32).to(torch.int64).sum().item())
+    return blended, evaluated, replayed, int(fr.state.n_pairs)
+
+
+def stage_bytes(stage, n, nv, pairs, npix, ntiles, geom_bytes, k):
+    """Algorithmic HBM bytes of one launch of an HBM-bound stage."""
+    nr = n * nv
+    rec = 16 + 16 + 16 + 4 + 4 + 4          # mean, conic+o, rgb+depth, radius, ntiles, depth key
+    if stage == "project":
+        return n * geom_bytes + nr * rec
+    if stage == "depth_sort":
+        return 4 * nr * (4 + 8 + 8)         # 4 passes: key read (count), key+value read, write
+    if stage == "scan":
+        return nr * (4 + 4 + 4 + 4)         # ntiles gathered through the order twice, order, offsets
+    if stage == "emit":
+        return nr * (4 + 4 + 16 + 8) + pairs * 8
+    if stage == "pair_sort":
+        passes = 2
+        return passes * pairs * (4 + 8 + 8)
+    if stage == "ranges":
+        return pairs * 4 + ntiles * 8
+    if stage == "project_bwd":
+        return n * geom_bytes + nr * 9 * 4 + n * (14 + 8 * k) * 4
+    return 0
+
+
+def cpu_baseline(scene, cam, tile, frac, seed=11):
+    """The FP64 oracle on the host: full projection, key table and projection backward of the
+    plain view; blend and blend backward on a seeded random sample of tiles. The sampled blend
+    time is scaled by the sampled share of the pair list. Returns a dict for the JSON line."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2509_07021_amd import scenes as S
+    pl = scene.widened()
+    t = {}
+    t0 = time.perf_counter()
+    rec = O.project(pl, scene.k, cam, tile)
+    t["project"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    keys, vals, ranges, off = O.pairs(rec["u"], rec["v"], rec["depth"].astype(np.float32), rec["radius"],
+                                      rec["valid"], np.zeros(scene.n, np.int32), [cam], tile)
+    t["pairs"] = time.perf_counter() - t0
+    rng = np.random.default_rng(seed)
+    ntl = ranges.shape[0]
+    pick = rng.random(ntl) < frac
+    rs = ranges.copy()
+    rs[~pick] = 0
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    share = max(lens[pick].sum() / max(lens.sum(), 1), 1e-9)
+    w = S.loss_weights([cam], seed)[0]
+    t0 = time.perf_counter()
+    O.blend(cam, tile, rec, vals, rs)
+    t["blend_sample"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g2 = O.blend_backward(cam, tile, rec, vals, rs, w)
+    t["blend_bwd_sample"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.project_backward(pl, scene.k, cam, tile, g2, O.zero_grads(pl))
+    t["project_bwd"] = time.perf_counter() - t0
+    est = t["project"] + t["pairs"] + (t["blend_sample"] + t["blend_bwd_sample"]) / share + t["project_bwd"]
+    mpix = cam.width * cam.height / est / 1e6
+    return {"value": round(mpix, 4), "unit": "Mpixel/s", "cores": O.threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle, plain FP32 scene, one {cam.width}x{cam.height} view: full projection, "
+                       f"key table and projection backward; blend and blend backward on {int(pick.sum())} of "
+                       f"{ntl} tiles ({share:.3%} of pairs), scaled by that share; est. {est:.1f} s per step"),
+            "seconds": {k: round(v, 3) for k, v in t.items()}}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU design is view sharding with one gradient all-reduce, not built).",
+              file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    from paper_2509_07021_amd import _lib as L
+    from paper_2509_07021_amd import render as R
+    from paper_2509_07021_amd import scenes as S
+
+    torch.cuda.set_device(0)
+    t_start = time.perf_counter()
+    scene, cams1 = S.make_workload("masked_1m_1080p", n=args.n)
+    scene16 = scene.stored("f16", "f16", "bf16")
+    cams8 = S.ring_cameras(args.views, seed=5)
+    log(f"scenes ready in {time.perf_counter() - t_start:.1f}s: n={scene.n} k={scene.k}")
+    cfg = R.Config(args.tile, args.batch)
+
+    # ---------------------------------------------------------------- plain FP32, 1 view
+    ds = R.DeviceScene.from_scene(scene)
+    npix1 = sum(c.width * c.height for c in cams1)
+    dl1 = torch.randn(3 * npix1, device="cuda")
+    if args.autotune:
+        cfg, table = R.autotune(ds, cams1, R.Config(16, 64), reps=2, dl_images=dl1)
+        log(f"autotune: tile {cfg.tile} batch {cfg.batch}; ms table (tile x batch):\n{table}")
+    stream = torch.cuda.current_stream()
+
+    def step_plain():
+        fr = R.forward(ds, cams1, cfg)
+        R.backward(ds, fr, dl1)
+
+    torch.cuda.synchronize()
+    base_alloc = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    fr = R.forward(ds, cams1, cfg)
+    torch.cuda.synchronize()
+    plain_fwd_peak = torch.cuda.max_memory_allocated()
+    R.backward(ds, fr, dl1)
+    torch.cuda.synchronize()
+    plain_fb_peak = torch.cuda.max_memory_allocated()
+    plain_pairs = int(fr.state.n_pairs)
+    del fr
+    ms_plain = timed(step_plain, args.steps, args.warmup, stream)
+    log(f"plain fp32: {ms_plain:.3f} ms/step, {npix1 / ms_plain / 1e3:.1f} Mpixel/s, pairs {plain_pairs}")
+
+    # ---------------------------------------------------------------- FP16 batched graph, 8 views
+    del ds
+    torch.cuda.empty_cache()
+    ds16 = R.DeviceScene.from_scene(scene16)
+    static16 = ds16.static_bytes()
+    npix8 = sum(c.width * c.height for c in cams8)
+    dl8 = torch.randn(3 * npix8, device="cuda")
+    fr = R.forward(ds16, cams8, cfg)
+    torch.cuda.synchronize()
+    pairs8 = int(fr.state.n_pairs)
+    del fr
+    torch.cuda.empty_cache()
+    cap = int(pairs8 * 1.02) + 4096
+    gcfg = R.Config(cfg.tile, cfg.batch, cfg.flags, cap)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    gf = R.Graph(ds16, cams8, gcfg, with_backward=False)
+    gf.launch()
+    torch.cuda.synchronize()
+    batched_fwd_peak = torch.cuda.max_memory_allocated()
+    gf.close()
+    del gf
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    g = R.Graph(ds16, cams8, gcfg, with_backward=True, dl_images=dl8)
+    g.launch()
+    torch.cuda.synchronize()
+    batched_fb_peak = torch.cuda.max_memory_allocated()
+    counted = g.status()
+    ms_batched = timed(g.launch, args.steps, args.warmup, g.stream)
+    counted_after = g.status()
+    assert counted == counted_after == pairs8, (counted, counted_after, pairs8)
+    mpix_batched = npix8 / ms_batched / 1e3
+    log(f"fp16 batched graph: {ms_batched:.3f} ms/step, {mpix_batched:.1f} Mpixel/s, pairs {pairs8}")
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- per-stage timing, same workload
+    prof_steps = max(2, min(args.steps, 5))
+    dl8b = dl8
+    for _ in range(2):
+        R.backward(ds16, R.forward(ds16, cams8, cfg), dl8b)
+    torch.cuda.synchronize()
+    with R.Profile() as prof:
+        for _ in range(prof_steps):
+            R.backward(ds16, R.forward(ds16, cams8, cfg), dl8b)
+    stage_ms = {s: prof.ms[s] / max(prof.count[s], 1) for s in L.STAGES if prof.count[s]}
+    blended, evaluated, replayed, _ = fragment_counts(R, ds16, cams8, cfg)
+    dominant = max(stage_ms, key=stage_ms.get)
+    nt8 = sum(((c.width + cfg.tile - 1) // cfg.tile) * ((c.height + cfg.tile - 1) // cfg.tile) for c in cams8)
+    geom_bytes = static16 // scene.n
+    if dominant in ("blend_fwd", "blend_bwd"):
+        flops = (FLOP_TEST * evaluated + FLOP_FWD_BLEND * blended if dominant == "blend_fwd"
+                 else FLOP_TEST * replayed + FLOP_BWD_BLEND * blended)
+        achieved = flops / (stage_ms[dominant] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "units_per_launch": {"blended": blended, "evaluated": evaluated, "replayed": replayed},
+                "avg_ms": round(stage_ms[dominant], 4)}
+    else:
+        by = stage_bytes(dominant, scene.n, len(cams8), pairs8, npix8, nt8, geom_bytes, scene.k)
+        achieved = by / (stage_ms[dominant] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "avg_ms": round(stage_ms[dominant], 4)}
+    log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+
+    out = {
+        "metric": "fwd+bwd Mpixel/s at 1M Gaussians 1080p, peak VRAM; FP16-batched vs FP32 plain",
+        "value": round(mpix_batched, 2),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"{scene.n} clustered Gaussians, {scene.k} SG lobes, soft masks, FP16 storage "
+                                f"(BF16 amplitudes), {len(cams8)} views 1920x1080, forward+backward in one hipGraph"),
+                   "gaussians": scene.n, "views": len(cams8), "resolution": "1920x1080", "tile": cfg.tile,
+                   "batch": cfg.batch, "storage": "f16/f16/bf16", "pairs": pairs8},
+        "peak_vram_mb": {"forward": round(batched_fwd_peak / 1e6, 1), "forward_backward": round(batched_fb_peak / 1e6, 1),
+                         "static_params": round(static16 / 1e6, 1)},
+        "plain_fp32": {"value": round(npix1 / ms_plain / 1e3, 2), "unit": "Mpixel/s", "ms_per_step": round(ms_plain, 4),
+                       "workload": f"{scene.n} clustered Gaussians, FP32, 1 view 1920x1080, eager",
+                       "pairs": plain_pairs,
+                       "peak_vram_mb": {"forward": round((plain_fwd_peak) / 1e6, 1),
+                                        "forward_backward": round(plain_fb_peak / 1e6, 1),
+                                        "static_params": round(scene.n * (14 + 8 * scene.k + 1) * 4 / 1e6, 1),
+                                        "resident_before": round(base_alloc / 1e6, 1)}},
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(scene, cams1[0], cfg.tile, args.cpu_sample)
+        log(f"cpu baseline in {time.perf_counter() - t0:.1f}s")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

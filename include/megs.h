@@ -1,0 +1,238 @@
+/*
+ * megs.h -- C ABI of libmegs.so, the MI355X (gfx950) differentiable SG-splatting renderer.
+ *
+ * What the library computes (MEGS^2, arXiv 2509.07021):
+ *   - colour per Gaussian and view from arbitrarily oriented Spherical-Gaussian lobes,
+ *     c(d) = c0 + sum_k m_k a_k exp(lambda_k (mu_k . d - 1)) (Sec. 3.2, the SG lobe and colour
+ *     equations), each lobe gated by a soft mask m_k = sigmoid(lobe mask logit);
+ *   - front-to-back alpha compositing C = sum_i c_i alpha_i prod_{j<i}(1 - alpha_j), alpha_i the
+ *     opacity (gated by a soft primitive mask) times the projected 2D Gaussian (Sec. 3.1);
+ *   - the tile/depth key table of the tile rasteriser the paper builds on (Sec. 1, and the
+ *     Appendix's evaluation details, which count it in the dynamic rendering memory);
+ *   - the exact gradient of the images with respect to every raw parameter.
+ *
+ * Conventions (the paper prints none of them; they follow the 3DGS rasteriser it builds on):
+ *   OpenCV camera axes (x right, y down, z forward), x_cam = R x_world + t; pixel (i, j) has
+ *   its centre at (i + 0.5, j + 0.5); EWA projection with a 0.3 px^2 dilation; alpha clamped
+ *   to 0.99; fragments with alpha < 1/255 skipped; a pixel stops before its transmittance
+ *   would drop below 1e-4 (that fragment is not blended); near plane from the camera; the
+ *   Jacobian is evaluated at the direction clamped to 1.3x the half field of view; the
+ *   footprint radius is ceil(sqrt(2 ln(255 o) lambda_max)) so that every pixel with
+ *   alpha >= 1/255 lies inside the tile rectangle; depth ties are ordered by record index.
+ *   Quaternions are (w, x, y, z) and normalised in the forward pass, lobe axes likewise;
+ *   scales are exp(log-scale), opacity and masks are sigmoid(logit), sharpness is used as
+ *   stored. Colours are not clamped.
+ *
+ * Memory: every device buffer belongs to the caller. The library never calls hipMalloc:
+ * it asks the caller's allocation callback for its working memory and never frees it.
+ * All work is enqueued on the caller's stream (a hipStream_t passed as void*).
+ *
+ * Errors: every entry point returns a megs_status and never throws. Arguments are checked
+ * before the first launch; megs_last_error() describes the last failure on the calling
+ * thread.
+ */
+#ifndef MEGS_H
+#define MEGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MEGS_OK = 0,
+    MEGS_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, bad dtype, ...) */
+    MEGS_ERR_HIP = -2,         /* a HIP runtime call failed */
+    MEGS_ERR_CAPACITY = -3,    /* the pair table overflowed its fixed capacity (graph mode) */
+    MEGS_ERR_UNSUPPORTED = -4, /* a configuration the library does not implement */
+    MEGS_ERR_ALLOC = -5        /* the allocation callback returned NULL */
+} megs_status;
+
+typedef enum { MEGS_F32 = 0, MEGS_F16 = 1, MEGS_BF16 = 2 } megs_dtype;
+
+#define MEGS_MAX_LOBES 8
+#define MEGS_MAX_VIEWS 64
+
+/*
+ * Scene parameters: structure-of-arrays planes in device memory, plane row r of Gaussian i
+ * at element r * n + i. Storage dtype per group: dt_geom for pos, logscale, quat, op_logit,
+ * pmask_logit; dt_color for base, axis, sharp, lmask_logit; dt_amp for amp. All arithmetic is
+ * FP32 (the camera-space mean and pixel mean in FP64); reduced-precision planes are widened in
+ * registers, never copied.
+ *   pos[3][n], logscale[3][n], quat[4][n] (w, x, y, z), op_logit[n],
+ *   pmask_logit[n]      (NULL: no primitive mask, m = 1),
+ *   base[3][n], axis[k][3][n], sharp[k][n], amp[k][3][n],
+ *   lmask_logit[k][n]   (NULL: no lobe masks, m_k = 1).
+ * 0 <= k <= MEGS_MAX_LOBES; 0 <= n; n * n_views < 2^31.
+ */
+typedef struct {
+    int64_t n;
+    int32_t k;
+    int32_t dt_geom, dt_color, dt_amp;
+    int32_t reserved;
+    const void *pos, *logscale, *quat, *op_logit, *pmask_logit;
+    const void *base, *axis, *sharp, *amp, *lmask_logit;
+} megs_scene;
+
+/* FP32 gradient planes with the shapes of megs_scene's planes; overwritten by the backward.
+ * pmask_logit / lmask_logit may be NULL (and must be when the scene has no masks). */
+typedef struct {
+    float *pos, *logscale, *quat, *op_logit, *pmask_logit;
+    float *base, *axis, *sharp, *amp, *lmask_logit;
+} megs_scene_grad;
+
+/* One pinhole view (host memory). R row-major world->camera, x_cam = R x + t. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float znear;
+    float bg[3];
+} megs_camera;
+
+#define MEGS_FLAG_ONE_STAGE_SORT 1u /* sort 64-bit tile|depth keys in one radix sort instead of
+                                       a depth pre-sort followed by a tile-only pair sort */
+#define MEGS_FLAG_PERSISTENT 2u     /* blend kernels pull (view, tile) work items from a queue */
+#define MEGS_FLAG_STATS 4u          /* forward also counts blended and evaluated fragments into
+                                       device_status (a separate kernel instance; measurement only) */
+
+typedef struct {
+    int32_t tile;          /* tile edge in pixels: 8, 16 or 32 */
+    int32_t batch;         /* records staged in LDS per batch: 64, 128 or 256 */
+    uint32_t flags;        /* MEGS_FLAG_* */
+    int32_t reserved;
+    int64_t pair_capacity; /* 0: size the pair table from the counted pairs (one host sync per
+                              forward); > 0: fixed capacity, no host sync, overflow reported
+                              as MEGS_ERR_CAPACITY by megs_state_status */
+} megs_config;
+
+/* Allocation callback: returns device memory of at least `bytes` bytes, 256-byte aligned,
+ * owned by the caller and valid until the caller drops it (the library never frees). */
+typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
+
+/*
+ * Forward state: filled by megs_render_forward, read by megs_render_backward. Every pointer is
+ * device memory obtained from the allocation callback. Layouts (NR = n * n_views records,
+ * record r = view * n + gaussian; P = pairs; T = tiles over all views; NP = pixels over all views):
+ *   mean      double[NR][2]  pixel-space mean (u, v)
+ *   conic_o   float[NR][4]   conic (a, b, c) of q = -(a dx^2 + c dy^2)/2 - b dx dy, and o_eff
+ *   rgbd      float[NR][4]   SG colour (r, g, b) and camera depth z
+ *   radius    int32[NR]      footprint radius in pixels, -1 when culled
+ *   ntiles    uint32[NR]     tiles covered by the record's rectangle
+ *   tile_keys uint32[P]      sorted global tile ids (two-stage sort) or NULL
+ *   keys64    uint64[P]      sorted tile<<32|depth keys (one-stage sort) or NULL
+ *   vals      uint32[P]      sorted record indices
+ *   ranges    uint32[T][2]   [start, end) of each tile in vals; (0, 0) when empty
+ *   T_final   float[NP]      final transmittance per pixel
+ *   last      uint32[NP]     1 + position (within its tile's list) of the last blended fragment
+ *   device_status int32[8]   [0] pairs counted, [1] overflow flag, [2..3] reserved,
+ *                            [4..5] uint64 blended fragments, [6..7] uint64 evaluated fragments
+ *                            (written only with MEGS_FLAG_STATS)
+ */
+typedef struct {
+    int64_t n_records, n_pairs, pair_capacity, n_pixels;
+    int32_t n_views, tile, n_tiles, k;
+    const void *mean, *conic_o, *rgbd, *radius, *ntiles;
+    const void *tile_keys, *keys64, *vals, *ranges, *T_final, *last, *device_status;
+    void *internal; /* library bookkeeping inside the caller's memory */
+} megs_state;
+
+/* Per-view image layout: images are concatenated, view v's float[3][H][W] planes starting at
+ * float offset 3 * sum_{u<v} W_u H_u. */
+
+/*
+ * Forward render of n_views views (front-to-back compositing, Sec. 3.1; SG colour, Sec. 3.2).
+ * images: device float[3 * NP], written. state: host struct, filled. Returns MEGS_OK or an
+ * error status; with pair_capacity == 0 it synchronises the stream once to size the pair table.
+ */
+megs_status megs_render_forward(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
+                                const megs_config *cfg, megs_alloc_fn alloc, void *alloc_ctx,
+                                float *images, megs_state *state, void *stream);
+
+/*
+ * Backward: gradients of L with respect to every raw parameter plane, given dL/dimage
+ * (dl_dimages, device float[3 * NP] in the image layout), summed over views. The blend is
+ * replayed back to front from the stored final transmittance and last index; no per-fragment
+ * state is kept. grads planes are overwritten. Scratch comes from alloc.
+ */
+megs_status megs_render_backward(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
+                                 const megs_config *cfg, const megs_state *state,
+                                 const float *dl_dimages, megs_alloc_fn alloc, void *alloc_ctx,
+                                 megs_scene_grad *grads, void *stream);
+
+/* Reads state->device_status (synchronises the stream). Returns MEGS_ERR_CAPACITY when the
+ * pair table overflowed; *pairs_needed receives the counted pairs (may be NULL). */
+megs_status megs_state_status(const megs_state *state, int64_t *pairs_needed, void *stream);
+
+/*
+ * Batched form: forward (and optionally backward) of all views captured once into a hipGraph
+ * and replayed with one launch. cfg->pair_capacity must be > 0. The camera table is uploaded
+ * at creation; scene, images, dl_dimages and grads are read/written in place at every launch.
+ * with_backward: 0 = forward only, 1 = forward + backward (dl_dimages and grads required).
+ * stream must not be the null stream. Overflow is reported by megs_graph_status.
+ */
+typedef struct megs_graph megs_graph;
+
+megs_status megs_graph_create(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
+                              const megs_config *cfg, megs_alloc_fn alloc, void *alloc_ctx,
+                              float *images, const float *dl_dimages, megs_scene_grad *grads,
+                              int32_t with_backward, void *stream, megs_graph **out);
+megs_status megs_graph_launch(megs_graph *graph, void *stream);
+megs_status megs_graph_status(megs_graph *graph, int64_t *pairs_needed, void *stream);
+const megs_state *megs_graph_state(const megs_graph *graph);
+void megs_graph_destroy(megs_graph *graph);
+
+/*
+ * Autotuner: times forward+backward for tile in {8, 16, 32} x batch in {64, 128, 256} on the
+ * given views (1 warm-up and `reps` timed runs each, HIP events on `stream`) and writes the
+ * fastest configuration to *best (flags and pair_capacity copied from *base). Images are
+ * independent of the choice (the footprint lies inside its tile rectangle), so the choice
+ * changes speed only. ms_out (nullable) receives 9 timings in the order tile-major.
+ */
+megs_status megs_autotune(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
+                          const megs_config *base, megs_alloc_fn alloc, void *alloc_ctx,
+                          float *images, const float *dl_dimages, megs_scene_grad *grads,
+                          int32_t reps, void *stream, megs_config *best, float *ms_out);
+
+/*
+ * Per-stage timing with HIP events (eager calls only; graph capture records no events).
+ * megs_profile_begin starts recording on the calling thread: every following
+ * megs_render_forward / megs_render_backward on this thread brackets each stage's launches with
+ * events on its stream. megs_profile_end waits for the recorded events, writes the summed
+ * milliseconds and launch counts per stage, and stops recording.
+ */
+typedef enum {
+    MEGS_STAGE_PROJECT = 0,   /* EWA projection and SG colour */
+    MEGS_STAGE_DEPTH_SORT,    /* depth pre-sort of records */
+    MEGS_STAGE_SCAN,          /* tile-count scan */
+    MEGS_STAGE_EMIT,          /* key emission */
+    MEGS_STAGE_PAIR_SORT,     /* pair sort on tile bits (or full keys) */
+    MEGS_STAGE_RANGES,        /* per-tile ranges */
+    MEGS_STAGE_BLEND_FWD,     /* front-to-back blend */
+    MEGS_STAGE_BLEND_BWD,     /* back-to-front replay */
+    MEGS_STAGE_PROJECT_BWD,   /* chain rule to raw parameters */
+    MEGS_STAGE_COUNT
+} megs_stage;
+
+typedef struct {
+    double ms[MEGS_STAGE_COUNT];
+    int64_t count[MEGS_STAGE_COUNT];
+} megs_profile;
+
+megs_status megs_profile_begin(void);
+megs_status megs_profile_end(megs_profile *out);
+
+/* Description of the last error on the calling thread ("" when none). */
+const char *megs_last_error(void);
+
+/* Library version string. */
+const char *megs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEGS_H */

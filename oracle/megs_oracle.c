@@ -31,6 +31,7 @@
  * sum for the blend backward). The 3DGS constants above are conventions, not pins.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -60,6 +61,9 @@ static const double ALPHA_MAX = 0.99;
 static const double T_MIN = 1e-4;
 static const double FOV_CLAMP = 1.3;
 static const double MAX_COORD = 1e7;
+
+/* threads the OpenMP loops of this file use */
+int32_t oracle_threads(void) { return omp_get_max_threads(); }
 
 static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
 
@@ -476,15 +480,18 @@ void oracle_bruteforce(int32_t w, int32_t h, const double *bg, int64_t nrec, con
  * the fragments behind instead of the running background recursion.
  * Contributions go to per-pair slots (one per list position), summed per record
  * in list order afterwards, so the result does not depend on the thread count.
- * grad2d must hold nrec * 9 zeros on entry; contributions are added.
+ * grad2d must hold nrec * 9 zeros on entry; contributions are added. grad2d_abs (nullable) receives
+ * the sum of the absolute values of the same contributions (the scale against which the rounding
+ * error of any summation order is measured).
  */
 void oracle_blend_backward(int32_t w, int32_t h, int32_t tile, const double *bg,
                            const double *u, const double *v, const double *conic, const double *o, const double *rgb,
                            const uint32_t *vals, const uint32_t *ranges, int64_t npairs, const double *dl,
-                           int32_t direct, double *grad2d) {
+                           int32_t direct, double *grad2d, double *grad2d_abs) {
     orecs rc = {u, v, conic, o, rgb};
     int tiles_x = (w + tile - 1) / tile, tiles_y = (h + tile - 1) / tile;
     double *slots = (double *)calloc((size_t)(npairs > 0 ? npairs : 1) * 9, sizeof(double));
+    double *aslots = (double *)calloc((size_t)(npairs > 0 ? npairs : 1) * 9, sizeof(double));
     #pragma omp parallel for schedule(dynamic)
     for (int t = 0; t < tiles_x * tiles_y; ++t) {
         int tx = t % tiles_x, ty = t / tiles_x;
@@ -523,7 +530,11 @@ void oracle_blend_backward(int32_t w, int32_t h, int32_t tile, const double *bg,
                     double alpha = f[0], G = f[1], Ti = f[2], dx = f[3], dy = f[4];
                     const double *c = rc.rgb + 3 * g;
                     double *slot = slots + 9 * (s + fpos[j]);
-                    for (int ch = 0; ch < 3; ++ch) slot[6 + ch] += alpha * Ti * gp[ch];
+                    double *aslot = aslots + 9 * (s + fpos[j]);
+                    for (int ch = 0; ch < 3; ++ch) {
+                        slot[6 + ch] += alpha * Ti * gp[ch];
+                        aslot[6 + ch] += fabs(alpha * Ti * gp[ch]);
+                    }
                     double dalpha = 0;
                     if (!direct) {
                         for (int ch = 0; ch < 3; ++ch) dalpha += Ti * (c[ch] - Bk[ch]) * gp[ch];
@@ -543,12 +554,12 @@ void oracle_blend_backward(int32_t w, int32_t h, int32_t tile, const double *bg,
                     if (f[5] != 0) continue; /* alpha clamped at 0.99: no dependence on o_eff or q */
                     const double *cn = rc.conic + 3 * g;
                     double dq = dalpha * alpha;
-                    slot[5] += dalpha * G;
-                    slot[0] += dq * (cn[0] * dx + cn[1] * dy);
-                    slot[1] += dq * (cn[1] * dx + cn[2] * dy);
-                    slot[2] += dq * (-0.5 * dx * dx);
-                    slot[3] += dq * (-dx * dy);
-                    slot[4] += dq * (-0.5 * dy * dy);
+                    double t9[6] = {dq * (cn[0] * dx + cn[1] * dy), dq * (cn[1] * dx + cn[2] * dy),
+                                    dq * (-0.5 * dx * dx), dq * (-dx * dy), dq * (-0.5 * dy * dy), dalpha * G};
+                    for (int c = 0; c < 6; ++c) {
+                        slot[c] += t9[c];
+                        aslot[c] += fabs(t9[c]);
+                    }
                 }
             }
         free(fpos);
@@ -557,8 +568,11 @@ void oracle_blend_backward(int32_t w, int32_t h, int32_t tile, const double *bg,
     for (int64_t i = 0; i < npairs; ++i) {
         uint32_t g = vals[i];
         for (int c = 0; c < 9; ++c) grad2d[9 * (int64_t)g + c] += slots[9 * i + c];
+        if (grad2d_abs)
+            for (int c = 0; c < 9; ++c) grad2d_abs[9 * (int64_t)g + c] += aslots[9 * i + c];
     }
     free(slots);
+    free(aslots);
 }
 
 /* -------------------------------------------------- projection backward ---- */

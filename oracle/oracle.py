@@ -64,6 +64,7 @@ def lib():
         build()
         L = ctypes.CDLL(LIB)
         vp = ctypes.c_void_p
+        L.oracle_threads.restype = ctypes.c_int32
         L.oracle_project.argtypes = [ctypes.POINTER(OScene), ctypes.POINTER(OCam), ctypes.c_int32, vp, vp]
         L.oracle_sg_color.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_sg_color_many.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_int64, vp, vp]
@@ -77,7 +78,7 @@ def lib():
                                         vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_blend_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                             vp, vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp,
-                                            ctypes.c_int32, vp]
+                                            ctypes.c_int32, vp, vp]
         L.oracle_project_backward.argtypes = [ctypes.POINTER(OScene), ctypes.POINTER(OCam), ctypes.c_int32,
                                               vp, ctypes.POINTER(OGrad)]
         _lib = L
@@ -151,6 +152,10 @@ def sg_color_many(base, axis, sharp, amp, directions, mask=None) -> np.ndarray:
     return out
 
 
+def threads() -> int:
+    return int(lib().oracle_threads())
+
+
 def tile_layout(cams: Sequence, tile: int):
     """Per-view tile counts and the global tile offset of each view."""
     counts = [((c.width + tile - 1) // tile) * ((c.height + tile - 1) // tile) for c in cams]
@@ -222,8 +227,10 @@ def bruteforce(cam, rec: dict, valid):
     return {"image": image, "T": T, "last": last, "flag": flag}
 
 
-def blend_backward(cam, tile: int, rec: dict, vals, ranges_view, dl, direct: bool = False, grad2d=None):
-    """Per-record 2D gradients [n][9] for one view (added into grad2d if given)."""
+def blend_backward(cam, tile: int, rec: dict, vals, ranges_view, dl, direct: bool = False, grad2d=None,
+                   grad2d_abs=None):
+    """Per-record 2D gradients [n][9] for one view (added into grad2d if given; the sums of the
+    contributions' absolute values are added into grad2d_abs when given)."""
     u, v, conic, o, rgb = _recs(rec)
     n = len(u)
     if grad2d is None:
@@ -233,7 +240,8 @@ def blend_backward(cam, tile: int, rec: dict, vals, ranges_view, dl, direct: boo
     rv = np.ascontiguousarray(ranges_view, np.uint32)
     dl = _c64(dl)
     lib().oracle_blend_backward(cam.width, cam.height, tile, _ptr(bg), _ptr(u), _ptr(v), _ptr(conic), _ptr(o),
-                                _ptr(rgb), _ptr(vals), _ptr(rv), len(vals), _ptr(dl), int(direct), _ptr(grad2d))
+                                _ptr(rgb), _ptr(vals), _ptr(rv), len(vals), _ptr(dl), int(direct), _ptr(grad2d),
+                                _ptr(grad2d_abs))
     return grad2d
 
 

@@ -1,0 +1,118 @@
+"""ctypes binding of libmegs.so (include/megs.h): structures and function signatures only.
+
+This module marshals arguments; every step of the renderer runs in the library's HIP
+kernels. Loading fails loudly when the library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmegs.so")
+
+MEGS_OK, MEGS_ERR_ARG, MEGS_ERR_HIP, MEGS_ERR_CAPACITY, MEGS_ERR_UNSUPPORTED, MEGS_ERR_ALLOC = 0, -1, -2, -3, -4, -5
+MEGS_F32, MEGS_F16, MEGS_BF16 = 0, 1, 2
+MEGS_FLAG_ONE_STAGE_SORT = 1
+MEGS_FLAG_PERSISTENT = 2
+MEGS_FLAG_STATS = 4
+STAGES = ("project", "depth_sort", "scan", "emit", "pair_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd")
+MEGS_MAX_LOBES = 8
+MEGS_MAX_VIEWS = 64
+
+EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", "megs_graph_create",
+            "megs_graph_launch", "megs_graph_status", "megs_graph_state", "megs_graph_destroy",
+            "megs_autotune", "megs_profile_begin", "megs_profile_end", "megs_last_error", "megs_version")
+
+PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
+          "base", "axis", "sharp", "amp", "lmask_logit")
+
+_vp = ctypes.c_void_p
+
+
+class MegsScene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("dt_geom", ctypes.c_int32),
+                ("dt_color", ctypes.c_int32), ("dt_amp", ctypes.c_int32), ("reserved", ctypes.c_int32)] + \
+               [(p, _vp) for p in PLANES]
+
+
+class MegsSceneGrad(ctypes.Structure):
+    _fields_ = [(p, _vp) for p in PLANES]
+
+
+class MegsCamera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("znear", ctypes.c_float),
+                ("bg", ctypes.c_float * 3)]
+
+
+class MegsConfig(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
+
+
+class MegsState(ctypes.Structure):
+    _fields_ = [("n_records", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("pair_capacity", ctypes.c_int64),
+                ("n_pixels", ctypes.c_int64), ("n_views", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("n_tiles", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("mean", _vp), ("conic_o", _vp), ("rgbd", _vp), ("radius", _vp), ("ntiles", _vp),
+                ("tile_keys", _vp), ("keys64", _vp), ("vals", _vp), ("ranges", _vp), ("T_final", _vp),
+                ("last", _vp), ("device_status", _vp), ("internal", _vp)]
+
+
+class MegsProfile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * len(STAGES)), ("count", ctypes.c_int64 * len(STAGES))]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+
+_lib = None
+
+
+class MegsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libmegs status {status}: {message}")
+        self.status = status
+
+
+def load():
+    """Load libmegs.so; raises when it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    L.megs_render_forward.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ALLOC_FN, _vp,
+                                      _vp, P(MegsState), _vp]
+    L.megs_render_backward.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), P(MegsState),
+                                       _vp, ALLOC_FN, _vp, P(MegsSceneGrad), _vp]
+    L.megs_state_status.argtypes = [P(MegsState), P(ctypes.c_int64), _vp]
+    L.megs_graph_create.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ALLOC_FN, _vp,
+                                    _vp, _vp, P(MegsSceneGrad), ctypes.c_int32, _vp, P(_vp)]
+    L.megs_graph_launch.argtypes = [_vp, _vp]
+    L.megs_graph_status.argtypes = [_vp, P(ctypes.c_int64), _vp]
+    L.megs_graph_state.argtypes = [_vp]
+    L.megs_graph_state.restype = P(MegsState)
+    L.megs_graph_destroy.argtypes = [_vp]
+    L.megs_graph_destroy.restype = None
+    L.megs_autotune.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ALLOC_FN, _vp,
+                                _vp, _vp, P(MegsSceneGrad), ctypes.c_int32, _vp, P(MegsConfig), P(ctypes.c_float)]
+    L.megs_profile_begin.argtypes = []
+    L.megs_profile_end.argtypes = [P(MegsProfile)]
+    for f in ("megs_render_forward", "megs_render_backward", "megs_state_status", "megs_graph_create",
+              "megs_graph_launch", "megs_graph_status", "megs_autotune", "megs_profile_begin", "megs_profile_end"):
+        getattr(L, f).restype = ctypes.c_int
+    L.megs_last_error.restype = ctypes.c_char_p
+    L.megs_last_error.argtypes = []
+    L.megs_version.restype = ctypes.c_char_p
+    L.megs_version.argtypes = []
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != MEGS_OK:
+        raise MegsError(status, load().megs_last_error().decode())

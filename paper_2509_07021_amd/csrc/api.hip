@@ -1,0 +1,659 @@
+// api.hip -- C ABI of libmegs: argument checks, working-memory layout, stream orchestration of
+// the forward and backward passes, hipGraph capture of the batched form, and the autotuner.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "megs_internal.hpp"
+
+using namespace megs;
+
+namespace {
+
+struct ProfileRec {
+    int stage;
+    hipEvent_t start, end;
+};
+struct Profiler {
+    bool on = false;
+    std::vector<ProfileRec> recs;
+};
+thread_local Profiler g_prof;
+
+}  // namespace
+
+namespace megs {
+
+StageTimer::StageTimer(int st, hipStream_t s) : stage(st), stream(s), start(nullptr) {
+    if (!g_prof.on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventRecord(e, s) != hipSuccess) { (void)hipEventDestroy(e); return; }
+    start = e;
+}
+
+StageTimer::~StageTimer() {
+    if (!start) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventRecord(e, stream) != hipSuccess) { (void)hipEventDestroy(e); return; }
+    g_prof.recs.push_back({stage, static_cast<hipEvent_t>(start), e});
+}
+
+}  // namespace megs
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+megs_status fail(megs_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIP_TRY(call)                                                                                     \
+    do {                                                                                                  \
+        hipError_t e_ = (call);                                                                           \
+        if (e_ != hipSuccess) return fail(MEGS_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr int kViewChunk = 8;
+struct ViewChunk {
+    ViewInfo v[kViewChunk];
+    int count;
+};
+
+__global__ void k_set_views(ViewInfo* dst, ViewChunk c) {
+    if ((int)threadIdx.x < c.count) dst[threadIdx.x] = c.v[threadIdx.x];
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bump allocator over one caller-provided block.
+struct Carver {
+    char* base;
+    size_t off;
+    template <typename T>
+    T* take(int64_t count) {
+        T* p = reinterpret_cast<T*>(base + off);
+        off += align256((size_t)(count > 0 ? count : 1) * sizeof(T));
+        return p;
+    }
+};
+
+struct Layout {
+    int nv;
+    int64_t n, nr, n_tiles, n_pixels;
+    int tile, tile_bits;
+    std::vector<ViewInfo> views;
+};
+
+bool valid_dtype(int32_t d) { return d == MEGS_F32 || d == MEGS_F16 || d == MEGS_BF16; }
+
+megs_status check_args(const megs_scene* sc, const megs_camera* cams, int32_t nv, const megs_config* cfg) {
+    if (!sc || !cams || !cfg) return fail(MEGS_ERR_ARG, "null scene, camera or config");
+    if (sc->n < 0) return fail(MEGS_ERR_ARG, "n = %lld < 0", (long long)sc->n);
+    if (sc->k < 0 || sc->k > MEGS_MAX_LOBES) return fail(MEGS_ERR_ARG, "k = %d outside [0, %d]", sc->k, MEGS_MAX_LOBES);
+    if (!valid_dtype(sc->dt_geom) || !valid_dtype(sc->dt_color) || !valid_dtype(sc->dt_amp))
+        return fail(MEGS_ERR_ARG, "unknown storage dtype");
+    if (nv < 1 || nv > MEGS_MAX_VIEWS) return fail(MEGS_ERR_ARG, "n_views = %d outside [1, %d]", nv, MEGS_MAX_VIEWS);
+    if (sc->n * (int64_t)nv >= (1ll << 31)) return fail(MEGS_ERR_ARG, "n * n_views must be < 2^31");
+    if (sc->n > 0) {
+        if (!sc->pos || !sc->logscale || !sc->quat || !sc->op_logit || !sc->base)
+            return fail(MEGS_ERR_ARG, "null geometry or base plane");
+        if (sc->k > 0 && (!sc->axis || !sc->sharp || !sc->amp)) return fail(MEGS_ERR_ARG, "null lobe plane");
+    }
+    if (cfg->tile != 8 && cfg->tile != 16 && cfg->tile != 32) return fail(MEGS_ERR_ARG, "tile = %d not in {8, 16, 32}", cfg->tile);
+    if (cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
+        return fail(MEGS_ERR_ARG, "batch = %d not in {64, 128, 256}", cfg->batch);
+    if (cfg->pair_capacity < 0 || cfg->pair_capacity >= (1ll << 31)) return fail(MEGS_ERR_ARG, "pair_capacity out of range");
+    if (cfg->flags & ~(uint32_t)(MEGS_FLAG_ONE_STAGE_SORT | MEGS_FLAG_PERSISTENT | MEGS_FLAG_STATS))
+        return fail(MEGS_ERR_ARG, "unknown flags 0x%x", cfg->flags);
+    for (int v = 0; v < nv; ++v) {
+        const megs_camera& c = cams[v];
+        if (c.width <= 0 || c.height <= 0 || c.width > 16384 || c.height > 16384)
+            return fail(MEGS_ERR_ARG, "view %d: image size %dx%d out of range", v, c.width, c.height);
+        if (!(c.fx > 0) || !(c.fy > 0) || !(c.znear > 0)) return fail(MEGS_ERR_ARG, "view %d: fx, fy, znear must be > 0", v);
+    }
+    return MEGS_OK;
+}
+
+Layout make_layout(const megs_scene* sc, const megs_camera* cams, int nv, int tile) {
+    Layout L;
+    L.nv = nv;
+    L.n = sc->n;
+    L.nr = sc->n * nv;
+    L.tile = tile;
+    L.views.resize(nv);
+    int64_t toff = 0, poff = 0;
+    for (int v = 0; v < nv; ++v) {
+        const megs_camera& c = cams[v];
+        ViewInfo& w = L.views[v];
+        memcpy(w.R, c.R, sizeof(w.R));
+        memcpy(w.t, c.t, sizeof(w.t));
+        w.fx = c.fx; w.fy = c.fy; w.cx = c.cx; w.cy = c.cy; w.znear = c.znear;
+        memcpy(w.bg, c.bg, sizeof(w.bg));
+        for (int a = 0; a < 3; ++a)
+            w.campos[a] = (float)-((double)c.R[a] * c.t[0] + (double)c.R[3 + a] * c.t[1] + (double)c.R[6 + a] * c.t[2]);
+        w.limx = (float)(1.3 * (0.5 * c.width) / (double)c.fx);
+        w.limy = (float)(1.3 * (0.5 * c.height) / (double)c.fy);
+        w.width = c.width; w.height = c.height;
+        w.tiles_x = (c.width + tile - 1) / tile;
+        w.tiles_y = (c.height + tile - 1) / tile;
+        w.tile_off = toff;
+        w.pix_off = poff;
+        toff += (int64_t)w.tiles_x * w.tiles_y;
+        poff += (int64_t)c.width * c.height;
+    }
+    L.n_tiles = toff;
+    L.n_pixels = poff;
+    int b = 1;
+    while ((1ll << b) < L.n_tiles) ++b;
+    L.tile_bits = b;
+    return L;
+}
+
+SceneDev scene_dev(const megs_scene* sc) {
+    SceneDev d;
+    d.n = sc->n; d.k = sc->k;
+    d.dt_geom = sc->dt_geom; d.dt_color = sc->dt_color; d.dt_amp = sc->dt_amp;
+    d.pos = sc->pos; d.logscale = sc->logscale; d.quat = sc->quat; d.op_logit = sc->op_logit;
+    d.pmask_logit = sc->pmask_logit; d.base = sc->base; d.axis = sc->axis; d.sharp = sc->sharp; d.amp = sc->amp;
+    d.lmask_logit = sc->lmask_logit;
+    return d;
+}
+
+// Device pointers of one forward.
+struct Frame {
+    ViewInfo* views;
+    Records rec;
+    uint32_t *dkey_alt, *order, *order_alt, *offs;
+    void *scan_scratch, *rs_scratch;
+    uint32_t* counters;  // [0] pairs counted, [1] pairs used, [2] record count
+    int32_t* status;     // [0] pairs counted, [1] overflow, [4..7] two uint64 fragment counters
+    uint2* ranges;
+    float* T_final;
+    uint32_t* last;
+    uint32_t* queue;     // [0] forward, [1] backward work counters
+};
+
+size_t frame_bytes(const Layout& L) {
+    size_t b = 0;
+    b += align256(sizeof(ViewInfo) * L.nv);
+    b += align256(sizeof(double2) * (L.nr ? L.nr : 1));
+    b += 2 * align256(sizeof(float4) * (L.nr ? L.nr : 1));
+    b += 7 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
+    b += align256(scan_scratch_bytes(L.nr)) + align256(radix_scratch_bytes(L.nr));
+    b += align256(sizeof(uint32_t) * 8) + align256(sizeof(int32_t) * 8);
+    b += align256(sizeof(uint2) * L.n_tiles);
+    b += 2 * align256(sizeof(float) * L.n_pixels);
+    b += align256(sizeof(uint32_t) * 4);
+    return b + 256;
+}
+
+Frame carve_frame(void* mem, const Layout& L) {
+    Carver c{static_cast<char*>(mem), 0};
+    Frame f;
+    f.views = c.take<ViewInfo>(L.nv);
+    f.rec.mean = c.take<double2>(L.nr);
+    f.rec.conic_o = c.take<float4>(L.nr);
+    f.rec.rgbd = c.take<float4>(L.nr);
+    f.rec.radius = c.take<int32_t>(L.nr);
+    f.rec.ntiles = c.take<uint32_t>(L.nr);
+    f.rec.dkey = c.take<uint32_t>(L.nr);
+    f.dkey_alt = c.take<uint32_t>(L.nr);
+    f.order = c.take<uint32_t>(L.nr);
+    f.order_alt = c.take<uint32_t>(L.nr);
+    f.offs = c.take<uint32_t>(L.nr);
+    f.scan_scratch = c.take<char>((int64_t)scan_scratch_bytes(L.nr));
+    f.rs_scratch = c.take<char>((int64_t)radix_scratch_bytes(L.nr));
+    f.counters = c.take<uint32_t>(8);
+    f.status = c.take<int32_t>(8);
+    f.ranges = c.take<uint2>(L.n_tiles);
+    f.T_final = c.take<float>(L.n_pixels);
+    f.last = c.take<uint32_t>(L.n_pixels);
+    f.queue = c.take<uint32_t>(4);
+    return f;
+}
+
+struct Pairs {
+    int64_t capacity;
+    uint32_t *tkeys, *tkeys_alt, *vals, *vals_alt;
+    uint64_t *k64, *k64_alt;
+    void* rs_scratch;
+};
+
+size_t pairs_bytes(int64_t cap, bool one_stage) {
+    const int64_t c = cap > 0 ? cap : 1;
+    size_t b = 2 * align256(sizeof(uint32_t) * c);
+    b += one_stage ? 2 * align256(sizeof(uint64_t) * c) : 2 * align256(sizeof(uint32_t) * c);
+    b += align256(radix_scratch_bytes(c));
+    return b + 256;
+}
+
+Pairs carve_pairs(void* mem, int64_t cap, bool one_stage) {
+    Carver c{static_cast<char*>(mem), 0};
+    Pairs p;
+    p.capacity = cap;
+    p.vals = c.take<uint32_t>(cap);
+    p.vals_alt = c.take<uint32_t>(cap);
+    p.tkeys = p.tkeys_alt = nullptr;
+    p.k64 = p.k64_alt = nullptr;
+    if (one_stage) {
+        p.k64 = c.take<uint64_t>(cap);
+        p.k64_alt = c.take<uint64_t>(cap);
+    } else {
+        p.tkeys = c.take<uint32_t>(cap);
+        p.tkeys_alt = c.take<uint32_t>(cap);
+    }
+    p.rs_scratch = c.take<char>((int64_t)radix_scratch_bytes(cap > 0 ? cap : 1));
+    return p;
+}
+
+megs_status upload_views(const Layout& L, ViewInfo* dst, hipStream_t s) {
+    for (int v0 = 0; v0 < L.nv; v0 += kViewChunk) {
+        ViewChunk ch;
+        memset(&ch, 0, sizeof(ch));
+        ch.count = L.nv - v0 < kViewChunk ? L.nv - v0 : kViewChunk;
+        for (int i = 0; i < ch.count; ++i) ch.v[i] = L.views[v0 + i];
+        hipLaunchKernelGGL(k_set_views, dim3(1), dim3(kViewChunk), 0, s, dst + v0, ch);
+        HIP_TRY(hipGetLastError());
+    }
+    return MEGS_OK;
+}
+
+// Projection, depth pre-sort and tile-count scan (the part before the pair count is known).
+megs_status enqueue_front(const megs_scene* sc, const Layout& L, const megs_config* cfg, Frame& f, hipStream_t s) {
+    const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    megs_status st = upload_views(L, f.views, s);
+    if (st != MEGS_OK) return st;
+    HIP_TRY(launch_fill_u32(f.counters, 0u, 8, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(f.status), 0u, 8, s));
+    {
+        StageTimer t(MEGS_STAGE_PROJECT, s);
+        HIP_TRY(launch_project(scene_dev(sc), f.views, L.nv, L.tile, f.rec, s));
+    }
+    if (one_stage) {
+        StageTimer t(MEGS_STAGE_SCAN, s);
+        HIP_TRY(launch_scan(f.rec.ntiles, nullptr, L.nr, f.offs, f.counters + 0, f.scan_scratch, s));
+        return MEGS_OK;
+    }
+    {
+        StageTimer t(MEGS_STAGE_DEPTH_SORT, s);
+        HIP_TRY(launch_iota(f.order, L.nr, s));
+        HIP_TRY(launch_fill_u32(f.counters + 2, (uint32_t)L.nr, 1, s));
+        bool alt = false;
+        HIP_TRY(launch_radix_sort_u32(f.rec.dkey, f.order, f.dkey_alt, f.order_alt, f.counters + 2, L.nr, 0, 32,
+                                      f.rs_scratch, s, &alt));
+        if (alt) return fail(MEGS_ERR_HIP, "depth sort ended in the alternate buffer");
+    }
+    {
+        StageTimer t(MEGS_STAGE_SCAN, s);
+        HIP_TRY(launch_scan(f.rec.ntiles, f.order, L.nr, f.offs, f.counters + 0, f.scan_scratch, s));
+    }
+    return MEGS_OK;
+}
+
+// Emission, pair sort, ranges and the forward blend; fills the pair fields of state.
+megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_config* cfg, Frame& f, Pairs& p,
+                         float* images, megs_state* state, hipStream_t s) {
+    const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    const bool persistent = cfg->flags & MEGS_FLAG_PERSISTENT;
+    {
+        StageTimer t(MEGS_STAGE_EMIT, s);
+        HIP_TRY(launch_clamp_count(f.counters + 0, p.capacity, f.counters + 1, f.status, s));
+        HIP_TRY(launch_emit(f.rec, f.views, L.nv, L.n, L.tile, one_stage ? nullptr : f.order, f.offs, L.nr, p.tkeys,
+                            p.k64, p.vals, p.capacity, f.status, s));
+    }
+    bool alt = false;
+    const uint32_t* sorted_t = nullptr;
+    const uint64_t* sorted_k = nullptr;
+    const uint32_t* sorted_v = nullptr;
+    {
+        StageTimer t(MEGS_STAGE_PAIR_SORT, s);
+        if (one_stage) {
+            HIP_TRY(launch_radix_sort_u64(p.k64, p.vals, p.k64_alt, p.vals_alt, f.counters + 1, p.capacity, 0,
+                                          32 + L.tile_bits, p.rs_scratch, s, &alt));
+            sorted_k = alt ? p.k64_alt : p.k64;
+        } else {
+            HIP_TRY(launch_radix_sort_u32(p.tkeys, p.vals, p.tkeys_alt, p.vals_alt, f.counters + 1, p.capacity, 0,
+                                          L.tile_bits, p.rs_scratch, s, &alt));
+            sorted_t = alt ? p.tkeys_alt : p.tkeys;
+        }
+    }
+    sorted_v = alt ? p.vals_alt : p.vals;
+    {
+        StageTimer t(MEGS_STAGE_RANGES, s);
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(f.ranges), 0u, 2 * L.n_tiles, s));
+        if (one_stage)
+            HIP_TRY(launch_ranges_u64(sorted_k, f.counters + 1, p.capacity, f.ranges, s));
+        else
+            HIP_TRY(launch_ranges_u32(sorted_t, f.counters + 1, p.capacity, f.ranges, s));
+    }
+    BlendArgs a;
+    memset(&a, 0, sizeof(a));
+    a.views = f.views; a.nv = L.nv; a.n_tiles = L.n_tiles;
+    a.mean = f.rec.mean; a.conic_o = f.rec.conic_o; a.rgbd = f.rec.rgbd;
+    a.vals = sorted_v; a.ranges = f.ranges;
+    a.image = images; a.T_final = f.T_final; a.last = f.last;
+    a.queue = f.queue;
+    a.stats = (cfg->flags & MEGS_FLAG_STATS) ? reinterpret_cast<unsigned long long*>(f.status + 4) : nullptr;
+    if (persistent) HIP_TRY(launch_fill_u32(f.queue, 0u, 4, s));
+    {
+        StageTimer t(MEGS_STAGE_BLEND_FWD, s);
+        HIP_TRY(launch_blend_fwd(a, L.tile, cfg->batch, persistent, s));
+    }
+
+    state->n_records = L.nr;
+    state->pair_capacity = p.capacity;
+    state->n_pixels = L.n_pixels;
+    state->n_views = L.nv;
+    state->tile = L.tile;
+    state->n_tiles = (int32_t)L.n_tiles;
+    state->k = sc->k;
+    state->mean = f.rec.mean;
+    state->conic_o = f.rec.conic_o;
+    state->rgbd = f.rec.rgbd;
+    state->radius = f.rec.radius;
+    state->ntiles = f.rec.ntiles;
+    state->tile_keys = sorted_t;
+    state->keys64 = sorted_k;
+    state->vals = sorted_v;
+    state->ranges = f.ranges;
+    state->T_final = f.T_final;
+    state->last = f.last;
+    state->device_status = f.status;
+    state->internal = f.views;
+    return MEGS_OK;
+}
+
+megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_config* cfg, const megs_state* st,
+                             const float* dl, float* grad2d, uint32_t* queue, const megs_scene_grad* gr,
+                             hipStream_t s) {
+    const bool persistent = cfg->flags & MEGS_FLAG_PERSISTENT;
+    BlendArgs a;
+    memset(&a, 0, sizeof(a));
+    a.views = static_cast<const ViewInfo*>(st->internal);
+    a.nv = L.nv; a.n_tiles = L.n_tiles;
+    a.mean = static_cast<const double2*>(st->mean);
+    a.conic_o = static_cast<const float4*>(st->conic_o);
+    a.rgbd = static_cast<const float4*>(st->rgbd);
+    a.vals = static_cast<const uint32_t*>(st->vals);
+    a.ranges = static_cast<const uint2*>(st->ranges);
+    a.T_final = const_cast<float*>(static_cast<const float*>(st->T_final));
+    a.last = const_cast<uint32_t*>(static_cast<const uint32_t*>(st->last));
+    a.dl = dl;
+    a.grad2d = grad2d;
+    a.queue = queue;
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * L.nr, s));
+    if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 1, s));
+    {
+        StageTimer t(MEGS_STAGE_BLEND_BWD, s);
+        HIP_TRY(launch_blend_bwd(a, L.tile, cfg->batch, persistent, s));
+    }
+    GradDev g;
+    g.pos = gr->pos; g.logscale = gr->logscale; g.quat = gr->quat; g.op_logit = gr->op_logit;
+    g.pmask_logit = gr->pmask_logit; g.base = gr->base; g.axis = gr->axis; g.sharp = gr->sharp; g.amp = gr->amp;
+    g.lmask_logit = gr->lmask_logit;
+    {
+        StageTimer t(MEGS_STAGE_PROJECT_BWD, s);
+        HIP_TRY(launch_project_bwd(scene_dev(sc), a.views, L.nv, grad2d, g, s));
+    }
+    return MEGS_OK;
+}
+
+megs_status check_grads(const megs_scene* sc, const megs_scene_grad* g) {
+    if (!g) return fail(MEGS_ERR_ARG, "null gradient struct");
+    if (sc->n == 0) return MEGS_OK;
+    if (!g->pos || !g->logscale || !g->quat || !g->op_logit || !g->base)
+        return fail(MEGS_ERR_ARG, "null gradient plane");
+    if (sc->k > 0 && (!g->axis || !g->sharp || !g->amp)) return fail(MEGS_ERR_ARG, "null lobe gradient plane");
+    if ((sc->pmask_logit != nullptr) != (g->pmask_logit != nullptr))
+        return fail(MEGS_ERR_ARG, "pmask_logit gradient must be given exactly when the scene has primitive masks");
+    if ((sc->lmask_logit != nullptr) != (g->lmask_logit != nullptr))
+        return fail(MEGS_ERR_ARG, "lmask_logit gradient must be given exactly when the scene has lobe masks");
+    return MEGS_OK;
+}
+
+megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t nv, const megs_config* cfg,
+                         megs_alloc_fn alloc, void* ctx, float* images, megs_state* state, hipStream_t s) {
+    megs_status st = check_args(sc, cams, nv, cfg);
+    if (st != MEGS_OK) return st;
+    if (!alloc || !images || !state) return fail(MEGS_ERR_ARG, "null allocator, image or state");
+    const Layout L = make_layout(sc, cams, nv, cfg->tile);
+    const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    memset(state, 0, sizeof(*state));
+    void* fm = alloc(ctx, frame_bytes(L));
+    if (!fm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", frame_bytes(L));
+    Frame f = carve_frame(fm, L);
+    st = enqueue_front(sc, L, cfg, f, s);
+    if (st != MEGS_OK) return st;
+    int64_t cap = cfg->pair_capacity;
+    int64_t counted = -1;
+    if (cap == 0) {
+        uint32_t total = 0;
+        HIP_TRY(hipMemcpyAsync(&total, f.counters, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        counted = total;
+        cap = total;
+    }
+    void* pm = alloc(ctx, pairs_bytes(cap, one_stage));
+    if (!pm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", pairs_bytes(cap, one_stage));
+    Pairs p = carve_pairs(pm, cap, one_stage);
+    st = enqueue_back(sc, L, cfg, f, p, images, state, s);
+    state->n_pairs = counted >= 0 ? counted : cap;
+    return st;
+}
+
+}  // namespace
+
+struct megs_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    megs_state state;
+};
+
+extern "C" {
+
+const char* megs_last_error(void) { return g_err; }
+
+const char* megs_version(void) { return "megs 0.1 (gfx950)"; }
+
+megs_status megs_profile_begin(void) {
+    g_err[0] = 0;
+    for (auto& r : g_prof.recs) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.end);
+    }
+    g_prof.recs.clear();
+    g_prof.on = true;
+    return MEGS_OK;
+}
+
+megs_status megs_profile_end(megs_profile* out) {
+    g_err[0] = 0;
+    megs_status st = MEGS_OK;
+    if (out) memset(out, 0, sizeof(*out));
+    for (auto& r : g_prof.recs) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.end);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.end);
+        if (e != hipSuccess && st == MEGS_OK) st = fail(MEGS_ERR_HIP, "profile event: %s", hipGetErrorString(e));
+        if (out && r.stage >= 0 && r.stage < MEGS_STAGE_COUNT) {
+            out->ms[r.stage] += ms;
+            out->count[r.stage] += 1;
+        }
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.end);
+    }
+    g_prof.recs.clear();
+    g_prof.on = false;
+    return st;
+}
+
+megs_status megs_render_forward(const megs_scene* scene, const megs_camera* cams, int32_t n_views,
+                                const megs_config* cfg, megs_alloc_fn alloc, void* alloc_ctx, float* images,
+                                megs_state* state, void* stream) {
+    g_err[0] = 0;
+    return forward_impl(scene, cams, n_views, cfg, alloc, alloc_ctx, images, state, static_cast<hipStream_t>(stream));
+}
+
+megs_status megs_render_backward(const megs_scene* scene, const megs_camera* cams, int32_t n_views,
+                                 const megs_config* cfg, const megs_state* state, const float* dl_dimages,
+                                 megs_alloc_fn alloc, void* alloc_ctx, megs_scene_grad* grads, void* stream) {
+    g_err[0] = 0;
+    megs_status st = check_args(scene, cams, n_views, cfg);
+    if (st != MEGS_OK) return st;
+    if (!state || !dl_dimages || !alloc) return fail(MEGS_ERR_ARG, "null state, dL/dimage or allocator");
+    st = check_grads(scene, grads);
+    if (st != MEGS_OK) return st;
+    const Layout L = make_layout(scene, cams, n_views, cfg->tile);
+    if (state->n_records != L.nr || state->n_views != n_views || state->tile != cfg->tile || !state->internal)
+        return fail(MEGS_ERR_ARG, "state does not belong to this scene, view set and tile size");
+    const size_t gbytes = align256(sizeof(float) * 9 * (L.nr ? L.nr : 1)) + 256;
+    void* gm = alloc(alloc_ctx, gbytes);
+    if (!gm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", gbytes);
+    float* grad2d = static_cast<float*>(gm);
+    uint32_t* queue = reinterpret_cast<uint32_t*>(static_cast<char*>(gm) + gbytes - 256);
+    return enqueue_backward(scene, L, cfg, state, dl_dimages, grad2d, queue, grads, static_cast<hipStream_t>(stream));
+}
+
+megs_status megs_state_status(const megs_state* state, int64_t* pairs_needed, void* stream) {
+    g_err[0] = 0;
+    if (!state || !state->device_status) return fail(MEGS_ERR_ARG, "null state");
+    int32_t h[2] = {0, 0};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(h, state->device_status, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (pairs_needed) *pairs_needed = (int64_t)(uint32_t)h[0];
+    if (h[1]) return fail(MEGS_ERR_CAPACITY, "pair table overflow: %u pairs counted, capacity %lld", (uint32_t)h[0],
+                          (long long)state->pair_capacity);
+    return MEGS_OK;
+}
+
+megs_status megs_graph_create(const megs_scene* scene, const megs_camera* cams, int32_t n_views,
+                              const megs_config* cfg, megs_alloc_fn alloc, void* alloc_ctx, float* images,
+                              const float* dl_dimages, megs_scene_grad* grads, int32_t with_backward, void* stream,
+                              megs_graph** out) {
+    g_err[0] = 0;
+    megs_status st = check_args(scene, cams, n_views, cfg);
+    if (st != MEGS_OK) return st;
+    if (!out || !alloc || !images) return fail(MEGS_ERR_ARG, "null output, allocator or images");
+    if (cfg->pair_capacity <= 0) return fail(MEGS_ERR_ARG, "graph mode needs pair_capacity > 0");
+    if (!stream) return fail(MEGS_ERR_ARG, "graph capture needs a non-null stream");
+    if (with_backward) {
+        if (!dl_dimages) return fail(MEGS_ERR_ARG, "null dL/dimage");
+        st = check_grads(scene, grads);
+        if (st != MEGS_OK) return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout L = make_layout(scene, cams, n_views, cfg->tile);
+    const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    void* fm = alloc(alloc_ctx, frame_bytes(L));
+    void* pm = alloc(alloc_ctx, pairs_bytes(cfg->pair_capacity, one_stage));
+    const size_t gbytes = align256(sizeof(float) * 9 * (L.nr ? L.nr : 1)) + 256;
+    void* gm = with_backward ? alloc(alloc_ctx, gbytes) : nullptr;
+    if (!fm || !pm || (with_backward && !gm)) return fail(MEGS_ERR_ALLOC, "allocation failed");
+    megs_graph* G = new (std::nothrow) megs_graph();
+    if (!G) return fail(MEGS_ERR_ALLOC, "host allocation failed");
+    Frame f = carve_frame(fm, L);
+    Pairs p = carve_pairs(pm, cfg->pair_capacity, one_stage);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { delete G; return fail(MEGS_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e)); }
+    st = enqueue_front(scene, L, cfg, f, s);
+    if (st == MEGS_OK) st = enqueue_back(scene, L, cfg, f, p, images, &G->state, s);
+    if (st == MEGS_OK && with_backward)
+        st = enqueue_backward(scene, L, cfg, &G->state, dl_dimages, static_cast<float*>(gm),
+                              reinterpret_cast<uint32_t*>(static_cast<char*>(gm) + gbytes - 256), grads, s);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (st != MEGS_OK) { if (graph) (void)hipGraphDestroy(graph); delete G; return st; }
+    if (e != hipSuccess) { delete G; return fail(MEGS_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e)); }
+    G->graph = graph;
+    e = hipGraphInstantiate(&G->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete G;
+        return fail(MEGS_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    G->state.n_pairs = cfg->pair_capacity;
+    *out = G;
+    return MEGS_OK;
+}
+
+megs_status megs_graph_launch(megs_graph* graph, void* stream) {
+    g_err[0] = 0;
+    if (!graph) return fail(MEGS_ERR_ARG, "null graph");
+    HIP_TRY(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+    return MEGS_OK;
+}
+
+megs_status megs_graph_status(megs_graph* graph, int64_t* pairs_needed, void* stream) {
+    if (!graph) return fail(MEGS_ERR_ARG, "null graph");
+    return megs_state_status(&graph->state, pairs_needed, stream);
+}
+
+const megs_state* megs_graph_state(const megs_graph* graph) { return graph ? &graph->state : nullptr; }
+
+void megs_graph_destroy(megs_graph* graph) {
+    if (!graph) return;
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+    delete graph;
+}
+
+megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int32_t n_views, const megs_config* base,
+                          megs_alloc_fn alloc, void* alloc_ctx, float* images, const float* dl_dimages,
+                          megs_scene_grad* grads, int32_t reps, void* stream, megs_config* best, float* ms_out) {
+    g_err[0] = 0;
+    if (!base || !best || !dl_dimages) return fail(MEGS_ERR_ARG, "null base config, best or dL/dimage");
+    if (reps < 1) reps = 1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int tiles[3] = {8, 16, 32};
+    const int batches[3] = {64, 128, 256};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    megs_status result = MEGS_OK;
+    for (int ti = 0; ti < 3 && result == MEGS_OK; ++ti)
+        for (int bi = 0; bi < 3 && result == MEGS_OK; ++bi) {
+            megs_config c = *base;
+            c.tile = tiles[ti];
+            c.batch = batches[bi];
+            float ms_total = 0.f;
+            for (int r = 0; r <= reps && result == MEGS_OK; ++r) {
+                megs_state st;
+                if (r > 0) (void)hipEventRecord(e0, s);
+                result = megs_render_forward(scene, cams, n_views, &c, alloc, alloc_ctx, images, &st, stream);
+                if (result == MEGS_OK)
+                    result = megs_render_backward(scene, cams, n_views, &c, &st, dl_dimages, alloc, alloc_ctx, grads,
+                                                  stream);
+                if (r > 0 && result == MEGS_OK) {
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    ms_total += ms;
+                }
+            }
+            const float ms = ms_total / reps;
+            if (ms_out) ms_out[ti * 3 + bi] = ms;
+            if (result == MEGS_OK && ms < best_ms) {
+                best_ms = ms;
+                *best = c;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return result;
+}
+
+}  // extern "C"

@@ -1,0 +1,334 @@
+// blend.hip -- per-tile front-to-back alpha blending (forward) and its back-to-front replay
+// (backward), gfx950.
+//
+// Compositing follows Sec. 3.1: C = sum_i c_i alpha_i prod_{j<i}(1 - alpha_j), alpha_i = o_i times
+// the 2D Gaussian at the pixel, with the 3DGS conventions (alpha clamped to 0.99, fragments below
+// 1/255 skipped, stop before the transmittance would fall under 1e-4).
+//
+// Mapping to CDNA4: one wave64 workgroup per (view, tile), TILE^2/64 pixels per lane, so a tile
+// needs no workgroup barrier beyond the wave itself and every LDS read of a staged Gaussian is
+// reused by all of a lane's pixels. Gaussians of the tile's list are staged into LDS in batches
+// (one record per lane per load, gathered through the sorted record indices); their means are
+// made tile-relative in FP64 while staging, so the per-fragment arithmetic works on small FP32
+// offsets. The wave stops as soon as all its pixels have terminated.
+//
+// The backward walks each tile's list from the largest per-pixel last index down to 0, recovers
+// the transmittance in front of each fragment by division, carries the background seen behind
+// the fragment, and accumulates the nine per-record 2D gradients. They are summed over the
+// wave's pixels with a transposed butterfly (16 cross-lane exchanges for 9 values) and added to
+// the record's slot with nine lanes of one hardware float atomic, only when some lane of the wave
+// contributed.
+#include "megs_internal.hpp"
+
+namespace megs {
+namespace {
+
+struct Staged {
+    float4 p0;  // u_rel, v_rel, o, nb2   (nb2 = -b log2 e)
+    float4 p1;  // na2, nc2, a, b        (na2 = -a log2 e / 2, nc2 = -c log2 e / 2)
+    float4 p2;  // c, r, g, b
+};
+
+__device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0, double y0, Staged* dst) {
+    const double2 m = a.mean[g];
+    const float4 co = a.conic_o[g];
+    const float4 cd = a.rgbd[g];
+    Staged s;
+    s.p0 = make_float4((float)(m.x - x0), (float)(m.y - y0), co.w, -co.y * kLog2e);
+    s.p1 = make_float4(-0.5f * co.x * kLog2e, -0.5f * co.z * kLog2e, co.x, co.y);
+    s.p2 = make_float4(co.z, cd.x, cd.y, cd.z);
+    *dst = s;
+}
+
+// One fragment: returns true when it passes q <= 0 and alpha >= 1/255. The forward and the
+// backward call this same function, so both take identical decisions.
+__device__ __forceinline__ bool frag(const Staged& s, float px, float py, float& dx, float& dy, float& G,
+                                     float& alpha, bool& clamped) {
+    dx = px - s.p0.x;
+    dy = py - s.p0.y;
+    const float h = __fmaf_rn(s.p1.x, dx, s.p0.w * dy);
+    const float q2 = __fmaf_rn(dx, h, (s.p1.y * dy) * dy);
+    if (q2 > 0.0f) return false;
+    G = __builtin_amdgcn_exp2f(q2);
+    const float raw = s.p0.z * G;
+    clamped = raw > kAlphaMax;
+    alpha = clamped ? kAlphaMax : raw;
+    return alpha >= kAlphaMin;
+}
+
+struct TileCtx {
+    int view;
+    int64_t tile;
+    int x0, y0, width, height;
+    int64_t pix_off;
+    float bg[3];
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const BlendArgs& a, int64_t t, int TILE) {
+    TileCtx c;
+    c.tile = t;
+    c.view = view_of_tile(a.views, a.nv, t);
+    const ViewInfo& vw = a.views[c.view];
+    const int64_t lt = t - vw.tile_off;
+    c.x0 = (int)(lt % vw.tiles_x) * TILE;
+    c.y0 = (int)(lt / vw.tiles_x) * TILE;
+    c.width = vw.width;
+    c.height = vw.height;
+    c.pix_off = vw.pix_off;
+    c.bg[0] = vw.bg[0]; c.bg[1] = vw.bg[1]; c.bg[2] = vw.bg[2];
+    return c;
+}
+
+// Next work item: blockIdx.x when not persistent, else pulled from the queue counter.
+__device__ __forceinline__ int64_t next_tile(const BlendArgs& a, int64_t prev, bool persistent) {
+    if (!persistent) return prev < 0 ? (int64_t)blockIdx.x : a.n_tiles;
+    uint32_t t = 0;
+    if (__lane_id() == 0) t = atomicAdd(a.queue, 1u);
+    t = __shfl(t, 0);
+    return (int64_t)t;
+}
+
+template <int TILE, bool STATS>
+__global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int persistent) {
+    constexpr int PPT = TILE * TILE / 64, ROWS = 64 / TILE;
+    extern __shared__ Staged lds[];
+    const int lane = threadIdx.x;
+    const int lx = lane % TILE, ly = lane / TILE;
+    uint32_t n_blended = 0, n_evaluated = 0;
+    for (int64_t t = next_tile(a, -1, persistent); t < a.n_tiles; t = next_tile(a, t, persistent)) {
+        const TileCtx c = tile_ctx(a, t, TILE);
+        const uint2 rg = a.ranges[t];
+        float T[PPT], C[PPT][3];
+        uint32_t last[PPT];
+        bool done[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            T[j] = 1.0f; C[j][0] = C[j][1] = C[j][2] = 0.0f; last[j] = 0;
+            done[j] = !(c.x0 + lx < c.width && c.y0 + ly + ROWS * j < c.height);
+        }
+        const float px = lx + 0.5f;
+        bool active = true;
+        for (uint32_t base = rg.x; base < rg.y && active; base += batch) {
+            const int cnt = (int)min((uint32_t)batch, rg.y - base);
+            for (int q = lane; q < cnt; q += 64) stage(a, a.vals[base + q], (double)c.x0, (double)c.y0, &lds[q]);
+            __syncthreads();
+            for (int jj = 0; jj < cnt; ++jj) {
+                const Staged s = lds[jj];
+                const uint32_t pos = base + jj - rg.x;
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    if (done[j]) continue;
+                    if (STATS) ++n_evaluated;
+                    float dx, dy, G, alpha;
+                    bool clamped;
+                    if (!frag(s, px, ly + ROWS * j + 0.5f, dx, dy, G, alpha, clamped)) continue;
+                    const float Tn = T[j] * (1.0f - alpha);
+                    if (Tn < kTMin) { done[j] = true; continue; }
+                    if (STATS) ++n_blended;
+                    const float w = alpha * T[j];
+                    C[j][0] = __fmaf_rn(w, s.p2.y, C[j][0]);
+                    C[j][1] = __fmaf_rn(w, s.p2.z, C[j][1]);
+                    C[j][2] = __fmaf_rn(w, s.p2.w, C[j][2]);
+                    T[j] = Tn;
+                    last[j] = pos + 1;
+                }
+                bool mine = false;
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) mine |= !done[j];
+                if (!__any(mine)) { active = false; break; }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int x = c.x0 + lx, y = c.y0 + ly + ROWS * j;
+            if (x >= c.width || y >= c.height) continue;
+            const int64_t p = (int64_t)y * c.width + x;
+            const int64_t plane = (int64_t)c.width * c.height;
+            float* img = a.image + 3 * c.pix_off;
+            img[p] = __fmaf_rn(T[j], c.bg[0], C[j][0]);
+            img[plane + p] = __fmaf_rn(T[j], c.bg[1], C[j][1]);
+            img[2 * plane + p] = __fmaf_rn(T[j], c.bg[2], C[j][2]);
+            a.T_final[c.pix_off + p] = T[j];
+            a.last[c.pix_off + p] = last[j];
+        }
+    }
+    if (STATS) {
+        unsigned long long nb = n_blended, ne = n_evaluated;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            nb += __shfl_xor(nb, d);
+            ne += __shfl_xor(ne, d);
+        }
+        if (lane == 0) {
+            atomicAdd(a.stats, nb);
+            atomicAdd(a.stats + 1, ne);
+        }
+    }
+}
+
+// Sum of v[0..8] over the wave. Afterwards lane 8m (m < 8) holds the total of v[m] and every
+// lane holds the total of v[8] in v8.
+__device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
+    const int lane = __lane_id();
+    float w4[4];
+    const bool b5 = lane & 32;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float send = b5 ? v[i] : v[i + 4];
+        const float keep = b5 ? v[i + 4] : v[i];
+        w4[i] = keep + __shfl_xor(send, 32);
+    }
+    float w2[2];
+    const bool b4 = lane & 16;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float send = b4 ? w4[i] : w4[i + 2];
+        const float keep = b4 ? w4[i + 2] : w4[i];
+        w2[i] = keep + __shfl_xor(send, 16);
+    }
+    const bool b3 = lane & 8;
+    float y = (b3 ? w2[1] : w2[0]) + __shfl_xor(b3 ? w2[0] : w2[1], 8);
+    y += __shfl_xor(y, 4);
+    y += __shfl_xor(y, 2);
+    y += __shfl_xor(y, 1);
+    out = y;
+    float z = v[8];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) z += __shfl_xor(z, d);
+    v8 = z;
+}
+
+template <int TILE>
+__global__ __launch_bounds__(64) void k_blend_bwd(BlendArgs a, int batch, int persistent) {
+    constexpr int PPT = TILE * TILE / 64, ROWS = 64 / TILE;
+    extern __shared__ Staged lds[];
+    uint32_t* lds_id = reinterpret_cast<uint32_t*>(lds + batch);
+    const int lane = threadIdx.x;
+    const int lx = lane % TILE, ly = lane / TILE;
+    const float px = lx + 0.5f;
+    for (int64_t t = next_tile(a, -1, persistent); t < a.n_tiles; t = next_tile(a, t, persistent)) {
+        const TileCtx c = tile_ctx(a, t, TILE);
+        const uint2 rg = a.ranges[t];
+        const int64_t plane = (int64_t)c.width * c.height;
+        float T[PPT], S[PPT][3], dl[PPT][3];
+        uint32_t lst[PPT];
+        uint32_t maxlast = 0;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int x = c.x0 + lx, y = c.y0 + ly + ROWS * j;
+            const bool inside = x < c.width && y < c.height;
+            const int64_t p = (int64_t)y * c.width + x;
+            T[j] = inside ? a.T_final[c.pix_off + p] : 1.0f;
+            lst[j] = inside ? a.last[c.pix_off + p] : 0u;
+            const float* dimg = a.dl + 3 * c.pix_off;
+            dl[j][0] = inside ? dimg[p] : 0.f;
+            dl[j][1] = inside ? dimg[plane + p] : 0.f;
+            dl[j][2] = inside ? dimg[2 * plane + p] : 0.f;
+            S[j][0] = c.bg[0]; S[j][1] = c.bg[1]; S[j][2] = c.bg[2];
+            maxlast = max(maxlast, lst[j]);
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, d));
+        for (uint32_t end = rg.x + maxlast; end > rg.x;) {
+            const uint32_t beg = end - rg.x > (uint32_t)batch ? end - batch : rg.x;
+            const int cnt = (int)(end - beg);
+            for (int q = lane; q < cnt; q += 64) {
+                const uint32_t g = a.vals[end - 1 - q];
+                stage(a, g, (double)c.x0, (double)c.y0, &lds[q]);
+                lds_id[q] = g;
+            }
+            __syncthreads();
+            for (int jj = 0; jj < cnt; ++jj) {
+                const Staged s = lds[jj];
+                const uint32_t pos = end - 1 - jj - rg.x;
+                float acc[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) acc[i] = 0.f;
+                bool contributed = false;
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    if (pos >= lst[j]) continue;
+                    float dx, dy, G, alpha;
+                    bool clamped;
+                    if (!frag(s, px, ly + ROWS * j + 0.5f, dx, dy, G, alpha, clamped)) continue;
+                    contributed = true;
+                    const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - alpha);
+                    const float w = alpha * Ti;
+                    const float d0 = s.p2.y - S[j][0], d1 = s.p2.z - S[j][1], d2 = s.p2.w - S[j][2];
+                    acc[6] = __fmaf_rn(w, dl[j][0], acc[6]);
+                    acc[7] = __fmaf_rn(w, dl[j][1], acc[7]);
+                    acc[8] = __fmaf_rn(w, dl[j][2], acc[8]);
+                    const float dal = Ti * __fmaf_rn(d0, dl[j][0], __fmaf_rn(d1, dl[j][1], d2 * dl[j][2]));
+                    S[j][0] = __fmaf_rn(alpha, d0, S[j][0]);
+                    S[j][1] = __fmaf_rn(alpha, d1, S[j][1]);
+                    S[j][2] = __fmaf_rn(alpha, d2, S[j][2]);
+                    T[j] = Ti;
+                    if (clamped) continue;
+                    const float dq = alpha * dal;
+                    acc[5] = __fmaf_rn(G, dal, acc[5]);
+                    acc[0] = __fmaf_rn(dq, __fmaf_rn(s.p1.z, dx, s.p1.w * dy), acc[0]);
+                    acc[1] = __fmaf_rn(dq, __fmaf_rn(s.p1.w, dx, s.p2.x * dy), acc[1]);
+                    const float hq = -0.5f * dq;
+                    acc[2] = __fmaf_rn(hq, dx * dx, acc[2]);
+                    acc[3] = __fmaf_rn(-dq, dx * dy, acc[3]);
+                    acc[4] = __fmaf_rn(hq, dy * dy, acc[4]);
+                }
+                if (__any(contributed)) {
+                    float tot, tot8;
+                    wave_sum9(acc, tot, tot8);
+                    float* slot = a.grad2d + 9 * (int64_t)lds_id[jj];
+                    if ((lane & 7) == 0) unsafeAtomicAdd(slot + (lane >> 3), tot);
+                    if (lane == 1) unsafeAtomicAdd(slot + 8, tot8);
+                }
+            }
+            __syncthreads();
+            end = beg;
+        }
+    }
+}
+
+constexpr int64_t kPersistentGroups = 256 * 24;  // 24 resident single-wave groups per CU
+
+template <int TILE>
+hipError_t launch_fwd_t(const BlendArgs& a, int batch, bool persistent, hipStream_t stream) {
+    const size_t lds = (size_t)batch * sizeof(Staged);
+    const unsigned grid = (unsigned)(persistent && a.n_tiles > kPersistentGroups ? kPersistentGroups : a.n_tiles);
+    if (a.stats)
+        hipLaunchKernelGGL((k_blend_fwd<TILE, true>), dim3(grid), dim3(64), lds, stream, a, batch, (int)persistent);
+    else
+        hipLaunchKernelGGL((k_blend_fwd<TILE, false>), dim3(grid), dim3(64), lds, stream, a, batch, (int)persistent);
+    return hipGetLastError();
+}
+
+template <int TILE>
+hipError_t launch_bwd_t(const BlendArgs& a, int batch, bool persistent, hipStream_t stream) {
+    const size_t lds = (size_t)batch * (sizeof(Staged) + sizeof(uint32_t));
+    const unsigned grid = (unsigned)(persistent && a.n_tiles > kPersistentGroups ? kPersistentGroups : a.n_tiles);
+    hipLaunchKernelGGL(k_blend_bwd<TILE>, dim3(grid), dim3(64), lds, stream, a, batch, (int)persistent);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int batch, bool persistent, hipStream_t stream) {
+    if (a.n_tiles <= 0) return hipSuccess;
+    switch (tile) {
+        case 8: return launch_fwd_t<8>(a, batch, persistent, stream);
+        case 16: return launch_fwd_t<16>(a, batch, persistent, stream);
+        case 32: return launch_fwd_t<32>(a, batch, persistent, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int batch, bool persistent, hipStream_t stream) {
+    if (a.n_tiles <= 0) return hipSuccess;
+    switch (tile) {
+        case 8: return launch_bwd_t<8>(a, batch, persistent, stream);
+        case 16: return launch_bwd_t<16>(a, batch, persistent, stream);
+        case 32: return launch_bwd_t<32>(a, batch, persistent, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace megs

@@ -1,0 +1,443 @@
+// project.hip -- EWA projection with Spherical-Gaussian colour (forward) and its chain rule
+// back to the raw parameters (backward), gfx950.
+//
+// One thread per Gaussian loops over all views, so the parameter planes are streamed from HBM
+// once per launch (coalesced SoA loads, widened from FP16/BF16 in registers) and the records of
+// every view are written. The camera-space position and pixel mean are computed in FP64 (a few
+// DFMAs; the kernel is HBM-bound), everything else in FP32.
+//
+// Colour: c(d) = c0 + sum_k m_k a_k exp(lambda_k (mu_k . d - 1)) (SG lobe and colour equations,
+// Sec. 3.2), with lambda (mu . d - 1) evaluated as -lambda |mu - d|^2 / 2 for unit mu and d, which
+// is the same quantity without the cancellation of mu . d - 1 near the lobe axis.
+#include "megs_internal.hpp"
+
+namespace megs {
+namespace {
+
+struct Geo {
+    float s[3];
+    float qh[4];
+    float Rq[9];
+    float S3[6];  // xx, xy, xz, yy, yz, zz
+    float o, mp, o_eff;
+    float qnorm;
+    bool ok;
+};
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+template <int K>
+struct Lobes {
+    float ax[K > 0 ? K : 1][3];
+    float lam[K > 0 ? K : 1];
+    float amp[K > 0 ? K : 1][3];
+    float m[K > 0 ? K : 1];
+};
+
+__device__ __forceinline__ void rot_from_quat(const float q[4], float R[9]) {
+    float w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// View-independent part: activations and the 3D covariance.
+__device__ __forceinline__ void load_geo(const SceneDev& sc, int64_t i, float pos[3], Geo& g) {
+    const int64_t n = sc.n;
+    for (int j = 0; j < 3; ++j) pos[j] = load_elem(sc.pos, sc.dt_geom, j * n + i);
+    for (int j = 0; j < 3; ++j) g.s[j] = __expf(load_elem(sc.logscale, sc.dt_geom, j * n + i));
+    float q[4];
+    for (int j = 0; j < 4; ++j) q[j] = load_elem(sc.quat, sc.dt_geom, j * n + i);
+    float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    g.ok = (qq > 0.0f) && isfinite(qq);
+    g.qnorm = sqrtf(qq);
+    float inv = 1.0f / g.qnorm;
+    for (int j = 0; j < 4; ++j) g.qh[j] = q[j] * inv;
+    rot_from_quat(g.qh, g.Rq);
+    float M[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = g.Rq[3 * r + c] * g.s[c];
+    g.S3[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+    g.S3[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+    g.S3[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+    g.S3[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+    g.S3[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+    g.S3[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+    g.o = sigmoidf(load_elem(sc.op_logit, sc.dt_geom, i));
+    g.mp = sc.pmask_logit ? sigmoidf(load_elem(sc.pmask_logit, sc.dt_geom, i)) : 1.0f;
+    g.o_eff = g.o * g.mp;
+}
+
+template <int K>
+__device__ __forceinline__ bool load_lobes(const SceneDev& sc, int64_t i, Lobes<K>& L) {
+    const int64_t n = sc.n;
+    bool ok = true;
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+        float a0 = load_elem(sc.axis, sc.dt_color, (l * 3 + 0) * n + i);
+        float a1 = load_elem(sc.axis, sc.dt_color, (l * 3 + 1) * n + i);
+        float a2 = load_elem(sc.axis, sc.dt_color, (l * 3 + 2) * n + i);
+        L.ax[l][0] = a0; L.ax[l][1] = a1; L.ax[l][2] = a2;
+        float al2 = a0 * a0 + a1 * a1 + a2 * a2;
+        ok = ok && (al2 > 0.0f) && isfinite(al2);
+        L.lam[l] = load_elem(sc.sharp, sc.dt_color, l * n + i);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) L.amp[l][c] = load_elem(sc.amp, sc.dt_amp, (l * 3 + c) * n + i);
+        L.m[l] = sc.lmask_logit ? sigmoidf(load_elem(sc.lmask_logit, sc.dt_color, l * n + i)) : 1.0f;
+    }
+    return ok;
+}
+
+// Per-view projection intermediates (shared by forward and backward so both take the same
+// culling decisions and see the same values).
+struct ViewProj {
+    bool ok;
+    double tx, ty, tz, u, v;
+    float txf, tyf, tzf, xi, eta;
+    bool xclamp, yclamp;
+    float T0[3], T1[3];
+    float A0, B0, C0, det0, det;
+    float conic[3];
+    int32_t radius;
+};
+
+__device__ __forceinline__ void project_view(const Geo& g, const float pos[3], const ViewInfo& vw, ViewProj& p) {
+    p.ok = g.ok;
+    const double px = pos[0], py = pos[1], pz = pos[2];
+    p.tx = fma((double)vw.R[0], px, fma((double)vw.R[1], py, fma((double)vw.R[2], pz, (double)vw.t[0])));
+    p.ty = fma((double)vw.R[3], px, fma((double)vw.R[4], py, fma((double)vw.R[5], pz, (double)vw.t[1])));
+    p.tz = fma((double)vw.R[6], px, fma((double)vw.R[7], py, fma((double)vw.R[8], pz, (double)vw.t[2])));
+    if (!(p.tz > (double)vw.znear)) p.ok = false;
+    if (!(g.o_eff >= kAlphaMin)) p.ok = false;
+    const double rz = 1.0 / p.tz;
+    p.u = fma((double)vw.fx * p.tx, rz, (double)vw.cx);
+    p.v = fma((double)vw.fy * p.ty, rz, (double)vw.cy);
+    p.txf = (float)p.tx; p.tyf = (float)p.ty; p.tzf = (float)p.tz;
+    float rx = (float)(p.tx * rz), ry = (float)(p.ty * rz);
+    p.xclamp = rx < -vw.limx || rx > vw.limx;
+    p.yclamp = ry < -vw.limy || ry > vw.limy;
+    p.xi = fminf(fmaxf(rx, -vw.limx), vw.limx);
+    p.eta = fminf(fmaxf(ry, -vw.limy), vw.limy);
+    const float irz = 1.0f / p.tzf;
+    const float J00 = vw.fx * irz, J02 = -vw.fx * p.xi * irz;
+    const float J11 = vw.fy * irz, J12 = -vw.fy * p.eta * irz;
+    // T = J W: row 0 = J00 W0 + J02 W2, row 1 = J11 W1 + J12 W2
+    for (int c = 0; c < 3; ++c) {
+        p.T0[c] = J00 * vw.R[c] + J02 * vw.R[6 + c];
+        p.T1[c] = J11 * vw.R[3 + c] + J12 * vw.R[6 + c];
+    }
+    // S3 * T0 and S3 * T1
+    const float* S = g.S3;
+    float s0[3] = {S[0] * p.T0[0] + S[1] * p.T0[1] + S[2] * p.T0[2],
+                   S[1] * p.T0[0] + S[3] * p.T0[1] + S[4] * p.T0[2],
+                   S[2] * p.T0[0] + S[4] * p.T0[1] + S[5] * p.T0[2]};
+    float s1[3] = {S[0] * p.T1[0] + S[1] * p.T1[1] + S[2] * p.T1[2],
+                   S[1] * p.T1[0] + S[3] * p.T1[1] + S[4] * p.T1[2],
+                   S[2] * p.T1[0] + S[4] * p.T1[1] + S[5] * p.T1[2]};
+    p.A0 = p.T0[0] * s0[0] + p.T0[1] * s0[1] + p.T0[2] * s0[2];
+    p.B0 = p.T0[0] * s1[0] + p.T0[1] * s1[1] + p.T0[2] * s1[2];
+    p.C0 = p.T1[0] * s1[0] + p.T1[1] * s1[1] + p.T1[2] * s1[2];
+    p.det0 = p.A0 * p.C0 - p.B0 * p.B0;
+    p.det = fmaxf(p.det0, 0.0f) + kDilation * (p.A0 + p.C0) + kDilation * kDilation;
+    const float A = p.A0 + kDilation, C = p.C0 + kDilation;
+    const float idet = 1.0f / p.det;
+    p.conic[0] = C * idet;
+    p.conic[1] = -p.B0 * idet;
+    p.conic[2] = A * idet;
+    const float mid = 0.5f * (A + C);
+    const float lmax = mid + sqrtf(fmaxf(mid * mid - p.det, 0.0f));
+    const float rho = sqrtf(2.0f * __logf(255.0f * g.o_eff) * lmax);
+    const float r = ceilf(rho);
+    if (!(isfinite(p.u) && isfinite(p.v) && isfinite(r)) || fabs(p.u) > kMaxCoord || fabs(p.v) > kMaxCoord ||
+        r > (float)kMaxCoord)
+        p.ok = false;
+    p.radius = p.ok ? (int32_t)r : -1;
+}
+
+// d = (mu - campos) / |mu - campos| and the SG colour; returns false if not finite.
+template <int K>
+__device__ __forceinline__ bool sg_colour(const SceneDev& sc, int64_t i, const float pos[3], const ViewInfo& vw,
+                                          const Lobes<K>& L, float d[3], float& dlen, float rgb[3], float e[K > 0 ? K : 1],
+                                          float muh[K > 0 ? K : 1][3], float dd2[K > 0 ? K : 1]) {
+    const int64_t n = sc.n;
+    float dv[3] = {pos[0] - vw.campos[0], pos[1] - vw.campos[1], pos[2] - vw.campos[2]};
+    dlen = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    const float il = 1.0f / dlen;
+    d[0] = dv[0] * il; d[1] = dv[1] * il; d[2] = dv[2] * il;
+    for (int c = 0; c < 3; ++c) rgb[c] = load_elem(sc.base, sc.dt_color, c * n + i);
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+        const float ia = rsqrtf(L.ax[l][0] * L.ax[l][0] + L.ax[l][1] * L.ax[l][1] + L.ax[l][2] * L.ax[l][2]);
+        float df2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            muh[l][c] = L.ax[l][c] * ia;
+            const float df = muh[l][c] - d[c];
+            df2 += df * df;
+        }
+        dd2[l] = df2;
+        e[l] = __expf(-0.5f * L.lam[l] * df2);
+        const float w = L.m[l] * e[l];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rgb[c] += w * L.amp[l][c];
+    }
+    return isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __restrict__ views, int nv, int tile,
+                                                 Records rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.n) return;
+    float pos[3];
+    Geo g;
+    load_geo(sc, i, pos, g);
+    Lobes<K> L;
+    const bool lobes_ok = load_lobes<K>(sc, i, L);
+    for (int v = 0; v < nv; ++v) {
+        const ViewInfo& vw = views[v];
+        const int64_t r = (int64_t)v * sc.n + i;
+        ViewProj p;
+        project_view(g, pos, vw, p);
+        float d[3], dlen, rgb[3], e[K > 0 ? K : 1], muh[K > 0 ? K : 1][3], dd2[K > 0 ? K : 1];
+        bool ok = p.ok && lobes_ok;
+        if (ok) ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
+        uint32_t nt = 0;
+        if (ok) {
+            int x0, x1, y0, y1;
+            nt = tile_rect(p.u, p.v, p.radius, vw, tile, x0, x1, y0, y1);
+            rec.mean[r] = make_double2(p.u, p.v);
+            rec.conic_o[r] = make_float4(p.conic[0], p.conic[1], p.conic[2], g.o_eff);
+            rec.rgbd[r] = make_float4(rgb[0], rgb[1], rgb[2], p.tzf);
+            rec.radius[r] = p.radius;
+        } else {
+            rec.mean[r] = make_double2(0.0, 0.0);
+            rec.conic_o[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec.rgbd[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec.radius[r] = -1;
+        }
+        rec.ntiles[r] = nt;
+        rec.dkey[r] = nt ? __float_as_uint(p.tzf) : 0xffffffffu;
+    }
+}
+
+// ----------------------------------------------------------------- backward ----
+
+__device__ __forceinline__ void quat_grad(const float q[4], const float gR[9], float gq[4]) {
+    const float w = q[0], x = q[1], y = q[2], z = q[3];
+    // d R / d (w, x, y, z) contracted with gR, for R of a unit quaternion (textbook form)
+    gq[0] = 2.f * (z * (gR[3] - gR[1]) + y * (gR[2] - gR[6]) + x * (gR[7] - gR[5]));
+    gq[1] = 2.f * (y * (gR[1] + gR[3]) + z * (gR[2] + gR[6]) + w * (gR[7] - gR[5])) - 4.f * x * (gR[4] + gR[8]);
+    gq[2] = 2.f * (x * (gR[1] + gR[3]) + w * (gR[2] - gR[6]) + z * (gR[5] + gR[7])) - 4.f * y * (gR[0] + gR[8]);
+    gq[3] = 2.f * (w * (gR[3] - gR[1]) + x * (gR[2] + gR[6]) + y * (gR[5] + gR[7])) - 4.f * z * (gR[0] + gR[4]);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
+                                                     const float* __restrict__ grad2d, GradDev G) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.n) return;
+    const int64_t n = sc.n;
+    float pos[3];
+    Geo g;
+    load_geo(sc, i, pos, g);
+    Lobes<K> L;
+    const bool lobes_ok = load_lobes<K>(sc, i, L);
+
+    float gpos[3] = {0.f, 0.f, 0.f}, gS3[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float gop = 0.f, gpm = 0.f, gbase[3] = {0.f, 0.f, 0.f};
+    constexpr int KK = K > 0 ? K : 1;
+    float gax[KK][3], glam[KK], gamp[KK][3], glm[KK];
+#pragma unroll
+    for (int l = 0; l < KK; ++l) {
+        gax[l][0] = gax[l][1] = gax[l][2] = 0.f;
+        glam[l] = 0.f; glm[l] = 0.f;
+        gamp[l][0] = gamp[l][1] = gamp[l][2] = 0.f;
+    }
+
+    for (int v = 0; v < nv; ++v) {
+        const ViewInfo& vw = views[v];
+        const int64_t r = (int64_t)v * n + i;
+        ViewProj p;
+        project_view(g, pos, vw, p);
+        float d[3], dlen, rgb[3], e[KK], muh[KK][3], dd2[KK];
+        bool ok = p.ok && lobes_ok;
+        if (ok) ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
+        if (!ok) continue;
+        const float* gr = grad2d + 9 * r;
+        const float gu = gr[0], gv = gr[1], ga = gr[2], gb = gr[3], gc = gr[4], go = gr[5];
+        const float gcol[3] = {gr[6], gr[7], gr[8]};
+
+        // colour
+        float gd[3] = {0.f, 0.f, 0.f};
+        for (int c = 0; c < 3; ++c) gbase[c] += gcol[c];
+#pragma unroll
+        for (int l = 0; l < K; ++l) {
+            const float ip = L.amp[l][0] * gcol[0] + L.amp[l][1] * gcol[1] + L.amp[l][2] * gcol[2];
+            const float w = L.m[l] * e[l];
+            for (int c = 0; c < 3; ++c) gamp[l][c] += w * gcol[c];
+            glam[l] += w * (-0.5f * dd2[l]) * ip;
+            const float coef = w * L.lam[l] * ip;
+            const float md = muh[l][0] * d[0] + muh[l][1] * d[1] + muh[l][2] * d[2];
+            const float ial = rsqrtf(L.ax[l][0] * L.ax[l][0] + L.ax[l][1] * L.ax[l][1] + L.ax[l][2] * L.ax[l][2]);
+            for (int c = 0; c < 3; ++c) {
+                gax[l][c] += coef * (d[c] - muh[l][c] * md) * ial;
+                gd[c] += coef * muh[l][c];
+            }
+            glm[l] += L.m[l] * (1.f - L.m[l]) * e[l] * ip;
+        }
+        {
+            const float dg = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+            const float il = 1.0f / dlen;
+            for (int c = 0; c < 3; ++c) gpos[c] += (gd[c] - d[c] * dg) * il;
+        }
+        // opacity and primitive mask
+        gop += go * g.mp * g.o * (1.f - g.o);
+        gpm += go * g.o * g.mp * (1.f - g.mp);
+
+        // conic = (C, -B, A) / det, A = A0 + h, C = C0 + h
+        const float A = p.A0 + kDilation, C = p.C0 + kDilation, B = p.B0;
+        const float idet = 1.0f / p.det;
+        const float gdet = -(ga * C - gb * B + gc * A) * idet * idet;
+        float gA0 = gc * idet, gC0 = ga * idet, gB0 = -gb * idet;
+        if (p.det0 > 0.f) {
+            gA0 += gdet * C;
+            gC0 += gdet * A;
+            gB0 -= 2.f * B * gdet;
+        } else {
+            gA0 += gdet * kDilation;
+            gC0 += gdet * kDilation;
+        }
+        // Sigma2 entries A0 = T0 S T0', B0 = T0 S T1', C0 = T1 S T1'
+        const float* T0 = p.T0;
+        const float* T1 = p.T1;
+        gS3[0] += gA0 * T0[0] * T0[0] + gB0 * T0[0] * T1[0] + gC0 * T1[0] * T1[0];
+        gS3[3] += gA0 * T0[1] * T0[1] + gB0 * T0[1] * T1[1] + gC0 * T1[1] * T1[1];
+        gS3[5] += gA0 * T0[2] * T0[2] + gB0 * T0[2] * T1[2] + gC0 * T1[2] * T1[2];
+        gS3[1] += 2.f * gA0 * T0[0] * T0[1] + gB0 * (T0[0] * T1[1] + T1[0] * T0[1]) + 2.f * gC0 * T1[0] * T1[1];
+        gS3[2] += 2.f * gA0 * T0[0] * T0[2] + gB0 * (T0[0] * T1[2] + T1[0] * T0[2]) + 2.f * gC0 * T1[0] * T1[2];
+        gS3[4] += 2.f * gA0 * T0[1] * T0[2] + gB0 * (T0[1] * T1[2] + T1[1] * T0[2]) + 2.f * gC0 * T1[1] * T1[2];
+        // gradient w.r.t. T rows: dA0/dT0 = 2 S T0, dB0/dT0 = S T1, dB0/dT1 = S T0, dC0/dT1 = 2 S T1
+        const float* S = g.S3;
+        const float sT0[3] = {S[0] * T0[0] + S[1] * T0[1] + S[2] * T0[2], S[1] * T0[0] + S[3] * T0[1] + S[4] * T0[2],
+                              S[2] * T0[0] + S[4] * T0[1] + S[5] * T0[2]};
+        const float sT1[3] = {S[0] * T1[0] + S[1] * T1[1] + S[2] * T1[2], S[1] * T1[0] + S[3] * T1[1] + S[4] * T1[2],
+                              S[2] * T1[0] + S[4] * T1[1] + S[5] * T1[2]};
+        float gT0[3], gT1[3];
+        for (int c = 0; c < 3; ++c) {
+            gT0[c] = 2.f * gA0 * sT0[c] + gB0 * sT1[c];
+            gT1[c] = 2.f * gC0 * sT1[c] + gB0 * sT0[c];
+        }
+        // T0 = J00 W0 + J02 W2, T1 = J11 W1 + J12 W2 (W rows of the camera rotation)
+        const float* W = vw.R;
+        const float gJ00 = gT0[0] * W[0] + gT0[1] * W[1] + gT0[2] * W[2];
+        const float gJ02 = gT0[0] * W[6] + gT0[1] * W[7] + gT0[2] * W[8];
+        const float gJ11 = gT1[0] * W[3] + gT1[1] * W[4] + gT1[2] * W[5];
+        const float gJ12 = gT1[0] * W[6] + gT1[1] * W[7] + gT1[2] * W[8];
+        const float tx = p.txf, ty = p.tyf, tz = p.tzf;
+        const float iz = 1.0f / tz, iz2 = iz * iz, iz3 = iz2 * iz;
+        const float fx = vw.fx, fy = vw.fy;
+        float gt[3];
+        // J00 = fx/tz; J02 = -fx xi/tz (xi = tx/tz unless clamped); J11, J12 likewise
+        gt[0] = p.xclamp ? 0.f : gJ02 * (-fx * iz2);
+        gt[1] = p.yclamp ? 0.f : gJ12 * (-fy * iz2);
+        gt[2] = -(gJ00 * fx + gJ11 * fy) * iz2 + gJ02 * (p.xclamp ? fx * p.xi * iz2 : 2.f * fx * tx * iz3) +
+                gJ12 * (p.yclamp ? fy * p.eta * iz2 : 2.f * fy * ty * iz3);
+        // pixel mean u = fx tx / tz + cx, v = fy ty / tz + cy
+        gt[0] += gu * fx * iz;
+        gt[1] += gv * fy * iz;
+        gt[2] -= (gu * fx * tx + gv * fy * ty) * iz2;
+        // t = W mu + t_c
+        for (int c = 0; c < 3; ++c) gpos[c] += W[c] * gt[0] + W[3 + c] * gt[1] + W[6 + c] * gt[2];
+    }
+
+    // S3 = M M', M = Rq diag(s): dL/dM = (G + G') M with G the full symmetric gradient
+    // (off-diagonal entries of gS3 hold the sum of both symmetric positions).
+    float Gf[9] = {gS3[0], 0.5f * gS3[1], 0.5f * gS3[2], 0.5f * gS3[1], gS3[3], 0.5f * gS3[4],
+                   0.5f * gS3[2], 0.5f * gS3[4], gS3[5]};
+    float M[9];
+    for (int rr = 0; rr < 3; ++rr)
+        for (int c = 0; c < 3; ++c) M[3 * rr + c] = g.Rq[3 * rr + c] * g.s[c];
+    float gR[9], gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
+    if (g.ok) {  // a zero quaternion is culled in every view and gets zero gradients
+        for (int rr = 0; rr < 3; ++rr)
+            for (int c = 0; c < 3; ++c) {
+                const float gM = 2.f * (Gf[3 * rr + 0] * M[c] + Gf[3 * rr + 1] * M[3 + c] + Gf[3 * rr + 2] * M[6 + c]);
+                gR[3 * rr + c] = gM * g.s[c];
+                gs[c] += gM * g.Rq[3 * rr + c];
+            }
+        quat_grad(g.qh, gR, gq);
+        const float qd = g.qh[0] * gq[0] + g.qh[1] * gq[1] + g.qh[2] * gq[2] + g.qh[3] * gq[3];
+        const float iq = 1.0f / g.qnorm;
+        for (int c = 0; c < 4; ++c) gq[c] = (gq[c] - g.qh[c] * qd) * iq;
+        for (int c = 0; c < 3; ++c) gs[c] *= g.s[c];
+    }
+
+    for (int c = 0; c < 3; ++c) G.pos[c * n + i] = gpos[c];
+    for (int c = 0; c < 3; ++c) G.logscale[c * n + i] = gs[c];
+    for (int c = 0; c < 4; ++c) G.quat[c * n + i] = gq[c];
+    G.op_logit[i] = gop;
+    if (G.pmask_logit) G.pmask_logit[i] = gpm;
+    for (int c = 0; c < 3; ++c) G.base[c * n + i] = gbase[c];
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+        for (int c = 0; c < 3; ++c) G.axis[(l * 3 + c) * n + i] = gax[l][c];
+        G.sharp[l * n + i] = glam[l];
+        for (int c = 0; c < 3; ++c) G.amp[(l * 3 + c) * n + i] = gamp[l][c];
+        if (G.lmask_logit) G.lmask_logit[l * n + i] = glm[l];
+    }
+}
+
+template <int K>
+hipError_t dispatch_fwd(const SceneDev& sc, const ViewInfo* views, int nv, int tile, const Records& rec,
+                        hipStream_t stream) {
+    const int64_t blocks = (sc.n + 255) / 256;
+    hipLaunchKernelGGL(k_project<K>, dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, tile, rec);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t dispatch_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d, const GradDev& g,
+                        hipStream_t stream) {
+    const int64_t blocks = (sc.n + 255) / 256;
+    hipLaunchKernelGGL(k_project_bwd<K>, dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, grad2d, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_project(const SceneDev& sc, const ViewInfo* views, int nv, int tile, const Records& rec,
+                          hipStream_t stream) {
+    if (sc.n == 0) return hipSuccess;
+    switch (sc.k) {
+        case 0: return dispatch_fwd<0>(sc, views, nv, tile, rec, stream);
+        case 1: return dispatch_fwd<1>(sc, views, nv, tile, rec, stream);
+        case 2: return dispatch_fwd<2>(sc, views, nv, tile, rec, stream);
+        case 3: return dispatch_fwd<3>(sc, views, nv, tile, rec, stream);
+        case 4: return dispatch_fwd<4>(sc, views, nv, tile, rec, stream);
+        case 5: return dispatch_fwd<5>(sc, views, nv, tile, rec, stream);
+        case 6: return dispatch_fwd<6>(sc, views, nv, tile, rec, stream);
+        case 7: return dispatch_fwd<7>(sc, views, nv, tile, rec, stream);
+        case 8: return dispatch_fwd<8>(sc, views, nv, tile, rec, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_project_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d,
+                              const GradDev& g, hipStream_t stream) {
+    if (sc.n == 0) return hipSuccess;
+    switch (sc.k) {
+        case 0: return dispatch_bwd<0>(sc, views, nv, grad2d, g, stream);
+        case 1: return dispatch_bwd<1>(sc, views, nv, grad2d, g, stream);
+        case 2: return dispatch_bwd<2>(sc, views, nv, grad2d, g, stream);
+        case 3: return dispatch_bwd<3>(sc, views, nv, grad2d, g, stream);
+        case 4: return dispatch_bwd<4>(sc, views, nv, grad2d, g, stream);
+        case 5: return dispatch_bwd<5>(sc, views, nv, grad2d, g, stream);
+        case 6: return dispatch_bwd<6>(sc, views, nv, grad2d, g, stream);
+        case 7: return dispatch_bwd<7>(sc, views, nv, grad2d, g, stream);
+        case 8: return dispatch_bwd<8>(sc, views, nv, grad2d, g, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace megs

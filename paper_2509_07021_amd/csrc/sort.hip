@@ -1,0 +1,433 @@
+// sort.hip -- fills, exclusive scan, tile|depth key emission, stable LSD radix sort and
+// per-tile ranges for the tile/depth key table (gfx950, wave64).
+//
+// The radix sort is reduce-then-scan with a fixed grid: each workgroup owns a contiguous chunk of
+// the input, so the per-pass digit counts form a [256][G] table whose digit-major exclusive scan
+// gives every workgroup its scatter base per digit. Ranks inside a workgroup are stable: each
+// wave64 owns a contiguous segment of a 2048-item tile, equal digits within a 64-item step are
+// found with eight 64-bit ballots, and per-wave running counts live in LDS. There are no
+// inter-workgroup waits, so no pass depends on forward progress of other workgroups. The element
+// count is read on device, which lets the same launches run inside a captured graph.
+#include "megs_internal.hpp"
+
+namespace megs {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanIpt = 8;
+constexpr int kScanTile = kScanThreads * kScanIpt;  // 2048
+
+constexpr int kRsThreads = 256;
+constexpr int kRsWaves = kRsThreads / kWave;
+constexpr int kRsIpt = 8;
+constexpr int kRsTile = kRsThreads * kRsIpt;  // 2048
+constexpr int kRsDigits = 256;
+constexpr int kRsMaxBlocks = 1024;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t lane = __lane_id();
+    return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_iota(uint32_t* p, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (uint32_t)i;
+}
+
+// ------------------------------------------------------------------- scan ----
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of the 256 threads' values; returns the thread's exclusive prefix and the total.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* lds4, uint32_t& total) {
+    const int lane = __lane_id(), w = threadIdx.x / kWave;
+    uint32_t inc = wave_incl_scan(x);
+    if (lane == kWave - 1) lds4[w] = inc;
+    __syncthreads();
+    uint32_t wbase = 0;
+    total = 0;
+    for (int i = 0; i < 4; ++i) {
+        uint32_t s = lds4[i];
+        if (i < w) wbase += s;
+        total += s;
+    }
+    __syncthreads();
+    return wbase + inc - x;
+}
+
+__device__ __forceinline__ uint32_t scan_load(const uint32_t* x, const uint32_t* idx, int64_t i, int64_t n) {
+    if (i >= n) return 0u;
+    return x[idx ? idx[i] : i];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* x, const uint32_t* idx, int64_t n,
+                                                              uint32_t* partial) {
+    __shared__ uint32_t lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int j = 0; j < kScanIpt; ++j) s += scan_load(x, idx, base + j * kScanThreads + threadIdx.x, n);
+    uint32_t total;
+    block_excl_scan256(s, lds, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Single workgroup: exclusive scan of partial[0..m) in place; writes the grand total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(uint32_t* partial, int64_t m, uint32_t* total_out) {
+    __shared__ uint32_t lds[4];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < m; base += kScanTile) {
+        uint32_t v[kScanIpt];
+        uint32_t s = 0;
+        for (int j = 0; j < kScanIpt; ++j) {
+            int64_t i = base + threadIdx.x * kScanIpt + j;
+            v[j] = i < m ? partial[i] : 0u;
+            s += v[j];
+        }
+        uint32_t total;
+        uint32_t ex = block_excl_scan256(s, lds, total) + carry;
+        for (int j = 0; j < kScanIpt; ++j) {
+            int64_t i = base + threadIdx.x * kScanIpt + j;
+            if (i < m) partial[i] = ex;
+            ex += v[j];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* x, const uint32_t* idx, int64_t n,
+                                                            const uint32_t* partial, uint32_t* out) {
+    __shared__ uint32_t lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
+    uint32_t v[kScanIpt];
+    uint32_t s = 0;
+    for (int j = 0; j < kScanIpt; ++j) {
+        v[j] = scan_load(x, idx, base + j, n);
+        s += v[j];
+    }
+    uint32_t total;
+    uint32_t ex = block_excl_scan256(s, lds, total) + partial[blockIdx.x];
+    for (int j = 0; j < kScanIpt; ++j) {
+        if (base + j < n) out[base + j] = ex;
+        ex += v[j];
+    }
+}
+
+// ------------------------------------------------------------- radix sort ----
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
+    return (uint32_t)(key >> shift) & mask;
+}
+
+// Lanes of the wave holding the same 8-bit digit as this lane, restricted to `valid`.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
+    uint64_t peers = valid;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+struct Chunk {
+    int64_t n, t0, t1;
+};
+
+__device__ __forceinline__ Chunk chunk_of(const uint32_t* d_count, int64_t max_count) {
+    Chunk c;
+    int64_t n = (int64_t)*d_count;
+    c.n = n < max_count ? n : max_count;
+    const int64_t tiles = (c.n + kRsTile - 1) / kRsTile;
+    const int64_t per = (tiles + gridDim.x - 1) / gridDim.x;
+    c.t0 = (int64_t)blockIdx.x * per;
+    c.t1 = c.t0 + per < tiles ? c.t0 + per : tiles;
+    return c;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kRsThreads) void k_radix_upsweep(const K* __restrict__ keys, const uint32_t* d_count,
+                                                              int64_t max_count, int shift, uint32_t mask,
+                                                              uint32_t* __restrict__ counts) {
+    __shared__ uint32_t hist[kRsWaves][kRsDigits];
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    for (int i = threadIdx.x; i < kRsWaves * kRsDigits; i += kRsThreads) (&hist[0][0])[i] = 0u;
+    __syncthreads();
+    const Chunk c = chunk_of(d_count, max_count);
+    for (int64_t t = c.t0; t < c.t1; ++t) {
+        const int64_t base = t * kRsTile + (int64_t)w * kWave * kRsIpt + lane;
+        for (int j = 0; j < kRsIpt; ++j) {
+            const int64_t idx = base + j * kWave;
+            const bool ok = idx < c.n;
+            const uint32_t d = ok ? digit_of(keys[idx], shift, mask) : 0u;
+            const uint64_t peers = match_digit(d, __ballot(ok));
+            if (ok && (__ffsll((unsigned long long)peers) - 1) == lane) hist[w][d] += (uint32_t)__popcll(peers);
+        }
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) {
+        uint32_t s = 0;
+        for (int ww = 0; ww < kRsWaves; ++ww) s += hist[ww][d];
+        counts[(int64_t)d * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// Single workgroup exclusive scan of the digit-major count table (in place).
+__global__ __launch_bounds__(kScanThreads) void k_radix_scan(uint32_t* counts, int64_t m) {
+    __shared__ uint32_t lds[4];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < m; base += kScanTile) {
+        uint32_t v[kScanIpt];
+        uint32_t s = 0;
+        for (int j = 0; j < kScanIpt; ++j) {
+            int64_t i = base + threadIdx.x * kScanIpt + j;
+            v[j] = i < m ? counts[i] : 0u;
+            s += v[j];
+        }
+        uint32_t total;
+        uint32_t ex = block_excl_scan256(s, lds, total) + carry;
+        for (int j = 0; j < kScanIpt; ++j) {
+            int64_t i = base + threadIdx.x * kScanIpt + j;
+            if (i < m) counts[i] = ex;
+            ex += v[j];
+        }
+        carry += total;
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kRsThreads) void k_radix_downsweep(const K* __restrict__ keys_in,
+                                                                const uint32_t* __restrict__ vals_in,
+                                                                K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                                const uint32_t* d_count, int64_t max_count, int shift,
+                                                                uint32_t mask, const uint32_t* __restrict__ offsets) {
+    __shared__ uint32_t run_off[kRsDigits];
+    __shared__ uint32_t whist[kRsWaves][kRsDigits];
+    __shared__ uint32_t tile_total[kRsDigits];
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) run_off[d] = offsets[(int64_t)d * gridDim.x + blockIdx.x];
+    const Chunk c = chunk_of(d_count, max_count);
+    const uint64_t lt = lanemask_lt();
+    for (int64_t t = c.t0; t < c.t1; ++t) {
+        for (int i = threadIdx.x; i < kRsWaves * kRsDigits; i += kRsThreads) (&whist[0][0])[i] = 0u;
+        __syncthreads();
+        K key[kRsIpt];
+        uint32_t val[kRsIpt], dig[kRsIpt], rank[kRsIpt];
+        const int64_t base = t * kRsTile + (int64_t)w * kWave * kRsIpt + lane;
+        for (int j = 0; j < kRsIpt; ++j) {
+            const int64_t idx = base + j * kWave;
+            const bool ok = idx < c.n;
+            key[j] = ok ? keys_in[idx] : K(0);
+            val[j] = ok ? vals_in[idx] : 0u;
+            const uint32_t d = ok ? digit_of(key[j], shift, mask) : 0u;
+            dig[j] = ok ? d : 0xffffffffu;
+            const uint64_t peers = match_digit(d, __ballot(ok));
+            uint32_t before = 0;
+            if (ok) before = whist[w][d];
+            rank[j] = before + (uint32_t)__popcll(peers & lt);
+            if (ok && (__ffsll((unsigned long long)peers) - 1) == lane) whist[w][d] = before + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) {
+            uint32_t acc = 0;
+            for (int ww = 0; ww < kRsWaves; ++ww) {
+                const uint32_t cnt = whist[ww][d];
+                whist[ww][d] = acc;
+                acc += cnt;
+            }
+            tile_total[d] = acc;
+        }
+        __syncthreads();
+        for (int j = 0; j < kRsIpt; ++j) {
+            if (dig[j] == 0xffffffffu) continue;
+            const uint32_t dst = run_off[dig[j]] + whist[w][dig[j]] + rank[j];
+            keys_out[dst] = key[j];
+            vals_out[dst] = val[j];
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) run_off[d] += tile_total[d];
+        __syncthreads();
+    }
+}
+
+template <typename K>
+hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, const uint32_t* d_count,
+                      int64_t max_count, int begin_bit, int end_bit, void* scratch, hipStream_t stream, bool* in_alt) {
+    *in_alt = false;
+    if (max_count <= 0 || end_bit <= begin_bit) return hipSuccess;
+    int64_t tiles = (max_count + kRsTile - 1) / kRsTile;
+    const int G = (int)(tiles < kRsMaxBlocks ? tiles : kRsMaxBlocks);
+    uint32_t* counts = static_cast<uint32_t*>(scratch);
+    K* src_k = keys; uint32_t* src_v = vals;
+    K* dst_k = keys_alt; uint32_t* dst_v = vals_alt;
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        const int bits = end_bit - shift < 8 ? end_bit - shift : 8;
+        const uint32_t mask = (1u << bits) - 1u;
+        hipLaunchKernelGGL(k_radix_upsweep<K>, dim3(G), dim3(kRsThreads), 0, stream, src_k, d_count, max_count, shift,
+                           mask, counts);
+        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kScanThreads), 0, stream, counts, (int64_t)kRsDigits * G);
+        hipLaunchKernelGGL(k_radix_downsweep<K>, dim3(G), dim3(kRsThreads), 0, stream, src_k, src_v, dst_k, dst_v,
+                           d_count, max_count, shift, mask, counts);
+        K* tk = src_k; src_k = dst_k; dst_k = tk;
+        uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
+        *in_alt = !*in_alt;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- key emission ----
+
+__global__ void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t n, int tile,
+                       const uint32_t* __restrict__ order, const uint32_t* __restrict__ offsets, int64_t n_records,
+                       uint32_t* __restrict__ tile_keys, uint64_t* __restrict__ keys64, uint32_t* __restrict__ vals,
+                       int64_t capacity, int32_t* status) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_records) return;
+    const uint32_t g = order ? order[k] : (uint32_t)k;
+    const uint32_t nt = rec.ntiles[g];
+    if (nt == 0) return;
+    const int v = (int)(g / n);
+    const ViewInfo& vw = views[v];
+    int x0, x1, y0, y1;
+    const double2 m = rec.mean[g];
+    tile_rect(m.x, m.y, rec.radius[g], vw, tile, x0, x1, y0, y1);
+    const uint64_t depth_bits = __float_as_uint(rec.rgbd[g].w);
+    int64_t pos = offsets[k];
+    if (pos + (int64_t)nt > capacity) status[1] = 1;
+    for (int ty = y0; ty <= y1; ++ty)
+        for (int tx = x0; tx <= x1; ++tx, ++pos) {
+            if (pos >= capacity) return;
+            const uint64_t gt = (uint64_t)(vw.tile_off + (int64_t)ty * vw.tiles_x + tx);
+            if (tile_keys) tile_keys[pos] = (uint32_t)gt;
+            if (keys64) keys64[pos] = (gt << 32) | depth_bits;
+            vals[pos] = g;
+        }
+}
+
+__global__ void k_clamp_count(const uint32_t* total, int64_t capacity, uint32_t* count, int32_t* status) {
+    const uint32_t t = *total;
+    *count = (int64_t)t > capacity ? (uint32_t)capacity : t;
+    status[0] = (int32_t)t;
+    if ((int64_t)t > capacity) status[1] = 1;
+}
+
+template <typename K>
+__global__ void k_ranges(const K* __restrict__ keys, int shift, const uint32_t* d_count, int64_t max_count,
+                         uint2* __restrict__ ranges) {
+    int64_t n = (int64_t)*d_count;
+    if (n > max_count) n = max_count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t t = (uint32_t)(keys[i] >> shift);
+        if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != t) ranges[t].x = (uint32_t)i;
+        if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != t) ranges[t].y = (uint32_t)(i + 1);
+    }
+}
+
+inline unsigned grid_for(int64_t count, int threads, int64_t cap = 65536) {
+    int64_t b = (count + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, 256, 8192)), dim3(256), 0, stream, p, value, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(uint32_t* p, int64_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(count, 256, 8192)), dim3(256), 0, stream, p, count);
+    return hipGetLastError();
+}
+
+size_t scan_scratch_bytes(int64_t n) {
+    const int64_t blocks = (n + kScanTile - 1) / kScanTile;
+    return (size_t)((blocks > 0 ? blocks : 1) * sizeof(uint32_t));
+}
+
+hipError_t launch_scan(const uint32_t* x, const uint32_t* idx, int64_t n, uint32_t* out, uint32_t* total,
+                       void* scratch, hipStream_t stream) {
+    if (n <= 0) {
+        return launch_fill_u32(total, 0u, 1, stream);
+    }
+    const int64_t blocks = (n + kScanTile - 1) / kScanTile;
+    uint32_t* partial = static_cast<uint32_t*>(scratch);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream, x, idx, n, partial);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, stream, partial, blocks, total);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream, x, idx, n, partial, out);
+    return hipGetLastError();
+}
+
+size_t radix_scratch_bytes(int64_t max_count) {
+    const int64_t tiles = (max_count + kRsTile - 1) / kRsTile;
+    const int64_t G = tiles < kRsMaxBlocks ? (tiles > 0 ? tiles : 1) : kRsMaxBlocks;
+    return (size_t)(kRsDigits * G * sizeof(uint32_t));
+}
+
+hipError_t launch_radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                                 const uint32_t* d_count, int64_t max_count, int begin_bit, int end_bit,
+                                 void* scratch, hipStream_t stream, bool* in_alt) {
+    return radix_sort<uint32_t>(keys, vals, keys_alt, vals_alt, d_count, max_count, begin_bit, end_bit, scratch,
+                                stream, in_alt);
+}
+
+hipError_t launch_radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                                 const uint32_t* d_count, int64_t max_count, int begin_bit, int end_bit,
+                                 void* scratch, hipStream_t stream, bool* in_alt) {
+    return radix_sort<uint64_t>(keys, vals, keys_alt, vals_alt, d_count, max_count, begin_bit, end_bit, scratch,
+                                stream, in_alt);
+}
+
+hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_t n, int tile,
+                       const uint32_t* order, const uint32_t* offsets, int64_t n_records,
+                       uint32_t* tile_keys, uint64_t* keys64, uint32_t* vals, int64_t capacity,
+                       int32_t* status, hipStream_t stream) {
+    (void)nv;
+    if (n_records <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_records + 255) / 256)), dim3(256), 0, stream, rec, views, n, tile,
+                       order, offsets, n_records, tile_keys, keys64, vals, capacity, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges_u32(const uint32_t* tile_keys, const uint32_t* d_count, int64_t max_count, uint2* ranges,
+                             hipStream_t stream) {
+    if (max_count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid_for(max_count, 256)), dim3(256), 0, stream, tile_keys, 0,
+                       d_count, max_count, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges_u64(const uint64_t* keys, const uint32_t* d_count, int64_t max_count, uint2* ranges,
+                             hipStream_t stream) {
+    if (max_count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(grid_for(max_count, 256)), dim3(256), 0, stream, keys, 32, d_count,
+                       max_count, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_clamp_count(const uint32_t* total, int64_t capacity, uint32_t* count, int32_t* status,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(k_clamp_count, dim3(1), dim3(1), 0, stream, total, capacity, count, status);
+    return hipGetLastError();
+}
+
+}  // namespace megs

@@ -301,6 +301,19 @@ def make_cameras(w: Workload) -> list:
     raise ValueError(w.cameras)
 
 
+def ring_cameras(nv: int, seed: int, resolution=(1920, 1080), radius: float = 6.0) -> list:
+    """nv cameras on a ring of the given radius around the origin, elevation jittered by up to
+    15 degrees (seeded), all at one resolution."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    cams = []
+    for i in range(nv):
+        az = 2.0 * math.pi * i / nv
+        el = math.radians(rng.uniform(-15.0, 15.0))
+        eye = radius * np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
+        cams.append(look_at(eye, *resolution))
+    return cams
+
+
 def make_workload(name: str, n: Optional[int] = None):
     """(scene, cameras) for a named workload; n overrides the Gaussian count."""
     w = WORKLOADS[name]

@@ -1,0 +1,101 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI and pull every stage's
+buffers back to numpy; compare against the FP64 oracle under the tolerances of the tests."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from paper_2509_07021_amd import render as R
+from paper_2509_07021_amd import scenes as S
+
+IMG_TOL = 1e-5          # max abs image difference (FP32 path vs FP64 oracle)
+GRAD_REL = 1e-4         # per-tensor relative L2 and per-element relative tolerance
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def flat_weights(weights) -> torch.Tensor:
+    return torch.from_numpy(np.concatenate([w.reshape(-1) for w in weights]).astype(np.float32)).cuda()
+
+
+def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
+    """Forward (and backward when weights are given) through the C ABI; all stage buffers as numpy."""
+    ds = R.DeviceScene.from_scene(scene)
+    fr = R.forward(ds, cams, cfg)
+    torch.cuda.synchronize()
+    st = fr.state
+    nr = scene.n * len(cams)
+    P = int(st.n_pairs)
+    T = int(st.n_tiles)
+    npix = int(st.n_pixels)
+    out = {"frame": fr, "dscene": ds, "n_pairs": P}
+    out["images"] = [x.cpu().numpy().astype(np.float64) for x in R.split_images(fr.images, cams)]
+    if nr:
+        out["mean"] = fr.buffer("mean", 2 * nr, torch.float64).view(nr, 2).cpu().numpy()
+        out["conic_o"] = fr.buffer("conic_o", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
+        out["rgbd"] = fr.buffer("rgbd", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
+        out["radius"] = fr.buffer("radius", nr, torch.int32).cpu().numpy()
+        out["ntiles"] = fr.buffer("ntiles", nr, torch.int32).cpu().numpy().view(np.uint32)
+    if P:
+        out["vals"] = fr.buffer("vals", P, torch.int32).cpu().numpy().view(np.uint32)
+        if st.tile_keys:
+            out["tile_keys"] = fr.buffer("tile_keys", P, torch.int32).cpu().numpy().view(np.uint32)
+        if st.keys64:
+            out["keys64"] = fr.buffer("keys64", P, torch.int64).cpu().numpy().view(np.uint64)
+    else:
+        out["vals"] = np.zeros(0, np.uint32)
+    out["ranges"] = fr.buffer("ranges", 2 * T, torch.int32).view(T, 2).cpu().numpy().view(np.uint32)
+    out["T_final"] = fr.buffer("T_final", npix, torch.float32).cpu().numpy()
+    out["last"] = fr.buffer("last", npix, torch.int32).cpu().numpy().view(np.uint32)
+    if weights is not None:
+        nblocks = len(fr.alloc.blocks)
+        grads = R.backward(ds, fr, flat_weights(weights))
+        torch.cuda.synchronize()
+        out["grads"] = {p: (None if g is None else g.cpu().numpy().astype(np.float64)) for p, g in grads.items()}
+        g2 = fr.alloc.blocks[nblocks]
+        out["grad2d"] = g2[: nr * 9 * 4].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
+    return out
+
+
+def gpu_records(g: dict) -> dict:
+    """The GPU's records in the oracle's record layout (float64 copies of the stored values)."""
+    m, co, cd = g["mean"], g["conic_o"], g["rgbd"]
+    return {"u": m[:, 0].copy(), "v": m[:, 1].copy(), "depth": cd[:, 3].astype(np.float64),
+            "conic": co[:, :3].astype(np.float64), "o": co[:, 3].astype(np.float64),
+            "rgb": cd[:, :3].astype(np.float64), "valid": (g["radius"] >= 0).astype(np.int32),
+            "radius": g["radius"].astype(np.int32)}
+
+
+def view_pixels(cams, vi):
+    off = sum(c.width * c.height for c in cams[:vi])
+    return off, cams[vi].width * cams[vi].height
+
+
+def grad_close(name, g, ref, rel=GRAD_REL, abs_sum=None):
+    """Gradient parity.
+
+    Per tensor: ||g - ref||_2 / ||ref||_2 <= rel (the stated 1e-4 relative tolerance).
+    Per element, as a guard against localised errors: when abs_sum (the oracle's sum of the
+    absolute values of the contributions summed into each element) is given,
+    |g - ref| <= rel * (|ref| + abs_sum); otherwise |g - ref| <= rel * |ref| + 1e-2 * rel * max|ref|.
+    Summing FP32 terms in any order errs relative to the terms' absolute sum, not to their
+    (possibly cancelling) total, which is what both forms allow for.
+    """
+    scale = np.abs(ref).max() if ref.size else 0.0
+    if scale == 0:
+        assert np.abs(g).max() == 0, name
+        return 0.0
+    d = np.abs(g - ref)
+    l2 = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    assert l2 <= rel, f"{name}: relative L2 {l2:.3e}"
+    if abs_sum is not None:
+        bound = rel * (np.abs(ref) + abs_sum)
+    else:
+        bound = rel * np.abs(ref) + 1e-2 * rel * scale
+    bad = d > bound
+    i = int(np.argmax(d / bound))
+    assert not bad.any(), (f"{name}: {bad.sum()} elements over; worst {(d / bound).max():.2f}x at {i}: "
+                           f"got {g[i]:.6e}, oracle {ref[i]:.6e}")
+    return l2

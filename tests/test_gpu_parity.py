@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, stage by stage and end
+to end. Tolerances: images 1e-5 max abs; gradients 1e-4 relative per tensor (L2), with a
+per-element guard scaled by each element's absolute contribution sum (see gpu_util.grad_close);
+keys, order and ranges bit-exact given the same record means, depths and radii. Pixels whose oracle decisions lie within the threshold
+bands are excluded from image comparisons and get zero loss weight in gradient comparisons.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_07021_amd import render as R
+from paper_2509_07021_amd import scenes as S
+
+from gpu_util import IMG_TOL, grad_close, gpu_records, gpu_run, log, view_pixels
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - the marker keeps these off CPU runs
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _oracle_masked_weights(scene, cams, tile, seed):
+    """Loss weights with zeros on pixels the oracle flags as near a decision threshold."""
+    fwd = O.render(scene.widened(), scene.k, cams, tile)
+    w = S.loss_weights(cams, seed)
+    wm = [wi * (1 - vw["flag"])[None].astype(np.float32) for wi, vw in zip(w, fwd["views"])]
+    return fwd, wm
+
+
+def _check_records(g, fwd, n_views):
+    rec = fwd["records"]
+    valid_o = rec["valid"].astype(bool)
+    valid_g = g["radius"] >= 0
+    assert np.array_equal(valid_o, valid_g), f"{np.sum(valid_o != valid_g)} culling decisions differ"
+    v = valid_g
+    np.testing.assert_allclose(g["mean"][v, 0], rec["u"][v], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(g["mean"][v, 1], rec["v"][v], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(g["rgbd"][v, 3], rec["depth"][v], rtol=1e-6)
+    np.testing.assert_allclose(g["conic_o"][v, :3], rec["conic"][v], rtol=2e-5,
+                               atol=2e-5 * np.abs(rec["conic"][v]).max())
+    np.testing.assert_allclose(g["conic_o"][v, 3], rec["o"][v], rtol=2e-6)
+    np.testing.assert_allclose(g["rgbd"][v, :3], rec["rgb"][v], rtol=0, atol=2e-6)
+    dr = np.abs(g["radius"][v] - rec["radius"][v])
+    assert dr.max() <= 1 and (dr > 0).mean() < 1e-3
+
+
+def _check_key_stage(g, cams, tile, n):
+    """Keys, order and ranges from the GPU's own records, bit-exact against the oracle's table."""
+    rec = gpu_records(g)
+    rec_view = np.repeat(np.arange(len(cams), dtype=np.int32), n)
+    keys, vals, ranges, off = O.pairs(rec["u"], rec["v"], g["rgbd"][:, 3], rec["radius"], rec["valid"], rec_view,
+                                      cams, tile)
+    assert g["n_pairs"] == len(keys)
+    np.testing.assert_array_equal(g["vals"], vals)
+    np.testing.assert_array_equal(g["ranges"], ranges)
+    depth_bits = g["rgbd"][:, 3].astype(np.float32).view(np.uint32).astype(np.uint64)
+    if "keys64" in g:
+        np.testing.assert_array_equal(g["keys64"], keys)
+    else:
+        rebuilt = (g["tile_keys"].astype(np.uint64) << np.uint64(32)) | depth_bits[g["vals"]]
+        np.testing.assert_array_equal(rebuilt, keys)
+    return rec, off
+
+
+def _check_blend_stage(g, rec, cams, tile, off):
+    """The blend over the GPU's own records and lists against the oracle's compositor."""
+    worst = 0.0
+    for vi, cam in enumerate(cams):
+        ob = O.blend(cam, tile, rec, g["vals"], g["ranges"][off[vi]:off[vi + 1]])
+        ok = ob["flag"] == 0
+        d = np.abs(g["images"][vi] - ob["image"])[:, ok]
+        worst = max(worst, float(d.max()) if d.size else 0.0)
+        p0, npx = view_pixels(cams, vi)
+        last = g["last"][p0:p0 + npx].reshape(cam.height, cam.width)
+        assert np.array_equal(last[ok], ob["last"][ok])
+        T = g["T_final"][p0:p0 + npx].reshape(cam.height, cam.width)
+        np.testing.assert_allclose(T[ok], ob["T"][ok], rtol=1e-5, atol=1e-7)
+    assert worst <= IMG_TOL, worst
+    return worst
+
+
+def _run_all_stages(scene, cams, cfg, seed=7):
+    log(f"case n={scene.n} k={scene.k} views={len(cams)} tile={cfg.tile} batch={cfg.batch} flags={cfg.flags}")
+    fwd, w = _oracle_masked_weights(scene, cams, cfg.tile, seed)
+    g = gpu_run(scene, cams, cfg, weights=w)
+    _check_records(g, fwd, len(cams))
+    rec, off = _check_key_stage(g, cams, cfg.tile, scene.n)
+    _check_blend_stage(g, rec, cams, cfg.tile, off)
+    # end-to-end images against the FP64 pipeline
+    for vi in range(len(cams)):
+        ok = fwd["views"][vi]["flag"] == 0
+        d = np.abs(g["images"][vi] - fwd["images"][vi])[:, ok]
+        assert d.max() <= IMG_TOL, (vi, d.max())
+    # backward, stage-wise: blend backward over the GPU's records and lists
+    g2_ref = np.zeros_like(g["grad2d"])
+    g2_abs = np.zeros_like(g["grad2d"])
+    for vi, cam in enumerate(cams):
+        O.blend_backward(cam, cfg.tile, rec, g["vals"], g["ranges"][off[vi]:off[vi + 1]], w[vi], grad2d=g2_ref,
+                         grad2d_abs=g2_abs)
+    for c, name in enumerate(("u", "v", "a", "b", "c", "o", "r", "g", "b_col")):
+        grad_close(f"grad2d[{name}]", g["grad2d"][:, c], g2_ref[:, c], abs_sum=g2_abs[:, c])
+    # projection backward, stage-wise: fed with the GPU's 2D gradients
+    pl = scene.widened()
+    gr_stage = O.zero_grads(pl)
+    n = scene.n
+    for vi, cam in enumerate(cams):
+        O.project_backward(pl, scene.k, cam, cfg.tile, g["grad2d"][vi * n:(vi + 1) * n], gr_stage)
+    for p in O.PLANES:
+        if gr_stage[p] is not None:
+            grad_close(f"stage {p}", g["grads"][p], gr_stage[p])
+    # end to end against the FP64 gradient
+    gr, _ = O.render_backward(pl, scene.k, cams, cfg.tile, w, fwd=fwd)
+    for p in O.PLANES:
+        if gr[p] is not None:
+            grad_close(p, g["grads"][p], gr[p])
+    return g, fwd
+
+
+def test_small_workload_all_stages():
+    scene, cams = S.make_workload("small_2k_128px")
+    _run_all_stages(scene, cams, R.Config(16, 64))
+
+
+@pytest.mark.parametrize("tile,batch", [(8, 64), (16, 128), (32, 256)])
+def test_tile_and_batch_variants(tile, batch):
+    scene, cams = S.make_workload("small_2k_128px")
+    _run_all_stages(scene, cams, R.Config(tile, batch))
+
+
+def test_one_stage_sort_matches_two_stage():
+    scene, cams = S.make_workload("small_2k_128px")
+    cams = cams + [S.look_at((2.0, -3.0, 1.5), 100, 60)]
+    a = gpu_run(scene, cams, R.Config(16, 64))
+    b = gpu_run(scene, cams, R.Config(16, 64, flags=1))
+    np.testing.assert_array_equal(a["vals"], b["vals"])
+    np.testing.assert_array_equal(a["ranges"], b["ranges"])
+    for x, y in zip(a["images"], b["images"]):
+        np.testing.assert_array_equal(x, y)
+    _check_key_stage(b, cams, 16, scene.n)
+
+
+def test_masked_crop_gradients():
+    """The masked 1M workload's 500-Gaussian crop (64x64 centre window), mask gradients included."""
+    scene, cams = S.make_workload("masked_1m_1080p", n=200_000)
+    idx = S.axis_nearest(scene, cams[0], 500)
+    crop = scene.subset(idx)
+    cam = S.crop_camera(cams[0], 64, 64)
+    g, _ = _run_all_stages(crop, [cam], R.Config(16, 64), seed=3)
+    assert np.abs(g["grads"]["pmask_logit"]).max() > 0 and np.abs(g["grads"]["lmask_logit"]).max() > 0
+
+
+def test_multiview_uneven_and_ragged():
+    rng = np.random.default_rng(5)
+    scene = S.random_scene(rng, 3000, 4, masks=True, spread=1.0, logscale_mu=-3.0)
+    cams = [S.look_at((0, -4, 0.3), 100, 37), S.look_at((3, -2, 1), 64, 64, bg=(0.2, 0.3, 0.4)),
+            S.look_at((-2.5, 2.5, 1.5), 150, 90), S.look_at((0.5, 0.5, 4.0), 33, 129)]
+    _run_all_stages(scene, cams, R.Config(16, 64))
+
+
+def test_reduced_precision_storage():
+    """FP16 planes with BF16 amplitudes, widened in registers; oracle reads the exact stored values."""
+    scene, cams = S.make_workload("clustered_200k_720p", n=20_000)
+    scene = scene.stored("f16", "f16", "bf16")
+    cams = [S.crop_camera(cams[0], 320, 180)]
+    _run_all_stages(scene, cams, R.Config(16, 64))
+
+
+def test_forward_is_deterministic():
+    scene, cams = S.make_workload("small_2k_128px")
+    a = gpu_run(scene, cams, R.Config(16, 64))
+    b = gpu_run(scene, cams, R.Config(16, 64))
+    for x, y in zip(a["images"], b["images"]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(a["vals"], b["vals"])
+
+
+def test_empty_and_culled_scenes():
+    cams = [S.look_at((0, -4, 0), 40, 24, bg=(0.25, 0.5, 0.75))]
+    empty = S.random_scene(np.random.default_rng(0), 0, 2, masks=False)
+    g = gpu_run(empty, cams, R.Config(8, 64))
+    np.testing.assert_array_equal(g["images"][0], np.broadcast_to(np.array([0.25, 0.5, 0.75])[:, None, None],
+                                                                  (3, 24, 40)).astype(np.float32))
+    behind = S.random_scene(np.random.default_rng(1), 50, 2, masks=False, spread=0.2)
+    behind.pos[1] -= 6.0  # all behind the camera at y = -4
+    g = gpu_run(behind, cams, R.Config(8, 64))
+    assert g["n_pairs"] == 0 and (g["radius"] < 0).all()
+    np.testing.assert_array_equal(g["images"][0].astype(np.float32), np.broadcast_to(
+        np.array([0.25, 0.5, 0.75], np.float32)[:, None, None], (3, 24, 40)))
+
+
+def test_zero_lobes_and_single_gaussian():
+    rng = np.random.default_rng(9)
+    scene = S.random_scene(rng, 1, 0, masks=False, spread=0.1, logscale_mu=-1.5)
+    _run_all_stages(scene, [S.look_at((0, -3, 0), 48, 40)], R.Config(16, 64))
