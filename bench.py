@@ -119,7 +119,8 @@ def cpu_baseline(scene, cam, tile, frac, seed=11):
     t["project"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     keys, vals, ranges, off = O.pairs(rec["u"], rec["v"], rec["depth"].astype(np.float32), rec["radius"],
-                                      rec["valid"], np.zeros(scene.n, np.int32), [cam], tile)
+                                      rec["conic"], rec["cutoff"], rec["valid"], np.zeros(scene.n, np.int32),
+                                      [cam], tile)
     t["pairs"] = time.perf_counter() - t0
     rng = np.random.default_rng(seed)
     ntl = ranges.shape[0]

@@ -18,7 +18,9 @@
  *   would drop below 1e-4 (that fragment is not blended); near plane from the camera; the
  *   Jacobian is evaluated at the direction clamped to 1.3x the half field of view; the
  *   footprint radius is ceil(sqrt(2 ln(255 o) lambda_max)) so that every pixel with
- *   alpha >= 1/255 lies inside the tile rectangle; depth ties are ordered by record index.
+ *   alpha >= 1/255 lies inside the tile rectangle, and of that rectangle only the tiles whose
+ *   pixel-centre box the ellipse q <= k reaches are listed (k slightly above 2 ln(255 o), see
+ *   megs_state.cutoff); depth ties are ordered by record index.
  *   Quaternions are (w, x, y, z) and normalised in the forward pass, lobe axes likewise;
  *   scales are exp(log-scale), opacity and masks are sigmoid(logit), sharpness is used as
  *   stored. Colours are not clamped.
@@ -121,7 +123,8 @@ typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
  *   conic_o   float[NR][4]   conic (a, b, c) of q = -(a dx^2 + c dy^2)/2 - b dx dy, and o_eff
  *   rgbd      float[NR][4]   SG colour (r, g, b) and camera depth z
  *   radius    int32[NR]      footprint radius in pixels, -1 when culled
- *   ntiles    uint32[NR]     tiles covered by the record's rectangle
+ *   ntiles    uint32[NR]     tiles of the record's rectangle that its footprint ellipse reaches
+ *   cutoff    float[NR]      k of that ellipse, {d : d' conic d <= k}; k bounds 2 ln(255 o_eff)
  *   tile_keys uint32[P]      sorted global tile ids (two-stage sort) or NULL
  *   keys64    uint64[P]      sorted tile<<32|depth keys (one-stage sort) or NULL
  *   vals      uint32[P]      sorted record indices
@@ -135,7 +138,7 @@ typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
 typedef struct {
     int64_t n_records, n_pairs, pair_capacity, n_pixels;
     int32_t n_views, tile, n_tiles, k;
-    const void *mean, *conic_o, *rgbd, *radius, *ntiles;
+    const void *mean, *conic_o, *rgbd, *radius, *ntiles, *cutoff;
     const void *tile_keys, *keys64, *vals, *ranges, *T_final, *last, *device_status;
     void *internal; /* library bookkeeping inside the caller's memory */
 } megs_state;

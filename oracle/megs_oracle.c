@@ -84,7 +84,7 @@ typedef struct {
     double J[6], T[6];
     double A0, B0, C0, det0, det, conic[3];
     double o, mp, o_eff;
-    double lmax, rho; int radius;
+    double lmax, rho, cutoff; int radius;
     double campos[3], dvec[3], dlen, d[3];
     double rgb[3];
     double ax_len[8], muh[8][3], mk[8], ek[8], dot[8];
@@ -92,6 +92,51 @@ typedef struct {
 } oproj;
 
 static double P(const double *plane, int64_t n, int64_t row, int64_t i) { return plane[row * n + i]; }
+
+/*
+ * Tile selection inside the rectangle: a tile is listed when the ellipse {p : q(p) <= k} reaches
+ * the box of its pixel centres [X0, X1] x [Y0, Y1], with q(p) = (p - m)' C (p - m) and C the conic.
+ * The minimum of q over the box is 0 when m is inside; otherwise it lies on one of the four
+ * edges, where q restricted to the edge is a 1D parabola whose minimiser is clamped to the edge.
+ * The level k is 2 ln(255 o) widened by 0.2% and 1e-4 (the blend's alpha >= 1/255 test is
+ * q <= 2 ln(255 o)), so FP32 rounding in a renderer cannot reach past an unlisted tile.
+ */
+static double cutoff_level(double o) { return 2.004 * log(255.0 * o) + 1e-4; }
+
+static int ellipse_reaches_box(double u, double v, double a, double b, double c, double k,
+                               double X0, double X1, double Y0, double Y1) {
+    if (u >= X0 && u <= X1 && v >= Y0 && v <= Y1) return 1;
+    double best = INFINITY;
+    for (int e = 0; e < 4; ++e) {
+        double dx, dy, lo, hi;
+        if (e < 2) {
+            dx = (e == 0 ? X0 : X1) - u;
+            lo = Y0 - v; hi = Y1 - v;
+            dy = -(b * dx) / c;
+            if (dy < lo) dy = lo;
+            else if (dy > hi) dy = hi;
+        } else {
+            dy = (e == 2 ? Y0 : Y1) - v;
+            lo = X0 - u; hi = X1 - u;
+            dx = -(b * dy) / a;
+            if (dx < lo) dx = lo;
+            else if (dx > hi) dx = hi;
+        }
+        double t1 = (a * dx) * dx;
+        double t2 = ((2.0 * b) * dx) * dy;
+        double t3 = (c * dy) * dy;
+        double q = (t1 + t2) + t3;
+        if (q < best) best = q;
+    }
+    return best <= k;
+}
+
+static void tile_pixel_box(int w, int h, int tile, int tx, int ty, double *X0, double *X1, double *Y0, double *Y1) {
+    int xe = (tx + 1) * tile < w ? (tx + 1) * tile : w;
+    int ye = (ty + 1) * tile < h ? (ty + 1) * tile : h;
+    *X0 = tx * tile + 0.5; *X1 = xe - 0.5;
+    *Y0 = ty * tile + 0.5; *Y1 = ye - 0.5;
+}
 
 /* Project Gaussian i into camera cam (tile edge tile). */
 static void project_one(const oscene *sc, const ocam *cam, int tile, int64_t i, oproj *p) {
@@ -216,24 +261,32 @@ static void project_one(const oscene *sc, const ocam *cam, int tile, int64_t i, 
     p->rect[0] = (int)x_lo / tile; p->rect[1] = (int)x_hi / tile;
     p->rect[2] = (int)y_lo / tile; p->rect[3] = (int)y_hi / tile;
     (void)tiles_x; (void)tiles_y;
-    p->ntiles = (p->rect[1] - p->rect[0] + 1) * (p->rect[3] - p->rect[2] + 1);
+    p->cutoff = cutoff_level(p->o_eff);
+    p->ntiles = 0;
+    for (int ty = p->rect[2]; ty <= p->rect[3]; ++ty)
+        for (int tx = p->rect[0]; tx <= p->rect[1]; ++tx) {
+            double X0, X1, Y0, Y1;
+            tile_pixel_box(cam->width, cam->height, tile, tx, ty, &X0, &X1, &Y0, &Y1);
+            p->ntiles += ellipse_reaches_box(p->u, p->v, p->conic[0], p->conic[1], p->conic[2], p->cutoff,
+                                             X0, X1, Y0, Y1);
+        }
 }
 
 /*
  * Records of all Gaussians in one view.
- * out_f: [n][10] = u, v, depth, conic a, b, c, o_eff, r, g, b
- * out_i: [n][7]  = valid, radius, tile x0, x1, y0, y1, ntiles
+ * out_f: [n][11] = u, v, depth, conic a, b, c, o_eff, r, g, b, cutoff level
+ * out_i: [n][7]  = valid, radius, tile x0, x1, y0, y1, ntiles (tiles of the rectangle reached)
  */
 void oracle_project(const oscene *sc, const ocam *cam, int32_t tile, double *out_f, int32_t *out_i) {
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < sc->n; ++i) {
         oproj p;
         project_one(sc, cam, tile, i, &p);
-        double *f = out_f + 10 * i;
+        double *f = out_f + 11 * i;
         int32_t *g = out_i + 7 * i;
         f[0] = p.u; f[1] = p.v; f[2] = p.t[2];
         f[3] = p.conic[0]; f[4] = p.conic[1]; f[5] = p.conic[2];
-        f[6] = p.o_eff; f[7] = p.rgb[0]; f[8] = p.rgb[1]; f[9] = p.rgb[2];
+        f[6] = p.o_eff; f[7] = p.rgb[0]; f[8] = p.rgb[1]; f[9] = p.rgb[2]; f[10] = p.cutoff;
         g[0] = p.valid; g[1] = p.radius;
         g[2] = p.rect[0]; g[3] = p.rect[1]; g[4] = p.rect[2]; g[5] = p.rect[3];
         g[6] = p.valid ? p.ntiles : 0;
@@ -292,13 +345,15 @@ static uint32_t f32_bits(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
 
 /*
  * Key table from records of several views (mean u, v; the depth as the float32
- * value whose bits form the low key half; integer radius). Record g belongs to view rec_view[g];
+ * value whose bits form the low key half; integer radius; conic [n][3] and cutoff level
+ * for the tile selection inside the rectangle). Record g belongs to view rec_view[g];
  * view v has image size (w[v], h[v]) and its tiles are numbered from tile_off[v].
  * When keys == NULL only the pair count is returned.
  * Otherwise keys/vals receive the pairs ordered by (key, value) and ranges[2*T]
  * the [start, end) of each global tile ((0, 0) when empty).
  */
 int64_t oracle_pairs(int64_t nrec, const double *u, const double *v, const float *depth, const int32_t *radius,
+                     const double *conic, const double *cutoff,
                      const int32_t *valid, const int32_t *rec_view, const int32_t *w, const int32_t *h,
                      const int64_t *tile_off, int32_t tile, int64_t total_tiles,
                      uint64_t *keys, uint32_t *vals, uint32_t *ranges) {
@@ -307,7 +362,14 @@ int64_t oracle_pairs(int64_t nrec, const double *u, const double *v, const float
     for (int64_t g = 0; g < nrec; ++g) {
         if (!valid[g]) continue;
         int vv = rec_view[g];
-        count += rect_of(u[g], v[g], radius[g], w[vv], h[vv], tile, rect);
+        if (!rect_of(u[g], v[g], radius[g], w[vv], h[vv], tile, rect)) continue;
+        for (int ty = rect[2]; ty <= rect[3]; ++ty)
+            for (int tx = rect[0]; tx <= rect[1]; ++tx) {
+                double X0, X1, Y0, Y1;
+                tile_pixel_box(w[vv], h[vv], tile, tx, ty, &X0, &X1, &Y0, &Y1);
+                count += ellipse_reaches_box(u[g], v[g], conic[3 * g], conic[3 * g + 1], conic[3 * g + 2], cutoff[g],
+                                             X0, X1, Y0, Y1);
+            }
     }
     if (!keys) return count;
     okv *kv = (okv *)malloc(sizeof(okv) * (size_t)(count > 0 ? count : 1));
@@ -319,6 +381,11 @@ int64_t oracle_pairs(int64_t nrec, const double *u, const double *v, const float
         int tiles_x = (w[vv] + tile - 1) / tile;
         for (int ty = rect[2]; ty <= rect[3]; ++ty)
             for (int tx = rect[0]; tx <= rect[1]; ++tx) {
+                double X0, X1, Y0, Y1;
+                tile_pixel_box(w[vv], h[vv], tile, tx, ty, &X0, &X1, &Y0, &Y1);
+                if (!ellipse_reaches_box(u[g], v[g], conic[3 * g], conic[3 * g + 1], conic[3 * g + 2], cutoff[g],
+                                         X0, X1, Y0, Y1))
+                    continue;
                 uint64_t gt = (uint64_t)(tile_off[vv] + (int64_t)ty * tiles_x + tx);
                 kv[e].key = (gt << 32) | f32_bits(depth[g]);
                 kv[e].val = (uint32_t)g;

@@ -68,7 +68,7 @@ def lib():
         L.oracle_project.argtypes = [ctypes.POINTER(OScene), ctypes.POINTER(OCam), ctypes.c_int32, vp, vp]
         L.oracle_sg_color.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_sg_color_many.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_int64, vp, vp]
-        L.oracle_pairs.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+        L.oracle_pairs.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                    ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.oracle_pairs.restype = ctypes.c_int64
         L.oracle_blend.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
@@ -121,12 +121,12 @@ def project(planes: dict, k: int, cam, tile: int) -> dict:
     """FP64 records of all Gaussians in one view."""
     s, keep = make_oscene(planes, k)
     n = s.n
-    f = np.zeros((n, 10), np.float64)
+    f = np.zeros((n, 11), np.float64)
     i = np.zeros((n, 7), np.int32)
     c = make_ocam(cam)
     lib().oracle_project(ctypes.byref(s), ctypes.byref(c), tile, _ptr(f), _ptr(i))
     return {"u": f[:, 0].copy(), "v": f[:, 1].copy(), "depth": f[:, 2].copy(),
-            "conic": f[:, 3:6].copy(), "o": f[:, 6].copy(), "rgb": f[:, 7:10].copy(),
+            "conic": f[:, 3:6].copy(), "o": f[:, 6].copy(), "rgb": f[:, 7:10].copy(), "cutoff": f[:, 10].copy(),
             "valid": i[:, 0].copy(), "radius": i[:, 1].copy(), "rect": i[:, 2:6].copy(),
             "ntiles": i[:, 6].copy()}
 
@@ -164,13 +164,15 @@ def tile_layout(cams: Sequence, tile: int):
     return off
 
 
-def pairs(u, v, depth_f32, radius, valid, rec_view, cams, tile: int):
+def pairs(u, v, depth_f32, radius, conic, cutoff, valid, rec_view, cams, tile: int):
     """Sorted key table over records of several views.
 
-    u, v: float64 means; depth_f32: float32 depths; radius, valid, rec_view: int32.
+    u, v: float64 means; depth_f32: float32 depths; radius, valid, rec_view: int32; conic [n][3]
+    and cutoff [n] (float64) select the tiles of each rectangle the footprint ellipse reaches.
     Returns keys (uint64), vals (uint32), ranges ([T][2] uint32), tile offsets.
     """
     u = _c64(u); v = _c64(v)
+    cn = _c64(conic); cu = _c64(cutoff)
     d = np.ascontiguousarray(depth_f32, np.float32)
     r = np.ascontiguousarray(radius, np.int32)
     va = np.ascontiguousarray(valid, np.int32)
@@ -181,12 +183,12 @@ def pairs(u, v, depth_f32, radius, valid, rec_view, cams, tile: int):
     total = int(off[-1])
     L = lib()
     n = len(u)
-    cnt = L.oracle_pairs(n, _ptr(u), _ptr(v), _ptr(d), _ptr(r), _ptr(va), _ptr(rv), _ptr(w), _ptr(h),
-                         _ptr(off), tile, total, None, None, None)
+    cnt = L.oracle_pairs(n, _ptr(u), _ptr(v), _ptr(d), _ptr(r), _ptr(cn), _ptr(cu), _ptr(va), _ptr(rv), _ptr(w),
+                         _ptr(h), _ptr(off), tile, total, None, None, None)
     keys = np.zeros(max(cnt, 1), np.uint64)
     vals = np.zeros(max(cnt, 1), np.uint32)
     ranges = np.zeros((total, 2), np.uint32)
-    L.oracle_pairs(n, _ptr(u), _ptr(v), _ptr(d), _ptr(r), _ptr(va), _ptr(rv), _ptr(w), _ptr(h),
+    L.oracle_pairs(n, _ptr(u), _ptr(v), _ptr(d), _ptr(r), _ptr(cn), _ptr(cu), _ptr(va), _ptr(rv), _ptr(w), _ptr(h),
                    _ptr(off), tile, total, _ptr(keys), _ptr(vals), _ptr(ranges))
     return keys[:cnt], vals[:cnt], ranges, off
 
@@ -266,10 +268,12 @@ def render(planes: dict, k: int, cams: Sequence, tile: int) -> dict:
     n = len(planes["op_logit"])
     recs = [project(planes, k, c, tile) for c in cams]
     cat = lambda key: np.concatenate([r[key] for r in recs])
-    rec_all = {key: cat(key) for key in ("u", "v", "depth", "conic", "o", "rgb", "valid", "radius", "ntiles")}
+    rec_all = {key: cat(key) for key in ("u", "v", "depth", "conic", "o", "rgb", "cutoff", "valid", "radius",
+                                         "ntiles")}
     rec_view = np.repeat(np.arange(len(cams), dtype=np.int32), n)
     keys, vals, ranges, off = pairs(rec_all["u"], rec_all["v"], rec_all["depth"].astype(np.float32),
-                                    rec_all["radius"], rec_all["valid"], rec_view, cams, tile)
+                                    rec_all["radius"], rec_all["conic"], rec_all["cutoff"], rec_all["valid"],
+                                    rec_view, cams, tile)
     views = []
     for vi, c in enumerate(cams):
         views.append(blend(c, tile, rec_all, vals, ranges[off[vi]:off[vi + 1]]))

@@ -56,7 +56,7 @@ class MegsState(ctypes.Structure):
     _fields_ = [("n_records", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("pair_capacity", ctypes.c_int64),
                 ("n_pixels", ctypes.c_int64), ("n_views", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("n_tiles", ctypes.c_int32), ("k", ctypes.c_int32),
-                ("mean", _vp), ("conic_o", _vp), ("rgbd", _vp), ("radius", _vp), ("ntiles", _vp),
+                ("mean", _vp), ("conic_o", _vp), ("rgbd", _vp), ("radius", _vp), ("ntiles", _vp), ("cutoff", _vp),
                 ("tile_keys", _vp), ("keys64", _vp), ("vals", _vp), ("ranges", _vp), ("T_final", _vp),
                 ("last", _vp), ("device_status", _vp), ("internal", _vp)]
 

@@ -189,7 +189,7 @@ size_t frame_bytes(const Layout& L) {
     b += align256(sizeof(ViewInfo) * L.nv);
     b += align256(sizeof(double2) * (L.nr ? L.nr : 1));
     b += 2 * align256(sizeof(float4) * (L.nr ? L.nr : 1));
-    b += 7 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
+    b += 8 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
     b += align256(scan_scratch_bytes(L.nr)) + align256(radix_scratch_bytes(L.nr));
     b += align256(sizeof(uint32_t) * 8) + align256(sizeof(int32_t) * 8);
     b += align256(sizeof(uint2) * L.n_tiles);
@@ -208,6 +208,7 @@ Frame carve_frame(void* mem, const Layout& L) {
     f.rec.radius = c.take<int32_t>(L.nr);
     f.rec.ntiles = c.take<uint32_t>(L.nr);
     f.rec.dkey = c.take<uint32_t>(L.nr);
+    f.rec.cutoff = c.take<float>(L.nr);
     f.dkey_alt = c.take<uint32_t>(L.nr);
     f.order = c.take<uint32_t>(L.nr);
     f.order_alt = c.take<uint32_t>(L.nr);
@@ -363,6 +364,7 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     state->rgbd = f.rec.rgbd;
     state->radius = f.rec.radius;
     state->ntiles = f.rec.ntiles;
+    state->cutoff = f.rec.cutoff;
     state->tile_keys = sorted_t;
     state->keys64 = sorted_k;
     state->vals = sorted_v;

@@ -52,8 +52,9 @@ struct Records {
     float4* conic_o;    // conic a, b, c and effective opacity
     float4* rgbd;       // colour and camera depth
     int32_t* radius;    // -1 when culled
-    uint32_t* ntiles;   // tiles in the rectangle
+    uint32_t* ntiles;   // tiles of the rectangle the footprint ellipse reaches
     uint32_t* dkey;     // depth sort key: float bits of depth, 0xffffffff when no tiles
+    float* cutoff;      // k of the footprint ellipse q(d) = d' conic d <= k (with margin)
 };
 
 __device__ __forceinline__ float load_elem(const void* p, int dt, int64_t idx) {
@@ -76,6 +77,48 @@ __device__ __forceinline__ uint32_t tile_rect(double u, double v, int32_t r, con
     int iyh = yh > vw.height - 1 ? vw.height - 1 : static_cast<int>(yh);
     x0 = ixl / tile; x1 = ixh / tile; y0 = iyl / tile; y1 = iyh / tile;
     return static_cast<uint32_t>((x1 - x0 + 1) * (y1 - y0 + 1));
+}
+
+// Does the ellipse {p : (p - m)' C (p - m) <= k} (C = [[a, b], [b, c]] positive definite) reach
+// the box [X0, X1] x [Y0, Y1] of a tile's pixel centres? The minimum of the convex quadratic over
+// the box is 0 when the mean lies inside, else it is attained on an edge, where the 1D minimiser
+// along the edge is clamped to the edge's extent. Plain FP64 +, *, / in a fixed order, so any
+// IEEE implementation takes the same decision from the same inputs.
+__device__ __forceinline__ bool tile_reached(double u, double v, double a, double b, double c, double k,
+                                             double X0, double X1, double Y0, double Y1) {
+    if (u >= X0 && u <= X1 && v >= Y0 && v <= Y1) return true;
+    double best = INFINITY;
+    for (int e = 0; e < 4; ++e) {
+        double dx, dy;
+        if (e < 2) {
+            dx = (e == 0 ? X0 : X1) - u;
+            const double lo = Y0 - v, hi = Y1 - v;
+            dy = -(b * dx) / c;
+            dy = dy < lo ? lo : (dy > hi ? hi : dy);
+        } else {
+            dy = (e == 2 ? Y0 : Y1) - v;
+            const double lo = X0 - u, hi = X1 - u;
+            dx = -(b * dy) / a;
+            dx = dx < lo ? lo : (dx > hi ? hi : dx);
+        }
+        const double t1 = (a * dx) * dx;
+        const double t2 = ((2.0 * b) * dx) * dy;
+        const double t3 = (c * dy) * dy;
+        const double q = (t1 + t2) + t3;
+        best = q < best ? q : best;
+    }
+    return best <= k;
+}
+
+// Pixel-centre box of tile (tx, ty) of view vw.
+__device__ __forceinline__ void tile_box(const ViewInfo& vw, int tile, int tx, int ty, double& X0, double& X1,
+                                         double& Y0, double& Y1) {
+    const int xe = (tx + 1) * tile < vw.width ? (tx + 1) * tile : vw.width;
+    const int ye = (ty + 1) * tile < vw.height ? (ty + 1) * tile : vw.height;
+    X0 = tx * tile + 0.5;
+    X1 = xe - 0.5;
+    Y0 = ty * tile + 0.5;
+    Y1 = ye - 0.5;
 }
 
 // View of a global tile id: linear scan of the (few) view tile offsets.

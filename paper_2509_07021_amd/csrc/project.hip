@@ -184,6 +184,12 @@ __device__ __forceinline__ bool sg_colour(const SceneDev& sc, int64_t i, const f
     return isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
 }
 
+// Ellipse level that bounds every pixel with alpha >= 1/255: q <= 2 ln(255 o), widened by 0.2% (and
+// 1e-4 absolute) so that FP32 rounding in the blend never reaches past a culled tile.
+__device__ __forceinline__ float cutoff_of(float o_eff) {
+    return 2.004f * __logf(255.0f * o_eff) + 1e-4f;
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __restrict__ views, int nv, int tile,
                                                  Records rec) {
@@ -205,16 +211,26 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
         uint32_t nt = 0;
         if (ok) {
             int x0, x1, y0, y1;
-            nt = tile_rect(p.u, p.v, p.radius, vw, tile, x0, x1, y0, y1);
+            const float cut = cutoff_of(g.o_eff);
+            if (tile_rect(p.u, p.v, p.radius, vw, tile, x0, x1, y0, y1)) {
+                for (int ty = y0; ty <= y1; ++ty)
+                    for (int tx = x0; tx <= x1; ++tx) {
+                        double X0, X1, Y0, Y1;
+                        tile_box(vw, tile, tx, ty, X0, X1, Y0, Y1);
+                        nt += tile_reached(p.u, p.v, p.conic[0], p.conic[1], p.conic[2], cut, X0, X1, Y0, Y1);
+                    }
+            }
             rec.mean[r] = make_double2(p.u, p.v);
             rec.conic_o[r] = make_float4(p.conic[0], p.conic[1], p.conic[2], g.o_eff);
             rec.rgbd[r] = make_float4(rgb[0], rgb[1], rgb[2], p.tzf);
             rec.radius[r] = p.radius;
+            rec.cutoff[r] = cut;
         } else {
             rec.mean[r] = make_double2(0.0, 0.0);
             rec.conic_o[r] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec.rgbd[r] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec.radius[r] = -1;
+            rec.cutoff[r] = 0.f;
         }
         rec.ntiles[r] = nt;
         rec.dkey[r] = nt ? __float_as_uint(p.tzf) : 0xffffffffu;

@@ -305,17 +305,23 @@ __global__ void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t 
     const ViewInfo& vw = views[v];
     int x0, x1, y0, y1;
     const double2 m = rec.mean[g];
+    const float4 co = rec.conic_o[g];
+    const double cut = rec.cutoff[g];
     tile_rect(m.x, m.y, rec.radius[g], vw, tile, x0, x1, y0, y1);
     const uint64_t depth_bits = __float_as_uint(rec.rgbd[g].w);
     int64_t pos = offsets[k];
     if (pos + (int64_t)nt > capacity) status[1] = 1;
     for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx, ++pos) {
+        for (int tx = x0; tx <= x1; ++tx) {
+            double X0, X1, Y0, Y1;
+            tile_box(vw, tile, tx, ty, X0, X1, Y0, Y1);
+            if (!tile_reached(m.x, m.y, co.x, co.y, co.z, cut, X0, X1, Y0, Y1)) continue;
             if (pos >= capacity) return;
             const uint64_t gt = (uint64_t)(vw.tile_off + (int64_t)ty * vw.tiles_x + tx);
             if (tile_keys) tile_keys[pos] = (uint32_t)gt;
             if (keys64) keys64[pos] = (gt << 32) | depth_bits;
             vals[pos] = g;
+            ++pos;
         }
 }
 

@@ -38,6 +38,7 @@ def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
         out["rgbd"] = fr.buffer("rgbd", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
         out["radius"] = fr.buffer("radius", nr, torch.int32).cpu().numpy()
         out["ntiles"] = fr.buffer("ntiles", nr, torch.int32).cpu().numpy().view(np.uint32)
+        out["cutoff"] = fr.buffer("cutoff", nr, torch.float32).cpu().numpy()
     if P:
         out["vals"] = fr.buffer("vals", P, torch.int32).cpu().numpy().view(np.uint32)
         if st.tile_keys:
@@ -65,7 +66,7 @@ def gpu_records(g: dict) -> dict:
     return {"u": m[:, 0].copy(), "v": m[:, 1].copy(), "depth": cd[:, 3].astype(np.float64),
             "conic": co[:, :3].astype(np.float64), "o": co[:, 3].astype(np.float64),
             "rgb": cd[:, :3].astype(np.float64), "valid": (g["radius"] >= 0).astype(np.int32),
-            "radius": g["radius"].astype(np.int32)}
+            "radius": g["radius"].astype(np.int32), "cutoff": g["cutoff"].astype(np.float64)}
 
 
 def view_pixels(cams, vi):

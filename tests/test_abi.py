@@ -1,0 +1,121 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point include/megs.h declares,
+and rejects bad arguments before any GPU work (no compute call needs a GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2509_07021_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "megs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(megs_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTED) == set(names)
+
+
+def test_version_and_empty_error():
+    lib = L.load()
+    assert lib.megs_version().startswith(b"megs")
+    assert isinstance(lib.megs_last_error(), bytes)
+
+
+def _args(tile=16, batch=64, flags=0, nv=1, k=0, width=32, height=32, n=0, dt=0, cap=0):
+    sc = L.MegsScene()
+    sc.n, sc.k, sc.dt_geom, sc.dt_color, sc.dt_amp = n, k, dt, 0, 0
+    cams = (L.MegsCamera * max(nv, 1))()
+    for c in cams:
+        c.width, c.height, c.fx, c.fy, c.znear = width, height, 20.0, 20.0, 0.2
+    cfg = L.MegsConfig(tile, batch, flags, 0, cap)
+    return sc, cams, cfg
+
+
+def _forward(sc, cams, nv, cfg):
+    lib = L.load()
+    st = L.MegsState()
+    noop = L.ALLOC_FN(lambda ctx, n: None)
+    status = lib.megs_render_forward(ctypes.byref(sc), cams, nv, ctypes.byref(cfg), noop, None,
+                                     ctypes.c_void_p(16), ctypes.byref(st), None)
+    return status, lib.megs_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(tile=12), "tile"),
+    (dict(batch=100), "batch"),
+    (dict(flags=64), "flags"),
+    (dict(nv=0), "n_views"),
+    (dict(nv=65), "n_views"),
+    (dict(k=9), "k ="),
+    (dict(width=0), "image size"),
+    (dict(dt=7), "dtype"),
+    (dict(n=-1), "n ="),
+    (dict(n=10), "null geometry"),
+    (dict(cap=-5), "pair_capacity"),
+])
+def test_forward_rejects_bad_arguments(kw, needle):
+    nv = kw.pop("nv", 1)
+    sc, cams, cfg = _args(nv=nv, **kw)
+    status, msg = _forward(sc, cams, nv, cfg)
+    assert status == L.MEGS_ERR_ARG, (status, msg)
+    assert needle in msg
+
+
+def test_backward_and_graph_reject_bad_state():
+    lib = L.load()
+    sc, cams, cfg = _args()
+    st = L.MegsState()
+    g = L.MegsSceneGrad()
+    noop = L.ALLOC_FN(lambda ctx, n: None)
+    status = lib.megs_render_backward(ctypes.byref(sc), cams, 1, ctypes.byref(cfg), ctypes.byref(st),
+                                      ctypes.c_void_p(16), noop, None, ctypes.byref(g), None)
+    assert status == L.MEGS_ERR_ARG
+    assert "state" in lib.megs_last_error().decode()
+    h = ctypes.c_void_p()
+    status = lib.megs_graph_create(ctypes.byref(sc), cams, 1, ctypes.byref(cfg), noop, None, ctypes.c_void_p(16),
+                                   None, None, 0, ctypes.c_void_p(1), ctypes.byref(h))
+    assert status == L.MEGS_ERR_ARG and "pair_capacity" in lib.megs_last_error().decode()
+
+
+def test_mask_gradient_planes_must_match_scene():
+    lib = L.load()
+    sc, cams, cfg = _args(n=4)
+    for p in L.PLANES:
+        if p not in ("pmask_logit", "lmask_logit", "axis", "sharp", "amp"):
+            setattr(sc, p, 16)
+    sc.pmask_logit = 16
+    g = L.MegsSceneGrad()
+    for p in ("pos", "logscale", "quat", "op_logit", "base"):
+        setattr(g, p, 16)
+    st = L.MegsState()
+    st.n_records, st.n_views, st.tile, st.internal = 4, 1, 16, 16
+    noop = L.ALLOC_FN(lambda ctx, n: None)
+    status = lib.megs_render_backward(ctypes.byref(sc), cams, 1, ctypes.byref(cfg), ctypes.byref(st),
+                                      ctypes.c_void_p(16), noop, None, ctypes.byref(g), None)
+    assert status == L.MEGS_ERR_ARG and "pmask_logit" in lib.megs_last_error().decode()
+
+
+def test_profile_calls_without_work():
+    lib = L.load()
+    assert lib.megs_profile_begin() == L.MEGS_OK
+    p = L.MegsProfile()
+    assert lib.megs_profile_end(ctypes.byref(p)) == L.MEGS_OK
+    assert all(c == 0 for c in p.count)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libmegs.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        L.load()

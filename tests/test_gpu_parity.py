@@ -43,14 +43,15 @@ def _check_records(g, fwd, n_views):
     np.testing.assert_allclose(g["rgbd"][v, :3], rec["rgb"][v], rtol=0, atol=2e-6)
     dr = np.abs(g["radius"][v] - rec["radius"][v])
     assert dr.max() <= 1 and (dr > 0).mean() < 1e-3
+    np.testing.assert_allclose(g["cutoff"][v], rec["cutoff"][v], rtol=1e-5)
 
 
 def _check_key_stage(g, cams, tile, n):
     """Keys, order and ranges from the GPU's own records, bit-exact against the oracle's table."""
     rec = gpu_records(g)
     rec_view = np.repeat(np.arange(len(cams), dtype=np.int32), n)
-    keys, vals, ranges, off = O.pairs(rec["u"], rec["v"], g["rgbd"][:, 3], rec["radius"], rec["valid"], rec_view,
-                                      cams, tile)
+    keys, vals, ranges, off = O.pairs(rec["u"], rec["v"], g["rgbd"][:, 3], rec["radius"], rec["conic"],
+                                      rec["cutoff"], rec["valid"], rec_view, cams, tile)
     assert g["n_pairs"] == len(keys)
     np.testing.assert_array_equal(g["vals"], vals)
     np.testing.assert_array_equal(g["ranges"], ranges)

@@ -300,12 +300,15 @@ def test_tiled_equals_bruteforce_and_tile_invariance(oracle):
 
 
 def test_key_table_structure(oracle):
-    """Keys ascend, ranges partition [0, P), and each valid Gaussian appears exactly in
-    the tiles of its rectangle (checked by a brute-force Python loop)."""
+    """Keys ascend; ranges partition [0, P); every listed (tile, record) pair lies inside the
+    record's rectangle; and -- the property the compositor relies on -- every pixel where a
+    record's alpha reaches 1/255 (brute force over the pixels, in numpy) lies in a tile listed for
+    that record. Tile culling inside the rectangle must drop pairs."""
     sc, cams = S.make_workload("small_2k_128px")
     cams = cams + [S.look_at((3.0, 1.0, 2.0), 72, 40)]
     pl = sc.widened()
-    out = oracle.render(pl, sc.k, cams, 16)
+    tile = 16
+    out = oracle.render(pl, sc.k, cams, tile)
     keys, vals, ranges, off = out["keys"], out["vals"], out["ranges"], out["tile_off"]
     order = np.lexsort((vals, keys))
     np.testing.assert_array_equal(order, np.arange(len(keys)))
@@ -316,24 +319,35 @@ def test_key_table_structure(oracle):
         cover[s:e] += 1
         assert np.all((keys[s:e] >> np.uint64(32)) == t)
     assert np.all(cover == 1)
+    got = set(zip((keys >> np.uint64(32)).astype(np.int64).tolist(), vals.astype(np.int64).tolist()))
     rec = out["records"]
     n = sc.n
-    expect = set()
+    rect_total = 0
     for g in np.nonzero(rec["valid"])[0]:
         vi = g // n
         cam = cams[vi]
-        tx = (cam.width + 15) // 16
+        tx = (cam.width + tile - 1) // tile
         u, v, r = rec["u"][g], rec["v"][g], rec["radius"][g]
         xl, xh, yl, yh = math.floor(u) - r, math.floor(u) + r, math.floor(v) - r, math.floor(v) + r
         if xh < 0 or yh < 0 or xl > cam.width - 1 or yl > cam.height - 1:
             continue
         xl, yl = max(xl, 0), max(yl, 0)
         xh, yh = min(xh, cam.width - 1), min(yh, cam.height - 1)
-        for ty in range(yl // 16, yh // 16 + 1):
-            for tx_ in range(xl // 16, xh // 16 + 1):
-                expect.add((int(off[vi]) + ty * tx + tx_, int(g)))
-    got = set(zip((keys >> np.uint64(32)).astype(np.int64).tolist(), vals.astype(np.int64).tolist()))
-    assert got == expect
+        rect = {(int(off[vi]) + ty * tx + tx_) for ty in range(yl // tile, yh // tile + 1)
+                for tx_ in range(xl // tile, xh // tile + 1)}
+        rect_total += len(rect)
+        listed = {t for t in rect if (t, int(g)) in got}
+        # pixels of the whole image where this record passes the compositor's alpha test
+        ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+        dx, dy = xs + 0.5 - u, ys + 0.5 - v
+        a, b, c = rec["conic"][g]
+        q = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+        alpha = np.minimum(0.99, rec["o"][g] * np.exp(q))
+        hit = (alpha >= 1 / 255) & (q <= 0)
+        need = {int(off[vi]) + (int(y) // tile) * tx + int(x) // tile for y, x in zip(*np.nonzero(hit))}
+        assert need <= listed, (g, need - listed)
+    assert len(got) < rect_total
+    assert all(k[1] < n * len(cams) for k in got)
     dep = rec["depth"].astype(np.float32).view(np.uint32)
     np.testing.assert_array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), dep[vals])
 
