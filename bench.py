@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="pick tile/batch with the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=0.02, help="fraction of tiles the oracle blends")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB (reference kernel for HBM counters)")
     return ap.parse_args()
 
 
@@ -162,6 +164,13 @@ def main():
     from paper_2509_07021_amd import scenes as S
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 4, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
+        del src, dst
     t_start = time.perf_counter()
     scene, cams1 = S.make_workload("masked_1m_1080p", n=args.n)
     scene16 = scene.stored("f16", "f16", "bf16")

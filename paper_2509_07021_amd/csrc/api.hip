@@ -111,8 +111,8 @@ megs_status check_args(const megs_scene* sc, const megs_camera* cams, int32_t nv
         if (sc->k > 0 && (!sc->axis || !sc->sharp || !sc->amp)) return fail(MEGS_ERR_ARG, "null lobe plane");
     }
     if (cfg->tile != 8 && cfg->tile != 16 && cfg->tile != 32) return fail(MEGS_ERR_ARG, "tile = %d not in {8, 16, 32}", cfg->tile);
-    if (cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
-        return fail(MEGS_ERR_ARG, "batch = %d not in {64, 128, 256}", cfg->batch);
+    if (cfg->batch != 32 && cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
+        return fail(MEGS_ERR_ARG, "batch = %d not in {32, 64, 128, 256}", cfg->batch);
     if (cfg->pair_capacity < 0 || cfg->pair_capacity >= (1ll << 31)) return fail(MEGS_ERR_ARG, "pair_capacity out of range");
     if (cfg->flags & ~(uint32_t)(MEGS_FLAG_ONE_STAGE_SORT | MEGS_FLAG_PERSISTENT | MEGS_FLAG_STATS))
         return fail(MEGS_ERR_ARG, "unknown flags 0x%x", cfg->flags);
@@ -619,14 +619,14 @@ megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int3
     if (reps < 1) reps = 1;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int tiles[3] = {8, 16, 32};
-    const int batches[3] = {64, 128, 256};
+    const int batches[4] = {32, 64, 128, 256};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f;
     megs_status result = MEGS_OK;
     for (int ti = 0; ti < 3 && result == MEGS_OK; ++ti)
-        for (int bi = 0; bi < 3 && result == MEGS_OK; ++bi) {
+        for (int bi = 0; bi < 4 && result == MEGS_OK; ++bi) {
             megs_config c = *base;
             c.tile = tiles[ti];
             c.batch = batches[bi];
@@ -647,7 +647,7 @@ megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int3
                 }
             }
             const float ms = ms_total / reps;
-            if (ms_out) ms_out[ti * 3 + bi] = ms;
+            if (ms_out) ms_out[ti * 4 + bi] = ms;
             if (result == MEGS_OK && ms < best_ms) {
                 best_ms = ms;
                 *best = c;

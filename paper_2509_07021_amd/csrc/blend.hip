@@ -40,20 +40,19 @@ __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0,
     *dst = s;
 }
 
-// One fragment: returns true when it passes q <= 0 and alpha >= 1/255. The forward and the
-// backward call this same function, so both take identical decisions.
+// Alpha test of one fragment (no branches): pass = (q <= 0 and alpha >= 1/255). The forward and
+// the backward call this same function, so both take identical decisions.
 __device__ __forceinline__ bool frag(const Staged& s, float px, float py, float& dx, float& dy, float& G,
                                      float& alpha, bool& clamped) {
     dx = px - s.p0.x;
     dy = py - s.p0.y;
     const float h = __fmaf_rn(s.p1.x, dx, s.p0.w * dy);
     const float q2 = __fmaf_rn(dx, h, (s.p1.y * dy) * dy);
-    if (q2 > 0.0f) return false;
     G = __builtin_amdgcn_exp2f(q2);
     const float raw = s.p0.z * G;
     clamped = raw > kAlphaMax;
     alpha = clamped ? kAlphaMax : raw;
-    return alpha >= kAlphaMin;
+    return (q2 <= 0.0f) & (alpha >= kAlphaMin);
 }
 
 struct TileCtx {
@@ -98,13 +97,15 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int pe
     for (int64_t t = next_tile(a, -1, persistent); t < a.n_tiles; t = next_tile(a, t, persistent)) {
         const TileCtx c = tile_ctx(a, t, TILE);
         const uint2 rg = a.ranges[t];
+        // T < 0 marks a pixel that has terminated (|T| is its final transmittance) or lies outside
+        // the image; this keeps the per-pixel state in float registers.
         float T[PPT], C[PPT][3];
         uint32_t last[PPT];
-        bool done[PPT];
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            T[j] = 1.0f; C[j][0] = C[j][1] = C[j][2] = 0.0f; last[j] = 0;
-            done[j] = !(c.x0 + lx < c.width && c.y0 + ly + ROWS * j < c.height);
+            T[j] = (c.x0 + lx < c.width && c.y0 + ly + ROWS * j < c.height) ? 1.0f : -1.0f;
+            C[j][0] = C[j][1] = C[j][2] = 0.0f;
+            last[j] = 0;
         }
         const float px = lx + 0.5f;
         bool active = true;
@@ -115,27 +116,34 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int pe
             for (int jj = 0; jj < cnt; ++jj) {
                 const Staged s = lds[jj];
                 const uint32_t pos = base + jj - rg.x;
+                float alpha[PPT];
+                bool pass[PPT];
+                bool any_pass = false;
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
-                    if (done[j]) continue;
-                    if (STATS) ++n_evaluated;
-                    float dx, dy, G, alpha;
+                    float dx, dy, G;
                     bool clamped;
-                    if (!frag(s, px, ly + ROWS * j + 0.5f, dx, dy, G, alpha, clamped)) continue;
-                    const float Tn = T[j] * (1.0f - alpha);
-                    if (Tn < kTMin) { done[j] = true; continue; }
-                    if (STATS) ++n_blended;
-                    const float w = alpha * T[j];
+                    pass[j] = frag(s, px, ly + ROWS * j + 0.5f, dx, dy, G, alpha[j], clamped) & (T[j] > 0.0f);
+                    any_pass |= pass[j];
+                    if (STATS) n_evaluated += T[j] > 0.0f;
+                }
+                if (!__any(any_pass)) continue;  // wave-uniform: no pixel of the tile is hit
+                bool live = false;
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    const float Tn = T[j] * (1.0f - alpha[j]);
+                    const bool term = pass[j] & (Tn < kTMin);
+                    const bool incl = pass[j] & !term;
+                    const float w = incl ? alpha[j] * T[j] : 0.0f;
                     C[j][0] = __fmaf_rn(w, s.p2.y, C[j][0]);
                     C[j][1] = __fmaf_rn(w, s.p2.z, C[j][1]);
                     C[j][2] = __fmaf_rn(w, s.p2.w, C[j][2]);
-                    T[j] = Tn;
-                    last[j] = pos + 1;
+                    T[j] = incl ? Tn : (term ? -T[j] : T[j]);
+                    last[j] = incl ? pos + 1 : last[j];
+                    live |= T[j] > 0.0f;
+                    if (STATS) n_blended += incl;
                 }
-                bool mine = false;
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) mine |= !done[j];
-                if (!__any(mine)) { active = false; break; }
+                if (!__any(live)) { active = false; break; }
             }
             __syncthreads();
         }
@@ -146,10 +154,11 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int pe
             const int64_t p = (int64_t)y * c.width + x;
             const int64_t plane = (int64_t)c.width * c.height;
             float* img = a.image + 3 * c.pix_off;
-            img[p] = __fmaf_rn(T[j], c.bg[0], C[j][0]);
-            img[plane + p] = __fmaf_rn(T[j], c.bg[1], C[j][1]);
-            img[2 * plane + p] = __fmaf_rn(T[j], c.bg[2], C[j][2]);
-            a.T_final[c.pix_off + p] = T[j];
+            const float Tf = fabsf(T[j]);
+            img[p] = __fmaf_rn(Tf, c.bg[0], C[j][0]);
+            img[plane + p] = __fmaf_rn(Tf, c.bg[1], C[j][1]);
+            img[2 * plane + p] = __fmaf_rn(Tf, c.bg[2], C[j][2]);
+            a.T_final[c.pix_off + p] = Tf;
             a.last[c.pix_off + p] = last[j];
         }
     }
@@ -242,31 +251,37 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendArgs a, int batch, int pe
             for (int jj = 0; jj < cnt; ++jj) {
                 const Staged s = lds[jj];
                 const uint32_t pos = end - 1 - jj - rg.x;
+                float alpha[PPT], G[PPT], dxs[PPT], dys[PPT];
+                bool incl[PPT], clamped[PPT];
+                bool any_incl = false;
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    incl[j] = frag(s, px, ly + ROWS * j + 0.5f, dxs[j], dys[j], G[j], alpha[j], clamped[j]) &
+                              (pos < lst[j]);
+                    any_incl |= incl[j];
+                }
+                if (!__any(any_incl)) continue;  // wave-uniform: no pixel of the tile blended it
                 float acc[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) acc[i] = 0.f;
-                bool contributed = false;
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
-                    if (pos >= lst[j]) continue;
-                    float dx, dy, G, alpha;
-                    bool clamped;
-                    if (!frag(s, px, ly + ROWS * j + 0.5f, dx, dy, G, alpha, clamped)) continue;
-                    contributed = true;
-                    const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - alpha);
-                    const float w = alpha * Ti;
+                    const float a = incl[j] ? alpha[j] : 0.0f;
+                    const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
+                    const float w = a * Ti;
                     const float d0 = s.p2.y - S[j][0], d1 = s.p2.z - S[j][1], d2 = s.p2.w - S[j][2];
                     acc[6] = __fmaf_rn(w, dl[j][0], acc[6]);
                     acc[7] = __fmaf_rn(w, dl[j][1], acc[7]);
                     acc[8] = __fmaf_rn(w, dl[j][2], acc[8]);
                     const float dal = Ti * __fmaf_rn(d0, dl[j][0], __fmaf_rn(d1, dl[j][1], d2 * dl[j][2]));
-                    S[j][0] = __fmaf_rn(alpha, d0, S[j][0]);
-                    S[j][1] = __fmaf_rn(alpha, d1, S[j][1]);
-                    S[j][2] = __fmaf_rn(alpha, d2, S[j][2]);
-                    T[j] = Ti;
-                    if (clamped) continue;
-                    const float dq = alpha * dal;
-                    acc[5] = __fmaf_rn(G, dal, acc[5]);
+                    S[j][0] = __fmaf_rn(a, d0, S[j][0]);
+                    S[j][1] = __fmaf_rn(a, d1, S[j][1]);
+                    S[j][2] = __fmaf_rn(a, d2, S[j][2]);
+                    T[j] = incl[j] ? Ti : T[j];
+                    const bool live = incl[j] & !clamped[j];
+                    const float dq = live ? a * dal : 0.0f;
+                    const float dx = dxs[j], dy = dys[j];
+                    acc[5] = __fmaf_rn(live ? G[j] : 0.0f, dal, acc[5]);
                     acc[0] = __fmaf_rn(dq, __fmaf_rn(s.p1.z, dx, s.p1.w * dy), acc[0]);
                     acc[1] = __fmaf_rn(dq, __fmaf_rn(s.p1.w, dx, s.p2.x * dy), acc[1]);
                     const float hq = -0.5f * dq;
@@ -274,13 +289,11 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendArgs a, int batch, int pe
                     acc[3] = __fmaf_rn(-dq, dx * dy, acc[3]);
                     acc[4] = __fmaf_rn(hq, dy * dy, acc[4]);
                 }
-                if (__any(contributed)) {
-                    float tot, tot8;
-                    wave_sum9(acc, tot, tot8);
-                    float* slot = a.grad2d + 9 * (int64_t)lds_id[jj];
-                    if ((lane & 7) == 0) unsafeAtomicAdd(slot + (lane >> 3), tot);
-                    if (lane == 1) unsafeAtomicAdd(slot + 8, tot8);
-                }
+                float tot, tot8;
+                wave_sum9(acc, tot, tot8);
+                float* slot = a.grad2d + 9 * (int64_t)lds_id[jj];
+                if ((lane & 7) == 0) unsafeAtomicAdd(slot + (lane >> 3), tot);
+                if (lane == 1) unsafeAtomicAdd(slot + 8, tot8);
             }
             __syncthreads();
             end = beg;

@@ -23,6 +23,7 @@ constexpr int kRsIpt = 8;
 constexpr int kRsTile = kRsThreads * kRsIpt;  // 2048
 constexpr int kRsDigits = 256;
 constexpr int kRsMaxBlocks = 1024;
+static_assert(kRsThreads == kRsDigits, "the downsweep maps one thread to one digit");
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const uint32_t lane = __lane_id();
@@ -216,9 +217,14 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_downsweep(const K* __restr
                                                                 K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                                 const uint32_t* d_count, int64_t max_count, int shift,
                                                                 uint32_t mask, const uint32_t* __restrict__ offsets) {
+    // Per tile: stable ranks -> local sorted order staged in LDS -> coalesced writes of each
+    // digit's run to its global position.
     __shared__ uint32_t run_off[kRsDigits];
     __shared__ uint32_t whist[kRsWaves][kRsDigits];
-    __shared__ uint32_t tile_total[kRsDigits];
+    __shared__ uint32_t tile_start[kRsDigits];
+    __shared__ uint32_t lds4[4];
+    __shared__ K stage_k[kRsTile];
+    __shared__ uint32_t stage_v[kRsTile];
     const int w = threadIdx.x / kWave, lane = __lane_id();
     for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) run_off[d] = offsets[(int64_t)d * gridDim.x + blockIdx.x];
     const Chunk c = chunk_of(d_count, max_count);
@@ -243,24 +249,36 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_downsweep(const K* __restr
             if (ok && (__ffsll((unsigned long long)peers) - 1) == lane) whist[w][d] = before + (uint32_t)__popcll(peers);
         }
         __syncthreads();
-        for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) {
-            uint32_t acc = 0;
+        // per digit (thread = digit): exclusive prefix over waves, tile total, tile-local start
+        uint32_t total_d = 0;
+        {
+            const int d = threadIdx.x;
             for (int ww = 0; ww < kRsWaves; ++ww) {
                 const uint32_t cnt = whist[ww][d];
-                whist[ww][d] = acc;
-                acc += cnt;
+                whist[ww][d] = total_d;
+                total_d += cnt;
             }
-            tile_total[d] = acc;
         }
+        uint32_t tile_count;
+        const uint32_t start_d = block_excl_scan256(total_d, lds4, tile_count);
+        tile_start[threadIdx.x] = start_d;
         __syncthreads();
         for (int j = 0; j < kRsIpt; ++j) {
             if (dig[j] == 0xffffffffu) continue;
-            const uint32_t dst = run_off[dig[j]] + whist[w][dig[j]] + rank[j];
-            keys_out[dst] = key[j];
-            vals_out[dst] = val[j];
+            const uint32_t lpos = tile_start[dig[j]] + whist[w][dig[j]] + rank[j];
+            stage_k[lpos] = key[j];
+            stage_v[lpos] = val[j];
         }
         __syncthreads();
-        for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) run_off[d] += tile_total[d];
+        for (uint32_t i = threadIdx.x; i < tile_count; i += kRsThreads) {
+            const K k = stage_k[i];
+            const uint32_t d = digit_of(k, shift, mask);
+            const uint32_t dst = run_off[d] + (i - tile_start[d]);
+            keys_out[dst] = k;
+            vals_out[dst] = stage_v[i];
+        }
+        __syncthreads();
+        run_off[threadIdx.x] += total_d;
         __syncthreads();
     }
 }

@@ -307,7 +307,7 @@ class Graph:
 
 
 def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps: int = 2, dl_images=None):
-    """Times tile {8, 16, 32} x batch {64, 128, 256}; returns (best Config, 3x3 ms table)."""
+    """Times tile {8, 16, 32} x batch {32, 64, 128, 256}; returns (best Config, 3x4 ms table)."""
     lib = L.load()
     npix = sum(h * w for h, w in image_sizes(cams))
     images = torch.empty(3 * npix, dtype=torch.float32, device="cuda")
@@ -316,7 +316,7 @@ def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps:
     grads = zero_grads_like(dscene)
     alloc = TorchAllocator()
     best = L.MegsConfig()
-    ms = (ctypes.c_float * 9)()
+    ms = (ctypes.c_float * 12)()
     sc = dscene.struct()
     cam_arr = cameras_struct(cams)
     c = base.struct()
@@ -324,7 +324,7 @@ def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps:
     L.check(lib.megs_autotune(ctypes.byref(sc), cam_arr, len(cams), ctypes.byref(c), alloc.fn, None,
                               images.data_ptr(), dl.data_ptr(), ctypes.byref(g), reps, _stream(None),
                               ctypes.byref(best), ms))
-    table = np.array(list(ms), np.float32).reshape(3, 3)
+    table = np.array(list(ms), np.float32).reshape(3, 4)
     return Config(best.tile, best.batch, best.flags, best.pair_capacity), table
 
 

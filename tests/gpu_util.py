@@ -84,7 +84,10 @@ def grad_close(name, g, ref, rel=GRAD_REL, abs_sum=None):
     Summing FP32 terms in any order errs relative to the terms' absolute sum, not to their
     (possibly cancelling) total, which is what both forms allow for.
     """
-    scale = np.abs(ref).max() if ref.size else 0.0
+    assert g.shape == ref.shape, (name, g.shape, ref.shape)
+    if ref.size == 0:
+        return 0.0
+    scale = np.abs(ref).max()
     if scale == 0:
         assert np.abs(g).max() == 0, name
         return 0.0

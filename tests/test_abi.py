@@ -54,6 +54,7 @@ def _forward(sc, cams, nv, cfg):
 @pytest.mark.parametrize("kw,needle", [
     (dict(tile=12), "tile"),
     (dict(batch=100), "batch"),
+    (dict(batch=16), "batch"),
     (dict(flags=64), "flags"),
     (dict(nv=0), "n_views"),
     (dict(nv=65), "n_views"),

@@ -1,0 +1,197 @@
+"""GPU tests of the batched form (hipGraph capture and replay, persistent work queue, autotuner,
+capacity overflow) and of the full-size workloads on sampled outputs."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_07021_amd import _lib as L
+from paper_2509_07021_amd import render as R
+from paper_2509_07021_amd import scenes as S
+
+from gpu_util import IMG_TOL, grad_close, gpu_records, gpu_run, log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _uneven():
+    rng = np.random.default_rng(17)
+    scene = S.random_scene(rng, 6000, 4, masks=True, spread=1.2, logscale_mu=-3.2)
+    cams = [S.look_at((0, -4, 0.3), 160, 90), S.look_at((3, -2, 1), 96, 96, bg=(0.2, 0.3, 0.4)),
+            S.look_at((-2.5, 2.5, 1.5), 200, 120), S.look_at((0.5, 0.5, 4.0), 48, 136)]
+    return scene, cams
+
+
+def _eager(ds, cams, cfg, dl):
+    fr = R.forward(ds, cams, cfg)
+    grads = R.backward(ds, fr, dl)
+    torch.cuda.synchronize()
+    return fr, {p: (None if g is None else g.cpu().numpy()) for p, g in grads.items()}
+
+
+def test_graph_replays_match_eager():
+    scene, cams = _uneven()
+    log("graph replay: 4 uneven views")
+    ds = R.DeviceScene.from_scene(scene)
+    npix = sum(c.width * c.height for c in cams)
+    dl = torch.from_numpy(np.random.default_rng(2).standard_normal(3 * npix).astype(np.float32)).cuda()
+    cfg = R.Config(16, 64)
+    fr, g_ref = _eager(ds, cams, cfg, dl)
+    img_ref = fr.images.cpu().numpy()
+    P = int(fr.state.n_pairs)
+    graph = R.Graph(ds, cams, R.Config(16, 64, 0, P + 1000), with_backward=True, dl_images=dl)
+    for rep in range(3):
+        graph.launch()
+        graph.stream.synchronize()
+        assert graph.status() == P
+        np.testing.assert_array_equal(graph.images.cpu().numpy(), img_ref)
+        for p, g in graph.grads.items():
+            if g is not None:
+                grad_close(f"replay {rep} {p}", g.cpu().numpy().astype(np.float64), g_ref[p].astype(np.float64),
+                           rel=1e-5)
+        # eager work between replays on the default stream
+        _eager(ds, cams, cfg, dl)
+    graph.close()
+
+
+def test_graph_forward_only_and_capacity_overflow():
+    scene, cams = _uneven()
+    ds = R.DeviceScene.from_scene(scene)
+    fr = R.forward(ds, cams, R.Config(16, 64))
+    torch.cuda.synchronize()
+    P = int(fr.state.n_pairs)
+    log(f"overflow: {P} pairs into capacity {P // 2}")
+    small = R.Graph(ds, cams, R.Config(16, 64, 0, P // 2), with_backward=False)
+    small.launch()
+    with pytest.raises(L.MegsError) as e:
+        small.status()
+    assert e.value.status == L.MEGS_ERR_CAPACITY
+    small.close()
+    ok = R.Graph(ds, cams, R.Config(16, 64, 0, P), with_backward=False)
+    ok.launch()
+    assert ok.status() == P
+    np.testing.assert_array_equal(ok.images.cpu().numpy(), fr.images.cpu().numpy())
+    ok.close()
+
+
+def test_persistent_queue_matches_one_group_per_tile():
+    scene, cams = _uneven()
+    ds = R.DeviceScene.from_scene(scene)
+    npix = sum(c.width * c.height for c in cams)
+    dl = torch.from_numpy(np.random.default_rng(3).standard_normal(3 * npix).astype(np.float32)).cuda()
+    for tile in (8, 16, 32):
+        log(f"persistent tile {tile}")
+        fa, ga = _eager(ds, cams, R.Config(tile, 64), dl)
+        fb, gb = _eager(ds, cams, R.Config(tile, 64, L.MEGS_FLAG_PERSISTENT), dl)
+        np.testing.assert_array_equal(fa.images.cpu().numpy(), fb.images.cpu().numpy())
+        for p in ga:
+            if ga[p] is not None:
+                grad_close(f"persistent {p}", gb[p].astype(np.float64), ga[p].astype(np.float64), rel=1e-5)
+
+
+def test_autotuner_picks_a_valid_config_with_the_same_images():
+    scene, cams = _uneven()
+    ds = R.DeviceScene.from_scene(scene)
+    best, table = R.autotune(ds, cams, R.Config(16, 64), reps=1)
+    log(f"autotune best tile {best.tile} batch {best.batch}\n{table}")
+    assert best.tile in (8, 16, 32) and best.batch in (32, 64, 128, 256)
+    assert np.all(np.isfinite(table)) and np.all(table > 0)
+    a = R.forward(ds, cams, R.Config(16, 64)).images.cpu().numpy()
+    b = R.forward(ds, cams, best).images.cpu().numpy()
+    d = np.abs(a - b)
+    assert (d > IMG_TOL).mean() < 1e-3 and d.max() < 1e-2
+
+
+def _sampled_tiles(ranges, frac, seed):
+    rng = np.random.default_rng(seed)
+    pick = rng.random(ranges.shape[0]) < frac
+    rs = ranges.copy()
+    rs[~pick] = 0
+    return pick, rs
+
+
+def test_full_size_masked_1m_1080p_sampled():
+    """The 1M-Gaussian 1080p masked workload in the benchmark's launch configuration: the whole key
+    table bit-exact; blend, blend backward and projection backward on a seeded sample of tiles
+    (the loss weights vanish outside them, so the GPU's gradients come from the same pixels)."""
+    scene, cams = S.make_workload("masked_1m_1080p")
+    cam = cams[0]
+    tile = 16
+    log("full-size masked 1M 1080p: forward")
+    ds = R.DeviceScene.from_scene(scene)
+    fr = R.forward(ds, cams, R.Config(tile, 64))
+    torch.cuda.synchronize()
+    g = {"n_pairs": int(fr.state.n_pairs)}
+    nr = scene.n
+    g["mean"] = fr.buffer("mean", 2 * nr, torch.float64).view(nr, 2).cpu().numpy()
+    g["conic_o"] = fr.buffer("conic_o", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
+    g["rgbd"] = fr.buffer("rgbd", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
+    g["radius"] = fr.buffer("radius", nr, torch.int32).cpu().numpy()
+    g["cutoff"] = fr.buffer("cutoff", nr, torch.float32).cpu().numpy()
+    P = g["n_pairs"]
+    vals = fr.buffer("vals", P, torch.int32).cpu().numpy().view(np.uint32)
+    tkeys = fr.buffer("tile_keys", P, torch.int32).cpu().numpy().view(np.uint32)
+    T = int(fr.state.n_tiles)
+    ranges = fr.buffer("ranges", 2 * T, torch.int32).view(T, 2).cpu().numpy().view(np.uint32)
+    rec = gpu_records(g)
+    log(f"key table: {P} pairs")
+    keys, ovals, oranges, _ = O.pairs(rec["u"], rec["v"], g["rgbd"][:, 3], rec["radius"], rec["conic"],
+                                      rec["cutoff"], rec["valid"], np.zeros(nr, np.int32), [cam], tile)
+    assert len(keys) == P
+    np.testing.assert_array_equal(vals, ovals)
+    np.testing.assert_array_equal(ranges, oranges)
+    np.testing.assert_array_equal(tkeys, (keys >> np.uint64(32)).astype(np.uint32))
+    pick, rs = _sampled_tiles(ranges, 0.02, 5)
+    log(f"blend on {pick.sum()} sampled tiles")
+    ob = O.blend(cam, tile, rec, vals, rs)
+    img = fr.images.view(3, cam.height, cam.width).cpu().numpy().astype(np.float64)
+    tx = (cam.width + tile - 1) // tile
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    in_pick = pick[(ys // tile) * tx + xs // tile]
+    ok = in_pick & (ob["flag"] == 0)
+    assert ok.sum() > 10000
+    assert np.abs(img - ob["image"])[:, ok].max() <= IMG_TOL
+    # backward on the sampled tiles only
+    w = S.loss_weights([cam], 21)[0] * ok[None].astype(np.float32)
+    nb = len(fr.alloc.blocks)
+    grads = R.backward(ds, fr, torch.from_numpy(w.reshape(-1)).cuda())
+    torch.cuda.synchronize()
+    g2 = fr.alloc.blocks[nb][: nr * 36].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
+    ref = np.zeros_like(g2)
+    ref_abs = np.zeros_like(g2)
+    O.blend_backward(cam, tile, rec, vals, rs, w, grad2d=ref, grad2d_abs=ref_abs)
+    for c, name in enumerate(("u", "v", "a", "b", "c", "o", "r", "g", "b_col")):
+        grad_close(f"grad2d[{name}]", g2[:, c], ref[:, c], abs_sum=ref_abs[:, c])
+    pl = scene.widened()
+    gr = O.zero_grads(pl)
+    O.project_backward(pl, scene.k, cam, tile, g2, gr)
+    for p in O.PLANES:
+        if gr[p] is not None:
+            grad_close(f"raw {p}", grads[p].cpu().numpy().astype(np.float64), gr[p])
+
+
+def test_fp16_3m_subsample_all_views():
+    """The 3M FP16/BF16 workload: a seeded 20k subsample, all 8 views at 1920x1080, end to end
+    against the FP64 oracle reading the exact stored values."""
+    scene, cams = S.make_workload("fp16_3m_8x1080p")
+    idx = np.sort(np.random.default_rng(105).choice(scene.n, 20_000, replace=False))
+    sub = scene.subset(idx)
+    log("fp16 subsample: 20k Gaussians x 8 views")
+    fwd = O.render(sub.widened(), sub.k, cams, 16)
+    w = [wi * (1 - vw["flag"])[None].astype(np.float32) for wi, vw in zip(S.loss_weights(cams, 4), fwd["views"])]
+    g = gpu_run(sub, cams, R.Config(16, 64), weights=w)
+    worst = 0.0
+    for vi in range(len(cams)):
+        ok = fwd["views"][vi]["flag"] == 0
+        d = np.abs(g["images"][vi] - fwd["images"][vi])[:, ok]
+        worst = max(worst, float(d.max()))
+    log(f"worst image error {worst:.2e}")
+    assert worst <= IMG_TOL
+    gr, _ = O.render_backward(sub.widened(), sub.k, cams, 16, w, fwd=fwd)
+    for p in O.PLANES:
+        if gr[p] is not None:
+            l2 = grad_close(p, g["grads"][p], gr[p])
+            log(f"  {p}: relative L2 {l2:.2e}")

@@ -43,7 +43,7 @@ def _check_records(g, fwd, n_views):
     np.testing.assert_allclose(g["rgbd"][v, :3], rec["rgb"][v], rtol=0, atol=2e-6)
     dr = np.abs(g["radius"][v] - rec["radius"][v])
     assert dr.max() <= 1 and (dr > 0).mean() < 1e-3
-    np.testing.assert_allclose(g["cutoff"][v], rec["cutoff"][v], rtol=1e-5)
+    np.testing.assert_allclose(g["cutoff"][v], rec["cutoff"][v], rtol=1e-5, atol=1e-5)
 
 
 def _check_key_stage(g, cams, tile, n):
@@ -123,7 +123,7 @@ def test_small_workload_all_stages():
     _run_all_stages(scene, cams, R.Config(16, 64))
 
 
-@pytest.mark.parametrize("tile,batch", [(8, 64), (16, 128), (32, 256)])
+@pytest.mark.parametrize("tile,batch", [(8, 64), (16, 32), (16, 128), (32, 256)])
 def test_tile_and_batch_variants(tile, batch):
     scene, cams = S.make_workload("small_2k_128px")
     _run_all_stages(scene, cams, R.Config(tile, batch))
