@@ -440,7 +440,7 @@ static int frag_alpha(const orecs *rc, int64_t g, double px, double py, double *
  */
 static int64_t composite(const orecs *rc, const uint32_t *list, int64_t len, double px, double py,
                          const double bg[3], double out[3], double *T_out, int32_t *last_out, int *flag_out,
-                         int64_t *sig_out) {
+                         int64_t *sig_out, double *weight_slots) {
     double T = 1.0, C[3] = {0, 0, 0};
     int32_t last = 0;
     int flag = 0;
@@ -455,6 +455,7 @@ static int64_t composite(const orecs *rc, const uint32_t *list, int64_t len, dou
         flag |= near_rel(Tn, T_MIN);
         if (Tn < T_MIN) break;
         for (int c = 0; c < 3; ++c) C[c] += alpha * T * rc->rgb[3 * g + c];
+        if (weight_slots) weight_slots[pos] += alpha * T;
         T = Tn;
         last = (int32_t)(pos + 1);
         sig = sig * 1000003 + (int64_t)g * 2 + clamped;
@@ -471,15 +472,20 @@ static int64_t composite(const orecs *rc, const uint32_t *list, int64_t len, dou
  * Tiled forward blend of one view. vals/ranges are the view's slice of the sorted
  * key table (ranges indexed by the view-local tile, positions into vals).
  * image [3][h][w], T [h][w], last [h][w], flag [h][w], sig [h][w] (decision signature).
+ * importance (nullable, [nrec]): adds each record's blending weights alpha * T summed over the
+ * pixels -- the importance score of the Appendix's proximal-operator description -- through
+ * per-pair slots summed in list order. npairs: length of vals (needed with importance).
  * Returns the number of (pixel, list entry) evaluations.
  */
 int64_t oracle_blend(int32_t w, int32_t h, int32_t tile, const double *bg,
                      const double *u, const double *v, const double *conic, const double *o, const double *rgb,
                      const uint32_t *vals, const uint32_t *ranges,
-                     double *image, double *T, int32_t *last, int32_t *flag, int64_t *sig) {
+                     double *image, double *T, int32_t *last, int32_t *flag, int64_t *sig,
+                     int64_t npairs, double *importance) {
     orecs rc = {u, v, conic, o, rgb};
     int tiles_x = (w + tile - 1) / tile, tiles_y = (h + tile - 1) / tile;
     int64_t total = 0;
+    double *wslots = importance ? (double *)calloc((size_t)(npairs > 0 ? npairs : 1), sizeof(double)) : NULL;
     #pragma omp parallel for schedule(dynamic) reduction(+ : total)
     for (int t = 0; t < tiles_x * tiles_y; ++t) {
         int tx = t % tiles_x, ty = t / tiles_x;
@@ -490,10 +496,14 @@ int64_t oracle_blend(int32_t w, int32_t h, int32_t tile, const double *bg,
                 int fl;
                 int64_t p = (int64_t)y * w + x;
                 total += composite(&rc, vals + s, (int64_t)e - s, x + 0.5, y + 0.5, bg, out, &T[p], &last[p], &fl,
-                                   sig ? &sig[p] : NULL);
+                                   sig ? &sig[p] : NULL, wslots ? wslots + s : NULL);
                 flag[p] = fl;
                 for (int c = 0; c < 3; ++c) image[(int64_t)c * w * h + p] = out[c];
             }
+    }
+    if (wslots) {
+        for (int64_t i = 0; i < npairs; ++i) importance[vals[i]] += wslots[i];
+        free(wslots);
     }
     return total;
 }
@@ -527,7 +537,7 @@ void oracle_bruteforce(int32_t w, int32_t h, const double *bg, int64_t nrec, con
             int fl;
             int32_t lst;
             int64_t p = (int64_t)y * w + x;
-            composite(&rc, list, m, x + 0.5, y + 0.5, bg, out, &T[p], &lst, &fl, NULL);
+            composite(&rc, list, m, x + 0.5, y + 0.5, bg, out, &T[p], &lst, &fl, NULL, NULL);
             last[p] = lst;
             flag[p] = fl;
             for (int c = 0; c < 3; ++c) image[(int64_t)c * w * h + p] = out[c];

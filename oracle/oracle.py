@@ -72,7 +72,7 @@ def lib():
                                    ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.oracle_pairs.restype = ctypes.c_int64
         L.oracle_blend.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
-                                   vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+                                   vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp]
         L.oracle_blend.restype = ctypes.c_int64
         L.oracle_bruteforce.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64, vp,
                                         vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -197,8 +197,9 @@ def _recs(rec):
     return (_c64(rec["u"]), _c64(rec["v"]), _c64(rec["conic"]), _c64(rec["o"]), _c64(rec["rgb"]))
 
 
-def blend(cam, tile: int, rec: dict, vals, ranges_view):
-    """Tiled forward blend of one view. ranges_view: the view's [T_v][2] slice."""
+def blend(cam, tile: int, rec: dict, vals, ranges_view, importance=None):
+    """Tiled forward blend of one view. ranges_view: the view's [T_v][2] slice. When importance
+    (float64 [records]) is given, each record's blending weights are added into it."""
     u, v, conic, o, rgb = _recs(rec)
     w, h = cam.width, cam.height
     bg = np.asarray(cam.bg, np.float64)
@@ -210,7 +211,8 @@ def blend(cam, tile: int, rec: dict, vals, ranges_view):
     vals = np.ascontiguousarray(vals, np.uint32)
     rv = np.ascontiguousarray(ranges_view, np.uint32)
     nfrag = lib().oracle_blend(w, h, tile, _ptr(bg), _ptr(u), _ptr(v), _ptr(conic), _ptr(o), _ptr(rgb),
-                               _ptr(vals), _ptr(rv), _ptr(image), _ptr(T), _ptr(last), _ptr(flag), _ptr(sig))
+                               _ptr(vals), _ptr(rv), _ptr(image), _ptr(T), _ptr(last), _ptr(flag), _ptr(sig),
+                               len(vals), _ptr(importance))
     return {"image": image, "T": T, "last": last, "flag": flag, "sig": sig, "nfrag": int(nfrag)}
 
 
@@ -324,3 +326,60 @@ def fd_gradient(planes: dict, k: int, cams, tile: int, weights, plane: str, flat
         out[j] = (Lp - Lm) / (2 * h)
         ok[j] = (sp == sig0) and (sm == sig0)
     return out, ok
+
+
+# ----------------------------------------------------------------- pruning ----
+# The memory-constrained optimisation of Sec. 3.3 (Alg. 1) and the proximal operators of the
+# Appendix, written as their plain definitions.
+
+def importance(planes: dict, k: int, cams, tile: int) -> np.ndarray:
+    """I_i = sum over the pixels of all views of Gaussian i's blending weight alpha * T
+    (Appendix, importance-based selection). Returns float64 [n]."""
+    fwd = render(planes, k, cams, tile)
+    n = len(planes["op_logit"])
+    imp = np.zeros(n * len(cams), np.float64)
+    off = fwd["tile_off"]
+    for vi, c in enumerate(cams):
+        blend(c, tile, fwd["records"], fwd["vals"], fwd["ranges"][off[vi]:off[vi + 1]], importance=imp)
+    return imp.reshape(len(cams), n).sum(0)
+
+
+def topk_keep(score, kappa: int) -> np.ndarray:
+    """Mask of the kappa largest scores; equal scores are taken in ascending index order."""
+    score = np.asarray(score, np.float64).ravel()
+    kappa = max(0, min(int(kappa), score.size))
+    order = np.lexsort((np.arange(score.size), -score))
+    keep = np.zeros(score.size, bool)
+    keep[order[:kappa]] = True
+    return keep
+
+
+def lobe_dynamic_range(z, amp) -> np.ndarray:
+    """D = |a| (1 - exp(-2 z)) per lobe (Sec. 3.3.2, the dynamic range of a lobe over the
+    sphere), with |a| the Euclidean norm of the RGB amplitude. z [k][n], amp [k][3][n]."""
+    a = np.linalg.norm(np.asarray(amp, np.float64), axis=1)
+    return a * (1.0 - np.exp(-2.0 * np.asarray(z, np.float64)))
+
+
+def prox(o, lam_o, imp, kappa_o: int, s, lam_s, amp, kappa_s: int):
+    """Proximal step of Alg. 1 with the factorised projection: keep the kappa_o entries of
+    o + lambda_o with the highest importance, and the kappa_s lobes of s + lambda_s with the
+    highest dynamic range D (evaluated at s + lambda_s); zero the rest."""
+    zo = np.asarray(o, np.float64) + np.asarray(lam_o, np.float64)
+    zs = np.asarray(s, np.float64) + np.asarray(lam_s, np.float64)
+    o_t = np.where(topk_keep(imp, kappa_o), zo, 0.0)
+    keep_s = topk_keep(lobe_dynamic_range(zs, amp).ravel(), kappa_s).reshape(zs.shape)
+    s_t = np.where(keep_s, zs, 0.0)
+    return o_t, s_t
+
+
+def dual_update(lam, x, x_t):
+    """lambda <- lambda + (x - x_tilde) (Alg. 1, dual update)."""
+    return np.asarray(lam, np.float64) + (np.asarray(x, np.float64) - np.asarray(x_t, np.float64))
+
+
+def penalty_grad(grad, delta: float, x, x_t, lam):
+    """grad + delta (x - x_tilde + lambda): the augmented-Lagrangian term of the gradient step
+    of Alg. 1 (delta_o = delta rho_o, delta_s = delta rho_s)."""
+    return np.asarray(grad, np.float64) + delta * (np.asarray(x, np.float64) - np.asarray(x_t, np.float64)
+                                                   + np.asarray(lam, np.float64))
