@@ -228,6 +228,42 @@ typedef struct {
 megs_status megs_profile_begin(void);
 megs_status megs_profile_end(megs_profile *out);
 
+/*
+ * ---- Memory-constrained optimisation steps (Sec. 3.3, Alg. 1; Appendix, proximal operators) ----
+ * All pointers are device memory; all calls enqueue on `stream` and return without syncing.
+ */
+
+/* Forward render (as megs_render_forward) that also adds, for every Gaussian i, its blending
+ * weights alpha * T summed over all pixels of all views into importance[i] (device float[n], not
+ * cleared): the importance score of the Appendix's importance-based opacity selection. */
+megs_status megs_render_importance(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
+                                   const megs_config *cfg, megs_alloc_fn alloc, void *alloc_ctx,
+                                   float *images, float *importance, megs_state *state, void *stream);
+
+/* Lobe dynamic range D = |a| (1 - exp(-2 z)) with z = sharp + lam (lam nullable) and |a| the
+ * Euclidean norm of the RGB amplitude (Sec. 3.3.2, Eq. for D_i). sharp, lam, D: float[k][n];
+ * amp: float[k][3][n]. */
+megs_status megs_lobe_range(int64_t n, int32_t k, const float *sharp, const float *lam, const float *amp,
+                            float *D, void *stream);
+
+/* keep[i] = 1 for the kappa largest score[i] (equal scores taken in ascending index order), else
+ * 0; kappa <= 0 keeps none, kappa >= n keeps all. score: float[n], keep: uint8[n]. Scratch of
+ * O(n) bytes comes from alloc. The selection of both factorised proximal operators. */
+megs_status megs_select_topk(const float *score, int64_t n, int64_t kappa, megs_alloc_fn alloc, void *alloc_ctx,
+                             uint8_t *keep, void *stream);
+
+/* Proximal step of Alg. 1 given the selection: x_tilde = keep ? x + lam : 0 (float[count]). */
+megs_status megs_prox_apply(int64_t count, const float *x, const float *lam, const uint8_t *keep, float *x_tilde,
+                            void *stream);
+
+/* Dual update of Alg. 1: lam += x - x_tilde (float[count], lam updated in place). */
+megs_status megs_dual_update(int64_t count, float *lam, const float *x, const float *x_tilde, void *stream);
+
+/* Penalty term of the gradient step of Alg. 1: grad += delta (x - x_tilde + lam), with
+ * delta = delta_o or delta_s (float[count], grad updated in place). */
+megs_status megs_penalty_grad(int64_t count, float delta, const float *x, const float *x_tilde, const float *lam,
+                              float *grad, void *stream);
+
 /* Description of the last error on the calling thread ("" when none). */
 const char *megs_last_error(void);
 

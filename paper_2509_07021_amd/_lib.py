@@ -22,7 +22,9 @@ MEGS_MAX_VIEWS = 64
 
 EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", "megs_graph_create",
             "megs_graph_launch", "megs_graph_status", "megs_graph_state", "megs_graph_destroy",
-            "megs_autotune", "megs_profile_begin", "megs_profile_end", "megs_last_error", "megs_version")
+            "megs_autotune", "megs_profile_begin", "megs_profile_end", "megs_last_error", "megs_version",
+            "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply", "megs_dual_update",
+            "megs_penalty_grad")
 
 PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
           "base", "axis", "sharp", "amp", "lmask_logit")
@@ -100,10 +102,19 @@ def load():
     L.megs_graph_destroy.restype = None
     L.megs_autotune.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ALLOC_FN, _vp,
                                 _vp, _vp, P(MegsSceneGrad), ctypes.c_int32, _vp, P(MegsConfig), P(ctypes.c_float)]
+    L.megs_render_importance.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ALLOC_FN,
+                                         _vp, _vp, _vp, P(MegsState), _vp]
+    L.megs_lobe_range.argtypes = [ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]
+    L.megs_select_topk.argtypes = [_vp, ctypes.c_int64, ctypes.c_int64, ALLOC_FN, _vp, _vp, _vp]
+    L.megs_prox_apply.argtypes = [ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+    L.megs_dual_update.argtypes = [ctypes.c_int64, _vp, _vp, _vp, _vp]
+    L.megs_penalty_grad.argtypes = [ctypes.c_int64, ctypes.c_float, _vp, _vp, _vp, _vp, _vp]
     L.megs_profile_begin.argtypes = []
     L.megs_profile_end.argtypes = [P(MegsProfile)]
     for f in ("megs_render_forward", "megs_render_backward", "megs_state_status", "megs_graph_create",
-              "megs_graph_launch", "megs_graph_status", "megs_autotune", "megs_profile_begin", "megs_profile_end"):
+              "megs_graph_launch", "megs_graph_status", "megs_autotune", "megs_profile_begin", "megs_profile_end",
+              "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply",
+              "megs_dual_update", "megs_penalty_grad"):
         getattr(L, f).restype = ctypes.c_int
     L.megs_last_error.restype = ctypes.c_char_p
     L.megs_last_error.argtypes = []

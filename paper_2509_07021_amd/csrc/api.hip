@@ -304,7 +304,7 @@ megs_status enqueue_front(const megs_scene* sc, const Layout& L, const megs_conf
 
 // Emission, pair sort, ranges and the forward blend; fills the pair fields of state.
 megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_config* cfg, Frame& f, Pairs& p,
-                         float* images, megs_state* state, hipStream_t s) {
+                         float* images, megs_state* state, hipStream_t s, float* importance = nullptr) {
     const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
     const bool persistent = cfg->flags & MEGS_FLAG_PERSISTENT;
     {
@@ -346,6 +346,8 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     a.image = images; a.T_final = f.T_final; a.last = f.last;
     a.queue = f.queue;
     a.stats = (cfg->flags & MEGS_FLAG_STATS) ? reinterpret_cast<unsigned long long*>(f.status + 4) : nullptr;
+    a.importance = importance;
+    a.n = L.n;
     if (persistent) HIP_TRY(launch_fill_u32(f.queue, 0u, 4, s));
     {
         StageTimer t(MEGS_STAGE_BLEND_FWD, s);
@@ -425,7 +427,8 @@ megs_status check_grads(const megs_scene* sc, const megs_scene_grad* g) {
 }
 
 megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t nv, const megs_config* cfg,
-                         megs_alloc_fn alloc, void* ctx, float* images, megs_state* state, hipStream_t s) {
+                         megs_alloc_fn alloc, void* ctx, float* images, megs_state* state, hipStream_t s,
+                         float* importance = nullptr) {
     megs_status st = check_args(sc, cams, nv, cfg);
     if (st != MEGS_OK) return st;
     if (!alloc || !images || !state) return fail(MEGS_ERR_ARG, "null allocator, image or state");
@@ -449,7 +452,7 @@ megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t 
     void* pm = alloc(ctx, pairs_bytes(cap, one_stage));
     if (!pm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", pairs_bytes(cap, one_stage));
     Pairs p = carve_pairs(pm, cap, one_stage);
-    st = enqueue_back(sc, L, cfg, f, p, images, state, s);
+    st = enqueue_back(sc, L, cfg, f, p, images, state, s, importance);
     state->n_pairs = counted >= 0 ? counted : cap;
     return st;
 }
@@ -525,6 +528,66 @@ megs_status megs_render_backward(const megs_scene* scene, const megs_camera* cam
     float* grad2d = static_cast<float*>(gm);
     uint32_t* queue = reinterpret_cast<uint32_t*>(static_cast<char*>(gm) + gbytes - 256);
     return enqueue_backward(scene, L, cfg, state, dl_dimages, grad2d, queue, grads, static_cast<hipStream_t>(stream));
+}
+
+megs_status megs_render_importance(const megs_scene* scene, const megs_camera* cams, int32_t n_views,
+                                   const megs_config* cfg, megs_alloc_fn alloc, void* alloc_ctx, float* images,
+                                   float* importance, megs_state* state, void* stream) {
+    g_err[0] = 0;
+    if (!importance) return fail(MEGS_ERR_ARG, "null importance output");
+    if (cfg && (cfg->flags & MEGS_FLAG_STATS)) return fail(MEGS_ERR_UNSUPPORTED, "importance with MEGS_FLAG_STATS");
+    return forward_impl(scene, cams, n_views, cfg, alloc, alloc_ctx, images, state, static_cast<hipStream_t>(stream),
+                        importance);
+}
+
+megs_status megs_lobe_range(int64_t n, int32_t k, const float* sharp, const float* lam, const float* amp, float* D,
+                            void* stream) {
+    g_err[0] = 0;
+    if (n < 0 || k < 0 || k > MEGS_MAX_LOBES) return fail(MEGS_ERR_ARG, "bad n or k");
+    if (n * k > 0 && (!sharp || !amp || !D)) return fail(MEGS_ERR_ARG, "null sharpness, amplitude or output");
+    HIP_TRY(launch_lobe_range(n, k, sharp, lam, amp, D, static_cast<hipStream_t>(stream)));
+    return MEGS_OK;
+}
+
+megs_status megs_select_topk(const float* score, int64_t n, int64_t kappa, megs_alloc_fn alloc, void* alloc_ctx,
+                             uint8_t* keep, void* stream) {
+    g_err[0] = 0;
+    if (n < 0 || n >= (1ll << 31)) return fail(MEGS_ERR_ARG, "n out of range");
+    if (n == 0) return MEGS_OK;
+    if (!score || !keep || !alloc) return fail(MEGS_ERR_ARG, "null score, keep or allocator");
+    void* scratch = nullptr;
+    if (kappa > 0 && kappa < n) {
+        scratch = alloc(alloc_ctx, select_scratch_bytes(n));
+        if (!scratch) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", select_scratch_bytes(n));
+    }
+    HIP_TRY(launch_select_topk(score, n, kappa, scratch, keep, static_cast<hipStream_t>(stream)));
+    return MEGS_OK;
+}
+
+megs_status megs_prox_apply(int64_t count, const float* x, const float* lam, const uint8_t* keep, float* x_tilde,
+                            void* stream) {
+    g_err[0] = 0;
+    if (count < 0) return fail(MEGS_ERR_ARG, "count < 0");
+    if (count > 0 && (!x || !lam || !keep || !x_tilde)) return fail(MEGS_ERR_ARG, "null argument");
+    HIP_TRY(launch_prox_apply(count, x, lam, keep, x_tilde, static_cast<hipStream_t>(stream)));
+    return MEGS_OK;
+}
+
+megs_status megs_dual_update(int64_t count, float* lam, const float* x, const float* x_tilde, void* stream) {
+    g_err[0] = 0;
+    if (count < 0) return fail(MEGS_ERR_ARG, "count < 0");
+    if (count > 0 && (!x || !lam || !x_tilde)) return fail(MEGS_ERR_ARG, "null argument");
+    HIP_TRY(launch_dual(count, lam, x, x_tilde, static_cast<hipStream_t>(stream)));
+    return MEGS_OK;
+}
+
+megs_status megs_penalty_grad(int64_t count, float delta, const float* x, const float* x_tilde, const float* lam,
+                              float* grad, void* stream) {
+    g_err[0] = 0;
+    if (count < 0) return fail(MEGS_ERR_ARG, "count < 0");
+    if (count > 0 && (!x || !lam || !x_tilde || !grad)) return fail(MEGS_ERR_ARG, "null argument");
+    HIP_TRY(launch_penalty(count, delta, x, x_tilde, lam, grad, static_cast<hipStream_t>(stream)));
+    return MEGS_OK;
 }
 
 megs_status megs_state_status(const megs_state* state, int64_t* pairs_needed, void* stream) {

@@ -87,10 +87,11 @@ __device__ __forceinline__ int64_t next_tile(const BlendArgs& a, int64_t prev, b
     return (int64_t)t;
 }
 
-template <int TILE, bool STATS>
+template <int TILE, bool STATS, bool IMP>
 __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int persistent) {
     constexpr int PPT = TILE * TILE / 64, ROWS = 64 / TILE;
     extern __shared__ Staged lds[];
+    uint32_t* lds_id = reinterpret_cast<uint32_t*>(lds + batch);  // record ids (importance only)
     const int lane = threadIdx.x;
     const int lx = lane % TILE, ly = lane / TILE;
     uint32_t n_blended = 0, n_evaluated = 0;
@@ -111,7 +112,11 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int pe
         bool active = true;
         for (uint32_t base = rg.x; base < rg.y && active; base += batch) {
             const int cnt = (int)min((uint32_t)batch, rg.y - base);
-            for (int q = lane; q < cnt; q += 64) stage(a, a.vals[base + q], (double)c.x0, (double)c.y0, &lds[q]);
+            for (int q = lane; q < cnt; q += 64) {
+                const uint32_t g = a.vals[base + q];
+                stage(a, g, (double)c.x0, (double)c.y0, &lds[q]);
+                if (IMP) lds_id[q] = g;
+            }
             __syncthreads();
             for (int jj = 0; jj < cnt; ++jj) {
                 const Staged s = lds[jj];
@@ -129,12 +134,14 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int pe
                 }
                 if (!__any(any_pass)) continue;  // wave-uniform: no pixel of the tile is hit
                 bool live = false;
+                float wsum = 0.0f;
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
                     const float Tn = T[j] * (1.0f - alpha[j]);
                     const bool term = pass[j] & (Tn < kTMin);
                     const bool incl = pass[j] & !term;
                     const float w = incl ? alpha[j] * T[j] : 0.0f;
+                    if (IMP) wsum += w;
                     C[j][0] = __fmaf_rn(w, s.p2.y, C[j][0]);
                     C[j][1] = __fmaf_rn(w, s.p2.z, C[j][1]);
                     C[j][2] = __fmaf_rn(w, s.p2.w, C[j][2]);
@@ -142,6 +149,13 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int pe
                     last[j] = incl ? pos + 1 : last[j];
                     live |= T[j] > 0.0f;
                     if (STATS) n_blended += incl;
+                }
+                if (IMP) {
+                    // importance score: blending weights of this record summed over the tile's pixels
+#pragma unroll
+                    for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d);
+                    if (lane == 0 && wsum != 0.0f)
+                        unsafeAtomicAdd(a.importance + (lds_id[jj] - (int64_t)c.view * a.n), wsum);
                 }
                 if (!__any(live)) { active = false; break; }
             }
@@ -305,12 +319,17 @@ constexpr int64_t kPersistentGroups = 256 * 24;  // 24 resident single-wave grou
 
 template <int TILE>
 hipError_t launch_fwd_t(const BlendArgs& a, int batch, bool persistent, hipStream_t stream) {
-    const size_t lds = (size_t)batch * sizeof(Staged);
+    const size_t lds = (size_t)batch * (sizeof(Staged) + (a.importance ? sizeof(uint32_t) : 0));
     const unsigned grid = (unsigned)(persistent && a.n_tiles > kPersistentGroups ? kPersistentGroups : a.n_tiles);
-    if (a.stats)
-        hipLaunchKernelGGL((k_blend_fwd<TILE, true>), dim3(grid), dim3(64), lds, stream, a, batch, (int)persistent);
+    if (a.importance)
+        hipLaunchKernelGGL((k_blend_fwd<TILE, false, true>), dim3(grid), dim3(64), lds, stream, a, batch,
+                           (int)persistent);
+    else if (a.stats)
+        hipLaunchKernelGGL((k_blend_fwd<TILE, true, false>), dim3(grid), dim3(64), lds, stream, a, batch,
+                           (int)persistent);
     else
-        hipLaunchKernelGGL((k_blend_fwd<TILE, false>), dim3(grid), dim3(64), lds, stream, a, batch, (int)persistent);
+        hipLaunchKernelGGL((k_blend_fwd<TILE, false, false>), dim3(grid), dim3(64), lds, stream, a, batch,
+                           (int)persistent);
     return hipGetLastError();
 }
 

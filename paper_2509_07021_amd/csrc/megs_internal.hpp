@@ -193,8 +193,22 @@ struct BlendArgs {
     float* grad2d;        // backward only, [NR][9]
     uint32_t* queue;      // persistent mode work counter (null: one workgroup per tile)
     unsigned long long* stats;  // forward fragment counters [blended, evaluated] (null: not counted)
+    float* importance;          // forward: per-Gaussian sum of blending weights (null: not computed)
+    int64_t n;                  // Gaussians per view (record r of view v is Gaussian r - v n)
 };
 hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int batch, bool persistent, hipStream_t stream);
 hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int batch, bool persistent, hipStream_t stream);
+
+// pruning steps (prune.hip)
+size_t select_scratch_bytes(int64_t n);
+hipError_t launch_select_topk(const float* score, int64_t n, int64_t kappa, void* scratch, uint8_t* keep,
+                              hipStream_t stream);
+hipError_t launch_lobe_range(int64_t n, int32_t k, const float* s, const float* lam, const float* amp, float* D,
+                             hipStream_t stream);
+hipError_t launch_prox_apply(int64_t count, const float* x, const float* lam, const uint8_t* keep, float* xt,
+                             hipStream_t stream);
+hipError_t launch_dual(int64_t count, float* lam, const float* x, const float* xt, hipStream_t stream);
+hipError_t launch_penalty(int64_t count, float delta, const float* x, const float* xt, const float* lam, float* grad,
+                          hipStream_t stream);
 
 }  // namespace megs
