@@ -249,6 +249,9 @@ static void project_one(const oscene *sc, const ocam *cam, int tile, int64_t i, 
     for (int c = 0; c < 3; ++c)
         if (!isfinite(p->rgb[c])) { p->valid = 0; return; }
 
+    /* the ellipse level bounding alpha >= 1/255 depends on the opacity only */
+    p->cutoff = cutoff_level(p->o_eff);
+
     /* tile rectangle from pixel bounds floor(u) -/+ r, clipped to the image */
     int tiles_x = (cam->width + tile - 1) / tile, tiles_y = (cam->height + tile - 1) / tile;
     double x_lo = floor(p->u) - r, x_hi = floor(p->u) + r;
@@ -261,7 +264,6 @@ static void project_one(const oscene *sc, const ocam *cam, int tile, int64_t i, 
     p->rect[0] = (int)x_lo / tile; p->rect[1] = (int)x_hi / tile;
     p->rect[2] = (int)y_lo / tile; p->rect[3] = (int)y_hi / tile;
     (void)tiles_x; (void)tiles_y;
-    p->cutoff = cutoff_level(p->o_eff);
     p->ntiles = 0;
     for (int ty = p->rect[2]; ty <= p->rect[3]; ++ty)
         for (int tx = p->rect[0]; tx <= p->rect[1]; ++tx) {

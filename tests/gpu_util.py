@@ -99,7 +99,8 @@ def grad_close(name, g, ref, rel=GRAD_REL, abs_sum=None):
     else:
         bound = rel * np.abs(ref) + 1e-2 * rel * scale
     bad = d > bound
-    i = int(np.argmax(d / bound))
-    assert not bad.any(), (f"{name}: {bad.sum()} elements over; worst {(d / bound).max():.2f}x at {i}: "
+    ratio = np.divide(d, bound, out=np.zeros_like(d), where=bound > 0)
+    i = int(np.argmax(np.where(bad, np.inf, ratio)))
+    assert not bad.any(), (f"{name}: {bad.sum()} elements over; worst {ratio.max():.2f}x at {i}: "
                            f"got {g[i]:.6e}, oracle {ref[i]:.6e}")
     return l2
