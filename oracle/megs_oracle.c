@@ -94,48 +94,61 @@ typedef struct {
 static double P(const double *plane, int64_t n, int64_t row, int64_t i) { return plane[row * n + i]; }
 
 /*
- * Tile selection inside the rectangle: a tile is listed when the ellipse {p : q(p) <= k} reaches
- * the box of its pixel centres [X0, X1] x [Y0, Y1], with q(p) = (p - m)' C (p - m) and C the conic.
- * The minimum of q over the box is 0 when m is inside; otherwise it lies on one of the four
- * edges, where q restricted to the edge is a 1D parabola whose minimiser is clamped to the edge.
- * The level k is 2 ln(255 o) widened by 0.2% and 1e-4 (the blend's alpha >= 1/255 test is
- * q <= 2 ln(255 o)), so FP32 rounding in a renderer cannot reach past an unlisted tile.
+ * Tile selection inside the rectangle. E = {p : (p - m)' C (p - m) <= k}, C the conic, k the
+ * cutoff level (2 ln(255 o) widened by 0.2% and 1e-4: the blend's alpha >= 1/255 test is
+ * q <= 2 ln(255 o), so FP32 rounding in a renderer cannot reach past an unlisted tile).
+ * For each tile row, with band = the row's pixel-centre rows [Y0, Y1], the listed columns are the
+ * tiles whose pixel-centre column range meets the x-extent of E restricted to the band.
+ * With S = C^-1 the leftmost/rightmost points of E sit at dy = -/+ S_xy sqrt(k / S_xx), and
+ * x_max(dy) = mx + (sqrt(k a - det dy^2) - b dy) / a is concave (x_min convex), so the extent over
+ * the band is attained at those dy clamped into the band. A tile column tx meets [x_min, x_max]
+ * when tx T + 1/2 <= x_max and (tx + 1) T - 1/2 >= x_min.
+ * Same FP64 operations, in the same order, as any implementation that must list the same tiles.
  */
 static double cutoff_level(double o) { return 2.004 * log(255.0 * o) + 1e-4; }
 
-static int ellipse_reaches_box(double u, double v, double a, double b, double c, double k,
-                               double X0, double X1, double Y0, double Y1) {
-    if (u >= X0 && u <= X1 && v >= Y0 && v <= Y1) return 1;
-    double best = INFINITY;
-    for (int e = 0; e < 4; ++e) {
-        double dx, dy, lo, hi;
-        if (e < 2) {
-            dx = (e == 0 ? X0 : X1) - u;
-            lo = Y0 - v; hi = Y1 - v;
-            dy = -(b * dx) / c;
-            if (dy < lo) dy = lo;
-            else if (dy > hi) dy = hi;
-        } else {
-            dy = (e == 2 ? Y0 : Y1) - v;
-            lo = X0 - u; hi = X1 - u;
-            dx = -(b * dy) / a;
-            if (dx < lo) dx = lo;
-            else if (dx > hi) dx = hi;
-        }
-        double t1 = (a * dx) * dx;
-        double t2 = ((2.0 * b) * dx) * dy;
-        double t3 = (c * dy) * dy;
-        double q = (t1 + t2) + t3;
-        if (q < best) best = q;
-    }
-    return best <= k;
+typedef struct {
+    double u, v, b, det, ia, ka, ry, dys;
+    int full; /* degenerate conic: the whole rectangle */
+} orows;
+
+static void rows_setup(double u, double v, double a, double b, double c, double k, orows *e) {
+    e->u = u; e->v = v; e->b = b;
+    e->det = a * c - b * b;
+    e->full = !(e->det > 0.0) || !(a > 0.0) || !(k > 0.0);
+    double sxx = c / e->det, syy = a / e->det, sxy = -b / e->det;
+    e->ry = sqrt(k * syy);
+    e->dys = sxy * sqrt(k / sxx);
+    e->ia = 1.0 / a;
+    e->ka = k * a;
 }
 
-static void tile_pixel_box(int w, int h, int tile, int tx, int ty, double *X0, double *X1, double *Y0, double *Y1) {
-    int xe = (tx + 1) * tile < w ? (tx + 1) * tile : w;
+/* columns [*lo, *hi] of tile row ty (inside rectangle columns [x0, x1]); 0 when none */
+static int rows_span(const orows *e, int h, int tile, int ty, int x0, int x1, int *lo, int *hi) {
+    if (e->full) { *lo = x0; *hi = x1; return 1; }
     int ye = (ty + 1) * tile < h ? (ty + 1) * tile : h;
-    *X0 = tx * tile + 0.5; *X1 = xe - 0.5;
-    *Y0 = ty * tile + 0.5; *Y1 = ye - 0.5;
+    double dl = (ty * tile + 0.5) - e->v, dh = (ye - 0.5) - e->v;
+    if (dl < -e->ry) dl = -e->ry;
+    if (dh > e->ry) dh = e->ry;
+    if (dl > dh) return 0;
+    double d1 = e->dys, d2 = -e->dys;
+    if (d1 < dl) d1 = dl;
+    if (d1 > dh) d1 = dh;
+    if (d2 < dl) d2 = dl;
+    if (d2 > dh) d2 = dh;
+    double r1 = e->ka - (e->det * d1) * d1;
+    double r2 = e->ka - (e->det * d2) * d2;
+    double s1 = sqrt(r1 > 0.0 ? r1 : 0.0);
+    double s2 = sqrt(r2 > 0.0 ? r2 : 0.0);
+    double xmax = e->u + (s1 - e->b * d1) * e->ia;
+    double xmin = e->u - (s2 + e->b * d2) * e->ia;
+    double flo = ceil((xmin + 0.5) / tile - 1.0), fhi = floor((xmax - 0.5) / tile);
+    if (flo < x0) flo = x0;
+    if (fhi > x1) fhi = x1;
+    if (flo > fhi) return 0;
+    *lo = (int)flo;
+    *hi = (int)fhi;
+    return 1;
 }
 
 /* Project Gaussian i into camera cam (tile edge tile). */
@@ -265,13 +278,12 @@ static void project_one(const oscene *sc, const ocam *cam, int tile, int64_t i, 
     p->rect[2] = (int)y_lo / tile; p->rect[3] = (int)y_hi / tile;
     (void)tiles_x; (void)tiles_y;
     p->ntiles = 0;
-    for (int ty = p->rect[2]; ty <= p->rect[3]; ++ty)
-        for (int tx = p->rect[0]; tx <= p->rect[1]; ++tx) {
-            double X0, X1, Y0, Y1;
-            tile_pixel_box(cam->width, cam->height, tile, tx, ty, &X0, &X1, &Y0, &Y1);
-            p->ntiles += ellipse_reaches_box(p->u, p->v, p->conic[0], p->conic[1], p->conic[2], p->cutoff,
-                                             X0, X1, Y0, Y1);
-        }
+    orows er;
+    rows_setup(p->u, p->v, p->conic[0], p->conic[1], p->conic[2], p->cutoff, &er);
+    for (int ty = p->rect[2]; ty <= p->rect[3]; ++ty) {
+        int lo, hi;
+        if (rows_span(&er, cam->height, tile, ty, p->rect[0], p->rect[1], &lo, &hi)) p->ntiles += hi - lo + 1;
+    }
 }
 
 /*
@@ -365,13 +377,12 @@ int64_t oracle_pairs(int64_t nrec, const double *u, const double *v, const float
         if (!valid[g]) continue;
         int vv = rec_view[g];
         if (!rect_of(u[g], v[g], radius[g], w[vv], h[vv], tile, rect)) continue;
-        for (int ty = rect[2]; ty <= rect[3]; ++ty)
-            for (int tx = rect[0]; tx <= rect[1]; ++tx) {
-                double X0, X1, Y0, Y1;
-                tile_pixel_box(w[vv], h[vv], tile, tx, ty, &X0, &X1, &Y0, &Y1);
-                count += ellipse_reaches_box(u[g], v[g], conic[3 * g], conic[3 * g + 1], conic[3 * g + 2], cutoff[g],
-                                             X0, X1, Y0, Y1);
-            }
+        orows er;
+        rows_setup(u[g], v[g], conic[3 * g], conic[3 * g + 1], conic[3 * g + 2], cutoff[g], &er);
+        for (int ty = rect[2]; ty <= rect[3]; ++ty) {
+            int lo, hi;
+            if (rows_span(&er, h[vv], tile, ty, rect[0], rect[1], &lo, &hi)) count += hi - lo + 1;
+        }
     }
     if (!keys) return count;
     okv *kv = (okv *)malloc(sizeof(okv) * (size_t)(count > 0 ? count : 1));
@@ -381,18 +392,18 @@ int64_t oracle_pairs(int64_t nrec, const double *u, const double *v, const float
         int vv = rec_view[g];
         if (!rect_of(u[g], v[g], radius[g], w[vv], h[vv], tile, rect)) continue;
         int tiles_x = (w[vv] + tile - 1) / tile;
-        for (int ty = rect[2]; ty <= rect[3]; ++ty)
-            for (int tx = rect[0]; tx <= rect[1]; ++tx) {
-                double X0, X1, Y0, Y1;
-                tile_pixel_box(w[vv], h[vv], tile, tx, ty, &X0, &X1, &Y0, &Y1);
-                if (!ellipse_reaches_box(u[g], v[g], conic[3 * g], conic[3 * g + 1], conic[3 * g + 2], cutoff[g],
-                                         X0, X1, Y0, Y1))
-                    continue;
+        orows er;
+        rows_setup(u[g], v[g], conic[3 * g], conic[3 * g + 1], conic[3 * g + 2], cutoff[g], &er);
+        for (int ty = rect[2]; ty <= rect[3]; ++ty) {
+            int lo, hi;
+            if (!rows_span(&er, h[vv], tile, ty, rect[0], rect[1], &lo, &hi)) continue;
+            for (int tx = lo; tx <= hi; ++tx) {
                 uint64_t gt = (uint64_t)(tile_off[vv] + (int64_t)ty * tiles_x + tx);
                 kv[e].key = (gt << 32) | f32_bits(depth[g]);
                 kv[e].val = (uint32_t)g;
                 ++e;
             }
+        }
     }
     qsort(kv, (size_t)count, sizeof(okv), cmp_kv);
     for (int64_t t = 0; t < 2 * total_tiles; ++t) ranges[t] = 0;

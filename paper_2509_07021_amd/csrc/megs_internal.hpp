@@ -79,46 +79,59 @@ __device__ __forceinline__ uint32_t tile_rect(double u, double v, int32_t r, con
     return static_cast<uint32_t>((x1 - x0 + 1) * (y1 - y0 + 1));
 }
 
-// Does the ellipse {p : (p - m)' C (p - m) <= k} (C = [[a, b], [b, c]] positive definite) reach
-// the box [X0, X1] x [Y0, Y1] of a tile's pixel centres? The minimum of the convex quadratic over
-// the box is 0 when the mean lies inside, else it is attained on an edge, where the 1D minimiser
-// along the edge is clamped to the edge's extent. Plain FP64 +, *, / in a fixed order, so any
-// IEEE implementation takes the same decision from the same inputs.
-__device__ __forceinline__ bool tile_reached(double u, double v, double a, double b, double c, double k,
-                                             double X0, double X1, double Y0, double Y1) {
-    if (u >= X0 && u <= X1 && v >= Y0 && v <= Y1) return true;
-    double best = INFINITY;
-    for (int e = 0; e < 4; ++e) {
-        double dx, dy;
-        if (e < 2) {
-            dx = (e == 0 ? X0 : X1) - u;
-            const double lo = Y0 - v, hi = Y1 - v;
-            dy = -(b * dx) / c;
-            dy = dy < lo ? lo : (dy > hi ? hi : dy);
-        } else {
-            dy = (e == 2 ? Y0 : Y1) - v;
-            const double lo = X0 - u, hi = X1 - u;
-            dx = -(b * dy) / a;
-            dx = dx < lo ? lo : (dx > hi ? hi : dx);
-        }
-        const double t1 = (a * dx) * dx;
-        const double t2 = ((2.0 * b) * dx) * dy;
-        const double t3 = (c * dy) * dy;
-        const double q = (t1 + t2) + t3;
-        best = q < best ? q : best;
-    }
-    return best <= k;
+// Tile selection inside a record's rectangle. For each tile row, the listed tiles are those whose
+// pixel-centre columns meet the x-extent of E ∩ band, where E = {p : (p - m)' C (p - m) <= k}
+// (C = [[a, b], [b, c]] the conic) and band = the row's pixel-centre rows [Y0, Y1]. E ∩ band is
+// convex, so a tile's box meets it exactly when their x-ranges overlap. With S = C^-1, the points
+// of E with extreme x lie at dy = +-S_xy sqrt(k / S_xx); the x-extent over the band is reached
+// there, clamped into the band (x_max(dy) is concave, x_min(dy) convex). Plain FP64 +, -, *, /
+// and sqrt in a fixed order, so any IEEE implementation lists the same tiles.
+struct EllipseRows {
+    double u, v, b, det, ia, ka, ry, dys;
+    bool full;  // degenerate conic: list the whole rectangle
+};
+
+__device__ __forceinline__ void ellipse_rows(double u, double v, double a, double b, double c, double k,
+                                             EllipseRows& e) {
+    e.u = u; e.v = v; e.b = b;
+    e.det = a * c - b * b;
+    e.full = !(e.det > 0.0) || !(a > 0.0) || !(k > 0.0);
+    const double sxx = c / e.det, syy = a / e.det, sxy = -b / e.det;
+    e.ry = sqrt(k * syy);
+    e.dys = sxy * sqrt(k / sxx);
+    e.ia = 1.0 / a;
+    e.ka = k * a;
 }
 
-// Pixel-centre box of tile (tx, ty) of view vw.
-__device__ __forceinline__ void tile_box(const ViewInfo& vw, int tile, int tx, int ty, double& X0, double& X1,
-                                         double& Y0, double& Y1) {
-    const int xe = (tx + 1) * tile < vw.width ? (tx + 1) * tile : vw.width;
+// Columns [lo, hi] of tile row ty listed for the record (within the rectangle columns [x0, x1]);
+// returns false when the row lists no tile.
+__device__ __forceinline__ bool row_span(const EllipseRows& e, const ViewInfo& vw, int tile, int ty, int x0, int x1,
+                                         int& lo, int& hi) {
+    if (e.full) { lo = x0; hi = x1; return true; }
     const int ye = (ty + 1) * tile < vw.height ? (ty + 1) * tile : vw.height;
-    X0 = tx * tile + 0.5;
-    X1 = xe - 0.5;
-    Y0 = ty * tile + 0.5;
-    Y1 = ye - 0.5;
+    double dl = (ty * tile + 0.5) - e.v, dh = (ye - 0.5) - e.v;
+    if (dl < -e.ry) dl = -e.ry;
+    if (dh > e.ry) dh = e.ry;
+    if (dl > dh) return false;
+    double d1 = e.dys;
+    if (d1 < dl) d1 = dl;
+    if (d1 > dh) d1 = dh;
+    double d2 = -e.dys;
+    if (d2 < dl) d2 = dl;
+    if (d2 > dh) d2 = dh;
+    const double r1 = e.ka - (e.det * d1) * d1;
+    const double r2 = e.ka - (e.det * d2) * d2;
+    const double s1 = sqrt(r1 > 0.0 ? r1 : 0.0);
+    const double s2 = sqrt(r2 > 0.0 ? r2 : 0.0);
+    const double xmax = e.u + (s1 - e.b * d1) * e.ia;
+    const double xmin = e.u - (s2 + e.b * d2) * e.ia;
+    double flo = ceil((xmin + 0.5) / tile - 1.0), fhi = floor((xmax - 0.5) / tile);
+    if (flo < x0) flo = x0;
+    if (fhi > x1) fhi = x1;
+    if (flo > fhi) return false;
+    lo = (int)flo;
+    hi = (int)fhi;
+    return true;
 }
 
 // View of a global tile id: linear scan of the (few) view tile offsets.

@@ -213,12 +213,12 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
             int x0, x1, y0, y1;
             const float cut = cutoff_of(g.o_eff);
             if (tile_rect(p.u, p.v, p.radius, vw, tile, x0, x1, y0, y1)) {
-                for (int ty = y0; ty <= y1; ++ty)
-                    for (int tx = x0; tx <= x1; ++tx) {
-                        double X0, X1, Y0, Y1;
-                        tile_box(vw, tile, tx, ty, X0, X1, Y0, Y1);
-                        nt += tile_reached(p.u, p.v, p.conic[0], p.conic[1], p.conic[2], cut, X0, X1, Y0, Y1);
-                    }
+                EllipseRows er;
+                ellipse_rows(p.u, p.v, p.conic[0], p.conic[1], p.conic[2], cut, er);
+                for (int ty = y0; ty <= y1; ++ty) {
+                    int lo, hi;
+                    if (row_span(er, vw, tile, ty, x0, x1, lo, hi)) nt += (uint32_t)(hi - lo + 1);
+                }
             }
             rec.mean[r] = make_double2(p.u, p.v);
             rec.conic_o[r] = make_float4(p.conic[0], p.conic[1], p.conic[2], g.o_eff);

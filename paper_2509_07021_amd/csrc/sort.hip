@@ -188,27 +188,30 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_upsweep(const K* __restric
     }
 }
 
-// Single workgroup exclusive scan of the digit-major count table (in place).
-__global__ __launch_bounds__(kScanThreads) void k_radix_scan(uint32_t* counts, int64_t m) {
+// Exclusive scan of one digit's row of the [256][G] count table (one workgroup per digit, in
+// place); the row total goes to totals[digit]. The downsweep adds the digit bases.
+__global__ __launch_bounds__(kScanThreads) void k_radix_scan_rows(uint32_t* counts, int G, uint32_t* totals) {
     __shared__ uint32_t lds[4];
+    uint32_t* row = counts + (int64_t)blockIdx.x * G;
     uint32_t carry = 0;
-    for (int64_t base = 0; base < m; base += kScanTile) {
-        uint32_t v[kScanIpt];
-        uint32_t s = 0;
-        for (int j = 0; j < kScanIpt; ++j) {
-            int64_t i = base + threadIdx.x * kScanIpt + j;
-            v[j] = i < m ? counts[i] : 0u;
-            s += v[j];
+    for (int base = 0; base < G; base += kScanThreads * 4) {
+        uint32_t v[4];
+        uint32_t sum = 0;
+        for (int j = 0; j < 4; ++j) {
+            const int i = base + threadIdx.x * 4 + j;
+            v[j] = i < G ? row[i] : 0u;
+            sum += v[j];
         }
         uint32_t total;
-        uint32_t ex = block_excl_scan256(s, lds, total) + carry;
-        for (int j = 0; j < kScanIpt; ++j) {
-            int64_t i = base + threadIdx.x * kScanIpt + j;
-            if (i < m) counts[i] = ex;
+        uint32_t ex = block_excl_scan256(sum, lds, total) + carry;
+        for (int j = 0; j < 4; ++j) {
+            const int i = base + threadIdx.x * 4 + j;
+            if (i < G) row[i] = ex;
             ex += v[j];
         }
         carry += total;
     }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 template <typename K>
@@ -216,7 +219,8 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_downsweep(const K* __restr
                                                                 const uint32_t* __restrict__ vals_in,
                                                                 K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                                 const uint32_t* d_count, int64_t max_count, int shift,
-                                                                uint32_t mask, const uint32_t* __restrict__ offsets) {
+                                                                uint32_t mask, const uint32_t* __restrict__ offsets,
+                                                                const uint32_t* __restrict__ totals) {
     // Per tile: stable ranks -> local sorted order staged in LDS -> coalesced writes of each
     // digit's run to its global position.
     __shared__ uint32_t run_off[kRsDigits];
@@ -226,7 +230,12 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_downsweep(const K* __restr
     __shared__ K stage_k[kRsTile];
     __shared__ uint32_t stage_v[kRsTile];
     const int w = threadIdx.x / kWave, lane = __lane_id();
-    for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) run_off[d] = offsets[(int64_t)d * gridDim.x + blockIdx.x];
+    {
+        // digit base = exclusive prefix of the digit totals (thread = digit)
+        uint32_t all;
+        const uint32_t digit_base = block_excl_scan256(totals[threadIdx.x], lds4, all);
+        run_off[threadIdx.x] = digit_base + offsets[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
+    }
     const Chunk c = chunk_of(d_count, max_count);
     const uint64_t lt = lanemask_lt();
     for (int64_t t = c.t0; t < c.t1; ++t) {
@@ -291,6 +300,7 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
     int64_t tiles = (max_count + kRsTile - 1) / kRsTile;
     const int G = (int)(tiles < kRsMaxBlocks ? tiles : kRsMaxBlocks);
     uint32_t* counts = static_cast<uint32_t*>(scratch);
+    uint32_t* totals = counts + (int64_t)kRsDigits * G;
     K* src_k = keys; uint32_t* src_v = vals;
     K* dst_k = keys_alt; uint32_t* dst_v = vals_alt;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
@@ -298,9 +308,9 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
         const uint32_t mask = (1u << bits) - 1u;
         hipLaunchKernelGGL(k_radix_upsweep<K>, dim3(G), dim3(kRsThreads), 0, stream, src_k, d_count, max_count, shift,
                            mask, counts);
-        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kScanThreads), 0, stream, counts, (int64_t)kRsDigits * G);
+        hipLaunchKernelGGL(k_radix_scan_rows, dim3(kRsDigits), dim3(kScanThreads), 0, stream, counts, G, totals);
         hipLaunchKernelGGL(k_radix_downsweep<K>, dim3(G), dim3(kRsThreads), 0, stream, src_k, src_v, dst_k, dst_v,
-                           d_count, max_count, shift, mask, counts);
+                           d_count, max_count, shift, mask, counts, totals);
         K* tk = src_k; src_k = dst_k; dst_k = tk;
         uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
         *in_alt = !*in_alt;
@@ -326,21 +336,22 @@ __global__ void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t 
     const float4 co = rec.conic_o[g];
     const double cut = rec.cutoff[g];
     tile_rect(m.x, m.y, rec.radius[g], vw, tile, x0, x1, y0, y1);
+    EllipseRows er;
+    ellipse_rows(m.x, m.y, co.x, co.y, co.z, cut, er);
     const uint64_t depth_bits = __float_as_uint(rec.rgbd[g].w);
     int64_t pos = offsets[k];
     if (pos + (int64_t)nt > capacity) status[1] = 1;
-    for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx) {
-            double X0, X1, Y0, Y1;
-            tile_box(vw, tile, tx, ty, X0, X1, Y0, Y1);
-            if (!tile_reached(m.x, m.y, co.x, co.y, co.z, cut, X0, X1, Y0, Y1)) continue;
+    for (int ty = y0; ty <= y1; ++ty) {
+        int lo, hi;
+        if (!row_span(er, vw, tile, ty, x0, x1, lo, hi)) continue;
+        for (int tx = lo; tx <= hi; ++tx, ++pos) {
             if (pos >= capacity) return;
             const uint64_t gt = (uint64_t)(vw.tile_off + (int64_t)ty * vw.tiles_x + tx);
             if (tile_keys) tile_keys[pos] = (uint32_t)gt;
             if (keys64) keys64[pos] = (gt << 32) | depth_bits;
             vals[pos] = g;
-            ++pos;
         }
+    }
 }
 
 __global__ void k_clamp_count(const uint32_t* total, int64_t capacity, uint32_t* count, int32_t* status) {
@@ -404,7 +415,7 @@ hipError_t launch_scan(const uint32_t* x, const uint32_t* idx, int64_t n, uint32
 size_t radix_scratch_bytes(int64_t max_count) {
     const int64_t tiles = (max_count + kRsTile - 1) / kRsTile;
     const int64_t G = tiles < kRsMaxBlocks ? (tiles > 0 ? tiles : 1) : kRsMaxBlocks;
-    return (size_t)(kRsDigits * G * sizeof(uint32_t));
+    return (size_t)((kRsDigits * G + kRsDigits) * sizeof(uint32_t));
 }
 
 hipError_t launch_radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
