@@ -105,7 +105,8 @@ typedef struct {
     int32_t tile;          /* tile edge in pixels: 8, 16 or 32 */
     int32_t batch;         /* records staged in LDS per batch: 32, 64, 128 or 256 */
     uint32_t flags;        /* MEGS_FLAG_* */
-    int32_t reserved;
+    int32_t waves;         /* wave64s per tile workgroup: 1, 2 or 4 (1 for 8x8 tiles); 0: default
+                              (1 for 8x8 tiles, 4 otherwise) */
     int64_t pair_capacity; /* 0: size the pair table from the counted pairs (one host sync per
                               forward); > 0: fixed capacity, no host sync, overflow reported
                               as MEGS_ERR_CAPACITY by megs_state_status */
@@ -189,11 +190,14 @@ const megs_state *megs_graph_state(const megs_graph *graph);
 void megs_graph_destroy(megs_graph *graph);
 
 /*
- * Autotuner: times forward+backward for tile in {8, 16, 32} x batch in {32, 64, 128, 256} on
- * the given views (1 warm-up and `reps` timed runs each, HIP events on `stream`) and writes the
- * fastest configuration to *best (flags and pair_capacity copied from *base). Images are
- * independent of the choice up to FP32 rounding (the footprint lies inside the listed tiles),
- * so the choice changes speed only. ms_out (nullable) receives 12 timings, tile-major.
+ * Autotuner: times forward+backward for every (tile, waves) in {(8,1), (16,1), (16,2), (16,4),
+ * (32,1), (32,2), (32,4)} x batch in {32, 64, 128, 256} on the given views (1 warm-up and `reps`
+ * timed runs each, HIP events on `stream`) and writes the fastest configuration to *best (flags
+ * and pair_capacity copied from *base). Images are independent of the choice up to FP32 rounding
+ * (the footprint lies inside the listed tiles), so the choice changes speed only. ms_out
+ * (nullable) receives MEGS_AUTOTUNE_CANDIDATES timings in that order, batch fastest-varying. */
+#define MEGS_AUTOTUNE_CANDIDATES 28
+/*
  */
 megs_status megs_autotune(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
                           const megs_config *base, megs_alloc_fn alloc, void *alloc_ctx,

@@ -19,6 +19,8 @@ MEGS_FLAG_STATS = 4
 STAGES = ("project", "depth_sort", "scan", "emit", "pair_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd")
 MEGS_MAX_LOBES = 8
 MEGS_MAX_VIEWS = 64
+AUTOTUNE_COMBOS = ((8, 1), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4))
+AUTOTUNE_BATCHES = (32, 64, 128, 256)
 
 EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", "megs_graph_create",
             "megs_graph_launch", "megs_graph_status", "megs_graph_state", "megs_graph_destroy",
@@ -51,7 +53,7 @@ class MegsCamera(ctypes.Structure):
 
 class MegsConfig(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
+                ("waves", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
 
 
 class MegsState(ctypes.Structure):

@@ -76,6 +76,8 @@ __global__ void k_set_views(ViewInfo* dst, ViewChunk c) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+int waves_of(const megs_config* cfg) { return cfg->waves ? cfg->waves : (cfg->tile == 8 ? 1 : 4); }
+
 // Bump allocator over one caller-provided block.
 struct Carver {
     char* base;
@@ -114,6 +116,9 @@ megs_status check_args(const megs_scene* sc, const megs_camera* cams, int32_t nv
     if (cfg->batch != 32 && cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
         return fail(MEGS_ERR_ARG, "batch = %d not in {32, 64, 128, 256}", cfg->batch);
     if (cfg->pair_capacity < 0 || cfg->pair_capacity >= (1ll << 31)) return fail(MEGS_ERR_ARG, "pair_capacity out of range");
+    if (cfg->waves != 0 && cfg->waves != 1 && cfg->waves != 2 && cfg->waves != 4)
+        return fail(MEGS_ERR_ARG, "waves = %d not in {0, 1, 2, 4}", cfg->waves);
+    if (cfg->tile == 8 && cfg->waves > 1) return fail(MEGS_ERR_ARG, "8x8 tiles take one wave");
     if (cfg->flags & ~(uint32_t)(MEGS_FLAG_ONE_STAGE_SORT | MEGS_FLAG_PERSISTENT | MEGS_FLAG_STATS))
         return fail(MEGS_ERR_ARG, "unknown flags 0x%x", cfg->flags);
     for (int v = 0; v < nv; ++v) {
@@ -351,7 +356,7 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     if (persistent) HIP_TRY(launch_fill_u32(f.queue, 0u, 4, s));
     {
         StageTimer t(MEGS_STAGE_BLEND_FWD, s);
-        HIP_TRY(launch_blend_fwd(a, L.tile, cfg->batch, persistent, s));
+        HIP_TRY(launch_blend_fwd(a, L.tile, waves_of(cfg), cfg->batch, persistent, s));
     }
 
     state->n_records = L.nr;
@@ -400,7 +405,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 1, s));
     {
         StageTimer t(MEGS_STAGE_BLEND_BWD, s);
-        HIP_TRY(launch_blend_bwd(a, L.tile, cfg->batch, persistent, s));
+        HIP_TRY(launch_blend_bwd(a, L.tile, waves_of(cfg), cfg->batch, persistent, s));
     }
     GradDev g;
     g.pos = gr->pos; g.logscale = gr->logscale; g.quat = gr->quat; g.op_logit = gr->op_logit;
@@ -681,17 +686,18 @@ megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int3
     if (!base || !best || !dl_dimages) return fail(MEGS_ERR_ARG, "null base config, best or dL/dimage");
     if (reps < 1) reps = 1;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int tiles[3] = {8, 16, 32};
+    const int combos[7][2] = {{8, 1}, {16, 1}, {16, 2}, {16, 4}, {32, 1}, {32, 2}, {32, 4}};
     const int batches[4] = {32, 64, 128, 256};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f;
     megs_status result = MEGS_OK;
-    for (int ti = 0; ti < 3 && result == MEGS_OK; ++ti)
+    for (int ci = 0; ci < 7 && result == MEGS_OK; ++ci)
         for (int bi = 0; bi < 4 && result == MEGS_OK; ++bi) {
             megs_config c = *base;
-            c.tile = tiles[ti];
+            c.tile = combos[ci][0];
+            c.waves = combos[ci][1];
             c.batch = batches[bi];
             float ms_total = 0.f;
             for (int r = 0; r <= reps && result == MEGS_OK; ++r) {
@@ -710,7 +716,7 @@ megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int3
                 }
             }
             const float ms = ms_total / reps;
-            if (ms_out) ms_out[ti * 4 + bi] = ms;
+            if (ms_out) ms_out[ci * 4 + bi] = ms;
             if (result == MEGS_OK && ms < best_ms) {
                 best_ms = ms;
                 *best = c;

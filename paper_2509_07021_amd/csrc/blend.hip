@@ -5,9 +5,11 @@
 // the 2D Gaussian at the pixel, with the 3DGS conventions (alpha clamped to 0.99, fragments below
 // 1/255 skipped, stop before the transmittance would fall under 1e-4).
 //
-// Mapping to CDNA4: one wave64 workgroup per (view, tile), TILE^2/64 pixels per lane, so a tile
-// needs no workgroup barrier beyond the wave itself and every LDS read of a staged Gaussian is
-// reused by all of a lane's pixels. Gaussians of the tile's list are staged into LDS in batches
+// Mapping to CDNA4: a workgroup of 1, 2 or 4 wave64s per (view, tile), TILE^2 / (64 waves) pixels
+// per lane; every LDS read of a staged Gaussian is reused by all of a lane's pixels, and a wave
+// skips a Gaussian that reaches none of its pixels. More waves per tile shorten the serial walk
+// of long tile lists (the latency of the densest tiles bounds a launch); one wave needs no
+// workgroup barrier at all. Gaussians of the tile's list are staged into LDS in batches
 // (one record per lane per load, gathered through the sorted record indices); their means are
 // made tile-relative in FP64 while staging, so the per-fragment arithmetic works on small FP32
 // offsets. The wave stops as soon as all its pixels have terminated.
@@ -78,47 +80,56 @@ __device__ __forceinline__ TileCtx tile_ctx(const BlendArgs& a, int64_t t, int T
     return c;
 }
 
-// Next work item: blockIdx.x when not persistent, else pulled from the queue counter.
-__device__ __forceinline__ int64_t next_tile(const BlendArgs& a, int64_t prev, bool persistent) {
+// Next work item: blockIdx.x when not persistent, else pulled from the queue counter (thread 0
+// takes the item, the workgroup reads it back through LDS).
+__device__ __forceinline__ int64_t next_tile(const BlendArgs& a, int64_t prev, bool persistent, uint32_t* slot) {
     if (!persistent) return prev < 0 ? (int64_t)blockIdx.x : a.n_tiles;
-    uint32_t t = 0;
-    if (__lane_id() == 0) t = atomicAdd(a.queue, 1u);
-    t = __shfl(t, 0);
-    return (int64_t)t;
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(a.queue, 1u);
+    __syncthreads();
+    return (int64_t)*slot;
 }
 
-template <int TILE, bool STATS, bool IMP>
-__global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int persistent) {
-    constexpr int PPT = TILE * TILE / 64, ROWS = 64 / TILE;
+// Workgroup of WAVES wave64s per tile, PPT = TILE^2 / (64 WAVES) pixels per lane. Pixel j of
+// thread t is (t % TILE, t / TILE + (64 WAVES / TILE) j), so each wave owns whole pixel rows.
+template <int TILE, int WAVES, bool STATS, bool IMP>
+__global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch, int persistent) {
+    constexpr int NT = 64 * WAVES, PPT = TILE * TILE / NT, ROWS = NT / TILE;
+    static_assert(PPT >= 1 && NT % TILE == 0, "tile and wave count mismatch");
     extern __shared__ Staged lds[];
     uint32_t* lds_id = reinterpret_cast<uint32_t*>(lds + batch);  // record ids (importance only)
-    const int lane = threadIdx.x;
-    const int lx = lane % TILE, ly = lane / TILE;
+    __shared__ uint32_t work_slot;
+    const int tid = threadIdx.x, lane = __lane_id();
+    const int lx = tid % TILE, ly = tid / TILE;
     uint32_t n_blended = 0, n_evaluated = 0;
-    for (int64_t t = next_tile(a, -1, persistent); t < a.n_tiles; t = next_tile(a, t, persistent)) {
+    for (int64_t t = next_tile(a, -1, persistent, &work_slot); t < a.n_tiles;
+         t = next_tile(a, t, persistent, &work_slot)) {
         const TileCtx c = tile_ctx(a, t, TILE);
         const uint2 rg = a.ranges[t];
         // T < 0 marks a pixel that has terminated (|T| is its final transmittance) or lies outside
         // the image; this keeps the per-pixel state in float registers.
         float T[PPT], C[PPT][3];
         uint32_t last[PPT];
+        bool mine = false;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             T[j] = (c.x0 + lx < c.width && c.y0 + ly + ROWS * j < c.height) ? 1.0f : -1.0f;
             C[j][0] = C[j][1] = C[j][2] = 0.0f;
             last[j] = 0;
+            mine |= T[j] > 0.0f;
         }
         const float px = lx + 0.5f;
-        bool active = true;
-        for (uint32_t base = rg.x; base < rg.y && active; base += batch) {
+        for (uint32_t base = rg.x; base < rg.y; base += batch) {
+            // the workgroup stops once every pixel of the tile has terminated
+            if (WAVES > 1 ? !__syncthreads_or(mine) : !__any(mine)) break;
             const int cnt = (int)min((uint32_t)batch, rg.y - base);
-            for (int q = lane; q < cnt; q += 64) {
+            for (int q = tid; q < cnt; q += NT) {
                 const uint32_t g = a.vals[base + q];
                 stage(a, g, (double)c.x0, (double)c.y0, &lds[q]);
                 if (IMP) lds_id[q] = g;
             }
             __syncthreads();
-            for (int jj = 0; jj < cnt; ++jj) {
+            for (int jj = 0; jj < cnt && __any(mine); ++jj) {
                 const Staged s = lds[jj];
                 const uint32_t pos = base + jj - rg.x;
                 float alpha[PPT];
@@ -132,9 +143,9 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int pe
                     any_pass |= pass[j];
                     if (STATS) n_evaluated += T[j] > 0.0f;
                 }
-                if (!__any(any_pass)) continue;  // wave-uniform: no pixel of the tile is hit
-                bool live = false;
+                if (!__any(any_pass)) continue;  // wave-uniform: none of this wave's pixels is hit
                 float wsum = 0.0f;
+                mine = false;
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
                     const float Tn = T[j] * (1.0f - alpha[j]);
@@ -147,17 +158,16 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a, int batch, int pe
                     C[j][2] = __fmaf_rn(w, s.p2.w, C[j][2]);
                     T[j] = incl ? Tn : (term ? -T[j] : T[j]);
                     last[j] = incl ? pos + 1 : last[j];
-                    live |= T[j] > 0.0f;
+                    mine |= T[j] > 0.0f;
                     if (STATS) n_blended += incl;
                 }
                 if (IMP) {
-                    // importance score: blending weights of this record summed over the tile's pixels
+                    // importance score: blending weights of this record summed over the wave's pixels
 #pragma unroll
                     for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d);
                     if (lane == 0 && wsum != 0.0f)
                         unsafeAtomicAdd(a.importance + (lds_id[jj] - (int64_t)c.view * a.n), wsum);
                 }
-                if (!__any(live)) { active = false; break; }
             }
             __syncthreads();
         }
@@ -222,15 +232,20 @@ __device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
     v8 = z;
 }
 
-template <int TILE>
-__global__ __launch_bounds__(64) void k_blend_bwd(BlendArgs a, int batch, int persistent) {
-    constexpr int PPT = TILE * TILE / 64, ROWS = 64 / TILE;
+template <int TILE, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch, int persistent) {
+    constexpr int NT = 64 * WAVES, PPT = TILE * TILE / NT, ROWS = NT / TILE;
+    static_assert(PPT >= 1 && NT % TILE == 0, "tile and wave count mismatch");
     extern __shared__ Staged lds[];
     uint32_t* lds_id = reinterpret_cast<uint32_t*>(lds + batch);
-    const int lane = threadIdx.x;
-    const int lx = lane % TILE, ly = lane / TILE;
+    float* lds_part = reinterpret_cast<float*>(lds_id + batch);  // [batch][WAVES][9] (WAVES > 1)
+    __shared__ uint32_t work_slot;
+    __shared__ uint32_t red_slot[WAVES];
+    const int tid = threadIdx.x, lane = __lane_id(), wv = tid / 64;
+    const int lx = tid % TILE, ly = tid / TILE;
     const float px = lx + 0.5f;
-    for (int64_t t = next_tile(a, -1, persistent); t < a.n_tiles; t = next_tile(a, t, persistent)) {
+    for (int64_t t = next_tile(a, -1, persistent, &work_slot); t < a.n_tiles;
+         t = next_tile(a, t, persistent, &work_slot)) {
         const TileCtx c = tile_ctx(a, t, TILE);
         const uint2 rg = a.ranges[t];
         const int64_t plane = (int64_t)c.width * c.height;
@@ -253,113 +268,153 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendArgs a, int batch, int pe
         }
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, d));
+        const uint32_t wave_last = maxlast;
+        if (WAVES > 1) {
+            if (lane == 0) red_slot[wv] = maxlast;
+            __syncthreads();
+            for (int w = 0; w < WAVES; ++w) maxlast = max(maxlast, red_slot[w]);
+            __syncthreads();
+        }
         for (uint32_t end = rg.x + maxlast; end > rg.x;) {
             const uint32_t beg = end - rg.x > (uint32_t)batch ? end - batch : rg.x;
             const int cnt = (int)(end - beg);
-            for (int q = lane; q < cnt; q += 64) {
+            for (int q = tid; q < cnt; q += NT) {
                 const uint32_t g = a.vals[end - 1 - q];
                 stage(a, g, (double)c.x0, (double)c.y0, &lds[q]);
                 lds_id[q] = g;
             }
             __syncthreads();
             for (int jj = 0; jj < cnt; ++jj) {
-                const Staged s = lds[jj];
                 const uint32_t pos = end - 1 - jj - rg.x;
-                float alpha[PPT], G[PPT], dxs[PPT], dys[PPT];
-                bool incl[PPT], clamped[PPT];
                 bool any_incl = false;
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    incl[j] = frag(s, px, ly + ROWS * j + 0.5f, dxs[j], dys[j], G[j], alpha[j], clamped[j]) &
-                              (pos < lst[j]);
-                    any_incl |= incl[j];
-                }
-                if (!__any(any_incl)) continue;  // wave-uniform: no pixel of the tile blended it
                 float acc[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) acc[i] = 0.f;
+                if (pos < wave_last) {  // wave-uniform: positions past every pixel's last are skipped
+                    const Staged s = lds[jj];
+                    float alpha[PPT], G[PPT], dxs[PPT], dys[PPT];
+                    bool incl[PPT], clamped[PPT];
 #pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    const float a = incl[j] ? alpha[j] : 0.0f;
-                    const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - a);
-                    const float w = a * Ti;
-                    const float d0 = s.p2.y - S[j][0], d1 = s.p2.z - S[j][1], d2 = s.p2.w - S[j][2];
-                    acc[6] = __fmaf_rn(w, dl[j][0], acc[6]);
-                    acc[7] = __fmaf_rn(w, dl[j][1], acc[7]);
-                    acc[8] = __fmaf_rn(w, dl[j][2], acc[8]);
-                    const float dal = Ti * __fmaf_rn(d0, dl[j][0], __fmaf_rn(d1, dl[j][1], d2 * dl[j][2]));
-                    S[j][0] = __fmaf_rn(a, d0, S[j][0]);
-                    S[j][1] = __fmaf_rn(a, d1, S[j][1]);
-                    S[j][2] = __fmaf_rn(a, d2, S[j][2]);
-                    T[j] = incl[j] ? Ti : T[j];
-                    const bool live = incl[j] & !clamped[j];
-                    const float dq = live ? a * dal : 0.0f;
-                    const float dx = dxs[j], dy = dys[j];
-                    acc[5] = __fmaf_rn(live ? G[j] : 0.0f, dal, acc[5]);
-                    acc[0] = __fmaf_rn(dq, __fmaf_rn(s.p1.z, dx, s.p1.w * dy), acc[0]);
-                    acc[1] = __fmaf_rn(dq, __fmaf_rn(s.p1.w, dx, s.p2.x * dy), acc[1]);
-                    const float hq = -0.5f * dq;
-                    acc[2] = __fmaf_rn(hq, dx * dx, acc[2]);
-                    acc[3] = __fmaf_rn(-dq, dx * dy, acc[3]);
-                    acc[4] = __fmaf_rn(hq, dy * dy, acc[4]);
+                    for (int j = 0; j < PPT; ++j) {
+                        incl[j] = frag(s, px, ly + ROWS * j + 0.5f, dxs[j], dys[j], G[j], alpha[j], clamped[j]) &
+                                  (pos < lst[j]);
+                        any_incl |= incl[j];
+                    }
+                    any_incl = __any(any_incl);
+                    if (any_incl) {
+#pragma unroll
+                        for (int j = 0; j < PPT; ++j) {
+                            const float al = incl[j] ? alpha[j] : 0.0f;
+                            const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - al);
+                            const float w = al * Ti;
+                            const float d0 = s.p2.y - S[j][0], d1 = s.p2.z - S[j][1], d2 = s.p2.w - S[j][2];
+                            acc[6] = __fmaf_rn(w, dl[j][0], acc[6]);
+                            acc[7] = __fmaf_rn(w, dl[j][1], acc[7]);
+                            acc[8] = __fmaf_rn(w, dl[j][2], acc[8]);
+                            const float dal = Ti * __fmaf_rn(d0, dl[j][0], __fmaf_rn(d1, dl[j][1], d2 * dl[j][2]));
+                            S[j][0] = __fmaf_rn(al, d0, S[j][0]);
+                            S[j][1] = __fmaf_rn(al, d1, S[j][1]);
+                            S[j][2] = __fmaf_rn(al, d2, S[j][2]);
+                            T[j] = incl[j] ? Ti : T[j];
+                            const bool live = incl[j] & !clamped[j];
+                            const float dq = live ? al * dal : 0.0f;
+                            const float dx = dxs[j], dy = dys[j];
+                            acc[5] = __fmaf_rn(live ? G[j] : 0.0f, dal, acc[5]);
+                            acc[0] = __fmaf_rn(dq, __fmaf_rn(s.p1.z, dx, s.p1.w * dy), acc[0]);
+                            acc[1] = __fmaf_rn(dq, __fmaf_rn(s.p1.w, dx, s.p2.x * dy), acc[1]);
+                            const float hq = -0.5f * dq;
+                            acc[2] = __fmaf_rn(hq, dx * dx, acc[2]);
+                            acc[3] = __fmaf_rn(-dq, dx * dy, acc[3]);
+                            acc[4] = __fmaf_rn(hq, dy * dy, acc[4]);
+                        }
+                    }
                 }
-                float tot, tot8;
-                wave_sum9(acc, tot, tot8);
-                float* slot = a.grad2d + 9 * (int64_t)lds_id[jj];
-                if ((lane & 7) == 0) unsafeAtomicAdd(slot + (lane >> 3), tot);
-                if (lane == 1) unsafeAtomicAdd(slot + 8, tot8);
+                if (WAVES == 1) {
+                    if (!any_incl) continue;
+                    float tot, tot8;
+                    wave_sum9(acc, tot, tot8);
+                    float* slot = a.grad2d + 9 * (int64_t)lds_id[jj];
+                    if ((lane & 7) == 0) unsafeAtomicAdd(slot + (lane >> 3), tot);
+                    if (lane == 1) unsafeAtomicAdd(slot + 8, tot8);
+                } else {
+                    // per-wave partial sums to LDS; summed across waves after the batch
+                    float tot = 0.f, tot8 = 0.f;
+                    if (any_incl) wave_sum9(acc, tot, tot8);
+                    float* part = lds_part + ((int64_t)jj * WAVES + wv) * 9;
+                    if ((lane & 7) == 0) part[lane >> 3] = tot;
+                    if (lane == 1) part[8] = tot8;
+                }
             }
             __syncthreads();
+            if (WAVES > 1) {
+                for (int i = tid; i < cnt * 9; i += NT) {
+                    const int jj = i / 9, comp = i - jj * 9;
+                    float sum = 0.f;
+#pragma unroll
+                    for (int w = 0; w < WAVES; ++w) sum += lds_part[((int64_t)jj * WAVES + w) * 9 + comp];
+                    if (sum != 0.f) unsafeAtomicAdd(a.grad2d + 9 * (int64_t)lds_id[jj] + comp, sum);
+                }
+                __syncthreads();
+            }
             end = beg;
         }
     }
 }
 
-constexpr int64_t kPersistentGroups = 256 * 24;  // 24 resident single-wave groups per CU
+constexpr int64_t kPersistentGroups = 256 * 24;  // resident workgroups pulling tiles in persistent mode
 
-template <int TILE>
+template <int TILE, int WAVES>
 hipError_t launch_fwd_t(const BlendArgs& a, int batch, bool persistent, hipStream_t stream) {
     const size_t lds = (size_t)batch * (sizeof(Staged) + (a.importance ? sizeof(uint32_t) : 0));
-    const unsigned grid = (unsigned)(persistent && a.n_tiles > kPersistentGroups ? kPersistentGroups : a.n_tiles);
+    const int64_t groups = persistent ? kPersistentGroups / WAVES : a.n_tiles;
+    const unsigned grid = (unsigned)(groups < a.n_tiles ? groups : a.n_tiles);
+    const dim3 block(64 * WAVES);
     if (a.importance)
-        hipLaunchKernelGGL((k_blend_fwd<TILE, false, true>), dim3(grid), dim3(64), lds, stream, a, batch,
+        hipLaunchKernelGGL((k_blend_fwd<TILE, WAVES, false, true>), dim3(grid), block, lds, stream, a, batch,
                            (int)persistent);
     else if (a.stats)
-        hipLaunchKernelGGL((k_blend_fwd<TILE, true, false>), dim3(grid), dim3(64), lds, stream, a, batch,
+        hipLaunchKernelGGL((k_blend_fwd<TILE, WAVES, true, false>), dim3(grid), block, lds, stream, a, batch,
                            (int)persistent);
     else
-        hipLaunchKernelGGL((k_blend_fwd<TILE, false, false>), dim3(grid), dim3(64), lds, stream, a, batch,
+        hipLaunchKernelGGL((k_blend_fwd<TILE, WAVES, false, false>), dim3(grid), block, lds, stream, a, batch,
                            (int)persistent);
     return hipGetLastError();
 }
 
-template <int TILE>
+template <int TILE, int WAVES>
 hipError_t launch_bwd_t(const BlendArgs& a, int batch, bool persistent, hipStream_t stream) {
-    const size_t lds = (size_t)batch * (sizeof(Staged) + sizeof(uint32_t));
-    const unsigned grid = (unsigned)(persistent && a.n_tiles > kPersistentGroups ? kPersistentGroups : a.n_tiles);
-    hipLaunchKernelGGL(k_blend_bwd<TILE>, dim3(grid), dim3(64), lds, stream, a, batch, (int)persistent);
+    size_t lds = (size_t)batch * (sizeof(Staged) + sizeof(uint32_t));
+    if (WAVES > 1) lds += (size_t)batch * WAVES * 9 * sizeof(float);
+    const int64_t groups = persistent ? kPersistentGroups / WAVES : a.n_tiles;
+    const unsigned grid = (unsigned)(groups < a.n_tiles ? groups : a.n_tiles);
+    hipLaunchKernelGGL((k_blend_bwd<TILE, WAVES>), dim3(grid), dim3(64 * WAVES), lds, stream, a, batch,
+                       (int)persistent);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int batch, bool persistent, hipStream_t stream) {
+hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream) {
     if (a.n_tiles <= 0) return hipSuccess;
-    switch (tile) {
-        case 8: return launch_fwd_t<8>(a, batch, persistent, stream);
-        case 16: return launch_fwd_t<16>(a, batch, persistent, stream);
-        case 32: return launch_fwd_t<32>(a, batch, persistent, stream);
-    }
+    if (tile == 8 && waves == 1) return launch_fwd_t<8, 1>(a, batch, persistent, stream);
+    if (tile == 16 && waves == 1) return launch_fwd_t<16, 1>(a, batch, persistent, stream);
+    if (tile == 16 && waves == 2) return launch_fwd_t<16, 2>(a, batch, persistent, stream);
+    if (tile == 16 && waves == 4) return launch_fwd_t<16, 4>(a, batch, persistent, stream);
+    if (tile == 32 && waves == 1) return launch_fwd_t<32, 1>(a, batch, persistent, stream);
+    if (tile == 32 && waves == 2) return launch_fwd_t<32, 2>(a, batch, persistent, stream);
+    if (tile == 32 && waves == 4) return launch_fwd_t<32, 4>(a, batch, persistent, stream);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int batch, bool persistent, hipStream_t stream) {
+hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream) {
     if (a.n_tiles <= 0) return hipSuccess;
-    switch (tile) {
-        case 8: return launch_bwd_t<8>(a, batch, persistent, stream);
-        case 16: return launch_bwd_t<16>(a, batch, persistent, stream);
-        case 32: return launch_bwd_t<32>(a, batch, persistent, stream);
-    }
+    if (tile == 8 && waves == 1) return launch_bwd_t<8, 1>(a, batch, persistent, stream);
+    if (tile == 16 && waves == 1) return launch_bwd_t<16, 1>(a, batch, persistent, stream);
+    if (tile == 16 && waves == 2) return launch_bwd_t<16, 2>(a, batch, persistent, stream);
+    if (tile == 16 && waves == 4) return launch_bwd_t<16, 4>(a, batch, persistent, stream);
+    if (tile == 32 && waves == 1) return launch_bwd_t<32, 1>(a, batch, persistent, stream);
+    if (tile == 32 && waves == 2) return launch_bwd_t<32, 2>(a, batch, persistent, stream);
+    if (tile == 32 && waves == 4) return launch_bwd_t<32, 4>(a, batch, persistent, stream);
     return hipErrorInvalidValue;
 }
 

@@ -209,8 +209,8 @@ struct BlendArgs {
     float* importance;          // forward: per-Gaussian sum of blending weights (null: not computed)
     int64_t n;                  // Gaussians per view (record r of view v is Gaussian r - v n)
 };
-hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int batch, bool persistent, hipStream_t stream);
-hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int batch, bool persistent, hipStream_t stream);
+hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream);
+hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream);
 
 // pruning steps (prune.hip)
 size_t select_scratch_bytes(int64_t n);

@@ -36,9 +36,10 @@ class Config:
     batch: int = 64
     flags: int = 0
     pair_capacity: int = 0
+    waves: int = 0  # wave64s per tile workgroup (0: library default)
 
     def struct(self) -> L.MegsConfig:
-        return L.MegsConfig(self.tile, self.batch, self.flags, 0, self.pair_capacity)
+        return L.MegsConfig(self.tile, self.batch, self.flags, self.waves, self.pair_capacity)
 
 
 class DeviceScene:
@@ -307,7 +308,8 @@ class Graph:
 
 
 def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps: int = 2, dl_images=None):
-    """Times tile {8, 16, 32} x batch {32, 64, 128, 256}; returns (best Config, 3x4 ms table)."""
+    """Times every (tile, waves) of AUTOTUNE_COMBOS x batch {32, 64, 128, 256}; returns
+    (best Config, ms table [combo][batch])."""
     lib = L.load()
     npix = sum(h * w for h, w in image_sizes(cams))
     images = torch.empty(3 * npix, dtype=torch.float32, device="cuda")
@@ -316,7 +318,7 @@ def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps:
     grads = zero_grads_like(dscene)
     alloc = TorchAllocator()
     best = L.MegsConfig()
-    ms = (ctypes.c_float * 12)()
+    ms = (ctypes.c_float * (len(L.AUTOTUNE_COMBOS) * len(L.AUTOTUNE_BATCHES)))()
     sc = dscene.struct()
     cam_arr = cameras_struct(cams)
     c = base.struct()
@@ -324,8 +326,8 @@ def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps:
     L.check(lib.megs_autotune(ctypes.byref(sc), cam_arr, len(cams), ctypes.byref(c), alloc.fn, None,
                               images.data_ptr(), dl.data_ptr(), ctypes.byref(g), reps, _stream(None),
                               ctypes.byref(best), ms))
-    table = np.array(list(ms), np.float32).reshape(3, 4)
-    return Config(best.tile, best.batch, best.flags, best.pair_capacity), table
+    table = np.array(list(ms), np.float32).reshape(len(L.AUTOTUNE_COMBOS), len(L.AUTOTUNE_BATCHES))
+    return Config(best.tile, best.batch, best.flags, best.pair_capacity, best.waves), table
 
 
 class Profile:

@@ -123,10 +123,11 @@ def test_small_workload_all_stages():
     _run_all_stages(scene, cams, R.Config(16, 64))
 
 
-@pytest.mark.parametrize("tile,batch", [(8, 64), (16, 32), (16, 128), (32, 256)])
-def test_tile_and_batch_variants(tile, batch):
+@pytest.mark.parametrize("tile,batch,waves", [(8, 64, 1), (16, 32, 1), (16, 128, 2), (16, 64, 4), (32, 256, 1),
+                                               (32, 64, 2), (32, 128, 4)])
+def test_tile_batch_and_wave_variants(tile, batch, waves):
     scene, cams = S.make_workload("small_2k_128px")
-    _run_all_stages(scene, cams, R.Config(tile, batch))
+    _run_all_stages(scene, cams, R.Config(tile, batch, waves=waves))
 
 
 def test_one_stage_sort_matches_two_stage():
