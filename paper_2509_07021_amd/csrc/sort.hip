@@ -320,37 +320,71 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
 
 // ------------------------------------------------------------- key emission ----
 
-__global__ void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t n, int tile,
-                       const uint32_t* __restrict__ order, const uint32_t* __restrict__ offsets, int64_t n_records,
-                       uint32_t* __restrict__ tile_keys, uint64_t* __restrict__ keys64, uint32_t* __restrict__ vals,
-                       int64_t capacity, int32_t* status) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_records) return;
-    const uint32_t g = order ? order[k] : (uint32_t)k;
-    const uint32_t nt = rec.ntiles[g];
-    if (nt == 0) return;
-    const int v = (int)(g / n);
-    const ViewInfo& vw = views[v];
-    int x0, x1, y0, y1;
-    const double2 m = rec.mean[g];
-    const float4 co = rec.conic_o[g];
-    const double cut = rec.cutoff[g];
-    tile_rect(m.x, m.y, rec.radius[g], vw, tile, x0, x1, y0, y1);
+// Key emission. Workgroup b handles the 256 records at positions [256 b, 256 b + 256) of the
+// emission order; their pairs occupy one contiguous range of the output (the offsets are an
+// exclusive scan in that order). Each thread walks its record's listed tiles row by row and
+// drops its pairs into an LDS window of the workgroup's range; the window is then written out
+// with coalesced stores, so the scattered per-record runs never reach HBM as scattered writes.
+constexpr int kEmitThreads = 256;
+constexpr int kEmitWindow = 4096;
+
+__global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t n,
+                                                       int tile, const uint32_t* __restrict__ order,
+                                                       const uint32_t* __restrict__ offsets, int64_t n_records,
+                                                       uint32_t* __restrict__ tile_keys, uint64_t* __restrict__ keys64,
+                                                       uint32_t* __restrict__ vals, int64_t capacity, int32_t* status) {
+    __shared__ uint32_t w_tile[kEmitWindow];
+    __shared__ uint32_t w_val[kEmitWindow];
+    __shared__ uint32_t range[2];
+    const int64_t k = (int64_t)blockIdx.x * kEmitThreads + threadIdx.x;
+    const int64_t k_last = min((int64_t)(blockIdx.x + 1) * kEmitThreads, n_records) - 1;
+    const bool has = k < n_records;
+    const uint32_t g = has ? (order ? order[k] : (uint32_t)k) : 0u;
+    const uint32_t nt = has ? rec.ntiles[g] : 0u;
+    const int64_t off = has ? (int64_t)offsets[k] : 0;
+    if (k == k_last) {
+        range[0] = offsets[(int64_t)blockIdx.x * kEmitThreads];
+        range[1] = (uint32_t)(off + nt);
+    }
+    __syncthreads();
+    const int64_t lo = range[0], hi = range[1];
+    if (has && nt && off + (int64_t)nt > capacity) status[1] = 1;
+    // record geometry (only threads with pairs)
+    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
     EllipseRows er;
-    ellipse_rows(m.x, m.y, co.x, co.y, co.z, cut, er);
-    const uint64_t depth_bits = __float_as_uint(rec.rgbd[g].w);
-    int64_t pos = offsets[k];
-    if (pos + (int64_t)nt > capacity) status[1] = 1;
-    for (int ty = y0; ty <= y1; ++ty) {
-        int lo, hi;
-        if (!row_span(er, vw, tile, ty, x0, x1, lo, hi)) continue;
-        for (int tx = lo; tx <= hi; ++tx, ++pos) {
-            if (pos >= capacity) return;
-            const uint64_t gt = (uint64_t)(vw.tile_off + (int64_t)ty * vw.tiles_x + tx);
-            if (tile_keys) tile_keys[pos] = (uint32_t)gt;
-            if (keys64) keys64[pos] = (gt << 32) | depth_bits;
-            vals[pos] = g;
+    const ViewInfo* vw = nullptr;
+    if (nt) {
+        vw = &views[g / n];
+        const double2 m = rec.mean[g];
+        const float4 co = rec.conic_o[g];
+        tile_rect(m.x, m.y, rec.radius[g], *vw, tile, x0, x1, y0, y1);
+        ellipse_rows(m.x, m.y, co.x, co.y, co.z, rec.cutoff[g], er);
+    }
+    for (int64_t w0 = lo; w0 < hi; w0 += kEmitWindow) {
+        const int64_t w1 = w0 + kEmitWindow < hi ? w0 + kEmitWindow : hi;
+        if (nt && off < w1 && off + (int64_t)nt > w0) {
+            int64_t pos = off;
+            for (int ty = y0; ty <= y1 && pos < w1; ++ty) {
+                int cl, ch;
+                if (!row_span(er, *vw, tile, ty, x0, x1, cl, ch)) continue;
+                for (int tx = cl; tx <= ch && pos < w1; ++tx, ++pos) {
+                    if (pos < w0) continue;
+                    w_tile[pos - w0] = (uint32_t)(vw->tile_off + (int64_t)ty * vw->tiles_x + tx);
+                    w_val[pos - w0] = g;
+                }
+            }
         }
+        __syncthreads();
+        const int cnt = (int)(w1 - w0);
+        for (int i = threadIdx.x; i < cnt; i += kEmitThreads) {
+            const int64_t pos = w0 + i;
+            if (pos >= capacity) break;
+            const uint32_t gt = w_tile[i], gv = w_val[i];
+            if (tile_keys) tile_keys[pos] = gt;
+            if (keys64) keys64[pos] = ((uint64_t)gt << 32) | __float_as_uint(rec.rgbd[gv].w);
+            vals[pos] = gv;
+        }
+        __syncthreads();
     }
 }
 
@@ -438,8 +472,9 @@ hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_
                        int32_t* status, hipStream_t stream) {
     (void)nv;
     if (n_records <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_records + 255) / 256)), dim3(256), 0, stream, rec, views, n, tile,
-                       order, offsets, n_records, tile_keys, keys64, vals, capacity, status);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_records + kEmitThreads - 1) / kEmitThreads)), dim3(kEmitThreads), 0,
+                       stream, rec, views, n, tile, order, offsets, n_records, tile_keys, keys64, vals, capacity,
+                       status);
     return hipGetLastError();
 }
 
