@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="pick tile/batch with the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=2, help="views of the workload the oracle renders")
+    ap.add_argument("--no-post", action="store_true", help="skip the post-processing measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -106,6 +107,66 @@ def stage_bytes(stage, n, nv, pairs, npix, ntiles, geom_bytes, k):
     if stage == "project_bwd":
         return n * geom_bytes + nr * 9 * 4 + n * (14 + 8 * k) * 4
     return 0
+
+
+def compact_bytes(scene, out_n, out_lobes):
+    """Algorithmic HBM bytes of the post-processing compaction: the mark pass reads the opacity,
+    mask and sharpness planes and writes a flag and a count per Gaussian; the two scans read and
+    write 4 B per Gaussian each; the write pass reads every input plane once and writes the
+    compacted planes, offsets and index maps."""
+    eg = 4 if scene.dt_geom == "f32" else 2
+    ec = 4 if scene.dt_color == "f32" else 2
+    ea = 4 if scene.dt_amp == "f32" else 2
+    n, k = scene.n, scene.k
+    masks = scene.pmask_logit is not None
+    mark = n * (eg * (1 + masks) + ec * k) + 8 * n
+    scans = 2 * 2 * 4 * n
+    read = n * (eg * (11 + masks) + ec * 3 + k * (ec * (4 + masks) + ea * 3)) + 12 * n
+    write = out_n * (eg * 11 + ec * 3 + 8) + out_lobes * (ec * 4 + ea * 3 + 4) + 4
+    return mark + scans + read + write
+
+
+def post_processing(args, cfg):
+    """Post-processing (Sec. 3.3) of the post-ADMM workload: compaction time, static parameter
+    memory before and after, and forward+backward Mpixel/s of the dense and compacted scenes."""
+    import torch
+    from paper_2509_07021_amd import prune as P
+    from paper_2509_07021_amd import render as R
+    from paper_2509_07021_amd import scenes as S
+    scene, cams = S.make_workload("post_admm_1600k_1080p")
+    ds = R.DeviceScene.from_scene(scene)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        P.compact(ds, 0.01, 1.0)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cds, kept, lsrc = P.compact(ds, 0.01, 1.0)
+    torch.cuda.synchronize()
+    ms_compact = (time.perf_counter() - t0) * 1e3 / reps
+    by = compact_bytes(scene, cds.n, cds.n_lobes)
+    npix = sum(c.width * c.height for c in cams)
+    dl = torch.randn(3 * npix, device="cuda")
+    stream = torch.cuda.current_stream()
+    rates = {}
+    for name, d in (("dense", ds), ("compacted", cds)):
+        ms = timed(lambda: R.backward(d, R.forward(d, cams, cfg), dl), args.steps, args.warmup, stream)
+        rates[name] = {"ms_per_step": round(ms, 4), "Mpixel/s": round(npix / ms / 1e3, 2),
+                       "static_params_mb": round(d.static_bytes() / 1e6, 1)}
+    lobes_per = cds.n_lobes / max(cds.n, 1)
+    log(f"post-processing: {scene.n} -> {cds.n} Gaussians, {cds.n_lobes} lobes ({lobes_per:.3f}/Gaussian), "
+        f"compaction {ms_compact:.3f} ms, dense {rates['dense']['Mpixel/s']} vs compacted "
+        f"{rates['compacted']['Mpixel/s']} Mpixel/s")
+    return {"workload": (f"{scene.n} clustered Gaussians, {scene.k} SG lobes, soft masks, FP32, post-ADMM state "
+                         f"(40% near-zero opacity, 68% of lobes with sharpness < 1); thresholds opacity 0.01, "
+                         f"sharpness 1; 1 view 1920x1080"),
+            "gaussians_in": scene.n, "gaussians_out": cds.n, "lobes_out": cds.n_lobes,
+            "lobes_per_gaussian": round(lobes_per, 4), "colour_floats_per_gaussian": round(3 + 7 * lobes_per, 3),
+            "compact_ms": round(ms_compact, 4),
+            "compact_note": "wall time of the call, including its one host synchronisation",
+            "compact_algorithmic_bytes": by, "compact_GBps": round(by / (ms_compact * 1e-3) / 1e9, 1),
+            "render": rates}
 
 
 def cpu_baseline(scene, cams, tile, n_sample_views, seed=11):
@@ -285,6 +346,10 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
     }
+    if not args.no_post:
+        del ds16
+        torch.cuda.empty_cache()
+        out["post_processing"] = post_processing(args, cfg)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(scene16, cams8, cfg.tile, args.cpu_views)

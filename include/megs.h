@@ -65,9 +65,15 @@ typedef enum { MEGS_F32 = 0, MEGS_F16 = 1, MEGS_BF16 = 2 } megs_dtype;
  * registers, never copied.
  *   pos[3][n], logscale[3][n], quat[4][n] (w, x, y, z), op_logit[n],
  *   pmask_logit[n]      (NULL: no primitive mask, m = 1),
- *   base[3][n], axis[k][3][n], sharp[k][n], amp[k][3][n],
- *   lmask_logit[k][n]   (NULL: no lobe masks, m_k = 1).
- * 0 <= k <= MEGS_MAX_LOBES; 0 <= n; n * n_views < 2^31.
+ *   base[3][n], and the lobes in one of two layouts:
+ *   dense (lobe_off NULL): every Gaussian has k lobes,
+ *     axis[k][3][n], sharp[k][n], amp[k][3][n], lmask_logit[k][n] (NULL: no lobe masks, m_k = 1);
+ *   compressed rows (lobe_off non-NULL; the post-processed form of Sec. 3.3, where Gaussians keep
+ *     different numbers of lobes): Gaussian i owns lobes lobe_off[i] .. lobe_off[i + 1] - 1, at
+ *     most k of them, lobe_off[0] = 0, lobe_off non-decreasing, lobe_off[n] = n_lobes,
+ *     axis[3][n_lobes], sharp[n_lobes], amp[3][n_lobes], lmask_logit[n_lobes] (or NULL).
+ *     A Gaussian whose offsets break these rules is culled and the forward reports MEGS_ERR_ARG.
+ * 0 <= k <= MEGS_MAX_LOBES; 0 <= n; n * n_views < 2^31; 0 <= n_lobes < 2^31.
  */
 typedef struct {
     int64_t n;
@@ -76,9 +82,12 @@ typedef struct {
     int32_t reserved;
     const void *pos, *logscale, *quat, *op_logit, *pmask_logit;
     const void *base, *axis, *sharp, *amp, *lmask_logit;
+    const int32_t *lobe_off; /* [n + 1] device, or NULL for the dense layout */
+    int64_t n_lobes;         /* compressed rows only: total lobes */
 } megs_scene;
 
-/* FP32 gradient planes with the shapes of megs_scene's planes; overwritten by the backward.
+/* FP32 gradient planes with the shapes of megs_scene's planes (compressed-row scenes: lobe planes
+ * of n_lobes elements per row, same offsets); overwritten by the backward.
  * pmask_logit / lmask_logit may be NULL (and must be when the scene has no masks). */
 typedef struct {
     float *pos, *logscale, *quat, *op_logit, *pmask_logit;
@@ -132,7 +141,8 @@ typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
  *   ranges    uint32[T][2]   [start, end) of each tile in vals; (0, 0) when empty
  *   T_final   float[NP]      final transmittance per pixel
  *   last      uint32[NP]     1 + position (within its tile's list) of the last blended fragment
- *   device_status int32[8]   [0] pairs counted, [1] overflow flag, [2..3] reserved,
+ *   device_status int32[8]   [0] pairs counted, [1] overflow flag, [2] malformed lobe offsets
+ *                            (compressed-row scenes), [3] reserved,
  *                            [4..5] uint64 blended fragments, [6..7] uint64 evaluated fragments
  *                            (written only with MEGS_FLAG_STATS)
  */
@@ -168,7 +178,8 @@ megs_status megs_render_backward(const megs_scene *scene, const megs_camera *cam
                                  megs_scene_grad *grads, void *stream);
 
 /* Reads state->device_status (synchronises the stream). Returns MEGS_ERR_CAPACITY when the
- * pair table overflowed; *pairs_needed receives the counted pairs (may be NULL). */
+ * pair table overflowed and MEGS_ERR_ARG when compressed-row lobe offsets were malformed;
+ * *pairs_needed receives the counted pairs (may be NULL). */
 megs_status megs_state_status(const megs_state *state, int64_t *pairs_needed, void *stream);
 
 /*
@@ -197,8 +208,6 @@ void megs_graph_destroy(megs_graph *graph);
  * (the footprint lies inside the listed tiles), so the choice changes speed only. ms_out
  * (nullable) receives MEGS_AUTOTUNE_CANDIDATES timings in that order, batch fastest-varying. */
 #define MEGS_AUTOTUNE_CANDIDATES 28
-/*
- */
 megs_status megs_autotune(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
                           const megs_config *base, megs_alloc_fn alloc, void *alloc_ctx,
                           float *images, const float *dl_dimages, megs_scene_grad *grads,
@@ -267,6 +276,35 @@ megs_status megs_dual_update(int64_t count, float *lam, const float *x, const fl
  * delta = delta_o or delta_s (float[count], grad updated in place). */
 megs_status megs_penalty_grad(int64_t count, float delta, const float *x, const float *x_tilde, const float *lam,
                               float *grad, void *stream);
+
+/*
+ * ---- Post-processing (Sec. 3.3, post-processing procedure; the compensation equation and its
+ * derivation in the Appendix) ----
+ * Keeps the Gaussians whose opacity o = sigmoid(op_logit) * sigmoid(pmask_logit) (the mask factor
+ * is 1 without primitive masks) is >= opacity_min, and of those the lobes whose sharpness is
+ * >= sharp_min. Every dropped lobe of a kept Gaussian adds its average over all directions,
+ * m a (1 - e^{-2s}) / (2s) (a at s = 0; m its lobe mask, 1 without masks), to the base colour.
+ * The masks are folded into the output, which has none: op_logit' = logit(o), amp' = m a.
+ * Decisions and the compensation sum are FP64 on the stored values; each computed value is rounded
+ * to FP32 and then to the plane's storage dtype; position, scale, rotation, axis and sharpness are
+ * copied bit for bit. Kept Gaussians keep their order, kept lobes their order within a Gaussian.
+ *
+ * out->scene is the compacted scene in the compressed-row layout (same storage dtypes and k, no
+ * mask planes); its planes, lobe_off, and the index maps below live in one block from alloc:
+ *   kept      int32[scene.n]        source index of each kept Gaussian (ascending)
+ *   lobe_src  int32[scene.n_lobes]  source element of each kept lobe in the input's sharp plane
+ *                                   (dense input: l * n + i; compressed rows: the lobe index)
+ * The call synchronises the stream once (to learn the output sizes). Thresholds must not be NaN.
+ * Errors: MEGS_ERR_ARG for a bad scene or malformed lobe offsets, MEGS_ERR_ALLOC, MEGS_ERR_HIP.
+ */
+typedef struct {
+    megs_scene scene;
+    int32_t *kept;
+    int32_t *lobe_src;
+} megs_compacted;
+
+megs_status megs_compact(const megs_scene *scene, double opacity_min, double sharp_min, megs_alloc_fn alloc,
+                         void *alloc_ctx, void *stream, megs_compacted *out);
 
 /* Description of the last error on the calling thread ("" when none). */
 const char *megs_last_error(void);

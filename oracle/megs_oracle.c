@@ -44,6 +44,11 @@ typedef struct {
     int32_t pad;
     const double *pos, *logscale, *quat, *op_logit, *pmask_logit;
     const double *base, *axis, *sharp, *amp, *lmask_logit;
+    /* NULL: k lobes per Gaussian, planes axis/amp [k][3][n], sharp/lmask_logit [k][n].
+     * Otherwise the lobes of Gaussian i are lobe_off[i] .. lobe_off[i + 1] - 1 (at most k) of
+     * planes axis/amp [3][n_lobes], sharp/lmask_logit [n_lobes] (compressed rows). */
+    const int32_t *lobe_off;
+    int64_t n_lobes;
 } oscene;
 
 typedef struct {
@@ -92,6 +97,22 @@ typedef struct {
 } oproj;
 
 static double P(const double *plane, int64_t n, int64_t row, int64_t i) { return plane[row * n + i]; }
+
+/* Lobes of Gaussian i: their count (-1 when the compressed-row offsets are malformed) and the
+ * element index of lobe l in a one-row plane (sharp, lobe mask) or of row c of a three-row
+ * plane (axis, amplitude). */
+static int lobe_count(const oscene *sc, int64_t i) {
+    if (!sc->lobe_off) return sc->k;
+    int64_t a = sc->lobe_off[i], b = sc->lobe_off[i + 1];
+    if (a < 0 || b < a || b > sc->n_lobes || b - a > sc->k) return -1;
+    return (int)(b - a);
+}
+static int64_t lobe1(const oscene *sc, int64_t i, int l) {
+    return sc->lobe_off ? sc->lobe_off[i] + l : (int64_t)l * sc->n + i;
+}
+static int64_t lobe3(const oscene *sc, int64_t i, int l, int c) {
+    return sc->lobe_off ? (int64_t)c * sc->n_lobes + sc->lobe_off[i] + l : ((int64_t)l * 3 + c) * sc->n + i;
+}
 
 /*
  * Tile selection inside the rectangle. E = {p : (p - m)' C (p - m) <= k}, C the conic, k the
@@ -154,9 +175,10 @@ static int rows_span(const orows *e, int h, int tile, int ty, int x0, int x1, in
 /* Project Gaussian i into camera cam (tile edge tile). */
 static void project_one(const oscene *sc, const ocam *cam, int tile, int64_t i, oproj *p) {
     int64_t n = sc->n;
-    int k = sc->k;
+    int k = lobe_count(sc, i);
     memset(p, 0, sizeof(*p));
     p->valid = 1;
+    if (k < 0) { p->valid = 0; return; }
     double mu[3] = {P(sc->pos, n, 0, i), P(sc->pos, n, 1, i), P(sc->pos, n, 2, i)};
     for (int j = 0; j < 3; ++j) p->s[j] = exp(P(sc->logscale, n, j, i));
     double q[4];
@@ -246,18 +268,18 @@ static void project_one(const oscene *sc, const ocam *cam, int tile, int64_t i, 
     for (int c = 0; c < 3; ++c) p->rgb[c] = P(sc->base, n, c, i);
     for (int l = 0; l < k; ++l) {
         double ax[3], al = 0;
-        for (int a = 0; a < 3; ++a) { ax[a] = sc->axis[((int64_t)l * 3 + a) * n + i]; al += ax[a] * ax[a]; }
+        for (int a = 0; a < 3; ++a) { ax[a] = sc->axis[lobe3(sc, i, l, a)]; al += ax[a] * ax[a]; }
         al = sqrt(al);
         if (!(al > 0) || !isfinite(al)) { p->valid = 0; return; }
         p->ax_len[l] = al;
         double dot = 0;
         for (int a = 0; a < 3; ++a) { p->muh[l][a] = ax[a] / al; dot += p->muh[l][a] * p->d[a]; }
         p->dot[l] = dot;
-        double lam = sc->sharp[(int64_t)l * n + i];
-        p->mk[l] = sc->lmask_logit ? sigmoid(sc->lmask_logit[(int64_t)l * n + i]) : 1.0;
+        double lam = sc->sharp[lobe1(sc, i, l)];
+        p->mk[l] = sc->lmask_logit ? sigmoid(sc->lmask_logit[lobe1(sc, i, l)]) : 1.0;
         p->ek[l] = exp(lam * (dot - 1.0));
         for (int c = 0; c < 3; ++c)
-            p->rgb[c] += p->mk[l] * sc->amp[((int64_t)l * 3 + c) * n + i] * p->ek[l];
+            p->rgb[c] += p->mk[l] * sc->amp[lobe3(sc, i, l, c)] * p->ek[l];
     }
     for (int c = 0; c < 3; ++c)
         if (!isfinite(p->rgb[c])) { p->valid = 0; return; }
@@ -679,7 +701,6 @@ typedef struct {
 
 void oracle_project_backward(const oscene *sc, const ocam *cam, int32_t tile, const double *grad2d, ograd *gr) {
     int64_t n = sc->n;
-    int k = sc->k;
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         oproj p;
@@ -692,19 +713,20 @@ void oracle_project_backward(const oscene *sc, const ocam *cam, int32_t tile, co
         /* colour */
         double gd[3] = {0, 0, 0};
         for (int c = 0; c < 3; ++c) gr->base[c * n + i] += drgb[c];
+        const int k = lobe_count(sc, i);
         for (int l = 0; l < k; ++l) {
-            double lam = sc->sharp[(int64_t)l * n + i];
+            double lam = sc->sharp[lobe1(sc, i, l)];
             double ip = 0;
-            for (int c = 0; c < 3; ++c) ip += sc->amp[((int64_t)l * 3 + c) * n + i] * drgb[c];
+            for (int c = 0; c < 3; ++c) ip += sc->amp[lobe3(sc, i, l, c)] * drgb[c];
             double wgt = p.mk[l] * p.ek[l];
-            for (int c = 0; c < 3; ++c) gr->amp[((int64_t)l * 3 + c) * n + i] += wgt * drgb[c];
-            gr->sharp[(int64_t)l * n + i] += wgt * (p.dot[l] - 1.0) * ip;
+            for (int c = 0; c < 3; ++c) gr->amp[lobe3(sc, i, l, c)] += wgt * drgb[c];
+            gr->sharp[lobe1(sc, i, l)] += wgt * (p.dot[l] - 1.0) * ip;
             double gmu[3], md = 0;
             for (int a = 0; a < 3; ++a) { gmu[a] = wgt * lam * ip * p.d[a]; md += p.muh[l][a] * gmu[a]; }
             for (int a = 0; a < 3; ++a)
-                gr->axis[((int64_t)l * 3 + a) * n + i] += (gmu[a] - p.muh[l][a] * md) / p.ax_len[l];
+                gr->axis[lobe3(sc, i, l, a)] += (gmu[a] - p.muh[l][a] * md) / p.ax_len[l];
             for (int a = 0; a < 3; ++a) gd[a] += wgt * lam * ip * p.muh[l][a];
-            if (gr->lmask_logit) gr->lmask_logit[(int64_t)l * n + i] += p.mk[l] * (1.0 - p.mk[l]) * p.ek[l] * ip;
+            if (gr->lmask_logit) gr->lmask_logit[lobe1(sc, i, l)] += p.mk[l] * (1.0 - p.mk[l]) * p.ek[l] * ip;
         }
         double gpos[3];
         {

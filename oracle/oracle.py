@@ -30,7 +30,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 class OScene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("pad", ctypes.c_int32)] + \
-               [(p, _dp) for p in PLANES]
+               [(p, _dp) for p in PLANES] + [("lobe_off", ctypes.POINTER(ctypes.c_int32)),
+                                              ("n_lobes", ctypes.c_int64)]
 
 
 class OCam(ctypes.Structure):
@@ -94,12 +95,19 @@ def _c64(a):
 
 
 def make_oscene(planes: dict, k: int):
-    """planes: float64 arrays (exact stored values). Returns (struct, keepalive)."""
+    """planes: float64 arrays (exact stored values), plus int32 "lobe_off" [n + 1] for the
+    compressed-row lobe layout. Returns (struct, keepalive)."""
     keep = {p: _c64(planes.get(p)) for p in PLANES}
     n = keep["op_logit"].shape[0]
     s = OScene(n=n, k=k, pad=0)
     for p in PLANES:
         setattr(s, p, None if keep[p] is None else keep[p].ctypes.data_as(_dp))
+    off = planes.get("lobe_off")
+    if off is not None:
+        off = np.ascontiguousarray(off, dtype=np.int32)
+        keep["lobe_off"] = off
+        s.lobe_off = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        s.n_lobes = int(off[-1])
     return s, keep
 
 
@@ -316,6 +324,8 @@ def fd_gradient(planes: dict, k: int, cams, tile: int, weights, plane: str, flat
     ok = np.ones(len(flat_indices), bool)
     for j, fi in enumerate(flat_indices):
         base = {p: (None if planes.get(p) is None else np.array(planes[p], np.float64, copy=True)) for p in PLANES}
+        if planes.get("lobe_off") is not None:
+            base["lobe_off"] = planes["lobe_off"]
         arr = base[plane].reshape(-1)
         x0 = arr[fi]
         h = rel_h * max(1.0, abs(x0))
@@ -383,3 +393,104 @@ def penalty_grad(grad, delta: float, x, x_t, lam):
     of Alg. 1 (delta_o = delta rho_o, delta_s = delta rho_s)."""
     return np.asarray(grad, np.float64) + delta * (np.asarray(x, np.float64) - np.asarray(x_t, np.float64)
                                                    + np.asarray(lam, np.float64))
+
+
+# ---------------------------------------------------------- post-processing ----
+# Sec. 3.3 (post-processing procedure) and the compensation equation with its derivation in the
+# Appendix.
+
+def sphere_mean_factor(s) -> np.ndarray:
+    """(1 - e^{-2s}) / (2s): the average of e^{s (mu . d - 1)} over all unit directions d
+    (the Appendix's integral, 2 pi (1 - e^{-2s}) / s, over the sphere's area 4 pi); 1 at s = 0."""
+    s = np.asarray(s, np.float64)
+    out = np.ones_like(s)
+    nz = s != 0
+    out[nz] = -np.expm1(-2.0 * s[nz]) / (2.0 * s[nz])
+    return out
+
+
+def _sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-np.asarray(x, np.float64)))
+
+
+def _lobe_table(planes: dict, k: int):
+    """Every lobe of the scene as (owner Gaussian, slot, source element), owner-major and slot
+    order within a Gaussian, for both lobe layouts."""
+    n = len(planes["op_logit"])
+    off = planes.get("lobe_off")
+    if off is None:
+        owner = np.repeat(np.arange(n), k)
+        slot = np.tile(np.arange(k), n)
+        src = slot * n + owner              # element of sharp[k][n] (flattened)
+    else:
+        off = np.asarray(off, np.int64)
+        cnt = np.diff(off)
+        owner = np.repeat(np.arange(n), cnt)
+        slot = np.arange(int(off[-1])) - np.repeat(off[:-1], cnt)
+        src = np.arange(int(off[-1]))
+    return owner, slot, src
+
+
+def _lobe_values(planes: dict, k: int, src):
+    """axis [3][m], sharp [m], amp [3][m], mask [m] of the lobes at source elements src."""
+    n = len(planes["op_logit"])
+    dense = planes.get("lobe_off") is None
+    sh = np.asarray(planes["sharp"], np.float64).reshape(-1)[src]
+    if dense:
+        slot, owner = src // max(n, 1), src % max(n, 1)
+        axis = np.asarray(planes["axis"], np.float64)[slot, :, owner].T
+        amp = np.asarray(planes["amp"], np.float64)[slot, :, owner].T
+    else:
+        axis = np.asarray(planes["axis"], np.float64)[:, src]
+        amp = np.asarray(planes["amp"], np.float64)[:, src]
+    lm = planes.get("lmask_logit")
+    m = np.ones(len(src)) if lm is None else _sigmoid(np.asarray(lm, np.float64).reshape(-1)[src])
+    return axis.reshape(3, -1), sh, amp.reshape(3, -1), m
+
+
+def compact(planes: dict, k: int, opacity_min: float, sharp_min: float) -> dict:
+    """Post-processing of Sec. 3.3 on float64 planes (the exact stored values).
+
+    Gaussians with opacity o = sigmoid(op_logit) sigmoid(pmask_logit) below opacity_min are
+    removed. Of the rest, lobes with sharpness below sharp_min are removed and each adds its
+    compensation m a (1 - e^{-2s}) / (2s) to the base colour (added in slot order); masks are then
+    folded (op_logit' = logit(o), amp' = m a), so the result has none. Returns the compacted planes
+    in the compressed-row layout with "lobe_off", plus "kept" (source Gaussians) and "lobe_src"
+    (source sharpness elements), all float64 except the index arrays."""
+    n = len(planes["op_logit"])
+    op = np.asarray(planes["op_logit"], np.float64)
+    pm = planes.get("pmask_logit")
+    o = _sigmoid(op) * (1.0 if pm is None else _sigmoid(pm))
+    keep = o >= opacity_min
+    kept = np.nonzero(keep)[0]
+
+    owner, slot, src = _lobe_table(planes, k)
+    axis, sh, amp, m = _lobe_values(planes, k, src)
+    of_kept = keep[owner]
+    keep_lobe = of_kept & (sh >= sharp_min)
+    drop_lobe = of_kept & ~(sh >= sharp_min)
+
+    base = np.array(planes["base"], np.float64, copy=True)
+    comp = m * sphere_mean_factor(np.where(drop_lobe, sh, 0.0))
+    for sl in range(max(k, 0)):              # slot order, as the sums are defined
+        sel = drop_lobe & (slot == sl)
+        for c in range(3):
+            np.add.at(base[c], owner[sel], comp[sel] * amp[c, sel])
+
+    if pm is None:
+        op_out = op[kept]
+    else:
+        a, b = op[kept], np.asarray(pm, np.float64)[kept]
+        op_out = -np.logaddexp(np.logaddexp(-a, -b), -a - b)   # logit(sigmoid(a) sigmoid(b))
+
+    lsel = np.nonzero(keep_lobe)[0]          # owner-major, slot order: the output order
+    cnt = np.bincount(owner[lsel], minlength=n)[kept]
+    lobe_off = np.zeros(len(kept) + 1, np.int32)
+    lobe_off[1:] = np.cumsum(cnt)
+    g = lambda name: np.asarray(planes[name], np.float64)
+    return {
+        "pos": g("pos")[:, kept], "logscale": g("logscale")[:, kept], "quat": g("quat")[:, kept],
+        "op_logit": op_out, "pmask_logit": None, "base": base[:, kept],
+        "axis": axis[:, lsel], "sharp": sh[lsel], "amp": amp[:, lsel] * m[lsel], "lmask_logit": None,
+        "lobe_off": lobe_off, "kept": kept.astype(np.int32), "lobe_src": src[lsel].astype(np.int32),
+    }

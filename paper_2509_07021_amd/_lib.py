@@ -26,7 +26,7 @@ EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", 
             "megs_graph_launch", "megs_graph_status", "megs_graph_state", "megs_graph_destroy",
             "megs_autotune", "megs_profile_begin", "megs_profile_end", "megs_last_error", "megs_version",
             "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply", "megs_dual_update",
-            "megs_penalty_grad")
+            "megs_penalty_grad", "megs_compact")
 
 PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
           "base", "axis", "sharp", "amp", "lmask_logit")
@@ -37,7 +37,11 @@ _vp = ctypes.c_void_p
 class MegsScene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("dt_geom", ctypes.c_int32),
                 ("dt_color", ctypes.c_int32), ("dt_amp", ctypes.c_int32), ("reserved", ctypes.c_int32)] + \
-               [(p, _vp) for p in PLANES]
+               [(p, _vp) for p in PLANES] + [("lobe_off", _vp), ("n_lobes", ctypes.c_int64)]
+
+
+class MegsCompacted(ctypes.Structure):
+    _fields_ = [("scene", MegsScene), ("kept", _vp), ("lobe_src", _vp)]
 
 
 class MegsSceneGrad(ctypes.Structure):
@@ -111,12 +115,14 @@ def load():
     L.megs_prox_apply.argtypes = [ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
     L.megs_dual_update.argtypes = [ctypes.c_int64, _vp, _vp, _vp, _vp]
     L.megs_penalty_grad.argtypes = [ctypes.c_int64, ctypes.c_float, _vp, _vp, _vp, _vp, _vp]
+    L.megs_compact.argtypes = [P(MegsScene), ctypes.c_double, ctypes.c_double, ALLOC_FN, _vp, _vp,
+                               P(MegsCompacted)]
     L.megs_profile_begin.argtypes = []
     L.megs_profile_end.argtypes = [P(MegsProfile)]
     for f in ("megs_render_forward", "megs_render_backward", "megs_state_status", "megs_graph_create",
               "megs_graph_launch", "megs_graph_status", "megs_autotune", "megs_profile_begin", "megs_profile_end",
               "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply",
-              "megs_dual_update", "megs_penalty_grad"):
+              "megs_dual_update", "megs_penalty_grad", "megs_compact"):
         getattr(L, f).restype = ctypes.c_int
     L.megs_last_error.restype = ctypes.c_char_p
     L.megs_last_error.argtypes = []

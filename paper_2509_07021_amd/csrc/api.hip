@@ -99,19 +99,38 @@ struct Layout {
 
 bool valid_dtype(int32_t d) { return d == MEGS_F32 || d == MEGS_F16 || d == MEGS_BF16; }
 
-megs_status check_args(const megs_scene* sc, const megs_camera* cams, int32_t nv, const megs_config* cfg) {
-    if (!sc || !cams || !cfg) return fail(MEGS_ERR_ARG, "null scene, camera or config");
+// True when the scene has lobe planes to read (dense with k > 0, or compressed rows with lobes).
+bool has_lobes(const megs_scene* sc) { return sc->k > 0 && (sc->lobe_off ? sc->n_lobes > 0 : true); }
+
+megs_status check_scene(const megs_scene* sc) {
+    if (!sc) return fail(MEGS_ERR_ARG, "null scene");
     if (sc->n < 0) return fail(MEGS_ERR_ARG, "n = %lld < 0", (long long)sc->n);
+    if (sc->n >= (1ll << 31)) return fail(MEGS_ERR_ARG, "n must be < 2^31");
     if (sc->k < 0 || sc->k > MEGS_MAX_LOBES) return fail(MEGS_ERR_ARG, "k = %d outside [0, %d]", sc->k, MEGS_MAX_LOBES);
     if (!valid_dtype(sc->dt_geom) || !valid_dtype(sc->dt_color) || !valid_dtype(sc->dt_amp))
         return fail(MEGS_ERR_ARG, "unknown storage dtype");
-    if (nv < 1 || nv > MEGS_MAX_VIEWS) return fail(MEGS_ERR_ARG, "n_views = %d outside [1, %d]", nv, MEGS_MAX_VIEWS);
-    if (sc->n * (int64_t)nv >= (1ll << 31)) return fail(MEGS_ERR_ARG, "n * n_views must be < 2^31");
+    if (sc->lobe_off) {
+        if (sc->n_lobes < 0 || sc->n_lobes >= (1ll << 31))
+            return fail(MEGS_ERR_ARG, "n_lobes = %lld outside [0, 2^31)", (long long)sc->n_lobes);
+        if (sc->n_lobes > sc->n * (int64_t)sc->k)
+            return fail(MEGS_ERR_ARG, "n_lobes = %lld exceeds n * k", (long long)sc->n_lobes);
+    } else if (sc->n_lobes != 0) {
+        return fail(MEGS_ERR_ARG, "n_lobes must be 0 for the dense lobe layout");
+    }
     if (sc->n > 0) {
         if (!sc->pos || !sc->logscale || !sc->quat || !sc->op_logit || !sc->base)
             return fail(MEGS_ERR_ARG, "null geometry or base plane");
-        if (sc->k > 0 && (!sc->axis || !sc->sharp || !sc->amp)) return fail(MEGS_ERR_ARG, "null lobe plane");
+        if (has_lobes(sc) && (!sc->axis || !sc->sharp || !sc->amp)) return fail(MEGS_ERR_ARG, "null lobe plane");
     }
+    return MEGS_OK;
+}
+
+megs_status check_args(const megs_scene* sc, const megs_camera* cams, int32_t nv, const megs_config* cfg) {
+    if (!sc || !cams || !cfg) return fail(MEGS_ERR_ARG, "null scene, camera or config");
+    megs_status st = check_scene(sc);
+    if (st != MEGS_OK) return st;
+    if (nv < 1 || nv > MEGS_MAX_VIEWS) return fail(MEGS_ERR_ARG, "n_views = %d outside [1, %d]", nv, MEGS_MAX_VIEWS);
+    if (sc->n * (int64_t)nv >= (1ll << 31)) return fail(MEGS_ERR_ARG, "n * n_views must be < 2^31");
     if (cfg->tile != 8 && cfg->tile != 16 && cfg->tile != 32) return fail(MEGS_ERR_ARG, "tile = %d not in {8, 16, 32}", cfg->tile);
     if (cfg->batch != 32 && cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
         return fail(MEGS_ERR_ARG, "batch = %d not in {32, 64, 128, 256}", cfg->batch);
@@ -165,13 +184,18 @@ Layout make_layout(const megs_scene* sc, const megs_camera* cams, int nv, int ti
     return L;
 }
 
-SceneDev scene_dev(const megs_scene* sc) {
+SceneDev scene_dev(const megs_scene* sc, int32_t* status) {
     SceneDev d;
     d.n = sc->n; d.k = sc->k;
     d.dt_geom = sc->dt_geom; d.dt_color = sc->dt_color; d.dt_amp = sc->dt_amp;
     d.pos = sc->pos; d.logscale = sc->logscale; d.quat = sc->quat; d.op_logit = sc->op_logit;
     d.pmask_logit = sc->pmask_logit; d.base = sc->base; d.axis = sc->axis; d.sharp = sc->sharp; d.amp = sc->amp;
     d.lmask_logit = sc->lmask_logit;
+    // a compressed-row scene without lobes reads no lobe plane and takes the dense k = 0 path
+    d.lobe_off = has_lobes(sc) ? sc->lobe_off : nullptr;
+    if (!has_lobes(sc)) d.k = 0;
+    d.n_lobes = sc->n_lobes;
+    d.status = status;
     return d;
 }
 
@@ -284,7 +308,7 @@ megs_status enqueue_front(const megs_scene* sc, const Layout& L, const megs_conf
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(f.status), 0u, 8, s));
     {
         StageTimer t(MEGS_STAGE_PROJECT, s);
-        HIP_TRY(launch_project(scene_dev(sc), f.views, L.nv, L.tile, f.rec, s));
+        HIP_TRY(launch_project(scene_dev(sc, f.status), f.views, L.nv, L.tile, f.rec, s));
     }
     if (one_stage) {
         StageTimer t(MEGS_STAGE_SCAN, s);
@@ -346,7 +370,7 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     BlendArgs a;
     memset(&a, 0, sizeof(a));
     a.views = f.views; a.nv = L.nv; a.n_tiles = L.n_tiles;
-    a.mean = f.rec.mean; a.conic_o = f.rec.conic_o; a.rgbd = f.rec.rgbd;
+    a.mean = f.rec.mean; a.conic_o = f.rec.conic_o; a.rgbd = f.rec.rgbd; a.cutoff = f.rec.cutoff;
     a.vals = sorted_v; a.ranges = f.ranges;
     a.image = images; a.T_final = f.T_final; a.last = f.last;
     a.queue = f.queue;
@@ -394,6 +418,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     a.mean = static_cast<const double2*>(st->mean);
     a.conic_o = static_cast<const float4*>(st->conic_o);
     a.rgbd = static_cast<const float4*>(st->rgbd);
+    a.cutoff = static_cast<const float*>(st->cutoff);
     a.vals = static_cast<const uint32_t*>(st->vals);
     a.ranges = static_cast<const uint2*>(st->ranges);
     a.T_final = const_cast<float*>(static_cast<const float*>(st->T_final));
@@ -413,7 +438,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     g.lmask_logit = gr->lmask_logit;
     {
         StageTimer t(MEGS_STAGE_PROJECT_BWD, s);
-        HIP_TRY(launch_project_bwd(scene_dev(sc), a.views, L.nv, grad2d, g, s));
+        HIP_TRY(launch_project_bwd(scene_dev(sc, nullptr), a.views, L.nv, grad2d, g, s));
     }
     return MEGS_OK;
 }
@@ -423,7 +448,7 @@ megs_status check_grads(const megs_scene* sc, const megs_scene_grad* g) {
     if (sc->n == 0) return MEGS_OK;
     if (!g->pos || !g->logscale || !g->quat || !g->op_logit || !g->base)
         return fail(MEGS_ERR_ARG, "null gradient plane");
-    if (sc->k > 0 && (!g->axis || !g->sharp || !g->amp)) return fail(MEGS_ERR_ARG, "null lobe gradient plane");
+    if (has_lobes(sc) && (!g->axis || !g->sharp || !g->amp)) return fail(MEGS_ERR_ARG, "null lobe gradient plane");
     if ((sc->pmask_logit != nullptr) != (g->pmask_logit != nullptr))
         return fail(MEGS_ERR_ARG, "pmask_logit gradient must be given exactly when the scene has primitive masks");
     if ((sc->lmask_logit != nullptr) != (g->lmask_logit != nullptr))
@@ -449,8 +474,11 @@ megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t 
     int64_t counted = -1;
     if (cap == 0) {
         uint32_t total = 0;
+        int32_t flags[4] = {0, 0, 0, 0};
         HIP_TRY(hipMemcpyAsync(&total, f.counters, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(flags, f.status, sizeof(flags), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (flags[kStatusBadLobes]) return fail(MEGS_ERR_ARG, "malformed lobe_off (compressed-row lobes)");
         counted = total;
         cap = total;
     }
@@ -595,14 +623,98 @@ megs_status megs_penalty_grad(int64_t count, float delta, const float* x, const 
     return MEGS_OK;
 }
 
+megs_status megs_compact(const megs_scene* scene, double opacity_min, double sharp_min, megs_alloc_fn alloc,
+                         void* alloc_ctx, void* stream, megs_compacted* out) {
+    g_err[0] = 0;
+    megs_status st = check_scene(scene);
+    if (st != MEGS_OK) return st;
+    if (!alloc || !out) return fail(MEGS_ERR_ARG, "null allocator or output");
+    if (isnan(opacity_min) || isnan(sharp_min)) return fail(MEGS_ERR_ARG, "NaN threshold");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = scene->n;
+    CompactArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = scene_dev(scene, nullptr);
+    a.in.k = scene->k;  // the compaction keeps k as given
+    a.in.lobe_off = scene->lobe_off;
+    a.opacity_min = opacity_min;
+    a.sharp_min = sharp_min;
+    // working block: keep, count, new_idx, lobe_pos [n], totals [2], status [8], scan scratch
+    const size_t wbytes = 4 * align256(sizeof(uint32_t) * (n ? n : 1)) + 2 * align256(32) +
+                          align256(scan_scratch_bytes(n)) + 256;
+    void* wm = alloc(alloc_ctx, wbytes);
+    if (!wm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", wbytes);
+    Carver w{static_cast<char*>(wm), 0};
+    a.keep = w.take<uint32_t>(n);
+    a.count = w.take<uint32_t>(n);
+    a.new_idx = w.take<uint32_t>(n);
+    a.lobe_pos = w.take<uint32_t>(n);
+    uint32_t* totals = w.take<uint32_t>(8);
+    int32_t* status = w.take<int32_t>(8);
+    void* scan_scratch = w.take<char>((int64_t)scan_scratch_bytes(n));
+    a.in.status = status;
+    HIP_TRY(launch_fill_u32(totals, 0u, 8, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(status), 0u, 8, s));
+    HIP_TRY(launch_compact_mark(a, s));
+    if (n > 0) {
+        HIP_TRY(launch_scan(a.keep, nullptr, n, a.new_idx, totals + 0, scan_scratch, s));
+        HIP_TRY(launch_scan(a.count, nullptr, n, a.lobe_pos, totals + 1, scan_scratch, s));
+    }
+    uint32_t ht[2] = {0, 0};
+    int32_t hs[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(ht, totals, sizeof(ht), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hs[kStatusBadLobes]) return fail(MEGS_ERR_ARG, "malformed lobe_off (compressed-row lobes)");
+    const int64_t no = ht[0], lo = ht[1];
+    a.n_out = no;
+    a.l_out = lo;
+    const size_t eg = scene->dt_geom == MEGS_F32 ? 4 : 2, ec = scene->dt_color == MEGS_F32 ? 4 : 2,
+                 ea = scene->dt_amp == MEGS_F32 ? 4 : 2;
+    const size_t obytes = align256(eg * 3 * no) * 2 + align256(eg * 4 * no) + align256(eg * no) +
+                          align256(ec * 3 * no) + align256(ec * 3 * lo) + align256(ec * lo) + align256(ea * 3 * lo) +
+                          align256(sizeof(int32_t) * (no + 1)) + align256(sizeof(int32_t) * no) +
+                          align256(sizeof(int32_t) * lo) + 256 * 12;
+    void* om = alloc(alloc_ctx, obytes);
+    if (!om) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", obytes);
+    Carver o{static_cast<char*>(om), 0};
+    a.pos = o.take<char>((int64_t)(eg * 3 * no));
+    a.logscale = o.take<char>((int64_t)(eg * 3 * no));
+    a.quat = o.take<char>((int64_t)(eg * 4 * no));
+    a.op_logit = o.take<char>((int64_t)(eg * no));
+    a.base = o.take<char>((int64_t)(ec * 3 * no));
+    a.axis = o.take<char>((int64_t)(ec * 3 * lo));
+    a.sharp = o.take<char>((int64_t)(ec * lo));
+    a.amp = o.take<char>((int64_t)(ea * 3 * lo));
+    a.lobe_off = o.take<int32_t>(no + 1);
+    a.kept = o.take<int32_t>(no);
+    a.lobe_src = o.take<int32_t>(lo);
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.lobe_off + no), (uint32_t)lo, 1, s));
+    HIP_TRY(launch_compact_write(a, s));
+
+    memset(out, 0, sizeof(*out));
+    megs_scene& r = out->scene;
+    r.n = no;
+    r.k = scene->k;
+    r.dt_geom = scene->dt_geom; r.dt_color = scene->dt_color; r.dt_amp = scene->dt_amp;
+    r.pos = a.pos; r.logscale = a.logscale; r.quat = a.quat; r.op_logit = a.op_logit; r.pmask_logit = nullptr;
+    r.base = a.base; r.axis = a.axis; r.sharp = a.sharp; r.amp = a.amp; r.lmask_logit = nullptr;
+    r.lobe_off = a.lobe_off;
+    r.n_lobes = lo;
+    out->kept = a.kept;
+    out->lobe_src = a.lobe_src;
+    return MEGS_OK;
+}
+
 megs_status megs_state_status(const megs_state* state, int64_t* pairs_needed, void* stream) {
     g_err[0] = 0;
     if (!state || !state->device_status) return fail(MEGS_ERR_ARG, "null state");
-    int32_t h[2] = {0, 0};
+    int32_t h[4] = {0, 0, 0, 0};
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(h, state->device_status, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (pairs_needed) *pairs_needed = (int64_t)(uint32_t)h[0];
+    if (h[kStatusBadLobes]) return fail(MEGS_ERR_ARG, "malformed lobe_off (compressed-row lobes)");
     if (h[1]) return fail(MEGS_ERR_CAPACITY, "pair table overflow: %u pairs counted, capacity %lld", (uint32_t)h[0],
                           (long long)state->pair_capacity);
     return MEGS_OK;

@@ -29,6 +29,7 @@ struct Staged {
     float4 p0;  // u_rel, v_rel, o, nb2   (nb2 = -b log2 e)
     float4 p1;  // na2, nc2, a, b        (na2 = -a log2 e / 2, nc2 = -c log2 e / 2)
     float4 p2;  // c, r, g, b
+    float2 yr;  // tile-relative rows [v - ry, v + ry] of the cutoff ellipse (ry = sqrt(k S_yy))
 };
 
 __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0, double y0, Staged* dst) {
@@ -36,10 +37,23 @@ __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0,
     const float4 co = a.conic_o[g];
     const float4 cd = a.rgbd[g];
     Staged s;
-    s.p0 = make_float4((float)(m.x - x0), (float)(m.y - y0), co.w, -co.y * kLog2e);
+    const float vr = (float)(m.y - y0);
+    s.p0 = make_float4((float)(m.x - x0), vr, co.w, -co.y * kLog2e);
     s.p1 = make_float4(-0.5f * co.x * kLog2e, -0.5f * co.z * kLog2e, co.x, co.y);
     s.p2 = make_float4(co.z, cd.x, cd.y, cd.z);
+    // every pixel with alpha >= 1/255 lies in the cutoff ellipse, whose rows span v -/+ sqrt(k S_yy),
+    // S_yy = a / (a c - b^2). The determinant is taken in FP64 (the products of FP32 values are
+    // exact there), so thin ellipses keep their extent; widened by 1e-3 relative and 1e-2 px.
+    const double det = (double)co.x * co.z - (double)co.y * co.y;
+    const float ry = det > 0.0 ? (float)sqrt((double)a.cutoff[g] * co.x / det) * 1.001f + 0.01f : 1e30f;
+    s.yr = make_float2(vr - ry, vr + ry);
     *dst = s;
+}
+
+// Does the row band [r0, r1] (tile-relative pixel rows, centres at +0.5) meet the staged
+// footprint's rows? Wave-uniform when the band is.
+__device__ __forceinline__ bool rows_meet(const Staged& s, int r0, int r1) {
+    return (r0 + 0.5f <= s.yr.y) & (r1 + 0.5f >= s.yr.x);
 }
 
 // Alpha test of one fragment (no branches): pass = (q <= 0 and alpha >= 1/255). The forward and
@@ -94,13 +108,14 @@ __device__ __forceinline__ int64_t next_tile(const BlendArgs& a, int64_t prev, b
 // thread t is (t % TILE, t / TILE + (64 WAVES / TILE) j), so each wave owns whole pixel rows.
 template <int TILE, int WAVES, bool STATS, bool IMP>
 __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch, int persistent) {
-    constexpr int NT = 64 * WAVES, PPT = TILE * TILE / NT, ROWS = NT / TILE;
+    constexpr int NT = 64 * WAVES, PPT = TILE * TILE / NT, ROWS = NT / TILE, WROWS = 64 / TILE;
     static_assert(PPT >= 1 && NT % TILE == 0, "tile and wave count mismatch");
     extern __shared__ Staged lds[];
     uint32_t* lds_id = reinterpret_cast<uint32_t*>(lds + batch);  // record ids (importance only)
     __shared__ uint32_t work_slot;
     const int tid = threadIdx.x, lane = __lane_id();
     const int lx = tid % TILE, ly = tid / TILE;
+    const int wrow0 = (tid / 64) * WROWS;  // first row of this wave in pixel slot 0
     uint32_t n_blended = 0, n_evaluated = 0;
     for (int64_t t = next_tile(a, -1, persistent, &work_slot); t < a.n_tiles;
          t = next_tile(a, t, persistent, &work_slot)) {
@@ -137,6 +152,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch
                 bool any_pass = false;
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
+                    pass[j] = false;
+                    alpha[j] = 0.0f;
+                    // this wave's rows of pixel slot j; skip the slot when the footprint misses them
+                    if (!rows_meet(s, wrow0 + ROWS * j, wrow0 + ROWS * j + WROWS - 1)) continue;
                     float dx, dy, G;
                     bool clamped;
                     pass[j] = frag(s, px, ly + ROWS * j + 0.5f, dx, dy, G, alpha[j], clamped) & (T[j] > 0.0f);
@@ -234,7 +253,7 @@ __device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
 
 template <int TILE, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch, int persistent) {
-    constexpr int NT = 64 * WAVES, PPT = TILE * TILE / NT, ROWS = NT / TILE;
+    constexpr int NT = 64 * WAVES, PPT = TILE * TILE / NT, ROWS = NT / TILE, WROWS = 64 / TILE;
     static_assert(PPT >= 1 && NT % TILE == 0, "tile and wave count mismatch");
     extern __shared__ Staged lds[];
     uint32_t* lds_id = reinterpret_cast<uint32_t*>(lds + batch);
@@ -243,6 +262,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
     __shared__ uint32_t red_slot[WAVES];
     const int tid = threadIdx.x, lane = __lane_id(), wv = tid / 64;
     const int lx = tid % TILE, ly = tid / TILE;
+    const int wrow0 = wv * WROWS;  // first row of this wave in pixel slot 0
     const float px = lx + 0.5f;
     for (int64_t t = next_tile(a, -1, persistent, &work_slot); t < a.n_tiles;
          t = next_tile(a, t, persistent, &work_slot)) {
@@ -296,6 +316,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                     bool incl[PPT], clamped[PPT];
 #pragma unroll
                     for (int j = 0; j < PPT; ++j) {
+                        incl[j] = false;
+                        alpha[j] = 0.0f; G[j] = 0.0f; dxs[j] = 0.0f; dys[j] = 0.0f; clamped[j] = false;
+                        if (!rows_meet(s, wrow0 + ROWS * j, wrow0 + ROWS * j + WROWS - 1)) continue;
                         incl[j] = frag(s, px, ly + ROWS * j + 0.5f, dxs[j], dys[j], G[j], alpha[j], clamped[j]) &
                                   (pos < lst[j]);
                         any_incl |= incl[j];

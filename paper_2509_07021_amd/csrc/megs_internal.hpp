@@ -33,12 +33,20 @@ struct ViewInfo {
     int64_t pix_off;   // first pixel (over all views) of the view
 };
 
+// Words of the per-forward device status block (int32[8]).
+constexpr int kStatusPairs = 0;     // pairs counted
+constexpr int kStatusOverflow = 1;  // pair table overflowed its capacity
+constexpr int kStatusBadLobes = 2;  // some compressed-row lobe offsets were malformed
+
 struct SceneDev {
     int64_t n;
-    int32_t k;
+    int32_t k;  // lobes per Gaussian (dense) or the most any Gaussian has (compressed rows)
     int32_t dt_geom, dt_color, dt_amp;
     const void *pos, *logscale, *quat, *op_logit, *pmask_logit;
     const void *base, *axis, *sharp, *amp, *lmask_logit;
+    const int32_t* lobe_off;  // NULL: dense lobe planes; else compressed-row offsets [n + 1]
+    int64_t n_lobes;
+    int32_t* status;          // device status block, or NULL
 };
 
 struct GradDev {
@@ -62,6 +70,55 @@ __device__ __forceinline__ float load_elem(const void* p, int dt, int64_t idx) {
     if (dt == MEGS_F16) return __half2float(static_cast<const __half*>(p)[idx]);
     uint32_t bits = static_cast<uint32_t>(static_cast<const uint16_t*>(p)[idx]) << 16;
     return __uint_as_float(bits);
+}
+
+// FP32 to the storage dtype, round to nearest even (BF16: the upper half of the FP32 pattern after
+// adding 0x7fff plus the lowest kept bit; NaNs stay NaN).
+__device__ __forceinline__ void store_elem(void* p, int dt, int64_t idx, float v) {
+    if (dt == MEGS_F32) { static_cast<float*>(p)[idx] = v; return; }
+    if (dt == MEGS_F16) { static_cast<__half*>(p)[idx] = __float2half_rn(v); return; }
+    const uint32_t b = __float_as_uint(v);
+    const uint32_t r = isnan(v) ? ((b >> 16) | 0x40u) : ((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+    static_cast<uint16_t*>(p)[idx] = (uint16_t)r;
+}
+
+// Copies one stored element bit for bit.
+__device__ __forceinline__ void copy_elem(void* dst, int64_t di, const void* src, int64_t si, int dt) {
+    if (dt == MEGS_F32)
+        static_cast<uint32_t*>(dst)[di] = static_cast<const uint32_t*>(src)[si];
+    else
+        static_cast<uint16_t*>(dst)[di] = static_cast<const uint16_t*>(src)[si];
+}
+
+// Where the lobes of Gaussian i live. Dense scenes: K lobes, element l n + i of a one-row plane
+// (sharpness, lobe mask) and (3 l + c) n + i of a three-row plane (axis, amplitude). Compressed-row
+// scenes: lobes lobe_off[i] .. lobe_off[i + 1] - 1, elements off + l and c n_lobes + off + l.
+template <bool RAGGED>
+struct LobeRef {
+    int64_t off, n;
+    int cnt;
+    __device__ __forceinline__ int64_t at1(int l) const { return RAGGED ? off + l : (int64_t)l * n + off; }
+    __device__ __forceinline__ int64_t at3(int l, int c) const {
+        return RAGGED ? (int64_t)c * n + off + l : ((int64_t)l * 3 + c) * n + off;
+    }
+};
+
+// Reads the lobe slice of Gaussian i (at most kmax lobes); false, with a flag in the status block,
+// when compressed-row offsets are malformed: decreasing, outside [0, n_lobes], or more than kmax.
+template <bool RAGGED>
+__device__ __forceinline__ bool lobe_ref(const SceneDev& sc, int64_t i, int kmax, LobeRef<RAGGED>& r) {
+    if (!RAGGED) {
+        r.off = i; r.n = sc.n; r.cnt = kmax;
+        return true;
+    }
+    const int64_t a = sc.lobe_off[i], b = sc.lobe_off[i + 1];
+    r.off = a; r.n = sc.n_lobes; r.cnt = (int)(b - a);
+    if (a < 0 || b < a || b > sc.n_lobes || b - a > kmax) {
+        r.off = 0; r.cnt = 0;
+        if (sc.status) sc.status[kStatusBadLobes] = 1;
+        return false;
+    }
+    return true;
 }
 
 // Tile rectangle [x0, x1] x [y0, y1] (inclusive tile indices) of pixel bounds floor(u) -/+ r,
@@ -197,6 +254,7 @@ struct BlendArgs {
     const double2* mean;
     const float4* conic_o;
     const float4* rgbd;
+    const float* cutoff;  // per-record cutoff level of the footprint ellipse
     const uint32_t* vals;
     const uint2* ranges;
     float* image;
@@ -211,6 +269,23 @@ struct BlendArgs {
 };
 hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream);
 hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream);
+
+// post-processing compaction (compact.hip)
+struct CompactArgs {
+    SceneDev in;
+    double opacity_min, sharp_min;
+    uint32_t* keep;      // [n] 1 when Gaussian i is kept
+    uint32_t* count;     // [n] lobes Gaussian i keeps
+    uint32_t* new_idx;   // [n] exclusive scan of keep
+    uint32_t* lobe_pos;  // [n] exclusive scan of count
+    int64_t n_out, l_out;
+    void *pos, *logscale, *quat, *op_logit, *base, *axis, *sharp, *amp;  // compacted planes
+    int32_t* lobe_off;   // [n_out + 1]
+    int32_t* kept;       // [n_out] source Gaussian
+    int32_t* lobe_src;   // [l_out] source lobe element
+};
+hipError_t launch_compact_mark(const CompactArgs& a, hipStream_t stream);
+hipError_t launch_compact_write(const CompactArgs& a, hipStream_t stream);
 
 // pruning steps (prune.hip)
 size_t select_scratch_bytes(int64_t n);

@@ -68,22 +68,28 @@ __device__ __forceinline__ void load_geo(const SceneDev& sc, int64_t i, float po
     g.o_eff = g.o * g.mp;
 }
 
-template <int K>
-__device__ __forceinline__ bool load_lobes(const SceneDev& sc, int64_t i, Lobes<K>& L) {
-    const int64_t n = sc.n;
+// Lobe slots at or past the Gaussian's count get zero mask and amplitude, so they add exactly +0.
+template <int K, bool RAGGED>
+__device__ __forceinline__ bool load_lobes(const SceneDev& sc, const LobeRef<RAGGED>& r, Lobes<K>& L) {
     bool ok = true;
 #pragma unroll
     for (int l = 0; l < K; ++l) {
-        float a0 = load_elem(sc.axis, sc.dt_color, (l * 3 + 0) * n + i);
-        float a1 = load_elem(sc.axis, sc.dt_color, (l * 3 + 1) * n + i);
-        float a2 = load_elem(sc.axis, sc.dt_color, (l * 3 + 2) * n + i);
+        if (RAGGED && l >= r.cnt) {
+            L.ax[l][0] = 1.0f; L.ax[l][1] = 0.0f; L.ax[l][2] = 0.0f;
+            L.lam[l] = 0.0f; L.m[l] = 0.0f;
+            L.amp[l][0] = L.amp[l][1] = L.amp[l][2] = 0.0f;
+            continue;
+        }
+        float a0 = load_elem(sc.axis, sc.dt_color, r.at3(l, 0));
+        float a1 = load_elem(sc.axis, sc.dt_color, r.at3(l, 1));
+        float a2 = load_elem(sc.axis, sc.dt_color, r.at3(l, 2));
         L.ax[l][0] = a0; L.ax[l][1] = a1; L.ax[l][2] = a2;
         float al2 = a0 * a0 + a1 * a1 + a2 * a2;
         ok = ok && (al2 > 0.0f) && isfinite(al2);
-        L.lam[l] = load_elem(sc.sharp, sc.dt_color, l * n + i);
+        L.lam[l] = load_elem(sc.sharp, sc.dt_color, r.at1(l));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) L.amp[l][c] = load_elem(sc.amp, sc.dt_amp, (l * 3 + c) * n + i);
-        L.m[l] = sc.lmask_logit ? sigmoidf(load_elem(sc.lmask_logit, sc.dt_color, l * n + i)) : 1.0f;
+        for (int c = 0; c < 3; ++c) L.amp[l][c] = load_elem(sc.amp, sc.dt_amp, r.at3(l, c));
+        L.m[l] = sc.lmask_logit ? sigmoidf(load_elem(sc.lmask_logit, sc.dt_color, r.at1(l))) : 1.0f;
     }
     return ok;
 }
@@ -190,7 +196,7 @@ __device__ __forceinline__ float cutoff_of(float o_eff) {
     return 2.004f * __logf(255.0f * o_eff) + 1e-4f;
 }
 
-template <int K>
+template <int K, bool RAGGED>
 __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __restrict__ views, int nv, int tile,
                                                  Records rec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -199,7 +205,8 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
     Geo g;
     load_geo(sc, i, pos, g);
     Lobes<K> L;
-    const bool lobes_ok = load_lobes<K>(sc, i, L);
+    LobeRef<RAGGED> lr;
+    const bool lobes_ok = lobe_ref<RAGGED>(sc, i, K, lr) && load_lobes<K, RAGGED>(sc, lr, L);
     for (int v = 0; v < nv; ++v) {
         const ViewInfo& vw = views[v];
         const int64_t r = (int64_t)v * sc.n + i;
@@ -248,7 +255,7 @@ __device__ __forceinline__ void quat_grad(const float q[4], const float gR[9], f
     gq[3] = 2.f * (w * (gR[3] - gR[1]) + x * (gR[2] + gR[6]) + y * (gR[5] + gR[7])) - 4.f * z * (gR[0] + gR[4]);
 }
 
-template <int K>
+template <int K, bool RAGGED>
 __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
                                                      const float* __restrict__ grad2d, GradDev G) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -258,7 +265,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo
     Geo g;
     load_geo(sc, i, pos, g);
     Lobes<K> L;
-    const bool lobes_ok = load_lobes<K>(sc, i, L);
+    LobeRef<RAGGED> lr;
+    const bool lobes_ok = lobe_ref<RAGGED>(sc, i, K, lr) && load_lobes<K, RAGGED>(sc, lr, L);
 
     float gpos[3] = {0.f, 0.f, 0.f}, gS3[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float gop = 0.f, gpm = 0.f, gbase[3] = {0.f, 0.f, 0.f};
@@ -397,63 +405,80 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo
     for (int c = 0; c < 3; ++c) G.base[c * n + i] = gbase[c];
 #pragma unroll
     for (int l = 0; l < K; ++l) {
-        for (int c = 0; c < 3; ++c) G.axis[(l * 3 + c) * n + i] = gax[l][c];
-        G.sharp[l * n + i] = glam[l];
-        for (int c = 0; c < 3; ++c) G.amp[(l * 3 + c) * n + i] = gamp[l][c];
-        if (G.lmask_logit) G.lmask_logit[l * n + i] = glm[l];
+        if (RAGGED && l >= lr.cnt) break;
+        for (int c = 0; c < 3; ++c) G.axis[lr.at3(l, c)] = gax[l][c];
+        G.sharp[lr.at1(l)] = glam[l];
+        for (int c = 0; c < 3; ++c) G.amp[lr.at3(l, c)] = gamp[l][c];
+        if (G.lmask_logit) G.lmask_logit[lr.at1(l)] = glm[l];
     }
 }
 
-template <int K>
+template <int K, bool RAGGED>
 hipError_t dispatch_fwd(const SceneDev& sc, const ViewInfo* views, int nv, int tile, const Records& rec,
                         hipStream_t stream) {
     const int64_t blocks = (sc.n + 255) / 256;
-    hipLaunchKernelGGL(k_project<K>, dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, tile, rec);
+    hipLaunchKernelGGL((k_project<K, RAGGED>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, tile, rec);
     return hipGetLastError();
 }
 
-template <int K>
+template <int K, bool RAGGED>
 hipError_t dispatch_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d, const GradDev& g,
                         hipStream_t stream) {
     const int64_t blocks = (sc.n + 255) / 256;
-    hipLaunchKernelGGL(k_project_bwd<K>, dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, grad2d, g);
+    hipLaunchKernelGGL((k_project_bwd<K, RAGGED>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, grad2d,
+                       g);
     return hipGetLastError();
+}
+
+template <bool RAGGED>
+hipError_t project_k(const SceneDev& sc, const ViewInfo* views, int nv, int tile, const Records& rec,
+                     hipStream_t stream) {
+    switch (sc.k) {
+        case 0: return dispatch_fwd<0, false>(sc, views, nv, tile, rec, stream);
+        case 1: return dispatch_fwd<1, RAGGED>(sc, views, nv, tile, rec, stream);
+        case 2: return dispatch_fwd<2, RAGGED>(sc, views, nv, tile, rec, stream);
+        case 3: return dispatch_fwd<3, RAGGED>(sc, views, nv, tile, rec, stream);
+        case 4: return dispatch_fwd<4, RAGGED>(sc, views, nv, tile, rec, stream);
+        case 5: return dispatch_fwd<5, RAGGED>(sc, views, nv, tile, rec, stream);
+        case 6: return dispatch_fwd<6, RAGGED>(sc, views, nv, tile, rec, stream);
+        case 7: return dispatch_fwd<7, RAGGED>(sc, views, nv, tile, rec, stream);
+        case 8: return dispatch_fwd<8, RAGGED>(sc, views, nv, tile, rec, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <bool RAGGED>
+hipError_t project_bwd_k(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d, const GradDev& g,
+                         hipStream_t stream) {
+    switch (sc.k) {
+        case 0: return dispatch_bwd<0, false>(sc, views, nv, grad2d, g, stream);
+        case 1: return dispatch_bwd<1, RAGGED>(sc, views, nv, grad2d, g, stream);
+        case 2: return dispatch_bwd<2, RAGGED>(sc, views, nv, grad2d, g, stream);
+        case 3: return dispatch_bwd<3, RAGGED>(sc, views, nv, grad2d, g, stream);
+        case 4: return dispatch_bwd<4, RAGGED>(sc, views, nv, grad2d, g, stream);
+        case 5: return dispatch_bwd<5, RAGGED>(sc, views, nv, grad2d, g, stream);
+        case 6: return dispatch_bwd<6, RAGGED>(sc, views, nv, grad2d, g, stream);
+        case 7: return dispatch_bwd<7, RAGGED>(sc, views, nv, grad2d, g, stream);
+        case 8: return dispatch_bwd<8, RAGGED>(sc, views, nv, grad2d, g, stream);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
+// A compressed-row scene with k = 0 has no lobes at all and takes the dense k = 0 kernels.
 hipError_t launch_project(const SceneDev& sc, const ViewInfo* views, int nv, int tile, const Records& rec,
                           hipStream_t stream) {
     if (sc.n == 0) return hipSuccess;
-    switch (sc.k) {
-        case 0: return dispatch_fwd<0>(sc, views, nv, tile, rec, stream);
-        case 1: return dispatch_fwd<1>(sc, views, nv, tile, rec, stream);
-        case 2: return dispatch_fwd<2>(sc, views, nv, tile, rec, stream);
-        case 3: return dispatch_fwd<3>(sc, views, nv, tile, rec, stream);
-        case 4: return dispatch_fwd<4>(sc, views, nv, tile, rec, stream);
-        case 5: return dispatch_fwd<5>(sc, views, nv, tile, rec, stream);
-        case 6: return dispatch_fwd<6>(sc, views, nv, tile, rec, stream);
-        case 7: return dispatch_fwd<7>(sc, views, nv, tile, rec, stream);
-        case 8: return dispatch_fwd<8>(sc, views, nv, tile, rec, stream);
-    }
-    return hipErrorInvalidValue;
+    return sc.lobe_off ? project_k<true>(sc, views, nv, tile, rec, stream)
+                       : project_k<false>(sc, views, nv, tile, rec, stream);
 }
 
 hipError_t launch_project_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d,
                               const GradDev& g, hipStream_t stream) {
     if (sc.n == 0) return hipSuccess;
-    switch (sc.k) {
-        case 0: return dispatch_bwd<0>(sc, views, nv, grad2d, g, stream);
-        case 1: return dispatch_bwd<1>(sc, views, nv, grad2d, g, stream);
-        case 2: return dispatch_bwd<2>(sc, views, nv, grad2d, g, stream);
-        case 3: return dispatch_bwd<3>(sc, views, nv, grad2d, g, stream);
-        case 4: return dispatch_bwd<4>(sc, views, nv, grad2d, g, stream);
-        case 5: return dispatch_bwd<5>(sc, views, nv, grad2d, g, stream);
-        case 6: return dispatch_bwd<6>(sc, views, nv, grad2d, g, stream);
-        case 7: return dispatch_bwd<7>(sc, views, nv, grad2d, g, stream);
-        case 8: return dispatch_bwd<8>(sc, views, nv, grad2d, g, stream);
-    }
-    return hipErrorInvalidValue;
+    return sc.lobe_off ? project_bwd_k<true>(sc, views, nv, grad2d, g, stream)
+                       : project_bwd_k<false>(sc, views, nv, grad2d, g, stream);
 }
 
 }  // namespace megs

@@ -79,3 +79,42 @@ def prox_step(o, lam_o, imp, kappa_o, sharp, lam_s, amp, kappa_s):
     D = lobe_range(sharp, amp, lam_s)
     s_t = prox_apply(sharp, lam_s, select_topk(D, kappa_s).view(sharp.shape))
     return o_t, s_t
+
+
+def compact(dscene: R.DeviceScene, opacity_min: float, sharp_min: float = 1.0):
+    """Post-processing (Sec. 3.3): drops Gaussians with opacity below opacity_min and lobes with
+    sharpness below sharp_min (the paper's lobe threshold is 1), folding each dropped lobe's
+    average over all directions into the base colour and the soft masks into opacity and amplitude.
+
+    Returns (compacted DeviceScene in the compressed-row layout, kept int32 [n'], lobe_src
+    int32 [n_lobes']): the source Gaussian of each kept Gaussian and the source sharpness element
+    of each kept lobe. Synchronises the stream once (the output sizes are data-dependent)."""
+    lib = L.load()
+    alloc = R.TorchAllocator()
+    out = L.MegsCompacted()
+    sc = dscene.struct()
+    L.check(lib.megs_compact(ctypes.byref(sc), float(opacity_min), float(sharp_min), alloc.fn, None, _s(),
+                             ctypes.byref(out)))
+    r = out.scene
+    n, nl = int(r.n), int(r.n_lobes)
+    dg, dc, da = (R._TORCH_DT[d] for d in dscene.dt)
+
+    def view(ptr, shape, dtype):
+        count = 1
+        for s in shape:
+            count *= s
+        if count == 0:
+            return torch.empty(shape, dtype=dtype, device="cuda")
+        return alloc.view(ptr, count, dtype).view(shape)
+
+    planes = {
+        "pos": view(r.pos, (3, n), dg), "logscale": view(r.logscale, (3, n), dg),
+        "quat": view(r.quat, (4, n), dg), "op_logit": view(r.op_logit, (n,), dg), "pmask_logit": None,
+        "base": view(r.base, (3, n), dc), "axis": view(r.axis, (3, nl), dc), "sharp": view(r.sharp, (nl,), dc),
+        "amp": view(r.amp, (3, nl), da), "lmask_logit": None,
+    }
+    lobe_off = alloc.view(r.lobe_off, n + 1, torch.int32)
+    kept = view(out.kept, (n,), torch.int32)
+    lobe_src = view(out.lobe_src, (nl,), torch.int32)
+    ds = R.DeviceScene(planes, int(r.k), *dscene.dt, lobe_off=lobe_off, n_lobes=nl, keepalive=alloc)
+    return ds, kept, lobe_src

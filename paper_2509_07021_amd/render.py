@@ -43,13 +43,22 @@ class Config:
 
 
 class DeviceScene:
-    """Parameter planes on the GPU (contiguous SoA torch tensors) and their storage dtypes."""
+    """Parameter planes on the GPU (contiguous SoA torch tensors) and their storage dtypes.
 
-    def __init__(self, planes: dict, k: int, dt_geom="f32", dt_color="f32", dt_amp="f32"):
+    Dense lobes: axis/amp [k][3][n], sharp/lmask_logit [k][n]. Compressed rows (the post-processed
+    form): lobe_off int32 [n + 1] on the device, Gaussian i owning lobes lobe_off[i] ..
+    lobe_off[i + 1] - 1 (at most k), lobe planes axis/amp [3][n_lobes], sharp/lmask_logit [n_lobes].
+    """
+
+    def __init__(self, planes: dict, k: int, dt_geom="f32", dt_color="f32", dt_amp="f32",
+                 lobe_off: Optional[torch.Tensor] = None, n_lobes: int = 0, keepalive=None):
         self.planes = planes
         self.k = k
         self.n = int(planes["op_logit"].shape[-1])
         self.dt = (dt_geom, dt_color, dt_amp)
+        self.lobe_off = lobe_off
+        self.n_lobes = int(n_lobes) if lobe_off is not None else 0
+        self._keepalive = keepalive
         for p in PLANES:
             t = planes.get(p)
             if t is None:
@@ -57,8 +66,13 @@ class DeviceScene:
             want = _TORCH_DT[_group_dt(p, *self.dt)]
             if t.dtype != want or not t.is_contiguous() or t.device.type != "cuda":
                 raise ValueError(f"plane {p}: expected a contiguous {want} CUDA tensor, got {t.dtype} on {t.device}")
-        if (planes.get("pmask_logit") is None) != (planes.get("lmask_logit") is None) and k > 0:
-            pass  # either mask kind may be used on its own
+        if lobe_off is not None:
+            if lobe_off.dtype != torch.int32 or lobe_off.numel() != self.n + 1 or lobe_off.device.type != "cuda":
+                raise ValueError("lobe_off: expected a CUDA int32 tensor of n + 1 offsets")
+
+    @property
+    def ragged(self) -> bool:
+        return self.lobe_off is not None
 
     @classmethod
     def from_scene(cls, scene, device="cuda") -> "DeviceScene":
@@ -75,7 +89,11 @@ class DeviceScene:
             else:
                 t = torch.from_numpy(np.ascontiguousarray(a))
             planes[p] = t.to(device).contiguous()
-        return cls(planes, scene.k, scene.dt_geom, scene.dt_color, scene.dt_amp)
+        lobe_off = None
+        if getattr(scene, "lobe_off", None) is not None:
+            lobe_off = torch.from_numpy(np.ascontiguousarray(scene.lobe_off, dtype=np.int32)).to(device)
+        return cls(planes, scene.k, scene.dt_geom, scene.dt_color, scene.dt_amp, lobe_off=lobe_off,
+                   n_lobes=scene.n_lobes if lobe_off is not None else 0)
 
     @property
     def has_pmask(self) -> bool:
@@ -93,10 +111,13 @@ class DeviceScene:
         for p in PLANES:
             t = planes.get(p)
             setattr(s, p, None if t is None else t.data_ptr())
+        s.lobe_off = None if self.lobe_off is None else self.lobe_off.data_ptr()
+        s.n_lobes = self.n_lobes
         return s
 
     def static_bytes(self) -> int:
-        return sum(t.numel() * t.element_size() for t in self.planes.values() if t is not None)
+        b = sum(t.numel() * t.element_size() for t in self.planes.values() if t is not None)
+        return b + (0 if self.lobe_off is None else self.lobe_off.numel() * 4)
 
 
 class TorchAllocator:

@@ -43,6 +43,7 @@ PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
 GEOM_PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit")
 COLOR_PLANES = ("base", "axis", "sharp", "lmask_logit")
 AMP_PLANES = ("amp",)
+LOBE_PLANES = ("axis", "sharp", "amp", "lmask_logit")
 
 
 @dataclasses.dataclass
@@ -63,23 +64,48 @@ class Scene:
     dt_geom: str = "f32"
     dt_color: str = "f32"
     dt_amp: str = "f32"
+    # compressed-row lobes: None for the dense [K][...][N] lobe planes; else int32 [N + 1]
+    # offsets, Gaussian i owning lobes lobe_off[i] .. lobe_off[i + 1] - 1 (at most K) of the
+    # planes axis[3][L], sharp[L], amp[3][L], lmask_logit[L] (L = lobe_off[N])
+    lobe_off: Optional[np.ndarray] = None
 
     @property
     def has_masks(self) -> bool:
         return self.pmask_logit is not None
+
+    @property
+    def ragged(self) -> bool:
+        return self.lobe_off is not None
+
+    @property
+    def n_lobes(self) -> int:
+        return int(self.lobe_off[-1]) if self.lobe_off is not None else self.n * self.k
 
     def planes(self) -> dict:
         return {p: getattr(self, p) for p in PLANES}
 
     def subset(self, idx: np.ndarray) -> "Scene":
         """The Gaussians idx (in the given order), same storage dtypes."""
-        idx = np.asarray(idx)
+        idx = np.asarray(idx, dtype=np.int64)
         out = {}
+        lobe_off = None
+        lobe_idx = None
+        if self.ragged:
+            cnt = np.diff(self.lobe_off.astype(np.int64))[idx]
+            lobe_off = np.zeros(len(idx) + 1, np.int32)
+            lobe_off[1:] = np.cumsum(cnt)
+            lobe_idx = (np.repeat(self.lobe_off[:-1].astype(np.int64)[idx] - lobe_off[:-1], cnt) +
+                        np.arange(int(lobe_off[-1])))
         for p in PLANES:
             a = getattr(self, p)
-            out[p] = None if a is None else np.ascontiguousarray(a[..., idx])
+            if a is None:
+                out[p] = None
+            elif self.ragged and p in LOBE_PLANES:
+                out[p] = np.ascontiguousarray(a[..., lobe_idx])
+            else:
+                out[p] = np.ascontiguousarray(a[..., idx])
         return Scene(n=len(idx), k=self.k, dt_geom=self.dt_geom,
-                     dt_color=self.dt_color, dt_amp=self.dt_amp, **out)
+                     dt_color=self.dt_color, dt_amp=self.dt_amp, lobe_off=lobe_off, **out)
 
     def stored(self, dt_geom="f32", dt_color="f32", dt_amp="f32") -> "Scene":
         """The same scene re-stored in reduced precision.
@@ -99,13 +125,17 @@ class Scene:
             a = getattr(self, p)
             out[p] = None if a is None else to_storage(widen(a, _dt_of(self, p)), groups[p])
         return Scene(n=self.n, k=self.k, dt_geom=dt_geom, dt_color=dt_color,
-                     dt_amp=dt_amp, **out)
+                     dt_amp=dt_amp, lobe_off=self.lobe_off, **out)
 
     def widened(self) -> dict:
-        """All planes as float64 holding exactly the stored values."""
-        return {p: (None if getattr(self, p) is None else
-                    widen(getattr(self, p), _dt_of(self, p)).astype(np.float64))
-                for p in PLANES}
+        """All planes as float64 holding exactly the stored values (plus "lobe_off" for
+        compressed-row scenes)."""
+        out = {p: (None if getattr(self, p) is None else
+                   widen(getattr(self, p), _dt_of(self, p)).astype(np.float64))
+               for p in PLANES}
+        if self.ragged:
+            out["lobe_off"] = np.ascontiguousarray(self.lobe_off, dtype=np.int32)
+        return out
 
 
 def _dt_of(scene: Scene, plane: str) -> str:
@@ -256,6 +286,7 @@ class Workload:
     tile: int = 16
     storage: tuple = ("f32", "f32", "f32")
     description: str = ""
+    recipe: str = "plain"   # "post_admm": post_admm() applied to the plain scene
 
 
 WORKLOADS = {
@@ -271,6 +302,12 @@ WORKLOADS = {
     "batched_500k_16views": Workload(
         "batched_500k_16views", 500_000, 4, True, False, 4, "ring16", (0, 0), 16,
         description="500k clustered Gaussians, 4 lobes, 16 views 360p-1080p, FP32"),
+    "post_admm_1600k_1080p": Workload(
+        "post_admm_1600k_1080p", 1_600_000, 3, True, True, 6, "sphere6", (1920, 1080), 16,
+        recipe="post_admm",
+        description="1.6M clustered Gaussians, 3 lobes, soft masks, as left by the memory-constrained "
+                    "optimisation (40% near-zero opacity, 68% of lobes with sharpness < 1); compacted "
+                    "to about 0.96M Gaussians with 0-3 lobes, 1 view 1920x1080, FP32"),
     "fp16_3m_8x1080p": Workload(
         "fp16_3m_8x1080p", 3_000_000, 4, True, False, 5, "ring8", (1920, 1080), 16,
         storage=("f16", "f16", "bf16"),
@@ -320,6 +357,8 @@ def make_workload(name: str, n: Optional[int] = None):
     if n is not None:
         w = dataclasses.replace(w, n=n)
     scene = make_scene(w.n, w.k, w.seed, w.clustered, w.masks)
+    if w.recipe == "post_admm":
+        scene = post_admm(scene, w.seed)
     if w.storage != ("f32", "f32", "f32"):
         scene = scene.stored(*w.storage)
     return scene, make_cameras(w)
@@ -342,6 +381,44 @@ def random_scene(rng: np.random.Generator, n: int, k: int, masks: bool,
     return Scene(n=n, k=k, pos=f32(pos), logscale=f32(logscale), quat=f32(quat),
                  op_logit=f32(op_logit), pmask_logit=f32(pm), base=f32(base),
                  axis=f32(axis), sharp=f32(sharp), amp=f32(amp), lmask_logit=f32(lm))
+
+
+def ragged_scene(rng: np.random.Generator, n: int, kmax: int, masks: bool,
+                 spread: float = 1.0, logscale_mu: float = -2.0) -> Scene:
+    """Small random compressed-row scene: each Gaussian draws 0..kmax lobes (uniform), lobes
+    drawn like random_scene's. Draw order: the dense fields of random_scene with k = 0, then the
+    lobe counts, axis, sharp, amp and (with masks) the lobe mask logits."""
+    sc = random_scene(rng, n, 0, masks, spread, logscale_mu)
+    cnt = rng.integers(0, kmax + 1, size=n)
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    nl = int(off[-1])
+    axis = _normalise(rng.standard_normal((3, nl)), 0)
+    sharp = np.exp(rng.uniform(0.0, math.log(50.0), size=nl))
+    amp = rng.normal(0.0, 0.2, size=(3, nl))
+    lm = rng.normal(0.5, 1.5, size=nl) if masks else None
+    f32 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+    return dataclasses.replace(sc, k=kmax, axis=f32(axis), sharp=f32(sharp), amp=f32(amp), lmask_logit=f32(lm),
+                               lobe_off=off.astype(np.int32))
+
+
+def post_admm(scene: Scene, seed: int, prim_frac: float = 0.4, lobe_frac: float = 0.68) -> Scene:
+    """The state the memory-constrained optimisation leaves behind (Sec. 3.3, post-processing
+    procedure: many Gaussians with near-zero opacity and many lobes with near-zero sharpness),
+    imposed on a dense scene: a prim_frac share of Gaussians gets opacity logits N(-9, 1)
+    (opacity about 1e-4, below any sensible threshold) and a lobe_frac share of lobes gets
+    sharpness U(0, 1) (below the paper's lobe threshold of 1). With K = 3 lobes and the default
+    0.68, the lobes that survive average 0.96 per Gaussian, i.e. 3 + 7 x 0.96 = 9.7 colour floats
+    (the paper's per-Gaussian colour cost after post-processing). Draw order: the Gaussian
+    choice, its logits, the lobe choice, its sharpness."""
+    rng = np.random.Generator(np.random.PCG64(seed + 2000))
+    op = scene.op_logit.astype(np.float32).copy()
+    sharp = scene.sharp.astype(np.float32).copy()
+    pick = rng.random(scene.n) < prim_frac
+    op[pick] = rng.normal(-9.0, 1.0, size=int(pick.sum()))
+    lpick = rng.random(sharp.shape) < lobe_frac
+    sharp[lpick] = rng.uniform(0.0, 1.0, size=int(lpick.sum()))
+    return dataclasses.replace(scene, op_logit=op, sharp=sharp)
 
 
 def axis_nearest(scene: Scene, cam: Camera, count: int) -> np.ndarray:

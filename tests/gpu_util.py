@@ -85,6 +85,9 @@ def grad_close(name, g, ref, rel=GRAD_REL, abs_sum=None):
     (possibly cancelling) total, which is what both forms allow for.
     """
     assert g.shape == ref.shape, (name, g.shape, ref.shape)
+    g, ref = np.ravel(g), np.ravel(ref)
+    if abs_sum is not None:
+        abs_sum = np.ravel(abs_sum)
     if ref.size == 0:
         return 0.0
     scale = np.abs(ref).max()
@@ -104,3 +107,18 @@ def grad_close(name, g, ref, rel=GRAD_REL, abs_sum=None):
     assert not bad.any(), (f"{name}: {bad.sum()} elements over; worst {ratio.max():.2f}x at {i}: "
                            f"got {g[i]:.6e}, oracle {ref[i]:.6e}")
     return l2
+
+
+def scene_from_device(ds: R.DeviceScene) -> S.Scene:
+    """A DeviceScene's planes back on the host as a scenes.Scene (bf16 as uint16 bit patterns)."""
+    def host(t):
+        if t is None:
+            return None
+        t = t.detach().cpu()
+        if t.dtype == torch.bfloat16:
+            return t.view(torch.int16).numpy().view(np.uint16).copy()
+        return t.numpy().copy()
+    planes = {p: host(ds.planes.get(p)) for p in S.PLANES}
+    lobe_off = None if ds.lobe_off is None else ds.lobe_off.cpu().numpy().astype(np.int32)
+    return S.Scene(n=ds.n, k=ds.k, dt_geom=ds.dt[0], dt_color=ds.dt[1], dt_amp=ds.dt[2], lobe_off=lobe_off,
+                   **planes)

@@ -122,3 +122,27 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libmegs.so"))
     with pytest.raises(RuntimeError, match="not built"):
         L.load()
+
+
+def test_compact_and_compressed_rows_reject_bad_arguments():
+    lib = L.load()
+    noop = L.ALLOC_FN(lambda ctx, n: None)
+    out = L.MegsCompacted()
+    sc, cams, cfg = _args()
+    status = lib.megs_compact(ctypes.byref(sc), float("nan"), 1.0, noop, None, None, ctypes.byref(out))
+    assert status == L.MEGS_ERR_ARG and "NaN" in lib.megs_last_error().decode()
+    status = lib.megs_compact(ctypes.byref(sc), 0.01, 1.0, ctypes.cast(None, L.ALLOC_FN), None, None,
+                              ctypes.byref(out))
+    assert status == L.MEGS_ERR_ARG
+    # dense scenes carry no lobe count; compressed rows need 0 <= n_lobes <= n k
+    sc, cams, cfg = _args(n=0, k=3)
+    sc.n_lobes = 5
+    status, msg = _forward(sc, cams, 1, cfg)
+    assert status == L.MEGS_ERR_ARG and "n_lobes" in msg
+    sc.lobe_off = 16
+    sc.n_lobes = 1
+    status, msg = _forward(sc, cams, 1, cfg)
+    assert status == L.MEGS_ERR_ARG and "exceeds" in msg
+    sc.n_lobes = -1
+    status, msg = _forward(sc, cams, 1, cfg)
+    assert status == L.MEGS_ERR_ARG and "n_lobes" in msg

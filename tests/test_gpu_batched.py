@@ -89,7 +89,8 @@ def test_persistent_queue_matches_one_group_per_tile():
         np.testing.assert_array_equal(fa.images.cpu().numpy(), fb.images.cpu().numpy())
         for p in ga:
             if ga[p] is not None:
-                grad_close(f"persistent {p}", gb[p].astype(np.float64), ga[p].astype(np.float64), rel=1e-5)
+                # the two runs differ only in the order of the float atomics
+                grad_close(f"persistent {p}", gb[p].astype(np.float64), ga[p].astype(np.float64))
 
 
 def test_autotuner_picks_a_valid_config_with_the_same_images():
