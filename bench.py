@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="pick tile/batch with the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=2, help="views of the workload the oracle renders")
-    ap.add_argument("--no-post", action="store_true", help="skip the post-processing measurement")
+    ap.add_argument("--no-post", action="store_true",
+                    help="skip the post-processing and colour-model measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -167,6 +168,37 @@ def post_processing(args, cfg):
             "compact_note": "wall time of the call, including its one host synchronisation",
             "compact_algorithmic_bytes": by, "compact_GBps": round(by / (ms_compact * 1e-3) / 1e9, 1),
             "render": rates}
+
+
+def colour_models(args, cfg, scene, cams):
+    """Same renderer, same geometry, two colour models: SG with 3 lobes (24 colour floats per
+    Gaussian, the paper's model before lobe pruning) and degree-3 spherical harmonics (48 floats,
+    3DGS's model). FP32, one view, eager forward+backward; static parameter bytes and Mpixel/s."""
+    import dataclasses
+    import torch
+    from paper_2509_07021_amd import render as R
+    from paper_2509_07021_amd import scenes as S
+    base = dataclasses.replace(scene, pmask_logit=None, lmask_logit=None)
+    sg3 = dataclasses.replace(base, k=3, axis=base.axis[:3].copy(), sharp=base.sharp[:3].copy(),
+                              amp=base.amp[:3].copy())
+    sh3 = S.sh_scene(base, 3, 3)
+    npix = sum(c.width * c.height for c in cams)
+    dl = torch.randn(3 * npix, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, sc in (("sg_3_lobes", sg3), ("sh_degree_3", sh3)):
+        ds = R.DeviceScene.from_scene(sc)
+        ms = timed(lambda: R.backward(ds, R.forward(ds, cams, cfg), dl), args.steps, args.warmup, stream)
+        with R.Profile() as prof:
+            R.backward(ds, R.forward(ds, cams, cfg), dl)
+        out[name] = {"ms_per_step": round(ms, 4), "Mpixel/s": round(npix / ms / 1e3, 2),
+                     "static_params_mb": round(ds.static_bytes() / 1e6, 1),
+                     "project_ms": round(prof.ms["project"], 4), "project_bwd_ms": round(prof.ms["project_bwd"], 4)}
+        del ds
+        torch.cuda.empty_cache()
+    log("colour models: " + ", ".join(f"{k} {v['Mpixel/s']} Mpixel/s {v['static_params_mb']} MB" for k, v in out.items()))
+    out["workload"] = f"{scene.n} clustered Gaussians (no masks), FP32, 1 view 1920x1080, eager forward+backward"
+    return out
 
 
 def cpu_baseline(scene, cams, tile, n_sample_views, seed=11):
@@ -350,6 +382,7 @@ def main():
         del ds16
         torch.cuda.empty_cache()
         out["post_processing"] = post_processing(args, cfg)
+        out["colour_models"] = colour_models(args, cfg, scene, cams1)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(scene16, cams8, cfg.tile, args.cpu_views)

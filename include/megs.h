@@ -84,14 +84,24 @@ typedef struct {
     const void *base, *axis, *sharp, *amp, *lmask_logit;
     const int32_t *lobe_off; /* [n + 1] device, or NULL for the dense layout */
     int64_t n_lobes;         /* compressed rows only: total lobes */
+    /* Spherical-harmonic colour instead of SG (3DGS's colour model, which the paper replaces;
+     * kept for the same-renderer comparison of bytes per Gaussian): when sh is non-NULL the colour
+     * is max(0, sum_m Y_m(d) sh[m] + 1/2) per channel, Y_m the real spherical harmonics of degree
+     * <= sh_degree (0..3) in the 3DGS sign convention, sh[(sh_degree + 1)^2][3][n] in dt_color.
+     * k must then be 0 and lobe_off NULL; base is not read (may be NULL). */
+    const void *sh;
+    int32_t sh_degree;
+    int32_t reserved2;
 } megs_scene;
 
 /* FP32 gradient planes with the shapes of megs_scene's planes (compressed-row scenes: lobe planes
  * of n_lobes elements per row, same offsets); overwritten by the backward.
- * pmask_logit / lmask_logit may be NULL (and must be when the scene has no masks). */
+ * pmask_logit / lmask_logit may be NULL (and must be when the scene has no masks); sh is required
+ * exactly for spherical-harmonic scenes, base for SG scenes. */
 typedef struct {
     float *pos, *logscale, *quat, *op_logit, *pmask_logit;
     float *base, *axis, *sharp, *amp, *lmask_logit;
+    float *sh;
 } megs_scene_grad;
 
 /* One pinhole view (host memory). R row-major world->camera, x_cam = R x + t. */

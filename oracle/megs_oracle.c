@@ -49,6 +49,12 @@ typedef struct {
      * planes axis/amp [3][n_lobes], sharp/lmask_logit [n_lobes] (compressed rows). */
     const int32_t *lobe_off;
     int64_t n_lobes;
+    /* NULL: SG colour. Otherwise the colour is max(0, sum_m Y_m(d) sh[m] + 1/2) per channel with
+     * real spherical harmonics of degree <= sh_degree (3DGS's colour model, the paper's baseline
+     * colour), coefficients sh[(sh_degree + 1)^2][3][n]; the SG planes are then unused. */
+    const double *sh;
+    int32_t sh_degree;
+    int32_t pad2;
 } oscene;
 
 typedef struct {
@@ -93,10 +99,56 @@ typedef struct {
     double campos[3], dvec[3], dlen, d[3];
     double rgb[3];
     double ax_len[8], muh[8][3], mk[8], ek[8], dot[8];
+    double shY[16], shdY[16][3];
+    int shclamp[3];
     int rect[4]; int ntiles;
 } oproj;
 
 static double P(const double *plane, int64_t n, int64_t row, int64_t i) { return plane[row * n + i]; }
+
+/*
+ * Real spherical harmonics of degree <= 3 at a unit direction d = (x, y, z), with their partial
+ * derivatives in x, y, z (the polynomials extended off the sphere; the caller projects the
+ * gradient onto the tangent plane). Orthonormal over the sphere; the sign convention is the one
+ * of the 3DGS rasteriser's colour model (degree 1 ordered -y, z, -x).
+ */
+static void sh_basis(const double d[3], double Y[16], double dY[16][3]) {
+    const double pi = acos(-1.0), x = d[0], y = d[1], z = d[2];
+    const double a0 = 0.5 * sqrt(1.0 / pi), a1 = sqrt(3.0 / (4.0 * pi));
+    const double b = 0.5 * sqrt(15.0 / pi), b6 = 0.25 * sqrt(5.0 / pi), b8 = 0.25 * sqrt(15.0 / pi);
+    const double c9 = 0.25 * sqrt(35.0 / (2.0 * pi)), c10 = 0.5 * sqrt(105.0 / pi);
+    const double c11 = 0.25 * sqrt(21.0 / (2.0 * pi)), c12 = 0.25 * sqrt(7.0 / pi), c14 = 0.25 * sqrt(105.0 / pi);
+    const double xx = x * x, yy = y * y, zz = z * z;
+    memset(dY, 0, 16 * 3 * sizeof(double));
+    Y[0] = a0;
+    Y[1] = -a1 * y;  dY[1][1] = -a1;
+    Y[2] = a1 * z;   dY[2][2] = a1;
+    Y[3] = -a1 * x;  dY[3][0] = -a1;
+    Y[4] = b * x * y;               dY[4][0] = b * y;  dY[4][1] = b * x;
+    Y[5] = -b * y * z;              dY[5][1] = -b * z; dY[5][2] = -b * y;
+    Y[6] = b6 * (2 * zz - xx - yy); dY[6][0] = -2 * b6 * x; dY[6][1] = -2 * b6 * y; dY[6][2] = 4 * b6 * z;
+    Y[7] = -b * x * z;              dY[7][0] = -b * z; dY[7][2] = -b * x;
+    Y[8] = b8 * (xx - yy);          dY[8][0] = 2 * b8 * x; dY[8][1] = -2 * b8 * y;
+    Y[9] = -c9 * y * (3 * xx - yy);
+    dY[9][0] = -6 * c9 * x * y; dY[9][1] = -c9 * (3 * xx - 3 * yy);
+    Y[10] = c10 * x * y * z;
+    dY[10][0] = c10 * y * z; dY[10][1] = c10 * x * z; dY[10][2] = c10 * x * y;
+    Y[11] = -c11 * y * (4 * zz - xx - yy);
+    dY[11][0] = 2 * c11 * x * y; dY[11][1] = -c11 * (4 * zz - xx - 3 * yy); dY[11][2] = -8 * c11 * y * z;
+    Y[12] = c12 * z * (2 * zz - 3 * xx - 3 * yy);
+    dY[12][0] = -6 * c12 * x * z; dY[12][1] = -6 * c12 * y * z; dY[12][2] = c12 * (6 * zz - 3 * xx - 3 * yy);
+    Y[13] = -c11 * x * (4 * zz - xx - yy);
+    dY[13][0] = -c11 * (4 * zz - 3 * xx - yy); dY[13][1] = 2 * c11 * x * y; dY[13][2] = -8 * c11 * x * z;
+    Y[14] = c14 * z * (xx - yy);
+    dY[14][0] = 2 * c14 * x * z; dY[14][1] = -2 * c14 * y * z; dY[14][2] = c14 * (xx - yy);
+    Y[15] = -c9 * x * (xx - 3 * yy);
+    dY[15][0] = -c9 * (3 * xx - 3 * yy); dY[15][1] = 6 * c9 * x * y;
+}
+
+/* The basis and its derivatives at ndir unit directions: Y[ndir][16], dY[ndir][16][3]. */
+void oracle_sh_basis(int64_t ndir, const double *dirs, double *Y, double *dY) {
+    for (int64_t i = 0; i < ndir; ++i) sh_basis(dirs + 3 * i, Y + 16 * i, (double (*)[3])(dY + 48 * i));
+}
 
 /* Lobes of Gaussian i: their count (-1 when the compressed-row offsets are malformed) and the
  * element index of lobe l in a one-row plane (sharp, lobe mask) or of row c of a three-row
@@ -265,7 +317,19 @@ static void project_one(const oscene *sc, const ocam *cam, int tile, int64_t i, 
     for (int a = 0; a < 3; ++a) { p->dvec[a] = mu[a] - p->campos[a]; dd += p->dvec[a] * p->dvec[a]; }
     p->dlen = sqrt(dd);
     for (int a = 0; a < 3; ++a) p->d[a] = p->dvec[a] / p->dlen;
-    for (int c = 0; c < 3; ++c) p->rgb[c] = P(sc->base, n, c, i);
+    if (sc->sh) {
+        const int nm = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+        sh_basis(p->d, p->shY, p->shdY);
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.5;
+            for (int m = 0; m < nm; ++m) acc += p->shY[m] * sc->sh[((int64_t)m * 3 + c) * n + i];
+            p->shclamp[c] = acc < 0.0;
+            p->rgb[c] = acc < 0.0 ? 0.0 : acc;
+        }
+        k = 0;
+    } else {
+        for (int c = 0; c < 3; ++c) p->rgb[c] = P(sc->base, n, c, i);
+    }
     for (int l = 0; l < k; ++l) {
         double ax[3], al = 0;
         for (int a = 0; a < 3; ++a) { ax[a] = sc->axis[lobe3(sc, i, l, a)]; al += ax[a] * ax[a]; }
@@ -697,6 +761,7 @@ void oracle_blend_backward(int32_t w, int32_t h, int32_t tile, const double *bg,
  */
 typedef struct {
     double *pos, *logscale, *quat, *op_logit, *pmask_logit, *base, *axis, *sharp, *amp, *lmask_logit;
+    double *sh;
 } ograd;
 
 void oracle_project_backward(const oscene *sc, const ocam *cam, int32_t tile, const double *grad2d, ograd *gr) {
@@ -712,8 +777,20 @@ void oracle_project_backward(const oscene *sc, const ocam *cam, int32_t tile, co
 
         /* colour */
         double gd[3] = {0, 0, 0};
-        for (int c = 0; c < 3; ++c) gr->base[c * n + i] += drgb[c];
-        const int k = lobe_count(sc, i);
+        if (sc->sh) {
+            const int nm = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+            for (int c = 0; c < 3; ++c) {
+                if (p.shclamp[c]) continue;
+                for (int m = 0; m < nm; ++m) {
+                    gr->sh[((int64_t)m * 3 + c) * n + i] += p.shY[m] * drgb[c];
+                    for (int a = 0; a < 3; ++a)
+                        gd[a] += sc->sh[((int64_t)m * 3 + c) * n + i] * drgb[c] * p.shdY[m][a];
+                }
+            }
+        } else {
+            for (int c = 0; c < 3; ++c) gr->base[c * n + i] += drgb[c];
+        }
+        const int k = sc->sh ? 0 : lobe_count(sc, i);
         for (int l = 0; l < k; ++l) {
             double lam = sc->sharp[lobe1(sc, i, l)];
             double ip = 0;

@@ -22,16 +22,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "megs_oracle.c")
 LIB = os.path.join(HERE, "libmegs_oracle.so")
 
-PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
-          "base", "axis", "sharp", "amp", "lmask_logit")
+SCENE_PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
+                "base", "axis", "sharp", "amp", "lmask_logit")
+PLANES = SCENE_PLANES + ("sh",)   # "sh": spherical-harmonic coefficients [(D + 1)^2][3][n] (SH colour)
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
 class OScene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("pad", ctypes.c_int32)] + \
-               [(p, _dp) for p in PLANES] + [("lobe_off", ctypes.POINTER(ctypes.c_int32)),
-                                              ("n_lobes", ctypes.c_int64)]
+               [(p, _dp) for p in SCENE_PLANES] + [("lobe_off", ctypes.POINTER(ctypes.c_int32)),
+                                                    ("n_lobes", ctypes.c_int64), ("sh", _dp),
+                                                    ("sh_degree", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 class OCam(ctypes.Structure):
@@ -82,6 +84,7 @@ def lib():
                                             ctypes.c_int32, vp, vp]
         L.oracle_project_backward.argtypes = [ctypes.POINTER(OScene), ctypes.POINTER(OCam), ctypes.c_int32,
                                               vp, ctypes.POINTER(OGrad)]
+        L.oracle_sh_basis.argtypes = [ctypes.c_int64, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -102,6 +105,10 @@ def make_oscene(planes: dict, k: int):
     s = OScene(n=n, k=k, pad=0)
     for p in PLANES:
         setattr(s, p, None if keep[p] is None else keep[p].ctypes.data_as(_dp))
+    if keep["sh"] is not None:
+        nm = keep["sh"].shape[0]
+        s.sh_degree = int(round(nm ** 0.5)) - 1
+        assert (s.sh_degree + 1) ** 2 == nm and 0 <= s.sh_degree <= 3, "sh planes must be [(D + 1)^2][3][n], D <= 3"
     off = planes.get("lobe_off")
     if off is not None:
         off = np.ascontiguousarray(off, dtype=np.int32)
@@ -158,6 +165,16 @@ def sg_color_many(base, axis, sharp, amp, directions, mask=None) -> np.ndarray:
     lib().oracle_sg_color_many(len(sharp), _ptr(base), _ptr(axis), _ptr(sharp), _ptr(amp), _ptr(mask),
                                len(d), _ptr(d), _ptr(out))
     return out
+
+
+def sh_basis(dirs):
+    """Real spherical harmonics of degree <= 3 at unit directions dirs [m][3]: (Y [m][16],
+    dY/d(x, y, z) [m][16][3])."""
+    dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    Y = np.zeros((len(dirs), 16))
+    dY = np.zeros((len(dirs), 16, 3))
+    lib().oracle_sh_basis(len(dirs), _ptr(dirs), _ptr(Y), _ptr(dY))
+    return Y, dY
 
 
 def threads() -> int:

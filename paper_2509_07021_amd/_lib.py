@@ -30,6 +30,7 @@ EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", 
 
 PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
           "base", "axis", "sharp", "amp", "lmask_logit")
+ALL_PLANES = PLANES + ("sh",)   # "sh": spherical-harmonic coefficients (SH-colour scenes)
 
 _vp = ctypes.c_void_p
 
@@ -37,7 +38,8 @@ _vp = ctypes.c_void_p
 class MegsScene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("dt_geom", ctypes.c_int32),
                 ("dt_color", ctypes.c_int32), ("dt_amp", ctypes.c_int32), ("reserved", ctypes.c_int32)] + \
-               [(p, _vp) for p in PLANES] + [("lobe_off", _vp), ("n_lobes", ctypes.c_int64)]
+               [(p, _vp) for p in PLANES] + [("lobe_off", _vp), ("n_lobes", ctypes.c_int64), ("sh", _vp),
+                                             ("sh_degree", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class MegsCompacted(ctypes.Structure):
@@ -45,7 +47,7 @@ class MegsCompacted(ctypes.Structure):
 
 
 class MegsSceneGrad(ctypes.Structure):
-    _fields_ = [(p, _vp) for p in PLANES]
+    _fields_ = [(p, _vp) for p in ALL_PLANES]
 
 
 class MegsCamera(ctypes.Structure):

@@ -117,8 +117,12 @@ megs_status check_scene(const megs_scene* sc) {
     } else if (sc->n_lobes != 0) {
         return fail(MEGS_ERR_ARG, "n_lobes must be 0 for the dense lobe layout");
     }
+    if (sc->sh) {
+        if (sc->sh_degree < 0 || sc->sh_degree > 3) return fail(MEGS_ERR_ARG, "sh_degree = %d outside [0, 3]", sc->sh_degree);
+        if (sc->k != 0 || sc->lobe_off) return fail(MEGS_ERR_ARG, "a spherical-harmonic scene has no SG lobes (k = 0)");
+    }
     if (sc->n > 0) {
-        if (!sc->pos || !sc->logscale || !sc->quat || !sc->op_logit || !sc->base)
+        if (!sc->pos || !sc->logscale || !sc->quat || !sc->op_logit || (!sc->base && !sc->sh))
             return fail(MEGS_ERR_ARG, "null geometry or base plane");
         if (has_lobes(sc) && (!sc->axis || !sc->sharp || !sc->amp)) return fail(MEGS_ERR_ARG, "null lobe plane");
     }
@@ -196,6 +200,8 @@ SceneDev scene_dev(const megs_scene* sc, int32_t* status) {
     if (!has_lobes(sc)) d.k = 0;
     d.n_lobes = sc->n_lobes;
     d.status = status;
+    d.sh = sc->sh;
+    d.sh_degree = sc->sh_degree;
     return d;
 }
 
@@ -436,6 +442,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     g.pos = gr->pos; g.logscale = gr->logscale; g.quat = gr->quat; g.op_logit = gr->op_logit;
     g.pmask_logit = gr->pmask_logit; g.base = gr->base; g.axis = gr->axis; g.sharp = gr->sharp; g.amp = gr->amp;
     g.lmask_logit = gr->lmask_logit;
+    g.sh = gr->sh;
     {
         StageTimer t(MEGS_STAGE_PROJECT_BWD, s);
         HIP_TRY(launch_project_bwd(scene_dev(sc, nullptr), a.views, L.nv, grad2d, g, s));
@@ -446,7 +453,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
 megs_status check_grads(const megs_scene* sc, const megs_scene_grad* g) {
     if (!g) return fail(MEGS_ERR_ARG, "null gradient struct");
     if (sc->n == 0) return MEGS_OK;
-    if (!g->pos || !g->logscale || !g->quat || !g->op_logit || !g->base)
+    if (!g->pos || !g->logscale || !g->quat || !g->op_logit || (sc->sh ? !g->sh : !g->base))
         return fail(MEGS_ERR_ARG, "null gradient plane");
     if (has_lobes(sc) && (!g->axis || !g->sharp || !g->amp)) return fail(MEGS_ERR_ARG, "null lobe gradient plane");
     if ((sc->pmask_logit != nullptr) != (g->pmask_logit != nullptr))
@@ -630,6 +637,7 @@ megs_status megs_compact(const megs_scene* scene, double opacity_min, double sha
     if (st != MEGS_OK) return st;
     if (!alloc || !out) return fail(MEGS_ERR_ARG, "null allocator or output");
     if (isnan(opacity_min) || isnan(sharp_min)) return fail(MEGS_ERR_ARG, "NaN threshold");
+    if (scene->sh) return fail(MEGS_ERR_UNSUPPORTED, "compaction of spherical-harmonic scenes");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = scene->n;
     CompactArgs a;

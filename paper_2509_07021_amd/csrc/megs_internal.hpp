@@ -47,11 +47,14 @@ struct SceneDev {
     const int32_t* lobe_off;  // NULL: dense lobe planes; else compressed-row offsets [n + 1]
     int64_t n_lobes;
     int32_t* status;          // device status block, or NULL
+    const void* sh;           // NULL: SG colour; else SH coefficients [(sh_degree + 1)^2][3][n]
+    int32_t sh_degree;
 };
 
 struct GradDev {
     float *pos, *logscale, *quat, *op_logit, *pmask_logit;
     float *base, *axis, *sharp, *amp, *lmask_logit;
+    float* sh;
 };
 
 // Record planes written by the projection (record r = view * n + i).

@@ -160,16 +160,21 @@ __device__ __forceinline__ void project_view(const Geo& g, const float pos[3], c
     p.radius = p.ok ? (int32_t)r : -1;
 }
 
-// d = (mu - campos) / |mu - campos| and the SG colour; returns false if not finite.
+// d = (mu - campos) / |mu - campos|, the viewing direction (from the camera to the Gaussian).
+__device__ __forceinline__ void view_dir(const float pos[3], const ViewInfo& vw, float d[3], float& dlen) {
+    float dv[3] = {pos[0] - vw.campos[0], pos[1] - vw.campos[1], pos[2] - vw.campos[2]};
+    dlen = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    const float il = 1.0f / dlen;
+    d[0] = dv[0] * il; d[1] = dv[1] * il; d[2] = dv[2] * il;
+}
+
+// The SG colour at d; returns false if not finite.
 template <int K>
 __device__ __forceinline__ bool sg_colour(const SceneDev& sc, int64_t i, const float pos[3], const ViewInfo& vw,
                                           const Lobes<K>& L, float d[3], float& dlen, float rgb[3], float e[K > 0 ? K : 1],
                                           float muh[K > 0 ? K : 1][3], float dd2[K > 0 ? K : 1]) {
     const int64_t n = sc.n;
-    float dv[3] = {pos[0] - vw.campos[0], pos[1] - vw.campos[1], pos[2] - vw.campos[2]};
-    dlen = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-    const float il = 1.0f / dlen;
-    d[0] = dv[0] * il; d[1] = dv[1] * il; d[2] = dv[2] * il;
+    view_dir(pos, vw, d, dlen);
     for (int c = 0; c < 3; ++c) rgb[c] = load_elem(sc.base, sc.dt_color, c * n + i);
 #pragma unroll
     for (int l = 0; l < K; ++l) {
@@ -190,13 +195,97 @@ __device__ __forceinline__ bool sg_colour(const SceneDev& sc, int64_t i, const f
     return isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
 }
 
+// ---- spherical-harmonic colour (3DGS's colour model, for the same-renderer comparison) ----
+// Real spherical harmonics of degree <= D at a unit direction (x, y, z), orthonormal over the
+// sphere, in the sign convention of the 3DGS rasteriser: Y_0 = 1 / (2 sqrt(pi)); degree 1:
+// sqrt(3 / (4 pi)) (-y, z, -x); degree 2 and 3: the Cartesian polynomials below with their
+// normalisations (sqrt(15 / pi) / 2, sqrt(5 / pi) / 4, sqrt(15 / pi) / 4; sqrt(35 / (2 pi)) / 4,
+// sqrt(105 / pi) / 2, sqrt(21 / (2 pi)) / 4, sqrt(7 / pi) / 4, sqrt(105 / pi) / 4).
+constexpr float kSh0 = 0.28209479177387814f;
+constexpr float kSh1 = 0.48860251190291992f;
+constexpr float kSh2a = 1.0925484305920792f, kSh2b = 0.31539156525252005f, kSh2c = 0.54627421529603959f;
+constexpr float kSh3a = 0.59004358992664352f, kSh3b = 2.8906114426405538f, kSh3c = 0.45704579946446572f;
+constexpr float kSh3d = 0.37317633259011540f, kSh3e = 1.4453057213202769f;
+
+// Basis values Y[m] and, when G, their partial derivatives dY[m][0..2] in x, y, z (polynomials
+// extended off the sphere; callers project onto the tangent plane).
+template <int D, bool G>
+__device__ __forceinline__ void sh_basis(const float d[3], float Y[16], float dY[16][3]) {
+    const float x = d[0], y = d[1], z = d[2];
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = kSh0;
+    if (G) dY[0][0] = dY[0][1] = dY[0][2] = 0.f;
+    if (D >= 1) {
+        Y[1] = -kSh1 * y; Y[2] = kSh1 * z; Y[3] = -kSh1 * x;
+        if (G) {
+            dY[1][0] = 0.f; dY[1][1] = -kSh1; dY[1][2] = 0.f;
+            dY[2][0] = 0.f; dY[2][1] = 0.f; dY[2][2] = kSh1;
+            dY[3][0] = -kSh1; dY[3][1] = 0.f; dY[3][2] = 0.f;
+        }
+    }
+    if (D >= 2) {
+        Y[4] = kSh2a * x * y;
+        Y[5] = -kSh2a * y * z;
+        Y[6] = kSh2b * (2.f * zz - xx - yy);
+        Y[7] = -kSh2a * x * z;
+        Y[8] = kSh2c * (xx - yy);
+        if (G) {
+            dY[4][0] = kSh2a * y; dY[4][1] = kSh2a * x; dY[4][2] = 0.f;
+            dY[5][0] = 0.f; dY[5][1] = -kSh2a * z; dY[5][2] = -kSh2a * y;
+            dY[6][0] = -2.f * kSh2b * x; dY[6][1] = -2.f * kSh2b * y; dY[6][2] = 4.f * kSh2b * z;
+            dY[7][0] = -kSh2a * z; dY[7][1] = 0.f; dY[7][2] = -kSh2a * x;
+            dY[8][0] = 2.f * kSh2c * x; dY[8][1] = -2.f * kSh2c * y; dY[8][2] = 0.f;
+        }
+    }
+    if (D >= 3) {
+        const float q = 4.f * zz - xx - yy;
+        Y[9] = -kSh3a * y * (3.f * xx - yy);
+        Y[10] = kSh3b * x * y * z;
+        Y[11] = -kSh3c * y * q;
+        Y[12] = kSh3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+        Y[13] = -kSh3c * x * q;
+        Y[14] = kSh3e * z * (xx - yy);
+        Y[15] = -kSh3a * x * (xx - 3.f * yy);
+        if (G) {
+            dY[9][0] = -6.f * kSh3a * x * y; dY[9][1] = -3.f * kSh3a * (xx - yy); dY[9][2] = 0.f;
+            dY[10][0] = kSh3b * y * z; dY[10][1] = kSh3b * x * z; dY[10][2] = kSh3b * x * y;
+            dY[11][0] = 2.f * kSh3c * x * y; dY[11][1] = -kSh3c * (q - 2.f * yy); dY[11][2] = -8.f * kSh3c * y * z;
+            dY[12][0] = -6.f * kSh3d * x * z; dY[12][1] = -6.f * kSh3d * y * z;
+            dY[12][2] = kSh3d * (6.f * zz - 3.f * xx - 3.f * yy);
+            dY[13][0] = -kSh3c * (q - 2.f * xx); dY[13][1] = 2.f * kSh3c * x * y; dY[13][2] = -8.f * kSh3c * x * z;
+            dY[14][0] = 2.f * kSh3e * x * z; dY[14][1] = -2.f * kSh3e * y * z; dY[14][2] = kSh3e * (xx - yy);
+            dY[15][0] = -3.f * kSh3a * (xx - yy); dY[15][1] = 6.f * kSh3a * x * y; dY[15][2] = 0.f;
+        }
+    }
+}
+
+// colour = max(0, sum_m Y_m(d) sh[m] + 1/2) per channel; clamped[c] records the clamp.
+template <int D>
+__device__ __forceinline__ bool sh_colour(const SceneDev& sc, int64_t i, const float pos[3], const ViewInfo& vw,
+                                          float d[3], float& dlen, float rgb[3], bool clamped[3]) {
+    constexpr int M = (D + 1) * (D + 1);
+    const int64_t n = sc.n;
+    view_dir(pos, vw, d, dlen);
+    float Y[16], dY[16][3];
+    sh_basis<D, false>(d, Y, dY);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float acc = 0.5f;
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc = __fmaf_rn(Y[m], load_elem(sc.sh, sc.dt_color, ((int64_t)m * 3 + c) * n + i), acc);
+        clamped[c] = acc < 0.0f;
+        rgb[c] = clamped[c] ? 0.0f : acc;
+    }
+    return isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
+}
+
 // Ellipse level that bounds every pixel with alpha >= 1/255: q <= 2 ln(255 o), widened by 0.2% (and
 // 1e-4 absolute) so that FP32 rounding in the blend never reaches past a culled tile.
 __device__ __forceinline__ float cutoff_of(float o_eff) {
     return 2.004f * __logf(255.0f * o_eff) + 1e-4f;
 }
 
-template <int K, bool RAGGED>
+template <int K, bool RAGGED, int SHD>
 __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __restrict__ views, int nv, int tile,
                                                  Records rec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -214,7 +303,14 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
         project_view(g, pos, vw, p);
         float d[3], dlen, rgb[3], e[K > 0 ? K : 1], muh[K > 0 ? K : 1][3], dd2[K > 0 ? K : 1];
         bool ok = p.ok && lobes_ok;
-        if (ok) ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
+        if (ok) {
+            if constexpr (SHD >= 0) {
+                bool clamped[3];
+                ok = sh_colour<SHD>(sc, i, pos, vw, d, dlen, rgb, clamped);
+            } else {
+                ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
+            }
+        }
         uint32_t nt = 0;
         if (ok) {
             int x0, x1, y0, y1;
@@ -255,9 +351,13 @@ __device__ __forceinline__ void quat_grad(const float q[4], const float gR[9], f
     gq[3] = 2.f * (w * (gR[3] - gR[1]) + x * (gR[2] + gR[6]) + y * (gR[5] + gR[7])) - 4.f * z * (gR[0] + gR[4]);
 }
 
-template <int K, bool RAGGED>
+template <int K, bool RAGGED, int SHD>
 __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
                                                      const float* __restrict__ grad2d, GradDev G) {
+    constexpr int SHM = SHD >= 0 ? (SHD + 1) * (SHD + 1) : 1;
+    float gsh[SHM][3];
+#pragma unroll
+    for (int m = 0; m < SHM; ++m) gsh[m][0] = gsh[m][1] = gsh[m][2] = 0.f;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= sc.n) return;
     const int64_t n = sc.n;
@@ -285,8 +385,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo
         ViewProj p;
         project_view(g, pos, vw, p);
         float d[3], dlen, rgb[3], e[KK], muh[KK][3], dd2[KK];
+        bool clamped[3] = {false, false, false};
         bool ok = p.ok && lobes_ok;
-        if (ok) ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
+        if (ok) {
+            if constexpr (SHD >= 0)
+                ok = sh_colour<SHD>(sc, i, pos, vw, d, dlen, rgb, clamped);
+            else
+                ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
+        }
         if (!ok) continue;
         const float* gr = grad2d + 9 * r;
         const float gu = gr[0], gv = gr[1], ga = gr[2], gb = gr[3], gc = gr[4], go = gr[5];
@@ -294,7 +400,24 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo
 
         // colour
         float gd[3] = {0.f, 0.f, 0.f};
-        for (int c = 0; c < 3; ++c) gbase[c] += gcol[c];
+        if constexpr (SHD >= 0) {
+            float Y[16], dY[16][3];
+            sh_basis<SHD, true>(d, Y, dY);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float gc = clamped[c] ? 0.f : gcol[c];
+#pragma unroll
+                for (int m = 0; m < SHM; ++m) {
+                    gsh[m][c] = __fmaf_rn(Y[m], gc, gsh[m][c]);
+                    const float w = gc * load_elem(sc.sh, sc.dt_color, ((int64_t)m * 3 + c) * n + i);
+                    gd[0] = __fmaf_rn(w, dY[m][0], gd[0]);
+                    gd[1] = __fmaf_rn(w, dY[m][1], gd[1]);
+                    gd[2] = __fmaf_rn(w, dY[m][2], gd[2]);
+                }
+            }
+        } else {
+            for (int c = 0; c < 3; ++c) gbase[c] += gcol[c];
+        }
 #pragma unroll
         for (int l = 0; l < K; ++l) {
             const float ip = L.amp[l][0] * gcol[0] + L.amp[l][1] * gcol[1] + L.amp[l][2] * gcol[2];
@@ -402,6 +525,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo
     for (int c = 0; c < 4; ++c) G.quat[c * n + i] = gq[c];
     G.op_logit[i] = gop;
     if (G.pmask_logit) G.pmask_logit[i] = gpm;
+    if constexpr (SHD >= 0) {
+#pragma unroll
+        for (int m = 0; m < SHM; ++m)
+            for (int c = 0; c < 3; ++c) G.sh[((int64_t)m * 3 + c) * n + i] = gsh[m][c];
+        return;
+    }
     for (int c = 0; c < 3; ++c) G.base[c * n + i] = gbase[c];
 #pragma unroll
     for (int l = 0; l < K; ++l) {
@@ -413,19 +542,19 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo
     }
 }
 
-template <int K, bool RAGGED>
+template <int K, bool RAGGED, int SHD = -1>
 hipError_t dispatch_fwd(const SceneDev& sc, const ViewInfo* views, int nv, int tile, const Records& rec,
                         hipStream_t stream) {
     const int64_t blocks = (sc.n + 255) / 256;
-    hipLaunchKernelGGL((k_project<K, RAGGED>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, tile, rec);
+    hipLaunchKernelGGL((k_project<K, RAGGED, SHD>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, tile, rec);
     return hipGetLastError();
 }
 
-template <int K, bool RAGGED>
+template <int K, bool RAGGED, int SHD = -1>
 hipError_t dispatch_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d, const GradDev& g,
                         hipStream_t stream) {
     const int64_t blocks = (sc.n + 255) / 256;
-    hipLaunchKernelGGL((k_project_bwd<K, RAGGED>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, grad2d,
+    hipLaunchKernelGGL((k_project_bwd<K, RAGGED, SHD>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, grad2d,
                        g);
     return hipGetLastError();
 }
@@ -467,9 +596,19 @@ hipError_t project_bwd_k(const SceneDev& sc, const ViewInfo* views, int nv, cons
 }  // namespace
 
 // A compressed-row scene with k = 0 has no lobes at all and takes the dense k = 0 kernels.
+// Spherical-harmonic scenes (sc.sh non-null) take the SH instances, one per degree.
 hipError_t launch_project(const SceneDev& sc, const ViewInfo* views, int nv, int tile, const Records& rec,
                           hipStream_t stream) {
     if (sc.n == 0) return hipSuccess;
+    if (sc.sh) {
+        switch (sc.sh_degree) {
+            case 0: return dispatch_fwd<0, false, 0>(sc, views, nv, tile, rec, stream);
+            case 1: return dispatch_fwd<0, false, 1>(sc, views, nv, tile, rec, stream);
+            case 2: return dispatch_fwd<0, false, 2>(sc, views, nv, tile, rec, stream);
+            case 3: return dispatch_fwd<0, false, 3>(sc, views, nv, tile, rec, stream);
+        }
+        return hipErrorInvalidValue;
+    }
     return sc.lobe_off ? project_k<true>(sc, views, nv, tile, rec, stream)
                        : project_k<false>(sc, views, nv, tile, rec, stream);
 }
@@ -477,6 +616,15 @@ hipError_t launch_project(const SceneDev& sc, const ViewInfo* views, int nv, int
 hipError_t launch_project_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d,
                               const GradDev& g, hipStream_t stream) {
     if (sc.n == 0) return hipSuccess;
+    if (sc.sh) {
+        switch (sc.sh_degree) {
+            case 0: return dispatch_bwd<0, false, 0>(sc, views, nv, grad2d, g, stream);
+            case 1: return dispatch_bwd<0, false, 1>(sc, views, nv, grad2d, g, stream);
+            case 2: return dispatch_bwd<0, false, 2>(sc, views, nv, grad2d, g, stream);
+            case 3: return dispatch_bwd<0, false, 3>(sc, views, nv, grad2d, g, stream);
+        }
+        return hipErrorInvalidValue;
+    }
     return sc.lobe_off ? project_bwd_k<true>(sc, views, nv, grad2d, g, stream)
                        : project_bwd_k<false>(sc, views, nv, grad2d, g, stream);
 }

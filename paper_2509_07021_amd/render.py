@@ -15,7 +15,7 @@ import torch
 
 from . import _lib as L
 
-PLANES = L.PLANES
+PLANES = L.ALL_PLANES
 _TORCH_DT = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
 _MEGS_DT = {"f32": L.MEGS_F32, "f16": L.MEGS_F16, "bf16": L.MEGS_BF16}
 GEOM = ("pos", "logscale", "quat", "op_logit", "pmask_logit")
@@ -59,6 +59,8 @@ class DeviceScene:
         self.lobe_off = lobe_off
         self.n_lobes = int(n_lobes) if lobe_off is not None else 0
         self._keepalive = keepalive
+        sh = planes.get("sh")
+        self.sh_degree = 0 if sh is None else int(round(sh.shape[0] ** 0.5)) - 1
         for p in PLANES:
             t = planes.get(p)
             if t is None:
@@ -113,6 +115,7 @@ class DeviceScene:
             setattr(s, p, None if t is None else t.data_ptr())
         s.lobe_off = None if self.lobe_off is None else self.lobe_off.data_ptr()
         s.n_lobes = self.n_lobes
+        s.sh_degree = self.sh_degree
         return s
 
     def static_bytes(self) -> int:

@@ -16,6 +16,8 @@ Parameter planes (structure of arrays, raw values as the renderer stores them):
     sharp[K][N]        SG sharpness, used as stored
     amp[K][3][N]       SG RGB amplitude
     lmask_logit[K][N]  optional per-lobe soft-mask logit (sigmoid)
+    sh[M][3][N]        spherical-harmonic colour (M = (D + 1)^2, D <= 3) instead of the SG
+                       planes, for the same-renderer comparison with 3DGS's colour model
 
 The Gaussian-count range (0.2 M to 3 M) follows the primitive counts the paper
 reports for its trained scenes (Appendix, table of Gaussian counts). The paper
@@ -37,11 +39,11 @@ from typing import Optional, Sequence
 import numpy as np
 
 PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
-          "base", "axis", "sharp", "amp", "lmask_logit")
+          "base", "axis", "sharp", "amp", "lmask_logit", "sh")
 
 # Which storage-dtype group each plane belongs to.
 GEOM_PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit")
-COLOR_PLANES = ("base", "axis", "sharp", "lmask_logit")
+COLOR_PLANES = ("base", "axis", "sharp", "lmask_logit", "sh")
 AMP_PLANES = ("amp",)
 LOBE_PLANES = ("axis", "sharp", "amp", "lmask_logit")
 
@@ -68,6 +70,8 @@ class Scene:
     # offsets, Gaussian i owning lobes lobe_off[i] .. lobe_off[i + 1] - 1 (at most K) of the
     # planes axis[3][L], sharp[L], amp[3][L], lmask_logit[L] (L = lobe_off[N])
     lobe_off: Optional[np.ndarray] = None
+    # spherical-harmonic colour instead of SG lobes: coefficients [(D + 1)^2][3][N] (None: SG)
+    sh: Optional[np.ndarray] = None
 
     @property
     def has_masks(self) -> bool:
@@ -419,6 +423,22 @@ def post_admm(scene: Scene, seed: int, prim_frac: float = 0.4, lobe_frac: float 
     lpick = rng.random(sharp.shape) < lobe_frac
     sharp[lpick] = rng.uniform(0.0, 1.0, size=int(lpick.sum()))
     return dataclasses.replace(scene, op_logit=op, sharp=sharp)
+
+
+def sh_scene(scene: Scene, seed: int, degree: int = 3) -> Scene:
+    """The scene's geometry with spherical-harmonic colour of the given degree instead of SG
+    lobes: DC coefficients U(-1, 1.8), higher coefficients N(0, 0.1^2) (seeded; draw order: the
+    DC plane, then coefficients 1.. in plane order)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 3000))
+    m = (degree + 1) ** 2
+    sh = np.zeros((m, 3, scene.n), np.float64)
+    sh[0] = rng.uniform(-1.0, 1.8, size=(3, scene.n))
+    sh[1:] = rng.normal(0.0, 0.1, size=(m - 1, 3, scene.n))
+    empty = lambda *shape: np.zeros(shape, np.float32)
+    sh = to_storage(sh.astype(np.float32), scene.dt_color)
+    return dataclasses.replace(scene, k=0, base=None, axis=empty(0, 3, scene.n), sharp=empty(0, scene.n),
+                               amp=to_storage(empty(0, 3, scene.n), scene.dt_amp), lmask_logit=None, lobe_off=None,
+                               sh=sh)
 
 
 def axis_nearest(scene: Scene, cam: Camera, count: int) -> np.ndarray:
