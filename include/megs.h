@@ -316,6 +316,32 @@ typedef struct {
 megs_status megs_compact(const megs_scene *scene, double opacity_min, double sharp_min, megs_alloc_fn alloc,
                          void *alloc_ctx, void *stream, megs_compacted *out);
 
+/*
+ * ---- Training step around the renderer (the 3DGS loss and optimiser the paper trains with;
+ * Appendix, experimental details) ----
+ *
+ * Photometric loss L = sum over views of (1 - lambda) mean|x - y| + lambda (1 - mean SSIM(x, y)),
+ * each mean over the view's 3 channels and pixels; SSIM with an 11x11 Gaussian window of sigma 1.5,
+ * zero padding, C1 = 0.01^2, C2 = 0.03^2 (3DGS uses lambda = 0.2). images and targets: device float
+ * in the image layout of megs_render_forward; sizes: host int32[n_views][2] = (width, height).
+ * loss: device double[1], written. dl_dimages: device float in the image layout, written with
+ * dL/dimages (|.| has gradient 0 where x = y), or NULL for the loss alone. SSIM arithmetic is FP64.
+ * Scratch (72 bytes per pixel) comes from alloc; the loss is deterministic.
+ */
+megs_status megs_photometric_loss(const float *images, const float *targets, int32_t n_views, const int32_t *sizes,
+                                  double lambda_dssim, megs_alloc_fn alloc, void *alloc_ctx, double *loss,
+                                  float *dl_dimages, void *stream);
+
+/*
+ * Adam step (Kingma and Ba, bias-corrected, eps added to the corrected root) on one parameter plane
+ * of count elements stored as dtype (MEGS_F32, MEGS_F16 or MEGS_BF16): m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2, p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps), in FP32,
+ * the parameter rounded back to its storage dtype (nearest even). grad, m, v: device float[count];
+ * m and v updated in place; step >= 1 is the 1-based step number.
+ */
+megs_status megs_adam_step(int64_t count, void *param, int32_t dtype, const float *grad, float *m, float *v, float lr,
+                           float beta1, float beta2, float eps, int32_t step, void *stream);
+
 /* Description of the last error on the calling thread ("" when none). */
 const char *megs_last_error(void);
 

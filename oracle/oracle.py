@@ -511,3 +511,79 @@ def compact(planes: dict, k: int, opacity_min: float, sharp_min: float) -> dict:
         "axis": axis[:, lsel], "sharp": sh[lsel], "amp": amp[:, lsel] * m[lsel], "lmask_logit": None,
         "lobe_off": lobe_off, "kept": kept.astype(np.int32), "lobe_src": src[lsel].astype(np.int32),
     }
+
+
+# ------------------------------------------------------------ training step ----
+# The photometric loss and optimiser of the 3DGS training the paper keeps (Appendix, experimental
+# details: the same hyperparameters and optimiser as vanilla 3DGS): L = (1 - lambda) L1 +
+# lambda (1 - SSIM), lambda = 0.2, SSIM with an 11x11 Gaussian window of sigma 1.5, zero padding,
+# C1 = 0.01^2, C2 = 0.03^2; Adam.
+
+SSIM_C1, SSIM_C2 = 0.01 ** 2, 0.03 ** 2
+
+
+def gaussian_window(size: int = 11, sigma: float = 1.5) -> np.ndarray:
+    """Normalised 1D Gaussian taps; the 2D window is their outer product."""
+    x = np.arange(size, dtype=np.float64) - size // 2
+    g = np.exp(-x * x / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def photometric_loss(images, targets, lam: float = 0.2):
+    """Sum over views of (1 - lam) mean|x - y| + lam (1 - mean SSIM(x, y)) over each view's three
+    channels and pixels, and its gradient with respect to every x, in FP64 (plain torch CPU ops
+    with autograd; |.| has gradient 0 at x = y). images, targets: lists of [3][H][W] arrays.
+    Returns (loss, [dL/dx per view])."""
+    import torch
+    import torch.nn.functional as F
+    g = torch.from_numpy(gaussian_window())
+    win = torch.outer(g, g)[None, None]
+    total = torch.zeros((), dtype=torch.float64)
+    xs = []
+    for img, tgt in zip(images, targets):
+        x = torch.tensor(np.asarray(img, np.float64), requires_grad=True)
+        y = torch.from_numpy(np.asarray(tgt, np.float64))
+        xs.append(x)
+        conv = lambda t: F.conv2d(t[:, None], win, padding=5)[:, 0]
+        mx, my = conv(x), conv(y)
+        sxx = conv(x * x) - mx * mx
+        syy = conv(y * y) - my * my
+        sxy = conv(x * y) - mx * my
+        ssim = ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+        total = total + (1 - lam) * (x - y).abs().mean() + lam * (1 - ssim.mean())
+    total.backward()
+    return float(total.detach()), [x.grad.numpy().copy() for x in xs]
+
+
+def ssim_map_direct(x, y) -> np.ndarray:
+    """The SSIM map of one channel by explicit window sums over zero-padded images (slow; for
+    small test images only)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    h, w = x.shape
+    g = gaussian_window()
+    W = np.outer(g, g)
+    xp = np.zeros((h + 10, w + 10)); xp[5:5 + h, 5:5 + w] = x
+    yp = np.zeros((h + 10, w + 10)); yp[5:5 + h, 5:5 + w] = y
+    out = np.zeros((h, w))
+    for i in range(h):
+        for j in range(w):
+            a = xp[i:i + 11, j:j + 11]
+            b = yp[i:i + 11, j:j + 11]
+            mx, my = (W * a).sum(), (W * b).sum()
+            vx = (W * a * a).sum() - mx * mx
+            vy = (W * b * b).sum() - my * my
+            cxy = (W * a * b).sum() - mx * my
+            out[i, j] = ((2 * mx * my + SSIM_C1) * (2 * cxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (vx + vy + SSIM_C2))
+    return out
+
+
+def adam_step(param, grad, m, v, lr: float, beta1: float, beta2: float, eps: float, step: int):
+    """One Adam update (Kingma and Ba, with bias correction; eps added to the corrected root):
+    returns (param', m', v') in FP64."""
+    g = np.asarray(grad, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1 - beta2) * g * g
+    mhat = m / (1 - beta1 ** step)
+    vhat = v / (1 - beta2 ** step)
+    return np.asarray(param, np.float64) - lr * mhat / (np.sqrt(vhat) + eps), m, v

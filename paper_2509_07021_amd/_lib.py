@@ -26,7 +26,7 @@ EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", 
             "megs_graph_launch", "megs_graph_status", "megs_graph_state", "megs_graph_destroy",
             "megs_autotune", "megs_profile_begin", "megs_profile_end", "megs_last_error", "megs_version",
             "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply", "megs_dual_update",
-            "megs_penalty_grad", "megs_compact")
+            "megs_penalty_grad", "megs_compact", "megs_photometric_loss", "megs_adam_step")
 
 PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
           "base", "axis", "sharp", "amp", "lmask_logit")
@@ -119,12 +119,17 @@ def load():
     L.megs_penalty_grad.argtypes = [ctypes.c_int64, ctypes.c_float, _vp, _vp, _vp, _vp, _vp]
     L.megs_compact.argtypes = [P(MegsScene), ctypes.c_double, ctypes.c_double, ALLOC_FN, _vp, _vp,
                                P(MegsCompacted)]
+    L.megs_photometric_loss.argtypes = [_vp, _vp, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_double, ALLOC_FN, _vp,
+                                        _vp, _vp, _vp]
+    L.megs_adam_step.argtypes = [ctypes.c_int64, _vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp]
     L.megs_profile_begin.argtypes = []
     L.megs_profile_end.argtypes = [P(MegsProfile)]
     for f in ("megs_render_forward", "megs_render_backward", "megs_state_status", "megs_graph_create",
               "megs_graph_launch", "megs_graph_status", "megs_autotune", "megs_profile_begin", "megs_profile_end",
               "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply",
-              "megs_dual_update", "megs_penalty_grad", "megs_compact"):
+              "megs_dual_update", "megs_penalty_grad", "megs_compact", "megs_photometric_loss",
+              "megs_adam_step"):
         getattr(L, f).restype = ctypes.c_int
     L.megs_last_error.restype = ctypes.c_char_p
     L.megs_last_error.argtypes = []

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmegs.so")
-SOURCES = ("api.hip", "project.hip", "sort.hip", "blend.hip", "prune.hip", "compact.hip")
+SOURCES = ("api.hip", "project.hip", "sort.hip", "blend.hip", "prune.hip", "compact.hip", "loss.hip")
 ARCH = os.environ.get("MEGS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

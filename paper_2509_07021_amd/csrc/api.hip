@@ -714,6 +714,59 @@ megs_status megs_compact(const megs_scene* scene, double opacity_min, double sha
     return MEGS_OK;
 }
 
+megs_status megs_photometric_loss(const float* images, const float* targets, int32_t n_views, const int32_t* sizes,
+                                  double lambda_dssim, megs_alloc_fn alloc, void* alloc_ctx, double* loss,
+                                  float* dl_dimages, void* stream) {
+    g_err[0] = 0;
+    if (n_views < 1 || n_views > MEGS_MAX_VIEWS) return fail(MEGS_ERR_ARG, "n_views = %d outside [1, %d]", n_views, MEGS_MAX_VIEWS);
+    if (!images || !targets || !sizes || !loss || !alloc) return fail(MEGS_ERR_ARG, "null argument");
+    if (!(lambda_dssim >= 0.0 && lambda_dssim <= 1.0)) return fail(MEGS_ERR_ARG, "lambda outside [0, 1]");
+    LossViews vs;
+    memset(&vs, 0, sizeof(vs));
+    int64_t pix = 0, parts = 0;
+    for (int i = 0; i < n_views; ++i) {
+        const int w = sizes[2 * i], h = sizes[2 * i + 1];
+        if (w <= 0 || h <= 0 || w > 16384 || h > 16384) return fail(MEGS_ERR_ARG, "view %d: image size %dx%d out of range", i, w, h);
+        vs.v[i].width = w; vs.v[i].height = h;
+        vs.v[i].pix_off = pix;
+        vs.v[i].part_off = parts;
+        vs.v[i].n_part = loss_partials(w, h);
+        pix += (int64_t)w * h;
+        parts += vs.v[i].n_part;
+    }
+    const size_t bytes = align256(sizeof(double) * 9 * pix) + align256(sizeof(double) * 2 * parts) +
+                         align256(sizeof(double) * n_views) + 256;
+    void* mem = alloc(alloc_ctx, bytes);
+    if (!mem) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", bytes);
+    Carver c{static_cast<char*>(mem), 0};
+    double* maps = c.take<double>(9 * pix);
+    double* partial = c.take<double>(2 * parts);
+    double* terms = c.take<double>(n_views);
+    Window11 g;
+    double sum = 0.0;
+    for (int k = 0; k < 11; ++k) {
+        g.w[k] = exp(-(double)((k - 5) * (k - 5)) / (2.0 * 1.5 * 1.5));
+        sum += g.w[k];
+    }
+    for (int k = 0; k < 11; ++k) g.w[k] /= sum;
+    HIP_TRY(launch_loss(vs, n_views, images, targets, maps, partial, terms, loss, dl_dimages, g, lambda_dssim,
+                        static_cast<hipStream_t>(stream)));
+    return MEGS_OK;
+}
+
+megs_status megs_adam_step(int64_t count, void* param, int32_t dtype, const float* grad, float* m, float* v, float lr,
+                           float beta1, float beta2, float eps, int32_t step, void* stream) {
+    g_err[0] = 0;
+    if (count < 0) return fail(MEGS_ERR_ARG, "count < 0");
+    if (!valid_dtype(dtype)) return fail(MEGS_ERR_ARG, "unknown storage dtype");
+    if (step < 1) return fail(MEGS_ERR_ARG, "step must be >= 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+        return fail(MEGS_ERR_ARG, "beta1, beta2 must lie in [0, 1) and eps >= 0");
+    if (count > 0 && (!param || !grad || !m || !v)) return fail(MEGS_ERR_ARG, "null argument");
+    HIP_TRY(launch_adam(count, param, dtype, grad, m, v, lr, beta1, beta2, eps, step, static_cast<hipStream_t>(stream)));
+    return MEGS_OK;
+}
+
 megs_status megs_state_status(const megs_state* state, int64_t* pairs_needed, void* stream) {
     g_err[0] = 0;
     if (!state || !state->device_status) return fail(MEGS_ERR_ARG, "null state");

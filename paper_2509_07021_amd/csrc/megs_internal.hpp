@@ -290,6 +290,25 @@ struct CompactArgs {
 hipError_t launch_compact_mark(const CompactArgs& a, hipStream_t stream);
 hipError_t launch_compact_write(const CompactArgs& a, hipStream_t stream);
 
+// training-step pieces (loss.hip)
+struct LossView {
+    int32_t width, height;
+    int64_t pix_off;   // first pixel of the view in the concatenated image layout
+    int64_t part_off;  // first loss partial of the view
+    int64_t n_part;    // partials of the view (3 channels x tiles)
+};
+struct LossViews {
+    LossView v[MEGS_MAX_VIEWS];
+};
+struct Window11 {
+    double w[11];
+};
+int64_t loss_partials(int width, int height);
+hipError_t launch_loss(const LossViews& vs, int nv, const float* x, const float* y, double* maps, double* partial,
+                       double* terms, double* loss, float* dl, const Window11& g, double lam, hipStream_t stream);
+hipError_t launch_adam(int64_t count, void* param, int dt, const float* grad, float* m, float* v, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t stream);
+
 // pruning steps (prune.hip)
 size_t select_scratch_bytes(int64_t n);
 hipError_t launch_select_topk(const float* score, int64_t n, int64_t kappa, void* scratch, uint8_t* keep,

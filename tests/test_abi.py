@@ -146,3 +146,27 @@ def test_compact_and_compressed_rows_reject_bad_arguments():
     sc.n_lobes = -1
     status, msg = _forward(sc, cams, 1, cfg)
     assert status == L.MEGS_ERR_ARG and "n_lobes" in msg
+
+
+def test_loss_and_adam_reject_bad_arguments():
+    lib = L.load()
+    noop = L.ALLOC_FN(lambda ctx, n: None)
+    sizes = (ctypes.c_int32 * 2)(16, 16)
+    st = lib.megs_photometric_loss(ctypes.c_void_p(16), ctypes.c_void_p(16), 0, sizes, 0.2, noop, None,
+                                   ctypes.c_void_p(16), None, None)
+    assert st == L.MEGS_ERR_ARG and "n_views" in lib.megs_last_error().decode()
+    st = lib.megs_photometric_loss(ctypes.c_void_p(16), ctypes.c_void_p(16), 1, sizes, 1.5, noop, None,
+                                   ctypes.c_void_p(16), None, None)
+    assert st == L.MEGS_ERR_ARG and "lambda" in lib.megs_last_error().decode()
+    bad = (ctypes.c_int32 * 2)(0, 16)
+    st = lib.megs_photometric_loss(ctypes.c_void_p(16), ctypes.c_void_p(16), 1, bad, 0.2, noop, None,
+                                   ctypes.c_void_p(16), None, None)
+    assert st == L.MEGS_ERR_ARG and "size" in lib.megs_last_error().decode()
+    st = lib.megs_photometric_loss(ctypes.c_void_p(16), ctypes.c_void_p(16), 1, sizes, 0.2, noop, None,
+                                   ctypes.c_void_p(16), None, None)
+    assert st == L.MEGS_ERR_ALLOC
+    v = ctypes.c_void_p(16)
+    assert lib.megs_adam_step(4, v, 7, v, v, v, 1e-3, 0.9, 0.999, 1e-15, 1, None) == L.MEGS_ERR_ARG
+    assert lib.megs_adam_step(4, v, 0, v, v, v, 1e-3, 0.9, 0.999, 1e-15, 0, None) == L.MEGS_ERR_ARG
+    assert lib.megs_adam_step(4, v, 0, v, v, v, 1e-3, 1.0, 0.999, 1e-15, 1, None) == L.MEGS_ERR_ARG
+    assert lib.megs_adam_step(0, None, 0, None, None, None, 1e-3, 0.9, 0.999, 1e-15, 1, None) == L.MEGS_OK
