@@ -119,6 +119,10 @@ typedef struct {
 #define MEGS_FLAG_PERSISTENT 2u     /* blend kernels pull (view, tile) work items from a queue */
 #define MEGS_FLAG_STATS 4u          /* forward also counts blended and evaluated fragments into
                                        device_status (a separate kernel instance; measurement only) */
+#define MEGS_FLAG_DETERMINISTIC 8u  /* bit-reproducible backward: each (tile, Gaussian) pair's 9 gradient
+                                       sums go to the pair's own slot (36 B per pair of scratch), then
+                                       every record adds its slots in a fixed order; no float atomics.
+                                       Set it on the forward and the backward alike. */
 
 typedef struct {
     int32_t tile;          /* tile edge in pixels: 8, 16 or 32 */
@@ -162,6 +166,10 @@ typedef struct {
     const void *mean, *conic_o, *rgbd, *radius, *ntiles, *cutoff;
     const void *tile_keys, *keys64, *vals, *ranges, *T_final, *last, *device_status;
     void *internal; /* library bookkeeping inside the caller's memory */
+    /* deterministic mode bookkeeping (device): sorted position of each emitted pair (NULL unless
+     * MEGS_FLAG_DETERMINISTIC), records in emission order (NULL: index order), the records'
+     * first emission positions, and the pair count */
+    const void *det_inv, *det_order, *det_offsets, *det_count;
 } megs_state;
 
 /* Per-view image layout: images are concatenated, view v's float[3][H][W] planes starting at

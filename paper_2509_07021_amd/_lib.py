@@ -16,6 +16,7 @@ MEGS_F32, MEGS_F16, MEGS_BF16 = 0, 1, 2
 MEGS_FLAG_ONE_STAGE_SORT = 1
 MEGS_FLAG_PERSISTENT = 2
 MEGS_FLAG_STATS = 4
+MEGS_FLAG_DETERMINISTIC = 8
 STAGES = ("project", "depth_sort", "scan", "emit", "pair_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd")
 MEGS_MAX_LOBES = 8
 MEGS_MAX_VIEWS = 64
@@ -68,7 +69,8 @@ class MegsState(ctypes.Structure):
                 ("n_tiles", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("mean", _vp), ("conic_o", _vp), ("rgbd", _vp), ("radius", _vp), ("ntiles", _vp), ("cutoff", _vp),
                 ("tile_keys", _vp), ("keys64", _vp), ("vals", _vp), ("ranges", _vp), ("T_final", _vp),
-                ("last", _vp), ("device_status", _vp), ("internal", _vp)]
+                ("last", _vp), ("device_status", _vp), ("internal", _vp), ("det_inv", _vp), ("det_order", _vp),
+                ("det_offsets", _vp), ("det_count", _vp)]
 
 
 class MegsProfile(ctypes.Structure):

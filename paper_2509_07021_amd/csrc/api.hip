@@ -142,7 +142,8 @@ megs_status check_args(const megs_scene* sc, const megs_camera* cams, int32_t nv
     if (cfg->waves != 0 && cfg->waves != 1 && cfg->waves != 2 && cfg->waves != 4)
         return fail(MEGS_ERR_ARG, "waves = %d not in {0, 1, 2, 4}", cfg->waves);
     if (cfg->tile == 8 && cfg->waves > 1) return fail(MEGS_ERR_ARG, "8x8 tiles take one wave");
-    if (cfg->flags & ~(uint32_t)(MEGS_FLAG_ONE_STAGE_SORT | MEGS_FLAG_PERSISTENT | MEGS_FLAG_STATS))
+    if (cfg->flags & ~(uint32_t)(MEGS_FLAG_ONE_STAGE_SORT | MEGS_FLAG_PERSISTENT | MEGS_FLAG_STATS |
+                                 MEGS_FLAG_DETERMINISTIC))
         return fail(MEGS_ERR_ARG, "unknown flags 0x%x", cfg->flags);
     for (int v = 0; v < nv; ++v) {
         const megs_camera& c = cams[v];
@@ -263,18 +264,20 @@ struct Pairs {
     int64_t capacity;
     uint32_t *tkeys, *tkeys_alt, *vals, *vals_alt;
     uint64_t *k64, *k64_alt;
+    uint32_t *rec_emit, *inv;  // deterministic mode: record per emission position, sorted position per emission
     void* rs_scratch;
 };
 
-size_t pairs_bytes(int64_t cap, bool one_stage) {
+size_t pairs_bytes(int64_t cap, bool one_stage, bool det) {
     const int64_t c = cap > 0 ? cap : 1;
     size_t b = 2 * align256(sizeof(uint32_t) * c);
     b += one_stage ? 2 * align256(sizeof(uint64_t) * c) : 2 * align256(sizeof(uint32_t) * c);
+    if (det) b += 2 * align256(sizeof(uint32_t) * c);
     b += align256(radix_scratch_bytes(c));
     return b + 256;
 }
 
-Pairs carve_pairs(void* mem, int64_t cap, bool one_stage) {
+Pairs carve_pairs(void* mem, int64_t cap, bool one_stage, bool det) {
     Carver c{static_cast<char*>(mem), 0};
     Pairs p;
     p.capacity = cap;
@@ -282,12 +285,17 @@ Pairs carve_pairs(void* mem, int64_t cap, bool one_stage) {
     p.vals_alt = c.take<uint32_t>(cap);
     p.tkeys = p.tkeys_alt = nullptr;
     p.k64 = p.k64_alt = nullptr;
+    p.rec_emit = p.inv = nullptr;
     if (one_stage) {
         p.k64 = c.take<uint64_t>(cap);
         p.k64_alt = c.take<uint64_t>(cap);
     } else {
         p.tkeys = c.take<uint32_t>(cap);
         p.tkeys_alt = c.take<uint32_t>(cap);
+    }
+    if (det) {
+        p.rec_emit = c.take<uint32_t>(cap);
+        p.inv = c.take<uint32_t>(cap);
     }
     p.rs_scratch = c.take<char>((int64_t)radix_scratch_bytes(cap > 0 ? cap : 1));
     return p;
@@ -348,6 +356,11 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
         HIP_TRY(launch_emit(f.rec, f.views, L.nv, L.n, L.tile, one_stage ? nullptr : f.order, f.offs, L.nr, p.tkeys,
                             p.k64, p.vals, p.capacity, f.status, s));
     }
+    const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
+    if (det) {  // sort emission positions; the record ids are gathered back after the sort
+        HIP_TRY(launch_copy_u32(p.rec_emit, p.vals, p.capacity, s));
+        HIP_TRY(launch_iota(p.vals, p.capacity, s));
+    }
     bool alt = false;
     const uint32_t* sorted_t = nullptr;
     const uint64_t* sorted_k = nullptr;
@@ -365,6 +378,12 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
         }
     }
     sorted_v = alt ? p.vals_alt : p.vals;
+    if (det) {
+        uint32_t* rec_sorted = alt ? p.vals : p.vals_alt;  // the ping-pong buffer the sort left free
+        StageTimer t(MEGS_STAGE_PAIR_SORT, s);
+        HIP_TRY(launch_perm_gather(sorted_v, p.rec_emit, f.counters + 1, p.capacity, rec_sorted, p.inv, s));
+        sorted_v = rec_sorted;
+    }
     {
         StageTimer t(MEGS_STAGE_RANGES, s);
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(f.ranges), 0u, 2 * L.n_tiles, s));
@@ -410,12 +429,31 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     state->last = f.last;
     state->device_status = f.status;
     state->internal = f.views;
+    state->det_inv = det ? p.inv : nullptr;
+    state->det_order = one_stage ? nullptr : f.order;
+    state->det_offsets = f.offs;
+    state->det_count = f.counters + 1;
     return MEGS_OK;
 }
 
+// Backward scratch: per-record 2D gradients [NR][9], the persistent-queue word, and in
+// deterministic mode the per-pair slots [P][9].
+size_t backward_bytes(const Layout& L, const megs_config* cfg, int64_t cap) {
+    size_t b = align256(sizeof(float) * 9 * (L.nr ? L.nr : 1)) + 256;
+    if (cfg->flags & MEGS_FLAG_DETERMINISTIC) b += align256(sizeof(float) * 9 * (cap > 0 ? cap : 1));
+    return b;
+}
+
 megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_config* cfg, const megs_state* st,
-                             const float* dl, float* grad2d, uint32_t* queue, const megs_scene_grad* gr,
-                             hipStream_t s) {
+                             const float* dl, void* scratch, const megs_scene_grad* gr, hipStream_t s) {
+    Carver c{static_cast<char*>(scratch), 0};
+    float* grad2d = c.take<float>(9 * L.nr);
+    uint32_t* queue = c.take<uint32_t>(4);
+    float* grad_pair = nullptr;
+    if (cfg->flags & MEGS_FLAG_DETERMINISTIC) {
+        if (!st->det_inv) return fail(MEGS_ERR_ARG, "deterministic backward needs a deterministic forward state");
+        grad_pair = c.take<float>(9 * st->pair_capacity);
+    }
     const bool persistent = cfg->flags & MEGS_FLAG_PERSISTENT;
     BlendArgs a;
     memset(&a, 0, sizeof(a));
@@ -432,11 +470,21 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     a.dl = dl;
     a.grad2d = grad2d;
     a.queue = queue;
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * L.nr, s));
+    a.grad_pair = grad_pair;
+    if (grad_pair)
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad_pair), 0u, 9 * st->pair_capacity, s));
+    else
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * L.nr, s));
     if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 1, s));
     {
         StageTimer t(MEGS_STAGE_BLEND_BWD, s);
         HIP_TRY(launch_blend_bwd(a, L.tile, waves_of(cfg), cfg->batch, persistent, s));
+        if (grad_pair)
+            HIP_TRY(launch_pair_reduce(static_cast<const uint32_t*>(st->det_order),
+                                       static_cast<const uint32_t*>(st->det_offsets),
+                                       static_cast<const uint32_t*>(st->ntiles), L.nr,
+                                       static_cast<const uint32_t*>(st->det_inv),
+                                       static_cast<const uint32_t*>(st->det_count), grad_pair, grad2d, s));
     }
     GradDev g;
     g.pos = gr->pos; g.logscale = gr->logscale; g.quat = gr->quat; g.op_logit = gr->op_logit;
@@ -489,9 +537,10 @@ megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t 
         counted = total;
         cap = total;
     }
-    void* pm = alloc(ctx, pairs_bytes(cap, one_stage));
-    if (!pm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", pairs_bytes(cap, one_stage));
-    Pairs p = carve_pairs(pm, cap, one_stage);
+    const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
+    void* pm = alloc(ctx, pairs_bytes(cap, one_stage, det));
+    if (!pm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", pairs_bytes(cap, one_stage, det));
+    Pairs p = carve_pairs(pm, cap, one_stage, det);
     st = enqueue_back(sc, L, cfg, f, p, images, state, s, importance);
     state->n_pairs = counted >= 0 ? counted : cap;
     return st;
@@ -562,12 +611,10 @@ megs_status megs_render_backward(const megs_scene* scene, const megs_camera* cam
     const Layout L = make_layout(scene, cams, n_views, cfg->tile);
     if (state->n_records != L.nr || state->n_views != n_views || state->tile != cfg->tile || !state->internal)
         return fail(MEGS_ERR_ARG, "state does not belong to this scene, view set and tile size");
-    const size_t gbytes = align256(sizeof(float) * 9 * (L.nr ? L.nr : 1)) + 256;
+    const size_t gbytes = backward_bytes(L, cfg, state->pair_capacity);
     void* gm = alloc(alloc_ctx, gbytes);
     if (!gm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", gbytes);
-    float* grad2d = static_cast<float*>(gm);
-    uint32_t* queue = reinterpret_cast<uint32_t*>(static_cast<char*>(gm) + gbytes - 256);
-    return enqueue_backward(scene, L, cfg, state, dl_dimages, grad2d, queue, grads, static_cast<hipStream_t>(stream));
+    return enqueue_backward(scene, L, cfg, state, dl_dimages, gm, grads, static_cast<hipStream_t>(stream));
 }
 
 megs_status megs_render_importance(const megs_scene* scene, const megs_camera* cams, int32_t n_views,
@@ -799,22 +846,21 @@ megs_status megs_graph_create(const megs_scene* scene, const megs_camera* cams, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Layout L = make_layout(scene, cams, n_views, cfg->tile);
     const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
     void* fm = alloc(alloc_ctx, frame_bytes(L));
-    void* pm = alloc(alloc_ctx, pairs_bytes(cfg->pair_capacity, one_stage));
-    const size_t gbytes = align256(sizeof(float) * 9 * (L.nr ? L.nr : 1)) + 256;
+    void* pm = alloc(alloc_ctx, pairs_bytes(cfg->pair_capacity, one_stage, det));
+    const size_t gbytes = backward_bytes(L, cfg, cfg->pair_capacity);
     void* gm = with_backward ? alloc(alloc_ctx, gbytes) : nullptr;
     if (!fm || !pm || (with_backward && !gm)) return fail(MEGS_ERR_ALLOC, "allocation failed");
     megs_graph* G = new (std::nothrow) megs_graph();
     if (!G) return fail(MEGS_ERR_ALLOC, "host allocation failed");
     Frame f = carve_frame(fm, L);
-    Pairs p = carve_pairs(pm, cfg->pair_capacity, one_stage);
+    Pairs p = carve_pairs(pm, cfg->pair_capacity, one_stage, det);
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { delete G; return fail(MEGS_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e)); }
     st = enqueue_front(scene, L, cfg, f, s);
     if (st == MEGS_OK) st = enqueue_back(scene, L, cfg, f, p, images, &G->state, s);
-    if (st == MEGS_OK && with_backward)
-        st = enqueue_backward(scene, L, cfg, &G->state, dl_dimages, static_cast<float*>(gm),
-                              reinterpret_cast<uint32_t*>(static_cast<char*>(gm) + gbytes - 256), grads, s);
+    if (st == MEGS_OK && with_backward) st = enqueue_backward(scene, L, cfg, &G->state, dl_dimages, gm, grads, s);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (st != MEGS_OK) { if (graph) (void)hipGraphDestroy(graph); delete G; return st; }

@@ -251,7 +251,10 @@ __device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
     v8 = z;
 }
 
-template <int TILE, int WAVES>
+// DET: instead of float atomics into the record's gradient, the tile's 9 sums for each list
+// position go to that position's own slot a.grad_pair[pos] (written by exactly one workgroup), and
+// a separate pass adds each record's slots in a fixed order: bit-reproducible gradients.
+template <int TILE, int WAVES, bool DET>
 __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch, int persistent) {
     constexpr int NT = 64 * WAVES, PPT = TILE * TILE / NT, ROWS = NT / TILE, WROWS = 64 / TILE;
     static_assert(PPT >= 1 && NT % TILE == 0, "tile and wave count mismatch");
@@ -356,6 +359,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                     if (!any_incl) continue;
                     float tot, tot8;
                     wave_sum9(acc, tot, tot8);
+                    if (DET) {
+                        float* slot = a.grad_pair + 9 * (int64_t)(end - 1 - jj);
+                        if ((lane & 7) == 0) slot[lane >> 3] = tot;
+                        if (lane == 1) slot[8] = tot8;
+                        continue;
+                    }
                     float* slot = a.grad2d + 9 * (int64_t)lds_id[jj];
                     if ((lane & 7) == 0) unsafeAtomicAdd(slot + (lane >> 3), tot);
                     if (lane == 1) unsafeAtomicAdd(slot + 8, tot8);
@@ -375,7 +384,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                     float sum = 0.f;
 #pragma unroll
                     for (int w = 0; w < WAVES; ++w) sum += lds_part[((int64_t)jj * WAVES + w) * 9 + comp];
-                    if (sum != 0.f) unsafeAtomicAdd(a.grad2d + 9 * (int64_t)lds_id[jj] + comp, sum);
+                    if (DET)
+                        a.grad_pair[9 * (int64_t)(end - 1 - jj) + comp] = sum;
+                    else if (sum != 0.f)
+                        unsafeAtomicAdd(a.grad2d + 9 * (int64_t)lds_id[jj] + comp, sum);
                 }
                 __syncthreads();
             }
@@ -410,8 +422,12 @@ hipError_t launch_bwd_t(const BlendArgs& a, int batch, bool persistent, hipStrea
     if (WAVES > 1) lds += (size_t)batch * WAVES * 9 * sizeof(float);
     const int64_t groups = persistent ? kPersistentGroups / WAVES : a.n_tiles;
     const unsigned grid = (unsigned)(groups < a.n_tiles ? groups : a.n_tiles);
-    hipLaunchKernelGGL((k_blend_bwd<TILE, WAVES>), dim3(grid), dim3(64 * WAVES), lds, stream, a, batch,
-                       (int)persistent);
+    if (a.grad_pair)
+        hipLaunchKernelGGL((k_blend_bwd<TILE, WAVES, true>), dim3(grid), dim3(64 * WAVES), lds, stream, a, batch,
+                           (int)persistent);
+    else
+        hipLaunchKernelGGL((k_blend_bwd<TILE, WAVES, false>), dim3(grid), dim3(64 * WAVES), lds, stream, a, batch,
+                           (int)persistent);
     return hipGetLastError();
 }
 

@@ -265,6 +265,7 @@ struct BlendArgs {
     uint32_t* last;
     const float* dl;      // backward only
     float* grad2d;        // backward only, [NR][9]
+    float* grad_pair;     // deterministic backward: per list position [P][9] (null: atomics into grad2d)
     uint32_t* queue;      // persistent mode work counter (null: one workgroup per tile)
     unsigned long long* stats;  // forward fragment counters [blended, evaluated] (null: not counted)
     float* importance;          // forward: per-Gaussian sum of blending weights (null: not computed)
@@ -272,6 +273,18 @@ struct BlendArgs {
 };
 hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream);
 hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream);
+
+// deterministic backward support (sort.hip)
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, int64_t count, hipStream_t stream);
+// perm[s] = emission position of sorted position s (s < *d_count): rec_sorted[s] = rec_emit[perm[s]],
+// inv[perm[s]] = s.
+hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* rec_emit, const uint32_t* d_count,
+                              int64_t max_count, uint32_t* rec_sorted, uint32_t* inv, hipStream_t stream);
+// grad2d[r] = sum over record r's pairs, in emission order, of grad_pair[inv[e]] (records walked in
+// the emission order `order`, or index order when null; offsets[i] = first emission position).
+hipError_t launch_pair_reduce(const uint32_t* order, const uint32_t* offsets, const uint32_t* ntiles,
+                              int64_t n_records, const uint32_t* inv, const uint32_t* d_count,
+                              const float* grad_pair, float* grad2d, hipStream_t stream);
 
 // post-processing compaction (compact.hip)
 struct CompactArgs {

@@ -388,6 +388,44 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     }
 }
 
+// ------------------------------------------------- deterministic backward support ----
+
+__global__ void k_copy_u32(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_perm_gather(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ rec_emit,
+                              const uint32_t* d_count, int64_t max_count, uint32_t* __restrict__ rec_sorted,
+                              uint32_t* __restrict__ inv) {
+    const int64_t count = min((int64_t)*d_count, max_count);
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < count; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = perm[s];
+        rec_sorted[s] = rec_emit[e];
+        inv[e] = (uint32_t)s;
+    }
+}
+
+__global__ void k_pair_reduce(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offsets,
+                              const uint32_t* __restrict__ ntiles, int64_t n_records, const uint32_t* __restrict__ inv,
+                              const uint32_t* d_count, const float* __restrict__ grad_pair, float* __restrict__ grad2d) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_records) return;
+    const uint32_t r = order ? order[i] : (uint32_t)i;
+    const int64_t count = *d_count;
+    const int64_t e0 = offsets[i];
+    int64_t e1 = e0 + ntiles[r];
+    if (e1 > count) e1 = count;
+    float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t e = e0; e < e1; ++e) {
+        const float* g = grad_pair + 9 * (int64_t)inv[e];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c] += g[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) grad2d[9 * (int64_t)r + c] = acc[c];
+}
+
 __global__ void k_clamp_count(const uint32_t* total, int64_t capacity, uint32_t* count, int32_t* status) {
     const uint32_t t = *total;
     *count = (int64_t)t > capacity ? (uint32_t)capacity : t;
@@ -491,6 +529,29 @@ hipError_t launch_ranges_u64(const uint64_t* keys, const uint32_t* d_count, int6
     if (max_count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(grid_for(max_count, 256)), dim3(256), 0, stream, keys, 32, d_count,
                        max_count, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, int64_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_u32, dim3(grid_for(count, 256)), dim3(256), 0, stream, dst, src, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* rec_emit, const uint32_t* d_count,
+                              int64_t max_count, uint32_t* rec_sorted, uint32_t* inv, hipStream_t stream) {
+    if (max_count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_perm_gather, dim3(grid_for(max_count, 256)), dim3(256), 0, stream, perm, rec_emit, d_count,
+                       max_count, rec_sorted, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_reduce(const uint32_t* order, const uint32_t* offsets, const uint32_t* ntiles,
+                              int64_t n_records, const uint32_t* inv, const uint32_t* d_count,
+                              const float* grad_pair, float* grad2d, hipStream_t stream) {
+    if (n_records <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)((n_records + 255) / 256)), dim3(256), 0, stream, order, offsets,
+                       ntiles, n_records, inv, d_count, grad_pair, grad2d);
     return hipGetLastError();
 }
 
