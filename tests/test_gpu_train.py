@@ -79,7 +79,9 @@ def test_adam_matches_oracle(dt):
         T.L.check(lib.megs_adam_step(n, p.data_ptr(), code, g.data_ptr(), m.data_ptr(), v.data_ptr(), 1e-2, 0.9,
                                      0.999, 1e-15, step, torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
-        new_p, ref_m, ref_v = O.adam_step(ref_p, g32, ref_m, ref_v, 1e-2, 0.9, 0.999, 1e-15, step)
+        # the kernel receives the hyperparameters as FP32 values; the oracle takes the same values
+        f = lambda x: float(np.float32(x))
+        new_p, ref_m, ref_v = O.adam_step(ref_p, g32, ref_m, ref_v, f(1e-2), f(0.9), f(0.999), f(1e-15), step)
         np.testing.assert_allclose(m.cpu().numpy(), ref_m, rtol=2e-6, atol=1e-9)
         np.testing.assert_allclose(v.cpu().numpy(), ref_v, rtol=2e-6, atol=1e-12)
         got = p.float().cpu().numpy().astype(np.float64)
