@@ -68,8 +68,7 @@ def test_adam_matches_oracle(dt):
     m = torch.zeros(n, device="cuda")
     v = torch.zeros(n, device="cuda")
     ref_p = S.widen(stored, dt).astype(np.float64)
-    ref_m = np.zeros(n)
-    ref_v = np.zeros(n)
+    m_host = v_host = None
     lib = T.L.load()
     code = {"f32": T.L.MEGS_F32, "f16": T.L.MEGS_F16, "bf16": T.L.MEGS_BF16}[dt]
     ulp = {"f32": 2.0 ** -23, "f16": 2.0 ** -10, "bf16": 2.0 ** -7}[dt]
@@ -81,9 +80,15 @@ def test_adam_matches_oracle(dt):
         torch.cuda.synchronize()
         # the kernel receives the hyperparameters as FP32 values; the oracle takes the same values
         f = lambda x: float(np.float32(x))
-        new_p, ref_m, ref_v = O.adam_step(ref_p, g32, ref_m, ref_v, f(1e-2), f(0.9), f(0.999), f(1e-15), step)
-        np.testing.assert_allclose(m.cpu().numpy(), ref_m, rtol=2e-6, atol=1e-9)
-        np.testing.assert_allclose(v.cpu().numpy(), ref_v, rtol=2e-6, atol=1e-12)
+        prev_m = m_host if step > 1 else np.zeros(n)
+        new_p, ref_m, ref_v = O.adam_step(ref_p, g32, prev_m, v_host if step > 1 else np.zeros(n), f(1e-2), f(0.9),
+                                          f(0.999), f(1e-15), step)
+        m_host = m.cpu().numpy().astype(np.float64)
+        v_host = v.cpu().numpy().astype(np.float64)
+        # FP32 rounding of a sum errs relative to its terms, which cancel where m crosses zero
+        m_terms = f(0.9) * np.abs(prev_m) + (1 - f(0.9)) * np.abs(g32)
+        assert np.all(np.abs(m_host - ref_m) <= 3e-7 * m_terms + 1e-30)
+        np.testing.assert_allclose(v_host, ref_v, rtol=1e-6, atol=1e-30)
         got = p.float().cpu().numpy().astype(np.float64)
         # one storage ulp for the final rounding plus FP32 rounding of the update
         assert np.all(np.abs(got - new_p) <= ulp * np.abs(new_p) + 1e-5 * 1e-2 + 1e-30)
