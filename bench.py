@@ -34,6 +34,27 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (packed); the unpacked FMA cei
 #   gradients, background recursion, summation over pixels): 58
 FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 58
 
+# HBM bytes per launch of a kernel on the headline workload, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a plain
+# copy of known size (--calibrate-copy). Each entry holds the SHA-256 of the kernel's source file
+# when the counters were taken; a changed source reports traffic as null.
+TRAFFIC = {}
+STAGE_SOURCE = {"project": "project.hip", "project_bwd": "project.hip", "blend_fwd": "blend.hip",
+                "blend_bwd": "blend.hip", "depth_sort": "sort.hip", "pair_sort": "sort.hip", "scan": "sort.hip",
+                "emit": "sort.hip", "ranges": "sort.hip"}
+
+
+def traffic_of(stage):
+    import hashlib
+    t = TRAFFIC.get(stage)
+    if not t:
+        return None
+    src = os.path.join(ROOT, "paper_2509_07021_amd", "csrc", STAGE_SOURCE[stage])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+            return None
+    return t["bytes"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -51,7 +72,7 @@ def parse():
     ap.add_argument("--waves", type=int, default=0, help="wave64s per tile workgroup (0: library default)")
     ap.add_argument("--autotune", action="store_true", help="pick tile/batch with the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=2, help="views of the workload the oracle renders")
+    ap.add_argument("--cpu-views", type=int, default=8, help="views of the workload the oracle renders")
     ap.add_argument("--no-post", action="store_true",
                     help="skip the post-processing and colour-model measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -338,14 +359,14 @@ def main():
                  else FLOP_TEST * replayed + FLOP_BWD_BLEND * blended)
         achieved = flops / (stage_ms[dominant] * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_of(dominant),
                 "units_per_launch": {"blended": blended, "evaluated": evaluated, "replayed": replayed},
                 "avg_ms": round(stage_ms[dominant], 4)}
     else:
         by = stage_bytes(dominant, scene.n, len(cams8), pairs8, npix8, nt8, geom_bytes, scene.k)
         achieved = by / (stage_ms[dominant] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_of(dominant),
                 "avg_ms": round(stage_ms[dominant], 4)}
     log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
 

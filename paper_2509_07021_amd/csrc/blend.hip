@@ -6,10 +6,11 @@
 // 1/255 skipped, stop before the transmittance would fall under 1e-4).
 //
 // Mapping to CDNA4: a workgroup of 1, 2 or 4 wave64s per (view, tile), TILE^2 / (64 waves) pixels
-// per lane; every LDS read of a staged Gaussian is reused by all of a lane's pixels, and a wave
-// skips a Gaussian that reaches none of its pixels. More waves per tile shorten the serial walk
-// of long tile lists (the latency of the densest tiles bounds a launch); one wave needs no
-// workgroup barrier at all. Gaussians of the tile's list are staged into LDS in batches
+// per lane, each wave owning a compact block of the tile (the whole tile, a half or a quadrant);
+// every LDS read of a staged Gaussian is reused by all of a lane's pixels, and a wave skips a
+// Gaussian whose footprint box misses its block or that reaches none of its pixels. More waves
+// per tile shorten the serial walk of long tile lists (the latency of the densest tiles bounds a
+// launch); one wave needs no workgroup barrier at all. Gaussians of the tile's list are staged into LDS in batches
 // (one record per lane per load, gathered through the sorted record indices); their means are
 // made tile-relative in FP64 while staging, so the per-fragment arithmetic works on small FP32
 // offsets. The wave stops as soon as all its pixels have terminated.
@@ -26,10 +27,26 @@ namespace megs {
 namespace {
 
 struct Staged {
+    float4 box; // tile-relative bounding box of the cutoff ellipse: x - rx, x + rx, y - ry, y + ry
     float4 p0;  // u_rel, v_rel, o, nb2   (nb2 = -b log2 e)
     float4 p1;  // na2, nc2, a, b        (na2 = -a log2 e / 2, nc2 = -c log2 e / 2)
     float4 p2;  // c, r, g, b
-    float2 yr;  // tile-relative rows [v - ry, v + ry] of the cutoff ellipse (ry = sqrt(k S_yy))
+};
+
+// Pixel layout of a (TILE, WAVES) workgroup: wave w owns a WW x WH block of the tile (the whole
+// tile, its upper/lower half, or one quadrant), its lanes cover LW x LH pixels per slot, and
+// pixel slot j of a lane lies LH j rows below slot 0. Compact blocks let a wave skip every staged
+// Gaussian whose footprint box misses its block, which is most of them for small footprints.
+template <int TILE, int WAVES>
+struct Layout {
+    static constexpr int WW = WAVES == 4 ? TILE / 2 : TILE;
+    static constexpr int WH = WAVES == 1 ? TILE : TILE / 2;
+    static constexpr int LW = WW;
+    static constexpr int LH = 64 / LW;
+    static constexpr int PPT = WW * WH / 64;
+    static_assert(LW * LH == 64 && PPT * 64 == WW * WH, "tile and wave count mismatch");
+    __device__ static int wx0(int wave) { return WAVES == 4 ? (wave & 1) * WW : 0; }
+    __device__ static int wy0(int wave) { return WAVES == 4 ? (wave >> 1) * WH : (WAVES == 2 ? wave * WH : 0); }
 };
 
 __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0, double y0, Staged* dst) {
@@ -37,23 +54,26 @@ __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0,
     const float4 co = a.conic_o[g];
     const float4 cd = a.rgbd[g];
     Staged s;
-    const float vr = (float)(m.y - y0);
-    s.p0 = make_float4((float)(m.x - x0), vr, co.w, -co.y * kLog2e);
+    const float ur = (float)(m.x - x0), vr = (float)(m.y - y0);
+    s.p0 = make_float4(ur, vr, co.w, -co.y * kLog2e);
     s.p1 = make_float4(-0.5f * co.x * kLog2e, -0.5f * co.z * kLog2e, co.x, co.y);
     s.p2 = make_float4(co.z, cd.x, cd.y, cd.z);
-    // every pixel with alpha >= 1/255 lies in the cutoff ellipse, whose rows span v -/+ sqrt(k S_yy),
-    // S_yy = a / (a c - b^2). The determinant is taken in FP64 (the products of FP32 values are
-    // exact there), so thin ellipses keep their extent; widened by 1e-3 relative and 1e-2 px.
+    // every pixel with alpha >= 1/255 lies in the cutoff ellipse, whose extents are
+    // u -/+ sqrt(k S_xx) and v -/+ sqrt(k S_yy), S_xx = c / (a c - b^2), S_yy = a / (a c - b^2).
+    // The determinant is taken in FP64 (the products of FP32 values are exact there), so thin
+    // ellipses keep their extent; widened by 1e-3 relative and 1e-2 px.
     const double det = (double)co.x * co.z - (double)co.y * co.y;
-    const float ry = det > 0.0 ? (float)sqrt((double)a.cutoff[g] * co.x / det) * 1.001f + 0.01f : 1e30f;
-    s.yr = make_float2(vr - ry, vr + ry);
+    const double k = a.cutoff[g];
+    const float rx = det > 0.0 ? (float)sqrt(k * co.z / det) * 1.001f + 0.01f : 1e30f;
+    const float ry = det > 0.0 ? (float)sqrt(k * co.x / det) * 1.001f + 0.01f : 1e30f;
+    s.box = make_float4(ur - rx, ur + rx, vr - ry, vr + ry);
     *dst = s;
 }
 
-// Does the row band [r0, r1] (tile-relative pixel rows, centres at +0.5) meet the staged
-// footprint's rows? Wave-uniform when the band is.
-__device__ __forceinline__ bool rows_meet(const Staged& s, int r0, int r1) {
-    return (r0 + 0.5f <= s.yr.y) & (r1 + 0.5f >= s.yr.x);
+// Does the pixel block [x0, x1] x [y0, y1] (tile-relative, centres at +0.5) meet the staged
+// footprint's box? Wave-uniform when the block is.
+__device__ __forceinline__ bool box_meets(const float4& b, int x0, int x1, int y0, int y1) {
+    return (x0 + 0.5f <= b.y) & (x1 + 0.5f >= b.x) & (y0 + 0.5f <= b.w) & (y1 + 0.5f >= b.z);
 }
 
 // Alpha test of one fragment (no branches): pass = (q <= 0 and alpha >= 1/255). The forward and
@@ -104,18 +124,18 @@ __device__ __forceinline__ int64_t next_tile(const BlendArgs& a, int64_t prev, b
     return (int64_t)*slot;
 }
 
-// Workgroup of WAVES wave64s per tile, PPT = TILE^2 / (64 WAVES) pixels per lane. Pixel j of
-// thread t is (t % TILE, t / TILE + (64 WAVES / TILE) j), so each wave owns whole pixel rows.
+// Workgroup of WAVES wave64s per tile, PPT = TILE^2 / (64 WAVES) pixels per lane, each wave owning
+// one compact block of the tile (Layout).
 template <int TILE, int WAVES, bool STATS, bool IMP>
 __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch, int persistent) {
-    constexpr int NT = 64 * WAVES, PPT = TILE * TILE / NT, ROWS = NT / TILE, WROWS = 64 / TILE;
-    static_assert(PPT >= 1 && NT % TILE == 0, "tile and wave count mismatch");
+    using Ly = Layout<TILE, WAVES>;
+    constexpr int NT = 64 * WAVES, PPT = Ly::PPT, LH = Ly::LH;
     extern __shared__ Staged lds[];
     uint32_t* lds_id = reinterpret_cast<uint32_t*>(lds + batch);  // record ids (importance only)
     __shared__ uint32_t work_slot;
-    const int tid = threadIdx.x, lane = __lane_id();
-    const int lx = tid % TILE, ly = tid / TILE;
-    const int wrow0 = (tid / 64) * WROWS;  // first row of this wave in pixel slot 0
+    const int tid = threadIdx.x, lane = __lane_id(), wv = tid / 64;
+    const int bx0 = Ly::wx0(wv), by0 = Ly::wy0(wv);   // this wave's block
+    const int lx = bx0 + lane % Ly::LW, ly = by0 + lane / Ly::LW;
     uint32_t n_blended = 0, n_evaluated = 0;
     for (int64_t t = next_tile(a, -1, persistent, &work_slot); t < a.n_tiles;
          t = next_tile(a, t, persistent, &work_slot)) {
@@ -128,7 +148,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch
         bool mine = false;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            T[j] = (c.x0 + lx < c.width && c.y0 + ly + ROWS * j < c.height) ? 1.0f : -1.0f;
+            T[j] = (c.x0 + lx < c.width && c.y0 + ly + LH * j < c.height) ? 1.0f : -1.0f;
             C[j][0] = C[j][1] = C[j][2] = 0.0f;
             last[j] = 0;
             mine |= T[j] > 0.0f;
@@ -145,6 +165,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch
             }
             __syncthreads();
             for (int jj = 0; jj < cnt && __any(mine); ++jj) {
+                const float4 box = lds[jj].box;
+                // wave-uniform: skip a Gaussian whose footprint box misses this wave's block
+                if (!box_meets(box, bx0, bx0 + Ly::WW - 1, by0, by0 + Ly::WH - 1)) continue;
                 const Staged s = lds[jj];
                 const uint32_t pos = base + jj - rg.x;
                 float alpha[PPT];
@@ -154,11 +177,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch
                 for (int j = 0; j < PPT; ++j) {
                     pass[j] = false;
                     alpha[j] = 0.0f;
-                    // this wave's rows of pixel slot j; skip the slot when the footprint misses them
-                    if (!rows_meet(s, wrow0 + ROWS * j, wrow0 + ROWS * j + WROWS - 1)) continue;
+                    // this wave's pixel rows of slot j; skip the slot when the footprint misses them
+                    if (PPT > 1 && !box_meets(box, bx0, bx0 + Ly::WW - 1, by0 + LH * j, by0 + LH * j + LH - 1))
+                        continue;
                     float dx, dy, G;
                     bool clamped;
-                    pass[j] = frag(s, px, ly + ROWS * j + 0.5f, dx, dy, G, alpha[j], clamped) & (T[j] > 0.0f);
+                    pass[j] = frag(s, px, ly + LH * j + 0.5f, dx, dy, G, alpha[j], clamped) & (T[j] > 0.0f);
                     any_pass |= pass[j];
                     if (STATS) n_evaluated += T[j] > 0.0f;
                 }
@@ -192,7 +216,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch
         }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            const int x = c.x0 + lx, y = c.y0 + ly + ROWS * j;
+            const int x = c.x0 + lx, y = c.y0 + ly + LH * j;
             if (x >= c.width || y >= c.height) continue;
             const int64_t p = (int64_t)y * c.width + x;
             const int64_t plane = (int64_t)c.width * c.height;
@@ -256,16 +280,16 @@ __device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
 // a separate pass adds each record's slots in a fixed order: bit-reproducible gradients.
 template <int TILE, int WAVES, bool DET>
 __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch, int persistent) {
-    constexpr int NT = 64 * WAVES, PPT = TILE * TILE / NT, ROWS = NT / TILE, WROWS = 64 / TILE;
-    static_assert(PPT >= 1 && NT % TILE == 0, "tile and wave count mismatch");
+    using Ly = Layout<TILE, WAVES>;
+    constexpr int NT = 64 * WAVES, PPT = Ly::PPT, LH = Ly::LH;
     extern __shared__ Staged lds[];
     uint32_t* lds_id = reinterpret_cast<uint32_t*>(lds + batch);
     float* lds_part = reinterpret_cast<float*>(lds_id + batch);  // [batch][WAVES][9] (WAVES > 1)
     __shared__ uint32_t work_slot;
     __shared__ uint32_t red_slot[WAVES];
     const int tid = threadIdx.x, lane = __lane_id(), wv = tid / 64;
-    const int lx = tid % TILE, ly = tid / TILE;
-    const int wrow0 = wv * WROWS;  // first row of this wave in pixel slot 0
+    const int bx0 = Ly::wx0(wv), by0 = Ly::wy0(wv);   // this wave's block
+    const int lx = bx0 + lane % Ly::LW, ly = by0 + lane / Ly::LW;
     const float px = lx + 0.5f;
     for (int64_t t = next_tile(a, -1, persistent, &work_slot); t < a.n_tiles;
          t = next_tile(a, t, persistent, &work_slot)) {
@@ -277,7 +301,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
         uint32_t maxlast = 0;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            const int x = c.x0 + lx, y = c.y0 + ly + ROWS * j;
+            const int x = c.x0 + lx, y = c.y0 + ly + LH * j;
             const bool inside = x < c.width && y < c.height;
             const int64_t p = (int64_t)y * c.width + x;
             T[j] = inside ? a.T_final[c.pix_off + p] : 1.0f;
@@ -313,7 +337,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                 float acc[9];
 #pragma unroll
                 for (int i = 0; i < 9; ++i) acc[i] = 0.f;
-                if (pos < wave_last) {  // wave-uniform: positions past every pixel's last are skipped
+                // wave-uniform: positions past every pixel's last, and Gaussians whose footprint
+                // box misses this wave's block, are skipped
+                if (pos < wave_last && box_meets(lds[jj].box, bx0, bx0 + Ly::WW - 1, by0, by0 + Ly::WH - 1)) {
                     const Staged s = lds[jj];
                     float alpha[PPT], G[PPT], dxs[PPT], dys[PPT];
                     bool incl[PPT], clamped[PPT];
@@ -321,8 +347,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                     for (int j = 0; j < PPT; ++j) {
                         incl[j] = false;
                         alpha[j] = 0.0f; G[j] = 0.0f; dxs[j] = 0.0f; dys[j] = 0.0f; clamped[j] = false;
-                        if (!rows_meet(s, wrow0 + ROWS * j, wrow0 + ROWS * j + WROWS - 1)) continue;
-                        incl[j] = frag(s, px, ly + ROWS * j + 0.5f, dxs[j], dys[j], G[j], alpha[j], clamped[j]) &
+                        if (PPT > 1 &&
+                            !box_meets(s.box, bx0, bx0 + Ly::WW - 1, by0 + LH * j, by0 + LH * j + LH - 1))
+                            continue;
+                        incl[j] = frag(s, px, ly + LH * j + 0.5f, dxs[j], dys[j], G[j], alpha[j], clamped[j]) &
                                   (pos < lst[j]);
                         any_incl |= incl[j];
                     }
