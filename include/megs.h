@@ -170,6 +170,11 @@ typedef struct {
      * MEGS_FLAG_DETERMINISTIC), records in emission order (NULL: index order), the records'
      * first emission positions, and the pair count */
     const void *det_inv, *det_order, *det_offsets, *det_count;
+    /* the records again, one 64-byte line each (read by the key emission and the blend, which
+     * gather records in depth and tile order): double mean[2]; float conic a, b, c, o_eff;
+     * float r, g, b, cutoff k; int32 radius; uint32 ntiles; float rx, ry, the widened half-extents
+     * of the ellipse {d' conic d <= k} */
+    const void *packed;
 } megs_state;
 
 /* Per-view image layout: images are concatenated, view v's float[3][H][W] planes starting at

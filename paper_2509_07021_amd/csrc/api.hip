@@ -223,6 +223,7 @@ struct Frame {
 size_t frame_bytes(const Layout& L) {
     size_t b = 0;
     b += align256(sizeof(ViewInfo) * L.nv);
+    b += align256(sizeof(PackedRec) * (L.nr ? L.nr : 1));
     b += align256(sizeof(double2) * (L.nr ? L.nr : 1));
     b += 2 * align256(sizeof(float4) * (L.nr ? L.nr : 1));
     b += 8 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
@@ -238,6 +239,7 @@ Frame carve_frame(void* mem, const Layout& L) {
     Carver c{static_cast<char*>(mem), 0};
     Frame f;
     f.views = c.take<ViewInfo>(L.nv);
+    f.rec.packed = c.take<PackedRec>(L.nr);
     f.rec.mean = c.take<double2>(L.nr);
     f.rec.conic_o = c.take<float4>(L.nr);
     f.rec.rgbd = c.take<float4>(L.nr);
@@ -395,7 +397,7 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     BlendArgs a;
     memset(&a, 0, sizeof(a));
     a.views = f.views; a.nv = L.nv; a.n_tiles = L.n_tiles;
-    a.mean = f.rec.mean; a.conic_o = f.rec.conic_o; a.rgbd = f.rec.rgbd; a.cutoff = f.rec.cutoff;
+    a.rec = f.rec.packed;
     a.vals = sorted_v; a.ranges = f.ranges;
     a.image = images; a.T_final = f.T_final; a.last = f.last;
     a.queue = f.queue;
@@ -421,6 +423,7 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     state->radius = f.rec.radius;
     state->ntiles = f.rec.ntiles;
     state->cutoff = f.rec.cutoff;
+    state->packed = f.rec.packed;
     state->tile_keys = sorted_t;
     state->keys64 = sorted_k;
     state->vals = sorted_v;
@@ -459,10 +462,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     memset(&a, 0, sizeof(a));
     a.views = static_cast<const ViewInfo*>(st->internal);
     a.nv = L.nv; a.n_tiles = L.n_tiles;
-    a.mean = static_cast<const double2*>(st->mean);
-    a.conic_o = static_cast<const float4*>(st->conic_o);
-    a.rgbd = static_cast<const float4*>(st->rgbd);
-    a.cutoff = static_cast<const float*>(st->cutoff);
+    a.rec = static_cast<const PackedRec*>(st->packed);
     a.vals = static_cast<const uint32_t*>(st->vals);
     a.ranges = static_cast<const uint2*>(st->ranges);
     a.T_final = const_cast<float*>(static_cast<const float*>(st->T_final));

@@ -50,23 +50,16 @@ struct Layout {
 };
 
 __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0, double y0, Staged* dst) {
-    const double2 m = a.mean[g];
-    const float4 co = a.conic_o[g];
-    const float4 cd = a.rgbd[g];
+    const float4* q = reinterpret_cast<const float4*>(a.rec + g);  // the record's 64-byte line
+    const float4 q0 = q[0], co = q[1], cd = q[2], q3 = q[3];
+    const double mx = __hiloint2double(__float_as_int(q0.y), __float_as_int(q0.x));
+    const double my = __hiloint2double(__float_as_int(q0.w), __float_as_int(q0.z));
     Staged s;
-    const float ur = (float)(m.x - x0), vr = (float)(m.y - y0);
+    const float ur = (float)(mx - x0), vr = (float)(my - y0);
     s.p0 = make_float4(ur, vr, co.w, -co.y * kLog2e);
     s.p1 = make_float4(-0.5f * co.x * kLog2e, -0.5f * co.z * kLog2e, co.x, co.y);
     s.p2 = make_float4(co.z, cd.x, cd.y, cd.z);
-    // every pixel with alpha >= 1/255 lies in the cutoff ellipse, whose extents are
-    // u -/+ sqrt(k S_xx) and v -/+ sqrt(k S_yy), S_xx = c / (a c - b^2), S_yy = a / (a c - b^2).
-    // The determinant is taken in FP64 (the products of FP32 values are exact there), so thin
-    // ellipses keep their extent; widened by 1e-3 relative and 1e-2 px.
-    const double det = (double)co.x * co.z - (double)co.y * co.y;
-    const double k = a.cutoff[g];
-    const float rx = det > 0.0 ? (float)sqrt(k * co.z / det) * 1.001f + 0.01f : 1e30f;
-    const float ry = det > 0.0 ? (float)sqrt(k * co.x / det) * 1.001f + 0.01f : 1e30f;
-    s.box = make_float4(ur - rx, ur + rx, vr - ry, vr + ry);
+    s.box = make_float4(ur - q3.z, ur + q3.z, vr - q3.w, vr + q3.w);
     *dst = s;
 }
 
@@ -164,7 +157,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch
                 if (IMP) lds_id[q] = g;
             }
             __syncthreads();
-            for (int jj = 0; jj < cnt && __any(mine); ++jj) {
+            for (int jj = 0; jj < cnt; ++jj) {
+                // the wave stops once all its pixels have terminated; checked every 4 Gaussians
+                // (a terminated pixel has T < 0 and takes no further fragment in between)
+                if ((jj & 3) == 0 && !__any(mine)) break;
                 const float4 box = lds[jj].box;
                 // wave-uniform: skip a Gaussian whose footprint box misses this wave's block
                 if (!box_meets(box, bx0, bx0 + Ly::WW - 1, by0, by0 + Ly::WH - 1)) continue;
@@ -243,36 +239,63 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch
     }
 }
 
-// Sum of v[0..8] over the wave. Afterwards lane 8m (m < 8) holds the total of v[m] and every
-// lane holds the total of v[8] in v8.
+// Cross-lane helpers on gfx950 VALU data paths (no LDS traffic). swap32(a, b): lanes 32-63 of a
+// trade places with lanes 0-31 of b; swap16 does the same between odd and even 16-lane rows of each
+// half. mirror16 / mirror8: the value of lane 15 - i (i - 8 ... ) within each 16- / 8-lane group.
+__device__ __forceinline__ void swap32(float& a, float& b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(float& a, float& b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), CTRL, 0xf, 0xf, false));
+}
+constexpr int kQuadXor1 = 0xb1, kQuadXor2 = 0x4e, kRowMirror = 0x140, kRowHalfMirror = 0x141;
+
+// Sum over one 8-lane group (every lane of the group ends with the total).
+__device__ __forceinline__ float sum8(float y) {
+    y += dpp<kQuadXor1>(y);
+    y += dpp<kQuadXor2>(y);
+    y += dpp<kRowHalfMirror>(y);
+    return y;
+}
+
+// Sum of v[0..8] over the wave: a transposed butterfly. After the swaps, lane group (b5 b4 b3) of
+// the lane index holds partial sums of v[4 b5 + 2 b4 + b3] only; the last three steps finish
+// them within each 8-lane group. Afterwards every lane of group m (lanes 8m..8m+7) holds the total
+// of v[m] in out, and every lane holds the total of v[8] in v8.
 __device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
     const int lane = __lane_id();
     float w4[4];
-    const bool b5 = lane & 32;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float send = b5 ? v[i] : v[i + 4];
-        const float keep = b5 ? v[i + 4] : v[i];
-        w4[i] = keep + __shfl_xor(send, 32);
+    for (int i = 0; i < 4; ++i) {  // lanes < 32 gather v[i] pairs, lanes >= 32 v[i + 4] pairs
+        float a = v[i], b = v[i + 4];
+        swap32(a, b);
+        w4[i] = a + b;
     }
     float w2[2];
-    const bool b4 = lane & 16;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float send = b4 ? w4[i] : w4[i + 2];
-        const float keep = b4 ? w4[i + 2] : w4[i];
-        w2[i] = keep + __shfl_xor(send, 16);
+    for (int i = 0; i < 2; ++i) {  // even rows keep w4[i], odd rows w4[i + 2]
+        float a = w4[i], b = w4[i + 2];
+        swap16(a, b);
+        w2[i] = a + b;
     }
-    const bool b3 = lane & 8;
-    float y = (b3 ? w2[1] : w2[0]) + __shfl_xor(b3 ? w2[0] : w2[1], 8);
-    y += __shfl_xor(y, 4);
-    y += __shfl_xor(y, 2);
-    y += __shfl_xor(y, 1);
-    out = y;
-    float z = v[8];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) z += __shfl_xor(z, d);
-    v8 = z;
+    const bool b3 = lane & 8;      // lanes 0-7 of a row pair with lanes 15..8 through the mirror
+    const float y = (b3 ? w2[1] : w2[0]) + dpp<kRowMirror>(b3 ? w2[0] : w2[1]);
+    out = sum8(y);
+    float z = v[8], z2 = v[8];
+    swap32(z, z2);
+    z += z2;
+    z2 = z;
+    swap16(z, z2);
+    z += z2;
+    v8 = sum8(z + dpp<kRowMirror>(z));
 }
 
 // DET: instead of float atomics into the record's gradient, the tile's 9 sums for each list

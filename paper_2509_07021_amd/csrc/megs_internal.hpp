@@ -57,8 +57,21 @@ struct GradDev {
     float* sh;
 };
 
+// One record in a single 64-byte line, for the consumers that gather records in depth or tile
+// order (key emission, blend staging): one line per gathered record instead of one per plane.
+struct __align__(64) PackedRec {
+    double2 mean;     // pixel-space mean
+    float4 conic_o;   // conic a, b, c and effective opacity
+    float4 rgbk;      // colour and the cutoff level k of the footprint ellipse
+    int32_t radius;   // -1 when culled
+    uint32_t ntiles;
+    float rx, ry;     // half-extents of the cutoff ellipse in x and y (widened; see the projection)
+};
+static_assert(sizeof(PackedRec) == 64, "one record per 64-byte line");
+
 // Record planes written by the projection (record r = view * n + i).
 struct Records {
+    PackedRec* packed;  // the same records, one line each
     double2* mean;      // pixel-space mean
     float4* conic_o;    // conic a, b, c and effective opacity
     float4* rgbd;       // colour and camera depth
@@ -254,10 +267,7 @@ struct BlendArgs {
     const ViewInfo* views;
     int nv;
     int64_t n_tiles;
-    const double2* mean;
-    const float4* conic_o;
-    const float4* rgbd;
-    const float* cutoff;  // per-record cutoff level of the footprint ellipse
+    const PackedRec* rec;  // the projection's records, one line each
     const uint32_t* vals;
     const uint2* ranges;
     float* image;

@@ -336,6 +336,31 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
             rec.cutoff[r] = 0.f;
         }
         rec.ntiles[r] = nt;
+        {
+            // packed copy; the half-extents of the cutoff ellipse {q <= k} are sqrt(k S_xx) and
+            // sqrt(k S_yy) with S_xx = c / (a c - b^2), S_yy = a / (a c - b^2), the FP32 conic's
+            // determinant taken in FP64 (products of FP32 values are exact there) so thin ellipses keep
+            // their extent, widened by 1e-3 relative and 1e-2 px: every pixel with alpha >= 1/255
+            // lies inside the box
+            float rx = 0.f, ry = 0.f;
+            if (ok) {
+                const double det = (double)p.conic[0] * p.conic[2] - (double)p.conic[1] * p.conic[1];
+                const double k = cutoff_of(g.o_eff);
+                rx = det > 0.0 ? (float)sqrt(k * p.conic[2] / det) * 1.001f + 0.01f : 1e30f;
+                ry = det > 0.0 ? (float)sqrt(k * p.conic[0] / det) * 1.001f + 0.01f : 1e30f;
+            }
+            PackedRec pr;
+            pr.mean = ok ? make_double2(p.u, p.v) : make_double2(0.0, 0.0);
+            pr.conic_o = ok ? make_float4(p.conic[0], p.conic[1], p.conic[2], g.o_eff) : make_float4(0.f, 0.f, 0.f, 0.f);
+            pr.rgbk = ok ? make_float4(rgb[0], rgb[1], rgb[2], cutoff_of(g.o_eff)) : make_float4(0.f, 0.f, 0.f, 0.f);
+            pr.radius = ok ? p.radius : -1;
+            pr.ntiles = nt;
+            pr.rx = rx;
+            pr.ry = ry;
+            float4* dst = reinterpret_cast<float4*>(rec.packed + r);
+            const float4* src = reinterpret_cast<const float4*>(&pr);
+            dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];
+        }
         rec.dkey[r] = nt ? __float_as_uint(p.tzf) : 0xffffffffu;
     }
 }

@@ -340,7 +340,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     const int64_t k_last = min((int64_t)(blockIdx.x + 1) * kEmitThreads, n_records) - 1;
     const bool has = k < n_records;
     const uint32_t g = has ? (order ? order[k] : (uint32_t)k) : 0u;
-    const uint32_t nt = has ? rec.ntiles[g] : 0u;
+    // the record's 64-byte line: mean, conic, colour + cutoff, radius / ntiles / half-extents
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
+    if (has) {
+        const float4* q = reinterpret_cast<const float4*>(rec.packed + g);
+        q0 = q[0]; q1 = q[1]; q2 = q[2]; q3 = q[3];
+    }
+    const uint32_t nt = has ? __float_as_uint(q3.y) : 0u;
     const int64_t off = has ? (int64_t)offsets[k] : 0;
     if (k == k_last) {
         range[0] = offsets[(int64_t)blockIdx.x * kEmitThreads];
@@ -355,10 +361,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     const ViewInfo* vw = nullptr;
     if (nt) {
         vw = &views[g / n];
-        const double2 m = rec.mean[g];
-        const float4 co = rec.conic_o[g];
-        tile_rect(m.x, m.y, rec.radius[g], *vw, tile, x0, x1, y0, y1);
-        ellipse_rows(m.x, m.y, co.x, co.y, co.z, rec.cutoff[g], er);
+        const double mx = __hiloint2double(__float_as_int(q0.y), __float_as_int(q0.x));
+        const double my = __hiloint2double(__float_as_int(q0.w), __float_as_int(q0.z));
+        tile_rect(mx, my, __float_as_int(q3.x), *vw, tile, x0, x1, y0, y1);
+        ellipse_rows(mx, my, q1.x, q1.y, q1.z, q2.w, er);
     }
     for (int64_t w0 = lo; w0 < hi; w0 += kEmitWindow) {
         const int64_t w1 = w0 + kEmitWindow < hi ? w0 + kEmitWindow : hi;
