@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--waves", type=int, default=0, help="wave64s per tile workgroup (0: library default)")
+    ap.add_argument("--subtile", type=int, default=0, help="8: blend per 8x8 sub-tile (16x16 / 32x32 tiles)")
     ap.add_argument("--autotune", action="store_true", help="pick tile/batch with the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=8, help="views of the workload the oracle renders")
@@ -99,7 +100,7 @@ def fragment_counts(R, ds, cams, cfg):
     """(blended, evaluated, replayed) fragments of one forward, counted by the stats instance."""
     import torch
     from paper_2509_07021_amd import _lib as L
-    c = R.Config(cfg.tile, cfg.batch, cfg.flags | L.MEGS_FLAG_STATS, 0, cfg.waves)
+    c = R.Config(cfg.tile, cfg.batch, cfg.flags | L.MEGS_FLAG_STATS, 0, cfg.waves, cfg.subtile)
     fr = R.forward(ds, cams, c)
     torch.cuda.synchronize()
     st = fr.buffer("device_status", 8, torch.int32).cpu().numpy()
@@ -272,7 +273,7 @@ def main():
     scene16 = scene.stored("f16", "f16", "bf16")
     cams8 = S.ring_cameras(args.views, seed=5)
     log(f"scenes ready in {time.perf_counter() - t_start:.1f}s: n={scene.n} k={scene.k}")
-    cfg = R.Config(args.tile, args.batch, waves=args.waves)
+    cfg = R.Config(args.tile, args.batch, waves=args.waves, subtile=args.subtile)
 
     # ---------------------------------------------------------------- plain FP32, 1 view
     ds = R.DeviceScene.from_scene(scene)
@@ -314,7 +315,7 @@ def main():
     del fr
     torch.cuda.empty_cache()
     cap = int(pairs8 * 1.02) + 4096
-    gcfg = R.Config(cfg.tile, cfg.batch, cfg.flags, cap, cfg.waves)
+    gcfg = R.Config(cfg.tile, cfg.batch, cfg.flags, cap, cfg.waves, cfg.subtile)
     torch.cuda.synchronize()
     before = torch.cuda.memory_allocated()
     torch.cuda.reset_peak_memory_stats()
@@ -386,7 +387,8 @@ def main():
         "config": {"workload": (f"{scene.n} clustered Gaussians, {scene.k} SG lobes, soft masks, FP16 storage "
                                 f"(BF16 amplitudes), {len(cams8)} views 1920x1080, forward+backward in one hipGraph"),
                    "gaussians": scene.n, "views": len(cams8), "resolution": "1920x1080", "tile": cfg.tile,
-                   "batch": cfg.batch, "waves": cfg.waves, "storage": "f16/f16/bf16", "pairs": pairs8},
+                   "batch": cfg.batch, "waves": cfg.waves, "subtile": cfg.subtile, "storage": "f16/f16/bf16",
+                   "pairs": pairs8},
         "peak_vram_mb": {"forward": round(batched_fwd_peak / 1e6, 1), "forward_backward": round(batched_fb_peak / 1e6, 1),
                          "static_params": round(static16 / 1e6, 1)},
         "plain_fp32": {"value": round(npix1 / ms_plain / 1e3, 2), "unit": "Mpixel/s", "ms_per_step": round(ms_plain, 4),

@@ -133,6 +133,11 @@ typedef struct {
     int64_t pair_capacity; /* 0: size the pair table from the counted pairs (one host sync per
                               forward); > 0: fixed capacity, no host sync, overflow reported
                               as MEGS_ERR_CAPACITY by megs_state_status */
+    int32_t subtile;       /* 0: blend per tile (waves as above); 8: blend per 8x8 sub-tile with one
+                              independent wave each, walking its 16x16 or 32x32 tile's list, so the
+                              key table keeps the tile's size (the deterministic backward keeps the
+                              per-tile kernel) */
+    int32_t reserved;
 } megs_config;
 
 /* Allocation callback: returns device memory of at least `bytes` bytes, 256-byte aligned,
@@ -224,13 +229,14 @@ const megs_state *megs_graph_state(const megs_graph *graph);
 void megs_graph_destroy(megs_graph *graph);
 
 /*
- * Autotuner: times forward+backward for every (tile, waves) in {(8,1), (16,1), (16,2), (16,4),
- * (32,1), (32,2), (32,4)} x batch in {32, 64, 128, 256} on the given views (1 warm-up and `reps`
- * timed runs each, HIP events on `stream`) and writes the fastest configuration to *best (flags
- * and pair_capacity copied from *base). Images are independent of the choice up to FP32 rounding
- * (the footprint lies inside the listed tiles), so the choice changes speed only. ms_out
- * (nullable) receives MEGS_AUTOTUNE_CANDIDATES timings in that order, batch fastest-varying. */
-#define MEGS_AUTOTUNE_CANDIDATES 28
+ * Autotuner: times forward+backward for every (tile, waves, subtile) in {(8,1,0), (16,1,0),
+ * (16,2,0), (16,4,0), (32,1,0), (32,2,0), (32,4,0), (16,1,8), (32,1,8)} x batch in
+ * {32, 64, 128, 256} on the given views (1 warm-up and `reps` timed runs each, HIP events on
+ * `stream`) and writes the fastest configuration to *best (flags and pair_capacity copied from
+ * *base). Images are independent of the choice up to FP32 rounding (the footprint lies inside the
+ * listed tiles), so the choice changes speed only. ms_out (nullable) receives
+ * MEGS_AUTOTUNE_CANDIDATES timings in that order, batch fastest-varying. */
+#define MEGS_AUTOTUNE_CANDIDATES 36
 megs_status megs_autotune(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
                           const megs_config *base, megs_alloc_fn alloc, void *alloc_ctx,
                           float *images, const float *dl_dimages, megs_scene_grad *grads,

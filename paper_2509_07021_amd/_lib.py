@@ -20,7 +20,8 @@ MEGS_FLAG_DETERMINISTIC = 8
 STAGES = ("project", "depth_sort", "scan", "emit", "pair_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd")
 MEGS_MAX_LOBES = 8
 MEGS_MAX_VIEWS = 64
-AUTOTUNE_COMBOS = ((8, 1), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4))
+AUTOTUNE_COMBOS = ((8, 1, 0), (16, 1, 0), (16, 2, 0), (16, 4, 0), (32, 1, 0), (32, 2, 0), (32, 4, 0), (16, 1, 8),
+                   (32, 1, 8))   # (tile, waves, subtile)
 AUTOTUNE_BATCHES = (32, 64, 128, 256)
 
 EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", "megs_graph_create",
@@ -60,7 +61,8 @@ class MegsCamera(ctypes.Structure):
 
 class MegsConfig(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("waves", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
+                ("waves", ctypes.c_int32), ("pair_capacity", ctypes.c_int64), ("subtile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class MegsState(ctypes.Structure):

@@ -142,6 +142,8 @@ megs_status check_args(const megs_scene* sc, const megs_camera* cams, int32_t nv
     if (cfg->waves != 0 && cfg->waves != 1 && cfg->waves != 2 && cfg->waves != 4)
         return fail(MEGS_ERR_ARG, "waves = %d not in {0, 1, 2, 4}", cfg->waves);
     if (cfg->tile == 8 && cfg->waves > 1) return fail(MEGS_ERR_ARG, "8x8 tiles take one wave");
+    if (cfg->subtile != 0 && cfg->subtile != 8) return fail(MEGS_ERR_ARG, "subtile = %d not in {0, 8}", cfg->subtile);
+    if (cfg->subtile == 8 && cfg->tile == 8) return fail(MEGS_ERR_ARG, "subtile 8 needs 16x16 or 32x32 tiles");
     if (cfg->flags & ~(uint32_t)(MEGS_FLAG_ONE_STAGE_SORT | MEGS_FLAG_PERSISTENT | MEGS_FLAG_STATS |
                                  MEGS_FLAG_DETERMINISTIC))
         return fail(MEGS_ERR_ARG, "unknown flags 0x%x", cfg->flags);
@@ -407,7 +409,7 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     if (persistent) HIP_TRY(launch_fill_u32(f.queue, 0u, 4, s));
     {
         StageTimer t(MEGS_STAGE_BLEND_FWD, s);
-        HIP_TRY(launch_blend_fwd(a, L.tile, waves_of(cfg), cfg->batch, persistent, s));
+        HIP_TRY(launch_blend_fwd(a, L.tile, waves_of(cfg), cfg->batch, persistent, s, cfg->subtile));
     }
 
     state->n_records = L.nr;
@@ -478,7 +480,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 1, s));
     {
         StageTimer t(MEGS_STAGE_BLEND_BWD, s);
-        HIP_TRY(launch_blend_bwd(a, L.tile, waves_of(cfg), cfg->batch, persistent, s));
+        HIP_TRY(launch_blend_bwd(a, L.tile, waves_of(cfg), cfg->batch, persistent, s, cfg->subtile));
         if (grad_pair)
             HIP_TRY(launch_pair_reduce(static_cast<const uint32_t*>(st->det_order),
                                        static_cast<const uint32_t*>(st->det_offsets),
@@ -905,18 +907,20 @@ megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int3
     if (!base || !best || !dl_dimages) return fail(MEGS_ERR_ARG, "null base config, best or dL/dimage");
     if (reps < 1) reps = 1;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int combos[7][2] = {{8, 1}, {16, 1}, {16, 2}, {16, 4}, {32, 1}, {32, 2}, {32, 4}};
+    const int combos[9][3] = {{8, 1, 0},  {16, 1, 0}, {16, 2, 0}, {16, 4, 0}, {32, 1, 0},
+                              {32, 2, 0}, {32, 4, 0}, {16, 1, 8}, {32, 1, 8}};
     const int batches[4] = {32, 64, 128, 256};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f;
     megs_status result = MEGS_OK;
-    for (int ci = 0; ci < 7 && result == MEGS_OK; ++ci)
+    for (int ci = 0; ci < 9 && result == MEGS_OK; ++ci)
         for (int bi = 0; bi < 4 && result == MEGS_OK; ++bi) {
             megs_config c = *base;
             c.tile = combos[ci][0];
             c.waves = combos[ci][1];
+            c.subtile = combos[ci][2];
             c.batch = batches[bi];
             float ms_total = 0.f;
             for (int r = 0; r <= reps && result == MEGS_OK; ++r) {

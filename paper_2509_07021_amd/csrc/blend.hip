@@ -447,6 +447,245 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
     }
 }
 
+// ------------------------------------------------------------- sub-tile kernels ----
+// One wave64 per 8 x 8 sub-tile of a 16 x 16 or 32 x 32 tile: the tile's sorted list (and so the
+// key table and its sort) stays at the tile's size, while blending runs at sub-tile size. The wave
+// walks the list in chunks of 64 entries; each lane stages one entry and keeps it only when the
+// entry's footprint box meets the sub-tile; the kept entries are packed in list order into the
+// wave's own LDS (ballot prefix) and blended. Sub-tiles of a tile never wait for each other: there
+// is no workgroup barrier anywhere.
+
+// LDS written by some lanes of a wave and read by others: order the wave's accesses.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int64_t next_item(const BlendArgs& a, int64_t prev, bool persistent, int64_t n_items,
+                                             uint32_t* slot) {
+    if (!persistent) return prev < 0 ? (int64_t)blockIdx.x : n_items;
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(a.queue, 1u);
+    __syncthreads();
+    return (int64_t)*slot;
+}
+
+// Rank of this lane among the lanes set in mask (lanes below it).
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+struct SubCtx {
+    TileCtx c;
+    int sx, sy;       // sub-tile origin inside the tile
+    int64_t t;
+};
+
+__device__ __forceinline__ SubCtx sub_ctx(const BlendArgs& a, int64_t w, int tile) {
+    constexpr int SUB = 8;
+    const int per_row = tile / SUB, nsub = per_row * per_row;
+    SubCtx q;
+    q.t = w / nsub;
+    const int s = (int)(w - q.t * nsub);
+    q.sx = (s % per_row) * SUB;
+    q.sy = (s / per_row) * SUB;
+    q.c = tile_ctx(a, q.t, tile);
+    return q;
+}
+
+template <bool STATS, bool IMP>
+__global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int persistent) {
+    constexpr int SUB = 8;
+    __shared__ Staged lds[64];
+    __shared__ uint32_t lds_pos[64];
+    __shared__ uint32_t lds_id[64];
+    __shared__ uint32_t work_slot;
+    const int lane = __lane_id();
+    const int64_t n_items = a.n_tiles * (int64_t)(tile / SUB) * (tile / SUB);
+    uint32_t n_blended = 0, n_evaluated = 0;
+    for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot); w < n_items;
+         w = next_item(a, w, persistent, n_items, &work_slot)) {
+        const SubCtx q = sub_ctx(a, w, tile);
+        const TileCtx& c = q.c;
+        const int lx = q.sx + (lane & 7), ly = q.sy + (lane >> 3);
+        const bool inside = c.x0 + lx < c.width && c.y0 + ly < c.height;
+        if (!__any(inside)) continue;  // a sub-tile past the image edge has no pixel
+        float T = inside ? 1.0f : -1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+        uint32_t last = 0;
+        const uint2 rg = a.ranges[q.t];
+        const float px = lx + 0.5f, py = ly + 0.5f;
+        for (uint32_t base = rg.x; base < rg.y; base += 64) {
+            if (!__any(T > 0.0f)) break;
+            const uint32_t idx = base + lane;
+            bool hit = false;
+            Staged st;
+            uint32_t g = 0;
+            if (idx < rg.y) {
+                g = a.vals[idx];
+                stage(a, g, (double)c.x0, (double)c.y0, &st);
+                hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
+            }
+            const uint64_t m = __ballot(hit);
+            const int nhit = __popcll(m);
+            if (hit) {
+                const int slot = lane_rank(m);
+                lds[slot] = st;
+                lds_pos[slot] = idx - rg.x;
+                if (IMP) lds_id[slot] = g;
+            }
+            wave_sync();
+            for (int k = 0; k < nhit; ++k) {
+                if ((k & 3) == 0 && !__any(T > 0.0f)) break;
+                const Staged s = lds[k];
+                float dx, dy, G, alpha;
+                bool clamped;
+                const bool pass = frag(s, px, py, dx, dy, G, alpha, clamped) & (T > 0.0f);
+                if (STATS) n_evaluated += T > 0.0f;
+                if (!__any(pass)) continue;
+                const float Tn = T * (1.0f - alpha);
+                const bool term = pass & (Tn < kTMin);
+                const bool incl = pass & !term;
+                const float wgt = incl ? alpha * T : 0.0f;
+                C0 = __fmaf_rn(wgt, s.p2.y, C0);
+                C1 = __fmaf_rn(wgt, s.p2.z, C1);
+                C2 = __fmaf_rn(wgt, s.p2.w, C2);
+                T = incl ? Tn : (term ? -T : T);
+                last = incl ? lds_pos[k] + 1 : last;
+                if (STATS) n_blended += incl;
+                if (IMP) {
+                    float wsum = wgt;
+#pragma unroll
+                    for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d);
+                    if (lane == 0 && wsum != 0.0f)
+                        unsafeAtomicAdd(a.importance + (lds_id[k] - (int64_t)c.view * a.n), wsum);
+                }
+            }
+            wave_sync();
+        }
+        if (inside) {
+            const int x = c.x0 + lx, y = c.y0 + ly;
+            const int64_t p = (int64_t)y * c.width + x;
+            const int64_t plane = (int64_t)c.width * c.height;
+            float* img = a.image + 3 * c.pix_off;
+            const float Tf = fabsf(T);
+            img[p] = __fmaf_rn(Tf, c.bg[0], C0);
+            img[plane + p] = __fmaf_rn(Tf, c.bg[1], C1);
+            img[2 * plane + p] = __fmaf_rn(Tf, c.bg[2], C2);
+            a.T_final[c.pix_off + p] = Tf;
+            a.last[c.pix_off + p] = last;
+        }
+    }
+    if (STATS) {
+        unsigned long long nb = n_blended, ne = n_evaluated;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            nb += __shfl_xor(nb, d);
+            ne += __shfl_xor(ne, d);
+        }
+        if (lane == 0) {
+            atomicAdd(a.stats, nb);
+            atomicAdd(a.stats + 1, ne);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int persistent) {
+    constexpr int SUB = 8;
+    __shared__ Staged lds[64];
+    __shared__ uint32_t lds_pos[64];
+    __shared__ uint32_t lds_id[64];
+    __shared__ uint32_t work_slot;
+    const int lane = __lane_id();
+    const int64_t n_items = a.n_tiles * (int64_t)(tile / SUB) * (tile / SUB);
+    for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot); w < n_items;
+         w = next_item(a, w, persistent, n_items, &work_slot)) {
+        const SubCtx q = sub_ctx(a, w, tile);
+        const TileCtx& c = q.c;
+        const int lx = q.sx + (lane & 7), ly = q.sy + (lane >> 3);
+        const int x = c.x0 + lx, y = c.y0 + ly;
+        const bool inside = x < c.width && y < c.height;
+        const int64_t plane = (int64_t)c.width * c.height;
+        const int64_t p = (int64_t)y * c.width + x;
+        float T = 1.0f, dl0 = 0.f, dl1 = 0.f, dl2 = 0.f;
+        uint32_t lst = 0;
+        if (inside) {
+            const float* dimg = a.dl + 3 * c.pix_off;
+            T = a.T_final[c.pix_off + p];
+            lst = a.last[c.pix_off + p];
+            dl0 = dimg[p];
+            dl1 = dimg[plane + p];
+            dl2 = dimg[2 * plane + p];
+        }
+        float S0 = c.bg[0], S1 = c.bg[1], S2 = c.bg[2];
+        uint32_t wave_last = lst;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, d));
+        if (wave_last == 0) continue;  // wave-uniform: no pixel of the sub-tile blended anything
+        const uint2 rg = a.ranges[q.t];
+        const float px = lx + 0.5f, py = ly + 0.5f;
+        for (uint32_t end = rg.x + wave_last; end > rg.x;) {
+            const uint32_t beg = end - rg.x > 64u ? end - 64u : rg.x;
+            const uint32_t cnt = end - beg;
+            const uint32_t idx = end - 1u - (uint32_t)lane;  // descending list positions
+            bool hit = false;
+            Staged st;
+            uint32_t g = 0;
+            if ((uint32_t)lane < cnt) {
+                g = a.vals[idx];
+                stage(a, g, (double)c.x0, (double)c.y0, &st);
+                hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
+            }
+            const uint64_t m = __ballot(hit);
+            const int nhit = __popcll(m);
+            if (hit) {
+                const int slot = lane_rank(m);
+                lds[slot] = st;
+                lds_pos[slot] = idx - rg.x;
+                lds_id[slot] = g;
+            }
+            wave_sync();
+            for (int k = 0; k < nhit; ++k) {
+                const Staged s = lds[k];
+                const uint32_t pos = lds_pos[k];
+                float alpha, G, dx, dy;
+                bool clamped;
+                const bool incl = frag(s, px, py, dx, dy, G, alpha, clamped) & (pos < lst);
+                if (!__any(incl)) continue;
+                float acc[9];
+                const float al = incl ? alpha : 0.0f;
+                const float Ti = T * __builtin_amdgcn_rcpf(1.0f - al);
+                const float wgt = al * Ti;
+                const float d0 = s.p2.y - S0, d1 = s.p2.z - S1, d2 = s.p2.w - S2;
+                acc[6] = wgt * dl0;
+                acc[7] = wgt * dl1;
+                acc[8] = wgt * dl2;
+                const float dal = Ti * __fmaf_rn(d0, dl0, __fmaf_rn(d1, dl1, d2 * dl2));
+                S0 = __fmaf_rn(al, d0, S0);
+                S1 = __fmaf_rn(al, d1, S1);
+                S2 = __fmaf_rn(al, d2, S2);
+                T = incl ? Ti : T;
+                const bool live = incl & !clamped;
+                const float dq = live ? al * dal : 0.0f;
+                acc[5] = (live ? G : 0.0f) * dal;
+                acc[0] = dq * __fmaf_rn(s.p1.z, dx, s.p1.w * dy);
+                acc[1] = dq * __fmaf_rn(s.p1.w, dx, s.p2.x * dy);
+                const float hq = -0.5f * dq;
+                acc[2] = hq * (dx * dx);
+                acc[3] = -dq * (dx * dy);
+                acc[4] = hq * (dy * dy);
+                float tot, tot8;
+                wave_sum9(acc, tot, tot8);
+                float* slot = a.grad2d + 9 * (int64_t)lds_id[k];
+                if ((lane & 7) == 0) unsafeAtomicAdd(slot + (lane >> 3), tot);
+                if (lane == 1) unsafeAtomicAdd(slot + 8, tot8);
+            }
+            wave_sync();
+            end = beg;
+        }
+    }
+}
+
 constexpr int64_t kPersistentGroups = 256 * 24;  // resident workgroups pulling tiles in persistent mode
 
 template <int TILE, int WAVES>
@@ -482,10 +721,33 @@ hipError_t launch_bwd_t(const BlendArgs& a, int batch, bool persistent, hipStrea
     return hipGetLastError();
 }
 
+hipError_t launch_fwd_sub(const BlendArgs& a, int tile, bool persistent, hipStream_t stream) {
+    const int64_t items = a.n_tiles * (int64_t)(tile / 8) * (tile / 8);
+    const int64_t groups = persistent ? kPersistentGroups : items;
+    const unsigned grid = (unsigned)(groups < items ? groups : items);
+    if (a.importance)
+        hipLaunchKernelGGL((k_blend_fwd_sub<false, true>), dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+    else if (a.stats)
+        hipLaunchKernelGGL((k_blend_fwd_sub<true, false>), dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+    else
+        hipLaunchKernelGGL((k_blend_fwd_sub<false, false>), dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_sub(const BlendArgs& a, int tile, bool persistent, hipStream_t stream) {
+    const int64_t items = a.n_tiles * (int64_t)(tile / 8) * (tile / 8);
+    const int64_t groups = persistent ? kPersistentGroups : items;
+    const unsigned grid = (unsigned)(groups < items ? groups : items);
+    hipLaunchKernelGGL(k_blend_bwd_sub, dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream) {
+hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream,
+                            int subtile) {
     if (a.n_tiles <= 0) return hipSuccess;
+    if (subtile == 8 && tile > 8) return launch_fwd_sub(a, tile, persistent, stream);
     if (tile == 8 && waves == 1) return launch_fwd_t<8, 1>(a, batch, persistent, stream);
     if (tile == 16 && waves == 1) return launch_fwd_t<16, 1>(a, batch, persistent, stream);
     if (tile == 16 && waves == 2) return launch_fwd_t<16, 2>(a, batch, persistent, stream);
@@ -496,8 +758,10 @@ hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int waves, int batch, 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream) {
+hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream,
+                            int subtile) {
     if (a.n_tiles <= 0) return hipSuccess;
+    if (subtile == 8 && tile > 8 && !a.grad_pair) return launch_bwd_sub(a, tile, persistent, stream);
     if (tile == 8 && waves == 1) return launch_bwd_t<8, 1>(a, batch, persistent, stream);
     if (tile == 16 && waves == 1) return launch_bwd_t<16, 1>(a, batch, persistent, stream);
     if (tile == 16 && waves == 2) return launch_bwd_t<16, 2>(a, batch, persistent, stream);

@@ -281,8 +281,12 @@ struct BlendArgs {
     float* importance;          // forward: per-Gaussian sum of blending weights (null: not computed)
     int64_t n;                  // Gaussians per view (record r of view v is Gaussian r - v n)
 };
-hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream);
-hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream);
+// subtile 8 (with 16 x 16 or 32 x 32 tiles): one independent wave per 8 x 8 sub-tile walking its
+// tile's list (the deterministic backward keeps the per-tile kernels).
+hipError_t launch_blend_fwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream,
+                            int subtile);
+hipError_t launch_blend_bwd(const BlendArgs& a, int tile, int waves, int batch, bool persistent, hipStream_t stream,
+                            int subtile);
 
 // deterministic backward support (sort.hip)
 hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, int64_t count, hipStream_t stream);

@@ -37,9 +37,10 @@ class Config:
     flags: int = 0
     pair_capacity: int = 0
     waves: int = 0  # wave64s per tile workgroup (0: library default)
+    subtile: int = 0  # 8: blend per 8x8 sub-tile, one independent wave each (16x16 / 32x32 tiles)
 
     def struct(self) -> L.MegsConfig:
-        return L.MegsConfig(self.tile, self.batch, self.flags, self.waves, self.pair_capacity)
+        return L.MegsConfig(self.tile, self.batch, self.flags, self.waves, self.pair_capacity, self.subtile, 0)
 
 
 class DeviceScene:
@@ -332,7 +333,7 @@ class Graph:
 
 
 def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps: int = 2, dl_images=None):
-    """Times every (tile, waves) of AUTOTUNE_COMBOS x batch {32, 64, 128, 256}; returns
+    """Times every (tile, waves, subtile) of AUTOTUNE_COMBOS x batch {32, 64, 128, 256}; returns
     (best Config, ms table [combo][batch])."""
     lib = L.load()
     npix = sum(h * w for h, w in image_sizes(cams))
@@ -351,7 +352,7 @@ def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps:
                               images.data_ptr(), dl.data_ptr(), ctypes.byref(g), reps, _stream(None),
                               ctypes.byref(best), ms))
     table = np.array(list(ms), np.float32).reshape(len(L.AUTOTUNE_COMBOS), len(L.AUTOTUNE_BATCHES))
-    return Config(best.tile, best.batch, best.flags, best.pair_capacity, best.waves), table
+    return Config(best.tile, best.batch, best.flags, best.pair_capacity, best.waves, best.subtile), table
 
 
 class Profile:

@@ -32,13 +32,13 @@ def test_version_and_empty_error():
     assert isinstance(lib.megs_last_error(), bytes)
 
 
-def _args(tile=16, batch=64, flags=0, nv=1, k=0, width=32, height=32, n=0, dt=0, cap=0, waves=0):
+def _args(tile=16, batch=64, flags=0, nv=1, k=0, width=32, height=32, n=0, dt=0, cap=0, waves=0, subtile=0):
     sc = L.MegsScene()
     sc.n, sc.k, sc.dt_geom, sc.dt_color, sc.dt_amp = n, k, dt, 0, 0
     cams = (L.MegsCamera * max(nv, 1))()
     for c in cams:
         c.width, c.height, c.fx, c.fy, c.znear = width, height, 20.0, 20.0, 0.2
-    cfg = L.MegsConfig(tile, batch, flags, waves, cap)
+    cfg = L.MegsConfig(tile, batch, flags, waves, cap, subtile, 0)
     return sc, cams, cfg
 
 
@@ -66,6 +66,8 @@ def _forward(sc, cams, nv, cfg):
     (dict(cap=-5), "pair_capacity"),
     (dict(waves=3), "waves"),
     (dict(tile=8, waves=2), "one wave"),
+    (dict(subtile=4), "subtile"),
+    (dict(tile=8, subtile=8), "subtile"),
 ])
 def test_forward_rejects_bad_arguments(kw, needle):
     nv = kw.pop("nv", 1)

@@ -82,10 +82,10 @@ def test_persistent_queue_matches_one_group_per_tile():
     ds = R.DeviceScene.from_scene(scene)
     npix = sum(c.width * c.height for c in cams)
     dl = torch.from_numpy(np.random.default_rng(3).standard_normal(3 * npix).astype(np.float32)).cuda()
-    for tile, waves in ((8, 1), (16, 1), (16, 4), (32, 2)):
-        log(f"persistent tile {tile} waves {waves}")
-        fa, ga = _eager(ds, cams, R.Config(tile, 64, waves=waves), dl)
-        fb, gb = _eager(ds, cams, R.Config(tile, 64, L.MEGS_FLAG_PERSISTENT, waves=waves), dl)
+    for tile, waves, sub in ((8, 1, 0), (16, 1, 0), (16, 4, 0), (32, 2, 0), (16, 1, 8), (32, 1, 8)):
+        log(f"persistent tile {tile} waves {waves} subtile {sub}")
+        fa, ga = _eager(ds, cams, R.Config(tile, 64, waves=waves, subtile=sub), dl)
+        fb, gb = _eager(ds, cams, R.Config(tile, 64, L.MEGS_FLAG_PERSISTENT, waves=waves, subtile=sub), dl)
         np.testing.assert_array_equal(fa.images.cpu().numpy(), fb.images.cpu().numpy())
         for p in ga:
             if ga[p] is not None:
@@ -98,7 +98,7 @@ def test_autotuner_picks_a_valid_config_with_the_same_images():
     ds = R.DeviceScene.from_scene(scene)
     best, table = R.autotune(ds, cams, R.Config(16, 64), reps=1)
     log(f"autotune best tile {best.tile} batch {best.batch}\n{table}")
-    assert (best.tile, best.waves) in L.AUTOTUNE_COMBOS and best.batch in L.AUTOTUNE_BATCHES
+    assert (best.tile, best.waves, best.subtile) in L.AUTOTUNE_COMBOS and best.batch in L.AUTOTUNE_BATCHES
     assert table.shape == (len(L.AUTOTUNE_COMBOS), len(L.AUTOTUNE_BATCHES))
     assert np.all(np.isfinite(table)) and np.all(table > 0)
     a = R.forward(ds, cams, R.Config(16, 64)).images.cpu().numpy()

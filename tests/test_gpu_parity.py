@@ -130,6 +130,15 @@ def test_tile_batch_and_wave_variants(tile, batch, waves):
     _run_all_stages(scene, cams, R.Config(tile, batch, waves=waves))
 
 
+@pytest.mark.parametrize("tile", [16, 32])
+def test_subtile_blend(tile):
+    """One independent wave per 8x8 sub-tile walking the tile's list: every stage against the
+    oracle, on views with ragged edges (sub-tiles past the image edge)."""
+    scene, cams = S.make_workload("small_2k_128px")
+    cams = cams + [S.look_at((2.0, -3.0, 1.5), 100, 60, bg=(0.2, 0.2, 0.2))]
+    _run_all_stages(scene, cams, R.Config(tile, 64, subtile=8))
+
+
 def test_one_stage_sort_matches_two_stage():
     scene, cams = S.make_workload("small_2k_128px")
     cams = cams + [S.look_at((2.0, -3.0, 1.5), 100, 60)]
@@ -197,13 +206,15 @@ def test_zero_lobes_and_single_gaussian():
     _run_all_stages(scene, [S.look_at((0, -3, 0), 48, 40)], R.Config(16, 64))
 
 
-@pytest.mark.parametrize("tile,waves,flags", [(16, 4, 8), (8, 1, 8), (32, 2, 8 | 2), (16, 1, 8 | 1)])
-def test_deterministic_backward_is_bitwise_reproducible(tile, waves, flags):
+@pytest.mark.parametrize("tile,waves,flags,sub", [(16, 4, 8, 0), (8, 1, 8, 0), (32, 2, 8 | 2, 0), (16, 1, 8 | 1, 0),
+                                                  (16, 1, 8, 8)])
+def test_deterministic_backward_is_bitwise_reproducible(tile, waves, flags, sub):
     """MEGS_FLAG_DETERMINISTIC: per-pair gradient slots summed per record in a fixed order. Every
-    stage still matches the oracle, and two runs give bit-identical gradients."""
+    stage still matches the oracle, and two runs give bit-identical gradients (with sub-tile
+    blending the forward runs per sub-tile and the backward per tile)."""
     scene, cams = S.make_workload("small_2k_128px")
     cams = cams + [S.look_at((2.0, -3.0, 1.5), 100, 60, bg=(0.2, 0.2, 0.2))]
-    cfg = R.Config(tile, 64, flags=flags, waves=waves)
+    cfg = R.Config(tile, 64, flags=flags, waves=waves, subtile=sub)
     g1, fwd = _run_all_stages(scene, cams, cfg)
     w = [np.asarray(x) for x in S.loss_weights(cams, 7)]
     g2 = gpu_run(scene, cams, cfg, weights=[wi * (1 - vw["flag"])[None].astype(np.float32)

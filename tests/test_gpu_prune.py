@@ -76,6 +76,11 @@ def test_importance_and_prox_step_on_the_masked_workload():
     np.testing.assert_allclose(imp.sum(), ref.sum(), rtol=1e-5)
     close = np.abs(imp - ref) <= 1e-4 * np.maximum(ref, 1.0)
     assert close.mean() > 0.995 and np.abs(imp - ref).max() < 0.05
+    # the sub-tile blend's importance instance gives the same scores
+    _, imp8 = PR.importance(ds, cams, R.Config(16, 64, subtile=8))
+    imp8 = imp8.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(imp8.sum(), ref.sum(), rtol=1e-5)
+    assert (np.abs(imp8 - ref) <= 1e-4 * np.maximum(ref, 1.0)).mean() > 0.995
     # the proximal step, kappa_o = 40% of the primitives and kappa_s = 50% of the lobes
     rng = np.random.default_rng(9)
     o = torch.sigmoid(ds.planes["op_logit"]).contiguous()
