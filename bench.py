@@ -67,10 +67,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1_000_000, help="Gaussians (default: the 1M workload)")
     ap.add_argument("--views", type=int, default=8)
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=32)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--waves", type=int, default=0, help="wave64s per tile workgroup (0: library default)")
-    ap.add_argument("--subtile", type=int, default=0, help="8: blend per 8x8 sub-tile (16x16 / 32x32 tiles)")
+    ap.add_argument("--subtile", type=int, default=8,
+                    help="8: blend per 8x8 sub-tile (16x16 / 32x32 tiles); 0: per tile")
     ap.add_argument("--autotune", action="store_true", help="pick tile/batch with the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=8, help="views of the workload the oracle renders")
