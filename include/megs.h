@@ -154,7 +154,9 @@ typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
  *   radius    int32[NR]      footprint radius in pixels, -1 when culled
  *   ntiles    uint32[NR]     tiles of the record's rectangle that its footprint ellipse reaches
  *   cutoff    float[NR]      k of that ellipse, {d : d' conic d <= k}; k bounds 2 ln(255 o_eff)
- *   tile_keys uint32[P]      sorted global tile ids (two-stage sort) or NULL
+ *   tile_keys uint32[P]      sorted global tile ids (two-stage sort) or NULL; with subtile = 8 and
+ *                            at most 65536 tiles, bits 16-31 flag the 8x8 sub-tiles of the tile that
+ *                            the record's cutoff ellipse reaches (bit r S + c, S = tile / 8)
  *   keys64    uint64[P]      sorted tile<<32|depth keys (one-stage sort) or NULL
  *   vals      uint32[P]      sorted record indices
  *   ranges    uint32[T][2]   [start, end) of each tile in vals; (0, 0) when empty

@@ -99,6 +99,12 @@ struct Layout {
 
 bool valid_dtype(int32_t d) { return d == MEGS_F32 || d == MEGS_F16 || d == MEGS_BF16; }
 
+// Sub-tile flags in the tile keys: sub-tile blending with the two-stage sort and tile ids that
+// leave the upper 16 bits of the 32-bit key free.
+bool sub_masks(const megs_config* cfg, const Layout& L) {
+    return cfg->subtile == 8 && cfg->tile > 8 && !(cfg->flags & MEGS_FLAG_ONE_STAGE_SORT) && L.n_tiles <= 65536;
+}
+
 // True when the scene has lobe planes to read (dense with k > 0, or compressed rows with lobes).
 bool has_lobes(const megs_scene* sc) { return sc->k > 0 && (sc->lobe_off ? sc->n_lobes > 0 : true); }
 
@@ -358,7 +364,7 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
         StageTimer t(MEGS_STAGE_EMIT, s);
         HIP_TRY(launch_clamp_count(f.counters + 0, p.capacity, f.counters + 1, f.status, s));
         HIP_TRY(launch_emit(f.rec, f.views, L.nv, L.n, L.tile, one_stage ? nullptr : f.order, f.offs, L.nr, p.tkeys,
-                            p.k64, p.vals, p.capacity, f.status, s));
+                            p.k64, p.vals, p.capacity, f.status, s, sub_masks(cfg, L) ? 8 : 0));
     }
     const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
     if (det) {  // sort emission positions; the record ids are gathered back after the sort
@@ -394,12 +400,14 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
         if (one_stage)
             HIP_TRY(launch_ranges_u64(sorted_k, f.counters + 1, p.capacity, f.ranges, s));
         else
-            HIP_TRY(launch_ranges_u32(sorted_t, f.counters + 1, p.capacity, f.ranges, s));
+            HIP_TRY(launch_ranges_u32(sorted_t, f.counters + 1, p.capacity, f.ranges, s,
+                                      sub_masks(cfg, L) ? 0xffffu : ~0u));
     }
     BlendArgs a;
     memset(&a, 0, sizeof(a));
     a.views = f.views; a.nv = L.nv; a.n_tiles = L.n_tiles;
     a.rec = f.rec.packed;
+    a.tkeys = sub_masks(cfg, L) ? sorted_t : nullptr;
     a.vals = sorted_v; a.ranges = f.ranges;
     a.image = images; a.T_final = f.T_final; a.last = f.last;
     a.queue = f.queue;
@@ -465,6 +473,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     a.views = static_cast<const ViewInfo*>(st->internal);
     a.nv = L.nv; a.n_tiles = L.n_tiles;
     a.rec = static_cast<const PackedRec*>(st->packed);
+    a.tkeys = sub_masks(cfg, L) ? static_cast<const uint32_t*>(st->tile_keys) : nullptr;
     a.vals = static_cast<const uint32_t*>(st->vals);
     a.ranges = static_cast<const uint2*>(st->ranges);
     a.T_final = const_cast<float*>(static_cast<const float*>(st->T_final));

@@ -479,6 +479,7 @@ __device__ __forceinline__ int lane_rank(uint64_t mask) {
 struct SubCtx {
     TileCtx c;
     int sx, sy;       // sub-tile origin inside the tile
+    int sidx;         // sub-tile index r S + c (the bit of its flag in the tile keys)
     int64_t t;
 };
 
@@ -488,6 +489,7 @@ __device__ __forceinline__ SubCtx sub_ctx(const BlendArgs& a, int64_t w, int til
     SubCtx q;
     q.t = w / nsub;
     const int s = (int)(w - q.t * nsub);
+    q.sidx = s;
     q.sx = (s % per_row) * SUB;
     q.sy = (s / per_row) * SUB;
     q.c = tile_ctx(a, q.t, tile);
@@ -522,9 +524,13 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
             Staged st;
             uint32_t g = 0;
             if (idx < rg.y) {
-                g = a.vals[idx];
-                stage(a, g, (double)c.x0, (double)c.y0, &st);
-                hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
+                // the key's sub-tile flags, when present, decide before the record is gathered
+                const bool flagged = !a.tkeys || ((a.tkeys[idx] >> (16 + q.sidx)) & 1u);
+                if (flagged) {
+                    g = a.vals[idx];
+                    stage(a, g, (double)c.x0, (double)c.y0, &st);
+                    hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
+                }
             }
             const uint64_t m = __ballot(hit);
             const int nhit = __popcll(m);
@@ -632,9 +638,12 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             Staged st;
             uint32_t g = 0;
             if ((uint32_t)lane < cnt) {
-                g = a.vals[idx];
-                stage(a, g, (double)c.x0, (double)c.y0, &st);
-                hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
+                const bool flagged = !a.tkeys || ((a.tkeys[idx] >> (16 + q.sidx)) & 1u);
+                if (flagged) {
+                    g = a.vals[idx];
+                    stage(a, g, (double)c.x0, (double)c.y0, &st);
+                    hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
+                }
             }
             const uint64_t m = __ballot(hit);
             const int nhit = __popcll(m);

@@ -252,12 +252,14 @@ hipError_t launch_radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_
 
 // Key emission: for every record (in `order`, or index order when order is null) write its
 // tiles' keys at offsets[pos]. Two-stage: u32 global tile ids; one-stage: u64 tile|depth keys.
+// sub = 8: the upper 16 bits of each 32-bit tile key flag the 8 x 8 sub-tiles the record reaches
+// (two-stage sort, tile ids below 2^16); sub = 0: plain tile ids.
 hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_t n, int tile,
                        const uint32_t* order, const uint32_t* offsets, int64_t n_records,
                        uint32_t* tile_keys, uint64_t* keys64, uint32_t* vals, int64_t capacity,
-                       int32_t* status, hipStream_t stream);
+                       int32_t* status, hipStream_t stream, int sub);
 hipError_t launch_ranges_u32(const uint32_t* tile_keys, const uint32_t* d_count, int64_t max_count,
-                             uint2* ranges, hipStream_t stream);
+                             uint2* ranges, hipStream_t stream, uint32_t tmask);
 hipError_t launch_ranges_u64(const uint64_t* keys, const uint32_t* d_count, int64_t max_count,
                              uint2* ranges, hipStream_t stream);
 hipError_t launch_clamp_count(const uint32_t* total, int64_t capacity, uint32_t* count, int32_t* status,
@@ -268,6 +270,7 @@ struct BlendArgs {
     int nv;
     int64_t n_tiles;
     const PackedRec* rec;  // the projection's records, one line each
+    const uint32_t* tkeys; // sorted tile keys carrying sub-tile flags in bits 16-31 (null: none)
     const uint32_t* vals;
     const uint2* ranges;
     float* image;

@@ -328,11 +328,16 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
 constexpr int kEmitThreads = 256;
 constexpr int kEmitWindow = 4096;
 
+// With sub-tile masks (sub = 8, tile ids below 2^16), the upper 16 bits of each 32-bit tile key
+// flag the 8 x 8 sub-tiles of the tile that the record's cutoff ellipse reaches (bit r S + c for
+// sub-row r and sub-column c, S = tile / 8): the same row-interval test as the tile selection, run
+// at 8-pixel granularity. The pair sort orders on the tile bits only, so the flags ride along.
 __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t n,
                                                        int tile, const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ offsets, int64_t n_records,
                                                        uint32_t* __restrict__ tile_keys, uint64_t* __restrict__ keys64,
-                                                       uint32_t* __restrict__ vals, int64_t capacity, int32_t* status) {
+                                                       uint32_t* __restrict__ vals, int64_t capacity, int32_t* status,
+                                                       int sub) {
     __shared__ uint32_t w_tile[kEmitWindow];
     __shared__ uint32_t w_val[kEmitWindow];
     __shared__ uint32_t range[2];
@@ -370,12 +375,34 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
         const int64_t w1 = w0 + kEmitWindow < hi ? w0 + kEmitWindow : hi;
         if (nt && off < w1 && off + (int64_t)nt > w0) {
             int64_t pos = off;
+            const int S = sub ? tile / sub : 0;  // sub-tiles per tile edge
             for (int ty = y0; ty <= y1 && pos < w1; ++ty) {
                 int cl, ch;
                 if (!row_span(er, *vw, tile, ty, x0, x1, cl, ch)) continue;
+                int blo[4], bhi[4];  // 8-pixel column span of each sub-row (empty: blo > bhi)
+                if (S) {
+                    for (int r = 0; r < S; ++r) {
+                        const int y8 = ty * S + r;
+                        blo[r] = 1; bhi[r] = 0;
+                        if (y8 * sub < vw->height) {
+                            int lo8, hi8;
+                            if (row_span(er, *vw, sub, y8, cl * S, ch * S + S - 1, lo8, hi8)) { blo[r] = lo8; bhi[r] = hi8; }
+                        }
+                    }
+                }
                 for (int tx = cl; tx <= ch && pos < w1; ++tx, ++pos) {
                     if (pos < w0) continue;
-                    w_tile[pos - w0] = (uint32_t)(vw->tile_off + (int64_t)ty * vw->tiles_x + tx);
+                    uint32_t key = (uint32_t)(vw->tile_off + (int64_t)ty * vw->tiles_x + tx);
+                    if (S) {
+                        uint32_t m = 0;
+                        for (int r = 0; r < S; ++r)
+                            for (int c = 0; c < S; ++c) {
+                                const int x8 = tx * S + c;
+                                m |= (uint32_t)(x8 >= blo[r] && x8 <= bhi[r]) << (r * S + c);
+                            }
+                        key |= m << 16;
+                    }
+                    w_tile[pos - w0] = key;
                     w_val[pos - w0] = g;
                 }
             }
@@ -440,14 +467,14 @@ __global__ void k_clamp_count(const uint32_t* total, int64_t capacity, uint32_t*
 }
 
 template <typename K>
-__global__ void k_ranges(const K* __restrict__ keys, int shift, const uint32_t* d_count, int64_t max_count,
-                         uint2* __restrict__ ranges) {
+__global__ void k_ranges(const K* __restrict__ keys, int shift, uint32_t tmask, const uint32_t* d_count,
+                         int64_t max_count, uint2* __restrict__ ranges) {
     int64_t n = (int64_t)*d_count;
     if (n > max_count) n = max_count;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t t = (uint32_t)(keys[i] >> shift);
-        if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != t) ranges[t].x = (uint32_t)i;
-        if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != t) ranges[t].y = (uint32_t)(i + 1);
+        const uint32_t t = (uint32_t)(keys[i] >> shift) & tmask;
+        if (i == 0 || ((uint32_t)(keys[i - 1] >> shift) & tmask) != t) ranges[t].x = (uint32_t)i;
+        if (i == n - 1 || ((uint32_t)(keys[i + 1] >> shift) & tmask) != t) ranges[t].y = (uint32_t)(i + 1);
     }
 }
 
@@ -513,19 +540,20 @@ hipError_t launch_radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_
 hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_t n, int tile,
                        const uint32_t* order, const uint32_t* offsets, int64_t n_records,
                        uint32_t* tile_keys, uint64_t* keys64, uint32_t* vals, int64_t capacity,
-                       int32_t* status, hipStream_t stream) {
+                       int32_t* status, hipStream_t stream, int sub) {
     (void)nv;
     if (n_records <= 0) return hipSuccess;
+    if (sub && (!tile_keys || tile / sub > 4)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_records + kEmitThreads - 1) / kEmitThreads)), dim3(kEmitThreads), 0,
                        stream, rec, views, n, tile, order, offsets, n_records, tile_keys, keys64, vals, capacity,
-                       status);
+                       status, sub);
     return hipGetLastError();
 }
 
 hipError_t launch_ranges_u32(const uint32_t* tile_keys, const uint32_t* d_count, int64_t max_count, uint2* ranges,
-                             hipStream_t stream) {
+                             hipStream_t stream, uint32_t tmask) {
     if (max_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid_for(max_count, 256)), dim3(256), 0, stream, tile_keys, 0,
+    hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid_for(max_count, 256)), dim3(256), 0, stream, tile_keys, 0, tmask,
                        d_count, max_count, ranges);
     return hipGetLastError();
 }
@@ -533,8 +561,8 @@ hipError_t launch_ranges_u32(const uint32_t* tile_keys, const uint32_t* d_count,
 hipError_t launch_ranges_u64(const uint64_t* keys, const uint32_t* d_count, int64_t max_count, uint2* ranges,
                              hipStream_t stream) {
     if (max_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(grid_for(max_count, 256)), dim3(256), 0, stream, keys, 32, d_count,
-                       max_count, ranges);
+    hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(grid_for(max_count, 256)), dim3(256), 0, stream, keys, 32, ~0u,
+                       d_count, max_count, ranges);
     return hipGetLastError();
 }
 

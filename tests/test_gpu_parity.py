@@ -46,8 +46,10 @@ def _check_records(g, fwd, n_views):
     np.testing.assert_allclose(g["cutoff"][v], rec["cutoff"][v], rtol=1e-5, atol=1e-5)
 
 
-def _check_key_stage(g, cams, tile, n):
-    """Keys, order and ranges from the GPU's own records, bit-exact against the oracle's table."""
+def _check_key_stage(g, cams, tile, n, sub=0):
+    """Keys, order and ranges from the GPU's own records, bit-exact against the oracle's table
+    (with sub-tile blending the upper 16 bits of the tile keys carry sub-tile flags; the tile id is
+    the lower 16, and every pair flags at least one sub-tile or lies past every pixel centre)."""
     rec = gpu_records(g)
     rec_view = np.repeat(np.arange(len(cams), dtype=np.int32), n)
     keys, vals, ranges, off = O.pairs(rec["u"], rec["v"], g["rgbd"][:, 3], rec["radius"], rec["conic"],
@@ -59,7 +61,11 @@ def _check_key_stage(g, cams, tile, n):
     if "keys64" in g:
         np.testing.assert_array_equal(g["keys64"], keys)
     else:
-        rebuilt = (g["tile_keys"].astype(np.uint64) << np.uint64(32)) | depth_bits[g["vals"]]
+        tk = g["tile_keys"]
+        if sub:
+            assert np.count_nonzero(tk >> np.uint32(16)) > 0.9 * len(tk)
+            tk = tk & np.uint32(0xFFFF)
+        rebuilt = (tk.astype(np.uint64) << np.uint64(32)) | depth_bits[g["vals"]]
         np.testing.assert_array_equal(rebuilt, keys)
     return rec, off
 
@@ -86,7 +92,7 @@ def _run_all_stages(scene, cams, cfg, seed=7):
     fwd, w = _oracle_masked_weights(scene, cams, cfg.tile, seed)
     g = gpu_run(scene, cams, cfg, weights=w)
     _check_records(g, fwd, len(cams))
-    rec, off = _check_key_stage(g, cams, cfg.tile, scene.n)
+    rec, off = _check_key_stage(g, cams, cfg.tile, scene.n, sub=cfg.subtile)
     _check_blend_stage(g, rec, cams, cfg.tile, off)
     # end-to-end images against the FP64 pipeline
     for vi in range(len(cams)):
