@@ -357,8 +357,10 @@ def main():
     nt8 = sum(((c.width + cfg.tile - 1) // cfg.tile) * ((c.height + cfg.tile - 1) // cfg.tile) for c in cams8)
     geom_bytes = static16 // scene.n
     if dominant in ("blend_fwd", "blend_bwd"):
+        # the backward re-tests the fragments the forward tested (the same culled lists, walked
+        # back from each pixel's last index) and differentiates the blended ones
         flops = (FLOP_TEST * evaluated + FLOP_FWD_BLEND * blended if dominant == "blend_fwd"
-                 else FLOP_TEST * replayed + FLOP_BWD_BLEND * blended)
+                 else FLOP_TEST * evaluated + FLOP_BWD_BLEND * blended)
         achieved = flops / (stage_ms[dominant] * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_of(dominant),

@@ -125,20 +125,25 @@ class DeviceScene:
 
 
 class TorchAllocator:
-    """Allocation callback for the C ABI: device memory from torch's caching allocator."""
+    """Allocation callback for the C ABI: device memory from torch's caching allocator.
+
+    The callback closes over the block list, not over the allocator, so dropping the allocator
+    frees its blocks at once (no reference cycle waiting for the garbage collector)."""
 
     def __init__(self, device="cuda"):
         self.device = torch.device(device)
         self.blocks = []
-        self.fn = L.ALLOC_FN(self._alloc)
+        blocks, dev = self.blocks, self.device
 
-    def _alloc(self, ctx, nbytes):
-        try:
-            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
-        except Exception:  # out of memory: the library reports MEGS_ERR_ALLOC
-            return None
-        self.blocks.append(t)
-        return t.data_ptr()
+        def _alloc(ctx, nbytes):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+            except Exception:  # out of memory: the library reports MEGS_ERR_ALLOC
+                return None
+            blocks.append(t)
+            return t.data_ptr()
+
+        self.fn = L.ALLOC_FN(_alloc)
 
     def view(self, ptr: int, count: int, dtype: torch.dtype) -> torch.Tensor:
         """A tensor view of `count` elements at device address ptr inside one of the blocks."""
