@@ -330,8 +330,54 @@ constexpr int kEmitWindow = 4096;
 
 // With sub-tile masks (sub = 8, tile ids below 2^16), the upper 16 bits of each 32-bit tile key
 // flag the 8 x 8 sub-tiles of the tile that the record's cutoff ellipse reaches (bit r S + c for
-// sub-row r and sub-column c, S = tile / 8): the same row-interval test as the tile selection, run
-// at 8-pixel granularity. The pair sort orders on the tile bits only, so the flags ride along.
+// sub-row r and sub-column c, S = tile / 8): the row-interval test of the tile selection run at
+// 8-pixel granularity, in FP32 and widened by a quarter pixel, so the flags are a superset of the
+// exact ones (the blend still tests every flagged record). The pair sort orders on the tile bits
+// only, so the flags ride along.
+struct BandsF {
+    float v, ry, dys, ka, det, b, ia, u;
+    bool full;
+};
+
+__device__ __forceinline__ BandsF bands_of(const EllipseRows& e) {
+    constexpr float kMargin = 0.25f;
+    BandsF f;
+    f.full = e.full;
+    f.u = (float)e.u; f.v = (float)e.v; f.b = (float)e.b; f.det = (float)e.det; f.ia = (float)e.ia;
+    f.ka = (float)e.ka; f.dys = (float)e.dys;
+    f.ry = (float)e.ry + kMargin;
+    return f;
+}
+
+// x-extent [xmin, xmax] (widened) of the ellipse within sub-row band y8 (rows y8 * sub ..
+// y8 * sub + sub - 1); xmin > xmax when the band misses it.
+__device__ __forceinline__ void band_extent(const BandsF& f, int sub, int y8, int height, float& xmin, float& xmax) {
+    constexpr float kMargin = 0.25f;
+    xmin = 1.0f; xmax = 0.0f;
+    if (y8 * sub >= height) return;
+    if (f.full) { xmin = -3.0e38f; xmax = 3.0e38f; return; }
+    const int ye = (y8 + 1) * sub < height ? (y8 + 1) * sub : height;
+    float dl = (y8 * sub + 0.5f) - f.v, dh = (ye - 0.5f) - f.v;
+    dl = fmaxf(dl, -f.ry);
+    dh = fminf(dh, f.ry);
+    if (dl > dh) return;
+    const float d1 = fminf(fmaxf(f.dys, dl), dh), d2 = fminf(fmaxf(-f.dys, dl), dh);
+    const float s1 = sqrtf(fmaxf(f.ka - f.det * d1 * d1, 0.0f)), s2 = sqrtf(fmaxf(f.ka - f.det * d2 * d2, 0.0f));
+    xmax = f.u + (s1 - f.b * d1) * f.ia + kMargin;
+    xmin = f.u - (s2 + f.b * d2) * f.ia - kMargin;
+}
+
+// Bits of the sub-columns of tile column tx whose pixel-centre range meets [xmin, xmax].
+__device__ __forceinline__ uint32_t band_bits(float xmin, float xmax, int sub, int tx, int S) {
+    if (xmin > xmax) return 0u;
+    const float x0 = (float)(tx * S * sub);
+    const float lo = fmaxf(ceilf((xmin + 0.5f - x0) / sub - 1.0f), 0.0f);
+    const float hi = fminf(floorf((xmax - 0.5f - x0) / sub), (float)(S - 1));
+    if (lo > hi) return 0u;
+    const int c0 = (int)lo, c1 = (int)hi;
+    return ((1u << (c1 + 1)) - 1u) & ~((1u << c0) - 1u);
+}
+
 __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t n,
                                                        int tile, const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ offsets, int64_t n_records,
@@ -376,30 +422,18 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
         if (nt && off < w1 && off + (int64_t)nt > w0) {
             int64_t pos = off;
             const int S = sub ? tile / sub : 0;  // sub-tiles per tile edge
+            const BandsF bf = bands_of(er);
             for (int ty = y0; ty <= y1 && pos < w1; ++ty) {
                 int cl, ch;
                 if (!row_span(er, *vw, tile, ty, x0, x1, cl, ch)) continue;
-                int blo[4], bhi[4];  // 8-pixel column span of each sub-row (empty: blo > bhi)
-                if (S) {
-                    for (int r = 0; r < S; ++r) {
-                        const int y8 = ty * S + r;
-                        blo[r] = 1; bhi[r] = 0;
-                        if (y8 * sub < vw->height) {
-                            int lo8, hi8;
-                            if (row_span(er, *vw, sub, y8, cl * S, ch * S + S - 1, lo8, hi8)) { blo[r] = lo8; bhi[r] = hi8; }
-                        }
-                    }
-                }
+                float bmin[4], bmax[4];
+                for (int r = 0; r < S; ++r) band_extent(bf, sub, ty * S + r, vw->height, bmin[r], bmax[r]);
                 for (int tx = cl; tx <= ch && pos < w1; ++tx, ++pos) {
                     if (pos < w0) continue;
                     uint32_t key = (uint32_t)(vw->tile_off + (int64_t)ty * vw->tiles_x + tx);
                     if (S) {
                         uint32_t m = 0;
-                        for (int r = 0; r < S; ++r)
-                            for (int c = 0; c < S; ++c) {
-                                const int x8 = tx * S + c;
-                                m |= (uint32_t)(x8 >= blo[r] && x8 <= bhi[r]) << (r * S + c);
-                            }
+                        for (int r = 0; r < S; ++r) m |= band_bits(bmin[r], bmax[r], sub, tx, S) << (r * S);
                         key |= m << 16;
                     }
                     w_tile[pos - w0] = key;
