@@ -462,9 +462,22 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Without the work queue, workgroup b runs item xcd_item(b): the hardware deals consecutive
+// workgroups round-robin to the 8 XCDs, so this hands each XCD one contiguous run of sub-tiles
+// (one band of the image), and the gradient atomics of neighbouring sub-tiles, which hit the same
+// records, meet in the same XCD's L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n_items) {
+    const int64_t per = n_items / kXcds, rem = n_items % kXcds;
+    const int64_t x = b % kXcds, k = b / kXcds;
+    // XCD x owns items [x per + min(x, rem), ...) of length per + (x < rem); the grid has exactly
+    // n_items workgroups, so XCD x receives exactly that many
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 __device__ __forceinline__ int64_t next_item(const BlendArgs& a, int64_t prev, bool persistent, int64_t n_items,
                                              uint32_t* slot) {
-    if (!persistent) return prev < 0 ? (int64_t)blockIdx.x : n_items;
+    if (!persistent) return prev < 0 ? xcd_item((int64_t)blockIdx.x, n_items) : n_items;
     __syncthreads();
     if (threadIdx.x == 0) *slot = atomicAdd(a.queue, 1u);
     __syncthreads();

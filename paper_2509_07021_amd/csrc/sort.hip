@@ -362,7 +362,9 @@ __device__ __forceinline__ void band_extent(const BandsF& f, int sub, int y8, in
     dh = fminf(dh, f.ry);
     if (dl > dh) return;
     const float d1 = fminf(fmaxf(f.dys, dl), dh), d2 = fminf(fmaxf(-f.dys, dl), dh);
-    const float s1 = sqrtf(fmaxf(f.ka - f.det * d1 * d1, 0.0f)), s2 = sqrtf(fmaxf(f.ka - f.det * d2 * d2, 0.0f));
+    // hardware square root (about 1 ulp): the quarter-pixel margin dwarfs its error
+    const float s1 = __builtin_amdgcn_sqrtf(fmaxf(f.ka - f.det * d1 * d1, 0.0f));
+    const float s2 = __builtin_amdgcn_sqrtf(fmaxf(f.ka - f.det * d2 * d2, 0.0f));
     xmax = f.u + (s1 - f.b * d1) * f.ia + kMargin;
     xmin = f.u - (s2 + f.b * d2) * f.ia - kMargin;
 }
@@ -370,9 +372,9 @@ __device__ __forceinline__ void band_extent(const BandsF& f, int sub, int y8, in
 // Bits of the sub-columns of tile column tx whose pixel-centre range meets [xmin, xmax].
 __device__ __forceinline__ uint32_t band_bits(float xmin, float xmax, int sub, int tx, int S) {
     if (xmin > xmax) return 0u;
-    const float x0 = (float)(tx * S * sub);
-    const float lo = fmaxf(ceilf((xmin + 0.5f - x0) / sub - 1.0f), 0.0f);
-    const float hi = fminf(floorf((xmax - 0.5f - x0) / sub), (float)(S - 1));
+    const float x0 = (float)(tx * S * sub), isub = 1.0f / (float)sub;  // sub is a power of two
+    const float lo = fmaxf(ceilf((xmin + 0.5f - x0) * isub - 1.0f), 0.0f);
+    const float hi = fminf(floorf((xmax - 0.5f - x0) * isub), (float)(S - 1));
     if (lo > hi) return 0u;
     const int c0 = (int)lo, c1 = (int)hi;
     return ((1u << (c1 + 1)) - 1u) & ~((1u << c0) - 1u);
@@ -426,6 +428,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
             for (int ty = y0; ty <= y1 && pos < w1; ++ty) {
                 int cl, ch;
                 if (!row_span(er, *vw, tile, ty, x0, x1, cl, ch)) continue;
+                if (pos + (ch - cl + 1) <= w0) {  // the whole row lies before this window
+                    pos += ch - cl + 1;
+                    continue;
+                }
                 float bmin[4], bmax[4];
                 for (int r = 0; r < S; ++r) band_extent(bf, sub, ty * S + r, vw->height, bmin[r], bmax[r]);
                 for (int tx = cl; tx <= ch && pos < w1; ++tx, ++pos) {
