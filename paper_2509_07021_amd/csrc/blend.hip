@@ -462,17 +462,18 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Without the work queue, workgroup b runs item xcd_item(b): the hardware deals consecutive
-// workgroups round-robin to the 8 XCDs, so this hands each XCD one contiguous run of sub-tiles
-// (one band of the image), and the gradient atomics of neighbouring sub-tiles, which hit the same
-// records, meet in the same XCD's L2.
+// Without the work queue, workgroup b runs item xcd_item(b). The hardware deals consecutive
+// workgroups round-robin to the 8 XCDs; this hands each XCD runs of kXcdRun consecutive items
+// (whole tiles' worth of sub-tiles), so the sub-tiles of a tile, which gather the same records,
+// share one XCD's L2, while neighbouring runs go to different XCDs and the load stays balanced.
+// Full groups of 8 kXcdRun items are permuted; a partial last group keeps identity order.
 constexpr int kXcds = 8;
+constexpr int64_t kXcdRun = 64;
 __device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n_items) {
-    const int64_t per = n_items / kXcds, rem = n_items % kXcds;
+    const int64_t full = n_items / (kXcds * kXcdRun) * (kXcds * kXcdRun);
+    if (b >= full) return b;
     const int64_t x = b % kXcds, k = b / kXcds;
-    // XCD x owns items [x per + min(x, rem), ...) of length per + (x < rem); the grid has exactly
-    // n_items workgroups, so XCD x receives exactly that many
-    return x * per + (x < rem ? x : rem) + k;
+    return ((k / kXcdRun) * kXcds + x) * kXcdRun + k % kXcdRun;
 }
 
 __device__ __forceinline__ int64_t next_item(const BlendArgs& a, int64_t prev, bool persistent, int64_t n_items,
