@@ -7,11 +7,13 @@ masks. Two forms are measured:
     ring of radius 6, forward+backward of all views captured once in a hipGraph and replayed;
   * `plain_fp32`: the same scene in FP32, one 1920x1080 view, eager launches.
 A step is one whole forward+backward of the workload's views. Inputs are resident in HBM before
-the timed region. Each stage's kernels are also timed live with HIP events (eager calls of the
-same workload); the slowest stage gives the roofline line. The FP64 CPU oracle is timed on two of
-the headline workload's views.
+the timed region. Default launch configuration: 32x32 tiles for the key table, blending per 8x8
+sub-tile. Each stage's kernels are also timed live with HIP events (eager calls of the same
+workload); the slowest stage gives the roofline line. The FP64 CPU oracle is timed on the headline
+workload's views (all 8 by default). Also reported: the post-processing of a post-ADMM scene and
+an SG-versus-SH colour comparison on the same renderer (skip with --no-post).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-post]
 """
 from __future__ import annotations
 
