@@ -462,23 +462,26 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Without the work queue, workgroup b runs item xcd_item(b). The hardware deals consecutive
-// workgroups round-robin to the 8 XCDs; this hands each XCD runs of kXcdRun consecutive items
-// (whole tiles' worth of sub-tiles), so the sub-tiles of a tile, which gather the same records,
-// share one XCD's L2, while neighbouring runs go to different XCDs and the load stays balanced.
-// Full groups of 8 kXcdRun items are permuted; a partial last group keeps identity order.
+// Without the work queue, the forward's workgroup b runs item xcd_item(b): the hardware deals
+// consecutive workgroups round-robin to the 8 XCDs, and this hands each XCD one contiguous eighth
+// of the sub-tiles (with 8 views, one view each), so the records an XCD gathers stay in its own L2.
+// The backward keeps identity order, which measured faster for it: its time goes to the gradient
+// atomics, which are executed beyond the L2 anyway.
 constexpr int kXcds = 8;
-constexpr int64_t kXcdRun = 64;
 __device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n_items) {
-    const int64_t full = n_items / (kXcds * kXcdRun) * (kXcds * kXcdRun);
-    if (b >= full) return b;
+    const int64_t per = n_items / kXcds, rem = n_items % kXcds;
     const int64_t x = b % kXcds, k = b / kXcds;
-    return ((k / kXcdRun) * kXcds + x) * kXcdRun + k % kXcdRun;
+    // XCD x owns items [x per + min(x, rem), ...) of length per + (x < rem); the grid has exactly
+    // n_items workgroups, so XCD x receives exactly that many
+    return x * per + (x < rem ? x : rem) + k;
 }
 
 __device__ __forceinline__ int64_t next_item(const BlendArgs& a, int64_t prev, bool persistent, int64_t n_items,
-                                             uint32_t* slot) {
-    if (!persistent) return prev < 0 ? xcd_item((int64_t)blockIdx.x, n_items) : n_items;
+                                             uint32_t* slot, bool by_xcd) {
+    if (!persistent) {
+        if (prev >= 0) return n_items;
+        return by_xcd ? xcd_item((int64_t)blockIdx.x, n_items) : (int64_t)blockIdx.x;
+    }
     __syncthreads();
     if (threadIdx.x == 0) *slot = atomicAdd(a.queue, 1u);
     __syncthreads();
@@ -520,8 +523,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
     const int lane = __lane_id();
     const int64_t n_items = a.n_tiles * (int64_t)(tile / SUB) * (tile / SUB);
     uint32_t n_blended = 0, n_evaluated = 0;
-    for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot); w < n_items;
-         w = next_item(a, w, persistent, n_items, &work_slot)) {
+    for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot, true); w < n_items;
+         w = next_item(a, w, persistent, n_items, &work_slot, true)) {
         const SubCtx q = sub_ctx(a, w, tile);
         const TileCtx& c = q.c;
         const int lx = q.sx + (lane & 7), ly = q.sy + (lane >> 3);
@@ -618,8 +621,8 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
     __shared__ uint32_t work_slot;
     const int lane = __lane_id();
     const int64_t n_items = a.n_tiles * (int64_t)(tile / SUB) * (tile / SUB);
-    for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot); w < n_items;
-         w = next_item(a, w, persistent, n_items, &work_slot)) {
+    for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot, false); w < n_items;
+         w = next_item(a, w, persistent, n_items, &work_slot, false)) {
         const SubCtx q = sub_ctx(a, w, tile);
         const TileCtx& c = q.c;
         const int lx = q.sx + (lane & 7), ly = q.sy + (lane >> 3);
