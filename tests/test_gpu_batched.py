@@ -115,19 +115,18 @@ def _sampled_tiles(ranges, frac, seed):
     return pick, rs
 
 
-def test_full_size_masked_1m_1080p_sampled():
-    """The 1M-Gaussian 1080p masked workload in the benchmark's launch configuration: the whole key
-    table bit-exact; blend, blend backward and projection backward on a seeded sample of tiles
-    (the loss weights vanish outside them, so the GPU's gradients come from the same pixels)."""
-    scene, cams = S.make_workload("masked_1m_1080p")
-    cam = cams[0]
-    tile = 16
-    log("full-size masked 1M 1080p: forward")
+def _full_size_sampled(scene, cams, cfg, frac, seed):
+    """A full-size workload in a given launch configuration: the whole key table bit-exact against
+    the oracle's (built from the GPU's own records); blend, blend backward and projection backward
+    on a seeded sample of tiles (the loss weights vanish outside them, so the GPU's gradients come
+    from the same pixels)."""
+    tile = cfg.tile
+    nv = len(cams)
     ds = R.DeviceScene.from_scene(scene)
-    fr = R.forward(ds, cams, R.Config(tile, 64))
+    fr = R.forward(ds, cams, cfg)
     torch.cuda.synchronize()
     g = {"n_pairs": int(fr.state.n_pairs)}
-    nr = scene.n
+    nr = scene.n * nv
     g["mean"] = fr.buffer("mean", 2 * nr, torch.float64).view(nr, 2).cpu().numpy()
     g["conic_o"] = fr.buffer("conic_o", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
     g["rgbd"] = fr.buffer("rgbd", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
@@ -139,40 +138,66 @@ def test_full_size_masked_1m_1080p_sampled():
     T = int(fr.state.n_tiles)
     ranges = fr.buffer("ranges", 2 * T, torch.int32).view(T, 2).cpu().numpy().view(np.uint32)
     rec = gpu_records(g)
-    log(f"key table: {P} pairs")
-    keys, ovals, oranges, _ = O.pairs(rec["u"], rec["v"], g["rgbd"][:, 3], rec["radius"], rec["conic"],
-                                      rec["cutoff"], rec["valid"], np.zeros(nr, np.int32), [cam], tile)
+    log(f"key table: {P} pairs over {nv} views")
+    rec_view = np.repeat(np.arange(nv, dtype=np.int32), scene.n)
+    keys, ovals, oranges, off = O.pairs(rec["u"], rec["v"], g["rgbd"][:, 3], rec["radius"], rec["conic"],
+                                        rec["cutoff"], rec["valid"], rec_view, cams, tile)
     assert len(keys) == P
     np.testing.assert_array_equal(vals, ovals)
     np.testing.assert_array_equal(ranges, oranges)
+    if cfg.subtile:
+        tkeys = tkeys & np.uint32(0xFFFF)   # the upper half carries the sub-tile flags
     np.testing.assert_array_equal(tkeys, (keys >> np.uint64(32)).astype(np.uint32))
-    pick, rs = _sampled_tiles(ranges, 0.02, 5)
+    pick, rs = _sampled_tiles(ranges, frac, seed)
     log(f"blend on {pick.sum()} sampled tiles")
-    ob = O.blend(cam, tile, rec, vals, rs)
-    img = fr.images.view(3, cam.height, cam.width).cpu().numpy().astype(np.float64)
-    tx = (cam.width + tile - 1) // tile
-    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
-    in_pick = pick[(ys // tile) * tx + xs // tile]
-    ok = in_pick & (ob["flag"] == 0)
-    assert ok.sum() > 10000
-    assert np.abs(img - ob["image"])[:, ok].max() <= IMG_TOL
-    # backward on the sampled tiles only
-    w = S.loss_weights([cam], 21)[0] * ok[None].astype(np.float32)
+    images = R.split_images(fr.images, cams)
+    weights, oks = [], []
+    for vi, cam in enumerate(cams):
+        ob = O.blend(cam, tile, rec, vals, rs[off[vi]:off[vi + 1]])
+        img = images[vi].cpu().numpy().astype(np.float64)
+        tx = (cam.width + tile - 1) // tile
+        ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+        in_pick = pick[off[vi]:off[vi + 1]][(ys // tile) * tx + xs // tile]
+        ok = in_pick & (ob["flag"] == 0)
+        assert ok.sum() > 2000
+        assert np.abs(img - ob["image"])[:, ok].max() <= IMG_TOL, vi
+        weights.append(S.loss_weights([cam], 21 + vi)[0] * ok[None].astype(np.float32))
     nb = len(fr.alloc.blocks)
-    grads = R.backward(ds, fr, torch.from_numpy(w.reshape(-1)).cuda())
+    dl = torch.from_numpy(np.concatenate([w.reshape(-1) for w in weights])).cuda()
+    grads = R.backward(ds, fr, dl)
     torch.cuda.synchronize()
     g2 = fr.alloc.blocks[nb][: nr * 36].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
     ref = np.zeros_like(g2)
     ref_abs = np.zeros_like(g2)
-    O.blend_backward(cam, tile, rec, vals, rs, w, grad2d=ref, grad2d_abs=ref_abs)
+    for vi, cam in enumerate(cams):
+        O.blend_backward(cam, tile, rec, vals, rs[off[vi]:off[vi + 1]], weights[vi], grad2d=ref, grad2d_abs=ref_abs)
     for c, name in enumerate(("u", "v", "a", "b", "c", "o", "r", "g", "b_col")):
         grad_close(f"grad2d[{name}]", g2[:, c], ref[:, c], abs_sum=ref_abs[:, c])
     pl = scene.widened()
     gr = O.zero_grads(pl)
-    O.project_backward(pl, scene.k, cam, tile, g2, gr)
+    for vi, cam in enumerate(cams):
+        O.project_backward(pl, scene.k, cam, tile, g2[vi * scene.n:(vi + 1) * scene.n], gr)
     for p in O.PLANES:
         if gr[p] is not None:
             grad_close(f"raw {p}", grads[p].cpu().numpy().astype(np.float64), gr[p])
+
+
+def test_full_size_masked_1m_1080p_sampled():
+    """The 1M-Gaussian 1080p masked workload (FP32, one view), per-tile blending at 16x16."""
+    scene, cams = S.make_workload("masked_1m_1080p")
+    log("full-size masked 1M 1080p, 16x16 tiles")
+    _full_size_sampled(scene, cams, R.Config(16, 64), 0.02, 5)
+
+
+def test_full_size_headline_in_bench_configuration():
+    """The benchmark's headline: the masked 1M scene stored in FP16 (BF16 amplitudes), 8 views at
+    1920x1080 on a ring, in the benchmark's launch configuration (32x32 tiles, 8x8 sub-tile
+    blending)."""
+    scene, _ = S.make_workload("masked_1m_1080p")
+    scene16 = scene.stored("f16", "f16", "bf16")
+    cams = S.ring_cameras(8, seed=5)
+    log("full-size headline: FP16, 8 x 1080p, 32x32 tiles, 8x8 sub-tiles")
+    _full_size_sampled(scene16, cams, R.Config(32, 64, subtile=8), 0.01, 6)
 
 
 def test_fp16_3m_subsample_all_views():
