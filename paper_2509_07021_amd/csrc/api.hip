@@ -350,7 +350,8 @@ megs_status enqueue_front(const megs_scene* sc, const Layout& L, const megs_conf
     }
     {
         StageTimer t(MEGS_STAGE_SCAN, s);
-        HIP_TRY(launch_scan(f.rec.ntiles, f.order, L.nr, f.offs, f.counters + 0, f.scan_scratch, s));
+        // the depth keys' ping-pong buffer is free after the sort: it takes the gathered tile counts
+        HIP_TRY(launch_scan(f.rec.ntiles, f.order, L.nr, f.offs, f.counters + 0, f.scan_scratch, s, f.dkey_alt));
     }
     return MEGS_OK;
 }

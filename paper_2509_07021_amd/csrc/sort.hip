@@ -74,12 +74,19 @@ __device__ __forceinline__ uint32_t scan_load(const uint32_t* x, const uint32_t*
     return x[idx ? idx[i] : i];
 }
 
+// Per-workgroup totals. With an index list, the gathered values x[idx[i]] are also stored densely
+// to `gathered` (when given), so the second pass reads them without gathering again.
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* x, const uint32_t* idx, int64_t n,
-                                                              uint32_t* partial) {
+                                                              uint32_t* partial, uint32_t* gathered) {
     __shared__ uint32_t lds[4];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     uint32_t s = 0;
-    for (int j = 0; j < kScanIpt; ++j) s += scan_load(x, idx, base + j * kScanThreads + threadIdx.x, n);
+    for (int j = 0; j < kScanIpt; ++j) {
+        const int64_t i = base + j * kScanThreads + threadIdx.x;
+        const uint32_t v = scan_load(x, idx, i, n);
+        if (gathered && i < n) gathered[i] = v;
+        s += v;
+    }
     uint32_t total;
     block_excl_scan256(s, lds, total);
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
@@ -134,11 +141,13 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
     return (uint32_t)(key >> shift) & mask;
 }
 
-// Lanes of the wave holding the same 8-bit digit as this lane, restricted to `valid`.
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
+// Lanes of the wave holding the same digit as this lane, restricted to `valid` (mask: the
+// pass's digit mask, at most 8 bits).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid, uint32_t mask) {
     uint64_t peers = valid;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
+        if (!((mask >> b) & 1u)) break;
         const bool bit = (d >> b) & 1u;
         const uint64_t bal = __ballot(bit);
         peers &= bit ? bal : ~bal;
@@ -165,19 +174,32 @@ template <typename K>
 __global__ __launch_bounds__(kRsThreads) void k_radix_upsweep(const K* __restrict__ keys, const uint32_t* d_count,
                                                               int64_t max_count, int shift, uint32_t mask,
                                                               uint32_t* __restrict__ counts) {
+    // Digit counts of the workgroup's chunk (order does not matter here): per-wave LDS histograms
+    // updated with LDS atomics, or with one add when the whole 64-key step shares its digit.
+    constexpr int U = 8;
     __shared__ uint32_t hist[kRsWaves][kRsDigits];
     const int w = threadIdx.x / kWave, lane = __lane_id();
     for (int i = threadIdx.x; i < kRsWaves * kRsDigits; i += kRsThreads) (&hist[0][0])[i] = 0u;
     __syncthreads();
     const Chunk c = chunk_of(d_count, max_count);
-    for (int64_t t = c.t0; t < c.t1; ++t) {
-        const int64_t base = t * kRsTile + (int64_t)w * kWave * kRsIpt + lane;
-        for (int j = 0; j < kRsIpt; ++j) {
-            const int64_t idx = base + j * kWave;
-            const bool ok = idx < c.n;
-            const uint32_t d = ok ? digit_of(keys[idx], shift, mask) : 0u;
-            const uint64_t peers = match_digit(d, __ballot(ok));
-            if (ok && (__ffsll((unsigned long long)peers) - 1) == lane) hist[w][d] += (uint32_t)__popcll(peers);
+    const int64_t i1 = c.t1 * kRsTile < c.n ? c.t1 * kRsTile : c.n;
+    for (int64_t base = c.t0 * kRsTile + (int64_t)w * kWave * U; base < i1; base += (int64_t)kRsThreads * U) {
+        uint32_t d[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t idx = base + u * kWave + lane;
+            d[u] = idx < i1 ? digit_of(keys[idx], shift, mask) : 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t valid = __ballot(d[u] != 0xffffffffu);
+            if (!valid) break;  // positions rise with u and lane: nothing valid after this step
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d[u]);  // lane 0 is valid here
+            if (__ballot(d[u] == d0) == valid) {
+                if (lane == 0) atomicAdd(&hist[w][d0], (uint32_t)__popcll(valid));
+            } else if (d[u] != 0xffffffffu) {
+                atomicAdd(&hist[w][d[u]], 1u);
+            }
         }
     }
     __syncthreads();
@@ -237,6 +259,15 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_downsweep(const K* __restr
         run_off[threadIdx.x] = digit_base + offsets[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
     }
     const Chunk c = chunk_of(d_count, max_count);
+    // a pass whose digit is the same for every key is the identity permutation: copy the chunk
+    if (__syncthreads_or(totals[threadIdx.x] == (uint32_t)c.n && c.n > 0)) {
+        const int64_t i1 = c.t1 * kRsTile < c.n ? c.t1 * kRsTile : c.n;
+        for (int64_t i = c.t0 * kRsTile + threadIdx.x; i < i1; i += kRsThreads) {
+            keys_out[i] = keys_in[i];
+            vals_out[i] = vals_in[i];
+        }
+        return;
+    }
     const uint64_t lt = lanemask_lt();
     for (int64_t t = c.t0; t < c.t1; ++t) {
         for (int i = threadIdx.x; i < kRsWaves * kRsDigits; i += kRsThreads) (&whist[0][0])[i] = 0u;
@@ -251,7 +282,7 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_downsweep(const K* __restr
             val[j] = ok ? vals_in[idx] : 0u;
             const uint32_t d = ok ? digit_of(key[j], shift, mask) : 0u;
             dig[j] = ok ? d : 0xffffffffu;
-            const uint64_t peers = match_digit(d, __ballot(ok));
+            const uint64_t peers = match_digit(d, __ballot(ok), mask);
             uint32_t before = 0;
             if (ok) before = whist[w][d];
             rank[j] = before + (uint32_t)__popcll(peers & lt);
@@ -283,6 +314,7 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_downsweep(const K* __restr
             const K k = stage_k[i];
             const uint32_t d = digit_of(k, shift, mask);
             const uint32_t dst = run_off[d] + (i - tile_start[d]);
+            if ((int64_t)dst >= c.n) continue;  // unreachable when the digit counts are consistent
             keys_out[dst] = k;
             vals_out[dst] = stage_v[i];
         }
@@ -545,15 +577,21 @@ size_t scan_scratch_bytes(int64_t n) {
 }
 
 hipError_t launch_scan(const uint32_t* x, const uint32_t* idx, int64_t n, uint32_t* out, uint32_t* total,
-                       void* scratch, hipStream_t stream) {
+                       void* scratch, hipStream_t stream, uint32_t* gathered) {
     if (n <= 0) {
         return launch_fill_u32(total, 0u, 1, stream);
     }
     const int64_t blocks = (n + kScanTile - 1) / kScanTile;
     uint32_t* partial = static_cast<uint32_t*>(scratch);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream, x, idx, n, partial);
+    uint32_t* g = idx ? gathered : nullptr;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream, x, idx, n, partial, g);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, stream, partial, blocks, total);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream, x, idx, n, partial, out);
+    if (g)
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream,
+                           static_cast<const uint32_t*>(g), static_cast<const uint32_t*>(nullptr), n, partial, out);
+    else
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream, x, idx, n, partial,
+                           out);
     return hipGetLastError();
 }
 
