@@ -416,9 +416,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                         if (lane == 1) slot[8] = tot8;
                         continue;
                     }
-                    float* slot = a.grad2d + 9 * (int64_t)lds_id[jj];
-                    if ((lane & 7) == 0) unsafeAtomicAdd(slot + (lane >> 3), tot);
-                    if (lane == 1) unsafeAtomicAdd(slot + 8, tot8);
+                    // one 9-lane atomic: lanes 0, 8, .., 56 add sums 0..7, lane 1 adds sum 8
+                    if ((lane & 7) == 0 || lane == 1)
+                        unsafeAtomicAdd(a.grad2d + 9 * (int64_t)lds_id[jj] + (lane == 1 ? 8 : lane >> 3),
+                                        lane == 1 ? tot8 : tot);
                 } else {
                     // per-wave partial sums to LDS; summed across waves after the batch
                     float tot = 0.f, tot8 = 0.f;
@@ -567,6 +568,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                     const int k = k0 + kk;
                     if (k >= nhit) break;
                     const Staged s = lds[k];
+                    const uint32_t posk = lds_pos[k];
                     float dx, dy, G, alpha;
                     bool clamped;
                     const bool pass = frag(s, px, py, dx, dy, G, alpha, clamped) & (T > 0.0f);
@@ -580,7 +582,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                     C1 = __fmaf_rn(wgt, s.p2.z, C1);
                     C2 = __fmaf_rn(wgt, s.p2.w, C2);
                     T = incl ? Tn : (term ? -T : T);
-                    last = incl ? lds_pos[k] + 1 : last;
+                    last = incl ? posk + 1 : last;
                     if (STATS) n_blended += incl;
                     if (IMP) {
                         float wsum = wgt;
@@ -624,9 +626,12 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
     constexpr int SUB = 8;
     __shared__ Staged lds[64];
     __shared__ uint32_t lds_pos[64];
-    __shared__ uint32_t lds_id[64];
+    __shared__ uint64_t lds_slot[64];  // 9 x record id: the record's first gradient element
     __shared__ uint32_t work_slot;
     const int lane = __lane_id();
+    // the 9 sums leave through one 9-lane atomic: lanes 0, 8, .., 56 hold sums 0..7, lane 1 sum 8
+    const bool adds = (lane & 7) == 0 || lane == 1;
+    const int comp = lane == 1 ? 8 : lane >> 3;
     const int64_t n_items = a.n_tiles * (int64_t)(tile / SUB) * (tile / SUB);
     for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot, false); w < n_items;
          w = next_item(a, w, persistent, n_items, &work_slot, false)) {
@@ -675,7 +680,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 const int slot = lane_rank(m);
                 lds[slot] = st;
                 lds_pos[slot] = idx - rg.x;
-                lds_id[slot] = g;
+                lds_slot[slot] = 9ull * g;
             }
             wave_sync();
             for (int k = 0; k < nhit; ++k) {
@@ -709,9 +714,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 acc[4] = hq * (dy * dy);
                 float tot, tot8;
                 wave_sum9(acc, tot, tot8);
-                float* slot = a.grad2d + 9 * (int64_t)lds_id[k];
-                if ((lane & 7) == 0) unsafeAtomicAdd(slot + (lane >> 3), tot);
-                if (lane == 1) unsafeAtomicAdd(slot + 8, tot8);
+                if (adds) unsafeAtomicAdd(a.grad2d + (lds_slot[k] + comp), lane == 1 ? tot8 : tot);
             }
             wave_sync();
             end = beg;

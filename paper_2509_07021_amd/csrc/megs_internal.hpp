@@ -234,10 +234,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 hipError_t launch_iota(uint32_t* p, int64_t count, hipStream_t stream);
 
 // Exclusive scan of x[idx[i]] (idx may be null) for i < n (n given on host), writing out[i];
-// total written to *total (device). scratch: scan_scratch_bytes(n).
+// total written to *total (device). scratch: scan_scratch_bytes(n). With idx, `gathered` (n
+// entries, optional) receives the gathered values, which saves the second pass a gather.
 size_t scan_scratch_bytes(int64_t n);
-// Exclusive scan of x[idx[i]] (or x[i] without idx). `gathered` (n entries, optional) receives the
-// gathered values, which saves the second pass a gather.
 hipError_t launch_scan(const uint32_t* x, const uint32_t* idx, int64_t n, uint32_t* out, uint32_t* total,
                        void* scratch, hipStream_t stream, uint32_t* gathered = nullptr);
 

@@ -4,8 +4,8 @@
 // The radix sort is reduce-then-scan with a fixed grid: each workgroup owns a contiguous chunk of
 // the input, so the per-pass digit counts form a [256][G] table whose digit-major exclusive scan
 // gives every workgroup its scatter base per digit. Ranks inside a workgroup are stable: each
-// wave64 owns a contiguous segment of a 2048-item tile, equal digits within a 64-item step are
-// found with eight 64-bit ballots, and per-wave running counts live in LDS. There are no
+// wave64 owns a contiguous segment of a 4096-item tile, equal digits within a 64-item step are
+// found with one 64-bit ballot per digit bit, and per-wave running counts live in LDS. There are no
 // inter-workgroup waits, so no pass depends on forward progress of other workgroups. The element
 // count is read on device, which lets the same launches run inside a captured graph.
 #include "megs_internal.hpp"
@@ -19,10 +19,10 @@ constexpr int kScanTile = kScanThreads * kScanIpt;  // 2048
 
 constexpr int kRsThreads = 256;
 constexpr int kRsWaves = kRsThreads / kWave;
-constexpr int kRsIpt = 8;
-constexpr int kRsTile = kRsThreads * kRsIpt;  // 2048
+constexpr int kRsIpt = 16;
+constexpr int kRsTile = kRsThreads * kRsIpt;  // 4096
 constexpr int kRsDigits = 256;
-constexpr int kRsMaxBlocks = 1024;
+constexpr int kRsMaxBlocks = 2048;
 static_assert(kRsThreads == kRsDigits, "the downsweep maps one thread to one digit");
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
