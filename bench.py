@@ -32,9 +32,12 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (packed); the unpacked FMA cei
 # Algorithmic FP32 operations per fragment (FMA = 2, add/mul/compare/exp = 1):
 #   alpha test of an evaluated fragment (offsets, quadratic form, exp, opacity, clamp, threshold): 15
 #   forward blend of an included fragment (transmittance, weight, colour accumulate): 10
-#   backward of an included fragment (transmittance recovery, colour/alpha/conic/mean/opacity
-#   gradients, background recursion, summation over pixels): 58
-FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 58
+#   backward of an included fragment: transmittance recovery (1 - alpha, divide) 2, weight 1,
+#   colour gradient 3, colour minus background 3, alpha gradient (dot product, times T) 6,
+#   background recursion (3 FMA) 6, exponent gradient 1, opacity gradient 1, the five moments of
+#   the exponent gradient (dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2) 5, summation of the 9 sums
+#   over pixels 9: 37 (the conic is applied to the moments once per record, not per fragment)
+FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 37
 
 # HBM bytes per launch of a kernel on the headline workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a plain

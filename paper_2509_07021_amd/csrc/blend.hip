@@ -397,12 +397,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                             const float dq = live ? al * dal : 0.0f;
                             const float dx = dxs[j], dy = dys[j];
                             acc[5] = __fmaf_rn(live ? G[j] : 0.0f, dal, acc[5]);
-                            acc[0] = __fmaf_rn(dq, __fmaf_rn(s.p1.z, dx, s.p1.w * dy), acc[0]);
-                            acc[1] = __fmaf_rn(dq, __fmaf_rn(s.p1.w, dx, s.p2.x * dy), acc[1]);
-                            const float hq = -0.5f * dq;
-                            acc[2] = __fmaf_rn(hq, dx * dx, acc[2]);
-                            acc[3] = __fmaf_rn(-dq, dx * dy, acc[3]);
-                            acc[4] = __fmaf_rn(hq, dy * dy, acc[4]);
+                            const float mx = dq * dx, my = dq * dy;
+                            acc[0] += mx;
+                            acc[1] += my;
+                            acc[2] = __fmaf_rn(mx, dx, acc[2]);
+                            acc[3] = __fmaf_rn(mx, dy, acc[3]);
+                            acc[4] = __fmaf_rn(my, dy, acc[4]);
                         }
                     }
                 }
@@ -706,12 +706,11 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 const bool live = incl & !clamped;
                 const float dq = live ? al * dal : 0.0f;
                 acc[5] = (live ? G : 0.0f) * dal;
-                acc[0] = dq * __fmaf_rn(s.p1.z, dx, s.p1.w * dy);
-                acc[1] = dq * __fmaf_rn(s.p1.w, dx, s.p2.x * dy);
-                const float hq = -0.5f * dq;
-                acc[2] = hq * (dx * dx);
-                acc[3] = -dq * (dx * dy);
-                acc[4] = hq * (dy * dy);
+                acc[0] = dq * dx;
+                acc[1] = dq * dy;
+                acc[2] = acc[0] * dx;
+                acc[3] = acc[0] * dy;
+                acc[4] = acc[1] * dy;
                 float tot, tot8;
                 wave_sum9(acc, tot, tot8);
                 if (adds) unsafeAtomicAdd(a.grad2d + (lds_slot[k] + comp), lane == 1 ? tot8 : tot);

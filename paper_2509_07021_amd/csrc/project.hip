@@ -419,8 +419,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo
                 ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
         }
         if (!ok) continue;
+        // the blend leaves the moments of dL/dq over the footprint (dq = dL/dq per fragment, q the
+        // Gaussian's exponent, (dx, dy) the pixel offset from the mean): sum dq dx, dq dy, dq dx^2,
+        // dq dx dy, dq dy^2. With q = -(a dx^2 + 2 b dx dy + c dy^2) / 2, the gradients of the pixel
+        // mean and of the conic (a, b, c) follow here, once per record.
         const float* gr = grad2d + 9 * r;
-        const float gu = gr[0], gv = gr[1], ga = gr[2], gb = gr[3], gc = gr[4], go = gr[5];
+        const float gu = p.conic[0] * gr[0] + p.conic[1] * gr[1];
+        const float gv = p.conic[1] * gr[0] + p.conic[2] * gr[1];
+        const float ga = -0.5f * gr[2], gb = -gr[3], gc = -0.5f * gr[4], go = gr[5];
         const float gcol[3] = {gr[6], gr[7], gr[8]};
 
         // colour

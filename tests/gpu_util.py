@@ -56,8 +56,26 @@ def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
         torch.cuda.synchronize()
         out["grads"] = {p: (None if g is None else g.cpu().numpy().astype(np.float64)) for p, g in grads.items()}
         g2 = fr.alloc.blocks[nblocks]
-        out["grad2d"] = g2[: nr * 9 * 4].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
+        moments = g2[: nr * 9 * 4].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
+        out["grad2d_moments"] = moments
+        conic = out["conic_o"][:, :3].astype(np.float64) if nr else np.zeros((0, 3))
+        out["grad2d"] = grad2d_from_moments(moments, conic)
     return out
+
+
+def grad2d_from_moments(m: np.ndarray, conic: np.ndarray) -> np.ndarray:
+    """The library's per-record backward buffer holds, per record, the sums over its fragments of
+    dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2 (dq the loss gradient of the Gaussian's exponent
+    q = -(a dx^2 + 2 b dx dy + c dy^2) / 2), then the opacity and RGB gradients. This returns the
+    gradients of (u, v, a, b, c, o, r, g, b) that the oracle's blend backward produces."""
+    g = np.array(m, dtype=np.float64, copy=True)
+    a, b, c = conic[:, 0], conic[:, 1], conic[:, 2]
+    g[:, 0] = a * m[:, 0] + b * m[:, 1]
+    g[:, 1] = b * m[:, 0] + c * m[:, 1]
+    g[:, 2] = -0.5 * m[:, 2]
+    g[:, 3] = -m[:, 3]
+    g[:, 4] = -0.5 * m[:, 4]
+    return g
 
 
 def gpu_records(g: dict) -> dict:

@@ -8,7 +8,7 @@ from paper_2509_07021_amd import _lib as L
 from paper_2509_07021_amd import render as R
 from paper_2509_07021_amd import scenes as S
 
-from gpu_util import IMG_TOL, grad_close, gpu_records, gpu_run, log
+from gpu_util import IMG_TOL, grad2d_from_moments, grad_close, gpu_records, gpu_run, log
 
 pytestmark = pytest.mark.gpu
 
@@ -166,7 +166,8 @@ def _full_size_sampled(scene, cams, cfg, frac, seed):
     dl = torch.from_numpy(np.concatenate([w.reshape(-1) for w in weights])).cuda()
     grads = R.backward(ds, fr, dl)
     torch.cuda.synchronize()
-    g2 = fr.alloc.blocks[nb][: nr * 36].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
+    g2 = grad2d_from_moments(fr.alloc.blocks[nb][: nr * 36].view(torch.float32).view(nr, 9).cpu().numpy(),
+                             rec["conic"])
     ref = np.zeros_like(g2)
     ref_abs = np.zeros_like(g2)
     for vi, cam in enumerate(cams):
