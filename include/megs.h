@@ -123,6 +123,10 @@ typedef struct {
                                        sums go to the pair's own slot (36 B per pair of scratch), then
                                        every record adds its slots in a fixed order; no float atomics.
                                        Set it on the forward and the backward alike. */
+#define MEGS_FLAG_RECORD_PLANES 16u /* also write the per-field record planes of megs_state (mean,
+                                       conic_o, rgbd, radius, cutoff) for inspection; without it
+                                       those pointers are NULL (the packed lines hold the same
+                                       records, and ntiles is always written) */
 
 typedef struct {
     int32_t tile;          /* tile edge in pixels: 8, 16 or 32 */
@@ -148,7 +152,8 @@ typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
  * Forward state: filled by megs_render_forward, read by megs_render_backward. Every pointer is
  * device memory obtained from the allocation callback. Layouts (NR = n * n_views records,
  * record r = view * n + gaussian; P = pairs; T = tiles over all views; NP = pixels over all views):
- *   mean      double[NR][2]  pixel-space mean (u, v)
+ *   mean      double[NR][2]  pixel-space mean (u, v)          (this and conic_o, rgbd, radius,
+ *                                                            cutoff: MEGS_FLAG_RECORD_PLANES only)
  *   conic_o   float[NR][4]   conic (a, b, c) of q = -(a dx^2 + c dy^2)/2 - b dx dy, and o_eff
  *   rgbd      float[NR][4]   SG colour (r, g, b) and camera depth z
  *   radius    int32[NR]      footprint radius in pixels, -1 when culled

@@ -17,6 +17,7 @@ MEGS_FLAG_ONE_STAGE_SORT = 1
 MEGS_FLAG_PERSISTENT = 2
 MEGS_FLAG_STATS = 4
 MEGS_FLAG_DETERMINISTIC = 8
+MEGS_FLAG_RECORD_PLANES = 16
 STAGES = ("project", "depth_sort", "scan", "emit", "pair_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd")
 MEGS_MAX_LOBES = 8
 MEGS_MAX_VIEWS = 64

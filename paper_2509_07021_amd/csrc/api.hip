@@ -94,6 +94,7 @@ struct Layout {
     int nv;
     int64_t n, nr, n_tiles, n_pixels;
     int tile, tile_bits;
+    bool planes;  // MEGS_FLAG_RECORD_PLANES
     std::vector<ViewInfo> views;
 };
 
@@ -151,7 +152,7 @@ megs_status check_args(const megs_scene* sc, const megs_camera* cams, int32_t nv
     if (cfg->subtile != 0 && cfg->subtile != 8) return fail(MEGS_ERR_ARG, "subtile = %d not in {0, 8}", cfg->subtile);
     if (cfg->subtile == 8 && cfg->tile == 8) return fail(MEGS_ERR_ARG, "subtile 8 needs 16x16 or 32x32 tiles");
     if (cfg->flags & ~(uint32_t)(MEGS_FLAG_ONE_STAGE_SORT | MEGS_FLAG_PERSISTENT | MEGS_FLAG_STATS |
-                                 MEGS_FLAG_DETERMINISTIC))
+                                 MEGS_FLAG_DETERMINISTIC | MEGS_FLAG_RECORD_PLANES))
         return fail(MEGS_ERR_ARG, "unknown flags 0x%x", cfg->flags);
     for (int v = 0; v < nv; ++v) {
         const megs_camera& c = cams[v];
@@ -162,8 +163,10 @@ megs_status check_args(const megs_scene* sc, const megs_camera* cams, int32_t nv
     return MEGS_OK;
 }
 
-Layout make_layout(const megs_scene* sc, const megs_camera* cams, int nv, int tile) {
+Layout make_layout(const megs_scene* sc, const megs_camera* cams, int nv, const megs_config* cfg) {
+    const int tile = cfg->tile;
     Layout L;
+    L.planes = cfg->flags & MEGS_FLAG_RECORD_PLANES;
     L.nv = nv;
     L.n = sc->n;
     L.nr = sc->n * nv;
@@ -232,9 +235,12 @@ size_t frame_bytes(const Layout& L) {
     size_t b = 0;
     b += align256(sizeof(ViewInfo) * L.nv);
     b += align256(sizeof(PackedRec) * (L.nr ? L.nr : 1));
-    b += align256(sizeof(double2) * (L.nr ? L.nr : 1));
-    b += 2 * align256(sizeof(float4) * (L.nr ? L.nr : 1));
-    b += 8 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
+    if (L.planes) {
+        b += align256(sizeof(double2) * (L.nr ? L.nr : 1));
+        b += 2 * align256(sizeof(float4) * (L.nr ? L.nr : 1));
+        b += 2 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
+    }
+    b += 6 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
     b += align256(scan_scratch_bytes(L.nr)) + align256(radix_scratch_bytes(L.nr));
     b += align256(sizeof(uint32_t) * 8) + align256(sizeof(int32_t) * 8);
     b += align256(sizeof(uint2) * L.n_tiles);
@@ -248,13 +254,20 @@ Frame carve_frame(void* mem, const Layout& L) {
     Frame f;
     f.views = c.take<ViewInfo>(L.nv);
     f.rec.packed = c.take<PackedRec>(L.nr);
-    f.rec.mean = c.take<double2>(L.nr);
-    f.rec.conic_o = c.take<float4>(L.nr);
-    f.rec.rgbd = c.take<float4>(L.nr);
-    f.rec.radius = c.take<int32_t>(L.nr);
+    if (L.planes) {
+        f.rec.mean = c.take<double2>(L.nr);
+        f.rec.conic_o = c.take<float4>(L.nr);
+        f.rec.rgbd = c.take<float4>(L.nr);
+        f.rec.radius = c.take<int32_t>(L.nr);
+        f.rec.cutoff = c.take<float>(L.nr);
+    } else {
+        f.rec.mean = nullptr;
+        f.rec.conic_o = f.rec.rgbd = nullptr;
+        f.rec.radius = nullptr;
+        f.rec.cutoff = nullptr;
+    }
     f.rec.ntiles = c.take<uint32_t>(L.nr);
     f.rec.dkey = c.take<uint32_t>(L.nr);
-    f.rec.cutoff = c.take<float>(L.nr);
     f.dkey_alt = c.take<uint32_t>(L.nr);
     f.order = c.take<uint32_t>(L.nr);
     f.order_alt = c.take<uint32_t>(L.nr);
@@ -529,7 +542,7 @@ megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t 
     megs_status st = check_args(sc, cams, nv, cfg);
     if (st != MEGS_OK) return st;
     if (!alloc || !images || !state) return fail(MEGS_ERR_ARG, "null allocator, image or state");
-    const Layout L = make_layout(sc, cams, nv, cfg->tile);
+    const Layout L = make_layout(sc, cams, nv, cfg);
     const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
     memset(state, 0, sizeof(*state));
     void* fm = alloc(ctx, frame_bytes(L));
@@ -620,7 +633,7 @@ megs_status megs_render_backward(const megs_scene* scene, const megs_camera* cam
     if (!state || !dl_dimages || !alloc) return fail(MEGS_ERR_ARG, "null state, dL/dimage or allocator");
     st = check_grads(scene, grads);
     if (st != MEGS_OK) return st;
-    const Layout L = make_layout(scene, cams, n_views, cfg->tile);
+    const Layout L = make_layout(scene, cams, n_views, cfg);
     if (state->n_records != L.nr || state->n_views != n_views || state->tile != cfg->tile || !state->internal)
         return fail(MEGS_ERR_ARG, "state does not belong to this scene, view set and tile size");
     const size_t gbytes = backward_bytes(L, cfg, state->pair_capacity);
@@ -856,7 +869,7 @@ megs_status megs_graph_create(const megs_scene* scene, const megs_camera* cams, 
         if (st != MEGS_OK) return st;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = make_layout(scene, cams, n_views, cfg->tile);
+    const Layout L = make_layout(scene, cams, n_views, cfg);
     const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
     const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
     void* fm = alloc(alloc_ctx, frame_bytes(L));

@@ -566,30 +566,32 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const int k = k0 + kk;
-                    if (k >= nhit) break;
-                    const Staged s = lds[k];
-                    const uint32_t posk = lds_pos[k];
-                    float dx, dy, G, alpha;
-                    bool clamped;
-                    const bool pass = frag(s, px, py, dx, dy, G, alpha, clamped) & (T > 0.0f);
-                    if (STATS) n_evaluated += T > 0.0f;
-                    if (!__any(pass)) continue;
-                    const float Tn = T * (1.0f - alpha);
-                    const bool term = pass & (Tn < kTMin);
-                    const bool incl = pass & !term;
-                    const float wgt = incl ? alpha * T : 0.0f;
-                    C0 = __fmaf_rn(wgt, s.p2.y, C0);
-                    C1 = __fmaf_rn(wgt, s.p2.z, C1);
-                    C2 = __fmaf_rn(wgt, s.p2.w, C2);
-                    T = incl ? Tn : (term ? -T : T);
-                    last = incl ? posk + 1 : last;
-                    if (STATS) n_blended += incl;
-                    if (IMP) {
-                        float wsum = wgt;
+                    if (k < nhit) {  // wave-uniform
+                        const Staged s = lds[k];
+                        const uint32_t posk = lds_pos[k];
+                        float dx, dy, G, alpha;
+                        bool clamped;
+                        const bool pass = frag(s, px, py, dx, dy, G, alpha, clamped) & (T > 0.0f);
+                        if (STATS) n_evaluated += T > 0.0f;
+                        if (__any(pass)) {
+                            const float Tn = T * (1.0f - alpha);
+                            const bool term = pass & (Tn < kTMin);
+                            const bool incl = pass & !term;
+                            const float wgt = incl ? alpha * T : 0.0f;
+                            C0 = __fmaf_rn(wgt, s.p2.y, C0);
+                            C1 = __fmaf_rn(wgt, s.p2.z, C1);
+                            C2 = __fmaf_rn(wgt, s.p2.w, C2);
+                            T = incl ? Tn : (term ? -T : T);
+                            last = incl ? posk + 1 : last;
+                            if (STATS) n_blended += incl;
+                            if (IMP) {
+                                float wsum = wgt;
 #pragma unroll
-                        for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d);
-                        if (lane == 0 && wsum != 0.0f)
-                            unsafeAtomicAdd(a.importance + (lds_id[k] - (int64_t)c.view * a.n), wsum);
+                                for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d);
+                                if (lane == 0 && wsum != 0.0f)
+                                    unsafeAtomicAdd(a.importance + (lds_id[k] - (int64_t)c.view * a.n), wsum);
+                            }
+                        }
                     }
                 }
             }

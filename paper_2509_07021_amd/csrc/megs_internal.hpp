@@ -72,6 +72,7 @@ static_assert(sizeof(PackedRec) == 64, "one record per 64-byte line");
 // Record planes written by the projection (record r = view * n + i).
 struct Records {
     PackedRec* packed;  // the same records, one line each
+    // per-field planes (null unless MEGS_FLAG_RECORD_PLANES): mean .. radius, cutoff
     double2* mean;      // pixel-space mean
     float4* conic_o;    // conic a, b, c and effective opacity
     float4* rgbd;       // colour and camera depth
@@ -148,7 +149,8 @@ __device__ __forceinline__ uint32_t tile_rect(double u, double v, int32_t r, con
     int iyl = yl < 0.0 ? 0 : static_cast<int>(yl);
     int ixh = xh > vw.width - 1 ? vw.width - 1 : static_cast<int>(xh);
     int iyh = yh > vw.height - 1 ? vw.height - 1 : static_cast<int>(yh);
-    x0 = ixl / tile; x1 = ixh / tile; y0 = iyl / tile; y1 = iyh / tile;
+    const int sh = __ffs(tile) - 1;  // tile is a power of two and the indices are >= 0
+    x0 = ixl >> sh; x1 = ixh >> sh; y0 = iyl >> sh; y1 = iyh >> sh;
     return static_cast<uint32_t>((x1 - x0 + 1) * (y1 - y0 + 1));
 }
 
@@ -198,7 +200,9 @@ __device__ __forceinline__ bool row_span(const EllipseRows& e, const ViewInfo& v
     const double s2 = sqrt(r2 > 0.0 ? r2 : 0.0);
     const double xmax = e.u + (s1 - e.b * d1) * e.ia;
     const double xmin = e.u - (s2 + e.b * d2) * e.ia;
-    double flo = ceil((xmin + 0.5) / tile - 1.0), fhi = floor((xmax - 0.5) / tile);
+    // division by the power-of-two tile size as an exact exponent shift (the same value as x / tile)
+    const int sh = __ffs(tile) - 1;
+    double flo = ceil(ldexp(xmin + 0.5, -sh) - 1.0), fhi = floor(ldexp(xmax - 0.5, -sh));
     if (flo < x0) flo = x0;
     if (fhi > x1) fhi = x1;
     if (flo > fhi) return false;

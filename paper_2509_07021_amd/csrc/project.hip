@@ -323,12 +323,14 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
                     if (row_span(er, vw, tile, ty, x0, x1, lo, hi)) nt += (uint32_t)(hi - lo + 1);
                 }
             }
-            rec.mean[r] = make_double2(p.u, p.v);
-            rec.conic_o[r] = make_float4(p.conic[0], p.conic[1], p.conic[2], g.o_eff);
-            rec.rgbd[r] = make_float4(rgb[0], rgb[1], rgb[2], p.tzf);
-            rec.radius[r] = p.radius;
-            rec.cutoff[r] = cut;
-        } else {
+            if (rec.mean) {  // per-field planes, on request only
+                rec.mean[r] = make_double2(p.u, p.v);
+                rec.conic_o[r] = make_float4(p.conic[0], p.conic[1], p.conic[2], g.o_eff);
+                rec.rgbd[r] = make_float4(rgb[0], rgb[1], rgb[2], p.tzf);
+                rec.radius[r] = p.radius;
+                rec.cutoff[r] = cut;
+            }
+        } else if (rec.mean) {
             rec.mean[r] = make_double2(0.0, 0.0);
             rec.conic_o[r] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec.rgbd[r] = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -486,7 +486,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
             if (pos >= capacity) break;
             const uint32_t gt = w_tile[i], gv = w_val[i];
             if (tile_keys) tile_keys[pos] = gt;
-            if (keys64) keys64[pos] = ((uint64_t)gt << 32) | __float_as_uint(rec.rgbd[gv].w);
+            if (keys64) keys64[pos] = ((uint64_t)gt << 32) | rec.dkey[gv];  // depth bits (gv has tiles)
             vals[pos] = gv;
         }
         __syncthreads();

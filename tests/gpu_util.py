@@ -2,9 +2,12 @@
 buffers back to numpy; compare against the FP64 oracle under the tolerances of the tests."""
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 import torch
 
+from paper_2509_07021_amd import _lib as L
 from paper_2509_07021_amd import render as R
 from paper_2509_07021_amd import scenes as S
 
@@ -21,7 +24,9 @@ def flat_weights(weights) -> torch.Tensor:
 
 
 def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
-    """Forward (and backward when weights are given) through the C ABI; all stage buffers as numpy."""
+    """Forward (and backward when weights are given) through the C ABI; all stage buffers as numpy.
+    The per-field record planes are requested (MEGS_FLAG_RECORD_PLANES), which only adds their writes."""
+    cfg = dataclasses.replace(cfg, flags=cfg.flags | L.MEGS_FLAG_RECORD_PLANES)
     ds = R.DeviceScene.from_scene(scene)
     fr = R.forward(ds, cams, cfg)
     torch.cuda.synchronize()

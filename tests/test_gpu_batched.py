@@ -1,5 +1,7 @@
 """GPU tests of the batched form (hipGraph capture and replay, persistent work queue, autotuner,
 capacity overflow) and of the full-size workloads on sampled outputs."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -123,7 +125,8 @@ def _full_size_sampled(scene, cams, cfg, frac, seed):
     tile = cfg.tile
     nv = len(cams)
     ds = R.DeviceScene.from_scene(scene)
-    fr = R.forward(ds, cams, cfg)
+    # the per-field record planes are read back below: requesting them only adds their writes
+    fr = R.forward(ds, cams, dataclasses.replace(cfg, flags=cfg.flags | L.MEGS_FLAG_RECORD_PLANES))
     torch.cuda.synchronize()
     g = {"n_pairs": int(fr.state.n_pairs)}
     nr = scene.n * nv
