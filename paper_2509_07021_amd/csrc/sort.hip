@@ -335,8 +335,12 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
     uint32_t* totals = counts + (int64_t)kRsDigits * G;
     K* src_k = keys; uint32_t* src_v = vals;
     K* dst_k = keys_alt; uint32_t* dst_v = vals_alt;
-    for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        const int bits = end_bit - shift < 8 ? end_bit - shift : 8;
+    // the fewest passes of at most 8 bits, with the bits spread evenly over them (14 tile bits sort
+    // as 7 + 7: fewer digits per pass give each digit longer runs in the scatter)
+    const int passes = (end_bit - begin_bit + 7) / 8;
+    const int width = (end_bit - begin_bit + passes - 1) / passes;
+    for (int shift = begin_bit; shift < end_bit; shift += width) {
+        const int bits = end_bit - shift < width ? end_bit - shift : width;
         const uint32_t mask = (1u << bits) - 1u;
         hipLaunchKernelGGL(k_radix_upsweep<K>, dim3(G), dim3(kRsThreads), 0, stream, src_k, d_count, max_count, shift,
                            mask, counts);
