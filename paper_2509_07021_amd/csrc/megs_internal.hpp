@@ -180,10 +180,10 @@ __device__ __forceinline__ void ellipse_rows(double u, double v, double a, doubl
 
 // Columns [lo, hi] of tile row ty listed for the record (within the rectangle columns [x0, x1]);
 // returns false when the row lists no tile.
-__device__ __forceinline__ bool row_span(const EllipseRows& e, const ViewInfo& vw, int tile, int ty, int x0, int x1,
+__device__ __forceinline__ bool row_span(const EllipseRows& e, int height, int tile, int ty, int x0, int x1,
                                          int& lo, int& hi) {
     if (e.full) { lo = x0; hi = x1; return true; }
-    const int ye = (ty + 1) * tile < vw.height ? (ty + 1) * tile : vw.height;
+    const int ye = (ty + 1) * tile < height ? (ty + 1) * tile : height;
     double dl = (ty * tile + 0.5) - e.v, dh = (ye - 0.5) - e.v;
     if (dl < -e.ry) dl = -e.ry;
     if (dh > e.ry) dh = e.ry;

@@ -406,22 +406,24 @@ __device__ __forceinline__ void band_extent(const BandsF& f, int sub, int y8, in
 }
 
 // Bits of the sub-columns of tile column tx whose pixel-centre range meets [xmin, xmax].
+// (Branch-free: the shift counts are clamped into [0, S], and the empty cases select 0.)
 __device__ __forceinline__ uint32_t band_bits(float xmin, float xmax, int sub, int tx, int S) {
-    if (xmin > xmax) return 0u;
     const float x0 = (float)(tx * S * sub), isub = 1.0f / (float)sub;  // sub is a power of two
     const float lo = fmaxf(ceilf((xmin + 0.5f - x0) * isub - 1.0f), 0.0f);
     const float hi = fminf(floorf((xmax - 0.5f - x0) * isub), (float)(S - 1));
-    if (lo > hi) return 0u;
-    const int c0 = (int)lo, c1 = (int)hi;
-    return ((1u << (c1 + 1)) - 1u) & ~((1u << c0) - 1u);
+    const int c0 = min((int)lo, S), c1 = max((int)hi, 0);
+    const uint32_t bits = ((2u << c1) - 1u) & ~((1u << c0) - 1u);
+    return (xmin <= xmax) & (lo <= hi) ? bits : 0u;
 }
 
+// S: sub-tiles per tile edge when the keys carry sub-tile flags (tile = 8 S), 0 without flags.
+template <int S>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t n,
                                                        int tile, const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ offsets, int64_t n_records,
                                                        uint32_t* __restrict__ tile_keys, uint64_t* __restrict__ keys64,
-                                                       uint32_t* __restrict__ vals, int64_t capacity, int32_t* status,
-                                                       int sub) {
+                                                       uint32_t* __restrict__ vals, int64_t capacity, int32_t* status) {
+    constexpr int SUB = 8;
     __shared__ uint32_t w_tile[kEmitWindow];
     __shared__ uint32_t w_val[kEmitWindow];
     __shared__ uint32_t range[2];
@@ -444,38 +446,44 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     __syncthreads();
     const int64_t lo = range[0], hi = range[1];
     if (has && nt && off + (int64_t)nt > capacity) status[1] = 1;
-    // record geometry (only threads with pairs)
+    // record geometry and the view fields the loops need, in registers (only threads with pairs)
     int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+    int vh = 0, tiles_x = 0;
+    int64_t tile_off = 0;
     EllipseRows er;
-    const ViewInfo* vw = nullptr;
     if (nt) {
-        vw = &views[g / n];
+        const ViewInfo& vw = views[g / n];
+        vh = vw.height;
+        tiles_x = vw.tiles_x;
+        tile_off = vw.tile_off;
         const double mx = __hiloint2double(__float_as_int(q0.y), __float_as_int(q0.x));
         const double my = __hiloint2double(__float_as_int(q0.w), __float_as_int(q0.z));
-        tile_rect(mx, my, __float_as_int(q3.x), *vw, tile, x0, x1, y0, y1);
+        tile_rect(mx, my, __float_as_int(q3.x), vw, tile, x0, x1, y0, y1);
         ellipse_rows(mx, my, q1.x, q1.y, q1.z, q2.w, er);
     }
     for (int64_t w0 = lo; w0 < hi; w0 += kEmitWindow) {
         const int64_t w1 = w0 + kEmitWindow < hi ? w0 + kEmitWindow : hi;
         if (nt && off < w1 && off + (int64_t)nt > w0) {
             int64_t pos = off;
-            const int S = sub ? tile / sub : 0;  // sub-tiles per tile edge
             const BandsF bf = bands_of(er);
             for (int ty = y0; ty <= y1 && pos < w1; ++ty) {
                 int cl, ch;
-                if (!row_span(er, *vw, tile, ty, x0, x1, cl, ch)) continue;
+                if (!row_span(er, vh, tile, ty, x0, x1, cl, ch)) continue;
                 if (pos + (ch - cl + 1) <= w0) {  // the whole row lies before this window
                     pos += ch - cl + 1;
                     continue;
                 }
-                float bmin[4], bmax[4];
-                for (int r = 0; r < S; ++r) band_extent(bf, sub, ty * S + r, vw->height, bmin[r], bmax[r]);
+                float bmin[S > 0 ? S : 1], bmax[S > 0 ? S : 1];
+#pragma unroll
+                for (int r = 0; r < S; ++r) band_extent(bf, SUB, ty * S + r, vh, bmin[r], bmax[r]);
+                const uint32_t row_key = (uint32_t)(tile_off + (int64_t)ty * tiles_x);
                 for (int tx = cl; tx <= ch && pos < w1; ++tx, ++pos) {
                     if (pos < w0) continue;
-                    uint32_t key = (uint32_t)(vw->tile_off + (int64_t)ty * vw->tiles_x + tx);
+                    uint32_t key = row_key + (uint32_t)tx;
                     if (S) {
                         uint32_t m = 0;
-                        for (int r = 0; r < S; ++r) m |= band_bits(bmin[r], bmax[r], sub, tx, S) << (r * S);
+#pragma unroll
+                        for (int r = 0; r < S; ++r) m |= band_bits(bmin[r], bmax[r], SUB, tx, S) << (r * S);
                         key |= m << 16;
                     }
                     w_tile[pos - w0] = key;
@@ -625,10 +633,17 @@ hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_
                        int32_t* status, hipStream_t stream, int sub) {
     (void)nv;
     if (n_records <= 0) return hipSuccess;
-    if (sub && (!tile_keys || tile / sub > 4)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_records + kEmitThreads - 1) / kEmitThreads)), dim3(kEmitThreads), 0,
-                       stream, rec, views, n, tile, order, offsets, n_records, tile_keys, keys64, vals, capacity,
-                       status, sub);
+    if (sub && (sub != 8 || !tile_keys || (tile != 16 && tile != 32))) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n_records + kEmitThreads - 1) / kEmitThreads));
+    if (!sub)
+        hipLaunchKernelGGL(k_emit<0>, grid, dim3(kEmitThreads), 0, stream, rec, views, n, tile, order, offsets,
+                           n_records, tile_keys, keys64, vals, capacity, status);
+    else if (tile == 16)
+        hipLaunchKernelGGL(k_emit<2>, grid, dim3(kEmitThreads), 0, stream, rec, views, n, tile, order, offsets,
+                           n_records, tile_keys, keys64, vals, capacity, status);
+    else
+        hipLaunchKernelGGL(k_emit<4>, grid, dim3(kEmitThreads), 0, stream, rec, views, n, tile, order, offsets,
+                           n_records, tile_keys, keys64, vals, capacity, status);
     return hipGetLastError();
 }
 
