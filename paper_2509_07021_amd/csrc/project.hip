@@ -379,8 +379,8 @@ __device__ __forceinline__ void quat_grad(const float q[4], const float gR[9], f
 }
 
 template <int K, bool RAGGED, int SHD>
-__global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
-                                                     const float* __restrict__ grad2d, GradDev G) {
+__device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewInfo* __restrict__ views, int nv,
+                                                const float* __restrict__ grad2d, const GradDev& G) {
     constexpr int SHM = SHD >= 0 ? (SHD + 1) * (SHD + 1) : 1;
     float gsh[SHM][3];
 #pragma unroll
@@ -575,6 +575,20 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneDev sc, const ViewInfo
     }
 }
 
+// The SG instances run at three waves per SIMD (the compiler keeps them within 168 registers, with
+// a few spills, which measured faster than two waves at 209); the SH instances keep their registers.
+template <int K, bool RAGGED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_project_bwd(
+    SceneDev sc, const ViewInfo* __restrict__ views, int nv, const float* __restrict__ grad2d, GradDev G) {
+    project_bwd_one<K, RAGGED, -1>(sc, views, nv, grad2d, G);
+}
+
+template <int SHD>
+__global__ __launch_bounds__(256) void k_project_bwd_sh(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
+                                                        const float* __restrict__ grad2d, GradDev G) {
+    project_bwd_one<0, false, SHD>(sc, views, nv, grad2d, G);
+}
+
 template <int K, bool RAGGED, int SHD = -1>
 hipError_t dispatch_fwd(const SceneDev& sc, const ViewInfo* views, int nv, int tile, const Records& rec,
                         hipStream_t stream) {
@@ -587,8 +601,12 @@ template <int K, bool RAGGED, int SHD = -1>
 hipError_t dispatch_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d, const GradDev& g,
                         hipStream_t stream) {
     const int64_t blocks = (sc.n + 255) / 256;
-    hipLaunchKernelGGL((k_project_bwd<K, RAGGED, SHD>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, grad2d,
-                       g);
+    if constexpr (SHD >= 0)
+        hipLaunchKernelGGL((k_project_bwd_sh<SHD>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv,
+                           grad2d, g);
+    else
+        hipLaunchKernelGGL((k_project_bwd<K, RAGGED>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv,
+                           grad2d, g);
     return hipGetLastError();
 }
 

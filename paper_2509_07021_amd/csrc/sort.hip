@@ -562,6 +562,37 @@ __global__ void k_ranges(const K* __restrict__ keys, int shift, uint32_t tmask, 
     }
 }
 
+// The same for 32-bit keys, four consecutive keys per thread through one 16-byte load (the key
+// arrays are 256-byte aligned), plus the keys just before and after them.
+__global__ void k_ranges_u32x4(const uint32_t* __restrict__ keys, uint32_t tmask, const uint32_t* d_count,
+                               int64_t max_count, uint2* __restrict__ ranges) {
+    int64_t n = (int64_t)*d_count;
+    if (n > max_count) n = max_count;
+    const int64_t nq = (n + 3) / 4;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i0 = 4 * q;
+        uint32_t t[4];
+        if (i0 + 4 <= n) {
+            const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
+            t[0] = v.x & tmask; t[1] = v.y & tmask; t[2] = v.z & tmask; t[3] = v.w & tmask;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) t[j] = i0 + j < n ? keys[i0 + j] & tmask : 0u;
+        }
+        const uint32_t before = i0 > 0 ? keys[i0 - 1] & tmask : 0u;
+        const uint32_t after = i0 + 4 < n ? keys[i0 + 4] & tmask : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = i0 + j;
+            if (i >= n) break;
+            const bool first = i == 0 || (j == 0 ? before : t[j - 1]) != t[j];
+            const bool last = i == n - 1 || (j == 3 ? after : t[j + 1]) != t[j];
+            if (first) ranges[t[j]].x = (uint32_t)i;
+            if (last) ranges[t[j]].y = (uint32_t)(i + 1);
+        }
+    }
+}
+
 inline unsigned grid_for(int64_t count, int threads, int64_t cap = 65536) {
     int64_t b = (count + threads - 1) / threads;
     if (b < 1) b = 1;
@@ -650,7 +681,7 @@ hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_
 hipError_t launch_ranges_u32(const uint32_t* tile_keys, const uint32_t* d_count, int64_t max_count, uint2* ranges,
                              hipStream_t stream, uint32_t tmask) {
     if (max_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid_for(max_count, 256)), dim3(256), 0, stream, tile_keys, 0, tmask,
+    hipLaunchKernelGGL(k_ranges_u32x4, dim3(grid_for((max_count + 3) / 4, 256)), dim3(256), 0, stream, tile_keys, tmask,
                        d_count, max_count, ranges);
     return hipGetLastError();
 }
