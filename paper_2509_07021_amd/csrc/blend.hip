@@ -257,6 +257,9 @@ __device__ __forceinline__ float dpp(float v) {
     return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), CTRL, 0xf, 0xf, false));
 }
 constexpr int kQuadXor1 = 0xb1, kQuadXor2 = 0x4e, kRowMirror = 0x140, kRowHalfMirror = 0x141;
+constexpr int kRowBcast15 = 0x142;  // lane 15 of the previous 16-lane row (rows 1-3)
+constexpr int kRowBcast31 = 0x143;  // lane 31 (rows 2 and 3)
+constexpr int kLaneSum8 = 63;       // the lane that ends with the wave total of v[8] in wave_sum9
 
 // Sum over one 8-lane group (every lane of the group ends with the total).
 __device__ __forceinline__ float sum8(float y) {
@@ -269,7 +272,8 @@ __device__ __forceinline__ float sum8(float y) {
 // Sum of v[0..8] over the wave: a transposed butterfly. After the swaps, lane group (b5 b4 b3) of
 // the lane index holds partial sums of v[4 b5 + 2 b4 + b3] only; the last three steps finish
 // them within each 8-lane group. Afterwards every lane of group m (lanes 8m..8m+7) holds the total
-// of v[m] in out, and every lane holds the total of v[8] in v8.
+// of v[m] in out. v[8] is summed within each 16-lane row, then across rows with the two row
+// broadcasts: lane kLaneSum8 (63) holds its wave total in v8.
 __device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
     const int lane = __lane_id();
     float w4[4];
@@ -289,13 +293,12 @@ __device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
     const bool b3 = lane & 8;      // lanes 0-7 of a row pair with lanes 15..8 through the mirror
     const float y = (b3 ? w2[1] : w2[0]) + dpp<kRowMirror>(b3 ? w2[0] : w2[1]);
     out = sum8(y);
-    float z = v[8], z2 = v[8];
-    swap32(z, z2);
-    z += z2;
-    z2 = z;
-    swap16(z, z2);
-    z += z2;
-    v8 = sum8(z + dpp<kRowMirror>(z));
+    // (all rows take part in both broadcasts so each folds into one DPP add; only row 3's result,
+    // which reads valid lanes in both steps, is used)
+    float z = sum8(v[8]);
+    z += dpp<kRowMirror>(z);      // row sums R0..R3 in every lane of their row
+    z += dpp<kRowBcast15>(z);     // row 1: R0 + R1, row 3: R2 + R3
+    v8 = z + dpp<kRowBcast31>(z);  // row 3: R2 + R3 + (R0 + R1)
 }
 
 // DET: instead of float atomics into the record's gradient, the tile's 9 sums for each list
@@ -413,20 +416,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                     if (DET) {
                         float* slot = a.grad_pair + 9 * (int64_t)(end - 1 - jj);
                         if ((lane & 7) == 0) slot[lane >> 3] = tot;
-                        if (lane == 1) slot[8] = tot8;
+                        if (lane == kLaneSum8) slot[8] = tot8;
                         continue;
                     }
-                    // one 9-lane atomic: lanes 0, 8, .., 56 add sums 0..7, lane 1 adds sum 8
-                    if ((lane & 7) == 0 || lane == 1)
-                        unsafeAtomicAdd(a.grad2d + 9 * (int64_t)lds_id[jj] + (lane == 1 ? 8 : lane >> 3),
-                                        lane == 1 ? tot8 : tot);
+                    // one 9-lane atomic: lanes 0, 8, .., 56 add sums 0..7, lane 63 adds sum 8
+                    if ((lane & 7) == 0 || lane == kLaneSum8)
+                        unsafeAtomicAdd(a.grad2d + 9 * (int64_t)lds_id[jj] + (lane == kLaneSum8 ? 8 : lane >> 3),
+                                        lane == kLaneSum8 ? tot8 : tot);
                 } else {
                     // per-wave partial sums to LDS; summed across waves after the batch
                     float tot = 0.f, tot8 = 0.f;
                     if (any_incl) wave_sum9(acc, tot, tot8);
                     float* part = lds_part + ((int64_t)jj * WAVES + wv) * 9;
                     if ((lane & 7) == 0) part[lane >> 3] = tot;
-                    if (lane == 1) part[8] = tot8;
+                    if (lane == kLaneSum8) part[8] = tot8;
                 }
             }
             __syncthreads();
@@ -631,9 +634,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
     __shared__ uint64_t lds_slot[64];  // 9 x record id: the record's first gradient element
     __shared__ uint32_t work_slot;
     const int lane = __lane_id();
-    // the 9 sums leave through one 9-lane atomic: lanes 0, 8, .., 56 hold sums 0..7, lane 1 sum 8
-    const bool adds = (lane & 7) == 0 || lane == 1;
-    const int comp = lane == 1 ? 8 : lane >> 3;
+    // the 9 sums leave through one 9-lane atomic: lanes 0, 8, .., 56 hold sums 0..7, lane 63 sum 8
+    const bool adds = (lane & 7) == 0 || lane == kLaneSum8;
+    const int comp = lane == kLaneSum8 ? 8 : lane >> 3;
     const int64_t n_items = a.n_tiles * (int64_t)(tile / SUB) * (tile / SUB);
     for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot, false); w < n_items;
          w = next_item(a, w, persistent, n_items, &work_slot, false)) {
@@ -715,7 +718,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 acc[4] = acc[1] * dy;
                 float tot, tot8;
                 wave_sum9(acc, tot, tot8);
-                if (adds) unsafeAtomicAdd(a.grad2d + (lds_slot[k] + comp), lane == 1 ? tot8 : tot);
+                if (adds) unsafeAtomicAdd(a.grad2d + (lds_slot[k] + comp), lane == kLaneSum8 ? tot8 : tot);
             }
             wave_sync();
             end = beg;
