@@ -275,11 +275,17 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_downsweep(const K* __restr
         K key[kRsIpt];
         uint32_t val[kRsIpt], dig[kRsIpt], rank[kRsIpt];
         const int64_t base = t * kRsTile + (int64_t)w * kWave * kRsIpt + lane;
+        // all of the tile's loads first (no branch between them), so they are in flight together
+#pragma unroll
         for (int j = 0; j < kRsIpt; ++j) {
             const int64_t idx = base + j * kWave;
             const bool ok = idx < c.n;
-            key[j] = ok ? keys_in[idx] : K(0);
-            val[j] = ok ? vals_in[idx] : 0u;
+            key[j] = ok ? keys_in[ok ? idx : 0] : K(0);
+            val[j] = ok ? vals_in[ok ? idx : 0] : 0u;
+        }
+        for (int j = 0; j < kRsIpt; ++j) {
+            const int64_t idx = base + j * kWave;
+            const bool ok = idx < c.n;
             const uint32_t d = ok ? digit_of(key[j], shift, mask) : 0u;
             dig[j] = ok ? d : 0xffffffffu;
             const uint64_t peers = match_digit(d, __ballot(ok), mask);
