@@ -268,6 +268,8 @@ Frame carve_frame(void* mem, const Layout& L) {
     }
     f.rec.ntiles = c.take<uint32_t>(L.nr);
     f.rec.dkey = c.take<uint32_t>(L.nr);
+    f.rec.order0 = nullptr;
+    f.rec.order_idb = 0;
     f.dkey_alt = c.take<uint32_t>(L.nr);
     f.order = c.take<uint32_t>(L.nr);
     f.order_alt = c.take<uint32_t>(L.nr);
@@ -343,10 +345,19 @@ megs_status enqueue_front(const megs_scene* sc, const Layout& L, const megs_conf
     if (st != MEGS_OK) return st;
     HIP_TRY(launch_fill_u32(f.counters, 0u, 8, s));
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(f.status), 0u, 8, s));
+    // Two-stage sort: the projection writes the depth sort's initial values with each record's tile
+    // count above its id (when the id leaves at least 4 bits), so the scan after the sort reads the
+    // counts in depth order without gathering them.
+    int idb = 1;
+    while (idb < 32 && (1ll << idb) < L.nr) ++idb;
+    const bool packed = !one_stage && idb <= 28;
+    f.rec.order0 = packed ? f.order : nullptr;
+    f.rec.order_idb = packed ? idb : 0;
     {
         StageTimer t(MEGS_STAGE_PROJECT, s);
         HIP_TRY(launch_project(scene_dev(sc, f.status), f.views, L.nv, L.tile, f.rec, s));
     }
+    f.rec.order0 = nullptr;
     if (one_stage) {
         StageTimer t(MEGS_STAGE_SCAN, s);
         HIP_TRY(launch_scan(f.rec.ntiles, nullptr, L.nr, f.offs, f.counters + 0, f.scan_scratch, s));
@@ -354,7 +365,7 @@ megs_status enqueue_front(const megs_scene* sc, const Layout& L, const megs_conf
     }
     {
         StageTimer t(MEGS_STAGE_DEPTH_SORT, s);
-        HIP_TRY(launch_iota(f.order, L.nr, s));
+        if (!packed) HIP_TRY(launch_iota(f.order, L.nr, s));
         HIP_TRY(launch_fill_u32(f.counters + 2, (uint32_t)L.nr, 1, s));
         bool alt = false;
         HIP_TRY(launch_radix_sort_u32(f.rec.dkey, f.order, f.dkey_alt, f.order_alt, f.counters + 2, L.nr, 0, 32,
@@ -363,8 +374,13 @@ megs_status enqueue_front(const megs_scene* sc, const Layout& L, const megs_conf
     }
     {
         StageTimer t(MEGS_STAGE_SCAN, s);
-        // the depth keys' ping-pong buffer is free after the sort: it takes the gathered tile counts
-        HIP_TRY(launch_scan(f.rec.ntiles, f.order, L.nr, f.offs, f.counters + 0, f.scan_scratch, s, f.dkey_alt));
+        if (packed) {
+            HIP_TRY(launch_scan_packed(f.order, f.rec.ntiles, L.nr, idb, f.offs, f.counters + 0, f.scan_scratch, s));
+        } else {
+            // the depth keys' ping-pong buffer is free after the sort: it takes the gathered counts
+            HIP_TRY(launch_scan(f.rec.ntiles, f.order, L.nr, f.offs, f.counters + 0, f.scan_scratch, s,
+                                f.dkey_alt));
+        }
     }
     return MEGS_OK;
 }

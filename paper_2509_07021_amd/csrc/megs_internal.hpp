@@ -79,6 +79,10 @@ struct Records {
     int32_t* radius;    // -1 when culled
     uint32_t* ntiles;   // tiles of the rectangle the footprint ellipse reaches
     uint32_t* dkey;     // depth sort key: float bits of depth, 0xffffffff when no tiles
+    // initial values of the depth sort when non-null: record id r in the low order_idb bits and
+    // min(ntiles, cap) above them, cap = 2^(32 - order_idb) - 1 marking a count that did not fit
+    uint32_t* order0;
+    int32_t order_idb;
     float* cutoff;      // k of the footprint ellipse q(d) = d' conic d <= k (with margin)
 };
 
@@ -241,6 +245,11 @@ hipError_t launch_iota(uint32_t* p, int64_t count, hipStream_t stream);
 // total written to *total (device). scratch: scan_scratch_bytes(n). With idx, `gathered` (n
 // entries, optional) receives the gathered values, which saves the second pass a gather.
 size_t scan_scratch_bytes(int64_t n);
+// The same scan over depth-sorted values that carry the tile count above the record id (see
+// Records::order0): counts come from the values themselves (ntiles[id] only for the escape value),
+// and the values are rewritten in place as bare record ids.
+hipError_t launch_scan_packed(uint32_t* order, const uint32_t* ntiles, int64_t n, int idb, uint32_t* out,
+                              uint32_t* total, void* scratch, hipStream_t stream);
 hipError_t launch_scan(const uint32_t* x, const uint32_t* idx, int64_t n, uint32_t* out, uint32_t* total,
                        void* scratch, hipStream_t stream, uint32_t* gathered = nullptr);
 

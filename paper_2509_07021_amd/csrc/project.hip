@@ -364,6 +364,10 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
             dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];
         }
         rec.dkey[r] = nt ? __float_as_uint(p.tzf) : 0xffffffffu;
+        if (rec.order0) {
+            const uint32_t cap = (1u << (32 - rec.order_idb)) - 1u;
+            rec.order0[r] = (min(nt, cap) << rec.order_idb) | (uint32_t)r;
+        }
     }
 }
 

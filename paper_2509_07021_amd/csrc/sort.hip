@@ -134,6 +134,50 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* x, c
     }
 }
 
+// Scan over depth-sorted packed values (record id below bit idb, tile count above it).
+__device__ __forceinline__ uint32_t packed_count(uint32_t v, const uint32_t* ntiles, int idb) {
+    const uint32_t c = v >> idb, cap = (1u << (32 - idb)) - 1u;
+    return c == cap ? ntiles[v & ((1u << idb) - 1u)] : c;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce_packed(const uint32_t* order, const uint32_t* ntiles,
+                                                                     int64_t n, int idb, uint32_t* partial) {
+    __shared__ uint32_t lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int j = 0; j < kScanIpt; ++j) {
+        const int64_t i = base + j * kScanThreads + threadIdx.x;
+        if (i < n) s += packed_count(order[i], ntiles, idb);
+    }
+    uint32_t total;
+    block_excl_scan256(s, lds, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down_packed(uint32_t* order, const uint32_t* ntiles, int64_t n,
+                                                                   int idb, const uint32_t* partial, uint32_t* out) {
+    __shared__ uint32_t lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
+    uint32_t v[kScanIpt];
+    uint32_t s = 0;
+    for (int j = 0; j < kScanIpt; ++j) {
+        uint32_t c = 0;
+        if (base + j < n) {
+            const uint32_t w = order[base + j];
+            c = packed_count(w, ntiles, idb);
+            order[base + j] = w & ((1u << idb) - 1u);
+        }
+        v[j] = c;
+        s += c;
+    }
+    uint32_t total;
+    uint32_t ex = block_excl_scan256(s, lds, total) + partial[blockIdx.x];
+    for (int j = 0; j < kScanIpt; ++j) {
+        if (base + j < n) out[base + j] = ex;
+        ex += v[j];
+    }
+}
+
 // ------------------------------------------------------------- radix sort ----
 
 template <typename K>
@@ -641,6 +685,20 @@ hipError_t launch_scan(const uint32_t* x, const uint32_t* idx, int64_t n, uint32
     else
         hipLaunchKernelGGL(k_scan_down, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream, x, idx, n, partial,
                            out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_packed(uint32_t* order, const uint32_t* ntiles, int64_t n, int idb, uint32_t* out,
+                              uint32_t* total, void* scratch, hipStream_t stream) {
+    if (n <= 0) return launch_fill_u32(total, 0u, 1, stream);
+    if (idb < 1 || idb > 28) return hipErrorInvalidValue;
+    const int64_t blocks = (n + kScanTile - 1) / kScanTile;
+    uint32_t* partial = static_cast<uint32_t*>(scratch);
+    hipLaunchKernelGGL(k_scan_reduce_packed, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream, order, ntiles, n,
+                       idb, partial);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, stream, partial, blocks, total);
+    hipLaunchKernelGGL(k_scan_down_packed, dim3((unsigned)blocks), dim3(kScanThreads), 0, stream, order, ntiles, n,
+                       idb, partial, out);
     return hipGetLastError();
 }
 

@@ -226,3 +226,35 @@ def test_fp16_3m_subsample_all_views():
         if gr[p] is not None:
             l2 = grad_close(p, g["grads"][p], gr[p])
             log(f"  {p}: relative L2 {l2:.2e}")
+
+
+def test_packed_depth_order_with_escaped_counts_full_size():
+    """The depth pre-sort carries each record's tile count above its id (9 bits at 8 M records), and
+    counts that do not fit take the escape value and are read back from the count array. At 8x8 tiles
+    the 8-view 1M workload has records past that cap; its key table must equal the one-stage 64-bit
+    sort's (which has no packing), bit for bit."""
+    scene, _ = S.make_workload("masked_1m_1080p")
+    ds = R.DeviceScene.from_scene(scene.stored("f16", "f16", "bf16"))
+    cams = S.ring_cameras(8, seed=5)
+    nr = scene.n * len(cams)
+    idb = max(1, int(np.ceil(np.log2(nr))))
+    cap = (1 << (32 - idb)) - 1
+    log(f"packed depth order: {nr} records, {idb} id bits, count cap {cap}")
+    two = R.forward(ds, cams, R.Config(8, 64))
+    torch.cuda.synchronize()
+    nt = two.buffer("ntiles", nr, torch.int32).cpu().numpy()
+    assert int(nt.max()) >= cap, (int(nt.max()), cap)   # the escape path is taken
+    P = int(two.state.n_pairs)
+    T = int(two.state.n_tiles)
+    v2 = two.buffer("vals", P, torch.int32).cpu().numpy()
+    t2 = two.buffer("tile_keys", P, torch.int32).cpu().numpy()
+    r2 = two.buffer("ranges", 2 * T, torch.int32).cpu().numpy()
+    del two
+    torch.cuda.empty_cache()
+    one = R.forward(ds, cams, R.Config(8, 64, flags=L.MEGS_FLAG_ONE_STAGE_SORT))
+    torch.cuda.synchronize()
+    assert int(one.state.n_pairs) == P
+    np.testing.assert_array_equal(one.buffer("vals", P, torch.int32).cpu().numpy(), v2)
+    k1 = one.buffer("keys64", P, torch.int64).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal((k1 >> np.uint64(32)).astype(np.uint32), t2.view(np.uint32))
+    np.testing.assert_array_equal(one.buffer("ranges", 2 * T, torch.int32).cpu().numpy(), r2)
