@@ -455,15 +455,22 @@ __device__ __forceinline__ void band_extent(const BandsF& f, int sub, int y8, in
     xmin = f.u - (s2 + f.b * d2) * f.ia - kMargin;
 }
 
-// Bits of the sub-columns of tile column tx whose pixel-centre range meets [xmin, xmax].
-// (Branch-free: the shift counts are clamped into [0, S], and the empty cases select 0.)
-__device__ __forceinline__ uint32_t band_bits(float xmin, float xmax, int sub, int tx, int S) {
-    const float x0 = (float)(tx * S * sub), isub = 1.0f / (float)sub;  // sub is a power of two
-    const float lo = fmaxf(ceilf((xmin + 0.5f - x0) * isub - 1.0f), 0.0f);
-    const float hi = fminf(floorf((xmax - 0.5f - x0) * isub), (float)(S - 1));
-    const int c0 = min((int)lo, S), c1 = max((int)hi, 0);
-    const uint32_t bits = ((2u << c1) - 1u) & ~((1u << c0) - 1u);
-    return (xmin <= xmax) & (lo <= hi) ? bits : 0u;
+// The image's sub-columns [c0, c1] (8 pixels each) whose pixel-centre range meets [xmin, xmax],
+// once per band; c0 > c1 when the band misses the ellipse. Clamped so the per-tile differences
+// below cannot overflow.
+__device__ __forceinline__ void band_columns(float xmin, float xmax, int sub, int& c0, int& c1) {
+    const float isub = 1.0f / (float)sub;  // sub is a power of two
+    const float lo = ceilf((xmin + 0.5f) * isub - 1.0f), hi = floorf((xmax - 0.5f) * isub);
+    const bool empty = !(xmin <= xmax);
+    c0 = empty ? 1 : (int)fminf(fmaxf(lo, -1.0f), 1048576.0f);
+    c1 = empty ? 0 : (int)fminf(fmaxf(hi, -2.0f), 1048576.0f);
+}
+
+// Bits of the sub-columns of tile column tx (S per tile) within [c0, c1] (branch-free).
+__device__ __forceinline__ uint32_t band_bits(int c0, int c1, int tx, int S) {
+    const int lo = max(c0 - tx * S, 0), hi = min(c1 - tx * S, S - 1);
+    const uint32_t bits = ((2u << max(hi, 0)) - 1u) & ~((1u << min(lo, 31)) - 1u);
+    return lo <= hi ? bits : 0u;
 }
 
 // S: sub-tiles per tile edge when the keys carry sub-tile flags (tile = 8 S), 0 without flags.
@@ -523,9 +530,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
                     pos += ch - cl + 1;
                     continue;
                 }
-                float bmin[S > 0 ? S : 1], bmax[S > 0 ? S : 1];
+                int bc0[S > 0 ? S : 1], bc1[S > 0 ? S : 1];
 #pragma unroll
-                for (int r = 0; r < S; ++r) band_extent(bf, SUB, ty * S + r, vh, bmin[r], bmax[r]);
+                for (int r = 0; r < S; ++r) {
+                    float xmin, xmax;
+                    band_extent(bf, SUB, ty * S + r, vh, xmin, xmax);
+                    band_columns(xmin, xmax, SUB, bc0[r], bc1[r]);
+                }
                 const uint32_t row_key = (uint32_t)(tile_off + (int64_t)ty * tiles_x);
                 for (int tx = cl; tx <= ch && pos < w1; ++tx, ++pos) {
                     if (pos < w0) continue;
@@ -533,7 +544,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
                     if (S) {
                         uint32_t m = 0;
 #pragma unroll
-                        for (int r = 0; r < S; ++r) m |= band_bits(bmin[r], bmax[r], SUB, tx, S) << (r * S);
+                        for (int r = 0; r < S; ++r) m |= band_bits(bc0[r], bc1[r], tx, S) << (r * S);
                         key |= m << 16;
                     }
                     w_tile[pos - w0] = key;
