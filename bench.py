@@ -34,10 +34,10 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (packed); the unpacked FMA cei
 #   forward blend of an included fragment (transmittance, weight, colour accumulate): 10
 #   backward of an included fragment: transmittance recovery (1 - alpha, divide) 2, weight 1,
 #   colour gradient 3, colour minus background 3, alpha gradient (dot product, times T) 6,
-#   background recursion (3 FMA) 6, exponent gradient 1, opacity gradient 1, the five moments of
-#   the exponent gradient (dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2) 5, summation of the 9 sums
-#   over pixels 9: 37 (the conic is applied to the moments once per record, not per fragment)
-FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 37
+#   background recursion (3 FMA) 6, opacity gradient e = G dL/dalpha 1, the five moments of e
+#   (e dx, e dy, e dx^2, e dx dy, e dy^2) 5, summation of the 9 sums over pixels 9: 36 (the
+#   exponent gradient is o_eff e; o_eff and the conic are applied once per record, not per fragment)
+FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 36
 
 # HBM bytes per launch of a kernel on the headline workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a plain

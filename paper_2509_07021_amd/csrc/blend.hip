@@ -397,10 +397,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                             S[j][2] = __fmaf_rn(al, d2, S[j][2]);
                             T[j] = incl[j] ? Ti : T[j];
                             const bool live = incl[j] & !clamped[j];
-                            const float dq = live ? al * dal : 0.0f;
+                            // dL/do_eff of the fragment; its exponent gradient is o_eff times this
+                            const float e = live ? G[j] * dal : 0.0f;
                             const float dx = dxs[j], dy = dys[j];
-                            acc[5] = __fmaf_rn(live ? G[j] : 0.0f, dal, acc[5]);
-                            const float mx = dq * dx, my = dq * dy;
+                            acc[5] += e;
+                            const float mx = e * dx, my = e * dy;
                             acc[0] += mx;
                             acc[1] += my;
                             acc[2] = __fmaf_rn(mx, dx, acc[2]);
@@ -709,10 +710,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 S2 = __fmaf_rn(al, d2, S2);
                 T = incl ? Ti : T;
                 const bool live = incl & !clamped;
-                const float dq = live ? al * dal : 0.0f;
-                acc[5] = (live ? G : 0.0f) * dal;
-                acc[0] = dq * dx;
-                acc[1] = dq * dy;
+                acc[5] = live ? G * dal : 0.0f;  // dL/do_eff; the exponent gradient is o_eff times this
+                acc[0] = acc[5] * dx;
+                acc[1] = acc[5] * dy;
                 acc[2] = acc[0] * dx;
                 acc[3] = acc[0] * dy;
                 acc[4] = acc[1] * dy;

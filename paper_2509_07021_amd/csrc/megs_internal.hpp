@@ -291,8 +291,9 @@ struct BlendArgs {
     float* T_final;
     uint32_t* last;
     const float* dl;      // backward only
-    float* grad2d;        // backward only, [NR][9]: sums over the record's fragments of dq dx, dq dy,
-                          // dq dx^2, dq dx dy, dq dy^2 (dq = dL/d exponent), dL/dopacity, dL/dRGB
+    float* grad2d;        // backward only, [NR][9]: sums over the record's fragments of e dx, e dy,
+                          // e dx^2, e dx dy, e dy^2 and e (e = dL/do_eff of an unclamped fragment;
+                          // its exponent gradient is o_eff e), then dL/dRGB
     float* grad_pair;     // deterministic backward: per list position [P][9] (null: atomics into grad2d)
     uint32_t* queue;      // persistent mode work counter (null: one workgroup per tile)
     unsigned long long* stats;  // forward fragment counters [blended, evaluated] (null: not counted)

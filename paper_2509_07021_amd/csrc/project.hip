@@ -425,14 +425,17 @@ __device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewIn
                 ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
         }
         if (!ok) continue;
-        // the blend leaves the moments of dL/dq over the footprint (dq = dL/dq per fragment, q the
-        // Gaussian's exponent, (dx, dy) the pixel offset from the mean): sum dq dx, dq dy, dq dx^2,
-        // dq dx dy, dq dy^2. With q = -(a dx^2 + 2 b dx dy + c dy^2) / 2, the gradients of the pixel
-        // mean and of the conic (a, b, c) follow here, once per record.
+        // The blend leaves, over the record's fragments, e = dL/do_eff per fragment (unclamped ones;
+        // go below is their sum) and the moments sum e dx, e dy, e dx^2, e dx dy, e dy^2, (dx, dy)
+        // the pixel offset from the mean. The exponent q = -(a dx^2 + 2 b dx dy + c dy^2) / 2 has
+        // dL/dq = o_eff e, so the gradients of the pixel mean and of the conic (a, b, c) follow here,
+        // once per record.
         const float* gr = grad2d + 9 * r;
-        const float gu = p.conic[0] * gr[0] + p.conic[1] * gr[1];
-        const float gv = p.conic[1] * gr[0] + p.conic[2] * gr[1];
-        const float ga = -0.5f * gr[2], gb = -gr[3], gc = -0.5f * gr[4], go = gr[5];
+        const float oe = g.o_eff;
+        const float m0 = oe * gr[0], m1 = oe * gr[1];
+        const float gu = p.conic[0] * m0 + p.conic[1] * m1;
+        const float gv = p.conic[1] * m0 + p.conic[2] * m1;
+        const float ga = -0.5f * oe * gr[2], gb = -oe * gr[3], gc = -0.5f * oe * gr[4], go = gr[5];
         const float gcol[3] = {gr[6], gr[7], gr[8]};
 
         // colour

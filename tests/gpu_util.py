@@ -63,23 +63,24 @@ def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
         g2 = fr.alloc.blocks[nblocks]
         moments = g2[: nr * 9 * 4].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
         out["grad2d_moments"] = moments
-        conic = out["conic_o"][:, :3].astype(np.float64) if nr else np.zeros((0, 3))
-        out["grad2d"] = grad2d_from_moments(moments, conic)
+        conic_o = out["conic_o"].astype(np.float64) if nr else np.zeros((0, 4))
+        out["grad2d"] = grad2d_from_moments(moments, conic_o)
     return out
 
 
-def grad2d_from_moments(m: np.ndarray, conic: np.ndarray) -> np.ndarray:
+def grad2d_from_moments(m: np.ndarray, conic_o: np.ndarray) -> np.ndarray:
     """The library's per-record backward buffer holds, per record, the sums over its fragments of
-    dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2 (dq the loss gradient of the Gaussian's exponent
-    q = -(a dx^2 + 2 b dx dy + c dy^2) / 2), then the opacity and RGB gradients. This returns the
-    gradients of (u, v, a, b, c, o, r, g, b) that the oracle's blend backward produces."""
+    e dx, e dy, e dx^2, e dx dy, e dy^2 and e, with e the loss gradient of the effective opacity of an
+    unclamped fragment (the gradient of the Gaussian's exponent q = -(a dx^2 + 2 b dx dy + c dy^2) / 2
+    is o_eff e), then the RGB gradients. This returns the gradients of (u, v, a, b, c, o, r, g, b)
+    that the oracle's blend backward produces. conic_o: the records' (a, b, c, o_eff)."""
     g = np.array(m, dtype=np.float64, copy=True)
-    a, b, c = conic[:, 0], conic[:, 1], conic[:, 2]
-    g[:, 0] = a * m[:, 0] + b * m[:, 1]
-    g[:, 1] = b * m[:, 0] + c * m[:, 1]
-    g[:, 2] = -0.5 * m[:, 2]
-    g[:, 3] = -m[:, 3]
-    g[:, 4] = -0.5 * m[:, 4]
+    a, b, c, oe = conic_o[:, 0], conic_o[:, 1], conic_o[:, 2], conic_o[:, 3]
+    g[:, 0] = oe * (a * m[:, 0] + b * m[:, 1])
+    g[:, 1] = oe * (b * m[:, 0] + c * m[:, 1])
+    g[:, 2] = -0.5 * oe * m[:, 2]
+    g[:, 3] = -oe * m[:, 3]
+    g[:, 4] = -0.5 * oe * m[:, 4]
     return g
 
 

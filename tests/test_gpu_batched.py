@@ -170,7 +170,7 @@ def _full_size_sampled(scene, cams, cfg, frac, seed):
     grads = R.backward(ds, fr, dl)
     torch.cuda.synchronize()
     g2 = grad2d_from_moments(fr.alloc.blocks[nb][: nr * 36].view(torch.float32).view(nr, 9).cpu().numpy(),
-                             rec["conic"])
+                             np.column_stack([rec["conic"], rec["o"]]))
     ref = np.zeros_like(g2)
     ref_abs = np.zeros_like(g2)
     for vi, cam in enumerate(cams):
