@@ -80,7 +80,7 @@ __device__ __forceinline__ bool frag(const Staged& s, float px, float py, float&
     G = __builtin_amdgcn_exp2f(q2);
     const float raw = s.p0.z * G;
     clamped = raw > kAlphaMax;
-    alpha = clamped ? kAlphaMax : raw;
+    alpha = fminf(raw, kAlphaMax);  // the same value (a NaN raw fails the q2 test below anyway)
     return (q2 <= 0.0f) & (alpha >= kAlphaMin);
 }
 
