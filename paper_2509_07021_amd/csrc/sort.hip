@@ -481,11 +481,42 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
                                                        uint32_t* __restrict__ tile_keys, uint64_t* __restrict__ keys64,
                                                        uint32_t* __restrict__ vals, int64_t capacity, int32_t* status) {
     constexpr int SUB = 8;
+    constexpr int kBuckets = 64;  // tile counts >= 63 share the last bucket
     __shared__ uint32_t w_tile[kEmitWindow];
     __shared__ uint32_t w_val[kEmitWindow];
     __shared__ uint32_t range[2];
-    const int64_t k = (int64_t)blockIdx.x * kEmitThreads + threadIdx.x;
-    const int64_t k_last = min((int64_t)(blockIdx.x + 1) * kEmitThreads, n_records) - 1;
+    __shared__ uint32_t bucket[kBuckets];
+    __shared__ uint16_t perm[kEmitThreads];
+    const int64_t kb = (int64_t)blockIdx.x * kEmitThreads;
+    const int64_t k_last = min(kb + kEmitThreads, n_records) - 1;
+    {
+        // A lane's time is set by the record with the most rows and tiles in its wave, so the
+        // workgroup's records are dealt to lanes grouped by tile count (a counting sort in LDS).
+        // Which lane handles a record does not change what is written where.
+        const int64_t k0 = kb + threadIdx.x;
+        uint32_t nt0 = 0;
+        if (k0 < n_records) {
+            const uint32_t g0 = order ? order[k0] : (uint32_t)k0;
+            nt0 = rec.packed[g0].ntiles;
+            if (k0 == k_last) {
+                range[0] = offsets[kb];
+                range[1] = (uint32_t)((int64_t)offsets[k0] + nt0);
+            }
+        }
+        if (threadIdx.x < kBuckets) bucket[threadIdx.x] = 0u;
+        __syncthreads();
+        const uint32_t key = min(nt0, (uint32_t)kBuckets - 1u);
+        const uint32_t rank = atomicAdd(&bucket[key], 1u);
+        __syncthreads();
+        if (threadIdx.x < kBuckets) {  // one wave: exclusive scan of the bucket sizes
+            const uint32_t c = bucket[threadIdx.x];
+            bucket[threadIdx.x] = wave_incl_scan(c) - c;
+        }
+        __syncthreads();
+        perm[bucket[key] + rank] = (uint16_t)threadIdx.x;
+        __syncthreads();
+    }
+    const int64_t k = kb + perm[threadIdx.x];
     const bool has = k < n_records;
     const uint32_t g = has ? (order ? order[k] : (uint32_t)k) : 0u;
     // the record's 64-byte line: mean, conic, colour + cutoff, radius / ntiles / half-extents
@@ -496,11 +527,6 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     }
     const uint32_t nt = has ? __float_as_uint(q3.y) : 0u;
     const int64_t off = has ? (int64_t)offsets[k] : 0;
-    if (k == k_last) {
-        range[0] = offsets[(int64_t)blockIdx.x * kEmitThreads];
-        range[1] = (uint32_t)(off + nt);
-    }
-    __syncthreads();
     const int64_t lo = range[0], hi = range[1];
     if (has && nt && off + (int64_t)nt > capacity) status[1] = 1;
     // record geometry and the view fields the loops need, in registers (only threads with pairs)
