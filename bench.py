@@ -9,7 +9,10 @@ masks. Two forms are measured:
 A step is one whole forward+backward of the workload's views. Inputs are resident in HBM before
 the timed region. Default launch configuration: 32x32 tiles for the key table, blending per 8x8
 sub-tile. Each stage's kernels are also timed live with HIP events (eager calls of the same
-workload); the slowest stage gives the roofline line. The FP64 CPU oracle is timed on the headline
+workload); the slowest stage gives the roofline line, and every stage is set against its own bound
+(`stage_roofline`: algorithmic HBM bytes at 8 TB/s, or blend FLOPs at the FP32 peak), the whole
+path against the sum of those bounds (`path_roofline`). Per-step p10/p50/p90 times of the graph
+come from a second run of single-step event pairs. The FP64 CPU oracle is timed on the headline
 workload's views (all 8 by default). Also reported: the post-processing of a post-ADMM scene and
 an SG-versus-SH colour comparison on the same renderer (skip with --no-post).
 
@@ -107,6 +110,20 @@ def timed(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def step_percentiles(fn, steps, stream):
+    """Per-step times (ms) of `steps` further launches, each bracketed by its own events."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    pick = lambda q: round(t[min(len(t) - 1, int(round(q * (len(t) - 1))))], 4)
+    return {"p10": pick(0.1), "p50": pick(0.5), "p90": pick(0.9), "steps": steps}
+
+
 def fragment_counts(R, ds, cams, cfg):
     """(blended, evaluated, replayed) fragments of one forward, counted by the stats instance."""
     import torch
@@ -121,20 +138,20 @@ def fragment_counts(R, ds, cams, cfg):
     return blended, evaluated, replayed, int(fr.state.n_pairs)
 
 
-def stage_bytes(stage, n, nv, pairs, npix, ntiles, geom_bytes, k):
-    """Algorithmic HBM bytes of one launch of an HBM-bound stage."""
+def stage_bytes(stage, n, nv, pairs, npix, ntiles, geom_bytes, k, tile_bits=14):
+    """Algorithmic HBM bytes of one launch of an HBM-bound stage (two-stage sort, default flags)."""
     nr = n * nv
-    rec = 16 + 16 + 16 + 4 + 4 + 4          # mean, conic+o, rgb+depth, radius, ntiles, depth key
+    rec = 64 + 4 + 4 + 4                    # packed record line, tile count, depth key, sort value
     if stage == "project":
         return n * geom_bytes + nr * rec
     if stage == "depth_sort":
         return 4 * nr * (4 + 8 + 8)         # 4 passes: key read (count), key+value read, write
     if stage == "scan":
-        return nr * (4 + 4 + 4 + 4)         # ntiles gathered through the order twice, order, offsets
+        return nr * (4 + 4 + 4 + 4)         # sorted values read twice, rewritten as ids, offsets written
     if stage == "emit":
-        return nr * (4 + 4 + 16 + 8) + pairs * 8
+        return nr * (4 + 4 + 64) + pairs * 8  # order, offset and record line per record; key+value per pair
     if stage == "pair_sort":
-        passes = 2
+        passes = (tile_bits + 7) // 8
         return passes * pairs * (4 + 8 + 8)
     if stage == "ranges":
         return pairs * 4 + ntiles * 8
@@ -250,7 +267,14 @@ def cpu_baseline(scene, cams, tile, n_sample_views, seed=11):
     O.render_backward(pl, scene.k, sample, tile, w, fwd=fwd)
     t2 = time.perf_counter()
     npix = sum(c.width * c.height for c in sample)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(npix / (t2 - t0) / 1e6, 4), "unit": "Mpixel/s", "cores": O.threads(), "kind": "oracle",
+            "cpu_model": model,
             "sample": (f"FP64 oracle on {len(sample)} of the {len(cams)} views of the benchmark workload "
                        f"({sample[0].width}x{sample[0].height}, full frames, {scene.n} Gaussians read from their "
                        f"{scene.dt_geom}/{scene.dt_color}/{scene.dt_amp} storage): forward {t1 - t0:.1f} s, "
@@ -344,6 +368,7 @@ def main():
     batched_fb_peak = torch.cuda.max_memory_allocated()
     counted = g.status()
     ms_batched = timed(g.launch, args.steps, args.warmup, g.stream)
+    step_ms = step_percentiles(g.launch, max(args.steps, 10), g.stream)
     counted_after = g.status()
     assert counted == counted_after == pairs8, (counted, counted_after, pairs8)
     mpix_batched = npix8 / ms_batched / 1e3
@@ -383,6 +408,25 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_of(dominant),
                 "avg_ms": round(stage_ms[dominant], 4)}
     log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+    # every stage against its own bound (HBM bytes at 8 TB/s, or blend FLOPs at the FP32 peak), and the
+    # whole path against the sum of those bounds
+    tile_bits = max(1, (nt8 - 1).bit_length())
+    stage_roof, bound_ms = {}, 0.0
+    for st, ms in stage_ms.items():
+        if st in ("blend_fwd", "blend_bwd"):
+            fl = FLOP_TEST * evaluated + (FLOP_FWD_BLEND if st == "blend_fwd" else FLOP_BWD_BLEND) * blended
+            ach = fl / (ms * 1e-3) / 1e12
+            stage_roof[st] = {"bound": "alu", "achieved": round(ach, 2), "unit": "TFLOP/s",
+                              "frac": round(ach / PEAK_FP32_TFLOPS, 4)}
+            bound_ms += fl / (PEAK_FP32_TFLOPS * 1e12) * 1e3
+        else:
+            by = stage_bytes(st, scene.n, len(cams8), pairs8, npix8, nt8, geom_bytes, scene.k, tile_bits)
+            ach = by / (ms * 1e-3) / 1e9
+            stage_roof[st] = {"bound": "hbm", "achieved": round(ach, 1), "unit": "GB/s",
+                              "frac": round(ach / PEAK_HBM_GBS, 4), "bytes": int(by)}
+            bound_ms += by / (PEAK_HBM_GBS * 1e9) * 1e3
+    path_roof = {"bound_ms": round(bound_ms, 4), "measured_ms": round(sum(stage_ms.values()), 4),
+                 "frac": round(bound_ms / sum(stage_ms.values()), 4)}
 
     out = {
         "metric": "fwd+bwd Mpixel/s at 1M Gaussians 1080p, peak VRAM; FP16-batched vs FP32 plain",
@@ -411,7 +455,10 @@ def main():
                                         "forward_backward": round(plain_fb_peak / 1e6, 1),
                                         "static_params": round(scene.n * (14 + 8 * scene.k + 1) * 4 / 1e6, 1),
                                         "resident_before": round(base_alloc / 1e6, 1)}},
+        "step_ms_percentiles": step_ms,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "stage_roofline": stage_roof,
+        "path_roofline": path_roof,
         "roofline": roof,
     }
     if not args.no_post:
