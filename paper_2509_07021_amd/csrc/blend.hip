@@ -546,10 +546,11 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
             Staged st;
             uint32_t g = 0;
             if (idx < rg.y) {
-                // the key's sub-tile flags, when present, decide before the record is gathered
+                // the key's sub-tile flags, when present, decide before the record is gathered (the
+                // record id is loaded with the key, not after it)
+                g = a.vals[idx];
                 const bool flagged = !a.tkeys || ((a.tkeys[idx] >> (16 + q.sidx)) & 1u);
                 if (flagged) {
-                    g = a.vals[idx];
                     stage(a, g, (double)c.x0, (double)c.y0, &st);
                     hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
                 }
@@ -673,9 +674,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             Staged st;
             uint32_t g = 0;
             if ((uint32_t)lane < cnt) {
+                g = a.vals[idx];
                 const bool flagged = !a.tkeys || ((a.tkeys[idx] >> (16 + q.sidx)) & 1u);
                 if (flagged) {
-                    g = a.vals[idx];
                     stage(a, g, (double)c.x0, (double)c.y0, &st);
                     hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
                 }
