@@ -539,17 +539,24 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
         uint32_t last = 0;
         const uint2 rg = a.ranges[q.t];
         const float px = lx + 0.5f, py = ly + 0.5f;
+        // each chunk's tile keys and record ids are loaded one chunk ahead, while the previous
+        // chunk's entries are blended
+        uint32_t key_n = 0, id_n = 0;
+        if (rg.x + lane < rg.y) {
+            id_n = a.vals[rg.x + lane];
+            key_n = a.tkeys ? a.tkeys[rg.x + lane] : 0u;
+        }
         for (uint32_t base = rg.x; base < rg.y; base += 64) {
             if (!__any(T > 0.0f)) break;
             const uint32_t idx = base + lane;
+            const uint32_t key = key_n, gid = id_n;
             bool hit = false;
             Staged st;
             uint32_t g = 0;
             if (idx < rg.y) {
-                // the key's sub-tile flags, when present, decide before the record is gathered (the
-                // record id is loaded with the key, not after it)
-                g = a.vals[idx];
-                const bool flagged = !a.tkeys || ((a.tkeys[idx] >> (16 + q.sidx)) & 1u);
+                // the key's sub-tile flags, when present, decide before the record is gathered
+                g = gid;
+                const bool flagged = !a.tkeys || ((key >> (16 + q.sidx)) & 1u);
                 if (flagged) {
                     stage(a, g, (double)c.x0, (double)c.y0, &st);
                     hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
@@ -562,6 +569,10 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                 lds[slot] = st;
                 lds_pos[slot] = idx - rg.x;
                 if (IMP) lds_id[slot] = g;
+            }
+            if (idx + 64u < rg.y) {
+                id_n = a.vals[idx + 64u];
+                key_n = a.tkeys ? a.tkeys[idx + 64u] : 0u;
             }
             wave_sync();
             for (int k0 = 0; k0 < nhit; k0 += 4) {
@@ -666,16 +677,24 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
         if (wave_last == 0) continue;  // wave-uniform: no pixel of the sub-tile blended anything
         const uint2 rg = a.ranges[q.t];
         const float px = lx + 0.5f, py = ly + 0.5f;
+        // tile keys and record ids loaded one chunk ahead, as in the forward
+        uint32_t key_n = 0, id_n = 0;
+        if ((uint32_t)lane < wave_last) {
+            const uint32_t i0 = rg.x + wave_last - 1u - (uint32_t)lane;
+            id_n = a.vals[i0];
+            key_n = a.tkeys ? a.tkeys[i0] : 0u;
+        }
         for (uint32_t end = rg.x + wave_last; end > rg.x;) {
             const uint32_t beg = end - rg.x > 64u ? end - 64u : rg.x;
             const uint32_t cnt = end - beg;
             const uint32_t idx = end - 1u - (uint32_t)lane;  // descending list positions
+            const uint32_t key = key_n, gid = id_n;
             bool hit = false;
             Staged st;
             uint32_t g = 0;
             if ((uint32_t)lane < cnt) {
-                g = a.vals[idx];
-                const bool flagged = !a.tkeys || ((a.tkeys[idx] >> (16 + q.sidx)) & 1u);
+                g = gid;
+                const bool flagged = !a.tkeys || ((key >> (16 + q.sidx)) & 1u);
                 if (flagged) {
                     stage(a, g, (double)c.x0, (double)c.y0, &st);
                     hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
@@ -688,6 +707,10 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 lds[slot] = st;
                 lds_pos[slot] = idx - rg.x;
                 lds_slot[slot] = 9ull * g;
+            }
+            if ((uint32_t)lane < beg - rg.x) {  // the next chunk: positions beg - 1 - lane downwards
+                id_n = a.vals[beg - 1u - (uint32_t)lane];
+                key_n = a.tkeys ? a.tkeys[beg - 1u - (uint32_t)lane] : 0u;
             }
             wave_sync();
             for (int k = 0; k < nhit; ++k) {
