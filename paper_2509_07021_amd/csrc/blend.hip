@@ -1,5 +1,6 @@
-// blend.hip -- per-tile front-to-back alpha blending (forward) and its back-to-front replay
-// (backward), gfx950.
+// blend.hip -- front-to-back alpha blending (forward) and its back-to-front replay (backward),
+// gfx950: per-tile workgroup kernels, and the sub-tile kernels further down (one wave64 per 8 x 8
+// sub-tile walking its tile's list; the configuration the benchmark runs).
 //
 // Compositing follows Sec. 3.1: C = sum_i c_i alpha_i prod_{j<i}(1 - alpha_j), alpha_i = o_i times
 // the 2D Gaussian at the pixel, with the 3DGS conventions (alpha clamped to 0.99, fragments below
@@ -17,10 +18,12 @@
 //
 // The backward walks each tile's list from the largest per-pixel last index down to 0, recovers
 // the transmittance in front of each fragment by division, carries the background seen behind
-// the fragment, and accumulates the nine per-record 2D gradients. They are summed over the
-// wave's pixels with a transposed butterfly (16 cross-lane exchanges for 9 values) and added to
-// the record's slot with nine lanes of one hardware float atomic, only when some lane of the wave
-// contributed.
+// the fragment, and accumulates nine per-record sums: e = dL/do_eff of each unclamped fragment,
+// its moments e dx, e dy, e dx^2, e dx dy, e dy^2 (the exponent's gradient is o_eff e, so the
+// projection backward turns them into the mean and conic gradients once per record), and the
+// colour gradient. They are summed over the wave's pixels with a transposed butterfly of
+// permlane swaps and DPP adds and added to the record's slot with nine lanes of one hardware
+// float atomic, only when some lane of the wave contributed.
 #include "megs_internal.hpp"
 
 namespace megs {
@@ -470,8 +473,7 @@ __device__ __forceinline__ void wave_sync() {
 // Without the work queue, the forward's workgroup b runs item xcd_item(b): the hardware deals
 // consecutive workgroups round-robin to the 8 XCDs, and this hands each XCD one contiguous eighth
 // of the sub-tiles (with 8 views, one view each), so the records an XCD gathers stay in its own L2.
-// The backward keeps identity order, which measured faster for it: its time goes to the gradient
-// atomics, which are executed beyond the L2 anyway.
+// The backward keeps identity order, which measured faster for it.
 constexpr int kXcds = 8;
 __device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n_items) {
     const int64_t per = n_items / kXcds, rem = n_items % kXcds;
