@@ -589,7 +589,10 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                         const uint32_t posk = lds_pos[k];
                         float dx, dy, G, alpha;
                         bool clamped;
-                        const bool pass = frag(s, px, py, dx, dy, G, alpha, clamped) & (T > 0.0f);
+                        // a live pixel has T >= kTMin, a terminated one (or one outside the image)
+                        // T < 0; this compare, not shared with the termination test above, lets the
+                        // wave vote below branch on the lane mask directly
+                        const bool pass = frag(s, px, py, dx, dy, G, alpha, clamped) & (T >= kTMin);
                         if (STATS) n_evaluated += T > 0.0f;
                         if (__any(pass)) {
                             const float Tn = T * (1.0f - alpha);
