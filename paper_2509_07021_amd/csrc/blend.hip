@@ -256,8 +256,8 @@ __device__ __forceinline__ void swap16(float& a, float& b) {
     b = __uint_as_float(r[1]);
 }
 template <int CTRL>
-__device__ __forceinline__ float dpp(float v) {
-    return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), CTRL, 0xf, 0xf, false));
+__device__ __forceinline__ float dpp(float v) {  // lanes whose source lane is invalid read 0
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 constexpr int kQuadXor1 = 0xb1, kQuadXor2 = 0x4e, kRowMirror = 0x140, kRowHalfMirror = 0x141;
 constexpr int kRowBcast15 = 0x142;  // lane 15 of the previous 16-lane row (rows 1-3)
