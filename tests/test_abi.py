@@ -26,6 +26,16 @@ def test_library_exports_every_declared_symbol():
     assert set(L.EXPORTED) == set(names)
 
 
+def test_flag_values_match_the_header():
+    text = open(os.path.join(ROOT, "include", "megs.h")).read()
+    flags = dict((name, int(val)) for name, val in re.findall(r"#define (MEGS_FLAG_[A-Z_]+) (\d+)u", text))
+    assert set(flags) == {"MEGS_FLAG_ONE_STAGE_SORT", "MEGS_FLAG_PERSISTENT", "MEGS_FLAG_STATS",
+                          "MEGS_FLAG_DETERMINISTIC", "MEGS_FLAG_RECORD_PLANES"}
+    for name, val in flags.items():
+        assert getattr(L, name) == val, name
+    assert len(set(flags.values())) == len(flags) and all(v & (v - 1) == 0 for v in flags.values())
+
+
 def test_version_and_empty_error():
     lib = L.load()
     assert lib.megs_version().startswith(b"megs")
