@@ -36,6 +36,26 @@ struct Staged {
     float4 p2;  // c, r, g, b
 };
 
+// An entry kept for an 8x8 sub-tile, as the sub-tile blends read it back from LDS: the staged
+// record without its box (the box only decides whether the entry is kept), with the entry's list
+// position and record id in its place, so that one LDS address serves every read of the entry.
+struct Kept {
+    float4 p0, p1, p2;  // as in Staged
+    uint32_t pos;       // list position relative to the tile's range start
+    uint32_t id;        // record id (importance output)
+    uint64_t e9;        // 9 x record id: the record's first gradient element (backward)
+};
+
+// &lds[k] through a VGPR copy of its byte offset. The compiler cannot rebuild the result of an asm
+// statement, so every read of the entry (and, with immediate offsets, of the entries after it)
+// shares this one address register, where it would otherwise re-derive the address from the
+// scalar index with a VALU move before each group of reads.
+__device__ __forceinline__ const Kept* kept_at(const Kept* lds, int k) {
+    uint32_t off;
+    asm("v_mov_b32 %0, %1" : "=v"(off) : "s"(k * (int)sizeof(Kept)));
+    return reinterpret_cast<const Kept*>(reinterpret_cast<const char*>(lds) + off);
+}
+
 // Pixel layout of a (TILE, WAVES) workgroup: wave w owns a WW x WH block of the tile (the whole
 // tile, its upper/lower half, or one quadrant), its lanes cover LW x LH pixels per slot, and
 // pixel slot j of a lane lies LH j rows below slot 0. Compact blocks let a wave skip every staged
@@ -74,7 +94,8 @@ __device__ __forceinline__ bool box_meets(const float4& b, int x0, int x1, int y
 
 // Alpha test of one fragment (no branches): pass = (q <= 0 and alpha >= 1/255). The forward and
 // the backward call this same function, so both take identical decisions.
-__device__ __forceinline__ bool frag(const Staged& s, float px, float py, float& dx, float& dy, float& G,
+template <class E>  // Staged or Kept
+__device__ __forceinline__ bool frag(const E& s, float px, float py, float& dx, float& dy, float& G,
                                      float& alpha, bool& clamped) {
     dx = px - s.p0.x;
     dy = py - s.p0.y;
@@ -523,9 +544,7 @@ __device__ __forceinline__ SubCtx sub_ctx(const BlendArgs& a, int64_t w, int til
 template <bool STATS, bool IMP>
 __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int persistent) {
     constexpr int SUB = 8;
-    __shared__ Staged lds[64];
-    __shared__ uint32_t lds_pos[64];
-    __shared__ uint32_t lds_id[64];
+    __shared__ Kept lds[64];
     __shared__ uint32_t work_slot;
     const int lane = __lane_id();
     const int64_t n_items = a.n_tiles * (int64_t)(tile / SUB) * (tile / SUB);
@@ -568,9 +587,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
             const int nhit = __popcll(m);
             if (hit) {
                 const int slot = lane_rank(m);
-                lds[slot] = st;
-                lds_pos[slot] = idx - rg.x;
-                if (IMP) lds_id[slot] = g;
+                lds[slot] = Kept{st.p0, st.p1, st.p2, idx - rg.x, g, 0ull};
             }
             if (idx + 64u < rg.y) {
                 id_n = a.vals[idx + 64u];
@@ -581,12 +598,13 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                 // the wave stops once all its pixels have terminated; checked every 4 entries (a
                 // terminated pixel has T < 0 and takes no further fragment in between)
                 if (!__any(T > 0.0f)) break;
+                const Kept* kp = kept_at(lds, k0);
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     const int k = k0 + kk;
                     if (k < nhit) {  // wave-uniform
-                        const Staged s = lds[k];
-                        const uint32_t posk = lds_pos[k];
+                        const Kept s = kp[kk];
+                        const uint32_t posk = s.pos;
                         float dx, dy, G, alpha;
                         bool clamped;
                         // a live pixel has T >= kTMin, a terminated one (or one outside the image)
@@ -610,7 +628,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
 #pragma unroll
                                 for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d);
                                 if (lane == 0 && wsum != 0.0f)
-                                    unsafeAtomicAdd(a.importance + (lds_id[k] - (int64_t)c.view * a.n), wsum);
+                                    unsafeAtomicAdd(a.importance + (s.id - (int64_t)c.view * a.n), wsum);
                             }
                         }
                     }
@@ -647,9 +665,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
 
 __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int persistent) {
     constexpr int SUB = 8;
-    __shared__ Staged lds[64];
-    __shared__ uint32_t lds_pos[64];
-    __shared__ uint64_t lds_slot[64];  // 9 x record id: the record's first gradient element
+    __shared__ Kept lds[64];
     __shared__ uint32_t work_slot;
     const int lane = __lane_id();
     // the 9 sums leave through one 9-lane atomic: lanes 0, 8, .., 56 hold sums 0..7, lane 63 sum 8
@@ -709,9 +725,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             const int nhit = __popcll(m);
             if (hit) {
                 const int slot = lane_rank(m);
-                lds[slot] = st;
-                lds_pos[slot] = idx - rg.x;
-                lds_slot[slot] = 9ull * g;
+                lds[slot] = Kept{st.p0, st.p1, st.p2, idx - rg.x, g, 9ull * g};
             }
             if ((uint32_t)lane < beg - rg.x) {  // the next chunk: positions beg - 1 - lane downwards
                 id_n = a.vals[beg - 1u - (uint32_t)lane];
@@ -719,8 +733,8 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             }
             wave_sync();
             for (int k = 0; k < nhit; ++k) {
-                const Staged s = lds[k];
-                const uint32_t pos = lds_pos[k];
+                const Kept s = *kept_at(lds, k);
+                const uint32_t pos = s.pos;
                 float alpha, G, dx, dy;
                 bool clamped;
                 const bool incl = frag(s, px, py, dx, dy, G, alpha, clamped) & (pos < lst);
@@ -747,7 +761,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 acc[4] = acc[1] * dy;
                 float tot, tot8;
                 wave_sum9(acc, tot, tot8);
-                if (adds) unsafeAtomicAdd(a.grad2d + (lds_slot[k] + comp), lane == kLaneSum8 ? tot8 : tot);
+                if (adds) unsafeAtomicAdd(a.grad2d + (s.e9 + comp), lane == kLaneSum8 ? tot8 : tot);
             }
             wave_sync();
             end = beg;
