@@ -12,9 +12,11 @@ sub-tile. Each stage's kernels are also timed live with HIP events (eager calls 
 workload); the slowest stage gives the roofline line, and every stage is set against its own bound
 (`stage_roofline`: algorithmic HBM bytes at 8 TB/s, or blend FLOPs at the FP32 peak), the whole
 path against the sum of those bounds (`path_roofline`). Per-step p10/p50/p90 times of the graph
-come from a second run of single-step event pairs. The FP64 CPU oracle is timed on the headline
-workload's views (all 8 by default). Also reported: the post-processing of a post-ADMM scene and
-an SG-versus-SH colour comparison on the same renderer (skip with --no-post).
+come from a second run of single-step event pairs; a plain device-to-device copy gives the
+achievable HBM rate (`hbm_copy`), which each HBM stage is also set against. The FP64 CPU oracle is
+timed on the headline workload's views (all 8 by default), and beside it on the plain FP32 view and
+on the 2,000-Gaussian 128x128 case. Also reported: the post-processing of a post-ADMM scene and an
+SG-versus-SH colour comparison on the same renderer (skip with --no-post).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-post]
 """
@@ -251,35 +253,63 @@ def colour_models(args, cfg, scene, cams):
     return out
 
 
-def cpu_baseline(scene, cams, tile, n_sample_views, seed=11):
-    """The FP64 oracle on the host, on the benchmark's own workload: full forward and backward
-    (projection, key table, blend, blend backward, projection backward) of the first
-    n_sample_views of its views at full resolution, reading the exact stored (FP16/BF16) values.
-    Mpixel/s of that sample is the oracle's rate for the whole step."""
+def oracle_seconds(scene, cams, tile, seed=11):
+    """(forward s, backward s, pixels) of one full FP64 oracle forward and backward (projection,
+    key table, blend, blend backward, projection backward) of `cams`, reading the exact stored
+    values of `scene`."""
     from oracle import oracle as O
     from paper_2509_07021_amd import scenes as S
-    sample = list(cams[:n_sample_views])
     pl = scene.widened()
-    w = S.loss_weights(sample, seed)
+    w = S.loss_weights(cams, seed)
     t0 = time.perf_counter()
-    fwd = O.render(pl, scene.k, sample, tile)
+    fwd = O.render(pl, scene.k, cams, tile)
     t1 = time.perf_counter()
-    O.render_backward(pl, scene.k, sample, tile, w, fwd=fwd)
+    O.render_backward(pl, scene.k, cams, tile, w, fwd=fwd)
     t2 = time.perf_counter()
-    npix = sum(c.width * c.height for c in sample)
+    return t1 - t0, t2 - t1, sum(c.width * c.height for c in cams)
+
+
+def cpu_baseline(scene, cams, tile, n_sample_views, others=()):
+    """The FP64 oracle on the host, on the benchmark's own workload: full forward and backward of
+    the first n_sample_views of its views at full resolution, reading the exact stored (FP16/BF16)
+    values. Mpixel/s of that sample is the oracle's rate for the whole step. `others` are
+    (name, scene, cameras, tile) workloads timed the same way and reported beside it."""
+    from oracle import oracle as O
+    sample = list(cams[:n_sample_views])
+    tf, tb, npix = oracle_seconds(scene, sample, tile)
+    also = {}
+    for name, sc, cm, tl in others:
+        f, b, n = oracle_seconds(sc, list(cm), tl)
+        also[name] = {"value": round(n / (f + b) / 1e6, 4), "unit": "Mpixel/s",
+                      "seconds": {"forward": round(f, 3), "backward": round(b, 3)}}
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": round(npix / (t2 - t0) / 1e6, 4), "unit": "Mpixel/s", "cores": O.threads(), "kind": "oracle",
+    return {"value": round(npix / (tf + tb) / 1e6, 4), "unit": "Mpixel/s", "cores": O.threads(), "kind": "oracle",
             "cpu_model": model,
             "sample": (f"FP64 oracle on {len(sample)} of the {len(cams)} views of the benchmark workload "
                        f"({sample[0].width}x{sample[0].height}, full frames, {scene.n} Gaussians read from their "
-                       f"{scene.dt_geom}/{scene.dt_color}/{scene.dt_amp} storage): forward {t1 - t0:.1f} s, "
-                       f"backward {t2 - t1:.1f} s"),
-            "seconds": {"forward": round(t1 - t0, 2), "backward": round(t2 - t1, 2)}}
+                       f"{scene.dt_geom}/{scene.dt_color}/{scene.dt_amp} storage): forward {tf:.1f} s, "
+                       f"backward {tb:.1f} s"),
+            "seconds": {"forward": round(tf, 2), "backward": round(tb, 2)},
+            "other_workloads": also}
+
+
+def copy_rate(stream, mib=1024, reps=10):
+    """Achievable HBM rate of a plain device-to-device copy of `mib` MiB (bytes read + written per
+    second, GB/s), timed with HIP events: the practical ceiling the HBM-bound stages are also set
+    against, beside the 8 TB/s of the specification."""
+    import torch
+    src = torch.ones(mib * (1 << 20) // 4, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timed(lambda: dst.copy_(src), reps, 2, stream)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": round(2 * mib * (1 << 20) / (ms * 1e-3) / 1e9, 1), "bytes_per_copy": 2 * mib * (1 << 20),
+            "ms_per_copy": round(ms, 4)}
 
 
 def main():
@@ -303,6 +333,8 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
         del src, dst
+    hbm_copy = copy_rate(torch.cuda.current_stream())
+    log(f"plain copy: {hbm_copy['GBps']:.0f} GB/s")
     t_start = time.perf_counter()
     scene, cams1 = S.make_workload("masked_1m_1080p", n=args.n)
     scene16 = scene.stored("f16", "f16", "bf16")
@@ -423,7 +455,8 @@ def main():
             by = stage_bytes(st, scene.n, len(cams8), pairs8, npix8, nt8, geom_bytes, scene.k, tile_bits)
             ach = by / (ms * 1e-3) / 1e9
             stage_roof[st] = {"bound": "hbm", "achieved": round(ach, 1), "unit": "GB/s",
-                              "frac": round(ach / PEAK_HBM_GBS, 4), "bytes": int(by)}
+                              "frac": round(ach / PEAK_HBM_GBS, 4), "frac_of_copy": round(ach / hbm_copy["GBps"], 4),
+                              "bytes": int(by)}
             bound_ms += by / (PEAK_HBM_GBS * 1e9) * 1e3
     path_roof = {"bound_ms": round(bound_ms, 4), "measured_ms": round(sum(stage_ms.values()), 4),
                  "frac": round(bound_ms / sum(stage_ms.values()), 4)}
@@ -460,6 +493,7 @@ def main():
         "stage_roofline": stage_roof,
         "path_roofline": path_roof,
         "roofline": roof,
+        "hbm_copy": hbm_copy,
     }
     if not args.no_post:
         del ds16
@@ -468,7 +502,10 @@ def main():
         out["colour_models"] = colour_models(args, cfg, scene, cams1)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(scene16, cams8, cfg.tile, args.cpu_views)
+        small, cams_small = S.make_workload("small_2k_128px")
+        others = [("masked_1m_1080p FP32, 1 view (the plain form)", scene, cams1, cfg.tile),
+                  ("small_2k_128px FP32, 1 view 128x128, 16x16 tiles", small, cams_small, 16)]
+        out["cpu_baseline"] = cpu_baseline(scene16, cams8, cfg.tile, args.cpu_views, others)
         log(f"cpu baseline in {time.perf_counter() - t0:.1f}s")
     print(json.dumps(out), flush=True)
     return 0
