@@ -29,21 +29,24 @@
 namespace megs {
 namespace {
 
+// A record as the blends use it, with the conic (a, b, c) folded into the exponent coefficients:
+// the backward needs the conic itself only per record, in the projection backward.
 struct Staged {
     float4 box; // tile-relative bounding box of the cutoff ellipse: x - rx, x + rx, y - ry, y + ry
     float4 p0;  // u_rel, v_rel, o, nb2   (nb2 = -b log2 e)
-    float4 p1;  // na2, nc2, a, b        (na2 = -a log2 e / 2, nc2 = -c log2 e / 2)
-    float4 p2;  // c, r, g, b
+    float4 p1;  // na2, nc2, r, g        (na2 = -a log2 e / 2, nc2 = -c log2 e / 2)
+    float b;    // blue
 };
 
 // An entry kept for an 8x8 sub-tile, as the sub-tile blends read it back from LDS: the staged
-// record without its box (the box only decides whether the entry is kept), with the entry's list
-// position and record id in its place, so that one LDS address serves every read of the entry.
+// record without its box (the box only decides whether the entry is kept), plus the entry's list
+// position and a record index, so that one LDS address serves every read of the entry (48 bytes).
 struct Kept {
-    float4 p0, p1, p2;  // as in Staged
-    uint32_t pos;       // list position relative to the tile's range start
-    uint32_t id;        // record id (importance output)
-    uint64_t e9;        // 9 x record id: the record's first gradient element (backward)
+    float4 p0, p1;   // as in Staged
+    float b;         // as in Staged
+    uint32_t pos1;   // one past the entry's list position (relative to the tile's range start)
+    uint64_t slot;   // forward: the record id (importance output); backward: 9 x record id, the
+                     // record's first gradient element
 };
 
 // &lds[k] through a VGPR copy of its byte offset. The compiler cannot rebuild the result of an asm
@@ -80,8 +83,8 @@ __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0,
     Staged s;
     const float ur = (float)(mx - x0), vr = (float)(my - y0);
     s.p0 = make_float4(ur, vr, co.w, -co.y * kLog2e);
-    s.p1 = make_float4(-0.5f * co.x * kLog2e, -0.5f * co.z * kLog2e, co.x, co.y);
-    s.p2 = make_float4(co.z, cd.x, cd.y, cd.z);
+    s.p1 = make_float4(-0.5f * co.x * kLog2e, -0.5f * co.z * kLog2e, cd.x, cd.y);
+    s.b = cd.z;
     s.box = make_float4(ur - q3.z, ur + q3.z, vr - q3.w, vr + q3.w);
     *dst = s;
 }
@@ -89,7 +92,7 @@ __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0,
 // Does the pixel block [x0, x1] x [y0, y1] (tile-relative, centres at +0.5) meet the staged
 // footprint's box? Wave-uniform when the block is.
 __device__ __forceinline__ bool box_meets(const float4& b, int x0, int x1, int y0, int y1) {
-    return (x0 + 0.5f <= b.y) & (x1 + 0.5f >= b.x) & (y0 + 0.5f <= b.w) & (y1 + 0.5f >= b.z);
+    return (x0 + 0.5f <= b.y) && (x1 + 0.5f >= b.x) && (y0 + 0.5f <= b.w) && (y1 + 0.5f >= b.z);
 }
 
 // Alpha test of one fragment (no branches): pass = (q <= 0 and alpha >= 1/255). The forward and
@@ -216,9 +219,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch
                     const bool incl = pass[j] & !term;
                     const float w = incl ? alpha[j] * T[j] : 0.0f;
                     if (IMP) wsum += w;
-                    C[j][0] = __fmaf_rn(w, s.p2.y, C[j][0]);
-                    C[j][1] = __fmaf_rn(w, s.p2.z, C[j][1]);
-                    C[j][2] = __fmaf_rn(w, s.p2.w, C[j][2]);
+                    C[j][0] = __fmaf_rn(w, s.p1.z, C[j][0]);
+                    C[j][1] = __fmaf_rn(w, s.p1.w, C[j][1]);
+                    C[j][2] = __fmaf_rn(w, s.b, C[j][2]);
                     T[j] = incl ? Tn : (term ? -T[j] : T[j]);
                     last[j] = incl ? pos + 1 : last[j];
                     mine |= T[j] > 0.0f;
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                             const float al = incl[j] ? alpha[j] : 0.0f;
                             const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - al);
                             const float w = al * Ti;
-                            const float d0 = s.p2.y - S[j][0], d1 = s.p2.z - S[j][1], d2 = s.p2.w - S[j][2];
+                            const float d0 = s.p1.z - S[j][0], d1 = s.p1.w - S[j][1], d2 = s.b - S[j][2];
                             acc[6] = __fmaf_rn(w, dl[j][0], acc[6]);
                             acc[7] = __fmaf_rn(w, dl[j][1], acc[7]);
                             acc[8] = __fmaf_rn(w, dl[j][2], acc[8]);
@@ -587,7 +590,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
             const int nhit = __popcll(m);
             if (hit) {
                 const int slot = lane_rank(m);
-                lds[slot] = Kept{st.p0, st.p1, st.p2, idx - rg.x, g, 0ull};
+                lds[slot] = Kept{st.p0, st.p1, st.b, idx - rg.x + 1u, g};
             }
             if (idx + 64u < rg.y) {
                 id_n = a.vals[idx + 64u];
@@ -604,7 +607,6 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                     const int k = k0 + kk;
                     if (k < nhit) {  // wave-uniform
                         const Kept s = kp[kk];
-                        const uint32_t posk = s.pos;
                         float dx, dy, G, alpha;
                         bool clamped;
                         // a live pixel has T >= kTMin, a terminated one (or one outside the image)
@@ -617,18 +619,18 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                             const bool term = pass & (Tn < kTMin);
                             const bool incl = pass & !term;
                             const float wgt = incl ? alpha * T : 0.0f;
-                            C0 = __fmaf_rn(wgt, s.p2.y, C0);
-                            C1 = __fmaf_rn(wgt, s.p2.z, C1);
-                            C2 = __fmaf_rn(wgt, s.p2.w, C2);
+                            C0 = __fmaf_rn(wgt, s.p1.z, C0);
+                            C1 = __fmaf_rn(wgt, s.p1.w, C1);
+                            C2 = __fmaf_rn(wgt, s.b, C2);
                             T = incl ? Tn : (term ? -T : T);
-                            last = incl ? posk + 1 : last;
+                            last = incl ? s.pos1 : last;
                             if (STATS) n_blended += incl;
                             if (IMP) {
                                 float wsum = wgt;
 #pragma unroll
                                 for (int d = 32; d >= 1; d >>= 1) wsum += __shfl_xor(wsum, d);
                                 if (lane == 0 && wsum != 0.0f)
-                                    unsafeAtomicAdd(a.importance + (s.id - (int64_t)c.view * a.n), wsum);
+                                    unsafeAtomicAdd(a.importance + ((int64_t)s.slot - (int64_t)c.view * a.n), wsum);
                             }
                         }
                     }
@@ -725,7 +727,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             const int nhit = __popcll(m);
             if (hit) {
                 const int slot = lane_rank(m);
-                lds[slot] = Kept{st.p0, st.p1, st.p2, idx - rg.x, g, 9ull * g};
+                lds[slot] = Kept{st.p0, st.p1, st.b, idx - rg.x + 1u, 9ull * g};
             }
             if ((uint32_t)lane < beg - rg.x) {  // the next chunk: positions beg - 1 - lane downwards
                 id_n = a.vals[beg - 1u - (uint32_t)lane];
@@ -734,16 +736,15 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             wave_sync();
             for (int k = 0; k < nhit; ++k) {
                 const Kept s = *kept_at(lds, k);
-                const uint32_t pos = s.pos;
                 float alpha, G, dx, dy;
                 bool clamped;
-                const bool incl = frag(s, px, py, dx, dy, G, alpha, clamped) & (pos < lst);
+                const bool incl = frag(s, px, py, dx, dy, G, alpha, clamped) & (s.pos1 <= lst);
                 if (!__any(incl)) continue;
                 float acc[9];
                 const float al = incl ? alpha : 0.0f;
                 const float Ti = T * __builtin_amdgcn_rcpf(1.0f - al);
                 const float wgt = al * Ti;
-                const float d0 = s.p2.y - S0, d1 = s.p2.z - S1, d2 = s.p2.w - S2;
+                const float d0 = s.p1.z - S0, d1 = s.p1.w - S1, d2 = s.b - S2;
                 acc[6] = wgt * dl0;
                 acc[7] = wgt * dl1;
                 acc[8] = wgt * dl2;
@@ -761,7 +762,11 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 acc[4] = acc[1] * dy;
                 float tot, tot8;
                 wave_sum9(acc, tot, tot8);
-                if (adds) unsafeAtomicAdd(a.grad2d + (s.e9 + comp), lane == kLaneSum8 ? tot8 : tot);
+                float val = lane == kLaneSum8 ? tot8 : tot;
+                // keeps the sums' last DPP adds in front of the branch: sunk into it (where only the
+                // adding lanes run), each would split into a DPP move and a separate add
+                asm volatile("" : "+v"(val));
+                if (adds) unsafeAtomicAdd(a.grad2d + (s.slot + comp), val);
             }
             wave_sync();
             end = beg;
