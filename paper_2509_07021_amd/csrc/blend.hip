@@ -693,7 +693,10 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             dl1 = dimg[plane + p];
             dl2 = dimg[2 * plane + p];
         }
-        float S0 = c.bg[0], S1 = c.bg[1], S2 = c.bg[2];
+        // the colour accumulated behind the current fragment (background included) enters the
+        // gradient only through its dot product with the pixel's colour gradient, so the replay
+        // carries that one scalar: P = S . dL/dC, updated as S is (S += alpha (c - S))
+        float P = __fmaf_rn(c.bg[0], dl0, __fmaf_rn(c.bg[1], dl1, c.bg[2] * dl2));
         uint32_t wave_last = lst;
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, d));
@@ -744,14 +747,13 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 const float al = incl ? alpha : 0.0f;
                 const float Ti = T * __builtin_amdgcn_rcpf(1.0f - al);
                 const float wgt = al * Ti;
-                const float d0 = s.p1.z - S0, d1 = s.p1.w - S1, d2 = s.b - S2;
+                // (c - S) . dL/dC, from c . dL/dC and the carried P
+                const float dcs = __fmaf_rn(s.p1.z, dl0, __fmaf_rn(s.p1.w, dl1, s.b * dl2)) - P;
                 acc[6] = wgt * dl0;
                 acc[7] = wgt * dl1;
                 acc[8] = wgt * dl2;
-                const float dal = Ti * __fmaf_rn(d0, dl0, __fmaf_rn(d1, dl1, d2 * dl2));
-                S0 = __fmaf_rn(al, d0, S0);
-                S1 = __fmaf_rn(al, d1, S1);
-                S2 = __fmaf_rn(al, d2, S2);
+                const float dal = Ti * dcs;
+                P = __fmaf_rn(al, dcs, P);
                 T = incl ? Ti : T;
                 const bool live = incl & !clamped;
                 acc[5] = live ? G * dal : 0.0f;  // dL/do_eff; the exponent gradient is o_eff times this
