@@ -38,11 +38,11 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (packed); the unpacked FMA cei
 #   alpha test of an evaluated fragment (offsets, quadratic form, exp, opacity, clamp, threshold): 15
 #   forward blend of an included fragment (transmittance, weight, colour accumulate): 10
 #   backward of an included fragment: transmittance recovery (1 - alpha, divide) 2, weight 1,
-#   colour gradient 3, colour minus background 3, alpha gradient (dot product, times T) 6,
-#   background recursion (3 FMA) 6, opacity gradient e = G dL/dalpha 1, the five moments of e
-#   (e dx, e dy, e dx^2, e dx dy, e dy^2) 5, summation of the 9 sums over pixels 9: 36 (the
+#   colour gradient 3, alpha gradient ((c - S) . dL/dC as c . dL/dC minus the carried P = S . dL/dC,
+#   times T) 7, recursion of P (1 FMA) 2, opacity gradient e = G dL/dalpha 1, the five moments of e
+#   (e dx, e dy, e dx^2, e dx dy, e dy^2) 5, summation of the 9 sums over pixels 9: 30 (the
 #   exponent gradient is o_eff e; o_eff and the conic are applied once per record, not per fragment)
-FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 36
+FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 30
 
 # HBM bytes per launch of a kernel on the headline workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a plain

@@ -17,8 +17,9 @@
 // offsets. The wave stops as soon as all its pixels have terminated.
 //
 // The backward walks each tile's list from the largest per-pixel last index down to 0, recovers
-// the transmittance in front of each fragment by division, carries the background seen behind
-// the fragment, and accumulates nine per-record sums: e = dL/do_eff of each unclamped fragment,
+// the transmittance in front of each fragment by division, carries the colour seen behind the
+// fragment (as its dot product with the pixel's colour gradient, the only form the gradient
+// uses), and accumulates nine per-record sums: e = dL/do_eff of each unclamped fragment,
 // its moments e dx, e dy, e dx^2, e dx dy, e dy^2 (the exponent's gradient is o_eff e, so the
 // projection backward turns them into the mean and conic gradients once per record), and the
 // colour gradient. They are summed over the wave's pixels with a transposed butterfly of
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
         const TileCtx c = tile_ctx(a, t, TILE);
         const uint2 rg = a.ranges[t];
         const int64_t plane = (int64_t)c.width * c.height;
-        float T[PPT], S[PPT][3], dl[PPT][3];
+        float T[PPT], P[PPT], dl[PPT][3];  // P = S . dL/dC, as in the sub-tile backward
         uint32_t lst[PPT];
         uint32_t maxlast = 0;
 #pragma unroll
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
             dl[j][0] = inside ? dimg[p] : 0.f;
             dl[j][1] = inside ? dimg[plane + p] : 0.f;
             dl[j][2] = inside ? dimg[2 * plane + p] : 0.f;
-            S[j][0] = c.bg[0]; S[j][1] = c.bg[1]; S[j][2] = c.bg[2];
+            P[j] = __fmaf_rn(c.bg[0], dl[j][0], __fmaf_rn(c.bg[1], dl[j][1], c.bg[2] * dl[j][2]));
             maxlast = max(maxlast, lst[j]);
         }
 #pragma unroll
@@ -414,14 +415,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                             const float al = incl[j] ? alpha[j] : 0.0f;
                             const float Ti = T[j] * __builtin_amdgcn_rcpf(1.0f - al);
                             const float w = al * Ti;
-                            const float d0 = s.p1.z - S[j][0], d1 = s.p1.w - S[j][1], d2 = s.b - S[j][2];
+                            const float dcs =
+                                __fmaf_rn(s.p1.z, dl[j][0], __fmaf_rn(s.p1.w, dl[j][1], s.b * dl[j][2])) - P[j];
                             acc[6] = __fmaf_rn(w, dl[j][0], acc[6]);
                             acc[7] = __fmaf_rn(w, dl[j][1], acc[7]);
                             acc[8] = __fmaf_rn(w, dl[j][2], acc[8]);
-                            const float dal = Ti * __fmaf_rn(d0, dl[j][0], __fmaf_rn(d1, dl[j][1], d2 * dl[j][2]));
-                            S[j][0] = __fmaf_rn(al, d0, S[j][0]);
-                            S[j][1] = __fmaf_rn(al, d1, S[j][1]);
-                            S[j][2] = __fmaf_rn(al, d2, S[j][2]);
+                            const float dal = Ti * dcs;
+                            P[j] = __fmaf_rn(al, dcs, P[j]);
                             T[j] = incl[j] ? Ti : T[j];
                             const bool live = incl[j] & !clamped[j];
                             // dL/do_eff of the fragment; its exponent gradient is o_eff times this
@@ -494,18 +494,9 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Without the work queue, the forward's workgroup b runs item xcd_item(b): the hardware deals
-// consecutive workgroups round-robin to the 8 XCDs, and this hands each XCD one contiguous eighth
-// of the sub-tiles (with 8 views, one view each), so the records an XCD gathers stay in its own L2.
-// The backward keeps identity order, which measured faster for it.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n_items) {
-    const int64_t per = n_items / kXcds, rem = n_items % kXcds;
-    const int64_t x = b % kXcds, k = b / kXcds;
-    // XCD x owns items [x per + min(x, rem), ...) of length per + (x < rem); the grid has exactly
-    // n_items workgroups, so XCD x receives exactly that many
-    return x * per + (x < rem ? x : rem) + k;
-}
+// Without the work queue, the forward's workgroup b runs item xcd_item(b): each XCD takes one
+// contiguous eighth of the sub-tiles (with 8 views, one view each), so the records an XCD gathers
+// stay in its own L2. The backward keeps identity order, which measured faster for it.
 
 __device__ __forceinline__ int64_t next_item(const BlendArgs& a, int64_t prev, bool persistent, int64_t n_items,
                                              uint32_t* slot, bool by_xcd) {

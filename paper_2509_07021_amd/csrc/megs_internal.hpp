@@ -20,6 +20,18 @@ constexpr float kLog2e = 1.4426950408889634f;
 
 constexpr int kWave = 64;
 
+// The hardware deals consecutive workgroups round-robin to the 8 XCDs (each with its own L2).
+// xcd_item(b, n) maps workgroup b of an n-workgroup grid to an item so that XCD x runs one
+// contiguous range of the n items: XCD x owns [x per + min(x, rem), ...) of length
+// per + (x < rem), and receives exactly that many workgroups. Items processed close together in
+// index order then share an L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n_items) {
+    const int64_t per = n_items / kXcds, rem = n_items % kXcds;
+    const int64_t x = b % kXcds, k = b / kXcds;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 // Per-view constants, device resident (uploaded once per forward or graph).
 struct ViewInfo {
     float R[9];
