@@ -169,14 +169,18 @@ __device__ __forceinline__ void view_dir(const float pos[3], const ViewInfo& vw,
     d[0] = dv[0] * il; d[1] = dv[1] * il; d[2] = dv[2] * il;
 }
 
+// The base colour c0 of Gaussian i (view-independent; read once, before the view loop).
+__device__ __forceinline__ void load_base(const SceneDev& sc, int64_t i, float base[3]) {
+    for (int c = 0; c < 3; ++c) base[c] = load_elem(sc.base, sc.dt_color, c * sc.n + i);
+}
+
 // The SG colour at d; returns false if not finite.
 template <int K>
-__device__ __forceinline__ bool sg_colour(const SceneDev& sc, int64_t i, const float pos[3], const ViewInfo& vw,
+__device__ __forceinline__ bool sg_colour(const float base[3], const float pos[3], const ViewInfo& vw,
                                           const Lobes<K>& L, float d[3], float& dlen, float rgb[3], float e[K > 0 ? K : 1],
                                           float muh[K > 0 ? K : 1][3], float dd2[K > 0 ? K : 1]) {
-    const int64_t n = sc.n;
     view_dir(pos, vw, d, dlen);
-    for (int c = 0; c < 3; ++c) rgb[c] = load_elem(sc.base, sc.dt_color, c * n + i);
+    for (int c = 0; c < 3; ++c) rgb[c] = base[c];
 #pragma unroll
     for (int l = 0; l < K; ++l) {
         const float ia = rsqrtf(L.ax[l][0] * L.ax[l][0] + L.ax[l][1] * L.ax[l][1] + L.ax[l][2] * L.ax[l][2]);
@@ -297,6 +301,8 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
     Lobes<K> L;
     LobeRef<RAGGED> lr;
     const bool lobes_ok = lobe_ref<RAGGED>(sc, i, K, lr) && load_lobes<K, RAGGED>(sc, lr, L);
+    float base[3] = {0.f, 0.f, 0.f};
+    if constexpr (SHD < 0) load_base(sc, i, base);
     for (int v = 0; v < nv; ++v) {
         const ViewInfo& vw = views[v];
         const int64_t r = (int64_t)v * sc.n + i;
@@ -309,7 +315,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
                 bool clamped[3];
                 ok = sh_colour<SHD>(sc, i, pos, vw, d, dlen, rgb, clamped);
             } else {
-                ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
+                ok = sg_colour<K>(base, pos, vw, L, d, dlen, rgb, e, muh, dd2);
             }
         }
         uint32_t nt = 0;
@@ -399,6 +405,8 @@ __device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewIn
     Lobes<K> L;
     LobeRef<RAGGED> lr;
     const bool lobes_ok = lobe_ref<RAGGED>(sc, i, K, lr) && load_lobes<K, RAGGED>(sc, lr, L);
+    float base[3] = {0.f, 0.f, 0.f};
+    if constexpr (SHD < 0) load_base(sc, i, base);
 
     float gpos[3] = {0.f, 0.f, 0.f}, gS3[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float gop = 0.f, gpm = 0.f, gbase[3] = {0.f, 0.f, 0.f};
@@ -423,7 +431,7 @@ __device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewIn
             if constexpr (SHD >= 0)
                 ok = sh_colour<SHD>(sc, i, pos, vw, d, dlen, rgb, clamped);
             else
-                ok = sg_colour<K>(sc, i, pos, vw, L, d, dlen, rgb, e, muh, dd2);
+                ok = sg_colour<K>(base, pos, vw, L, d, dlen, rgb, e, muh, dd2);
         }
         if (!ok) continue;
         // The blend leaves, over the record's fragments, e = dL/do_eff per fragment (unclamped ones;
@@ -539,6 +547,12 @@ __device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewIn
         for (int c = 0; c < 3; ++c) gpos[c] += W[c] * gt[0] + W[3 + c] * gt[1] + W[6 + c] * gt[2];
     }
 
+    // The rotation, scales and normalised quaternion are read and formed again here rather than
+    // kept in registers through the view loop, which would otherwise spill.
+    {
+        float pos2[3];
+        load_geo(sc, i, pos2, g);
+    }
     // S3 = M M', M = Rq diag(s): dL/dM = (G + G') M with G the full symmetric gradient
     // (off-diagonal entries of gS3 hold the sum of both symmetric positions).
     float Gf[9] = {gS3[0], 0.5f * gS3[1], 0.5f * gS3[2], 0.5f * gS3[1], gS3[3], 0.5f * gS3[4],
