@@ -29,7 +29,8 @@ __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __exp
 
 template <int K>
 struct Lobes {
-    float ax[K > 0 ? K : 1][3];
+    float mu[K > 0 ? K : 1][3];  // unit lobe axes mu / |mu| (view-independent, formed once)
+    float ia[K > 0 ? K : 1];     // 1 / |mu| of the raw axes
     float lam[K > 0 ? K : 1];
     float amp[K > 0 ? K : 1][3];
     float m[K > 0 ? K : 1];
@@ -76,7 +77,8 @@ __device__ __forceinline__ bool load_lobes(const SceneDev& sc, const LobeRef<RAG
 #pragma unroll
     for (int l = 0; l < K; ++l) {
         if (RAGGED && l >= r.cnt) {
-            L.ax[l][0] = 1.0f; L.ax[l][1] = 0.0f; L.ax[l][2] = 0.0f;
+            L.mu[l][0] = 1.0f; L.mu[l][1] = 0.0f; L.mu[l][2] = 0.0f;
+            L.ia[l] = 1.0f;
             L.lam[l] = 0.0f; L.m[l] = 0.0f;
             L.amp[l][0] = L.amp[l][1] = L.amp[l][2] = 0.0f;
             continue;
@@ -84,8 +86,10 @@ __device__ __forceinline__ bool load_lobes(const SceneDev& sc, const LobeRef<RAG
         float a0 = load_elem(sc.axis, sc.dt_color, r.at3(l, 0));
         float a1 = load_elem(sc.axis, sc.dt_color, r.at3(l, 1));
         float a2 = load_elem(sc.axis, sc.dt_color, r.at3(l, 2));
-        L.ax[l][0] = a0; L.ax[l][1] = a1; L.ax[l][2] = a2;
         float al2 = a0 * a0 + a1 * a1 + a2 * a2;
+        const float ia = rsqrtf(al2);
+        L.ia[l] = ia;
+        L.mu[l][0] = a0 * ia; L.mu[l][1] = a1 * ia; L.mu[l][2] = a2 * ia;
         ok = ok && (al2 > 0.0f) && isfinite(al2);
         L.lam[l] = load_elem(sc.sharp, sc.dt_color, r.at1(l));
 #pragma unroll
@@ -183,11 +187,10 @@ __device__ __forceinline__ bool sg_colour(const float base[3], const float pos[3
     for (int c = 0; c < 3; ++c) rgb[c] = base[c];
 #pragma unroll
     for (int l = 0; l < K; ++l) {
-        const float ia = rsqrtf(L.ax[l][0] * L.ax[l][0] + L.ax[l][1] * L.ax[l][1] + L.ax[l][2] * L.ax[l][2]);
         float df2 = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            muh[l][c] = L.ax[l][c] * ia;
+            muh[l][c] = L.mu[l][c];
             const float df = muh[l][c] - d[c];
             df2 += df * df;
         }
@@ -348,15 +351,16 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
         {
             // packed copy; the half-extents of the cutoff ellipse {q <= k} are sqrt(k S_xx) and
             // sqrt(k S_yy) with S_xx = c / (a c - b^2), S_yy = a / (a c - b^2), the FP32 conic's
-            // determinant taken in FP64 (products of FP32 values are exact there) so thin ellipses keep
-            // their extent, widened by 1e-3 relative and 1e-2 px: every pixel with alpha >= 1/255
-            // lies inside the box
+            // determinant taken in FP64 (products of FP32 values are exact there, so thin ellipses
+            // keep their extent) and rounded once to FP32; the rest in FP32 with the hardware
+            // reciprocal and square root (about 1 ulp each), far inside the widening by 1e-3
+            // relative and 1e-2 px: every pixel with alpha >= 1/255 lies inside the box
             float rx = 0.f, ry = 0.f;
             if (ok) {
-                const double det = (double)p.conic[0] * p.conic[2] - (double)p.conic[1] * p.conic[1];
-                const double k = cutoff_of(g.o_eff);
-                rx = det > 0.0 ? (float)sqrt(k * p.conic[2] / det) * 1.001f + 0.01f : 1e30f;
-                ry = det > 0.0 ? (float)sqrt(k * p.conic[0] / det) * 1.001f + 0.01f : 1e30f;
+                const double detd = (double)p.conic[0] * p.conic[2] - (double)p.conic[1] * p.conic[1];
+                const float kd = cutoff_of(g.o_eff) * __builtin_amdgcn_rcpf((float)detd);
+                rx = detd > 0.0 ? __builtin_amdgcn_sqrtf(kd * p.conic[2]) * 1.001f + 0.01f : 1e30f;
+                ry = detd > 0.0 ? __builtin_amdgcn_sqrtf(kd * p.conic[0]) * 1.001f + 0.01f : 1e30f;
             }
             PackedRec pr;
             pr.mean = ok ? make_double2(p.u, p.v) : make_double2(0.0, 0.0);
@@ -475,7 +479,7 @@ __device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewIn
             glam[l] += w * (-0.5f * dd2[l]) * ip;
             const float coef = w * L.lam[l] * ip;
             const float md = muh[l][0] * d[0] + muh[l][1] * d[1] + muh[l][2] * d[2];
-            const float ial = rsqrtf(L.ax[l][0] * L.ax[l][0] + L.ax[l][1] * L.ax[l][1] + L.ax[l][2] * L.ax[l][2]);
+            const float ial = L.ia[l];
             for (int c = 0; c < 3; ++c) {
                 gax[l][c] += coef * (d[c] - muh[l][c] * md) * ial;
                 gd[c] += coef * muh[l][c];
