@@ -3,9 +3,11 @@
 //
 // One thread per Gaussian loops over all views, so the parameter planes are streamed from HBM
 // once per launch (coalesced SoA loads, widened from FP16/BF16 in registers) and the records of
-// every view are written. The camera-space position and pixel mean are computed in FP64 (a few
-// DFMAs), everything else in FP32. The kernels are bound by the latency of their dependent
-// arithmetic at the occupancy their registers allow (four and three waves per SIMD).
+// every view are written. View-independent values (activations, 3D covariance, unit lobe axes,
+// base colour) are formed once per Gaussian. The camera-space position, the pixel mean and the
+// tile count (the row-interval test of the key emission) are computed in FP64, everything else in
+// FP32. The kernels are bound by the latency of their dependent arithmetic at the occupancy their
+// registers allow (four and three waves per SIMD).
 //
 // Colour: c(d) = c0 + sum_k m_k a_k exp(lambda_k (mu_k . d - 1)) (SG lobe and colour equations,
 // Sec. 3.2), with lambda (mu . d - 1) evaluated as -lambda |mu - d|^2 / 2 for unit mu and d, which
