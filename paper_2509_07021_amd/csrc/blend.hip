@@ -49,6 +49,7 @@ struct Kept {
     uint64_t slot;   // forward: the record id (importance output); backward: 9 x record id, the
                      // record's first gradient element
 };
+static_assert(sizeof(Kept) == 48 && offsetof(Kept, slot) % 8 == 0, "kept entries are 48 bytes, slot 8-aligned");
 
 // &lds[k] through a VGPR copy of its byte offset. The compiler cannot rebuild the result of an asm
 // statement, so every read of the entry (and, with immediate offsets, of the entries after it)
