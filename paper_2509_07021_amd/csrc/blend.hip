@@ -97,8 +97,12 @@ __device__ __forceinline__ bool box_meets(const float4& b, int x0, int x1, int y
     return (x0 + 0.5f <= b.y) && (x1 + 0.5f >= b.x) && (y0 + 0.5f <= b.w) && (y1 + 0.5f >= b.z);
 }
 
-// Alpha test of one fragment (no branches): pass = (q <= 0 and alpha >= 1/255). The forward and
-// the backward call this same function, so both take identical decisions.
+// Alpha test of one fragment (no branches): pass = alpha >= 1/255 with alpha = min(o G, 0.99).
+// The compositing rule also skips fragments with q > 0, which no listed record has: its conic is
+// positive definite, so q <= 0 exactly, and in FP32 q can round above 0 only where its exact value
+// is about 0, a fragment the exact rule passes; so q is not tested. The threshold is tested on the
+// unclamped value (the same decision for any number, and a NaN fails it). The forward and the
+// backward call this same function, so both take identical decisions.
 template <class E>  // Staged or Kept
 __device__ __forceinline__ bool frag(const E& s, float px, float py, float& dx, float& dy, float& G,
                                      float& alpha, bool& clamped) {
@@ -109,8 +113,11 @@ __device__ __forceinline__ bool frag(const E& s, float px, float py, float& dx, 
     G = __builtin_amdgcn_exp2f(q2);
     const float raw = s.p0.z * G;
     clamped = raw > kAlphaMax;
-    alpha = fminf(raw, kAlphaMax);  // the same value (a NaN raw fails the q2 test below anyway)
-    return (q2 <= 0.0f) & (alpha >= kAlphaMin);
+    alpha = fminf(raw, kAlphaMax);
+    // keeps the clamp next to the product: moved into the callers' blend branches, it would need a
+    // separate NaN-quieting step there
+    asm volatile("" : "+v"(alpha));
+    return raw >= kAlphaMin;
 }
 
 struct TileCtx {
