@@ -219,11 +219,16 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_upsweep(const K* __restric
                                                               int64_t max_count, int shift, uint32_t mask,
                                                               uint32_t* __restrict__ counts) {
     // Digit counts of the workgroup's chunk (order does not matter here): per-wave LDS histograms
-    // updated with LDS atomics, or with one add when the whole 64-key step shares its digit.
+    // updated with LDS atomics, or with one add when the whole 64-key step shares its digit. Each
+    // wave keeps kCopies histograms, lane l adding to copy l % kCopies: lanes with equal digits
+    // then collide on one address a quarter as often (the atomics on one address serialise), and
+    // the odd stride puts the copies of a digit in different LDS banks.
     constexpr int U = 8;
-    __shared__ uint32_t hist[kRsWaves][kRsDigits];
+    constexpr int kCopies = 4, kStride = kRsDigits + 1;
+    __shared__ uint32_t hist[kRsWaves][kCopies * kStride];
     const int w = threadIdx.x / kWave, lane = __lane_id();
-    for (int i = threadIdx.x; i < kRsWaves * kRsDigits; i += kRsThreads) (&hist[0][0])[i] = 0u;
+    const int cp = (lane & (kCopies - 1)) * kStride;
+    for (int i = threadIdx.x; i < kRsWaves * kCopies * kStride; i += kRsThreads) (&hist[0][0])[i] = 0u;
     __syncthreads();
     const Chunk c = chunk_of(d_count, max_count);
     const int64_t i1 = c.t1 * kRsTile < c.n ? c.t1 * kRsTile : c.n;
@@ -242,14 +247,15 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_upsweep(const K* __restric
             if (__ballot(d[u] == d0) == valid) {
                 if (lane == 0) atomicAdd(&hist[w][d0], (uint32_t)__popcll(valid));
             } else if (d[u] != 0xffffffffu) {
-                atomicAdd(&hist[w][d[u]], 1u);
+                atomicAdd(&hist[w][cp + d[u]], 1u);
             }
         }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) {
         uint32_t s = 0;
-        for (int ww = 0; ww < kRsWaves; ++ww) s += hist[ww][d];
+        for (int ww = 0; ww < kRsWaves; ++ww)
+            for (int cc = 0; cc < kCopies; ++cc) s += hist[ww][cc * kStride + d];
         counts[(int64_t)d * gridDim.x + blockIdx.x] = s;
     }
 }
