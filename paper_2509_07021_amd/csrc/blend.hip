@@ -495,6 +495,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
 // wave's own LDS (ballot prefix) and blended. Sub-tiles of a tile never wait for each other: there
 // is no workgroup barrier anywhere.
 
+// LDS written by some lanes of a wave and read by others: order the wave's accesses.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Without the work queue, the forward's workgroup b runs item xcd_item(b): each XCD takes one
 // contiguous eighth of the sub-tiles (with 8 views, one view each), so the records an XCD gathers
 // stay in its own L2. The backward keeps identity order, which measured faster for it.

@@ -25,13 +25,6 @@ constexpr int kWave = 64;
 // contiguous range of the n items: XCD x owns [x per + min(x, rem), ...) of length
 // per + (x < rem), and receives exactly that many workgroups. Items processed close together in
 // index order then share an L2.
-// LDS written by some lanes of a wave and read by others: order the wave's accesses.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 constexpr int kXcds = 8;
 __device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n_items) {
     const int64_t per = n_items / kXcds, rem = n_items % kXcds;
