@@ -28,7 +28,17 @@ def _oracle_masked_weights(scene, cams, tile, seed):
     return fwd, wm
 
 
-def _check_records(g, fwd, n_views):
+def conic_condition(conic):
+    """Condition number lambda_max / lambda_min of each 2x2 conic (a, b, c)."""
+    tr, det = conic[:, 0] + conic[:, 2], conic[:, 0] * conic[:, 2] - conic[:, 1] ** 2
+    lam = tr / 2 + np.sqrt(np.maximum(tr * tr / 4 - det, 0))
+    return lam * lam / det
+
+
+def _check_records(g, fwd, n_views, conic_cond_tol=False):
+    """Records against the oracle's. The FP32 conic is the inverse of the dilated 2D covariance;
+    with conic_cond_tol its relative tolerance grows with the conic's condition number (FP32 loses
+    about cond x 2^-24 inverting it), for scenes built to reach near-degenerate footprints."""
     rec = fwd["records"]
     valid_o = rec["valid"].astype(bool)
     valid_g = g["radius"] >= 0
@@ -37,8 +47,15 @@ def _check_records(g, fwd, n_views):
     np.testing.assert_allclose(g["mean"][v, 0], rec["u"][v], rtol=0, atol=1e-9)
     np.testing.assert_allclose(g["mean"][v, 1], rec["v"][v], rtol=0, atol=1e-9)
     np.testing.assert_allclose(g["rgbd"][v, 3], rec["depth"][v], rtol=1e-6)
-    np.testing.assert_allclose(g["conic_o"][v, :3], rec["conic"][v], rtol=2e-5,
-                               atol=2e-5 * np.abs(rec["conic"][v]).max())
+    if conic_cond_tol:
+        oc = rec["conic"][v]
+        rtol = 2e-5 + 2 * conic_condition(oc) * 2.0 ** -23
+        err = np.abs(g["conic_o"][v, :3] - oc)
+        tol = rtol[:, None] * np.abs(oc).max(axis=1, keepdims=True) + 2e-5 * np.abs(oc).max()
+        assert (err <= tol).all(), f"conic error {float((err / tol).max()):.2f} x tolerance"
+    else:
+        np.testing.assert_allclose(g["conic_o"][v, :3], rec["conic"][v], rtol=2e-5,
+                                   atol=2e-5 * np.abs(rec["conic"][v]).max())
     np.testing.assert_allclose(g["conic_o"][v, 3], rec["o"][v], rtol=2e-6)
     np.testing.assert_allclose(g["rgbd"][v, :3], rec["rgb"][v], rtol=0, atol=2e-6)
     dr = np.abs(g["radius"][v] - rec["radius"][v])
@@ -70,8 +87,10 @@ def _check_key_stage(g, cams, tile, n, sub=0):
     return rec, off
 
 
-def _check_blend_stage(g, rec, cams, tile, off):
-    """The blend over the GPU's own records and lists against the oracle's compositor."""
+def _check_blend_stage(g, rec, cams, tile, off, img_tol=IMG_TOL, t_rtol=1e-5):
+    """The blend over the GPU's own records and lists against the oracle's compositor: last
+    indices (every alpha and termination decision) exactly, colour and transmittance within the
+    given tolerances."""
     worst = 0.0
     for vi, cam in enumerate(cams):
         ob = O.blend(cam, tile, rec, g["vals"], g["ranges"][off[vi]:off[vi + 1]])
@@ -82,23 +101,35 @@ def _check_blend_stage(g, rec, cams, tile, off):
         last = g["last"][p0:p0 + npx].reshape(cam.height, cam.width)
         assert np.array_equal(last[ok], ob["last"][ok])
         T = g["T_final"][p0:p0 + npx].reshape(cam.height, cam.width)
-        np.testing.assert_allclose(T[ok], ob["T"][ok], rtol=1e-5, atol=1e-7)
-    assert worst <= IMG_TOL, worst
+        np.testing.assert_allclose(T[ok], ob["T"][ok], rtol=t_rtol, atol=1e-7)
+    assert worst <= img_tol, worst
     return worst
 
 
-def _run_all_stages(scene, cams, cfg, seed=7):
+def _run_all_stages(scene, cams, cfg, seed=7, near_degenerate=False):
+    """Every stage against the oracle: stage-wise on the GPU's own records (keys, order, ranges and
+    last indices bit-exact, blend and blend backward within the FP32 tolerances), then end to end
+    against the FP64 pipeline. With near_degenerate (conics with condition numbers in the
+    thousands), the FP32 conic and the FP32 quadratic form of the blend lose about cond x 2^-24
+    relative: the conics take a condition-aware tolerance, the stage-wise blend 1e-3, and the
+    stage-wise and end-to-end gradient errors are returned for the caller to bound."""
     log(f"case n={scene.n} k={scene.k} views={len(cams)} tile={cfg.tile} batch={cfg.batch} flags={cfg.flags}")
     fwd, w = _oracle_masked_weights(scene, cams, cfg.tile, seed)
     g = gpu_run(scene, cams, cfg, weights=w)
-    _check_records(g, fwd, len(cams))
+    _check_records(g, fwd, len(cams), conic_cond_tol=near_degenerate)
     rec, off = _check_key_stage(g, cams, cfg.tile, scene.n, sub=cfg.subtile)
-    _check_blend_stage(g, rec, cams, cfg.tile, off)
+    if near_degenerate:
+        _check_blend_stage(g, rec, cams, cfg.tile, off, img_tol=1e-3, t_rtol=1e-3)
+    else:
+        _check_blend_stage(g, rec, cams, cfg.tile, off)
     # end-to-end images against the FP64 pipeline
+    e2e = {"image": 0.0}
     for vi in range(len(cams)):
         ok = fwd["views"][vi]["flag"] == 0
         d = np.abs(g["images"][vi] - fwd["images"][vi])[:, ok]
-        assert d.max() <= IMG_TOL, (vi, d.max())
+        e2e["image"] = max(e2e["image"], float(d.max()))
+        if not near_degenerate:
+            assert d.max() <= IMG_TOL, (vi, d.max())
     # backward, stage-wise: blend backward over the GPU's records and lists
     g2_ref = np.zeros_like(g["grad2d"])
     g2_abs = np.zeros_like(g["grad2d"])
@@ -106,7 +137,11 @@ def _run_all_stages(scene, cams, cfg, seed=7):
         O.blend_backward(cam, cfg.tile, rec, g["vals"], g["ranges"][off[vi]:off[vi + 1]], w[vi], grad2d=g2_ref,
                          grad2d_abs=g2_abs)
     for c, name in enumerate(("u", "v", "a", "b", "c", "o", "r", "g", "b_col")):
-        grad_close(f"grad2d[{name}]", g["grad2d"][:, c], g2_ref[:, c], abs_sum=g2_abs[:, c])
+        if near_degenerate:
+            e2e[f"grad2d[{name}]"] = float(np.linalg.norm(g["grad2d"][:, c] - g2_ref[:, c]) /
+                                           max(np.linalg.norm(g2_ref[:, c]), 1e-30))
+        else:
+            grad_close(f"grad2d[{name}]", g["grad2d"][:, c], g2_ref[:, c], abs_sum=g2_abs[:, c])
     # projection backward, stage-wise: fed with the GPU's 2D gradients
     pl = scene.widened()
     gr_stage = O.zero_grads(pl)
@@ -115,12 +150,22 @@ def _run_all_stages(scene, cams, cfg, seed=7):
         O.project_backward(pl, scene.k, cam, cfg.tile, g["grad2d"][vi * n:(vi + 1) * n], gr_stage)
     for p in O.PLANES:
         if gr_stage[p] is not None:
-            grad_close(f"stage {p}", g["grads"][p], gr_stage[p])
+            if near_degenerate:
+                e2e[f"stage {p}"] = float(np.linalg.norm(g["grads"][p] - gr_stage[p]) /
+                                          max(np.linalg.norm(gr_stage[p]), 1e-30))
+            else:
+                grad_close(f"stage {p}", g["grads"][p], gr_stage[p])
     # end to end against the FP64 gradient
     gr, _ = O.render_backward(pl, scene.k, cams, cfg.tile, w, fwd=fwd)
     for p in O.PLANES:
         if gr[p] is not None:
-            grad_close(p, g["grads"][p], gr[p])
+            if near_degenerate:
+                e2e[p] = float(np.linalg.norm(g["grads"][p] - gr[p]) / max(np.linalg.norm(gr[p]), 1e-30))
+            else:
+                grad_close(p, g["grads"][p], gr[p])
+    if near_degenerate:
+        log("end-to-end errors: " + ", ".join(f"{k} {v:.2e}" for k, v in e2e.items()))
+        return g, fwd, e2e
     return g, fwd
 
 
@@ -204,6 +249,32 @@ def test_empty_and_culled_scenes():
     assert g["n_pairs"] == 0 and (g["radius"] < 0).all()
     np.testing.assert_array_equal(g["images"][0].astype(np.float32), np.broadcast_to(
         np.array([0.25, 0.5, 0.75], np.float32)[:, None, None], (3, 24, 40)))
+
+
+@pytest.mark.parametrize("tile,sub", [(32, 8), (16, 0)])
+def test_needle_footprints(tile, sub):
+    """Needle-shaped Gaussians (one long axis, two very thin ones): 2D conics with condition numbers
+    in the thousands, where the FP32 exponent cancels most and the culling box and sub-tile flags
+    of a thin ellipse are tightest; every stage against the oracle, in the benchmark's launch
+    configuration (32x32 tiles, 8x8 sub-tiles) and a per-tile one."""
+    rng = np.random.default_rng(11)
+    scene = S.random_scene(rng, 600, 3, masks=True, spread=0.8, logscale_mu=-4.0)
+    scene.logscale[0] = rng.uniform(-0.3, 0.7, scene.n).astype(np.float32)
+    scene.logscale[1:] = rng.uniform(-7.0, -5.5, (2, scene.n)).astype(np.float32)
+    cams = [S.look_at((0, -4, 0.5), 120, 96), S.look_at((3, -2, 1), 72, 72, bg=(0.1, 0.2, 0.3))]
+    g, fwd, e2e = _run_all_stages(scene, cams, R.Config(tile, 64, subtile=sub), seed=5, near_degenerate=True)
+    rec = fwd["records"]
+    assert conic_condition(rec["conic"][rec["valid"].astype(bool)]).max() > 1e3  # thin ellipses reached
+    # the FP32 conic's and quadratic form's error (about cond x 2^-24 relative) carries into the
+    # images and gradients of the thinnest footprints. Measured on this scene: images 3.2e-3 max
+    # abs end to end; per-tensor gradient errors 1.1e-4 stage-wise (on the GPU's own records) and
+    # 1.4e-3 end to end. Bounds with margin:
+    assert e2e["image"] <= 1e-2, e2e
+    for p, err in e2e.items():
+        if p.startswith("grad2d[") or p.startswith("stage "):
+            assert err <= 1e-3, (p, err)
+        elif p != "image":
+            assert err <= 1e-2, (p, err)
 
 
 def test_zero_lobes_and_single_gaussian():
