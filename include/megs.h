@@ -49,7 +49,7 @@ typedef enum {
     MEGS_ERR_HIP = -2,         /* a HIP runtime call failed */
     MEGS_ERR_CAPACITY = -3,    /* the pair table overflowed its fixed capacity (graph mode) */
     MEGS_ERR_UNSUPPORTED = -4, /* a configuration the library does not implement */
-    MEGS_ERR_ALLOC = -5        /* the allocation callback returned NULL */
+    MEGS_ERR_ALLOC = -5        /* the allocation callback returned NULL or memory not 256-byte aligned */
 } megs_status;
 
 typedef enum { MEGS_F32 = 0, MEGS_F16 = 1, MEGS_BF16 = 2 } megs_dtype;

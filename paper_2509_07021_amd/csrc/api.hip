@@ -76,6 +76,11 @@ __global__ void k_set_views(ViewInfo* dst, ViewChunk c) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The allocation callback's memory must be 256-byte aligned (the carved buffers inherit the
+// alignment, and the kernels read records and index arrays with 16-byte vector accesses): NULL or
+// a misaligned pointer is an allocation error, reported before anything is launched.
+bool bad_alloc(const void* p) { return !p || (reinterpret_cast<uintptr_t>(p) & 255u) != 0; }
+
 int waves_of(const megs_config* cfg) { return cfg->waves ? cfg->waves : (cfg->tile == 8 ? 1 : 4); }
 
 // Bump allocator over one caller-provided block.
@@ -562,7 +567,7 @@ megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t 
     const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
     memset(state, 0, sizeof(*state));
     void* fm = alloc(ctx, frame_bytes(L));
-    if (!fm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", frame_bytes(L));
+    if (bad_alloc(fm)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", frame_bytes(L));
     Frame f = carve_frame(fm, L);
     st = enqueue_front(sc, L, cfg, f, s);
     if (st != MEGS_OK) return st;
@@ -580,7 +585,7 @@ megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t 
     }
     const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
     void* pm = alloc(ctx, pairs_bytes(cap, one_stage, det));
-    if (!pm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", pairs_bytes(cap, one_stage, det));
+    if (bad_alloc(pm)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", pairs_bytes(cap, one_stage, det));
     Pairs p = carve_pairs(pm, cap, one_stage, det);
     st = enqueue_back(sc, L, cfg, f, p, images, state, s, importance);
     state->n_pairs = counted >= 0 ? counted : cap;
@@ -654,7 +659,7 @@ megs_status megs_render_backward(const megs_scene* scene, const megs_camera* cam
         return fail(MEGS_ERR_ARG, "state does not belong to this scene, view set and tile size");
     const size_t gbytes = backward_bytes(L, cfg, state->pair_capacity);
     void* gm = alloc(alloc_ctx, gbytes);
-    if (!gm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", gbytes);
+    if (bad_alloc(gm)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", gbytes);
     return enqueue_backward(scene, L, cfg, state, dl_dimages, gm, grads, static_cast<hipStream_t>(stream));
 }
 
@@ -686,7 +691,7 @@ megs_status megs_select_topk(const float* score, int64_t n, int64_t kappa, megs_
     void* scratch = nullptr;
     if (kappa > 0 && kappa < n) {
         scratch = alloc(alloc_ctx, select_scratch_bytes(n));
-        if (!scratch) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", select_scratch_bytes(n));
+        if (bad_alloc(scratch)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", select_scratch_bytes(n));
     }
     HIP_TRY(launch_select_topk(score, n, kappa, scratch, keep, static_cast<hipStream_t>(stream)));
     return MEGS_OK;
@@ -739,7 +744,7 @@ megs_status megs_compact(const megs_scene* scene, double opacity_min, double sha
     const size_t wbytes = 4 * align256(sizeof(uint32_t) * (n ? n : 1)) + 2 * align256(32) +
                           align256(scan_scratch_bytes(n)) + 256;
     void* wm = alloc(alloc_ctx, wbytes);
-    if (!wm) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", wbytes);
+    if (bad_alloc(wm)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", wbytes);
     Carver w{static_cast<char*>(wm), 0};
     a.keep = w.take<uint32_t>(n);
     a.count = w.take<uint32_t>(n);
@@ -772,7 +777,7 @@ megs_status megs_compact(const megs_scene* scene, double opacity_min, double sha
                           align256(sizeof(int32_t) * (no + 1)) + align256(sizeof(int32_t) * no) +
                           align256(sizeof(int32_t) * lo) + 256 * 12;
     void* om = alloc(alloc_ctx, obytes);
-    if (!om) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", obytes);
+    if (bad_alloc(om)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", obytes);
     Carver o{static_cast<char*>(om), 0};
     a.pos = o.take<char>((int64_t)(eg * 3 * no));
     a.logscale = o.take<char>((int64_t)(eg * 3 * no));
@@ -825,7 +830,7 @@ megs_status megs_photometric_loss(const float* images, const float* targets, int
     const size_t bytes = align256(sizeof(double) * 9 * pix) + align256(sizeof(double) * 2 * parts) +
                          align256(sizeof(double) * n_views) + 256;
     void* mem = alloc(alloc_ctx, bytes);
-    if (!mem) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed", bytes);
+    if (bad_alloc(mem)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", bytes);
     Carver c{static_cast<char*>(mem), 0};
     double* maps = c.take<double>(9 * pix);
     double* partial = c.take<double>(2 * parts);
@@ -892,7 +897,8 @@ megs_status megs_graph_create(const megs_scene* scene, const megs_camera* cams, 
     void* pm = alloc(alloc_ctx, pairs_bytes(cfg->pair_capacity, one_stage, det));
     const size_t gbytes = backward_bytes(L, cfg, cfg->pair_capacity);
     void* gm = with_backward ? alloc(alloc_ctx, gbytes) : nullptr;
-    if (!fm || !pm || (with_backward && !gm)) return fail(MEGS_ERR_ALLOC, "allocation failed");
+    if (bad_alloc(fm) || bad_alloc(pm) || (with_backward && bad_alloc(gm)))
+        return fail(MEGS_ERR_ALLOC, "allocation failed or not 256-byte aligned");
     megs_graph* G = new (std::nothrow) megs_graph();
     if (!G) return fail(MEGS_ERR_ALLOC, "host allocation failed");
     Frame f = carve_frame(fm, L);

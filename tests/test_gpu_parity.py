@@ -277,6 +277,42 @@ def test_needle_footprints(tile, sub):
             assert err <= 1e-2, (p, err)
 
 
+def test_misaligned_allocation_is_rejected():
+    """The allocation callback must return 256-byte aligned memory: a pointer that is not (here 16
+    bytes past an aligned block) fails with MEGS_ERR_ALLOC before anything is launched, and the
+    same call with aligned memory still renders."""
+    import ctypes
+    from paper_2509_07021_amd import _lib as L
+    scene, cams = S.make_workload("small_2k_128px")
+    ds = R.DeviceScene.from_scene(scene)
+    lib = L.load()
+    blocks = []
+
+    def make(shift):
+        def _alloc(ctx, nbytes):
+            t = torch.empty(int(nbytes) + 512, dtype=torch.uint8, device="cuda")
+            blocks.append(t)
+            base = (t.data_ptr() + 255) // 256 * 256
+            return base + shift
+        return L.ALLOC_FN(_alloc)
+
+    sc = ds.struct(None)
+    cam_arr = R.cameras_struct(cams)
+    cfg = R.Config(32, 64, subtile=8).struct()
+    images = torch.zeros(3 * 128 * 128, device="cuda")
+    for shift, expect in ((16, L.MEGS_ERR_ALLOC), (0, L.MEGS_OK)):
+        fn = make(shift)
+        state = L.MegsState()
+        rc = lib.megs_render_forward(ctypes.byref(sc), cam_arr, len(cams), ctypes.byref(cfg), fn, None,
+                                     images.data_ptr(), ctypes.byref(state), R._stream(None))
+        torch.cuda.synchronize()
+        assert rc == expect, (shift, rc, lib.megs_last_error().decode())
+        if shift:
+            assert "256-byte aligned" in lib.megs_last_error().decode()
+            assert float(images.abs().max()) == 0.0  # nothing was rendered
+    assert float(images.abs().max()) > 0.0
+
+
 def test_zero_lobes_and_single_gaussian():
     rng = np.random.default_rng(9)
     scene = S.random_scene(rng, 1, 0, masks=False, spread=0.1, logscale_mu=-1.5)
