@@ -157,24 +157,50 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce_packed(const uint3
 __global__ __launch_bounds__(kScanThreads) void k_scan_down_packed(uint32_t* order, const uint32_t* ntiles, int64_t n,
                                                                    int idb, const uint32_t* partial, uint32_t* out) {
     __shared__ uint32_t lds[4];
+    static_assert(kScanIpt == 8, "a thread's items are two 16-byte vectors");
+    // a thread's 8 consecutive items move as two 16-byte vectors (order and out are 256-byte
+    // aligned and base is a multiple of 8), so every access of the wave is contiguous
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
-    uint32_t v[kScanIpt];
+    const bool whole = base + kScanIpt <= n;
+    const uint32_t idmask = (1u << idb) - 1u;
+    uint32_t w[kScanIpt], v[kScanIpt];
+    if (whole) {
+        const uint4* q = reinterpret_cast<const uint4*>(order + base);
+        const uint4 a = q[0], b = q[1];
+        w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w; w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanIpt; ++j) w[j] = base + j < n ? order[base + j] : 0u;
+    }
     uint32_t s = 0;
+#pragma unroll
     for (int j = 0; j < kScanIpt; ++j) {
-        uint32_t c = 0;
-        if (base + j < n) {
-            const uint32_t w = order[base + j];
-            c = packed_count(w, ntiles, idb);
-            order[base + j] = w & ((1u << idb) - 1u);
-        }
-        v[j] = c;
-        s += c;
+        v[j] = base + j < n ? packed_count(w[j], ntiles, idb) : 0u;
+        s += v[j];
+        w[j] &= idmask;
     }
     uint32_t total;
     uint32_t ex = block_excl_scan256(s, lds, total) + partial[blockIdx.x];
+    uint32_t o[kScanIpt];
+#pragma unroll
     for (int j = 0; j < kScanIpt; ++j) {
-        if (base + j < n) out[base + j] = ex;
+        o[j] = ex;
         ex += v[j];
+    }
+    if (whole) {
+        uint4* q = reinterpret_cast<uint4*>(order + base);
+        q[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        q[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        uint4* r = reinterpret_cast<uint4*>(out + base);
+        r[0] = make_uint4(o[0], o[1], o[2], o[3]);
+        r[1] = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanIpt; ++j)
+            if (base + j < n) {
+                order[base + j] = w[j];
+                out[base + j] = o[j];
+            }
     }
 }
 
