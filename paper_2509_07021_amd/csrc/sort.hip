@@ -682,15 +682,20 @@ __global__ void k_ranges(const K* __restrict__ keys, int shift, uint32_t tmask, 
 }
 
 // The same for 32-bit keys, four consecutive keys per thread through one 16-byte load (the key
-// arrays are 256-byte aligned), plus the keys just before and after them.
+// arrays are 256-byte aligned), plus the keys just before and after them: those are the
+// neighbouring lanes' last and first keys, taken by shuffles, and loaded only at the wave's ends.
 __global__ void k_ranges_u32x4(const uint32_t* __restrict__ keys, uint32_t tmask, const uint32_t* d_count,
                                int64_t max_count, uint2* __restrict__ ranges) {
     int64_t n = (int64_t)*d_count;
     if (n > max_count) n = max_count;
     const int64_t nq = (n + 3) / 4;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = __lane_id();
+    // whole waves take part in every iteration (the shuffles read the neighbouring lanes), lanes
+    // past the end with no keys
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q - lane < nq; q += stride) {
         const int64_t i0 = 4 * q;
-        uint32_t t[4];
+        uint32_t t[4] = {0u, 0u, 0u, 0u};
         if (i0 + 4 <= n) {
             const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
             t[0] = v.x & tmask; t[1] = v.y & tmask; t[2] = v.z & tmask; t[3] = v.w & tmask;
@@ -698,8 +703,11 @@ __global__ void k_ranges_u32x4(const uint32_t* __restrict__ keys, uint32_t tmask
 #pragma unroll
             for (int j = 0; j < 4; ++j) t[j] = i0 + j < n ? keys[i0 + j] & tmask : 0u;
         }
-        const uint32_t before = i0 > 0 ? keys[i0 - 1] & tmask : 0u;
-        const uint32_t after = i0 + 4 < n ? keys[i0 + 4] & tmask : 0u;
+        uint32_t before = (uint32_t)__shfl_up((int)t[3], 1);
+        uint32_t after = (uint32_t)__shfl_down((int)t[0], 1);
+        if (lane == 0) before = i0 > 0 && i0 - 1 < n ? keys[i0 - 1] & tmask : 0u;
+        if (lane == kWave - 1) after = i0 + 4 < n ? keys[i0 + 4] & tmask : 0u;
+        if (q >= nq) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t i = i0 + j;
