@@ -54,21 +54,47 @@ TRAFFIC = {
     "blend_bwd": {"bytes": 5189769603,
                   "source_sha256": "157d9c7272df76ed22e5f3f2cb7f9f356a0020a3029beea4c847cc659b5ef7c1"},
 }
+# VALU instructions per launch of the blend kernels on the same workload, from a rocprofv3 --pmc
+# SQ_INSTS_VALU run (per dispatch, averaged), with the SHA-256 of the source they were taken on (a
+# changed source reports them as null). At one wave64 VALU instruction per 4 cycles on each of the
+# 1024 SIMDs at 2.4 GHz they give the issue time; set against the measured time it is the kernel's
+# VALU utilisation.
+VALU = {
+    "blend_fwd": {"instructions": 561979079,
+                  "source_sha256": "157d9c7272df76ed22e5f3f2cb7f9f356a0020a3029beea4c847cc659b5ef7c1"},
+    "blend_bwd": {"instructions": 1305345581,
+                  "source_sha256": "157d9c7272df76ed22e5f3f2cb7f9f356a0020a3029beea4c847cc659b5ef7c1"},
+}
+SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4
 STAGE_SOURCE = {"project": "project.hip", "project_bwd": "project.hip", "blend_fwd": "blend.hip",
                 "blend_bwd": "blend.hip", "depth_sort": "sort.hip", "pair_sort": "sort.hip", "scan": "sort.hip",
                 "emit": "sort.hip", "ranges": "sort.hip"}
 
 
-def traffic_of(stage):
+def _measured(table, stage, key):
+    """table[stage][key] if it was measured on the stage's current source, else None."""
     import hashlib
-    t = TRAFFIC.get(stage)
+    t = table.get(stage)
     if not t:
         return None
     src = os.path.join(ROOT, "paper_2509_07021_amd", "csrc", STAGE_SOURCE[stage])
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
             return None
-    return t["bytes"]
+    return t[key]
+
+
+def traffic_of(stage):
+    return _measured(TRAFFIC, stage, "bytes")
+
+
+def valu_of(stage, avg_ms):
+    """VALU instructions per launch, their issue time and its share of the measured time, or None."""
+    n = _measured(VALU, stage, "instructions")
+    if n is None:
+        return None
+    issue_ms = n * VALU_CYCLES / (SIMDS * CLOCK_HZ) * 1e3
+    return {"instructions": n, "issue_ms": round(issue_ms, 4), "issue_frac": round(issue_ms / avg_ms, 4)}
 
 
 def log(*a):
@@ -432,7 +458,7 @@ def main():
         roof = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_of(dominant),
                 "units_per_launch": {"blended": blended, "evaluated": evaluated, "replayed": replayed},
-                "avg_ms": round(stage_ms[dominant], 4)}
+                "avg_ms": round(stage_ms[dominant], 4), "valu": valu_of(dominant, stage_ms[dominant])}
     else:
         by = stage_bytes(dominant, scene.n, len(cams8), pairs8, npix8, nt8, geom_bytes, scene.k)
         achieved = by / (stage_ms[dominant] * 1e-3) / 1e9
@@ -448,8 +474,10 @@ def main():
         if st in ("blend_fwd", "blend_bwd"):
             fl = FLOP_TEST * evaluated + (FLOP_FWD_BLEND if st == "blend_fwd" else FLOP_BWD_BLEND) * blended
             ach = fl / (ms * 1e-3) / 1e12
+            v = valu_of(st, ms)
             stage_roof[st] = {"bound": "alu", "achieved": round(ach, 2), "unit": "TFLOP/s",
-                              "frac": round(ach / PEAK_FP32_TFLOPS, 4)}
+                              "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                              "valu_issue_frac": v["issue_frac"] if v else None}
             bound_ms += fl / (PEAK_FP32_TFLOPS * 1e12) * 1e3
         else:
             by = stage_bytes(st, scene.n, len(cams8), pairs8, npix8, nt8, geom_bytes, scene.k, tile_bits)

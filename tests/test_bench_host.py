@@ -31,6 +31,18 @@ def test_traffic_is_reported_only_for_the_source_it_was_measured_on(monkeypatch)
     assert "emit" not in bench.TRAFFIC and bench.traffic_of("emit") is None
 
 
+def test_valu_issue_time_is_reported_only_for_the_measured_source(monkeypatch):
+    src = os.path.join(bench.ROOT, "paper_2509_07021_amd", "csrc", "blend.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    n = 1024 * 2_400_000 // 4  # one millisecond of issue: 1024 SIMDs x 2.4e9 cycles x 1e-3 / 4 cycles
+    monkeypatch.setitem(bench.VALU, "blend_bwd", {"instructions": n, "source_sha256": sha})
+    v = bench.valu_of("blend_bwd", 2.0)
+    assert v["instructions"] == n and v["issue_ms"] == 1.0 and v["issue_frac"] == 0.5
+    monkeypatch.setitem(bench.VALU, "blend_bwd", {"instructions": n, "source_sha256": "0" * 64})
+    assert bench.valu_of("blend_bwd", 2.0) is None
+
+
 def test_stage_bytes_follow_the_per_unit_counts():
     n, nv, pairs, npix, ntiles, gb, k = 1000, 8, 40_000, 8 * 1920 * 1080, 16_320, 94, 4
     nr = n * nv
