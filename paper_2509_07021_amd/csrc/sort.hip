@@ -505,6 +505,15 @@ __device__ __forceinline__ uint32_t band_bits(int c0, int c1, int tx, int S) {
     return lo <= hi ? bits : 0u;
 }
 
+// Sub-columns [c0, c1] as a bit mask relative to sub-column `first`, over `nbits` <= 64 bits
+// (bit p: sub-column first + p); c0 > c1 or no overlap gives 0 (branch-free, shifts kept in range).
+__device__ __forceinline__ uint64_t band_mask(int c0, int c1, int first, int nbits) {
+    const int lo = max(c0 - first, 0), hi = min(c1 - first, nbits - 1);
+    const uint64_t upto = (2ull << min(max(hi, 0), 63)) - 1ull;  // bits 0..hi (all 64 when hi = 63)
+    const uint64_t below = (1ull << min(lo, 63)) - 1ull;        // bits 0..lo-1
+    return lo <= hi ? upto & ~below : 0ull;
+}
+
 // S: sub-tiles per tile edge when the keys carry sub-tile flags (tile = 8 S), 0 without flags.
 template <int S>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t n,
@@ -596,13 +605,28 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
                     band_columns(xmin, xmax, SUB, bc0[r], bc1[r]);
                 }
                 const uint32_t row_key = (uint32_t)(tile_off + (int64_t)ty * tiles_x);
+                // a row of at most 64 / S tiles takes each sub-row's flags from one 64-bit mask of
+                // its sub-columns (a shift per tile); wider rows form them per tile
+                const bool narrow = (ch - cl + 1) * S <= 64;
+                uint64_t rmask[S > 0 ? S : 1];
+                if (S && narrow) {
+#pragma unroll
+                    for (int r = 0; r < S; ++r) rmask[r] = band_mask(bc0[r], bc1[r], cl * S, (ch - cl + 1) * S);
+                }
                 for (int tx = cl; tx <= ch && pos < w1; ++tx, ++pos) {
                     if (pos < w0) continue;
                     uint32_t key = row_key + (uint32_t)tx;
                     if (S) {
                         uint32_t m = 0;
+                        if (narrow) {
+                            const int sh = (tx - cl) * S;
 #pragma unroll
-                        for (int r = 0; r < S; ++r) m |= band_bits(bc0[r], bc1[r], tx, S) << (r * S);
+                            for (int r = 0; r < S; ++r)
+                                m |= ((uint32_t)(rmask[r] >> sh) & ((1u << S) - 1u)) << (r * S);
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < S; ++r) m |= band_bits(bc0[r], bc1[r], tx, S) << (r * S);
+                        }
                         key |= m << 16;
                     }
                     w_tile[pos - w0] = key;
