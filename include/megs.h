@@ -18,9 +18,10 @@
  *   would drop below 1e-4 (that fragment is not blended); near plane from the camera; the
  *   Jacobian is evaluated at the direction clamped to 1.3x the half field of view; the
  *   footprint radius is ceil(sqrt(2 ln(255 o) lambda_max)) so that every pixel with
- *   alpha >= 1/255 lies inside the tile rectangle, and of that rectangle only the tiles whose
- *   pixel-centre box the ellipse q <= k reaches are listed (k slightly above 2 ln(255 o), see
- *   megs_state.cutoff); depth ties are ordered by record index.
+ *   alpha >= 1/255 lies inside the tile rectangle, and of that rectangle exactly the tiles are
+ *   listed whose pixel-centre box (the centres of the tile's pixels inside the image) the ellipse
+ *   (p - m)' conic (p - m) <= k reaches, k = 2.004 ln(255 o) + 1e-4, slightly above the level
+ *   2 ln(255 o) of alpha = 1/255 (see megs_state.cutoff); depth ties are ordered by record index.
  *   Quaternions are (w, x, y, z) and normalised in the forward pass, lobe axes likewise;
  *   scales are exp(log-scale), opacity and masks are sigmoid(logit), sharpness is used as
  *   stored. Colours are not clamped.

@@ -167,61 +167,73 @@ static int64_t lobe3(const oscene *sc, int64_t i, int l, int c) {
 }
 
 /*
- * Tile selection inside the rectangle. E = {p : (p - m)' C (p - m) <= k}, C the conic, k the
- * cutoff level (2 ln(255 o) widened by 0.2% and 1e-4: the blend's alpha >= 1/255 test is
- * q <= 2 ln(255 o), so FP32 rounding in a renderer cannot reach past an unlisted tile).
- * For each tile row, with band = the row's pixel-centre rows [Y0, Y1], the listed columns are the
- * tiles whose pixel-centre column range meets the x-extent of E restricted to the band.
- * With S = C^-1 the leftmost/rightmost points of E sit at dy = -/+ S_xy sqrt(k / S_xx), and
- * x_max(dy) = mx + (sqrt(k a - det dy^2) - b dy) / a is concave (x_min convex), so the extent over
- * the band is attained at those dy clamped into the band. A tile column tx meets [x_min, x_max]
- * when tx T + 1/2 <= x_max and (tx + 1) T - 1/2 >= x_min.
- * Same FP64 operations, in the same order, as any implementation that must list the same tiles.
+ * Tile selection inside the rectangle, written as its plain definition. With the conic C = [[a, b], [b, c]]
+ * and Q(p) = (p - m)' C (p - m), a tile of the rectangle is listed exactly when the ellipse {Q <= k} meets
+ * the box spanned by the centres of the tile's pixels that lie inside the image, that is when the minimum of Q
+ * over that box is <= k. The level k = 2.004 ln(255 o) + 1e-4 sits slightly above 2 ln(255 o), the level of
+ * alpha = 1/255 (alpha = o exp(-Q / 2)), so that FP32 rounding in a renderer cannot reach a pixel of an
+ * unlisted tile. A conic that is not positive definite bounds nothing: every tile of the rectangle is listed.
  */
 static double cutoff_level(double o) { return 2.004 * log(255.0 * o) + 1e-4; }
 
-typedef struct {
-    double u, v, b, det, ia, ka, ry, dys;
-    int full; /* degenerate conic: the whole rectangle */
-} orows;
+static double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
-static void rows_setup(double u, double v, double a, double b, double c, double k, orows *e) {
-    e->u = u; e->v = v; e->b = b;
-    e->det = a * c - b * b;
-    e->full = !(e->det > 0.0) || !(a > 0.0) || !(k > 0.0);
-    double sxx = c / e->det, syy = a / e->det, sxy = -b / e->det;
-    e->ry = sqrt(k * syy);
-    e->dys = sxy * sqrt(k / sxx);
-    e->ia = 1.0 / a;
-    e->ka = k * a;
+static double quad_form(double a, double b, double c, double dx, double dy) {
+    return a * dx * dx + 2.0 * b * dx * dy + c * dy * dy;
 }
 
-/* columns [*lo, *hi] of tile row ty (inside rectangle columns [x0, x1]); 0 when none */
-static int rows_span(const orows *e, int h, int tile, int ty, int x0, int x1, int *lo, int *hi) {
-    if (e->full) { *lo = x0; *hi = x1; return 1; }
+/* positive definite conic (a > 0 and a c - b^2 > 0; the products of FP32 inputs are exact in FP64) */
+static int conic_pd(double a, double b, double c) { return a > 0.0 && a * c - b * b > 0.0; }
+
+/*
+ * min of Q over the box [x0, x1] x [y0, y1] for a positive definite conic. Q is strictly convex, so the
+ * minimum is 0 at the mean when the mean lies in the box; otherwise it lies on the box's boundary. On each
+ * edge Q restricted to the edge is a convex parabola in the free coordinate, minimal at its vertex (for
+ * x fixed: dy = -b dx / c; for y fixed: dx = -b dy / a) clamped to the edge.
+ */
+static double box_min_q(double u, double v, double a, double b, double c, double x0, double x1, double y0,
+                        double y1) {
+    if (u >= x0 && u <= x1 && v >= y0 && v <= y1) return 0.0;
+    const double xs[2] = {x0, x1}, ys[2] = {y0, y1};
+    double best = INFINITY;
+    for (int e = 0; e < 2; ++e) {
+        double dx = xs[e] - u;
+        double dy = clampd(-b * dx / c, y0 - v, y1 - v);
+        double q = quad_form(a, b, c, dx, dy);
+        if (q < best) best = q;
+        dy = ys[e] - v;
+        dx = clampd(-b * dy / a, x0 - u, x1 - u);
+        q = quad_form(a, b, c, dx, dy);
+        if (q < best) best = q;
+    }
+    return best;
+}
+
+/* box_min_q for m problems: mean (u, v), conic [m][3], box [m][4] = x0, x1, y0, y1 -> out [m] (for the pins) */
+void oracle_box_min(int64_t m, const double *u, const double *v, const double *conic, const double *box,
+                    double *out) {
+    for (int64_t i = 0; i < m; ++i) {
+        const double *cn = conic + 3 * i, *b = box + 4 * i;
+        out[i] = conic_pd(cn[0], cn[1], cn[2]) ? box_min_q(u[i], v[i], cn[0], cn[1], cn[2], b[0], b[1], b[2], b[3])
+                                               : -INFINITY;
+    }
+}
+
+/* pixel-centre box of tile (tx, ty) of edge `tile` in a w x h image: [x0, x1] x [y0, y1] */
+static void tile_box(int tx, int ty, int tile, int w, int h, double box[4]) {
+    int xe = (tx + 1) * tile < w ? (tx + 1) * tile : w;
     int ye = (ty + 1) * tile < h ? (ty + 1) * tile : h;
-    double dl = (ty * tile + 0.5) - e->v, dh = (ye - 0.5) - e->v;
-    if (dl < -e->ry) dl = -e->ry;
-    if (dh > e->ry) dh = e->ry;
-    if (dl > dh) return 0;
-    double d1 = e->dys, d2 = -e->dys;
-    if (d1 < dl) d1 = dl;
-    if (d1 > dh) d1 = dh;
-    if (d2 < dl) d2 = dl;
-    if (d2 > dh) d2 = dh;
-    double r1 = e->ka - (e->det * d1) * d1;
-    double r2 = e->ka - (e->det * d2) * d2;
-    double s1 = sqrt(r1 > 0.0 ? r1 : 0.0);
-    double s2 = sqrt(r2 > 0.0 ? r2 : 0.0);
-    double xmax = e->u + (s1 - e->b * d1) * e->ia;
-    double xmin = e->u - (s2 + e->b * d2) * e->ia;
-    double flo = ceil((xmin + 0.5) / tile - 1.0), fhi = floor((xmax - 0.5) / tile);
-    if (flo < x0) flo = x0;
-    if (fhi > x1) fhi = x1;
-    if (flo > fhi) return 0;
-    *lo = (int)flo;
-    *hi = (int)fhi;
-    return 1;
+    box[0] = tx * tile + 0.5; box[1] = xe - 0.5;
+    box[2] = ty * tile + 0.5; box[3] = ye - 0.5;
+}
+
+/* min of Q over tile (tx, ty)'s pixel-centre box; -INFINITY when the conic is not positive definite
+ * (every tile listed) */
+static double tile_q(double u, double v, const double cn[3], int tx, int ty, int tile, int w, int h) {
+    if (!conic_pd(cn[0], cn[1], cn[2])) return -INFINITY;
+    double box[4];
+    tile_box(tx, ty, tile, w, h, box);
+    return box_min_q(u, v, cn[0], cn[1], cn[2], box[0], box[1], box[2], box[3]);
 }
 
 /* Project Gaussian i into camera cam (tile edge tile). */
@@ -364,12 +376,9 @@ static void project_one(const oscene *sc, const ocam *cam, int tile, int64_t i, 
     p->rect[2] = (int)y_lo / tile; p->rect[3] = (int)y_hi / tile;
     (void)tiles_x; (void)tiles_y;
     p->ntiles = 0;
-    orows er;
-    rows_setup(p->u, p->v, p->conic[0], p->conic[1], p->conic[2], p->cutoff, &er);
-    for (int ty = p->rect[2]; ty <= p->rect[3]; ++ty) {
-        int lo, hi;
-        if (rows_span(&er, cam->height, tile, ty, p->rect[0], p->rect[1], &lo, &hi)) p->ntiles += hi - lo + 1;
-    }
+    for (int ty = p->rect[2]; ty <= p->rect[3]; ++ty)
+        for (int tx = p->rect[0]; tx <= p->rect[1]; ++tx)
+            if (tile_q(p->u, p->v, p->conic, tx, ty, tile, cam->width, cam->height) <= p->cutoff) ++p->ntiles;
 }
 
 /*
@@ -432,6 +441,66 @@ static int rect_of(double u, double v, int32_t r, int w, int h, int tile, int re
     return (rect[1] - rect[0] + 1) * (rect[3] - rect[2] + 1);
 }
 
+/*
+ * Candidate pairs of the key table over records of several views. Record g belongs to view rec_view[g];
+ * view v has image size (w[v], h[v]) and its tiles are numbered from tile_off[v]. For every valid record
+ * and every tile of its rectangle, q = the minimum of Q over the tile's pixel-centre box is compared with
+ * the record's level k (cutoff[g]):
+ *   state 1: listed, q <= k, and q is not within the band;
+ *   state 2: |q - k| <= band * k: the decision lies within a relative band of the level, where a
+ *            renderer evaluating the same definition in another rounding order may take either side.
+ * Tiles with q > k outside the band are not returned. With band = 0 no pair has state 2.
+ * When out_tile == NULL only the number of returned pairs is computed. out_tile: global tile id,
+ * out_rec: record index, out_state: 1 or 2, in record order and row-major tile order per record.
+ */
+static int64_t record_candidates(int64_t g, const double *u, const double *v, const int32_t *radius,
+                                 const double *conic, const double *cutoff, const int32_t *rec_view,
+                                 const int32_t *w, const int32_t *h, const int64_t *tile_off, int tile, double band,
+                                 int64_t *out_tile, uint32_t *out_rec, uint8_t *out_state) {
+    int vv = rec_view[g];
+    int rect[4];
+    if (!rect_of(u[g], v[g], radius[g], w[vv], h[vv], tile, rect)) return 0;
+    int tiles_x = (w[vv] + tile - 1) / tile;
+    double k = cutoff[g];
+    int64_t m = 0;
+    for (int ty = rect[2]; ty <= rect[3]; ++ty)
+        for (int tx = rect[0]; tx <= rect[1]; ++tx) {
+            double q = tile_q(u[g], v[g], conic + 3 * g, tx, ty, tile, w[vv], h[vv]);
+            int state = (band > 0.0 && fabs(q - k) <= band * k) ? 2 : (q <= k ? 1 : 0);
+            if (!state) continue;
+            if (out_tile) {
+                out_tile[m] = tile_off[vv] + (int64_t)ty * tiles_x + tx;
+                out_rec[m] = (uint32_t)g;
+                out_state[m] = (uint8_t)state;
+            }
+            ++m;
+        }
+    return m;
+}
+
+int64_t oracle_tile_candidates(int64_t nrec, const double *u, const double *v, const int32_t *radius,
+                               const double *conic, const double *cutoff, const int32_t *valid,
+                               const int32_t *rec_view, const int32_t *w, const int32_t *h, const int64_t *tile_off,
+                               int32_t tile, double band, int64_t *out_tile, uint32_t *out_rec, uint8_t *out_state) {
+    int64_t *cnt = (int64_t *)calloc((size_t)(nrec > 0 ? nrec : 1) + 1, sizeof(int64_t));
+    #pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t g = 0; g < nrec; ++g)
+        if (valid[g])
+            cnt[g + 1] = record_candidates(g, u, v, radius, conic, cutoff, rec_view, w, h, tile_off, tile, band,
+                                           NULL, NULL, NULL);
+    for (int64_t g = 0; g < nrec; ++g) cnt[g + 1] += cnt[g];
+    int64_t total = cnt[nrec];
+    if (out_tile) {
+        #pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t g = 0; g < nrec; ++g)
+            if (valid[g] && cnt[g + 1] > cnt[g])
+                record_candidates(g, u, v, radius, conic, cutoff, rec_view, w, h, tile_off, tile, band,
+                                  out_tile + cnt[g], out_rec + cnt[g], out_state + cnt[g]);
+    }
+    free(cnt);
+    return total;
+}
+
 typedef struct { uint64_t key; uint32_t val; } okv;
 
 static int cmp_kv(const void *a, const void *b) {
@@ -441,56 +510,13 @@ static int cmp_kv(const void *a, const void *b) {
     return 0;
 }
 
-static uint32_t f32_bits(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
-
 /*
- * Key table from records of several views (mean u, v; the depth as the float32
- * value whose bits form the low key half; integer radius; conic [n][3] and cutoff level
- * for the tile selection inside the rectangle). Record g belongs to view rec_view[g];
- * view v has image size (w[v], h[v]) and its tiles are numbered from tile_off[v].
- * When keys == NULL only the pair count is returned.
- * Otherwise keys/vals receive the pairs ordered by (key, value) and ranges[2*T]
- * the [start, end) of each global tile ((0, 0) when empty).
+ * Orders (key, value) pairs by key, then value, in place, and writes the [start, end) of every tile
+ * (key >> 32) into ranges[2 * total_tiles] ((0, 0) when the tile has no pair).
  */
-int64_t oracle_pairs(int64_t nrec, const double *u, const double *v, const float *depth, const int32_t *radius,
-                     const double *conic, const double *cutoff,
-                     const int32_t *valid, const int32_t *rec_view, const int32_t *w, const int32_t *h,
-                     const int64_t *tile_off, int32_t tile, int64_t total_tiles,
-                     uint64_t *keys, uint32_t *vals, uint32_t *ranges) {
-    int64_t count = 0;
-    int rect[4];
-    for (int64_t g = 0; g < nrec; ++g) {
-        if (!valid[g]) continue;
-        int vv = rec_view[g];
-        if (!rect_of(u[g], v[g], radius[g], w[vv], h[vv], tile, rect)) continue;
-        orows er;
-        rows_setup(u[g], v[g], conic[3 * g], conic[3 * g + 1], conic[3 * g + 2], cutoff[g], &er);
-        for (int ty = rect[2]; ty <= rect[3]; ++ty) {
-            int lo, hi;
-            if (rows_span(&er, h[vv], tile, ty, rect[0], rect[1], &lo, &hi)) count += hi - lo + 1;
-        }
-    }
-    if (!keys) return count;
+void oracle_sort_pairs(int64_t count, uint64_t *keys, uint32_t *vals, int64_t total_tiles, uint32_t *ranges) {
     okv *kv = (okv *)malloc(sizeof(okv) * (size_t)(count > 0 ? count : 1));
-    int64_t e = 0;
-    for (int64_t g = 0; g < nrec; ++g) {
-        if (!valid[g]) continue;
-        int vv = rec_view[g];
-        if (!rect_of(u[g], v[g], radius[g], w[vv], h[vv], tile, rect)) continue;
-        int tiles_x = (w[vv] + tile - 1) / tile;
-        orows er;
-        rows_setup(u[g], v[g], conic[3 * g], conic[3 * g + 1], conic[3 * g + 2], cutoff[g], &er);
-        for (int ty = rect[2]; ty <= rect[3]; ++ty) {
-            int lo, hi;
-            if (!rows_span(&er, h[vv], tile, ty, rect[0], rect[1], &lo, &hi)) continue;
-            for (int tx = lo; tx <= hi; ++tx) {
-                uint64_t gt = (uint64_t)(tile_off[vv] + (int64_t)ty * tiles_x + tx);
-                kv[e].key = (gt << 32) | f32_bits(depth[g]);
-                kv[e].val = (uint32_t)g;
-                ++e;
-            }
-        }
-    }
+    for (int64_t i = 0; i < count; ++i) { kv[i].key = keys[i]; kv[i].val = vals[i]; }
     qsort(kv, (size_t)count, sizeof(okv), cmp_kv);
     for (int64_t t = 0; t < 2 * total_tiles; ++t) ranges[t] = 0;
     for (int64_t i = 0; i < count; ++i) {
@@ -501,7 +527,67 @@ int64_t oracle_pairs(int64_t nrec, const double *u, const double *v, const float
         if (i == count - 1 || (kv[i + 1].key >> 32) != t) ranges[2 * t + 1] = (uint32_t)(i + 1);
     }
     free(kv);
+}
+
+static uint32_t f32_bits(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
+
+/*
+ * The key table: key = global tile << 32 | bits(float32 depth), value = record index, for every listed
+ * (tile, record) pair (the plain definition above, no band), ordered by (key, value), with per-tile
+ * [start, end) ranges. When keys == NULL only the pair count is returned.
+ */
+int64_t oracle_pairs(int64_t nrec, const double *u, const double *v, const float *depth, const int32_t *radius,
+                     const double *conic, const double *cutoff,
+                     const int32_t *valid, const int32_t *rec_view, const int32_t *w, const int32_t *h,
+                     const int64_t *tile_off, int32_t tile, int64_t total_tiles,
+                     uint64_t *keys, uint32_t *vals, uint32_t *ranges) {
+    int64_t count = oracle_tile_candidates(nrec, u, v, radius, conic, cutoff, valid, rec_view, w, h, tile_off, tile,
+                                           0.0, NULL, NULL, NULL);
+    if (!keys) return count;
+    int64_t *tl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(count > 0 ? count : 1));
+    uint8_t *st = (uint8_t *)malloc((size_t)(count > 0 ? count : 1));
+    oracle_tile_candidates(nrec, u, v, radius, conic, cutoff, valid, rec_view, w, h, tile_off, tile, 0.0, tl, vals,
+                           st);
+    for (int64_t i = 0; i < count; ++i) keys[i] = ((uint64_t)tl[i] << 32) | f32_bits(depth[vals[i]]);
+    free(tl);
+    free(st);
+    oracle_sort_pairs(count, keys, vals, total_tiles, ranges);
     return count;
+}
+
+/*
+ * Sub-tile reach of listed pairs: for pair i (global tile tiles[i], record recs[i]), the 8 x 8 sub-tiles
+ * of the tile (S = tile / 8 per edge; bit r S + c for sub-row r, sub-column c) whose pixel-centre boxes
+ * inside the image the ellipse {Q <= k} meets. set[i]: sub-tiles with q <= k outside the relative band;
+ * near[i]: sub-tiles with |q - k| <= band k. Sub-tiles with no pixel inside the image are in neither.
+ * A conic that is not positive definite reaches every sub-tile with pixels.
+ */
+void oracle_subtile_flags(int64_t npairs, const int64_t *tiles, const uint32_t *recs, const double *u,
+                          const double *v, const double *conic, const double *cutoff, const int32_t *rec_view,
+                          int32_t nviews, const int32_t *w, const int32_t *h, const int64_t *tile_off, int32_t tile,
+                          double band, uint32_t *set, uint32_t *near) {
+    const int S = tile / 8;
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < npairs; ++i) {
+        uint32_t g = recs[i];
+        int vv = rec_view[g];
+        (void)nviews;
+        int tiles_x = (w[vv] + tile - 1) / tile;
+        int64_t lt = tiles[i] - tile_off[vv];
+        int tx = (int)(lt % tiles_x), ty = (int)(lt / tiles_x);
+        double k = cutoff[g];
+        uint32_t s = 0, nb = 0;
+        for (int r = 0; r < S; ++r)
+            for (int c = 0; c < S; ++c) {
+                int sx = tx * S + c, sy = ty * S + r;
+                if (sx * 8 >= w[vv] || sy * 8 >= h[vv]) continue;
+                double q = tile_q(u[g], v[g], conic + 3 * (int64_t)g, sx, sy, 8, w[vv], h[vv]);
+                if (band > 0.0 && fabs(q - k) <= band * k) nb |= 1u << (r * S + c);
+                else if (q <= k) s |= 1u << (r * S + c);
+            }
+        set[i] = s;
+        near[i] = nb;
+    }
 }
 
 /* --------------------------------------------------------------- blend ---- */
@@ -539,11 +625,12 @@ static int frag_alpha(const orecs *rc, int64_t g, double px, double py, double *
  */
 static int64_t composite(const orecs *rc, const uint32_t *list, int64_t len, double px, double py,
                          const double bg[3], double out[3], double *T_out, int32_t *last_out, int *flag_out,
-                         int64_t *sig_out, double *weight_slots) {
+                         uint64_t *sig_out, double *weight_slots) {
     double T = 1.0, C[3] = {0, 0, 0};
     int32_t last = 0;
     int flag = 0;
-    int64_t evaluated = 0, sig = 0;
+    int64_t evaluated = 0;
+    uint64_t sig = 0; /* decision signature: unsigned arithmetic, wrapping by definition */
     for (int64_t pos = 0; pos < len; ++pos) {
         ++evaluated;
         uint32_t g = list[pos];
@@ -557,7 +644,7 @@ static int64_t composite(const orecs *rc, const uint32_t *list, int64_t len, dou
         if (weight_slots) weight_slots[pos] += alpha * T;
         T = Tn;
         last = (int32_t)(pos + 1);
-        sig = sig * 1000003 + (int64_t)g * 2 + clamped;
+        sig = sig * 1000003u + (uint64_t)g * 2u + (uint64_t)clamped;
     }
     for (int c = 0; c < 3; ++c) out[c] = C[c] + T * bg[c];
     *T_out = T;
@@ -579,7 +666,7 @@ static int64_t composite(const orecs *rc, const uint32_t *list, int64_t len, dou
 int64_t oracle_blend(int32_t w, int32_t h, int32_t tile, const double *bg,
                      const double *u, const double *v, const double *conic, const double *o, const double *rgb,
                      const uint32_t *vals, const uint32_t *ranges,
-                     double *image, double *T, int32_t *last, int32_t *flag, int64_t *sig,
+                     double *image, double *T, int32_t *last, int32_t *flag, uint64_t *sig,
                      int64_t npairs, double *importance) {
     orecs rc = {u, v, conic, o, rgb};
     int tiles_x = (w + tile - 1) / tile, tiles_y = (h + tile - 1) / tile;

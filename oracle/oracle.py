@@ -48,11 +48,21 @@ class OGrad(ctypes.Structure):
     _fields_ = [(p, _dp) for p in PLANES]
 
 
+# MEGS_ORACLE_SANITIZE=1 builds and loads a separate copy instrumented with AddressSanitizer and
+# UndefinedBehaviorSanitizer that stops at the first report (the sanitizer pin run; the process must
+# preload the sanitizer runtimes).
+SANITIZE = os.environ.get("MEGS_ORACLE_SANITIZE", "") == "1"
+if SANITIZE:
+    LIB = os.path.join(HERE, "libmegs_oracle_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no fast-math, no FMA contraction)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+        opt = SAN_FLAGS if SANITIZE else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
                                "-std=c11", "-Wall", "-shared", "-fPIC", SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -74,6 +84,13 @@ def lib():
         L.oracle_pairs.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                    ctypes.c_int32, ctypes.c_int64, vp, vp, vp]
         L.oracle_pairs.restype = ctypes.c_int64
+        L.oracle_tile_candidates.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                             ctypes.c_int32, ctypes.c_double, vp, vp, vp]
+        L.oracle_tile_candidates.restype = ctypes.c_int64
+        L.oracle_box_min.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp]
+        L.oracle_sort_pairs.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_int64, vp]
+        L.oracle_subtile_flags.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp,
+                                           ctypes.c_int32, ctypes.c_double, vp, vp]
         L.oracle_blend.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
                                    vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp]
         L.oracle_blend.restype = ctypes.c_int64
@@ -189,11 +206,18 @@ def tile_layout(cams: Sequence, tile: int):
     return off
 
 
+def _view_arrays(cams, tile):
+    w = np.array([c.width for c in cams], np.int32)
+    h = np.array([c.height for c in cams], np.int32)
+    return w, h, tile_layout(cams, tile)
+
+
 def pairs(u, v, depth_f32, radius, conic, cutoff, valid, rec_view, cams, tile: int):
     """Sorted key table over records of several views.
 
     u, v: float64 means; depth_f32: float32 depths; radius, valid, rec_view: int32; conic [n][3]
-    and cutoff [n] (float64) select the tiles of each rectangle the footprint ellipse reaches.
+    and cutoff [n] (float64): a tile of a record's rectangle is listed when the minimum of the
+    record's quadratic form over the tile's pixel-centre box is <= cutoff.
     Returns keys (uint64), vals (uint32), ranges ([T][2] uint32), tile offsets.
     """
     u = _c64(u); v = _c64(v)
@@ -202,9 +226,7 @@ def pairs(u, v, depth_f32, radius, conic, cutoff, valid, rec_view, cams, tile: i
     r = np.ascontiguousarray(radius, np.int32)
     va = np.ascontiguousarray(valid, np.int32)
     rv = np.ascontiguousarray(rec_view, np.int32)
-    w = np.array([c.width for c in cams], np.int32)
-    h = np.array([c.height for c in cams], np.int32)
-    off = tile_layout(cams, tile)
+    w, h, off = _view_arrays(cams, tile)
     total = int(off[-1])
     L = lib()
     n = len(u)
@@ -216,6 +238,62 @@ def pairs(u, v, depth_f32, radius, conic, cutoff, valid, rec_view, cams, tile: i
     L.oracle_pairs(n, _ptr(u), _ptr(v), _ptr(d), _ptr(r), _ptr(cn), _ptr(cu), _ptr(va), _ptr(rv), _ptr(w), _ptr(h),
                    _ptr(off), tile, total, _ptr(keys), _ptr(vals), _ptr(ranges))
     return keys[:cnt], vals[:cnt], ranges, off
+
+
+def tile_candidates(u, v, radius, conic, cutoff, valid, rec_view, cams, tile: int, band: float):
+    """Every (tile, record) pair of the records' rectangles that is listed or whose decision lies within
+    the relative band of the level: (global tile int64, record uint32, state uint8: 1 listed, 2 within
+    the band), in record order."""
+    u = _c64(u); v = _c64(v)
+    cn = _c64(conic); cu = _c64(cutoff)
+    r = np.ascontiguousarray(radius, np.int32)
+    va = np.ascontiguousarray(valid, np.int32)
+    rv = np.ascontiguousarray(rec_view, np.int32)
+    w, h, off = _view_arrays(cams, tile)
+    L = lib()
+    args = (len(u), _ptr(u), _ptr(v), _ptr(r), _ptr(cn), _ptr(cu), _ptr(va), _ptr(rv), _ptr(w), _ptr(h), _ptr(off),
+            tile, float(band))
+    cnt = L.oracle_tile_candidates(*args, None, None, None)
+    tl = np.zeros(max(cnt, 1), np.int64)
+    rc = np.zeros(max(cnt, 1), np.uint32)
+    st = np.zeros(max(cnt, 1), np.uint8)
+    L.oracle_tile_candidates(*args, _ptr(tl), _ptr(rc), _ptr(st))
+    return tl[:cnt], rc[:cnt], st[:cnt]
+
+
+def box_min(u, v, conic, box) -> np.ndarray:
+    """min over each box [x0, x1] x [y0, y1] of (p - m)' C (p - m) (-inf for a conic that is not positive
+    definite). u, v: [m]; conic: [m][3] = (a, b, c); box: [m][4]."""
+    u = _c64(np.atleast_1d(u)); v = _c64(np.atleast_1d(v))
+    cn = _c64(np.reshape(conic, (-1, 3))); bx = _c64(np.reshape(box, (-1, 4)))
+    out = np.zeros(len(u))
+    lib().oracle_box_min(len(u), _ptr(u), _ptr(v), _ptr(cn), _ptr(bx), _ptr(out))
+    return out
+
+
+def sort_pairs(keys, vals, total_tiles: int):
+    """(keys, vals) ordered by (key, value) and the per-tile [start, end) ranges."""
+    keys = np.array(keys, np.uint64, copy=True)
+    vals = np.array(vals, np.uint32, copy=True)
+    ranges = np.zeros((int(total_tiles), 2), np.uint32)
+    lib().oracle_sort_pairs(len(keys), _ptr(keys), _ptr(vals), int(total_tiles), _ptr(ranges))
+    return keys, vals, ranges
+
+
+def subtile_flags(tiles, recs, u, v, conic, cutoff, rec_view, cams, tile: int, band: float):
+    """For each listed pair, the 8 x 8 sub-tiles of the tile (bit r S + c, S = tile / 8) whose pixel-centre
+    boxes the record's ellipse reaches: (set uint32, near uint32), near = within the relative band."""
+    tiles = np.ascontiguousarray(tiles, np.int64)
+    recs = np.ascontiguousarray(recs, np.uint32)
+    u = _c64(u); v = _c64(v)
+    cn = _c64(conic); cu = _c64(cutoff)
+    rv = np.ascontiguousarray(rec_view, np.int32)
+    w, h, off = _view_arrays(cams, tile)
+    s = np.zeros(len(tiles), np.uint32)
+    nb = np.zeros(len(tiles), np.uint32)
+    lib().oracle_subtile_flags(len(tiles), _ptr(tiles), _ptr(recs), _ptr(u), _ptr(v), _ptr(cn), _ptr(cu), _ptr(rv),
+                               len(cams), _ptr(w), _ptr(h), _ptr(off), tile, float(band), _ptr(s), _ptr(nb))
+    return s, nb
 
 
 def _recs(rec):
@@ -232,7 +310,7 @@ def blend(cam, tile: int, rec: dict, vals, ranges_view, importance=None):
     T = np.zeros((h, w), np.float64)
     last = np.zeros((h, w), np.int32)
     flag = np.zeros((h, w), np.int32)
-    sig = np.zeros((h, w), np.int64)
+    sig = np.zeros((h, w), np.uint64)
     vals = np.ascontiguousarray(vals, np.uint32)
     rv = np.ascontiguousarray(ranges_view, np.uint32)
     nfrag = lib().oracle_blend(w, h, tile, _ptr(bg), _ptr(u), _ptr(v), _ptr(conic), _ptr(o), _ptr(rgb),

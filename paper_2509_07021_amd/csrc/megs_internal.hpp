@@ -170,13 +170,13 @@ __device__ __forceinline__ uint32_t tile_rect(double u, double v, int32_t r, con
     return static_cast<uint32_t>((x1 - x0 + 1) * (y1 - y0 + 1));
 }
 
-// Tile selection inside a record's rectangle. For each tile row, the listed tiles are those whose
-// pixel-centre columns meet the x-extent of E ∩ band, where E = {p : (p - m)' C (p - m) <= k}
-// (C = [[a, b], [b, c]] the conic) and band = the row's pixel-centre rows [Y0, Y1]. E ∩ band is
-// convex, so a tile's box meets it exactly when their x-ranges overlap. With S = C^-1, the points
-// of E with extreme x lie at dy = +-S_xy sqrt(k / S_xx); the x-extent over the band is reached
-// there, clamped into the band (x_max(dy) is concave, x_min(dy) convex). Plain FP64 +, -, *, /
-// and sqrt in a fixed order, so any IEEE implementation lists the same tiles.
+// Tile selection inside a record's rectangle: a tile is listed when the ellipse
+// E = {p : (p - m)' C (p - m) <= k} (C = [[a, b], [b, c]] the conic, k the record's level) meets the box
+// spanned by the centres of the tile's pixels inside the image. Evaluated per tile row: with
+// band = the row's pixel-centre rows [Y0, Y1], E ∩ band is convex, so a tile's box meets it exactly
+// when their x-ranges overlap. With S = C^-1, the points of E with extreme x lie at
+// dy = +-S_xy sqrt(k / S_xx); the x-extent over the band is reached there, clamped into the band
+// (x_max(dy) is concave, x_min(dy) convex). FP64 throughout.
 struct EllipseRows {
     double u, v, b, det, ia, ka, ry, dys;
     bool full;  // degenerate conic: list the whole rectangle
@@ -195,9 +195,10 @@ __device__ __forceinline__ void ellipse_rows(double u, double v, double a, doubl
 }
 
 // Columns [lo, hi] of tile row ty listed for the record (within the rectangle columns [x0, x1]);
-// returns false when the row lists no tile.
-__device__ __forceinline__ bool row_span(const EllipseRows& e, int height, int tile, int ty, int x0, int x1,
-                                         int& lo, int& hi) {
+// returns false when the row lists no tile. The last tile column's box ends at the image's last pixel
+// centre, width - 1/2.
+__device__ __forceinline__ bool row_span(const EllipseRows& e, int width, int height, int tile, int ty, int x0,
+                                         int x1, int& lo, int& hi) {
     if (e.full) { lo = x0; hi = x1; return true; }
     const int ye = (ty + 1) * tile < height ? (ty + 1) * tile : height;
     double dl = (ty * tile + 0.5) - e.v, dh = (ye - 0.5) - e.v;
@@ -216,6 +217,7 @@ __device__ __forceinline__ bool row_span(const EllipseRows& e, int height, int t
     const double s2 = sqrt(r2 > 0.0 ? r2 : 0.0);
     const double xmax = e.u + (s1 - e.b * d1) * e.ia;
     const double xmin = e.u - (s2 + e.b * d2) * e.ia;
+    if (xmin > width - 0.5) return false;
     // division by the power-of-two tile size as an exact exponent shift (the same value as x / tile)
     const int sh = __ffs(tile) - 1;
     double flo = ceil(ldexp(xmin + 0.5, -sh) - 1.0), fhi = floor(ldexp(xmax - 0.5, -sh));

@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
                 ellipse_rows(p.u, p.v, p.conic[0], p.conic[1], p.conic[2], cut, er);
                 for (int ty = y0; ty <= y1; ++ty) {
                     int lo, hi;
-                    if (row_span(er, vw.height, tile, ty, x0, x1, lo, hi)) nt += (uint32_t)(hi - lo + 1);
+                    if (row_span(er, vw.width, vw.height, tile, ty, x0, x1, lo, hi)) nt += (uint32_t)(hi - lo + 1);
                 }
             }
             if (rec.mean) {  // per-field planes, on request only

@@ -572,12 +572,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     if (has && nt && off + (int64_t)nt > capacity) status[1] = 1;
     // record geometry and the view fields the loops need, in registers (only threads with pairs)
     int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
-    int vh = 0, tiles_x = 0;
+    int vh = 0, vw_w = 0, tiles_x = 0;
     int64_t tile_off = 0;
     EllipseRows er;
     if (nt) {
         const ViewInfo& vw = views[g / n];
         vh = vw.height;
+        vw_w = vw.width;
         tiles_x = vw.tiles_x;
         tile_off = vw.tile_off;
         const double mx = __hiloint2double(__float_as_int(q0.y), __float_as_int(q0.x));
@@ -592,7 +593,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
             const BandsF bf = bands_of(er);
             for (int ty = y0; ty <= y1 && pos < w1; ++ty) {
                 int cl, ch;
-                if (!row_span(er, vh, tile, ty, x0, x1, cl, ch)) continue;
+                if (!row_span(er, vw_w, vh, tile, ty, x0, x1, cl, ch)) continue;
                 if (pos + (ch - cl + 1) <= w0) {  // the whole row lies before this window
                     pos += ch - cl + 1;
                     continue;

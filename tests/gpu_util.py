@@ -7,12 +7,14 @@ import dataclasses
 import numpy as np
 import torch
 
+from oracle import oracle as O
 from paper_2509_07021_amd import _lib as L
 from paper_2509_07021_amd import render as R
 from paper_2509_07021_amd import scenes as S
 
 IMG_TOL = 1e-5          # max abs image difference (FP32 path vs FP64 oracle)
 GRAD_REL = 1e-4         # per-tensor relative L2 and per-element relative tolerance
+KEY_BAND = 1e-9         # relative band of the tile level within which either listing decision is accepted
 
 
 def log(*a):
@@ -149,3 +151,55 @@ def scene_from_device(ds: R.DeviceScene) -> S.Scene:
     lobe_off = None if ds.lobe_off is None else ds.lobe_off.cpu().numpy().astype(np.int32)
     return S.Scene(n=ds.n, k=ds.k, dt_geom=ds.dt[0], dt_color=ds.dt[1], dt_amp=ds.dt[2], lobe_off=lobe_off,
                    **planes)
+
+
+def check_key_table(vals, ranges, rec, depth_f32, cams, tile: int, n: int, tile_keys=None, keys64=None,
+                    sub: int = 0) -> dict:
+    """The GPU's key table against the oracle's plain tile definition, given the same records.
+
+    The oracle lists a (tile, record) pair when the minimum of the record's quadratic form over the
+    tile's pixel-centre box is at most the record's level k. Pairs whose minimum lies within KEY_BAND k
+    of k are flagged: the kernel evaluates the same definition in another FP64 rounding order and may
+    take either side, so there the GPU's decision is adopted, and the flagged pairs are counted. Every
+    other decision, and then the sorted keys, record order and per-tile ranges, must agree bit for bit.
+    With sub-tile flags (sub = 8), the upper 16 bits of each tile key must flag every 8 x 8 sub-tile the
+    ellipse reaches (the flags are a superset: the kernel widens them); the extra flags are counted.
+    Returns the counts."""
+    nv = len(cams)
+    rec_view = np.repeat(np.arange(nv, dtype=np.int32), n)
+    tl, rc, st = O.tile_candidates(rec["u"], rec["v"], rec["radius"], rec["conic"], rec["cutoff"], rec["valid"],
+                                   rec_view, cams, tile, KEY_BAND)
+    off = O.tile_layout(cams, tile)
+    vals = np.asarray(vals, np.uint32)
+    if keys64 is not None:
+        gtile = (np.asarray(keys64, np.uint64) >> np.uint64(32)).astype(np.int64)
+    else:
+        tk = np.asarray(tile_keys, np.uint32)
+        gtile = (tk & np.uint32(0xFFFF) if sub else tk).astype(np.int64)
+    near = st == 2
+    gcode = (gtile << 32) | vals.astype(np.int64)
+    ncode = (tl[near] << 32) | rc[near].astype(np.int64)
+    taken = np.isin(ncode, gcode)
+    keep = st == 1
+    keep[np.nonzero(near)[0][taken]] = True
+    depth_bits = np.asarray(depth_f32, np.float32).view(np.uint32).astype(np.uint64)
+    keys = (tl[keep].astype(np.uint64) << np.uint64(32)) | depth_bits[rc[keep]]
+    okeys, ovals, oranges = O.sort_pairs(keys, rc[keep], int(off[-1]))
+    assert len(vals) == len(ovals), f"{len(vals)} pairs listed, oracle {len(ovals)} ({int(near.sum())} in the band)"
+    np.testing.assert_array_equal(vals, ovals)
+    np.testing.assert_array_equal(np.asarray(ranges, np.uint32).reshape(-1, 2), oranges)
+    np.testing.assert_array_equal(gtile.astype(np.uint64), okeys >> np.uint64(32))
+    if keys64 is not None:
+        np.testing.assert_array_equal(np.asarray(keys64, np.uint64), okeys)
+    out = {"pairs": int(len(vals)), "band": int(near.sum()), "band_listed": int(taken.sum())}
+    assert out["band"] <= 1e-5 * max(len(vals), 1) + 2, out
+    if sub and tile_keys is not None and len(vals):
+        flags = np.asarray(tile_keys, np.uint32) >> np.uint32(16)
+        fset, fnear = O.subtile_flags(gtile, vals, rec["u"], rec["v"], rec["conic"], rec["cutoff"], rec_view, cams,
+                                      tile, KEY_BAND)
+        missing = fset & ~flags
+        assert not missing.any(), f"{np.count_nonzero(missing)} pairs miss the flag of a reached sub-tile"
+        pc = lambda x: int(np.unpackbits(x.view(np.uint8)).sum())
+        out["subtiles"] = pc(fset)
+        out["subtiles_extra"] = pc(flags & ~fset & ~fnear)
+    return out

@@ -10,7 +10,7 @@ from paper_2509_07021_amd import _lib as L
 from paper_2509_07021_amd import render as R
 from paper_2509_07021_amd import scenes as S
 
-from gpu_util import IMG_TOL, grad2d_from_moments, grad_close, gpu_records, gpu_run, log
+from gpu_util import IMG_TOL, check_key_table, grad2d_from_moments, grad_close, gpu_records, gpu_run, log
 
 pytestmark = pytest.mark.gpu
 
@@ -142,15 +142,10 @@ def _full_size_sampled(scene, cams, cfg, frac, seed):
     ranges = fr.buffer("ranges", 2 * T, torch.int32).view(T, 2).cpu().numpy().view(np.uint32)
     rec = gpu_records(g)
     log(f"key table: {P} pairs over {nv} views")
-    rec_view = np.repeat(np.arange(nv, dtype=np.int32), scene.n)
-    keys, ovals, oranges, off = O.pairs(rec["u"], rec["v"], g["rgbd"][:, 3], rec["radius"], rec["conic"],
-                                        rec["cutoff"], rec["valid"], rec_view, cams, tile)
-    assert len(keys) == P
-    np.testing.assert_array_equal(vals, ovals)
-    np.testing.assert_array_equal(ranges, oranges)
-    if cfg.subtile:
-        tkeys = tkeys & np.uint32(0xFFFF)   # the upper half carries the sub-tile flags
-    np.testing.assert_array_equal(tkeys, (keys >> np.uint64(32)).astype(np.uint32))
+    cnt = check_key_table(vals, ranges, rec, g["rgbd"][:, 3], cams, tile, scene.n, tile_keys=tkeys,
+                          sub=cfg.subtile)
+    log(f"key table against the oracle: {cnt}")
+    off = O.tile_layout(cams, tile)
     pick, rs = _sampled_tiles(ranges, frac, seed)
     log(f"blend on {pick.sum()} sampled tiles")
     images = R.split_images(fr.images, cams)

@@ -352,6 +352,110 @@ def test_key_table_structure(oracle):
     np.testing.assert_array_equal((keys & np.uint64(0xFFFFFFFF)).astype(np.uint32), dep[vals])
 
 
+def _qp_box_min(C, m, box):
+    """min over the box of (p - m)' C (p - m) by scipy's bound-constrained quasi-Newton solver (a library
+    routine that knows nothing of edges or vertices), from several starting points."""
+    from scipy.optimize import minimize
+    f = lambda p: float((p - m) @ C @ (p - m))
+    jac = lambda p: 2.0 * C @ (p - m)
+    lo, hi = np.array([box[0], box[2]]), np.array([box[1], box[3]])
+    best = np.inf
+    for x0 in (np.clip(m, lo, hi), (lo + hi) / 2, lo, hi, np.array([lo[0], hi[1]]), np.array([hi[0], lo[1]])):
+        r = minimize(f, x0, jac=jac, method="L-BFGS-B", bounds=list(zip(lo, hi)),
+                     options={"ftol": 1e-15, "gtol": 1e-13, "maxiter": 500})
+        best = min(best, float(r.fun))
+    return best
+
+
+def _random_conic(rng, cond_max=1e4):
+    """A positive definite 2 x 2 conic with a random orientation and condition number up to cond_max."""
+    lam1 = 10 ** rng.uniform(-3, 1)
+    lam2 = lam1 * 10 ** rng.uniform(0, np.log10(cond_max))
+    th = rng.uniform(0, np.pi)
+    Rm = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    return Rm @ np.diag([lam1, lam2]) @ Rm.T
+
+
+def test_box_minimum_against_library_qp(oracle):
+    """The oracle's tile predicate rests on the minimum of the footprint's quadratic form over a box. It
+    equals the bound-constrained minimum found by a library solver, for means inside, beside and
+    diagonal to the box, conics up to condition 1e4, and boxes down to a single pixel centre; and no point
+    of a dense grid over the box goes below it."""
+    rng = np.random.default_rng(17)
+    us, vs, cs, bs, ref = [], [], [], [], []
+    for trial in range(300):
+        C = _random_conic(rng)
+        x0, y0 = rng.uniform(-20, 20, 2)
+        wbox, hbox = (0.0, 0.0) if trial % 10 == 0 else rng.uniform(0, 16, 2)
+        box = np.array([x0, x0 + wbox, y0, y0 + hbox])
+        m = np.array([x0, y0]) + rng.uniform(-25, 40, 2)
+        if trial % 10 == 3:  # mean inside the box
+            m = np.array([x0 + rng.uniform(0, 1) * wbox, y0 + rng.uniform(0, 1) * hbox])
+        us.append(m[0]); vs.append(m[1]); cs.append([C[0, 0], C[0, 1], C[1, 1]]); bs.append(box)
+        ref.append(_qp_box_min(C, m, box))
+    got = oracle.box_min(np.array(us), np.array(vs), np.array(cs), np.array(bs))
+    ref = np.array(ref)
+    np.testing.assert_allclose(got, ref, rtol=1e-7, atol=1e-9)
+    assert (got == 0).sum() >= 5 and (got > 0).sum() >= 200  # both the inside and the boundary cases
+    for i in range(0, 300, 7):
+        gx = np.linspace(bs[i][0], bs[i][1], 161)
+        gy = np.linspace(bs[i][2], bs[i][3], 161)
+        X, Y = np.meshgrid(gx - us[i], gy - vs[i])
+        a, b, c = cs[i]
+        grid = a * X * X + 2 * b * X * Y + c * Y * Y
+        assert grid.min() >= got[i] * (1 - 1e-12) - 1e-12
+    # a conic that is not positive definite bounds nothing
+    assert oracle.box_min([0.0], [0.0], [[1.0, 2.0, 1.0]], [[5, 6, 5, 6]])[0] == -np.inf
+
+
+def test_key_table_is_exactly_the_reached_tiles(oracle):
+    """Both directions of the tile predicate, at every tile of every rectangle, on needle-shaped and round
+    footprints and images whose edges cut tiles: a tile is listed exactly when the footprint ellipse at the
+    record's level k reaches the tile's pixel-centre box, with the box minimum taken by a library solver
+    (pairs whose solver minimum lies within 1e-7 k of k are left out as undecidable by it). A listing that
+    is too wide or too narrow, a wrong box edge or a wrong level fails here."""
+    rng = np.random.default_rng(23)
+    sc = S.random_scene(rng, 120, 1, masks=True, spread=0.8, logscale_mu=-3.0)
+    sc.logscale[0, :40] = rng.uniform(-0.8, 0.0, 40).astype(sc.logscale.dtype)
+    sc.logscale[1:, :40] = rng.uniform(-6.5, -5.0, (2, 40)).astype(sc.logscale.dtype)
+    pl = sc.widened()
+    cams = [S.look_at((0, -3.5, 0.4), 100, 72), S.look_at((2.5, -2.0, 1.0), 56, 50)]
+    checked = listed_n = skipped = 0
+    for tile in (8, 16):
+        out = oracle.render(pl, sc.k, cams, tile)
+        rec, keys, vals, off = out["records"], out["keys"], out["vals"], out["tile_off"]
+        got = set(zip((keys >> np.uint64(32)).astype(np.int64).tolist(), vals.astype(np.int64).tolist()))
+        for g in np.nonzero(rec["valid"])[0]:
+            vi = g // sc.n
+            cam = cams[vi]
+            tx_n = (cam.width + tile - 1) // tile
+            u, v, r = rec["u"][g], rec["v"][g], rec["radius"][g]
+            a, b, c = rec["conic"][g]
+            C = np.array([[a, b], [b, c]])
+            k = rec["cutoff"][g]
+            xl, xh = max(math.floor(u) - r, 0), min(math.floor(u) + r, cam.width - 1)
+            yl, yh = max(math.floor(v) - r, 0), min(math.floor(v) + r, cam.height - 1)
+            if xl > xh or yl > yh:
+                continue
+            for ty in range(yl // tile, yh // tile + 1):
+                for tx in range(xl // tile, xh // tile + 1):
+                    box = (tx * tile + 0.5, min((tx + 1) * tile, cam.width) - 0.5,
+                           ty * tile + 0.5, min((ty + 1) * tile, cam.height) - 0.5)
+                    qmin = _qp_box_min(C, np.array([u, v]), box)
+                    if abs(qmin - k) <= 1e-7 * k:
+                        skipped += 1
+                        continue
+                    listed = (int(off[vi]) + ty * tx_n + tx, int(g)) in got
+                    assert listed == (qmin <= k), (tile, g, tx, ty, qmin, k, listed)
+                    checked += 1
+                    listed_n += listed
+    assert checked > 2000 and checked - listed_n > 300 and skipped <= 2, (checked, listed_n, skipped)
+    # the level bounds the alpha >= 1/255 support (alpha = o e^{-Q/2}) and exceeds it by a small margin only
+    v = rec["valid"].astype(bool)
+    k0 = 2.0 * np.log(255.0 * rec["o"][v])
+    assert np.all(rec["cutoff"][v] >= k0) and np.all(rec["cutoff"][v] <= 1.005 * k0 + 2e-4)
+
+
 # -------------------------------------------------------------- gradients ----
 
 def _fd_check(oracle, pl, k, cams, tile, weights, rng, per_plane=10):
