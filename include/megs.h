@@ -27,7 +27,8 @@
  *   stored. Colours are not clamped.
  *
  * Memory: every device buffer belongs to the caller. The library never calls hipMalloc:
- * it asks the caller's allocation callback for its working memory and never frees it.
+ * it asks the caller's allocation callback for its working memory and never frees it
+ * (megs_render_forward_noalloc takes its working memory from a static per-device array instead).
  * All work is enqueued on the caller's stream (a hipStream_t passed as void*).
  *
  * Errors: every entry point returns a megs_status and never throws. Arguments are checked
@@ -48,7 +49,8 @@ typedef enum {
     MEGS_OK = 0,
     MEGS_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, bad dtype, ...) */
     MEGS_ERR_HIP = -2,         /* a HIP runtime call failed */
-    MEGS_ERR_CAPACITY = -3,    /* the pair table overflowed its fixed capacity (graph mode) */
+    MEGS_ERR_CAPACITY = -3,    /* the pair table overflowed its fixed capacity (graph mode), or the
+                                  working memory exceeds the static scratch (no-allocation forward) */
     MEGS_ERR_UNSUPPORTED = -4, /* a configuration the library does not implement */
     MEGS_ERR_ALLOC = -5        /* the allocation callback returned NULL or memory not 256-byte aligned */
 } megs_status;
@@ -201,6 +203,27 @@ typedef struct {
 megs_status megs_render_forward(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
                                 const megs_config *cfg, megs_alloc_fn alloc, void *alloc_ctx,
                                 float *images, megs_state *state, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under hipGraph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): megs_render_forward with its working memory (the records, sort
+ * buffers, per-pixel state and pair table that megs_render_forward obtains from the allocation
+ * callback) carved from one static array of MEGS_NOALLOC_SCRATCH_BYTES bytes per device instead. The
+ * array lives in the library's code object: each device the library runs on holds it until the
+ * process ends. The call allocates nothing; images and state are as for megs_render_forward, and the
+ * state's buffers lie in the array, valid until the next call of this function on the same device
+ * (megs_render_backward accepts that state). The device current on the calling thread must be the
+ * stream's device. All calls on one device share its array, so calls that overlap in time on one
+ * device (other streams, other threads) race: the caller serialises them.
+ * pair_capacity == 0 synchronises the stream once, as megs_render_forward does; pair_capacity > 0
+ * does not (overflow is then reported by megs_state_status).
+ * Errors: as megs_render_forward, and MEGS_ERR_CAPACITY, before anything is launched, when the frame
+ * (plus a fixed pair table) needs more than MEGS_NOALLOC_SCRATCH_BYTES, or, after the one
+ * synchronisation, when the counted pairs do not fit beside it.
+ */
+#define MEGS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+megs_status megs_render_forward_noalloc(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
+                                        const megs_config *cfg, float *images, megs_state *state, void *stream);
 
 /*
  * Backward: gradients of L with respect to every raw parameter plane, given dL/dimage

@@ -21,6 +21,7 @@ MEGS_FLAG_RECORD_PLANES = 16
 STAGES = ("project", "depth_sort", "scan", "emit", "pair_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd")
 MEGS_MAX_LOBES = 8
 MEGS_MAX_VIEWS = 64
+MEGS_NOALLOC_SCRATCH_BYTES = 64 << 20
 AUTOTUNE_COMBOS = ((8, 1, 0), (16, 1, 0), (16, 2, 0), (16, 4, 0), (32, 1, 0), (32, 2, 0), (32, 4, 0), (16, 1, 8),
                    (32, 1, 8))   # (tile, waves, subtile)
 AUTOTUNE_BATCHES = (32, 64, 128, 256)
@@ -29,7 +30,8 @@ EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", 
             "megs_graph_launch", "megs_graph_status", "megs_graph_state", "megs_graph_destroy",
             "megs_autotune", "megs_profile_begin", "megs_profile_end", "megs_last_error", "megs_version",
             "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply", "megs_dual_update",
-            "megs_penalty_grad", "megs_compact", "megs_photometric_loss", "megs_adam_step")
+            "megs_penalty_grad", "megs_compact", "megs_photometric_loss", "megs_adam_step",
+            "megs_render_forward_noalloc")
 
 PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
           "base", "axis", "sharp", "amp", "lmask_logit")
@@ -102,6 +104,8 @@ def load():
     P = ctypes.POINTER
     L.megs_render_forward.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ALLOC_FN, _vp,
                                       _vp, P(MegsState), _vp]
+    L.megs_render_forward_noalloc.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), _vp,
+                                              P(MegsState), _vp]
     L.megs_render_backward.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), P(MegsState),
                                        _vp, ALLOC_FN, _vp, P(MegsSceneGrad), _vp]
     L.megs_state_status.argtypes = [P(MegsState), P(ctypes.c_int64), _vp]
@@ -130,7 +134,7 @@ def load():
                                  ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp]
     L.megs_profile_begin.argtypes = []
     L.megs_profile_end.argtypes = [P(MegsProfile)]
-    for f in ("megs_render_forward", "megs_render_backward", "megs_state_status", "megs_graph_create",
+    for f in ("megs_render_forward", "megs_render_forward_noalloc", "megs_render_backward", "megs_state_status", "megs_graph_create",
               "megs_graph_launch", "megs_graph_status", "megs_autotune", "megs_profile_begin", "megs_profile_end",
               "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply",
               "megs_dual_update", "megs_penalty_grad", "megs_compact", "megs_photometric_loss",

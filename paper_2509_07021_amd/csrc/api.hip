@@ -5,12 +5,19 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "megs_internal.hpp"
 
 using namespace megs;
+
+// Working memory of megs_render_forward_noalloc: one array per device in the library's code object, so
+// that a forward can run where the caller cannot allocate. In host code the name `scratch` denotes a
+// host-side stand-in, not device memory: host code takes the array's device address once per device
+// (hipGetSymbolAddress, below) and uses only that address.
+static __device__ __align__(256) unsigned char scratch[MEGS_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -592,6 +599,45 @@ megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t 
     return st;
 }
 
+// Device address of `scratch` on the calling thread's current device, taken once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];
+
+megs_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MEGS_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(MEGS_ERR_HIP, "hipGetSymbolAddress returned a null address for the static scratch");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return MEGS_OK;
+}
+
+// Bump allocation over the static scratch, in place of the caller's allocation callback.
+struct ScratchBump {
+    char* base;
+    size_t off, cap;
+    size_t needed;  // the total the first request that did not fit would have needed (0: none)
+};
+
+void* scratch_take(void* ctx, size_t bytes) {
+    ScratchBump* b = static_cast<ScratchBump*>(ctx);
+    const size_t a = align256(bytes);
+    if (a > b->cap - b->off) {
+        if (!b->needed) b->needed = b->off + a;
+        return nullptr;
+    }
+    void* p = b->base + b->off;
+    b->off += a;
+    return p;
+}
+
 }  // namespace
 
 struct megs_graph {
@@ -643,6 +689,34 @@ megs_status megs_render_forward(const megs_scene* scene, const megs_camera* cams
                                 megs_state* state, void* stream) {
     g_err[0] = 0;
     return forward_impl(scene, cams, n_views, cfg, alloc, alloc_ctx, images, state, static_cast<hipStream_t>(stream));
+}
+
+megs_status megs_render_forward_noalloc(const megs_scene* scene, const megs_camera* cams, int32_t n_views,
+                                        const megs_config* cfg, float* images, megs_state* state, void* stream) {
+    g_err[0] = 0;
+    megs_status st = check_args(scene, cams, n_views, cfg);
+    if (st != MEGS_OK) return st;
+    if (!images || !state) return fail(MEGS_ERR_ARG, "null image or state");
+    const Layout L = make_layout(scene, cams, n_views, cfg);
+    const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
+    const size_t cap = MEGS_NOALLOC_SCRATCH_BYTES;
+    // what is known before any launch: the frame, and the pair table when its capacity is fixed
+    size_t need = align256(frame_bytes(L));
+    if (cfg->pair_capacity > 0) need += align256(pairs_bytes(cfg->pair_capacity, one_stage, det));
+    if (need > cap)
+        return fail(MEGS_ERR_CAPACITY, "this forward needs %zu bytes of working memory; the static scratch holds %zu",
+                    need, cap);
+    void* base = nullptr;
+    st = scratch_of_current_device(&base);
+    if (st != MEGS_OK) return st;
+    ScratchBump b{static_cast<char*>(base), 0, cap, 0};
+    st = forward_impl(scene, cams, n_views, cfg, scratch_take, &b, images, state, static_cast<hipStream_t>(stream));
+    if (st == MEGS_ERR_ALLOC && b.needed)
+        return fail(MEGS_ERR_CAPACITY,
+                    "the counted pairs need %zu bytes of working memory in all; the static scratch holds %zu",
+                    b.needed, cap);
+    return st;
 }
 
 megs_status megs_render_backward(const megs_scene* scene, const megs_camera* cams, int32_t n_views,

@@ -182,3 +182,24 @@ def test_loss_and_adam_reject_bad_arguments():
     assert lib.megs_adam_step(4, v, 0, v, v, v, 1e-3, 0.9, 0.999, 1e-15, 0, None) == L.MEGS_ERR_ARG
     assert lib.megs_adam_step(4, v, 0, v, v, v, 1e-3, 1.0, 0.999, 1e-15, 1, None) == L.MEGS_ERR_ARG
     assert lib.megs_adam_step(0, None, 0, None, None, None, 1e-3, 0.9, 0.999, 1e-15, 1, None) == L.MEGS_OK
+
+
+def test_noalloc_forward_rejects_what_does_not_fit():
+    """The no-allocation forward refuses, before any launch, work whose memory exceeds its static
+    scratch: here the per-pixel state of one 4096 x 4096 view alone."""
+    lib = L.load()
+    sc, cams, cfg = _args(width=4096, height=4096)
+    st = L.MegsState()
+    status = lib.megs_render_forward_noalloc(ctypes.byref(sc), cams, 1, ctypes.byref(cfg), ctypes.c_void_p(16),
+                                             ctypes.byref(st), None)
+    assert status == L.MEGS_ERR_CAPACITY
+    msg = lib.megs_last_error().decode()
+    assert "static scratch" in msg and str(L.MEGS_NOALLOC_SCRATCH_BYTES) in msg
+    sc, cams, cfg = _args(cap=8 << 20)  # a fixed pair table of 8M pairs does not fit either
+    status = lib.megs_render_forward_noalloc(ctypes.byref(sc), cams, 1, ctypes.byref(cfg), ctypes.c_void_p(16),
+                                             ctypes.byref(st), None)
+    assert status == L.MEGS_ERR_CAPACITY
+    sc, cams, cfg = _args(tile=12)  # argument checks come first, as in megs_render_forward
+    status = lib.megs_render_forward_noalloc(ctypes.byref(sc), cams, 1, ctypes.byref(cfg), ctypes.c_void_p(16),
+                                             ctypes.byref(st), None)
+    assert status == L.MEGS_ERR_ARG
