@@ -184,7 +184,9 @@ def stage_bytes(stage, n, nv, pairs, npix, ntiles, geom_bytes, k, tile_bits=14):
     if stage == "ranges":
         return pairs * 4 + ntiles * 8
     if stage == "project_bwd":
-        return n * geom_bytes + nr * 9 * 4 + n * (14 + 8 * k) * 4
+        # parameters (both passes read their planes once), the records' 9 sums and conic factors, the
+        # gradient planes written
+        return n * geom_bytes + nr * (9 * 4 + 16) + n * (14 + 8 * k) * 4
     return 0
 
 

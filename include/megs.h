@@ -156,12 +156,19 @@ typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
  * device memory obtained from the allocation callback. Layouts (NR = n * n_views records,
  * record r = view * n + gaussian; P = pairs; T = tiles over all views; NP = pixels over all views):
  *   mean      double[NR][2]  pixel-space mean (u, v)          (this and conic_o, rgbd, radius,
- *                                                            cutoff: MEGS_FLAG_RECORD_PLANES only)
+ *                                                            cutoff, chol: MEGS_FLAG_RECORD_PLANES only)
  *   conic_o   float[NR][4]   conic (a, b, c) of q = -(a dx^2 + c dy^2)/2 - b dx dy, and o_eff
  *   rgbd      float[NR][4]   SG colour (r, g, b) and camera depth z
  *   radius    int32[NR]      footprint radius in pixels, -1 when culled
  *   ntiles    uint32[NR]     tiles of the record's rectangle that its footprint ellipse reaches
  *   cutoff    float[NR]      k of that ellipse, {d : d' conic d <= k}; k bounds 2 ln(255 o_eff)
+ *   chol      double[NR][4]  (l11, r, l22, 0): the conic as the key emission and the blend use it,
+ *                            conic = L L', L = [[l11, 0], [l11 r, l22]], so that
+ *                            q = (l11 (dx + r dy))^2 + (l22 dy)^2 (a sum of squares, no cancellation);
+ *                            l11 = sqrt(C / det), r = -B / C, l22 = 1 / sqrt(C) for the dilated 2D
+ *                            covariance [[A, B], [B, C]], det = A C - B^2, all formed in FP64; l11 and
+ *                            l22 are stored as FP32, r as FP64. conic_o's (a, b, c) are the FP32
+ *                            roundings of l11^2, l11^2 r, (l11 r)^2 + l22^2.
  *   tile_keys uint32[P]      sorted global tile ids (two-stage sort) or NULL; with subtile = 8 and
  *                            at most 65536 tiles, bits 16-31 flag the 8x8 sub-tiles of the tile that
  *                            the record's cutoff ellipse reaches (bit r S + c, S = tile / 8)
@@ -186,10 +193,11 @@ typedef struct {
      * first emission positions, and the pair count */
     const void *det_inv, *det_order, *det_offsets, *det_count;
     /* the records again, one 64-byte line each (read by the key emission and the blend, which
-     * gather records in depth and tile order): double mean[2]; float conic a, b, c, o_eff;
-     * float r, g, b, cutoff k; int32 radius; uint32 ntiles; float rx, ry, the widened half-extents
-     * of the ellipse {d' conic d <= k} */
+     * gather records in depth and tile order): double mean[2]; double r; float l11, l22 (the conic's
+     * factors, as in chol); float o_eff; float rgb[3]; float rx, ry, the widened half-extents of the
+     * ellipse {d' conic d <= k}; int32 radius; uint32 ntiles */
     const void *packed;
+    const void *chol; /* see above (MEGS_FLAG_RECORD_PLANES only) */
 } megs_state;
 
 /* Per-view image layout: images are concatenated, view v's float[3][H][W] planes starting at

@@ -75,7 +75,7 @@ class MegsState(ctypes.Structure):
                 ("mean", _vp), ("conic_o", _vp), ("rgbd", _vp), ("radius", _vp), ("ntiles", _vp), ("cutoff", _vp),
                 ("tile_keys", _vp), ("keys64", _vp), ("vals", _vp), ("ranges", _vp), ("T_final", _vp),
                 ("last", _vp), ("device_status", _vp), ("internal", _vp), ("det_inv", _vp), ("det_order", _vp),
-                ("det_offsets", _vp), ("det_count", _vp), ("packed", _vp)]
+                ("det_offsets", _vp), ("det_count", _vp), ("packed", _vp), ("chol", _vp)]
 
 
 class MegsProfile(ctypes.Structure):

@@ -251,6 +251,7 @@ size_t frame_bytes(const Layout& L) {
         b += align256(sizeof(double2) * (L.nr ? L.nr : 1));
         b += 2 * align256(sizeof(float4) * (L.nr ? L.nr : 1));
         b += 2 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
+        b += align256(sizeof(double4) * (L.nr ? L.nr : 1));
     }
     b += 6 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
     b += align256(scan_scratch_bytes(L.nr)) + align256(radix_scratch_bytes(L.nr));
@@ -272,11 +273,13 @@ Frame carve_frame(void* mem, const Layout& L) {
         f.rec.rgbd = c.take<float4>(L.nr);
         f.rec.radius = c.take<int32_t>(L.nr);
         f.rec.cutoff = c.take<float>(L.nr);
+        f.rec.chol = c.take<double4>(L.nr);
     } else {
         f.rec.mean = nullptr;
         f.rec.conic_o = f.rec.rgbd = nullptr;
         f.rec.radius = nullptr;
         f.rec.cutoff = nullptr;
+        f.rec.chol = nullptr;
     }
     f.rec.ntiles = c.take<uint32_t>(L.nr);
     f.rec.dkey = c.take<uint32_t>(L.nr);
@@ -476,6 +479,7 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     state->ntiles = f.rec.ntiles;
     state->cutoff = f.rec.cutoff;
     state->packed = f.rec.packed;
+    state->chol = f.rec.chol;
     state->tile_keys = sorted_t;
     state->keys64 = sorted_k;
     state->vals = sorted_v;
@@ -491,8 +495,8 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     return MEGS_OK;
 }
 
-// Backward scratch: per-record 2D gradients [NR][9], the persistent-queue word, and in
-// deterministic mode the per-pair slots [P][9].
+// Backward scratch: the per-record sums of the blend backward [NR][9] (grad2d_index), the
+// persistent-queue word, and in deterministic mode the per-pair slots [P][9].
 size_t backward_bytes(const Layout& L, const megs_config* cfg, int64_t cap) {
     size_t b = align256(sizeof(float) * 9 * (L.nr ? L.nr : 1)) + 256;
     if (cfg->flags & MEGS_FLAG_DETERMINISTIC) b += align256(sizeof(float) * 9 * (cap > 0 ? cap : 1));
@@ -514,6 +518,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     memset(&a, 0, sizeof(a));
     a.views = static_cast<const ViewInfo*>(st->internal);
     a.nv = L.nv; a.n_tiles = L.n_tiles;
+    a.n = L.n;
     a.rec = static_cast<const PackedRec*>(st->packed);
     a.tkeys = sub_masks(cfg, L) ? static_cast<const uint32_t*>(st->tile_keys) : nullptr;
     a.vals = static_cast<const uint32_t*>(st->vals);
@@ -546,7 +551,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
     g.sh = gr->sh;
     {
         StageTimer t(MEGS_STAGE_PROJECT_BWD, s);
-        HIP_TRY(launch_project_bwd(scene_dev(sc, nullptr), a.views, L.nv, grad2d, g, s));
+        HIP_TRY(launch_project_bwd(scene_dev(sc, nullptr), a.views, L.nv, grad2d, a.rec, g, s));
     }
     return MEGS_OK;
 }

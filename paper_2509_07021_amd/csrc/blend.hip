@@ -20,9 +20,9 @@
 // the transmittance in front of each fragment by division, carries the colour seen behind the
 // fragment (as its dot product with the pixel's colour gradient, the only form the gradient
 // uses), and accumulates nine per-record sums: e = dL/do_eff of each unclamped fragment,
-// its moments e dx, e dy, e dx^2, e dx dy, e dy^2 (the exponent's gradient is o_eff e, so the
-// projection backward turns them into the mean and conic gradients once per record), and the
-// colour gradient. They are summed over the wave's pixels with a transposed butterfly of
+// its moments e w1, e w2, e w1^2, e w1 w2, e w2^2 in the exponent's factors (Staged; the exponent's
+// gradient is o_eff e, so the projection backward turns them into the mean and conic gradients once
+// per record), and the colour gradient. They are summed over the wave's pixels with a transposed butterfly of
 // permlane swaps and DPP adds and added to the record's slot with nine lanes of one hardware
 // float atomic, only when some lane of the wave contributed.
 #include "megs_internal.hpp"
@@ -30,12 +30,19 @@
 namespace megs {
 namespace {
 
-// A record as the blends use it, with the conic (a, b, c) folded into the exponent coefficients:
-// the backward needs the conic itself only per record, in the projection backward.
+// A record as the blends use it, its shape folded into the exponent's affine factors over the
+// pixel centres of one frame (a tile or a sub-tile, origin (X0, Y0), pixel centre (px, py) relative
+// to it): the exponent in log2 units is -(w1^2 + w2^2) with
+//   w1 = ax px + ay py + c1,  w2 = by py + c2,
+// ax = kQ2 l11, ay = kQ2 l11 r, by = kQ2 l22 (Shape), c1 = kQ2 l11 ((X0 - u) + r (Y0 - v)) and
+// c2 = kQ2 l22 (Y0 - v). c1 and c2 are formed in FP64 from the FP64 mean and ratio, so the
+// cancellation along a thin footprint happens there, once per staged record; per pixel the FP32
+// terms stay within a frame's width of the footprint. The backward needs the conic itself only per
+// record, in the projection backward.
 struct Staged {
-    float4 box; // tile-relative bounding box of the cutoff ellipse: x - rx, x + rx, y - ry, y + ry
-    float4 p0;  // u_rel, v_rel, o, nb2   (nb2 = -b log2 e)
-    float4 p1;  // na2, nc2, r, g        (na2 = -a log2 e / 2, nc2 = -c log2 e / 2)
+    float4 box; // frame-relative bounding box of the cutoff ellipse: x - rx, x + rx, y - ry, y + ry
+    float4 p0;  // ax, ay, c1, o
+    float4 p1;  // by, c2, r, g
     float b;    // blue
 };
 
@@ -46,8 +53,8 @@ struct Kept {
     float4 p0, p1;   // as in Staged
     float b;         // as in Staged
     uint32_t pos1;   // one past the entry's list position (relative to the tile's range start)
-    uint64_t slot;   // forward: the record id (importance output); backward: 9 x record id, the
-                     // record's first gradient element
+    uint64_t slot;   // forward: the record id (importance output); backward: the record's first
+                     // element in the per-record sums (grad2d_index)
 };
 static_assert(sizeof(Kept) == 48 && offsetof(Kept, slot) % 8 == 0, "kept entries are 48 bytes, slot 8-aligned");
 
@@ -77,17 +84,23 @@ struct Layout {
     __device__ static int wy0(int wave) { return WAVES == 4 ? (wave >> 1) * WH : (WAVES == 2 ? wave * WH : 0); }
 };
 
+// Stages record g for the frame with origin (x0, y0) (pixel coordinates of its top-left corner). Only
+// t = (X0 - u) + r (Y0 - v), which cancels along a thin footprint, needs FP64; it is rounded once, and
+// c1 = ax t and c2 = by (Y0 - v) then err by about one FP32 rounding of their own size.
 __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0, double y0, Staged* dst) {
     const float4* q = reinterpret_cast<const float4*>(a.rec + g);  // the record's 64-byte line
-    const float4 q0 = q[0], co = q[1], cd = q[2], q3 = q[3];
+    const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
     const double mx = __hiloint2double(__float_as_int(q0.y), __float_as_int(q0.x));
     const double my = __hiloint2double(__float_as_int(q0.w), __float_as_int(q0.z));
+    const double r = __hiloint2double(__float_as_int(q1.y), __float_as_int(q1.x));
+    const double dx0 = x0 - mx, dy0 = y0 - my;
+    const float t = (float)fma(r, dy0, dx0), dxf = (float)dx0, dyf = (float)dy0;
+    const float ax = kQ2 * q1.z, by = kQ2 * q1.w;
     Staged s;
-    const float ur = (float)(mx - x0), vr = (float)(my - y0);
-    s.p0 = make_float4(ur, vr, co.w, -co.y * kLog2e);
-    s.p1 = make_float4(-0.5f * co.x * kLog2e, -0.5f * co.z * kLog2e, cd.x, cd.y);
-    s.b = cd.z;
-    s.box = make_float4(ur - q3.z, ur + q3.z, vr - q3.w, vr + q3.w);
+    s.p0 = make_float4(ax, ax * (float)r, ax * t, q2.x);
+    s.p1 = make_float4(by, by * dyf, q2.y, q2.z);
+    s.b = q2.w;
+    s.box = make_float4(-dxf - q3.x, -dxf + q3.x, -dyf - q3.y, -dyf + q3.y);
     *dst = s;
 }
 
@@ -97,21 +110,19 @@ __device__ __forceinline__ bool box_meets(const float4& b, int x0, int x1, int y
     return (x0 + 0.5f <= b.y) && (x1 + 0.5f >= b.x) && (y0 + 0.5f <= b.w) && (y1 + 0.5f >= b.z);
 }
 
-// Alpha test of one fragment (no branches): pass = alpha >= 1/255 with alpha = min(o G, 0.99).
-// The compositing rule also skips fragments with q > 0, which no listed record has: its conic is
-// positive definite, so q <= 0 exactly, and in FP32 q can round above 0 only where its exact value
-// is about 0, a fragment the exact rule passes; so q is not tested. The threshold is tested on the
-// unclamped value (the same decision for any number, and a NaN fails it). The forward and the
-// backward call this same function, so both take identical decisions.
+// Alpha test of one fragment (no branches): pass = alpha >= 1/255 with alpha = min(o G, 0.99) and
+// G = 2^(-(w1^2 + w2^2)) (Staged). The compositing rule also skips fragments with a positive
+// exponent, which a sum of squares never is. The threshold is tested on the unclamped value (the
+// same decision for any number, and a NaN fails it). The forward and the backward call this same
+// function, so both take identical decisions; w1 and w2 are returned for the backward's moments.
 template <class E>  // Staged or Kept
-__device__ __forceinline__ bool frag(const E& s, float px, float py, float& dx, float& dy, float& G,
+__device__ __forceinline__ bool frag(const E& s, float px, float py, float& w1, float& w2, float& G,
                                      float& alpha, bool& clamped) {
-    dx = px - s.p0.x;
-    dy = py - s.p0.y;
-    const float h = __fmaf_rn(s.p1.x, dx, s.p0.w * dy);
-    const float q2 = __fmaf_rn(dx, h, (s.p1.y * dy) * dy);
+    w1 = __fmaf_rn(s.p0.x, px, __fmaf_rn(s.p0.y, py, s.p0.z));
+    w2 = __fmaf_rn(s.p1.x, py, s.p1.y);
+    const float q2 = __fmaf_rn(-w1, w1, -(w2 * w2));
     G = __builtin_amdgcn_exp2f(q2);
-    const float raw = s.p0.z * G;
+    const float raw = s.p0.w * G;
     clamped = raw > kAlphaMax;
     alpha = fminf(raw, kAlphaMax);
     // keeps the clamp next to the product: moved into the callers' blend branches, it would need a
@@ -212,9 +223,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_fwd(BlendArgs a, int batch
                     // this wave's pixel rows of slot j; skip the slot when the footprint misses them
                     if (PPT > 1 && !box_meets(box, bx0, bx0 + Ly::WW - 1, by0 + LH * j, by0 + LH * j + LH - 1))
                         continue;
-                    float dx, dy, G;
+                    float w1, w2, G;
                     bool clamped;
-                    pass[j] = frag(s, px, ly + LH * j + 0.5f, dx, dy, G, alpha[j], clamped) & (T[j] > 0.0f);
+                    pass[j] = frag(s, px, ly + LH * j + 0.5f, w1, w2, G, alpha[j], clamped) & (T[j] > 0.0f);
                     any_pass |= pass[j];
                     if (STATS) n_evaluated += T[j] > 0.0f;
                 }
@@ -403,16 +414,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                 // box misses this wave's block, are skipped
                 if (pos < wave_last && box_meets(lds[jj].box, bx0, bx0 + Ly::WW - 1, by0, by0 + Ly::WH - 1)) {
                     const Staged s = lds[jj];
-                    float alpha[PPT], G[PPT], dxs[PPT], dys[PPT];
+                    float alpha[PPT], G[PPT], w1s[PPT], w2s[PPT];
                     bool incl[PPT], clamped[PPT];
 #pragma unroll
                     for (int j = 0; j < PPT; ++j) {
                         incl[j] = false;
-                        alpha[j] = 0.0f; G[j] = 0.0f; dxs[j] = 0.0f; dys[j] = 0.0f; clamped[j] = false;
+                        alpha[j] = 0.0f; G[j] = 0.0f; w1s[j] = 0.0f; w2s[j] = 0.0f; clamped[j] = false;
                         if (PPT > 1 &&
                             !box_meets(s.box, bx0, bx0 + Ly::WW - 1, by0 + LH * j, by0 + LH * j + LH - 1))
                             continue;
-                        incl[j] = frag(s, px, ly + LH * j + 0.5f, dxs[j], dys[j], G[j], alpha[j], clamped[j]) &
+                        incl[j] = frag(s, px, ly + LH * j + 0.5f, w1s[j], w2s[j], G[j], alpha[j], clamped[j]) &
                                   (pos < lst[j]);
                         any_incl |= incl[j];
                     }
@@ -434,14 +445,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                             const bool live = incl[j] & !clamped[j];
                             // dL/do_eff of the fragment; its exponent gradient is o_eff times this
                             const float e = live ? G[j] * dal : 0.0f;
-                            const float dx = dxs[j], dy = dys[j];
+                            const float w1 = w1s[j], w2 = w2s[j];
                             acc[5] += e;
-                            const float mx = e * dx, my = e * dy;
-                            acc[0] += mx;
-                            acc[1] += my;
-                            acc[2] = __fmaf_rn(mx, dx, acc[2]);
-                            acc[3] = __fmaf_rn(mx, dy, acc[3]);
-                            acc[4] = __fmaf_rn(my, dy, acc[4]);
+                            const float m1 = e * w1, m2 = e * w2;
+                            acc[0] += m1;
+                            acc[1] += m2;
+                            acc[2] = __fmaf_rn(m1, w1, acc[2]);
+                            acc[3] = __fmaf_rn(m1, w2, acc[3]);
+                            acc[4] = __fmaf_rn(m2, w2, acc[4]);
                         }
                     }
                 }
@@ -457,7 +468,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                     }
                     // one 9-lane atomic: lanes 0, 8, .., 56 add sums 0..7, lane 63 adds sum 8
                     if ((lane & 7) == 0 || lane == kLaneSum8)
-                        unsafeAtomicAdd(a.grad2d + 9 * (int64_t)lds_id[jj] + (lane == kLaneSum8 ? 8 : lane >> 3),
+                        unsafeAtomicAdd(a.grad2d + grad2d_index(lds_id[jj], lane == kLaneSum8 ? 8 : lane >> 3),
                                         lane == kLaneSum8 ? tot8 : tot);
                 } else {
                     // per-wave partial sums to LDS; summed across waves after the batch
@@ -478,7 +489,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                     if (DET)
                         a.grad_pair[9 * (int64_t)(end - 1 - jj) + comp] = sum;
                     else if (sum != 0.f)
-                        unsafeAtomicAdd(a.grad2d + 9 * (int64_t)lds_id[jj] + comp, sum);
+                        unsafeAtomicAdd(a.grad2d + grad2d_index(lds_id[jj], comp), sum);
                 }
                 __syncthreads();
             }
@@ -491,8 +502,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
 // One wave64 per 8 x 8 sub-tile of a 16 x 16 or 32 x 32 tile: the tile's sorted list (and so the
 // key table and its sort) stays at the tile's size, while blending runs at sub-tile size. The wave
 // walks the list in chunks of 64 entries; each lane stages one entry and keeps it only when the
-// entry's footprint box meets the sub-tile; the kept entries are packed in list order into the
-// wave's own LDS (ballot prefix) and blended. Sub-tiles of a tile never wait for each other: there
+// tile key flags the sub-tile (the emission tested the entry's ellipse against it), or, without
+// flags, when the entry's footprint box meets the sub-tile; the kept entries are packed in list
+// order into the wave's own LDS (ballot prefix) and blended. Entries are staged relative to the
+// sub-tile's corner, so each pixel's exponent factors stay within eight pixels of it. Sub-tiles of a tile never wait for each other: there
 // is no workgroup barrier anywhere.
 
 // LDS written by some lanes of a wave and read by others: order the wave's accesses.
@@ -561,7 +574,9 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
         float T = inside ? 1.0f : -1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
         uint32_t last = 0;
         const uint2 rg = a.ranges[q.t];
-        const float px = lx + 0.5f, py = ly + 0.5f;
+        // pixel centre relative to the sub-tile, the frame the entries are staged in
+        const float px = (lane & 7) + 0.5f, py = (lane >> 3) + 0.5f;
+        const double fx0 = (double)(c.x0 + q.sx), fy0 = (double)(c.y0 + q.sy);
         // each chunk's tile keys and record ids are loaded one chunk ahead, while the previous
         // chunk's entries are blended
         uint32_t key_n = 0, id_n = 0;
@@ -581,8 +596,9 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                 g = gid;
                 const bool flagged = !a.tkeys || ((key >> (16 + q.sidx)) & 1u);
                 if (flagged) {
-                    stage(a, g, (double)c.x0, (double)c.y0, &st);
-                    hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
+                    stage(a, g, fx0, fy0, &st);
+                    // the flags already test the ellipse against the sub-tile; without them, its box
+                    hit = a.tkeys ? true : box_meets(st.box, 0, SUB - 1, 0, SUB - 1);
                 }
             }
             const uint64_t m = __ballot(hit);
@@ -606,12 +622,12 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                     const int k = k0 + kk;
                     if (k < nhit) {  // wave-uniform
                         const Kept s = kp[kk];
-                        float dx, dy, G, alpha;
+                        float w1, w2, G, alpha;
                         bool clamped;
                         // a live pixel has T >= kTMin, a terminated one (or one outside the image)
                         // T < 0; this compare, not shared with the termination test above, lets the
                         // wave vote below branch on the lane mask directly
-                        const bool pass = frag(s, px, py, dx, dy, G, alpha, clamped) & (T >= kTMin);
+                        const bool pass = frag(s, px, py, w1, w2, G, alpha, clamped) & (T >= kTMin);
                         if (STATS) n_evaluated += T > 0.0f;
                         if (__any(pass)) {
                             const float Tn = T * (1.0f - alpha);
@@ -701,7 +717,8 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
         for (int d = 32; d >= 1; d >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, d));
         if (wave_last == 0) continue;  // wave-uniform: no pixel of the sub-tile blended anything
         const uint2 rg = a.ranges[q.t];
-        const float px = lx + 0.5f, py = ly + 0.5f;
+        const float px = (lane & 7) + 0.5f, py = (lane >> 3) + 0.5f;  // relative to the sub-tile
+        const double fx0 = (double)(c.x0 + q.sx), fy0 = (double)(c.y0 + q.sy);
         // tile keys and record ids loaded one chunk ahead, as in the forward
         uint32_t key_n = 0, id_n = 0;
         if ((uint32_t)lane < wave_last) {
@@ -721,15 +738,16 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 g = gid;
                 const bool flagged = !a.tkeys || ((key >> (16 + q.sidx)) & 1u);
                 if (flagged) {
-                    stage(a, g, (double)c.x0, (double)c.y0, &st);
-                    hit = box_meets(st.box, q.sx, q.sx + SUB - 1, q.sy, q.sy + SUB - 1);
+                    stage(a, g, fx0, fy0, &st);
+                    // the flags already test the ellipse against the sub-tile; without them, its box
+                    hit = a.tkeys ? true : box_meets(st.box, 0, SUB - 1, 0, SUB - 1);
                 }
             }
             const uint64_t m = __ballot(hit);
             const int nhit = __popcll(m);
             if (hit) {
                 const int slot = lane_rank(m);
-                lds[slot] = Kept{st.p0, st.p1, st.b, idx - rg.x + 1u, 9ull * g};
+                lds[slot] = Kept{st.p0, st.p1, st.b, idx - rg.x + 1u, (uint64_t)grad2d_index(g, 0)};
             }
             if ((uint32_t)lane < beg - rg.x) {  // the next chunk: positions beg - 1 - lane downwards
                 id_n = a.vals[beg - 1u - (uint32_t)lane];
@@ -738,9 +756,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             wave_sync();
             for (int k = 0; k < nhit; ++k) {
                 const Kept s = *kept_at(lds, k);
-                float alpha, G, dx, dy;
+                float alpha, G, w1, w2;
                 bool clamped;
-                const bool incl = frag(s, px, py, dx, dy, G, alpha, clamped) & (s.pos1 <= lst);
+                const bool incl = frag(s, px, py, w1, w2, G, alpha, clamped) & (s.pos1 <= lst);
                 if (!__any(incl)) continue;
                 float acc[9];
                 const float al = incl ? alpha : 0.0f;
@@ -756,11 +774,11 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 T = incl ? Ti : T;
                 const bool live = incl & !clamped;
                 acc[5] = live ? G * dal : 0.0f;  // dL/do_eff; the exponent gradient is o_eff times this
-                acc[0] = acc[5] * dx;
-                acc[1] = acc[5] * dy;
-                acc[2] = acc[0] * dx;
-                acc[3] = acc[0] * dy;
-                acc[4] = acc[1] * dy;
+                acc[0] = acc[5] * w1;
+                acc[1] = acc[5] * w2;
+                acc[2] = acc[0] * w1;
+                acc[3] = acc[0] * w2;
+                acc[4] = acc[1] * w2;
                 float tot, tot8;
                 wave_sum9(acc, tot, tot8);
                 float val = lane == kLaneSum8 ? tot8 : tot;

@@ -17,6 +17,8 @@ constexpr float kTMin = 1e-4f;             // stop before transmittance drops be
 constexpr float kFovClamp = 1.3f;          // Jacobian direction clamp, x half field of view
 constexpr double kMaxCoord = 1e7;          // guard on |u|, |v| and the radius
 constexpr float kLog2e = 1.4426950408889634f;
+// sqrt(log2(e) / 2): the blend's exponent in log2 units is -(w1^2 + w2^2) with w = kQ2 L' d (Shape)
+constexpr float kQ2 = 0.84932180028801904f;
 
 constexpr int kWave = 64;
 
@@ -69,24 +71,48 @@ struct GradDev {
     float* sh;
 };
 
+// The 2D shape of a record. The conic Q = [[a, b], [b, c]] (q = d' Q d for a pixel offset d from the
+// mean) is kept as the factors of Q = L L', L = [[l11, 0], [l11 r, l22]]:
+//   q = (l11 (dx + r dy))^2 + (l22 dy)^2,
+// with l11 = sqrt(C / det), r = -B / C, l22 = 1 / sqrt(C) for the dilated covariance [[A, B], [B, C]] and
+// det = A C - B^2. Both terms are squares, so q never cancels; along a thin footprint the first factor
+// does, and the ratio r is kept in FP64 so that the footprint's direction survives to hundreds of pixels.
+// a = l11^2, b = l11^2 r, c = (l11 r)^2 + l22^2 and a c - b^2 = (l11 l22)^2 follow in FP64.
+struct Shape {
+    double a, b, c, det;
+};
+__device__ __forceinline__ Shape shape_of(float l11, double r, float l22) {
+    Shape s;
+    const double p = (double)l11, q = (double)l22;
+    s.a = p * p;
+    s.b = s.a * r;
+    const double pr = p * r;
+    s.c = pr * pr + q * q;
+    const double pq = p * q;
+    s.det = pq * pq;
+    return s;
+}
+
 // One record in a single 64-byte line, for the consumers that gather records in depth or tile
 // order (key emission, blend staging): one line per gathered record instead of one per plane.
 struct __align__(64) PackedRec {
     double2 mean;     // pixel-space mean
-    float4 conic_o;   // conic a, b, c and effective opacity
-    float4 rgbk;      // colour and the cutoff level k of the footprint ellipse
+    double r;         // the conic's factor ratio (Shape)
+    float l11, l22;   // the conic's diagonal factors (Shape)
+    float o;          // effective opacity
+    float rgb[3];     // colour
+    float rx, ry;     // half-extents of the cutoff ellipse in x and y (widened; see the projection)
     int32_t radius;   // -1 when culled
     uint32_t ntiles;
-    float rx, ry;     // half-extents of the cutoff ellipse in x and y (widened; see the projection)
 };
 static_assert(sizeof(PackedRec) == 64, "one record per 64-byte line");
 
 // Record planes written by the projection (record r = view * n + i).
 struct Records {
     PackedRec* packed;  // the same records, one line each
-    // per-field planes (null unless MEGS_FLAG_RECORD_PLANES): mean .. radius, cutoff
+    // per-field planes (null unless MEGS_FLAG_RECORD_PLANES): mean .. radius, cutoff, chol
     double2* mean;      // pixel-space mean
-    float4* conic_o;    // conic a, b, c and effective opacity
+    float4* conic_o;    // conic a, b, c (FP32 roundings of the factors' products) and effective opacity
     float4* rgbd;       // colour and camera depth
     int32_t* radius;    // -1 when culled
     uint32_t* ntiles;   // tiles of the rectangle the footprint ellipse reaches
@@ -96,7 +122,14 @@ struct Records {
     uint32_t* order0;
     int32_t order_idb;
     float* cutoff;      // k of the footprint ellipse q(d) = d' conic d <= k (with margin)
+    double4* chol;      // the conic's factors as the blend uses them: l11, r, l22, 0
 };
+
+// Ellipse level that bounds every pixel with alpha >= 1/255: q <= 2 ln(255 o), widened by 0.2% (and
+// 1e-4 absolute) so that FP32 rounding in the blend never reaches past a culled tile.
+__device__ __forceinline__ float cutoff_of(float o_eff) {
+    return 2.004f * __logf(255.0f * o_eff) + 1e-4f;
+}
 
 __device__ __forceinline__ float load_elem(const void* p, int dt, int64_t idx) {
     if (dt == MEGS_F32) return static_cast<const float*>(p)[idx];
@@ -182,16 +215,15 @@ struct EllipseRows {
     bool full;  // degenerate conic: list the whole rectangle
 };
 
-__device__ __forceinline__ void ellipse_rows(double u, double v, double a, double b, double c, double k,
-                                             EllipseRows& e) {
-    e.u = u; e.v = v; e.b = b;
-    e.det = a * c - b * b;
-    e.full = !(e.det > 0.0) || !(a > 0.0) || !(k > 0.0);
-    const double sxx = c / e.det, syy = a / e.det, sxy = -b / e.det;
+__device__ __forceinline__ void ellipse_rows(double u, double v, const Shape& q, double k, EllipseRows& e) {
+    e.u = u; e.v = v; e.b = q.b;
+    e.det = q.det;
+    e.full = !(e.det > 0.0) || !(q.a > 0.0) || !(k > 0.0);
+    const double sxx = q.c / e.det, syy = q.a / e.det, sxy = -q.b / e.det;
     e.ry = sqrt(k * syy);
     e.dys = sxy * sqrt(k / sxx);
-    e.ia = 1.0 / a;
-    e.ka = k * a;
+    e.ia = 1.0 / q.a;
+    e.ka = k * q.a;
 }
 
 // Columns [lo, hi] of tile row ty listed for the record (within the rectangle columns [x0, x1]);
@@ -229,6 +261,11 @@ __device__ __forceinline__ bool row_span(const EllipseRows& e, int width, int he
     return true;
 }
 
+// Element comp (0..8) of record r in the backward's per-record sums: nine consecutive floats per
+// record, the six exponent sums then the colour gradient (the blend's nine-lane atomic adds to one
+// contiguous run; the projection backward's two passes each read their part of it).
+__device__ __forceinline__ int64_t grad2d_index(int64_t r, int comp) { return 9 * r + comp; }
+
 // View of a global tile id: linear scan of the (few) view tile offsets.
 __device__ __forceinline__ int view_of_tile(const ViewInfo* views, int nv, int64_t t) {
     int v = 0;
@@ -249,8 +286,9 @@ struct StageTimer {
 
 hipError_t launch_project(const SceneDev& sc, const ViewInfo* views, int nv, int tile, const Records& rec,
                           hipStream_t stream);
+// rec: the forward's records (the backward reads each record's conic factors from them)
 hipError_t launch_project_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d,
-                              const GradDev& g, hipStream_t stream);
+                              const PackedRec* rec, const GradDev& g, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t stream);
 hipError_t launch_iota(uint32_t* p, int64_t count, hipStream_t stream);
@@ -305,9 +343,10 @@ struct BlendArgs {
     float* T_final;
     uint32_t* last;
     const float* dl;      // backward only
-    float* grad2d;        // backward only, [NR][9]: sums over the record's fragments of e dx, e dy,
-                          // e dx^2, e dx dy, e dy^2 and e (e = dL/do_eff of an unclamped fragment;
-                          // its exponent gradient is o_eff e), then dL/dRGB
+    float* grad2d;        // backward only, [NR][9] (grad2d_index): sums over the record's fragments
+                          // of e w1, e w2, e w1^2, e w1 w2, e w2^2 and e (e = dL/do_eff of an unclamped
+                          // fragment, whose exponent gradient is o_eff e; w1, w2 the exponent's
+                          // factors kQ2 L' d of the pixel offset d, Shape), then dL/dRGB
     float* grad_pair;     // deterministic backward: per list position [P][9] (null: atomics into grad2d)
     uint32_t* queue;      // persistent mode work counter (null: one workgroup per tile)
     unsigned long long* stats;  // forward fragment counters [blended, evaluated] (null: not counted)

@@ -72,6 +72,27 @@ __device__ __forceinline__ void load_geo(const SceneDev& sc, int64_t i, float po
     g.o_eff = g.o * g.mp;
 }
 
+// The 3D covariance's factor M = R(q) diag(s) (Sigma3 = M M'), from which each view projects the
+// footprint's shape in FP64: a thin footprint's direction and width must survive the subtraction
+// that forms its determinant. Kept across the view loop as the normalised quaternion (FP64) and the
+// scales; each view forms the columns of M one at a time (cheaper in registers than holding M).
+struct Cov64 {
+    double w, x, y, z;
+    float s[3];
+};
+
+__device__ __forceinline__ void load_cov64(const SceneDev& sc, int64_t i, Cov64& cv) {
+    const int64_t n = sc.n;
+    double q[4], qq = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        q[j] = (double)load_elem(sc.quat, sc.dt_geom, j * n + i);
+        qq = fma(q[j], q[j], qq);
+    }
+    const double inv = 1.0 / sqrt(qq);
+    cv.w = q[0] * inv; cv.x = q[1] * inv; cv.y = q[2] * inv; cv.z = q[3] * inv;
+    for (int j = 0; j < 3; ++j) cv.s[j] = __expf(load_elem(sc.logscale, sc.dt_geom, j * n + i));
+}
+
 // Lobe slots at or past the Gaussian's count get zero mask and amplitude, so they add exactly +0.
 template <int K, bool RAGGED>
 __device__ __forceinline__ bool load_lobes(const SceneDev& sc, const LobeRef<RAGGED>& r, Lobes<K>& L) {
@@ -108,13 +129,19 @@ struct ViewProj {
     double tx, ty, tz, u, v;
     float txf, tyf, tzf, xi, eta;
     bool xclamp, yclamp;
-    float T0[3], T1[3];
-    float A0, B0, C0, det0, det;
-    float conic[3];
+    float T0[3], T1[3];   // rows of J W (FP32 copies for the backward's chain rule)
+    double A, B, C, det;  // dilated 2D covariance [[A, B], [B, C]] and its determinant
+    float l11, l22;       // the conic's factors as stored (Shape)
+    double r;
     int32_t radius;
 };
 
-__device__ __forceinline__ void project_view(const Geo& g, const float pos[3], const ViewInfo& vw, ViewProj& p) {
+// Camera-space position, pixel mean, the Jacobian's clamp decisions (FP64) and the rows T0, T1 of
+// J W: in FP64 for the forward's covariance (T64), and as FP32 copies, which are all the backward's
+// chain rule needs. Shared by the forward and the backward, so both take the same decisions.
+template <bool T64>
+__device__ __forceinline__ void project_cam(const Geo& g, const float pos[3], const ViewInfo& vw, ViewProj& p,
+                                            double T0[3], double T1[3]) {
     p.ok = g.ok;
     const double px = pos[0], py = pos[1], pz = pos[2];
     p.tx = fma((double)vw.R[0], px, fma((double)vw.R[1], py, fma((double)vw.R[2], pz, (double)vw.t[0])));
@@ -126,45 +153,79 @@ __device__ __forceinline__ void project_view(const Geo& g, const float pos[3], c
     p.u = fma((double)vw.fx * p.tx, rz, (double)vw.cx);
     p.v = fma((double)vw.fy * p.ty, rz, (double)vw.cy);
     p.txf = (float)p.tx; p.tyf = (float)p.ty; p.tzf = (float)p.tz;
-    float rx = (float)(p.tx * rz), ry = (float)(p.ty * rz);
-    p.xclamp = rx < -vw.limx || rx > vw.limx;
-    p.yclamp = ry < -vw.limy || ry > vw.limy;
-    p.xi = fminf(fmaxf(rx, -vw.limx), vw.limx);
-    p.eta = fminf(fmaxf(ry, -vw.limy), vw.limy);
-    const float irz = 1.0f / p.tzf;
-    const float J00 = vw.fx * irz, J02 = -vw.fx * p.xi * irz;
-    const float J11 = vw.fy * irz, J12 = -vw.fy * p.eta * irz;
-    // T = J W: row 0 = J00 W0 + J02 W2, row 1 = J11 W1 + J12 W2
-    for (int c = 0; c < 3; ++c) {
-        p.T0[c] = J00 * vw.R[c] + J02 * vw.R[6 + c];
-        p.T1[c] = J11 * vw.R[3 + c] + J12 * vw.R[6 + c];
+    const double rx = p.tx * rz, ry = p.ty * rz, limx = vw.limx, limy = vw.limy;
+    p.xclamp = rx < -limx || rx > limx;
+    p.yclamp = ry < -limy || ry > limy;
+    const double xi = fmin(fmax(rx, -limx), limx), eta = fmin(fmax(ry, -limy), limy);
+    p.xi = (float)xi;
+    p.eta = (float)eta;
+    if constexpr (T64) {
+        const double J00 = vw.fx * rz, J02 = -vw.fx * xi * rz;
+        const double J11 = vw.fy * rz, J12 = -vw.fy * eta * rz;
+        // T = J W: row 0 = J00 W0 + J02 W2, row 1 = J11 W1 + J12 W2
+        for (int c = 0; c < 3; ++c) {
+            T0[c] = fma(J00, (double)vw.R[c], J02 * vw.R[6 + c]);
+            T1[c] = fma(J11, (double)vw.R[3 + c], J12 * vw.R[6 + c]);
+            p.T0[c] = (float)T0[c];
+            p.T1[c] = (float)T1[c];
+        }
+    } else {
+        const float irz = 1.0f / p.tzf;
+        const float J00 = vw.fx * irz, J02 = -vw.fx * p.xi * irz;
+        const float J11 = vw.fy * irz, J12 = -vw.fy * p.eta * irz;
+        for (int c = 0; c < 3; ++c) {
+            p.T0[c] = J00 * vw.R[c] + J02 * vw.R[6 + c];
+            p.T1[c] = J11 * vw.R[3 + c] + J12 * vw.R[6 + c];
+        }
     }
-    // S3 * T0 and S3 * T1
-    const float* S = g.S3;
-    float s0[3] = {S[0] * p.T0[0] + S[1] * p.T0[1] + S[2] * p.T0[2],
-                   S[1] * p.T0[0] + S[3] * p.T0[1] + S[4] * p.T0[2],
-                   S[2] * p.T0[0] + S[4] * p.T0[1] + S[5] * p.T0[2]};
-    float s1[3] = {S[0] * p.T1[0] + S[1] * p.T1[1] + S[2] * p.T1[2],
-                   S[1] * p.T1[0] + S[3] * p.T1[1] + S[4] * p.T1[2],
-                   S[2] * p.T1[0] + S[4] * p.T1[1] + S[5] * p.T1[2]};
-    p.A0 = p.T0[0] * s0[0] + p.T0[1] * s0[1] + p.T0[2] * s0[2];
-    p.B0 = p.T0[0] * s1[0] + p.T0[1] * s1[1] + p.T0[2] * s1[2];
-    p.C0 = p.T1[0] * s1[0] + p.T1[1] * s1[1] + p.T1[2] * s1[2];
-    p.det0 = p.A0 * p.C0 - p.B0 * p.B0;
-    p.det = fmaxf(p.det0, 0.0f) + kDilation * (p.A0 + p.C0) + kDilation * kDilation;
-    const float A = p.A0 + kDilation, C = p.C0 + kDilation;
-    const float idet = 1.0f / p.det;
-    p.conic[0] = C * idet;
-    p.conic[1] = -p.B0 * idet;
-    p.conic[2] = A * idet;
-    const float mid = 0.5f * (A + C);
-    const float lmax = mid + sqrtf(fmaxf(mid * mid - p.det, 0.0f));
+}
+
+// The forward's projection: project_cam, then the dilated 2D covariance in FP64,
+// Sigma2 = (J W M)(J W M)' + h I, formed from the projected scaled axes J W M (so it is positive
+// semi-definite before the dilation), det = A C - B^2 >= h^2, its factors (Shape), and the radius.
+__device__ __forceinline__ void project_view(const Geo& g, const Cov64& cv, const float pos[3],
+                                             const ViewInfo& vw, ViewProj& p) {
+    double T0[3], T1[3];
+    project_cam<true>(g, pos, vw, p, T0, T1);
+    // the projected scaled axes, column c of T M = (T e_c) s_c with e_c column c of R(q), one at a time
+    const double w = cv.w, x = cv.x, y = cv.y, z = cv.z;
+    double A0 = 0.0, B0 = 0.0, C0 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double e0, e1, e2;
+        if (c == 0) {
+            e0 = 1.0 - 2.0 * (y * y + z * z); e1 = 2.0 * (x * y + w * z); e2 = 2.0 * (x * z - w * y);
+        } else if (c == 1) {
+            e0 = 2.0 * (x * y - w * z); e1 = 1.0 - 2.0 * (x * x + z * z); e2 = 2.0 * (y * z + w * x);
+        } else {
+            e0 = 2.0 * (x * z + w * y); e1 = 2.0 * (y * z - w * x); e2 = 1.0 - 2.0 * (x * x + y * y);
+        }
+        const double sc = cv.s[c];
+        const double p0 = fma(T0[0], e0, fma(T0[1], e1, T0[2] * e2)) * sc;
+        const double p1 = fma(T1[0], e0, fma(T1[1], e1, T1[2] * e2)) * sc;
+        A0 = fma(p0, p0, A0);
+        B0 = fma(p0, p1, B0);
+        C0 = fma(p1, p1, C0);
+    }
+    p.A = A0 + (double)kDilation;
+    p.B = B0;
+    p.C = C0 + (double)kDilation;
+    p.det = fma(p.A, p.C, -p.B * p.B);
+    // only the ratio needs FP64 (it carries the footprint's direction); the diagonal factors are
+    // stored in FP32 and formed there, from the FP64 covariance rounded once
+    p.r = -p.B / p.C;
+    const float Cf = (float)p.C, detf = (float)p.det;
+    p.l11 = __builtin_amdgcn_sqrtf(Cf / detf);
+    p.l22 = __builtin_amdgcn_rsqf(Cf);
+    const float Af = (float)p.A;
+    const float mid = 0.5f * (Af + Cf);
+    const float lmax = mid + sqrtf(fmaxf(mid * mid - detf, 0.0f));
     const float rho = sqrtf(2.0f * __logf(255.0f * g.o_eff) * lmax);
-    const float r = ceilf(rho);
-    if (!(isfinite(p.u) && isfinite(p.v) && isfinite(r)) || fabs(p.u) > kMaxCoord || fabs(p.v) > kMaxCoord ||
-        r > (float)kMaxCoord)
+    const float rr = ceilf(rho);
+    if (!(isfinite(p.u) && isfinite(p.v) && isfinite(rr)) || fabs(p.u) > kMaxCoord || fabs(p.v) > kMaxCoord ||
+        rr > (float)kMaxCoord)
         p.ok = false;
-    p.radius = p.ok ? (int32_t)r : -1;
+    p.radius = p.ok ? (int32_t)rr : -1;
 }
 
 // d = (mu - campos) / |mu - campos|, the viewing direction (from the camera to the Gaussian).
@@ -289,12 +350,6 @@ __device__ __forceinline__ bool sh_colour(const SceneDev& sc, int64_t i, const f
     return isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
 }
 
-// Ellipse level that bounds every pixel with alpha >= 1/255: q <= 2 ln(255 o), widened by 0.2% (and
-// 1e-4 absolute) so that FP32 rounding in the blend never reaches past a culled tile.
-__device__ __forceinline__ float cutoff_of(float o_eff) {
-    return 2.004f * __logf(255.0f * o_eff) + 1e-4f;
-}
-
 template <int K, bool RAGGED, int SHD>
 __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __restrict__ views, int nv, int tile,
                                                  Records rec) {
@@ -303,16 +358,24 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
     float pos[3];
     Geo g;
     load_geo(sc, i, pos, g);
+    Cov64 cv;
+    load_cov64(sc, i, cv);
     Lobes<K> L;
     LobeRef<RAGGED> lr;
     const bool lobes_ok = lobe_ref<RAGGED>(sc, i, K, lr) && load_lobes<K, RAGGED>(sc, lr, L);
+    // the forward needs each lobe's mask only as a factor of its amplitude: fold it in once
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+        for (int c = 0; c < 3; ++c) L.amp[l][c] *= L.m[l];
+        L.m[l] = 1.0f;
+    }
     float base[3] = {0.f, 0.f, 0.f};
     if constexpr (SHD < 0) load_base(sc, i, base);
     for (int v = 0; v < nv; ++v) {
         const ViewInfo& vw = views[v];
         const int64_t r = (int64_t)v * sc.n + i;
         ViewProj p;
-        project_view(g, pos, vw, p);
+        project_view(g, cv, pos, vw, p);
         float d[3], dlen, rgb[3], e[K > 0 ? K : 1], muh[K > 0 ? K : 1][3], dd2[K > 0 ? K : 1];
         bool ok = p.ok && lobes_ok;
         if (ok) {
@@ -323,59 +386,54 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
                 ok = sg_colour<K>(base, pos, vw, L, d, dlen, rgb, e, muh, dd2);
             }
         }
+        const float cut = cutoff_of(g.o_eff);
+        // the conic the stored factors describe: the key emission and the blend read exactly these
+        const Shape shp = shape_of(p.l11, p.r, p.l22);
+        if (rec.mean) {  // per-field planes, on request only
+            rec.mean[r] = ok ? make_double2(p.u, p.v) : make_double2(0.0, 0.0);
+            rec.conic_o[r] = ok ? make_float4((float)shp.a, (float)shp.b, (float)shp.c, g.o_eff)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+            rec.rgbd[r] = ok ? make_float4(rgb[0], rgb[1], rgb[2], p.tzf) : make_float4(0.f, 0.f, 0.f, 0.f);
+            rec.radius[r] = ok ? p.radius : -1;
+            rec.cutoff[r] = ok ? cut : 0.f;
+            rec.chol[r] = ok ? make_double4((double)p.l11, p.r, (double)p.l22, 0.0) : make_double4(0.0, 0.0, 0.0, 0.0);
+        }
+        // the packed line, written in two parts: the record's values now, the tile count after the
+        // row loop below (fewer values live through it)
+        float4* dst = reinterpret_cast<float4*>(rec.packed + r);
+        {
+            PackedRec pr;
+            pr.mean = ok ? make_double2(p.u, p.v) : make_double2(0.0, 0.0);
+            pr.r = ok ? p.r : 0.0;
+            pr.l11 = ok ? p.l11 : 0.f;
+            pr.l22 = ok ? p.l22 : 0.f;
+            pr.o = ok ? g.o_eff : 0.f;
+            pr.rgb[0] = ok ? rgb[0] : 0.f;
+            pr.rgb[1] = ok ? rgb[1] : 0.f;
+            pr.rgb[2] = ok ? rgb[2] : 0.f;
+            const float4* src = reinterpret_cast<const float4*>(&pr);
+            dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2];
+        }
+        // the half-extents of the cutoff ellipse {q <= k} are sqrt(k A) and sqrt(k C) for the dilated
+        // covariance (A, C its diagonal), widened by 1e-3 relative and 1e-2 px, far more than FP32
+        // rounding of the stored factors moves the blend's ellipse: every pixel with alpha >= 1/255
+        // lies inside the box
+        const float rx = ok ? __builtin_amdgcn_sqrtf(cut * (float)p.A) * 1.001f + 0.01f : 0.f;
+        const float ry = ok ? __builtin_amdgcn_sqrtf(cut * (float)p.C) * 1.001f + 0.01f : 0.f;
         uint32_t nt = 0;
         if (ok) {
             int x0, x1, y0, y1;
-            const float cut = cutoff_of(g.o_eff);
             if (tile_rect(p.u, p.v, p.radius, vw, tile, x0, x1, y0, y1)) {
                 EllipseRows er;
-                ellipse_rows(p.u, p.v, p.conic[0], p.conic[1], p.conic[2], cut, er);
+                ellipse_rows(p.u, p.v, shp, cut, er);
                 for (int ty = y0; ty <= y1; ++ty) {
                     int lo, hi;
                     if (row_span(er, vw.width, vw.height, tile, ty, x0, x1, lo, hi)) nt += (uint32_t)(hi - lo + 1);
                 }
             }
-            if (rec.mean) {  // per-field planes, on request only
-                rec.mean[r] = make_double2(p.u, p.v);
-                rec.conic_o[r] = make_float4(p.conic[0], p.conic[1], p.conic[2], g.o_eff);
-                rec.rgbd[r] = make_float4(rgb[0], rgb[1], rgb[2], p.tzf);
-                rec.radius[r] = p.radius;
-                rec.cutoff[r] = cut;
-            }
-        } else if (rec.mean) {
-            rec.mean[r] = make_double2(0.0, 0.0);
-            rec.conic_o[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec.rgbd[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec.radius[r] = -1;
-            rec.cutoff[r] = 0.f;
         }
         rec.ntiles[r] = nt;
-        {
-            // packed copy; the half-extents of the cutoff ellipse {q <= k} are sqrt(k S_xx) and
-            // sqrt(k S_yy) with S_xx = c / (a c - b^2), S_yy = a / (a c - b^2), the FP32 conic's
-            // determinant taken in FP64 (products of FP32 values are exact there, so thin ellipses
-            // keep their extent) and rounded once to FP32; the rest in FP32 with the hardware
-            // reciprocal and square root (about 1 ulp each), far inside the widening by 1e-3
-            // relative and 1e-2 px: every pixel with alpha >= 1/255 lies inside the box
-            float rx = 0.f, ry = 0.f;
-            if (ok) {
-                const double detd = (double)p.conic[0] * p.conic[2] - (double)p.conic[1] * p.conic[1];
-                const float kd = cutoff_of(g.o_eff) * __builtin_amdgcn_rcpf((float)detd);
-                rx = detd > 0.0 ? __builtin_amdgcn_sqrtf(kd * p.conic[2]) * 1.001f + 0.01f : 1e30f;
-                ry = detd > 0.0 ? __builtin_amdgcn_sqrtf(kd * p.conic[0]) * 1.001f + 0.01f : 1e30f;
-            }
-            PackedRec pr;
-            pr.mean = ok ? make_double2(p.u, p.v) : make_double2(0.0, 0.0);
-            pr.conic_o = ok ? make_float4(p.conic[0], p.conic[1], p.conic[2], g.o_eff) : make_float4(0.f, 0.f, 0.f, 0.f);
-            pr.rgbk = ok ? make_float4(rgb[0], rgb[1], rgb[2], cutoff_of(g.o_eff)) : make_float4(0.f, 0.f, 0.f, 0.f);
-            pr.radius = ok ? p.radius : -1;
-            pr.ntiles = nt;
-            pr.rx = rx;
-            pr.ry = ry;
-            float4* dst = reinterpret_cast<float4*>(rec.packed + r);
-            const float4* src = reinterpret_cast<const float4*>(&pr);
-            dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];
-        }
+        dst[3] = make_float4(rx, ry, __int_as_float(ok ? p.radius : -1), __uint_as_float(nt));
         rec.dkey[r] = nt ? __float_as_uint(p.tzf) : 0xffffffffu;
         if (rec.order0) {
             const uint32_t cap = (1u << (32 - rec.order_idb)) - 1u;
@@ -395,9 +453,18 @@ __device__ __forceinline__ void quat_grad(const float q[4], const float gR[9], f
     gq[3] = 2.f * (w * (gR[3] - gR[1]) + x * (gR[2] + gR[6]) + y * (gR[5] + gR[7])) - 4.f * z * (gR[0] + gR[4]);
 }
 
+// The backward runs in two passes over the Gaussians, each looping over the views: the colour pass
+// (the colour model's parameters and the colour's share of the position gradient) and then the
+// geometry pass (position, scales, rotation, opacity and mask), which adds its share of the position
+// gradient to the colour pass's. Each pass keeps only its own state in registers through the view
+// loop, and reads its part of the per-record sums the blend leaves ([NR][9]: the six exponent sums,
+// then the colour gradient).
+
+// Colour pass. A record whose colour gradient is exactly zero contributes nothing here (every term is
+// proportional to it) and is skipped; among them are all records the forward culled.
 template <int K, bool RAGGED, int SHD>
-__device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewInfo* __restrict__ views, int nv,
-                                                const float* __restrict__ grad2d, const GradDev& G) {
+__device__ __forceinline__ void project_bwd_colour(const SceneDev& sc, const ViewInfo* __restrict__ views, int nv,
+                                                   const float* __restrict__ sums_col, const GradDev& G) {
     constexpr int SHM = SHD >= 0 ? (SHD + 1) * (SHD + 1) : 1;
     float gsh[SHM][3];
 #pragma unroll
@@ -406,16 +473,13 @@ __device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewIn
     if (i >= sc.n) return;
     const int64_t n = sc.n;
     float pos[3];
-    Geo g;
-    load_geo(sc, i, pos, g);
+    for (int j = 0; j < 3; ++j) pos[j] = load_elem(sc.pos, sc.dt_geom, j * n + i);
     Lobes<K> L;
     LobeRef<RAGGED> lr;
     const bool lobes_ok = lobe_ref<RAGGED>(sc, i, K, lr) && load_lobes<K, RAGGED>(sc, lr, L);
     float base[3] = {0.f, 0.f, 0.f};
     if constexpr (SHD < 0) load_base(sc, i, base);
-
-    float gpos[3] = {0.f, 0.f, 0.f}, gS3[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float gop = 0.f, gpm = 0.f, gbase[3] = {0.f, 0.f, 0.f};
+    float gpos[3] = {0.f, 0.f, 0.f}, gbase[3] = {0.f, 0.f, 0.f};
     constexpr int KK = K > 0 ? K : 1;
     float gax[KK][3], glam[KK], gamp[KK][3], glm[KK];
 #pragma unroll
@@ -424,36 +488,17 @@ __device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewIn
         glam[l] = 0.f; glm[l] = 0.f;
         gamp[l][0] = gamp[l][1] = gamp[l][2] = 0.f;
     }
-
-    for (int v = 0; v < nv; ++v) {
+    for (int v = 0; v < nv && lobes_ok; ++v) {
         const ViewInfo& vw = views[v];
         const int64_t r = (int64_t)v * n + i;
-        ViewProj p;
-        project_view(g, pos, vw, p);
+        const float gcol[3] = {sums_col[9 * r], sums_col[9 * r + 1], sums_col[9 * r + 2]};
+        if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
         float d[3], dlen, rgb[3], e[KK], muh[KK][3], dd2[KK];
         bool clamped[3] = {false, false, false};
-        bool ok = p.ok && lobes_ok;
-        if (ok) {
-            if constexpr (SHD >= 0)
-                ok = sh_colour<SHD>(sc, i, pos, vw, d, dlen, rgb, clamped);
-            else
-                ok = sg_colour<K>(base, pos, vw, L, d, dlen, rgb, e, muh, dd2);
-        }
-        if (!ok) continue;
-        // The blend leaves, over the record's fragments, e = dL/do_eff per fragment (unclamped ones;
-        // go below is their sum) and the moments sum e dx, e dy, e dx^2, e dx dy, e dy^2, (dx, dy)
-        // the pixel offset from the mean. The exponent q = -(a dx^2 + 2 b dx dy + c dy^2) / 2 has
-        // dL/dq = o_eff e, so the gradients of the pixel mean and of the conic (a, b, c) follow here,
-        // once per record.
-        const float* gr = grad2d + 9 * r;
-        const float oe = g.o_eff;
-        const float m0 = oe * gr[0], m1 = oe * gr[1];
-        const float gu = p.conic[0] * m0 + p.conic[1] * m1;
-        const float gv = p.conic[1] * m0 + p.conic[2] * m1;
-        const float ga = -0.5f * oe * gr[2], gb = -oe * gr[3], gc = -0.5f * oe * gr[4], go = gr[5];
-        const float gcol[3] = {gr[6], gr[7], gr[8]};
-
-        // colour
+        if constexpr (SHD >= 0)
+            sh_colour<SHD>(sc, i, pos, vw, d, dlen, rgb, clamped);
+        else
+            sg_colour<K>(base, pos, vw, L, d, dlen, rgb, e, muh, dd2);
         float gd[3] = {0.f, 0.f, 0.f};
         if constexpr (SHD >= 0) {
             float Y[16], dY[16][3];
@@ -493,32 +538,117 @@ __device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewIn
             const float il = 1.0f / dlen;
             for (int c = 0; c < 3; ++c) gpos[c] += (gd[c] - d[c] * dg) * il;
         }
+    }
+    // the colour's share of the position gradient; the geometry pass adds its own
+    for (int c = 0; c < 3; ++c) G.pos[c * n + i] = gpos[c];
+    if constexpr (SHD >= 0) {
+#pragma unroll
+        for (int m = 0; m < SHM; ++m)
+            for (int c = 0; c < 3; ++c) G.sh[((int64_t)m * 3 + c) * n + i] = gsh[m][c];
+        return;
+    }
+    for (int c = 0; c < 3; ++c) G.base[c * n + i] = gbase[c];
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+        if (RAGGED && l >= lr.cnt) break;
+        for (int c = 0; c < 3; ++c) G.axis[lr.at3(l, c)] = gax[l][c];
+        G.sharp[lr.at1(l)] = glam[l];
+        for (int c = 0; c < 3; ++c) G.amp[lr.at3(l, c)] = gamp[l][c];
+        if (G.lmask_logit) G.lmask_logit[lr.at1(l)] = glm[l];
+    }
+}
+
+// Geometry pass: the exponent sums to the pixel mean and the dilated covariance, then through the
+// projection to the position, scales, rotation, opacity and mask. Records the forward culled (zero
+// factors in the record) are skipped.
+__device__ __forceinline__ void project_bwd_geometry(const SceneDev& sc, const ViewInfo* __restrict__ views, int nv,
+                                                     const float* __restrict__ sums_exp,
+                                                     const PackedRec* __restrict__ rec, const GradDev& G) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.n) return;
+    const int64_t n = sc.n;
+    float pos[3];
+    Geo g;
+    load_geo(sc, i, pos, g);
+    Cov64 cv;
+    load_cov64(sc, i, cv);
+    // H = R' (dL/dSigma3) R, the 3D covariance's gradient in the Gaussian's own axes (xx, xy, xz, yy,
+    // yz, zz; full-matrix convention)
+    float gpos[3] = {0.f, 0.f, 0.f}, H[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float gop = 0.f, gpm = 0.f;
+    for (int v = 0; v < nv; ++v) {
+        const ViewInfo& vw = views[v];
+        const int64_t r = (int64_t)v * n + i;
+        // the record's conic factors as the forward stored them (zero when the forward culled it)
+        const float4 fq = reinterpret_cast<const float4*>(rec + r)[1];
+        if (!(fq.w > 0.0f)) continue;
+        ViewProj p;
+        double T0d[3], T1d[3];
+        project_cam<true>(g, pos, vw, p, T0d, T1d);
+        const float l11 = fq.z, l22 = fq.w;
+        const double l21d = (double)l11 * __hiloint2double(__float_as_int(fq.y), __float_as_int(fq.x));
+        const float l21 = (float)l21d;
+        // The blend leaves, over the record's fragments, e = dL/do_eff of each unclamped fragment and
+        // the moments S = sum e w, M = sum e w w' (w1^2, w1 w2, w2^2), then sum e (= dL/do_eff), with
+        // w = kQ2 L' d the exponent's factors of the pixel offset d from the mean (conic Q = L L',
+        // L = [[l11, 0], [l21, l22]], l21 = l11 r; the exponent is -d' Q d / 2). A fragment's alpha
+        // o exp(-d' Q d / 2) has gradient alpha Q d in the mean and (alpha / 2) (Q d)(Q d)' in the
+        // dilated covariance Sigma = Q^-1 (from dQ = -Q dSigma Q), and Q d = L w / kQ2, so per record
+        //   dL/dmean = (o_eff / kQ2) L S,  dL/dSigma = (o_eff / (2 kQ2^2)) L M L',
+        // products of the factors only: no inverse, no determinant, nothing that cancels for a thin
+        // footprint.
+        const float* gr = sums_exp + 9 * r;
+        const float oe = g.o_eff;
+        const float s1 = oe * (1.0f / kQ2), s2 = oe * (0.5f / (kQ2 * kQ2));
+        const float gu = s1 * (l11 * gr[0]);
+        const float gv = s1 * __fmaf_rn(l21, gr[0], l22 * gr[1]);
+        const float t1 = __fmaf_rn(l21, gr[2], l22 * gr[3]);  // sum e w1 (L w)_2
+        const float t2 = __fmaf_rn(l21, gr[3], l22 * gr[4]);  // sum e w2 (L w)_2
+        const float gA0 = s2 * (l11 * l11 * gr[2]);
+        const float gB0 = 2.0f * s2 * (l11 * t1);
+        const float gC0 = s2 * __fmaf_rn(l21, t1, l22 * t2);
+        const float go = gr[5];
         // opacity and primitive mask
         gop += go * g.mp * g.o * (1.f - g.o);
         gpm += go * g.o * g.mp * (1.f - g.mp);
-
-        // conic = (C, -B, A) / det, A = A0 + h, C = C0 + h
-        const float A = p.A0 + kDilation, C = p.C0 + kDilation, B = p.B0;
-        const float idet = 1.0f / p.det;
-        const float gdet = -(ga * C - gb * B + gc * A) * idet * idet;
-        float gA0 = gc * idet, gC0 = ga * idet, gB0 = -gb * idet;
-        if (p.det0 > 0.f) {
-            gA0 += gdet * C;
-            gC0 += gdet * A;
-            gB0 -= 2.f * B * gdet;
-        } else {
-            gA0 += gdet * kDilation;
-            gC0 += gdet * kDilation;
+        // Sigma3's gradient in the Gaussian's axes: with p_c = T R e_c the projected axis c,
+        // H_ij += p_i' (dL/dSigma) p_j = s2 q_i' M q_j, q_c = L' p_c. Along a thin footprint the first
+        // component of q_c cancels (that is the footprint's direction), so q_c is formed in FP64 from
+        // FP64 axes; summing in the axes' frame keeps each axis's own term, which a world-frame sum
+        // would bury under the others.
+        {
+            const double w = cv.w, x = cv.x, y = cv.y, z = cv.z;
+            float qv[3][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double e0, e1, e2;
+                if (c == 0) {
+                    e0 = 1.0 - 2.0 * (y * y + z * z); e1 = 2.0 * (x * y + w * z); e2 = 2.0 * (x * z - w * y);
+                } else if (c == 1) {
+                    e0 = 2.0 * (x * y - w * z); e1 = 1.0 - 2.0 * (x * x + z * z); e2 = 2.0 * (y * z + w * x);
+                } else {
+                    e0 = 2.0 * (x * z + w * y); e1 = 2.0 * (y * z - w * x); e2 = 1.0 - 2.0 * (x * x + y * y);
+                }
+                const double p0 = fma(T0d[0], e0, fma(T0d[1], e1, T0d[2] * e2));
+                const double p1 = fma(T1d[0], e0, fma(T1d[1], e1, T1d[2] * e2));
+                qv[c][0] = (float)fma((double)l11, p0, l21d * p1);
+                qv[c][1] = (float)((double)l22 * p1);
+            }
+            float mq[3][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                mq[c][0] = __fmaf_rn(gr[2], qv[c][0], gr[3] * qv[c][1]);
+                mq[c][1] = __fmaf_rn(gr[3], qv[c][0], gr[4] * qv[c][1]);
+            }
+            H[0] += s2 * __fmaf_rn(qv[0][0], mq[0][0], qv[0][1] * mq[0][1]);
+            H[1] += s2 * __fmaf_rn(qv[0][0], mq[1][0], qv[0][1] * mq[1][1]);
+            H[2] += s2 * __fmaf_rn(qv[0][0], mq[2][0], qv[0][1] * mq[2][1]);
+            H[3] += s2 * __fmaf_rn(qv[1][0], mq[1][0], qv[1][1] * mq[1][1]);
+            H[4] += s2 * __fmaf_rn(qv[1][0], mq[2][0], qv[1][1] * mq[2][1]);
+            H[5] += s2 * __fmaf_rn(qv[2][0], mq[2][0], qv[2][1] * mq[2][1]);
         }
-        // Sigma2 entries A0 = T0 S T0', B0 = T0 S T1', C0 = T1 S T1'
         const float* T0 = p.T0;
         const float* T1 = p.T1;
-        gS3[0] += gA0 * T0[0] * T0[0] + gB0 * T0[0] * T1[0] + gC0 * T1[0] * T1[0];
-        gS3[3] += gA0 * T0[1] * T0[1] + gB0 * T0[1] * T1[1] + gC0 * T1[1] * T1[1];
-        gS3[5] += gA0 * T0[2] * T0[2] + gB0 * T0[2] * T1[2] + gC0 * T1[2] * T1[2];
-        gS3[1] += 2.f * gA0 * T0[0] * T0[1] + gB0 * (T0[0] * T1[1] + T1[0] * T0[1]) + 2.f * gC0 * T1[0] * T1[1];
-        gS3[2] += 2.f * gA0 * T0[0] * T0[2] + gB0 * (T0[0] * T1[2] + T1[0] * T0[2]) + 2.f * gC0 * T1[0] * T1[2];
-        gS3[4] += 2.f * gA0 * T0[1] * T0[2] + gB0 * (T0[1] * T1[2] + T1[1] * T0[2]) + 2.f * gC0 * T1[1] * T1[2];
         // gradient w.r.t. T rows: dA0/dT0 = 2 S T0, dB0/dT0 = S T1, dB0/dT1 = S T0, dC0/dT1 = 2 S T1
         const float* S = g.S3;
         const float sT0[3] = {S[0] * T0[0] + S[1] * T0[1] + S[2] * T0[2], S[1] * T0[0] + S[3] * T0[1] + S[4] * T0[2],
@@ -552,69 +682,46 @@ __device__ __forceinline__ void project_bwd_one(const SceneDev& sc, const ViewIn
         // t = W mu + t_c
         for (int c = 0; c < 3; ++c) gpos[c] += W[c] * gt[0] + W[3 + c] * gt[1] + W[6 + c] * gt[2];
     }
-
-    // The rotation, scales and normalised quaternion are read and formed again here rather than
-    // kept in registers through the view loop, which would otherwise spill.
-    {
-        float pos2[3];
-        load_geo(sc, i, pos2, g);
-    }
-    // S3 = M M', M = Rq diag(s): dL/dM = (G + G') M with G the full symmetric gradient
-    // (off-diagonal entries of gS3 hold the sum of both symmetric positions).
-    float Gf[9] = {gS3[0], 0.5f * gS3[1], 0.5f * gS3[2], 0.5f * gS3[1], gS3[3], 0.5f * gS3[4],
-                   0.5f * gS3[2], 0.5f * gS3[4], gS3[5]};
-    float M[9];
-    for (int rr = 0; rr < 3; ++rr)
-        for (int c = 0; c < 3; ++c) M[3 * rr + c] = g.Rq[3 * rr + c] * g.s[c];
+    // Sigma3 = M M', M = R diag(s): dL/dM = 2 G M with G = dL/dSigma3 = R H R', so
+    // dL/dlog s_c = s_c (dL/dM)_{:,c} . R e_c = 2 s_c^2 H_cc and dL/dR = (dL/dM) diag(s) = 2 R H diag(s^2)
+    const float Hf[9] = {H[0], H[1], H[2], H[1], H[3], H[4], H[2], H[4], H[5]};
     float gR[9], gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
     if (g.ok) {  // a zero quaternion is culled in every view and gets zero gradients
-        for (int rr = 0; rr < 3; ++rr)
-            for (int c = 0; c < 3; ++c) {
-                const float gM = 2.f * (Gf[3 * rr + 0] * M[c] + Gf[3 * rr + 1] * M[3 + c] + Gf[3 * rr + 2] * M[6 + c]);
-                gR[3 * rr + c] = gM * g.s[c];
-                gs[c] += gM * g.Rq[3 * rr + c];
-            }
+        for (int c = 0; c < 3; ++c) {
+            const float s2c = g.s[c] * g.s[c];
+            gs[c] = 2.f * s2c * Hf[4 * c];
+            for (int rr = 0; rr < 3; ++rr)
+                gR[3 * rr + c] = 2.f * s2c *
+                                 (g.Rq[3 * rr] * Hf[c] + g.Rq[3 * rr + 1] * Hf[3 + c] + g.Rq[3 * rr + 2] * Hf[6 + c]);
+        }
         quat_grad(g.qh, gR, gq);
         const float qd = g.qh[0] * gq[0] + g.qh[1] * gq[1] + g.qh[2] * gq[2] + g.qh[3] * gq[3];
         const float iq = 1.0f / g.qnorm;
         for (int c = 0; c < 4; ++c) gq[c] = (gq[c] - g.qh[c] * qd) * iq;
-        for (int c = 0; c < 3; ++c) gs[c] *= g.s[c];
     }
-
-    for (int c = 0; c < 3; ++c) G.pos[c * n + i] = gpos[c];
+    for (int c = 0; c < 3; ++c) G.pos[c * n + i] += gpos[c];  // after the colour pass's share
     for (int c = 0; c < 3; ++c) G.logscale[c * n + i] = gs[c];
     for (int c = 0; c < 4; ++c) G.quat[c * n + i] = gq[c];
     G.op_logit[i] = gop;
     if (G.pmask_logit) G.pmask_logit[i] = gpm;
-    if constexpr (SHD >= 0) {
-#pragma unroll
-        for (int m = 0; m < SHM; ++m)
-            for (int c = 0; c < 3; ++c) G.sh[((int64_t)m * 3 + c) * n + i] = gsh[m][c];
-        return;
-    }
-    for (int c = 0; c < 3; ++c) G.base[c * n + i] = gbase[c];
-#pragma unroll
-    for (int l = 0; l < K; ++l) {
-        if (RAGGED && l >= lr.cnt) break;
-        for (int c = 0; c < 3; ++c) G.axis[lr.at3(l, c)] = gax[l][c];
-        G.sharp[lr.at1(l)] = glam[l];
-        for (int c = 0; c < 3; ++c) G.amp[lr.at3(l, c)] = gamp[l][c];
-        if (G.lmask_logit) G.lmask_logit[lr.at1(l)] = glm[l];
-    }
 }
 
-// The SG instances run at three waves per SIMD (the compiler keeps them within 168 registers, with
-// a few spills, which measured faster than two waves at 209); the SH instances keep their registers.
 template <int K, bool RAGGED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_project_bwd(
-    SceneDev sc, const ViewInfo* __restrict__ views, int nv, const float* __restrict__ grad2d, GradDev G) {
-    project_bwd_one<K, RAGGED, -1>(sc, views, nv, grad2d, G);
+__global__ __launch_bounds__(256) void k_project_bwd_col(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
+                                                         const float* __restrict__ sums_col, GradDev G) {
+    project_bwd_colour<K, RAGGED, -1>(sc, views, nv, sums_col, G);
 }
 
 template <int SHD>
 __global__ __launch_bounds__(256) void k_project_bwd_sh(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
-                                                        const float* __restrict__ grad2d, GradDev G) {
-    project_bwd_one<0, false, SHD>(sc, views, nv, grad2d, G);
+                                                        const float* __restrict__ sums_col, GradDev G) {
+    project_bwd_colour<0, false, SHD>(sc, views, nv, sums_col, G);
+}
+
+__global__ __launch_bounds__(256) void k_project_bwd_geo(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
+                                                         const float* __restrict__ sums_exp,
+                                                         const PackedRec* __restrict__ rec, GradDev G) {
+    project_bwd_geometry(sc, views, nv, sums_exp, rec, G);
 }
 
 template <int K, bool RAGGED, int SHD = -1>
@@ -625,16 +732,22 @@ hipError_t dispatch_fwd(const SceneDev& sc, const ViewInfo* views, int nv, int t
     return hipGetLastError();
 }
 
+// colour pass, then geometry pass (which adds to the position gradient the colour pass wrote)
 template <int K, bool RAGGED, int SHD = -1>
-hipError_t dispatch_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d, const GradDev& g,
-                        hipStream_t stream) {
+hipError_t dispatch_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d,
+                        const PackedRec* rec, const GradDev& g, hipStream_t stream) {
     const int64_t blocks = (sc.n + 255) / 256;
+    const float* sums_exp = grad2d;     // record r's exponent sums at 9 r .. 9 r + 5
+    const float* sums_col = grad2d + 6; // its colour gradient at 9 r + 6 .. 9 r + 8
     if constexpr (SHD >= 0)
         hipLaunchKernelGGL((k_project_bwd_sh<SHD>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv,
-                           grad2d, g);
+                           sums_col, g);
     else
-        hipLaunchKernelGGL((k_project_bwd<K, RAGGED>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv,
-                           grad2d, g);
+        hipLaunchKernelGGL((k_project_bwd_col<K, RAGGED>), dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv,
+                           sums_col, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_project_bwd_geo, dim3((unsigned)blocks), dim3(256), 0, stream, sc, views, nv, sums_exp, rec, g);
     return hipGetLastError();
 }
 
@@ -656,18 +769,18 @@ hipError_t project_k(const SceneDev& sc, const ViewInfo* views, int nv, int tile
 }
 
 template <bool RAGGED>
-hipError_t project_bwd_k(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d, const GradDev& g,
-                         hipStream_t stream) {
+hipError_t project_bwd_k(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d,
+                         const PackedRec* rec, const GradDev& g, hipStream_t stream) {
     switch (sc.k) {
-        case 0: return dispatch_bwd<0, false>(sc, views, nv, grad2d, g, stream);
-        case 1: return dispatch_bwd<1, RAGGED>(sc, views, nv, grad2d, g, stream);
-        case 2: return dispatch_bwd<2, RAGGED>(sc, views, nv, grad2d, g, stream);
-        case 3: return dispatch_bwd<3, RAGGED>(sc, views, nv, grad2d, g, stream);
-        case 4: return dispatch_bwd<4, RAGGED>(sc, views, nv, grad2d, g, stream);
-        case 5: return dispatch_bwd<5, RAGGED>(sc, views, nv, grad2d, g, stream);
-        case 6: return dispatch_bwd<6, RAGGED>(sc, views, nv, grad2d, g, stream);
-        case 7: return dispatch_bwd<7, RAGGED>(sc, views, nv, grad2d, g, stream);
-        case 8: return dispatch_bwd<8, RAGGED>(sc, views, nv, grad2d, g, stream);
+        case 0: return dispatch_bwd<0, false>(sc, views, nv, grad2d, rec, g, stream);
+        case 1: return dispatch_bwd<1, RAGGED>(sc, views, nv, grad2d, rec, g, stream);
+        case 2: return dispatch_bwd<2, RAGGED>(sc, views, nv, grad2d, rec, g, stream);
+        case 3: return dispatch_bwd<3, RAGGED>(sc, views, nv, grad2d, rec, g, stream);
+        case 4: return dispatch_bwd<4, RAGGED>(sc, views, nv, grad2d, rec, g, stream);
+        case 5: return dispatch_bwd<5, RAGGED>(sc, views, nv, grad2d, rec, g, stream);
+        case 6: return dispatch_bwd<6, RAGGED>(sc, views, nv, grad2d, rec, g, stream);
+        case 7: return dispatch_bwd<7, RAGGED>(sc, views, nv, grad2d, rec, g, stream);
+        case 8: return dispatch_bwd<8, RAGGED>(sc, views, nv, grad2d, rec, g, stream);
     }
     return hipErrorInvalidValue;
 }
@@ -693,19 +806,19 @@ hipError_t launch_project(const SceneDev& sc, const ViewInfo* views, int nv, int
 }
 
 hipError_t launch_project_bwd(const SceneDev& sc, const ViewInfo* views, int nv, const float* grad2d,
-                              const GradDev& g, hipStream_t stream) {
+                              const PackedRec* rec, const GradDev& g, hipStream_t stream) {
     if (sc.n == 0) return hipSuccess;
     if (sc.sh) {
         switch (sc.sh_degree) {
-            case 0: return dispatch_bwd<0, false, 0>(sc, views, nv, grad2d, g, stream);
-            case 1: return dispatch_bwd<0, false, 1>(sc, views, nv, grad2d, g, stream);
-            case 2: return dispatch_bwd<0, false, 2>(sc, views, nv, grad2d, g, stream);
-            case 3: return dispatch_bwd<0, false, 3>(sc, views, nv, grad2d, g, stream);
+            case 0: return dispatch_bwd<0, false, 0>(sc, views, nv, grad2d, rec, g, stream);
+            case 1: return dispatch_bwd<0, false, 1>(sc, views, nv, grad2d, rec, g, stream);
+            case 2: return dispatch_bwd<0, false, 2>(sc, views, nv, grad2d, rec, g, stream);
+            case 3: return dispatch_bwd<0, false, 3>(sc, views, nv, grad2d, rec, g, stream);
         }
         return hipErrorInvalidValue;
     }
-    return sc.lobe_off ? project_bwd_k<true>(sc, views, nv, grad2d, g, stream)
-                       : project_bwd_k<false>(sc, views, nv, grad2d, g, stream);
+    return sc.lobe_off ? project_bwd_k<true>(sc, views, nv, grad2d, rec, g, stream)
+                       : project_bwd_k<false>(sc, views, nv, grad2d, rec, g, stream);
 }
 
 }  // namespace megs

@@ -560,13 +560,14 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     const int64_t k = kb + perm[threadIdx.x];
     const bool has = k < n_records;
     const uint32_t g = has ? (order ? order[k] : (uint32_t)k) : 0u;
-    // the record's 64-byte line: mean, conic, colour + cutoff, radius / ntiles / half-extents
+    // the record's 64-byte line: mean | factor ratio, diagonal factors | opacity, colour |
+    // half-extents, radius, ntiles
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
     if (has) {
         const float4* q = reinterpret_cast<const float4*>(rec.packed + g);
         q0 = q[0]; q1 = q[1]; q2 = q[2]; q3 = q[3];
     }
-    const uint32_t nt = has ? __float_as_uint(q3.y) : 0u;
+    const uint32_t nt = has ? __float_as_uint(q3.w) : 0u;
     const int64_t off = has ? (int64_t)offsets[k] : 0;
     const int64_t lo = range[0], hi = range[1];
     if (has && nt && off + (int64_t)nt > capacity) status[1] = 1;
@@ -583,8 +584,9 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
         tile_off = vw.tile_off;
         const double mx = __hiloint2double(__float_as_int(q0.y), __float_as_int(q0.x));
         const double my = __hiloint2double(__float_as_int(q0.w), __float_as_int(q0.z));
-        tile_rect(mx, my, __float_as_int(q3.x), vw, tile, x0, x1, y0, y1);
-        ellipse_rows(mx, my, q1.x, q1.y, q1.z, q2.w, er);
+        const double rr = __hiloint2double(__float_as_int(q1.y), __float_as_int(q1.x));
+        tile_rect(mx, my, __float_as_int(q3.z), vw, tile, x0, x1, y0, y1);
+        ellipse_rows(mx, my, shape_of(q1.z, rr, q1.w), cutoff_of(q2.x), er);
     }
     for (int64_t w0 = lo; w0 < hi; w0 += kEmitWindow) {
         const int64_t w1 = w0 + kEmitWindow < hi ? w0 + kEmitWindow : hi;
@@ -684,7 +686,7 @@ __global__ void k_pair_reduce(const uint32_t* __restrict__ order, const uint32_t
         for (int c = 0; c < 9; ++c) acc[c] += g[c];
     }
 #pragma unroll
-    for (int c = 0; c < 9; ++c) grad2d[9 * (int64_t)r + c] = acc[c];
+    for (int c = 0; c < 9; ++c) grad2d[grad2d_index(r, c)] = acc[c];
 }
 
 __global__ void k_clamp_count(const uint32_t* total, int64_t capacity, uint32_t* count, int32_t* status) {

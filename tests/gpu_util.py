@@ -46,6 +46,7 @@ def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
         out["radius"] = fr.buffer("radius", nr, torch.int32).cpu().numpy()
         out["ntiles"] = fr.buffer("ntiles", nr, torch.int32).cpu().numpy().view(np.uint32)
         out["cutoff"] = fr.buffer("cutoff", nr, torch.float32).cpu().numpy()
+        out["chol"] = fr.buffer("chol", 4 * nr, torch.float64).view(nr, 4).cpu().numpy()
     if P:
         out["vals"] = fr.buffer("vals", P, torch.int32).cpu().numpy().view(np.uint32)
         if st.tile_keys:
@@ -62,35 +63,66 @@ def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
         grads = R.backward(ds, fr, flat_weights(weights))
         torch.cuda.synchronize()
         out["grads"] = {p: (None if g is None else g.cpu().numpy().astype(np.float64)) for p, g in grads.items()}
-        g2 = fr.alloc.blocks[nblocks]
-        moments = g2[: nr * 9 * 4].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
+        moments = grad2d_buffer(fr.alloc.blocks[nblocks], nr)
         out["grad2d_moments"] = moments
-        conic_o = out["conic_o"].astype(np.float64) if nr else np.zeros((0, 4))
-        out["grad2d"] = grad2d_from_moments(moments, conic_o)
+        nr0 = out["conic_o"] if nr else np.zeros((0, 4))
+        out["grad2d"] = grad2d_from_moments(moments, out["chol"] if nr else np.zeros((0, 4)),
+                                            nr0[:, 3].astype(np.float64))
     return out
 
 
-def grad2d_from_moments(m: np.ndarray, conic_o: np.ndarray) -> np.ndarray:
+def grad2d_buffer(block: torch.Tensor, nr: int) -> np.ndarray:
+    """The backward's per-record sums [nr][9] from the start of its scratch block (FP64 copy)."""
+    return block[: nr * 9 * 4].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
+
+
+# The blend's exponent scale: its exponent in log2 units is -(w1^2 + w2^2), w = KQ2 (l11 (dx + r dy), l22 dy),
+# KQ2 = sqrt(log2(e) / 2) rounded to FP32 as the library holds it.
+KQ2 = float(np.float32(np.sqrt(np.log2(np.e) / 2)))
+
+
+def chol_conic(chol: np.ndarray) -> np.ndarray:
+    """The conic (a, b, c) that a record's factors (l11, r, l22) describe, in FP64:
+    a = l11^2, b = l11^2 r, c = (l11 r)^2 + l22^2."""
+    l11, r, l22 = chol[:, 0], chol[:, 1], chol[:, 2]
+    a = l11 * l11
+    return np.stack([a, a * r, (l11 * r) ** 2 + l22 * l22], axis=1)
+
+
+def grad2d_from_moments(m: np.ndarray, chol: np.ndarray, oe: np.ndarray) -> np.ndarray:
     """The library's per-record backward buffer holds, per record, the sums over its fragments of
-    e dx, e dy, e dx^2, e dx dy, e dy^2 and e, with e the loss gradient of the effective opacity of an
-    unclamped fragment (the gradient of the Gaussian's exponent q = -(a dx^2 + 2 b dx dy + c dy^2) / 2
-    is o_eff e), then the RGB gradients. This returns the gradients of (u, v, a, b, c, o, r, g, b)
-    that the oracle's blend backward produces. conic_o: the records' (a, b, c, o_eff)."""
+    e w1, e w2, e w1^2, e w1 w2, e w2^2 and e, with e the loss gradient of the effective opacity of an
+    unclamped fragment and w = KQ2 (l11 (dx + r dy), l22 dy) the exponent's factors of the pixel
+    offset, then the RGB gradients. Back to pixel offsets (dy = w2 / (KQ2 l22), dx = w1 / (KQ2 l11) -
+    r dy); the gradient of the Gaussian's exponent q = -(a dx^2 + 2 b dx dy + c dy^2) / 2 is o_eff e.
+    Returns the gradients of (u, v, a, b, c, o, r, g, b) that the oracle's blend backward produces,
+    for the conic the factors describe. chol: the records' (l11, r, l22, 0); oe: o_eff."""
     g = np.array(m, dtype=np.float64, copy=True)
-    a, b, c, oe = conic_o[:, 0], conic_o[:, 1], conic_o[:, 2], conic_o[:, 3]
-    g[:, 0] = oe * (a * m[:, 0] + b * m[:, 1])
-    g[:, 1] = oe * (b * m[:, 0] + c * m[:, 1])
-    g[:, 2] = -0.5 * oe * m[:, 2]
-    g[:, 3] = -oe * m[:, 3]
-    g[:, 4] = -0.5 * oe * m[:, 4]
+    l11, r, l22 = chol[:, 0], chol[:, 1], chol[:, 2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        i1 = np.where(l11 > 0, 1.0 / (KQ2 * l11), 0.0)
+        i2 = np.where(l22 > 0, 1.0 / (KQ2 * l22), 0.0)
+    ey = m[:, 1] * i2
+    ex = m[:, 0] * i1 - r * ey
+    eyy = m[:, 4] * i2 * i2
+    pxy = m[:, 3] * i1 * i2
+    exy = pxy - r * eyy
+    exx = m[:, 2] * i1 * i1 - 2.0 * r * pxy + r * r * eyy
+    a, b, c = chol_conic(chol).T
+    g[:, 0] = oe * (a * ex + b * ey)
+    g[:, 1] = oe * (b * ex + c * ey)
+    g[:, 2] = -0.5 * oe * exx
+    g[:, 3] = -oe * exy
+    g[:, 4] = -0.5 * oe * eyy
     return g
 
 
 def gpu_records(g: dict) -> dict:
-    """The GPU's records in the oracle's record layout (float64 copies of the stored values)."""
+    """The GPU's records in the oracle's record layout (float64 copies of the stored values; the conic
+    is the one the stored factors describe, formed in FP64)."""
     m, co, cd = g["mean"], g["conic_o"], g["rgbd"]
     return {"u": m[:, 0].copy(), "v": m[:, 1].copy(), "depth": cd[:, 3].astype(np.float64),
-            "conic": co[:, :3].astype(np.float64), "o": co[:, 3].astype(np.float64),
+            "conic": chol_conic(g["chol"]), "o": co[:, 3].astype(np.float64),
             "rgb": cd[:, :3].astype(np.float64), "valid": (g["radius"] >= 0).astype(np.int32),
             "radius": g["radius"].astype(np.int32), "cutoff": g["cutoff"].astype(np.float64)}
 

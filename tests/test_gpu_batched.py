@@ -10,7 +10,8 @@ from paper_2509_07021_amd import _lib as L
 from paper_2509_07021_amd import render as R
 from paper_2509_07021_amd import scenes as S
 
-from gpu_util import IMG_TOL, check_key_table, grad2d_from_moments, grad_close, gpu_records, gpu_run, log
+from gpu_util import (IMG_TOL, check_key_table, grad2d_buffer, grad2d_from_moments, grad_close, gpu_records, gpu_run,
+                      log)
 
 pytestmark = pytest.mark.gpu
 
@@ -135,6 +136,7 @@ def _full_size_sampled(scene, cams, cfg, frac, seed):
     g["rgbd"] = fr.buffer("rgbd", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
     g["radius"] = fr.buffer("radius", nr, torch.int32).cpu().numpy()
     g["cutoff"] = fr.buffer("cutoff", nr, torch.float32).cpu().numpy()
+    g["chol"] = fr.buffer("chol", 4 * nr, torch.float64).view(nr, 4).cpu().numpy()
     P = g["n_pairs"]
     vals = fr.buffer("vals", P, torch.int32).cpu().numpy().view(np.uint32)
     tkeys = fr.buffer("tile_keys", P, torch.int32).cpu().numpy().view(np.uint32)
@@ -164,8 +166,7 @@ def _full_size_sampled(scene, cams, cfg, frac, seed):
     dl = torch.from_numpy(np.concatenate([w.reshape(-1) for w in weights])).cuda()
     grads = R.backward(ds, fr, dl)
     torch.cuda.synchronize()
-    g2 = grad2d_from_moments(fr.alloc.blocks[nb][: nr * 36].view(torch.float32).view(nr, 9).cpu().numpy(),
-                             np.column_stack([rec["conic"], rec["o"]]))
+    g2 = grad2d_from_moments(grad2d_buffer(fr.alloc.blocks[nb], nr), g["chol"], rec["o"])
     ref = np.zeros_like(g2)
     ref_abs = np.zeros_like(g2)
     for vi, cam in enumerate(cams):

@@ -35,10 +35,11 @@ def conic_condition(conic):
     return lam * lam / det
 
 
-def _check_records(g, fwd, n_views, conic_cond_tol=False):
-    """Records against the oracle's. The FP32 conic is the inverse of the dilated 2D covariance;
-    with conic_cond_tol its relative tolerance grows with the conic's condition number (FP32 loses
-    about cond x 2^-24 inverting it), for scenes built to reach near-degenerate footprints."""
+def _check_records(g, fwd, n_views):
+    """Records against the oracle's. The conic is formed in FP64 and kept as FP32 diagonal factors and
+    an FP64 ratio (the record's chol plane, conic = L L'), so it is accurate whatever its condition
+    number: the factors are checked against the Cholesky factors of the oracle's FP64 conic, and the
+    FP32 conic plane against that conic."""
     rec = fwd["records"]
     valid_o = rec["valid"].astype(bool)
     valid_g = g["radius"] >= 0
@@ -47,15 +48,19 @@ def _check_records(g, fwd, n_views, conic_cond_tol=False):
     np.testing.assert_allclose(g["mean"][v, 0], rec["u"][v], rtol=0, atol=1e-9)
     np.testing.assert_allclose(g["mean"][v, 1], rec["v"][v], rtol=0, atol=1e-9)
     np.testing.assert_allclose(g["rgbd"][v, 3], rec["depth"][v], rtol=1e-6)
-    if conic_cond_tol:
-        oc = rec["conic"][v]
-        rtol = 2e-5 + 2 * conic_condition(oc) * 2.0 ** -23
-        err = np.abs(g["conic_o"][v, :3] - oc)
-        tol = rtol[:, None] * np.abs(oc).max(axis=1, keepdims=True) + 2e-5 * np.abs(oc).max()
-        assert (err <= tol).all(), f"conic error {float((err / tol).max()):.2f} x tolerance"
-    else:
-        np.testing.assert_allclose(g["conic_o"][v, :3], rec["conic"][v], rtol=2e-5,
-                                   atol=2e-5 * np.abs(rec["conic"][v]).max())
+    np.testing.assert_allclose(g["conic_o"][v, :3], rec["conic"][v], rtol=2e-5,
+                               atol=2e-5 * np.abs(rec["conic"][v]).max())
+    # the factors: l11 = sqrt(a), r = b / a, l22 = sqrt(c - b^2 / a) of the oracle's conic (a, b, c)
+    oc = rec["conic"][v]
+    l11 = np.sqrt(oc[:, 0])
+    ratio = oc[:, 1] / oc[:, 0]
+    l22 = np.sqrt((oc[:, 0] * oc[:, 2] - oc[:, 1] ** 2) / oc[:, 0])
+    ch = g["chol"][v]
+    np.testing.assert_allclose(ch[:, 0], l11, rtol=2e-6)
+    np.testing.assert_allclose(ch[:, 2], l22, rtol=2e-6)
+    # the ratio carries the footprint's direction: relative to the factors' own precision it is exact
+    rerr = np.abs(ch[:, 1] - ratio) / (1.0 + np.abs(ratio))
+    assert rerr.max() <= 2e-6, f"factor ratio error {rerr.max():.2e}"
     np.testing.assert_allclose(g["conic_o"][v, 3], rec["o"][v], rtol=2e-6)
     np.testing.assert_allclose(g["rgbd"][v, :3], rec["rgb"][v], rtol=0, atol=2e-6)
     dr = np.abs(g["radius"][v] - rec["radius"][v])
@@ -96,30 +101,24 @@ def _check_blend_stage(g, rec, cams, tile, off, img_tol=IMG_TOL, t_rtol=1e-5):
     return worst
 
 
-def _run_all_stages(scene, cams, cfg, seed=7, near_degenerate=False):
+def _run_all_stages(scene, cams, cfg, seed=7):
     """Every stage against the oracle: stage-wise on the GPU's own records (keys, order, ranges and
     last indices bit-exact, blend and blend backward within the FP32 tolerances), then end to end
-    against the FP64 pipeline. With near_degenerate (conics with condition numbers in the
-    thousands), the FP32 conic and the FP32 quadratic form of the blend lose about cond x 2^-24
-    relative: the conics take a condition-aware tolerance, the stage-wise blend 1e-3, and the
-    stage-wise and end-to-end gradient errors are returned for the caller to bound."""
+    against the FP64 pipeline. Returns the GPU's buffers, the oracle's forward and the measured
+    end-to-end errors (max abs image error; per-tensor relative gradient errors)."""
     log(f"case n={scene.n} k={scene.k} views={len(cams)} tile={cfg.tile} batch={cfg.batch} flags={cfg.flags}")
     fwd, w = _oracle_masked_weights(scene, cams, cfg.tile, seed)
     g = gpu_run(scene, cams, cfg, weights=w)
-    _check_records(g, fwd, len(cams), conic_cond_tol=near_degenerate)
+    _check_records(g, fwd, len(cams))
     rec, off = _check_key_stage(g, cams, cfg.tile, scene.n, sub=cfg.subtile)
-    if near_degenerate:
-        _check_blend_stage(g, rec, cams, cfg.tile, off, img_tol=1e-3, t_rtol=1e-3)
-    else:
-        _check_blend_stage(g, rec, cams, cfg.tile, off)
+    _check_blend_stage(g, rec, cams, cfg.tile, off)
     # end-to-end images against the FP64 pipeline
     e2e = {"image": 0.0}
     for vi in range(len(cams)):
         ok = fwd["views"][vi]["flag"] == 0
         d = np.abs(g["images"][vi] - fwd["images"][vi])[:, ok]
         e2e["image"] = max(e2e["image"], float(d.max()))
-        if not near_degenerate:
-            assert d.max() <= IMG_TOL, (vi, d.max())
+        assert d.max() <= IMG_TOL, (vi, d.max())
     # backward, stage-wise: blend backward over the GPU's records and lists
     g2_ref = np.zeros_like(g["grad2d"])
     g2_abs = np.zeros_like(g["grad2d"])
@@ -127,11 +126,7 @@ def _run_all_stages(scene, cams, cfg, seed=7, near_degenerate=False):
         O.blend_backward(cam, cfg.tile, rec, g["vals"], g["ranges"][off[vi]:off[vi + 1]], w[vi], grad2d=g2_ref,
                          grad2d_abs=g2_abs)
     for c, name in enumerate(("u", "v", "a", "b", "c", "o", "r", "g", "b_col")):
-        if near_degenerate:
-            e2e[f"grad2d[{name}]"] = float(np.linalg.norm(g["grad2d"][:, c] - g2_ref[:, c]) /
-                                           max(np.linalg.norm(g2_ref[:, c]), 1e-30))
-        else:
-            grad_close(f"grad2d[{name}]", g["grad2d"][:, c], g2_ref[:, c], abs_sum=g2_abs[:, c])
+        e2e[f"grad2d[{name}]"] = grad_close(f"grad2d[{name}]", g["grad2d"][:, c], g2_ref[:, c], abs_sum=g2_abs[:, c])
     # projection backward, stage-wise: fed with the GPU's 2D gradients
     pl = scene.widened()
     gr_stage = O.zero_grads(pl)
@@ -140,23 +135,14 @@ def _run_all_stages(scene, cams, cfg, seed=7, near_degenerate=False):
         O.project_backward(pl, scene.k, cam, cfg.tile, g["grad2d"][vi * n:(vi + 1) * n], gr_stage)
     for p in O.PLANES:
         if gr_stage[p] is not None:
-            if near_degenerate:
-                e2e[f"stage {p}"] = float(np.linalg.norm(g["grads"][p] - gr_stage[p]) /
-                                          max(np.linalg.norm(gr_stage[p]), 1e-30))
-            else:
-                grad_close(f"stage {p}", g["grads"][p], gr_stage[p])
+            e2e[f"stage {p}"] = grad_close(f"stage {p}", g["grads"][p], gr_stage[p])
     # end to end against the FP64 gradient
     gr, _ = O.render_backward(pl, scene.k, cams, cfg.tile, w, fwd=fwd)
     for p in O.PLANES:
         if gr[p] is not None:
-            if near_degenerate:
-                e2e[p] = float(np.linalg.norm(g["grads"][p] - gr[p]) / max(np.linalg.norm(gr[p]), 1e-30))
-            else:
-                grad_close(p, g["grads"][p], gr[p])
-    if near_degenerate:
-        log("end-to-end errors: " + ", ".join(f"{k} {v:.2e}" for k, v in e2e.items()))
-        return g, fwd, e2e
-    return g, fwd
+            e2e[p] = grad_close(p, g["grads"][p], gr[p])
+    log("errors: " + ", ".join(f"{k} {v:.2e}" for k, v in e2e.items()))
+    return g, fwd, e2e
 
 
 def test_small_workload_all_stages():
@@ -198,7 +184,7 @@ def test_masked_crop_gradients():
     idx = S.axis_nearest(scene, cams[0], 500)
     crop = scene.subset(idx)
     cam = S.crop_camera(cams[0], 64, 64)
-    g, _ = _run_all_stages(crop, [cam], R.Config(16, 64), seed=3)
+    g, _, _ = _run_all_stages(crop, [cam], R.Config(16, 64), seed=3)
     assert np.abs(g["grads"]["pmask_logit"]).max() > 0 and np.abs(g["grads"]["lmask_logit"]).max() > 0
 
 
@@ -244,27 +230,20 @@ def test_empty_and_culled_scenes():
 @pytest.mark.parametrize("tile,sub", [(32, 8), (16, 0)])
 def test_needle_footprints(tile, sub):
     """Needle-shaped Gaussians (one long axis, two very thin ones): 2D conics with condition numbers
-    in the thousands, where the FP32 exponent cancels most and the culling box and sub-tile flags
-    of a thin ellipse are tightest; every stage against the oracle, in the benchmark's launch
-    configuration (32x32 tiles, 8x8 sub-tiles) and a per-tile one."""
+    in the thousands, where an FP32 determinant or quadratic form would cancel most and the culling
+    box and sub-tile flags of a thin ellipse are tightest; every stage against the oracle at the
+    standard tolerances (images 1e-5, gradients 1e-4), in the benchmark's launch configuration
+    (32x32 tiles, 8x8 sub-tiles) and a per-tile one. The shape is projected in FP64 and the blend's
+    exponent is a sum of squares staged per sub-tile, so nothing here depends on the condition
+    number (measured: images 7e-7 max abs, gradients 5e-5 per tensor at most, for the log-scales)."""
     rng = np.random.default_rng(11)
     scene = S.random_scene(rng, 600, 3, masks=True, spread=0.8, logscale_mu=-4.0)
     scene.logscale[0] = rng.uniform(-0.3, 0.7, scene.n).astype(np.float32)
     scene.logscale[1:] = rng.uniform(-7.0, -5.5, (2, scene.n)).astype(np.float32)
     cams = [S.look_at((0, -4, 0.5), 120, 96), S.look_at((3, -2, 1), 72, 72, bg=(0.1, 0.2, 0.3))]
-    g, fwd, e2e = _run_all_stages(scene, cams, R.Config(tile, 64, subtile=sub), seed=5, near_degenerate=True)
+    g, fwd, e2e = _run_all_stages(scene, cams, R.Config(tile, 64, subtile=sub), seed=5)
     rec = fwd["records"]
     assert conic_condition(rec["conic"][rec["valid"].astype(bool)]).max() > 1e3  # thin ellipses reached
-    # the FP32 conic's and quadratic form's error (about cond x 2^-24 relative) carries into the
-    # images and gradients of the thinnest footprints. Measured on this scene: images 3.2e-3 max
-    # abs end to end; per-tensor gradient errors 1.1e-4 stage-wise (on the GPU's own records) and
-    # 1.4e-3 end to end. Bounds with margin:
-    assert e2e["image"] <= 1e-2, e2e
-    for p, err in e2e.items():
-        if p.startswith("grad2d[") or p.startswith("stage "):
-            assert err <= 1e-3, (p, err)
-        elif p != "image":
-            assert err <= 1e-2, (p, err)
 
 
 def test_misaligned_allocation_is_rejected():
@@ -318,7 +297,7 @@ def test_deterministic_backward_is_bitwise_reproducible(tile, waves, flags, sub)
     scene, cams = S.make_workload("small_2k_128px")
     cams = cams + [S.look_at((2.0, -3.0, 1.5), 100, 60, bg=(0.2, 0.2, 0.2))]
     cfg = R.Config(tile, 64, flags=flags, waves=waves, subtile=sub)
-    g1, fwd = _run_all_stages(scene, cams, cfg)
+    g1, fwd, _ = _run_all_stages(scene, cams, cfg)
     w = [np.asarray(x) for x in S.loss_weights(cams, 7)]
     g2 = gpu_run(scene, cams, cfg, weights=[wi * (1 - vw["flag"])[None].astype(np.float32)
                                             for wi, vw in zip(w, fwd["views"])])
