@@ -118,6 +118,8 @@ def parse():
     ap.add_argument("--cpu-views", type=int, default=8, help="views of the workload the oracle renders")
     ap.add_argument("--no-post", action="store_true",
                     help="skip the post-processing and colour-model measurements")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the 200k 720p, 500k x 16-view and 3M x 8-view workload lines")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -340,6 +342,148 @@ def copy_rate(stream, mib=1024, reps=10):
             "ms_per_copy": round(ms, 4)}
 
 
+def stage_rooflines(R, L, ds, cams, cfg, scene, geom_bytes, pairs, hbm_copy, steps):
+    """Per-stage milliseconds of eager forward+backward calls (HIP events), the dominant kernel's
+    roofline line, every stage against its own bound (HBM bytes at 8 TB/s, or blend FLOPs at the FP32
+    peak), and the whole path against the sum of those bounds."""
+    import torch
+    npix = sum(c.width * c.height for c in cams)
+    dl = torch.randn(3 * npix, device="cuda")
+    prof_steps = max(2, min(steps, 5))
+    for _ in range(2):
+        R.backward(ds, R.forward(ds, cams, cfg), dl)
+    torch.cuda.synchronize()
+    with R.Profile() as prof:
+        for _ in range(prof_steps):
+            R.backward(ds, R.forward(ds, cams, cfg), dl)
+    stage_ms = {s: prof.ms[s] / max(prof.count[s], 1) for s in L.STAGES if prof.count[s]}
+    blended, evaluated, replayed, _ = fragment_counts(R, ds, cams, cfg)
+    dominant = max(stage_ms, key=stage_ms.get)
+    nt = sum(((c.width + cfg.tile - 1) // cfg.tile) * ((c.height + cfg.tile - 1) // cfg.tile) for c in cams)
+    tile_bits = max(1, (nt - 1).bit_length())
+    if dominant in ("blend_fwd", "blend_bwd"):
+        # the backward re-tests the fragments the forward tested (the same culled lists, walked
+        # back from each pixel's last index) and differentiates the blended ones
+        flops = (FLOP_TEST * evaluated + FLOP_FWD_BLEND * blended if dominant == "blend_fwd"
+                 else FLOP_TEST * evaluated + FLOP_BWD_BLEND * blended)
+        achieved = flops / (stage_ms[dominant] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_of(dominant),
+                "units_per_launch": {"blended": blended, "evaluated": evaluated, "replayed": replayed},
+                "avg_ms": round(stage_ms[dominant], 4), "valu": valu_of(dominant, stage_ms[dominant])}
+    else:
+        by = stage_bytes(dominant, scene.n, len(cams), pairs, npix, nt, geom_bytes, scene.k, tile_bits)
+        achieved = by / (stage_ms[dominant] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_of(dominant),
+                "avg_ms": round(stage_ms[dominant], 4)}
+    stage_roof, bound_ms = {}, 0.0
+    for st, ms in stage_ms.items():
+        if st in ("blend_fwd", "blend_bwd"):
+            fl = FLOP_TEST * evaluated + (FLOP_FWD_BLEND if st == "blend_fwd" else FLOP_BWD_BLEND) * blended
+            ach = fl / (ms * 1e-3) / 1e12
+            v = valu_of(st, ms)
+            stage_roof[st] = {"bound": "alu", "achieved": round(ach, 2), "unit": "TFLOP/s",
+                              "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                              "valu_issue_frac": v["issue_frac"] if v else None}
+            bound_ms += fl / (PEAK_FP32_TFLOPS * 1e12) * 1e3
+        else:
+            by = stage_bytes(st, scene.n, len(cams), pairs, npix, nt, geom_bytes, scene.k, tile_bits)
+            ach = by / (ms * 1e-3) / 1e9
+            stage_roof[st] = {"bound": "hbm", "achieved": round(ach, 1), "unit": "GB/s",
+                              "frac": round(ach / PEAK_HBM_GBS, 4), "frac_of_copy": round(ach / hbm_copy["GBps"], 4),
+                              "bytes": int(by)}
+            bound_ms += by / (PEAK_HBM_GBS * 1e9) * 1e3
+    path_roof = {"bound_ms": round(bound_ms, 4), "measured_ms": round(sum(stage_ms.values()), 4),
+                 "frac": round(bound_ms / sum(stage_ms.values()), 4)}
+    del dl
+    return stage_ms, roof, stage_roof, path_roof
+
+
+def workload_line(args, name, cfg, graph, hbm_copy, autotune=False):
+    """One more workload at its full size: forward+backward Mpixel/s (eager calls, or one hipGraph replay
+    of all views), peak VRAM (forward only and forward+backward), the per-view dynamic part, and the
+    dominant kernel's roofline line. With autotune, the launch configuration is the autotuner's."""
+    import torch
+    from paper_2509_07021_amd import _lib as L
+    from paper_2509_07021_amd import render as R
+    from paper_2509_07021_amd import scenes as S
+    t0 = time.perf_counter()
+    scene, cams = S.make_workload(name)
+    ds = R.DeviceScene.from_scene(scene)
+    npix = sum(c.width * c.height for c in cams)
+    dl = torch.randn(3 * npix, device="cuda")
+    tune = None
+    if autotune:
+        stats = {}
+        cfg, table = R.autotune(ds, cams, R.Config(16, 64), reps=1, dl_images=dl, stats=stats)
+        tune = {"tile": cfg.tile, "waves": cfg.waves, "subtile": cfg.subtile, "batch": cfg.batch,
+                "best_ms": round(float(table.min()), 4), "sweep_vram_mb": round(stats["sweep_bytes"] / 1e6, 1)}
+        torch.cuda.empty_cache()
+    stream = torch.cuda.current_stream()
+    fr = R.forward(ds, cams, cfg)
+    torch.cuda.synchronize()
+    pairs = int(fr.state.n_pairs)
+    del fr
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    if graph:
+        gcfg = R.Config(cfg.tile, cfg.batch, cfg.flags, int(pairs * 1.02) + 4096, cfg.waves, cfg.subtile)
+        gf = R.Graph(ds, cams, gcfg, with_backward=False)
+        gf.launch()
+        torch.cuda.synchronize()
+        fwd_peak = torch.cuda.max_memory_allocated()
+        gf.close()
+        del gf
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        g = R.Graph(ds, cams, gcfg, with_backward=True, dl_images=dl)
+        g.launch()
+        torch.cuda.synchronize()
+        fb_peak = torch.cuda.max_memory_allocated()
+        ms = timed(g.launch, args.steps, args.warmup, g.stream)
+        assert g.status() == pairs
+        g.close()
+        del g
+    else:
+        fr = R.forward(ds, cams, cfg)
+        torch.cuda.synchronize()
+        fwd_peak = torch.cuda.max_memory_allocated()
+        R.backward(ds, fr, dl)
+        torch.cuda.synchronize()
+        fb_peak = torch.cuda.max_memory_allocated()
+        del fr
+
+        def step():
+            R.backward(ds, R.forward(ds, cams, cfg), dl)
+        ms = timed(step, args.steps, args.warmup, stream)
+    torch.cuda.empty_cache()
+    static = ds.static_bytes()
+    _, roof, _, path_roof = stage_rooflines(R, L, ds, cams, cfg, scene, static // scene.n, pairs, hbm_copy,
+                                            args.steps)
+    mpix = npix / ms / 1e3
+    res = sorted({f"{c.width}x{c.height}" for c in cams})
+    log(f"{name}: {ms:.3f} ms/step, {mpix:.1f} Mpixel/s, pairs {pairs}, fwd+bwd peak {fb_peak / 1e6:.0f} MB "
+        f"({time.perf_counter() - t0:.1f}s)")
+    out = {"value": round(mpix, 2), "unit": "Mpixel/s", "ms_per_step": round(ms, 4),
+           "workload": (f"{scene.n} clustered Gaussians, {scene.k} SG lobes, "
+                        f"{scene.dt_geom}/{scene.dt_color}/{scene.dt_amp} storage, {len(cams)} view(s) "
+                        f"{'/'.join(res)}, forward+backward {'in one hipGraph' if graph else 'eager'}"),
+           "gaussians": scene.n, "views": len(cams), "pixels": npix, "pairs": pairs,
+           "launch": {"tile": cfg.tile, "batch": cfg.batch, "waves": cfg.waves, "subtile": cfg.subtile},
+           "peak_vram_mb": {"forward": round(fwd_peak / 1e6, 1), "forward_backward": round(fb_peak / 1e6, 1),
+                            "static_params": round(static / 1e6, 1), "resident_before": round(before / 1e6, 1),
+                            "dynamic_per_view": round((fb_peak - before) / len(cams) / 1e6, 1)},
+           "roofline": roof, "path_roofline": path_roof}
+    if tune:
+        out["autotune"] = tune
+    del ds, dl
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -438,58 +582,11 @@ def main():
     torch.cuda.empty_cache()
 
     # ---------------------------------------------------------------- per-stage timing, same workload
-    prof_steps = max(2, min(args.steps, 5))
-    dl8b = dl8
-    for _ in range(2):
-        R.backward(ds16, R.forward(ds16, cams8, cfg), dl8b)
-    torch.cuda.synchronize()
-    with R.Profile() as prof:
-        for _ in range(prof_steps):
-            R.backward(ds16, R.forward(ds16, cams8, cfg), dl8b)
-    stage_ms = {s: prof.ms[s] / max(prof.count[s], 1) for s in L.STAGES if prof.count[s]}
-    blended, evaluated, replayed, _ = fragment_counts(R, ds16, cams8, cfg)
-    dominant = max(stage_ms, key=stage_ms.get)
-    nt8 = sum(((c.width + cfg.tile - 1) // cfg.tile) * ((c.height + cfg.tile - 1) // cfg.tile) for c in cams8)
     geom_bytes = static16 // scene.n
-    if dominant in ("blend_fwd", "blend_bwd"):
-        # the backward re-tests the fragments the forward tested (the same culled lists, walked
-        # back from each pixel's last index) and differentiates the blended ones
-        flops = (FLOP_TEST * evaluated + FLOP_FWD_BLEND * blended if dominant == "blend_fwd"
-                 else FLOP_TEST * evaluated + FLOP_BWD_BLEND * blended)
-        achieved = flops / (stage_ms[dominant] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic_of(dominant),
-                "units_per_launch": {"blended": blended, "evaluated": evaluated, "replayed": replayed},
-                "avg_ms": round(stage_ms[dominant], 4), "valu": valu_of(dominant, stage_ms[dominant])}
-    else:
-        by = stage_bytes(dominant, scene.n, len(cams8), pairs8, npix8, nt8, geom_bytes, scene.k)
-        achieved = by / (stage_ms[dominant] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_of(dominant),
-                "avg_ms": round(stage_ms[dominant], 4)}
+    stage_ms, roof, stage_roof, path_roof = stage_rooflines(R, L, ds16, cams8, cfg, scene, geom_bytes, pairs8,
+                                                            hbm_copy, args.steps)
     log("stage ms: " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
-    # every stage against its own bound (HBM bytes at 8 TB/s, or blend FLOPs at the FP32 peak), and the
-    # whole path against the sum of those bounds
-    tile_bits = max(1, (nt8 - 1).bit_length())
-    stage_roof, bound_ms = {}, 0.0
-    for st, ms in stage_ms.items():
-        if st in ("blend_fwd", "blend_bwd"):
-            fl = FLOP_TEST * evaluated + (FLOP_FWD_BLEND if st == "blend_fwd" else FLOP_BWD_BLEND) * blended
-            ach = fl / (ms * 1e-3) / 1e12
-            v = valu_of(st, ms)
-            stage_roof[st] = {"bound": "alu", "achieved": round(ach, 2), "unit": "TFLOP/s",
-                              "frac": round(ach / PEAK_FP32_TFLOPS, 4),
-                              "valu_issue_frac": v["issue_frac"] if v else None}
-            bound_ms += fl / (PEAK_FP32_TFLOPS * 1e12) * 1e3
-        else:
-            by = stage_bytes(st, scene.n, len(cams8), pairs8, npix8, nt8, geom_bytes, scene.k, tile_bits)
-            ach = by / (ms * 1e-3) / 1e9
-            stage_roof[st] = {"bound": "hbm", "achieved": round(ach, 1), "unit": "GB/s",
-                              "frac": round(ach / PEAK_HBM_GBS, 4), "frac_of_copy": round(ach / hbm_copy["GBps"], 4),
-                              "bytes": int(by)}
-            bound_ms += by / (PEAK_HBM_GBS * 1e9) * 1e3
-    path_roof = {"bound_ms": round(bound_ms, 4), "measured_ms": round(sum(stage_ms.values()), 4),
-                 "frac": round(bound_ms / sum(stage_ms.values()), 4)}
+    dyn_per_view = (batched_fb_peak - before) / len(cams8)
 
     out = {
         "metric": "fwd+bwd Mpixel/s at 1M Gaussians 1080p, peak VRAM; FP16-batched vs FP32 plain",
@@ -510,7 +607,8 @@ def main():
                    "batch": cfg.batch, "waves": cfg.waves, "subtile": cfg.subtile, "storage": "f16/f16/bf16",
                    "pairs": pairs8},
         "peak_vram_mb": {"forward": round(batched_fwd_peak / 1e6, 1), "forward_backward": round(batched_fb_peak / 1e6, 1),
-                         "static_params": round(static16 / 1e6, 1)},
+                         "static_params": round(static16 / 1e6, 1), "resident_before": round(before / 1e6, 1),
+                         "dynamic_per_view": round(dyn_per_view / 1e6, 1)},
         "plain_fp32": {"value": round(npix1 / ms_plain / 1e3, 2), "unit": "Mpixel/s", "ms_per_step": round(ms_plain, 4),
                        "workload": f"{scene.n} clustered Gaussians, FP32, 1 view 1920x1080, eager",
                        "pairs": plain_pairs,
@@ -525,11 +623,17 @@ def main():
         "roofline": roof,
         "hbm_copy": hbm_copy,
     }
+    del ds16
+    torch.cuda.empty_cache()
     if not args.no_post:
-        del ds16
-        torch.cuda.empty_cache()
         out["post_processing"] = post_processing(args, cfg)
         out["colour_models"] = colour_models(args, cfg, scene, cams1)
+    if not args.no_workloads:
+        out["workloads"] = {
+            "clustered_200k_720p": workload_line(args, "clustered_200k_720p", cfg, False, hbm_copy),
+            "batched_500k_16views": workload_line(args, "batched_500k_16views", cfg, True, hbm_copy, autotune=True),
+            "fp16_3m_8x1080p": workload_line(args, "fp16_3m_8x1080p", cfg, True, hbm_copy),
+        }
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         small, cams_small = S.make_workload("small_2k_128px")

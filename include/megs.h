@@ -272,9 +272,13 @@ void megs_graph_destroy(megs_graph *graph);
  * (16,2,0), (16,4,0), (32,1,0), (32,2,0), (32,4,0), (16,1,8), (32,1,8)} x batch in
  * {32, 64, 128, 256} on the given views (1 warm-up and `reps` timed runs each, HIP events on
  * `stream`) and writes the fastest configuration to *best (flags and pair_capacity copied from
- * *base). Images are independent of the choice up to FP32 rounding (the footprint lies inside the
- * listed tiles), so the choice changes speed only. ms_out (nullable) receives
- * MEGS_AUTOTUNE_CANDIDATES timings in that order, batch fastest-varying. */
+ * *base). The sub-tile blends (subtile 8) stage no batches: each of those two candidates is timed
+ * once, with batch 64, and its timing reported for all four batch sizes. Images are independent of
+ * the choice up to FP32 rounding (the footprint lies inside the listed tiles), so the choice changes
+ * speed only. ms_out (nullable) receives MEGS_AUTOTUNE_CANDIDATES timings in that order, batch
+ * fastest-varying. Working memory: every run of the sweep reuses the same blocks, taken from alloc
+ * once for the largest candidate (8x8 tiles, timed first) and again only if a later one needs more,
+ * so the sweep holds about one forward+backward's memory. */
 #define MEGS_AUTOTUNE_CANDIDATES 36
 megs_status megs_autotune(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
                           const megs_config *base, megs_alloc_fn alloc, void *alloc_ctx,

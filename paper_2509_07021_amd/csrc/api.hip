@@ -7,6 +7,7 @@
 
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "megs_internal.hpp"
@@ -643,6 +644,36 @@ void* scratch_take(void* ctx, size_t bytes) {
     return p;
 }
 
+// Working memory of the autotuner's sweep. Every forward+backward asks for the same sequence of blocks
+// (frame, pair table, backward scratch), so the k-th request of a run reuses the pool's k-th block and
+// asks the caller for a larger one only when a candidate needs more (the caller's allocator never frees:
+// the smaller block stays with it). The sweep runs the largest candidate first, so the pool's size is
+// one candidate's working memory, not the sum over the sweep. All runs go to one stream, so a block is
+// reused only after the run before has finished with it.
+struct SweepPool {
+    megs_alloc_fn alloc;
+    void* ctx;
+    std::vector<std::pair<void*, size_t>> blocks;
+    size_t next;
+    bool failed;
+};
+
+void* sweep_take(void* ctx, size_t bytes) {
+    SweepPool* p = static_cast<SweepPool*>(ctx);
+    const size_t k = p->next++;
+    if (k < p->blocks.size() && p->blocks[k].second >= bytes) return p->blocks[k].first;
+    void* m = p->alloc(p->ctx, bytes);
+    if (bad_alloc(m)) {
+        p->failed = true;
+        return nullptr;
+    }
+    if (k < p->blocks.size())
+        p->blocks[k] = {m, bytes};
+    else
+        p->blocks.push_back({m, bytes});
+    return m;
+}
+
 }  // namespace
 
 struct megs_graph {
@@ -1028,12 +1059,15 @@ megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int3
                           megs_alloc_fn alloc, void* alloc_ctx, float* images, const float* dl_dimages,
                           megs_scene_grad* grads, int32_t reps, void* stream, megs_config* best, float* ms_out) {
     g_err[0] = 0;
-    if (!base || !best || !dl_dimages) return fail(MEGS_ERR_ARG, "null base config, best or dL/dimage");
+    if (!base || !best || !dl_dimages || !alloc) return fail(MEGS_ERR_ARG, "null base config, best, dL/dimage or allocator");
     if (reps < 1) reps = 1;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // 8x8 tiles first: they list the most pairs and tiles, so the working memory they take is reused by
+    // every later candidate (SweepPool)
     const int combos[9][3] = {{8, 1, 0},  {16, 1, 0}, {16, 2, 0}, {16, 4, 0}, {32, 1, 0},
                               {32, 2, 0}, {32, 4, 0}, {16, 1, 8}, {32, 1, 8}};
     const int batches[4] = {32, 64, 128, 256};
+    SweepPool pool{alloc, alloc_ctx, {}, 0, false};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1046,13 +1080,20 @@ megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int3
             c.waves = combos[ci][1];
             c.subtile = combos[ci][2];
             c.batch = batches[bi];
+            // the sub-tile blends stage no batches: one timing serves all four batch sizes
+            if (c.subtile && bi > 0) {
+                if (ms_out) ms_out[ci * 4 + bi] = ms_out[ci * 4];
+                continue;
+            }
+            if (c.subtile) c.batch = 64;
             float ms_total = 0.f;
             for (int r = 0; r <= reps && result == MEGS_OK; ++r) {
                 megs_state st;
+                pool.next = 0;  // every run reuses the pool's blocks from the start
                 if (r > 0) (void)hipEventRecord(e0, s);
-                result = megs_render_forward(scene, cams, n_views, &c, alloc, alloc_ctx, images, &st, stream);
+                result = megs_render_forward(scene, cams, n_views, &c, sweep_take, &pool, images, &st, stream);
                 if (result == MEGS_OK)
-                    result = megs_render_backward(scene, cams, n_views, &c, &st, dl_dimages, alloc, alloc_ctx, grads,
+                    result = megs_render_backward(scene, cams, n_views, &c, &st, dl_dimages, sweep_take, &pool, grads,
                                                   stream);
                 if (r > 0 && result == MEGS_OK) {
                     (void)hipEventRecord(e1, s);
@@ -1062,6 +1103,7 @@ megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int3
                     ms_total += ms;
                 }
             }
+            if (pool.failed) result = fail(MEGS_ERR_ALLOC, "allocation failed or not 256-byte aligned during the sweep");
             const float ms = ms_total / reps;
             if (ms_out) ms_out[ci * 4 + bi] = ms;
             if (result == MEGS_OK && ms < best_ms) {

@@ -337,9 +337,53 @@ class Graph:
             pass
 
 
-def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps: int = 2, dl_images=None):
+def autotune_key(dscene: DeviceScene, cams: Sequence, base: Config, arch: str) -> str:
+    """The cache key of an autotuning: the GPU architecture and everything about the work that the
+    timings depend on (scene size, lobes, storage dtypes, masks, layout, colour model, flags, and each
+    view's resolution)."""
+    views = ",".join(f"{int(c.width)}x{int(c.height)}" for c in cams)
+    return (f"{arch}|n={dscene.n}|k={dscene.k}|dt={'/'.join(dscene.dt)}|pmask={int(dscene.has_pmask)}"
+            f"|lmask={int(dscene.has_lmask)}|ragged={int(dscene.ragged)}|sh={dscene.sh_degree if dscene.planes.get('sh') is not None else -1}"
+            f"|flags={int(base.flags)}|views={views}")
+
+
+def _load_cache(path: str) -> dict:
+    import json
+    import os
+    if not path or not os.path.exists(path):
+        return {}
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(path: str, key: str, entry: dict) -> None:
+    import json
+    import os
+    d = _load_cache(path)
+    d[key] = entry
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps: int = 2, dl_images=None,
+             cache: Optional[str] = None, stats: Optional[dict] = None):
     """Times every (tile, waves, subtile) of AUTOTUNE_COMBOS x batch {32, 64, 128, 256}; returns
-    (best Config, ms table [combo][batch])."""
+    (best Config, ms table [combo][batch]). With `cache` (a JSON file path), a result stored under
+    this GPU architecture and work (autotune_key) is returned without timing (table None), and a new
+    result is stored there. `stats` (a dict) receives the sweep's device memory in bytes."""
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    key = autotune_key(dscene, cams, base, arch)
+    if cache:
+        hit = _load_cache(cache).get(key)
+        if hit:
+            return Config(int(hit["tile"]), int(hit["batch"]), base.flags, base.pair_capacity, int(hit["waves"]),
+                          int(hit["subtile"])), None
     lib = L.load()
     npix = sum(h * w for h, w in image_sizes(cams))
     images = torch.empty(3 * npix, dtype=torch.float32, device="cuda")
@@ -356,8 +400,14 @@ def autotune(dscene: DeviceScene, cams: Sequence, base: Config = Config(), reps:
     L.check(lib.megs_autotune(ctypes.byref(sc), cam_arr, len(cams), ctypes.byref(c), alloc.fn, None,
                               images.data_ptr(), dl.data_ptr(), ctypes.byref(g), reps, _stream(None),
                               ctypes.byref(best), ms))
+    if stats is not None:
+        stats["sweep_bytes"] = alloc.nbytes()
     table = np.array(list(ms), np.float32).reshape(len(L.AUTOTUNE_COMBOS), len(L.AUTOTUNE_BATCHES))
-    return Config(best.tile, best.batch, best.flags, best.pair_capacity, best.waves, best.subtile), table
+    cfg = Config(best.tile, best.batch, best.flags, best.pair_capacity, best.waves, best.subtile)
+    if cache:
+        _store_cache(cache, key, {"tile": cfg.tile, "batch": cfg.batch, "waves": cfg.waves, "subtile": cfg.subtile,
+                                  "ms": float(table.min())})
+    return cfg, table
 
 
 class Profile:

@@ -127,6 +127,39 @@ def gpu_records(g: dict) -> dict:
             "radius": g["radius"].astype(np.int32), "cutoff": g["cutoff"].astype(np.float64)}
 
 
+def check_records(g: dict, rec: dict) -> None:
+    """Records against the oracle's (g: the GPU's record planes, rec: the oracle's records, same rows).
+    The conic is formed in FP64 and kept as FP32 diagonal factors and an FP64 ratio (the record's
+    chol plane, conic = L L'), so it is accurate whatever its condition number: the factors are
+    checked against the Cholesky factors of the oracle's FP64 conic, and the FP32 conic plane
+    against that conic."""
+    valid_o = rec["valid"].astype(bool)
+    valid_g = g["radius"] >= 0
+    assert np.array_equal(valid_o, valid_g), f"{np.sum(valid_o != valid_g)} culling decisions differ"
+    v = valid_g
+    np.testing.assert_allclose(g["mean"][v, 0], rec["u"][v], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(g["mean"][v, 1], rec["v"][v], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(g["rgbd"][v, 3], rec["depth"][v], rtol=1e-6)
+    np.testing.assert_allclose(g["conic_o"][v, :3], rec["conic"][v], rtol=2e-5,
+                               atol=2e-5 * np.abs(rec["conic"][v]).max())
+    # the factors: l11 = sqrt(a), r = b / a, l22 = sqrt(c - b^2 / a) of the oracle's conic (a, b, c)
+    oc = rec["conic"][v]
+    l11 = np.sqrt(oc[:, 0])
+    ratio = oc[:, 1] / oc[:, 0]
+    l22 = np.sqrt((oc[:, 0] * oc[:, 2] - oc[:, 1] ** 2) / oc[:, 0])
+    ch = g["chol"][v]
+    np.testing.assert_allclose(ch[:, 0], l11, rtol=2e-6)
+    np.testing.assert_allclose(ch[:, 2], l22, rtol=2e-6)
+    # the ratio carries the footprint's direction: relative to the factors' own precision it is exact
+    rerr = np.abs(ch[:, 1] - ratio) / (1.0 + np.abs(ratio))
+    assert rerr.max() <= 2e-6, f"factor ratio error {rerr.max():.2e}"
+    np.testing.assert_allclose(g["conic_o"][v, 3], rec["o"][v], rtol=2e-6)
+    np.testing.assert_allclose(g["rgbd"][v, :3], rec["rgb"][v], rtol=0, atol=2e-6)
+    dr = np.abs(g["radius"][v] - rec["radius"][v])
+    assert dr.max() <= 1 and (dr > 0).mean() < 1e-3
+    np.testing.assert_allclose(g["cutoff"][v], rec["cutoff"][v], rtol=1e-5, atol=1e-5)
+
+
 def view_pixels(cams, vi):
     off = sum(c.width * c.height for c in cams[:vi])
     return off, cams[vi].width * cams[vi].height

@@ -10,8 +10,8 @@ from paper_2509_07021_amd import _lib as L
 from paper_2509_07021_amd import render as R
 from paper_2509_07021_amd import scenes as S
 
-from gpu_util import (IMG_TOL, check_key_table, grad2d_buffer, grad2d_from_moments, grad_close, gpu_records, gpu_run,
-                      log)
+from gpu_util import (IMG_TOL, check_key_table, check_records, grad2d_buffer, grad2d_from_moments, grad_close,
+                      gpu_records, gpu_run, log)
 
 pytestmark = pytest.mark.gpu
 
@@ -96,14 +96,30 @@ def test_persistent_queue_matches_one_group_per_tile():
                 grad_close(f"persistent {p}", gb[p].astype(np.float64), ga[p].astype(np.float64))
 
 
-def test_autotuner_picks_a_valid_config_with_the_same_images():
+def test_autotuner_picks_a_valid_config_with_the_same_images(tmp_path):
     scene, cams = _uneven()
     ds = R.DeviceScene.from_scene(scene)
-    best, table = R.autotune(ds, cams, R.Config(16, 64), reps=1)
-    log(f"autotune best tile {best.tile} batch {best.batch}\n{table}")
+    stats = {}
+    cache = str(tmp_path / "autotune.json")
+    best, table = R.autotune(ds, cams, R.Config(16, 64), reps=1, cache=cache, stats=stats)
+    log(f"autotune best tile {best.tile} batch {best.batch}, sweep memory {stats['sweep_bytes']} B\n{table}")
     assert (best.tile, best.waves, best.subtile) in L.AUTOTUNE_COMBOS and best.batch in L.AUTOTUNE_BATCHES
     assert table.shape == (len(L.AUTOTUNE_COMBOS), len(L.AUTOTUNE_BATCHES))
     assert np.all(np.isfinite(table)) and np.all(table > 0)
+    # the sub-tile candidates stage no batches: one timing for all four batch sizes
+    for i, combo in enumerate(L.AUTOTUNE_COMBOS):
+        if combo[2]:
+            assert np.all(table[i] == table[i, 0])
+    # the sweep reuses one forward+backward's memory (its largest candidate, 8x8 tiles), not 36 x 2 of them
+    fr = R.forward(ds, cams, R.Config(8, 64))
+    npix = sum(c.width * c.height for c in cams)
+    R.backward(ds, fr, torch.ones(3 * npix, device="cuda"))
+    torch.cuda.synchronize()
+    assert stats["sweep_bytes"] <= 1.01 * fr.alloc.nbytes(), (stats["sweep_bytes"], fr.alloc.nbytes())
+    # a second call finds the result in the cache (keyed by architecture and work) and times nothing
+    cached, t2 = R.autotune(ds, cams, R.Config(16, 64), reps=1, cache=cache)
+    assert t2 is None and (cached.tile, cached.batch, cached.waves, cached.subtile) == \
+        (best.tile, best.batch, best.waves, best.subtile)
     a = R.forward(ds, cams, R.Config(16, 64)).images.cpu().numpy()
     b = R.forward(ds, cams, best).images.cpu().numpy()
     d = np.abs(a - b)
@@ -118,30 +134,64 @@ def _sampled_tiles(ranges, frac, seed):
     return pick, rs
 
 
-def _full_size_sampled(scene, cams, cfg, frac, seed):
-    """A full-size workload in a given launch configuration: the whole key table bit-exact against
-    the oracle's (built from the GPU's own records); blend, blend backward and projection backward
-    on a seeded sample of tiles (the loss weights vanish outside them, so the GPU's gradients come
-    from the same pixels)."""
+RECORD_FIELDS = (("mean", 2, torch.float64), ("conic_o", 4, torch.float32), ("rgbd", 4, torch.float32),
+                 ("radius", 1, torch.int32), ("cutoff", 1, torch.float32), ("chol", 4, torch.float64))
+
+
+def _check_sampled_records(buf, scene, cams, tile, count, seed):
+    """The records of a seeded sample of Gaussians, in every view, against the oracle's projection of
+    the same Gaussians (read from their stored values)."""
+    n, nv = scene.n, len(cams)
+    idx = np.sort(np.random.default_rng(seed).choice(n, size=min(count, n), replace=False))
+    sub = scene.subset(idx).widened()
+    for vi, cam in enumerate(cams):
+        rows = vi * n + idx
+        g = {}
+        for name, width, dt in RECORD_FIELDS:
+            t = buf(name, width * n * nv, dt).view(n * nv, width) if width > 1 else buf(name, n * nv, dt)
+            g[name] = t[torch.from_numpy(rows).to(t.device)].cpu().numpy()
+        check_records(g, O.project(sub, scene.k, cam, tile))
+    log(f"records of {len(idx)} sampled Gaussians in {nv} views against the oracle's projection")
+
+
+def _full_size_sampled(scene, cams, cfg, frac, seed, graph=False, record_sample=20_000):
+    """A full-size workload in a given launch configuration, eager or as one captured hipGraph
+    (forward and backward of all views in one replay): the records of a seeded sample of Gaussians
+    against the oracle's projection, the whole key table bit-exact against the oracle's (built from the
+    GPU's own records); blend, blend backward and projection backward on a seeded sample of tiles (the
+    loss weights vanish outside them, so the GPU's gradients come from the same pixels)."""
     tile = cfg.tile
     nv = len(cams)
     ds = R.DeviceScene.from_scene(scene)
+    npix = sum(c.width * c.height for c in cams)
     # the per-field record planes are read back below: requesting them only adds their writes
-    fr = R.forward(ds, cams, dataclasses.replace(cfg, flags=cfg.flags | L.MEGS_FLAG_RECORD_PLANES))
+    rcfg = dataclasses.replace(cfg, flags=cfg.flags | L.MEGS_FLAG_RECORD_PLANES)
+    fr = R.forward(ds, cams, rcfg)
     torch.cuda.synchronize()
-    g = {"n_pairs": int(fr.state.n_pairs)}
+    P = int(fr.state.n_pairs)
+    if graph:
+        G = R.Graph(ds, cams, dataclasses.replace(rcfg, pair_capacity=P + P // 20 + 1024), with_backward=True)
+        G.launch()
+        assert G.status() == P
+        np.testing.assert_array_equal(G.images.cpu().numpy(), fr.images.cpu().numpy())  # replay == eager
+        state, alloc, images_flat = G.state, G.alloc, G.images
+        log(f"graph: forward+backward of {nv} views in one replay, {P} pairs")
+    else:
+        state, alloc, images_flat = fr.state, fr.alloc, fr.images
+    buf = lambda field, count, dtype: alloc.view(getattr(state, field), count, dtype)
+    _check_sampled_records(buf, scene, cams, tile, record_sample, seed + 50)
+    g = {"n_pairs": P}
     nr = scene.n * nv
-    g["mean"] = fr.buffer("mean", 2 * nr, torch.float64).view(nr, 2).cpu().numpy()
-    g["conic_o"] = fr.buffer("conic_o", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
-    g["rgbd"] = fr.buffer("rgbd", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
-    g["radius"] = fr.buffer("radius", nr, torch.int32).cpu().numpy()
-    g["cutoff"] = fr.buffer("cutoff", nr, torch.float32).cpu().numpy()
-    g["chol"] = fr.buffer("chol", 4 * nr, torch.float64).view(nr, 4).cpu().numpy()
-    P = g["n_pairs"]
-    vals = fr.buffer("vals", P, torch.int32).cpu().numpy().view(np.uint32)
-    tkeys = fr.buffer("tile_keys", P, torch.int32).cpu().numpy().view(np.uint32)
-    T = int(fr.state.n_tiles)
-    ranges = fr.buffer("ranges", 2 * T, torch.int32).view(T, 2).cpu().numpy().view(np.uint32)
+    g["mean"] = buf("mean", 2 * nr, torch.float64).view(nr, 2).cpu().numpy()
+    g["conic_o"] = buf("conic_o", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
+    g["rgbd"] = buf("rgbd", 4 * nr, torch.float32).view(nr, 4).cpu().numpy()
+    g["radius"] = buf("radius", nr, torch.int32).cpu().numpy()
+    g["cutoff"] = buf("cutoff", nr, torch.float32).cpu().numpy()
+    g["chol"] = buf("chol", 4 * nr, torch.float64).view(nr, 4).cpu().numpy()
+    vals = buf("vals", P, torch.int32).cpu().numpy().view(np.uint32)
+    tkeys = buf("tile_keys", P, torch.int32).cpu().numpy().view(np.uint32)
+    T = int(state.n_tiles)
+    ranges = buf("ranges", 2 * T, torch.int32).view(T, 2).cpu().numpy().view(np.uint32)
     rec = gpu_records(g)
     log(f"key table: {P} pairs over {nv} views")
     cnt = check_key_table(vals, ranges, rec, g["rgbd"][:, 3], cams, tile, scene.n, tile_keys=tkeys,
@@ -150,8 +200,8 @@ def _full_size_sampled(scene, cams, cfg, frac, seed):
     off = O.tile_layout(cams, tile)
     pick, rs = _sampled_tiles(ranges, frac, seed)
     log(f"blend on {pick.sum()} sampled tiles")
-    images = R.split_images(fr.images, cams)
-    weights, oks = [], []
+    images = R.split_images(images_flat, cams)
+    weights, checked = [], 0
     for vi, cam in enumerate(cams):
         ob = O.blend(cam, tile, rec, vals, rs[off[vi]:off[vi + 1]])
         img = images[vi].cpu().numpy().astype(np.float64)
@@ -159,14 +209,25 @@ def _full_size_sampled(scene, cams, cfg, frac, seed):
         ys, xs = np.mgrid[0:cam.height, 0:cam.width]
         in_pick = pick[off[vi]:off[vi + 1]][(ys // tile) * tx + xs // tile]
         ok = in_pick & (ob["flag"] == 0)
-        assert ok.sum() > 2000
-        assert np.abs(img - ob["image"])[:, ok].max() <= IMG_TOL, vi
+        checked += int(ok.sum())
+        if ok.any():
+            assert np.abs(img - ob["image"])[:, ok].max() <= IMG_TOL, vi
         weights.append(S.loss_weights([cam], 21 + vi)[0] * ok[None].astype(np.float32))
-    nb = len(fr.alloc.blocks)
+    assert checked > 0.3 * frac * npix, (checked, npix)
+    log(f"blend: {checked} pixels of the sampled tiles against the oracle")
     dl = torch.from_numpy(np.concatenate([w.reshape(-1) for w in weights])).cuda()
-    grads = R.backward(ds, fr, dl)
-    torch.cuda.synchronize()
-    g2 = grad2d_from_moments(grad2d_buffer(fr.alloc.blocks[nb], nr), g["chol"], rec["o"])
+    assert dl.numel() == 3 * npix
+    if graph:
+        G.dl.copy_(dl)  # the graph reads dL/dimage in place at every replay
+        G.launch()
+        G.stream.synchronize()
+        grads = G.grads
+        g2 = grad2d_from_moments(grad2d_buffer(G.alloc.blocks[2], nr), g["chol"], rec["o"])
+    else:
+        nb = len(fr.alloc.blocks)
+        grads = R.backward(ds, fr, dl)
+        torch.cuda.synchronize()
+        g2 = grad2d_from_moments(grad2d_buffer(fr.alloc.blocks[nb], nr), g["chol"], rec["o"])
     ref = np.zeros_like(g2)
     ref_abs = np.zeros_like(g2)
     for vi, cam in enumerate(cams):
@@ -180,6 +241,8 @@ def _full_size_sampled(scene, cams, cfg, frac, seed):
     for p in O.PLANES:
         if gr[p] is not None:
             grad_close(f"raw {p}", grads[p].cpu().numpy().astype(np.float64), gr[p])
+    if graph:
+        G.close()
 
 
 def test_full_size_masked_1m_1080p_sampled():
@@ -254,3 +317,18 @@ def test_packed_depth_order_with_escaped_counts_full_size():
     k1 = one.buffer("keys64", P, torch.int64).cpu().numpy().view(np.uint64)
     np.testing.assert_array_equal((k1 >> np.uint64(32)).astype(np.uint32), t2.view(np.uint32))
     np.testing.assert_array_equal(one.buffer("ranges", 2 * T, torch.int32).cpu().numpy(), r2)
+
+
+def test_batched_500k_16views_graph_autotuned():
+    """The batched workload at its real shape: 500k clustered Gaussians, 16 views of uneven resolution
+    (360p to 1080p) on a ring, forward and backward of all views in one hipGraph replay, at the launch
+    configuration the autotuner picks; checked as the other full-size workloads (sampled records, the
+    whole key table, blend and gradients on 2% of the tiles)."""
+    scene, cams = S.make_workload("batched_500k_16views")
+    ds = R.DeviceScene.from_scene(scene)
+    best, table = R.autotune(ds, cams, R.Config(16, 64), reps=1)
+    del ds
+    torch.cuda.empty_cache()
+    log(f"autotuned for 500k x 16 views: tile {best.tile} waves {best.waves} subtile {best.subtile} "
+        f"batch {best.batch} ({float(np.nanmin(table)):.3f} ms)")
+    _full_size_sampled(scene, cams, best, 0.02, 8, graph=True)
