@@ -177,8 +177,8 @@ typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
  *   ranges    uint32[T][2]   [start, end) of each tile in vals; (0, 0) when empty
  *   T_final   float[NP]      final transmittance per pixel
  *   last      uint32[NP]     1 + position (within its tile's list) of the last blended fragment
- *   device_status int32[8]   [0] pairs counted, [1] overflow flag, [2] malformed lobe offsets
- *                            (compressed-row scenes), [3] reserved,
+ *   device_status int32[8]   [0] pairs counted (at most 2^31 - 1), [1] overflow flag, [2] malformed
+ *                            lobe offsets (compressed-row scenes), [3] culled records,
  *                            [4..5] uint64 blended fragments, [6..7] uint64 evaluated fragments
  *                            (written only with MEGS_FLAG_STATS)
  */
@@ -206,7 +206,8 @@ typedef struct {
 /*
  * Forward render of n_views views (front-to-back compositing, Sec. 3.1; SG colour, Sec. 3.2).
  * images: device float[3 * NP], written. state: host struct, filled. Returns MEGS_OK or an
- * error status; with pair_capacity == 0 it synchronises the stream once to size the pair table.
+ * error status; with pair_capacity == 0 it synchronises the stream once to size the pair table,
+ * and returns MEGS_ERR_CAPACITY when the records list more than 2^31 - 1 tile pairs.
  */
 megs_status megs_render_forward(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
                                 const megs_config *cfg, megs_alloc_fn alloc, void *alloc_ctx,
@@ -245,9 +246,23 @@ megs_status megs_render_backward(const megs_scene *scene, const megs_camera *cam
                                  megs_scene_grad *grads, void *stream);
 
 /* Reads state->device_status (synchronises the stream). Returns MEGS_ERR_CAPACITY when the
- * pair table overflowed and MEGS_ERR_ARG when compressed-row lobe offsets were malformed;
- * *pairs_needed receives the counted pairs (may be NULL). */
+ * pair table overflowed (its capacity, or 2^31 - 1 pairs, the most a key table holds: its positions
+ * are 32-bit) and MEGS_ERR_ARG when compressed-row lobe offsets were malformed; *pairs_needed receives
+ * the counted pairs (may be NULL). */
 megs_status megs_state_status(const megs_state *state, int64_t *pairs_needed, void *stream);
+
+/* The forward's counts (synchronises the stream): pairs the records list (saturated at 2^31 - 1),
+ * records the projection culled (behind the near plane, anything non-finite, a zero quaternion or lobe
+ * axis, effective opacity below 1/255, a mean or radius beyond 1e7 pixels, malformed compressed-row
+ * lobes: the record takes part in no view's image), and the overflow and malformed-lobes flags. Records
+ * that are valid but reach no tile of their view are not culled. */
+typedef struct {
+    int64_t pairs_needed;
+    int64_t culled;
+    int32_t overflow;
+    int32_t bad_lobes;
+} megs_counts;
+megs_status megs_state_counts(const megs_state *state, megs_counts *out, void *stream);
 
 /*
  * Batched form: forward (and optionally backward) of all views captured once into a hipGraph

@@ -31,7 +31,7 @@ EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", 
             "megs_autotune", "megs_profile_begin", "megs_profile_end", "megs_last_error", "megs_version",
             "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply", "megs_dual_update",
             "megs_penalty_grad", "megs_compact", "megs_photometric_loss", "megs_adam_step",
-            "megs_render_forward_noalloc")
+            "megs_render_forward_noalloc", "megs_state_counts")
 
 PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
           "base", "axis", "sharp", "amp", "lmask_logit")
@@ -78,6 +78,11 @@ class MegsState(ctypes.Structure):
                 ("det_offsets", _vp), ("det_count", _vp), ("packed", _vp), ("chol", _vp)]
 
 
+class MegsCounts(ctypes.Structure):
+    _fields_ = [("pairs_needed", ctypes.c_int64), ("culled", ctypes.c_int64), ("overflow", ctypes.c_int32),
+                ("bad_lobes", ctypes.c_int32)]
+
+
 class MegsProfile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * len(STAGES)), ("count", ctypes.c_int64 * len(STAGES))]
 
@@ -109,6 +114,7 @@ def load():
     L.megs_render_backward.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), P(MegsState),
                                        _vp, ALLOC_FN, _vp, P(MegsSceneGrad), _vp]
     L.megs_state_status.argtypes = [P(MegsState), P(ctypes.c_int64), _vp]
+    L.megs_state_counts.argtypes = [P(MegsState), P(MegsCounts), _vp]
     L.megs_graph_create.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ALLOC_FN, _vp,
                                     _vp, _vp, P(MegsSceneGrad), ctypes.c_int32, _vp, P(_vp)]
     L.megs_graph_launch.argtypes = [_vp, _vp]
@@ -134,7 +140,8 @@ def load():
                                  ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp]
     L.megs_profile_begin.argtypes = []
     L.megs_profile_end.argtypes = [P(MegsProfile)]
-    for f in ("megs_render_forward", "megs_render_forward_noalloc", "megs_render_backward", "megs_state_status", "megs_graph_create",
+    for f in ("megs_render_forward", "megs_render_forward_noalloc", "megs_state_counts", "megs_render_backward",
+              "megs_state_status", "megs_graph_create",
               "megs_graph_launch", "megs_graph_status", "megs_autotune", "megs_profile_begin", "megs_profile_end",
               "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply",
               "megs_dual_update", "megs_penalty_grad", "megs_compact", "megs_photometric_loss",

@@ -593,6 +593,9 @@ megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t 
         HIP_TRY(hipMemcpyAsync(flags, f.status, sizeof(flags), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (flags[kStatusBadLobes]) return fail(MEGS_ERR_ARG, "malformed lobe_off (compressed-row lobes)");
+        if (total > kMaxPairs)
+            return fail(MEGS_ERR_CAPACITY, "the records list %s%u tile pairs; a key table holds at most %u",
+                        total == 0xffffffffu ? "at least " : "", total, kMaxPairs);
         counted = total;
         cap = total;
     }
@@ -981,6 +984,20 @@ megs_status megs_state_status(const megs_state* state, int64_t* pairs_needed, vo
     if (h[kStatusBadLobes]) return fail(MEGS_ERR_ARG, "malformed lobe_off (compressed-row lobes)");
     if (h[1]) return fail(MEGS_ERR_CAPACITY, "pair table overflow: %u pairs counted, capacity %lld", (uint32_t)h[0],
                           (long long)state->pair_capacity);
+    return MEGS_OK;
+}
+
+megs_status megs_state_counts(const megs_state* state, megs_counts* out, void* stream) {
+    g_err[0] = 0;
+    if (!state || !state->device_status || !out) return fail(MEGS_ERR_ARG, "null state or output");
+    int32_t h[4] = {0, 0, 0, 0};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(h, state->device_status, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out->pairs_needed = (int64_t)(uint32_t)h[0];
+    out->culled = (int64_t)(uint32_t)h[kStatusCulled];
+    out->overflow = h[kStatusOverflow] != 0;
+    out->bad_lobes = h[kStatusBadLobes] != 0;
     return MEGS_OK;
 }
 

@@ -47,10 +47,14 @@ struct ViewInfo {
     int64_t pix_off;   // first pixel (over all views) of the view
 };
 
+// The most pairs a key table holds: positions are 32-bit and the counted total is reported in an int32.
+constexpr uint32_t kMaxPairs = 0x7fffffffu;
+
 // Words of the per-forward device status block (int32[8]).
 constexpr int kStatusPairs = 0;     // pairs counted
 constexpr int kStatusOverflow = 1;  // pair table overflowed its capacity
 constexpr int kStatusBadLobes = 2;  // some compressed-row lobe offsets were malformed
+constexpr int kStatusCulled = 3;    // records the projection culled (not rendered in their view)
 
 struct SceneDev {
     int64_t n;

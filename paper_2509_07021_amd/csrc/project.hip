@@ -433,6 +433,11 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
             }
         }
         rec.ntiles[r] = nt;
+        if (sc.status) {  // culled records, one atomic per wave (the lanes here are the wave's Gaussians)
+            const uint64_t culled = __ballot(!ok);
+            if (culled && __lane_id() == (unsigned)__builtin_ctzll(__ballot(true)))
+                atomicAdd(&sc.status[kStatusCulled], (int32_t)__popcll(culled));
+        }
         dst[3] = make_float4(rx, ry, __int_as_float(ok ? p.radius : -1), __uint_as_float(nt));
         rec.dkey[r] = nt ? __float_as_uint(p.tzf) : 0xffffffffu;
         if (rec.order0) {

@@ -69,6 +69,22 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* lds
     return wbase + inc - x;
 }
 
+// Sum of the 256 threads' values in 64 bits (every thread receives it). The tile counts are summed in
+// 32 bits everywhere else; these wider sums only detect a total that 32 bits cannot hold.
+__device__ __forceinline__ uint64_t block_sum64(uint64_t x, uint64_t* lds4) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    __syncthreads();
+    if (__lane_id() == 0) lds4[threadIdx.x / kWave] = x;
+    __syncthreads();
+    const uint64_t t = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+    __syncthreads();
+    return t;
+}
+
+// A 64-bit sum as a 32-bit word, saturated: a total of 2^32 - 1 or more reads as 0xffffffff.
+__device__ __forceinline__ uint32_t sat32(uint64_t x) { return x > 0xffffffffull ? 0xffffffffu : (uint32_t)x; }
+
 __device__ __forceinline__ uint32_t scan_load(const uint32_t* x, const uint32_t* idx, int64_t i, int64_t n) {
     if (i >= n) return 0u;
     return x[idx ? idx[i] : i];
@@ -78,31 +94,36 @@ __device__ __forceinline__ uint32_t scan_load(const uint32_t* x, const uint32_t*
 // to `gathered` (when given), so the second pass reads them without gathering again.
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* x, const uint32_t* idx, int64_t n,
                                                               uint32_t* partial, uint32_t* gathered) {
-    __shared__ uint32_t lds[4];
+    __shared__ uint64_t lds[4];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    uint32_t s = 0;
+    uint64_t s = 0;
     for (int j = 0; j < kScanIpt; ++j) {
         const int64_t i = base + j * kScanThreads + threadIdx.x;
         const uint32_t v = scan_load(x, idx, i, n);
         if (gathered && i < n) gathered[i] = v;
         s += v;
     }
-    uint32_t total;
-    block_excl_scan256(s, lds, total);
-    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+    const uint64_t total = block_sum64(s, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sat32(total);
 }
 
-// Single workgroup: exclusive scan of partial[0..m) in place; writes the grand total.
+// Single workgroup: exclusive scan of partial[0..m) in place; writes the grand total, saturated at
+// 0xffffffff (sat32: a total 32 bits cannot hold, which the pair count check then refuses; the 32-bit
+// offsets written here are then meaningless).
 __global__ __launch_bounds__(kScanThreads) void k_scan_top(uint32_t* partial, int64_t m, uint32_t* total_out) {
     __shared__ uint32_t lds[4];
+    __shared__ uint64_t lds64[4];
     uint32_t carry = 0;
+    uint64_t carry64 = 0;
     for (int64_t base = 0; base < m; base += kScanTile) {
         uint32_t v[kScanIpt];
         uint32_t s = 0;
+        uint64_t s64 = 0;
         for (int j = 0; j < kScanIpt; ++j) {
             int64_t i = base + threadIdx.x * kScanIpt + j;
             v[j] = i < m ? partial[i] : 0u;
             s += v[j];
+            s64 += v[j];
         }
         uint32_t total;
         uint32_t ex = block_excl_scan256(s, lds, total) + carry;
@@ -112,8 +133,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(uint32_t* partial, in
             ex += v[j];
         }
         carry += total;
+        carry64 += block_sum64(s64, lds64);
     }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
+    if (threadIdx.x == 0 && total_out) *total_out = sat32(carry64);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* x, const uint32_t* idx, int64_t n,
@@ -142,16 +164,15 @@ __device__ __forceinline__ uint32_t packed_count(uint32_t v, const uint32_t* nti
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce_packed(const uint32_t* order, const uint32_t* ntiles,
                                                                      int64_t n, int idb, uint32_t* partial) {
-    __shared__ uint32_t lds[4];
+    __shared__ uint64_t lds[4];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    uint32_t s = 0;
+    uint64_t s = 0;
     for (int j = 0; j < kScanIpt; ++j) {
         const int64_t i = base + j * kScanThreads + threadIdx.x;
         if (i < n) s += packed_count(order[i], ntiles, idb);
     }
-    uint32_t total;
-    block_excl_scan256(s, lds, total);
-    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+    const uint64_t total = block_sum64(s, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sat32(total);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down_packed(uint32_t* order, const uint32_t* ntiles, int64_t n,
@@ -569,7 +590,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     }
     const uint32_t nt = has ? __float_as_uint(q3.w) : 0u;
     const int64_t off = has ? (int64_t)offsets[k] : 0;
-    const int64_t lo = range[0], hi = range[1];
+    // windows past the table's capacity hold nothing that is written (an overflowed table)
+    const int64_t lo = range[0], hi = min((int64_t)range[1], capacity);
     if (has && nt && off + (int64_t)nt > capacity) status[1] = 1;
     // record geometry and the view fields the loops need, in registers (only threads with pairs)
     int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
@@ -689,11 +711,15 @@ __global__ void k_pair_reduce(const uint32_t* __restrict__ order, const uint32_t
     for (int c = 0; c < 9; ++c) grad2d[grad2d_index(r, c)] = acc[c];
 }
 
+// The pair count the sort and ranges read, clamped to the table's capacity; the counted total goes to
+// status[0] (saturated at 2^31 - 1), and status[1] flags a total beyond the capacity or beyond 2^31 - 1
+// pairs (kMaxPairs: the tables' 32-bit positions and the status word hold no more).
 __global__ void k_clamp_count(const uint32_t* total, int64_t capacity, uint32_t* count, int32_t* status) {
     const uint32_t t = *total;
-    *count = (int64_t)t > capacity ? (uint32_t)capacity : t;
-    status[0] = (int32_t)t;
-    if ((int64_t)t > capacity) status[1] = 1;
+    const bool over = (int64_t)t > capacity || t > kMaxPairs;
+    *count = over ? (uint32_t)(capacity < (int64_t)kMaxPairs ? capacity : (int64_t)kMaxPairs) : t;
+    status[0] = (int32_t)(t > kMaxPairs ? kMaxPairs : t);
+    if (over) status[1] = 1;
 }
 
 template <typename K>

@@ -207,6 +207,14 @@ class Frame:
     def buffer(self, field: str, count: int, dtype) -> torch.Tensor:
         return self.alloc.view(getattr(self.state, field), count, dtype)
 
+    def counts(self, stream=None) -> dict:
+        """The forward's counts (megs_state_counts; synchronises the stream): pairs listed, records
+        culled, overflow and malformed-lobes flags."""
+        c = L.MegsCounts()
+        L.check(L.load().megs_state_counts(ctypes.byref(self.state), ctypes.byref(c), _stream(stream)))
+        return {"pairs_needed": int(c.pairs_needed), "culled": int(c.culled), "overflow": bool(c.overflow),
+                "bad_lobes": bool(c.bad_lobes)}
+
 
 def forward(dscene: DeviceScene, cams: Sequence, cfg: Config = Config(), planes: Optional[dict] = None,
             stream=None) -> Frame:

@@ -37,7 +37,7 @@ def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
     P = int(st.n_pairs)
     T = int(st.n_tiles)
     npix = int(st.n_pixels)
-    out = {"frame": fr, "dscene": ds, "n_pairs": P}
+    out = {"frame": fr, "dscene": ds, "n_pairs": P, "counts": fr.counts()}
     out["images"] = [x.cpu().numpy().astype(np.float64) for x in R.split_images(fr.images, cams)]
     if nr:
         out["mean"] = fr.buffer("mean", 2 * nr, torch.float64).view(nr, 2).cpu().numpy()
@@ -136,6 +136,9 @@ def check_records(g: dict, rec: dict) -> None:
     valid_o = rec["valid"].astype(bool)
     valid_g = g["radius"] >= 0
     assert np.array_equal(valid_o, valid_g), f"{np.sum(valid_o != valid_g)} culling decisions differ"
+    if "counts" in g:   # the library's culled count: the records the oracle finds invalid
+        assert g["counts"]["culled"] == int((~valid_o).sum()), (g["counts"], int((~valid_o).sum()))
+        assert not g["counts"]["overflow"] and g["counts"]["pairs_needed"] == g["n_pairs"]
     v = valid_g
     np.testing.assert_allclose(g["mean"][v, 0], rec["u"][v], rtol=0, atol=1e-9)
     np.testing.assert_allclose(g["mean"][v, 1], rec["v"][v], rtol=0, atol=1e-9)

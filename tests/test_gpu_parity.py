@@ -194,6 +194,7 @@ def test_empty_and_culled_scenes():
     behind.pos[1] -= 6.0  # all behind the camera at y = -4
     g = gpu_run(behind, cams, R.Config(8, 64))
     assert g["n_pairs"] == 0 and (g["radius"] < 0).all()
+    assert g["counts"]["culled"] == 50 and g["counts"]["pairs_needed"] == 0
     np.testing.assert_array_equal(g["images"][0].astype(np.float32), np.broadcast_to(
         np.array([0.25, 0.5, 0.75], np.float32)[:, None, None], (3, 24, 40)))
 
@@ -251,6 +252,35 @@ def test_misaligned_allocation_is_rejected():
             assert "256-byte aligned" in lib.megs_last_error().decode()
             assert float(images.abs().max()) == 0.0  # nothing was rendered
     assert float(images.abs().max()) > 0.0
+
+
+def test_pair_count_beyond_32_bits():
+    """1200 Gaussians that each cover a whole 16384 x 16384 view reach all of its 2048 x 2048 8x8
+    tiles: about 5.0e9 tile pairs, more than 32 bits count. The pair count is summed in 64 bits and
+    saturated, so the eager forward refuses the work (MEGS_ERR_CAPACITY) instead of sizing a table
+    from a wrapped count; with a fixed capacity the forward runs, flags the overflow and reports
+    2^31 - 1 pairs needed (the most a key table holds)."""
+    import ctypes
+    from paper_2509_07021_amd import _lib as L
+    rng = np.random.default_rng(21)
+    scene = S.random_scene(rng, 1200, 0, masks=False, spread=0.2)
+    scene.logscale[:] = 0.7
+    scene.op_logit[:] = 4.0
+    cams = [S.look_at((0, -4, 0), 16384, 16384)]
+    ds = R.DeviceScene.from_scene(scene)
+    log("pair count beyond 32 bits: eager forward")
+    with pytest.raises(L.MegsError) as e:
+        R.forward(ds, cams, R.Config(8, 64))
+    assert e.value.status == L.MEGS_ERR_CAPACITY and "at least 4294967295" in str(e.value), str(e.value)
+    log("pair count beyond 32 bits: fixed capacity")
+    fr = R.forward(ds, cams, R.Config(8, 64, pair_capacity=1 << 16))
+    c = fr.counts()
+    assert c["overflow"] and c["pairs_needed"] == (1 << 31) - 1 and c["culled"] == 0, c
+    need = ctypes.c_int64(0)
+    rc = L.load().megs_state_status(ctypes.byref(fr.state), ctypes.byref(need), R._stream(None))
+    assert rc == L.MEGS_ERR_CAPACITY and need.value == (1 << 31) - 1
+    nt = fr.alloc.view(fr.state.ntiles, scene.n, torch.int32).cpu().numpy()
+    assert (nt == 2048 * 2048).all()   # every record reaches every tile
 
 
 def test_zero_lobes_and_single_gaussian():
