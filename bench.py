@@ -171,7 +171,7 @@ def fragment_counts(R, ds, cams, cfg):
 def stage_bytes(stage, n, nv, pairs, npix, ntiles, geom_bytes, k, tile_bits=14):
     """Algorithmic HBM bytes of one launch of an HBM-bound stage (two-stage sort, default flags)."""
     nr = n * nv
-    rec = 64 + 4 + 4 + 4                    # packed record line, tile count, depth key, sort value
+    rec = 48 + 4 + 4 + 4 + 4                # packed record, radius, tile count, depth key, sort value
     if stage == "project":
         return n * geom_bytes + nr * rec
     if stage == "depth_sort":
@@ -179,7 +179,8 @@ def stage_bytes(stage, n, nv, pairs, npix, ntiles, geom_bytes, k, tile_bits=14):
     if stage == "scan":
         return nr * (4 + 4 + 4 + 4)         # sorted values read twice, rewritten as ids, offsets written
     if stage == "emit":
-        return nr * (4 + 4 + 64) + pairs * 8  # order, offset and record line per record; key+value per pair
+        # order and offset per record, the record's mean, factors and opacity and its radius; key+value per pair
+        return nr * (4 + 4 + 36 + 4) + pairs * 8
     if stage == "pair_sort":
         passes = (tile_bits + 7) // 8
         return passes * pairs * (4 + 8 + 8)

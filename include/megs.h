@@ -160,7 +160,8 @@ typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
  *   conic_o   float[NR][4]   conic (a, b, c) of q = -(a dx^2 + c dy^2)/2 - b dx dy, and o_eff
  *   rgbd      float[NR][4]   SG colour (r, g, b) and camera depth z
  *   radius    int32[NR]      footprint radius in pixels, -1 when culled
- *   ntiles    uint32[NR]     tiles of the record's rectangle that its footprint ellipse reaches
+ *   ntiles    uint32[NR]     tiles of the record's rectangle that its footprint ellipse reaches (in
+ *                            the work space below: valid until a backward takes it over)
  *   cutoff    float[NR]      k of that ellipse, {d : d' conic d <= k}; k bounds 2 ln(255 o_eff)
  *   chol      double[NR][4]  (l11, r, l22, 0): the conic as the key emission and the blend use it,
  *                            conic = L L', L = [[l11, 0], [l11 r, l22]], so that
@@ -192,12 +193,17 @@ typedef struct {
      * MEGS_FLAG_DETERMINISTIC), records in emission order (NULL: index order), the records'
      * first emission positions, and the pair count */
     const void *det_inv, *det_order, *det_offsets, *det_count;
-    /* the records again, one 64-byte line each (read by the key emission and the blend, which
-     * gather records in depth and tile order): double mean[2]; double r; float l11, l22 (the conic's
-     * factors, as in chol); float o_eff; float rgb[3]; float rx, ry, the widened half-extents of the
-     * ellipse {d' conic d <= k}; int32 radius; uint32 ntiles */
+    /* the records again, 48 bytes each (read by the key emission, the blend and the projection
+     * backward, which gather records in depth and tile order): double mean[2]; double r; float l11,
+     * l22 (the conic's factors, as in chol; l22 = 0 when culled); float o_eff; float rgb[3] */
     const void *packed;
     const void *chol; /* see above (MEGS_FLAG_RECORD_PLANES only) */
+    /* the forward's work space (device, work_bytes bytes; NULL in deterministic mode): it holds the
+     * depth sort, the scan, the key emission's planes (ntiles above, the footprint radius) and, when
+     * they fit, the pair sort's alternate buffers; megs_render_backward takes its scratch from it
+     * when it is large enough, so ntiles and the sort's intermediates are valid only until then */
+    void *work;
+    int64_t work_bytes;
 } megs_state;
 
 /* Per-view image layout: images are concatenated, view v's float[3][H][W] planes starting at
@@ -251,6 +257,20 @@ megs_status megs_render_backward(const megs_scene *scene, const megs_camera *cam
  * the counted pairs (may be NULL). */
 megs_status megs_state_status(const megs_state *state, int64_t *pairs_needed, void *stream);
 
+/* Device memory of one forward and backward, as megs_render_forward, megs_render_backward and
+ * megs_graph_create ask the allocation callback for it (host only: nothing is launched). With
+ * cfg->pair_capacity = 0, n_pairs is the count the sizing forward will find (the pair block is sized
+ * for it); with a fixed capacity n_pairs is ignored. */
+typedef struct {
+    size_t frame;    /* first block: views, records, per-tile ranges, per-pixel state, then the work space */
+    size_t pairs;    /* second block: the sorted tile keys and record indices (and, when they do not fit in
+                        the work space, the sort's alternate buffers) */
+    size_t backward; /* the backward's block; 0 when it takes the forward's work space */
+    size_t work;     /* the part of frame that is the work space */
+} megs_memory;
+megs_status megs_state_bytes(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
+                             const megs_config *cfg, int64_t n_pairs, megs_memory *out);
+
 /* The forward's counts (synchronises the stream): pairs the records list (saturated at 2^31 - 1),
  * records the projection culled (behind the near plane, anything non-finite, a zero quaternion or lobe
  * axis, effective opacity below 1/255, a mean or radius beyond 1e7 pixels, malformed compressed-row
@@ -291,9 +311,10 @@ void megs_graph_destroy(megs_graph *graph);
  * once, with batch 64, and its timing reported for all four batch sizes. Images are independent of
  * the choice up to FP32 rounding (the footprint lies inside the listed tiles), so the choice changes
  * speed only. ms_out (nullable) receives MEGS_AUTOTUNE_CANDIDATES timings in that order, batch
- * fastest-varying. Working memory: every run of the sweep reuses the same blocks, taken from alloc
- * once for the largest candidate (8x8 tiles, timed first) and again only if a later one needs more,
- * so the sweep holds about one forward+backward's memory. */
+ * fastest-varying. Working memory: a sizing pass runs each candidate's front end (projection,
+ * depth sort, pair count) once; then the frame, pair-table and (when needed) backward blocks are
+ * taken from alloc once, each at its largest size over the candidates, and every run of the sweep
+ * reuses them, so the sweep holds about one forward+backward's memory. */
 #define MEGS_AUTOTUNE_CANDIDATES 36
 megs_status megs_autotune(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
                           const megs_config *base, megs_alloc_fn alloc, void *alloc_ctx,

@@ -31,7 +31,7 @@ EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", 
             "megs_autotune", "megs_profile_begin", "megs_profile_end", "megs_last_error", "megs_version",
             "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply", "megs_dual_update",
             "megs_penalty_grad", "megs_compact", "megs_photometric_loss", "megs_adam_step",
-            "megs_render_forward_noalloc", "megs_state_counts")
+            "megs_render_forward_noalloc", "megs_state_counts", "megs_state_bytes")
 
 PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
           "base", "axis", "sharp", "amp", "lmask_logit")
@@ -75,12 +75,18 @@ class MegsState(ctypes.Structure):
                 ("mean", _vp), ("conic_o", _vp), ("rgbd", _vp), ("radius", _vp), ("ntiles", _vp), ("cutoff", _vp),
                 ("tile_keys", _vp), ("keys64", _vp), ("vals", _vp), ("ranges", _vp), ("T_final", _vp),
                 ("last", _vp), ("device_status", _vp), ("internal", _vp), ("det_inv", _vp), ("det_order", _vp),
-                ("det_offsets", _vp), ("det_count", _vp), ("packed", _vp), ("chol", _vp)]
+                ("det_offsets", _vp), ("det_count", _vp), ("packed", _vp), ("chol", _vp),
+                ("work", _vp), ("work_bytes", ctypes.c_int64)]
 
 
 class MegsCounts(ctypes.Structure):
     _fields_ = [("pairs_needed", ctypes.c_int64), ("culled", ctypes.c_int64), ("overflow", ctypes.c_int32),
                 ("bad_lobes", ctypes.c_int32)]
+
+
+class MegsMemory(ctypes.Structure):
+    _fields_ = [("frame", ctypes.c_size_t), ("pairs", ctypes.c_size_t), ("backward", ctypes.c_size_t),
+                ("work", ctypes.c_size_t)]
 
 
 class MegsProfile(ctypes.Structure):
@@ -115,6 +121,8 @@ def load():
                                        _vp, ALLOC_FN, _vp, P(MegsSceneGrad), _vp]
     L.megs_state_status.argtypes = [P(MegsState), P(ctypes.c_int64), _vp]
     L.megs_state_counts.argtypes = [P(MegsState), P(MegsCounts), _vp]
+    L.megs_state_bytes.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ctypes.c_int64,
+                                   P(MegsMemory)]
     L.megs_graph_create.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ALLOC_FN, _vp,
                                     _vp, _vp, P(MegsSceneGrad), ctypes.c_int32, _vp, P(_vp)]
     L.megs_graph_launch.argtypes = [_vp, _vp]
@@ -140,7 +148,8 @@ def load():
                                  ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp]
     L.megs_profile_begin.argtypes = []
     L.megs_profile_end.argtypes = [P(MegsProfile)]
-    for f in ("megs_render_forward", "megs_render_forward_noalloc", "megs_state_counts", "megs_render_backward",
+    for f in ("megs_render_forward", "megs_render_forward_noalloc", "megs_state_counts", "megs_state_bytes",
+              "megs_render_backward",
               "megs_state_status", "megs_graph_create",
               "megs_graph_launch", "megs_graph_status", "megs_autotune", "megs_profile_begin", "megs_profile_end",
               "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply",

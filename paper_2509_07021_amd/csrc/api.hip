@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <utility>
@@ -230,7 +231,11 @@ SceneDev scene_dev(const megs_scene* sc, int32_t* status) {
     return d;
 }
 
-// Device pointers of one forward.
+// Device pointers of one forward. Its memory is one block: the part that lives as long as the state
+// (views, records, per-tile ranges, per-pixel state, counters) and then the work space, which holds
+// the depth sort, the scan and the key emission's per-record planes, is free once the pairs are
+// emitted, and is then taken, when large enough, by the pair sort's alternate buffers and afterwards
+// by the backward's scratch.
 struct Frame {
     ViewInfo* views;
     Records rec;
@@ -242,28 +247,79 @@ struct Frame {
     float* T_final;
     uint32_t* last;
     uint32_t* queue;     // [0] forward, [1] backward work counters
+    char* work;          // the work space and its size
+    size_t work_bytes;
 };
 
-size_t frame_bytes(const Layout& L) {
+size_t nr1(const Layout& L) { return (size_t)(L.nr ? L.nr : 1); }
+
+// The part of the frame that lives as long as the state.
+size_t frame_main_bytes(const Layout& L) {
     size_t b = 0;
     b += align256(sizeof(ViewInfo) * L.nv);
-    b += align256(sizeof(PackedRec) * (L.nr ? L.nr : 1));
+    b += align256(sizeof(PackedRec) * nr1(L));
     if (L.planes) {
-        b += align256(sizeof(double2) * (L.nr ? L.nr : 1));
-        b += 2 * align256(sizeof(float4) * (L.nr ? L.nr : 1));
-        b += 2 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
-        b += align256(sizeof(double4) * (L.nr ? L.nr : 1));
+        b += align256(sizeof(double2) * nr1(L));
+        b += 2 * align256(sizeof(float4) * nr1(L));
+        b += 2 * align256(sizeof(uint32_t) * nr1(L));
+        b += align256(sizeof(double4) * nr1(L));
     }
-    b += 6 * align256(sizeof(uint32_t) * (L.nr ? L.nr : 1));
-    b += align256(scan_scratch_bytes(L.nr)) + align256(radix_scratch_bytes(L.nr));
     b += align256(sizeof(uint32_t) * 8) + align256(sizeof(int32_t) * 8);
     b += align256(sizeof(uint2) * L.n_tiles);
     b += 2 * align256(sizeof(float) * L.n_pixels);
     b += align256(sizeof(uint32_t) * 4);
-    return b + 256;
+    return b;
 }
 
-Frame carve_frame(void* mem, const Layout& L) {
+// What the forward itself needs of the work space: radius, tile count, depth keys and order (each
+// double-buffered), offsets, scan and sort scratch.
+size_t work_fwd_bytes(const Layout& L) {
+    return 7 * align256(sizeof(uint32_t) * nr1(L)) + align256(scan_scratch_bytes(L.nr)) +
+           align256(radix_scratch_bytes(L.nr));
+}
+
+// The backward's scratch: the per-record sums of the blend backward [NR][9] (grad2d_index), the
+// persistent-queue word, and in deterministic mode the per-pair slots [P][9].
+size_t backward_bytes(const Layout& L, const megs_config* cfg, int64_t cap) {
+    size_t b = align256(sizeof(float) * 9 * nr1(L)) + 256;
+    if (cfg->flags & MEGS_FLAG_DETERMINISTIC) b += align256(sizeof(float) * 9 * (cap > 0 ? cap : 1));
+    return b;
+}
+
+// The pair sort's alternate keys and values and its scratch.
+size_t pairs_alt_bytes(int64_t cap, bool one_stage) {
+    const int64_t c = cap > 0 ? cap : 1;
+    return align256(sizeof(uint32_t) * c) + align256((one_stage ? sizeof(uint64_t) : sizeof(uint32_t)) * c) +
+           align256(radix_scratch_bytes(c));
+}
+
+// The work space is free for other use after the key emission unless the deterministic mode keeps
+// its order and offsets for the backward. The pair sort's alternate buffers may go there only when
+// the sort takes an even number of passes, so that the sorted pairs end in the pair block.
+bool work_reusable(const megs_config* cfg) { return !(cfg->flags & MEGS_FLAG_DETERMINISTIC); }
+
+bool alt_in_work(const Layout& L, const megs_config* cfg, int64_t cap, size_t work_bytes) {
+    if (!work_reusable(cfg)) return false;
+    const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    if (radix_passes(0, one_stage ? 32 + L.tile_bits : L.tile_bits) % 2) return false;
+    return pairs_alt_bytes(cap, one_stage) <= work_bytes;
+}
+
+// Size of the work space: the forward's own needs, and, where the frame is reusable, room for the
+// backward's scratch (when one may follow) and for the pair sort's alternate buffers (when the pair
+// capacity is known here: cap > 0).
+size_t work_bytes(const Layout& L, const megs_config* cfg, int64_t cap, bool backward) {
+    size_t w = work_fwd_bytes(L);
+    if (!work_reusable(cfg)) return w;
+    if (backward) w = std::max(w, backward_bytes(L, cfg, cap));
+    const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    if (cap > 0 && alt_in_work(L, cfg, cap, (size_t)-1)) w = std::max(w, pairs_alt_bytes(cap, one_stage));
+    return w;
+}
+
+size_t frame_bytes(const Layout& L, size_t work) { return frame_main_bytes(L) + align256(work) + 256; }
+
+Frame carve_frame(void* mem, const Layout& L, size_t work) {
     Carver c{static_cast<char*>(mem), 0};
     Frame f;
     f.views = c.take<ViewInfo>(L.nv);
@@ -282,22 +338,27 @@ Frame carve_frame(void* mem, const Layout& L) {
         f.rec.cutoff = nullptr;
         f.rec.chol = nullptr;
     }
-    f.rec.ntiles = c.take<uint32_t>(L.nr);
-    f.rec.dkey = c.take<uint32_t>(L.nr);
-    f.rec.order0 = nullptr;
-    f.rec.order_idb = 0;
-    f.dkey_alt = c.take<uint32_t>(L.nr);
-    f.order = c.take<uint32_t>(L.nr);
-    f.order_alt = c.take<uint32_t>(L.nr);
-    f.offs = c.take<uint32_t>(L.nr);
-    f.scan_scratch = c.take<char>((int64_t)scan_scratch_bytes(L.nr));
-    f.rs_scratch = c.take<char>((int64_t)radix_scratch_bytes(L.nr));
     f.counters = c.take<uint32_t>(8);
     f.status = c.take<int32_t>(8);
     f.ranges = c.take<uint2>(L.n_tiles);
     f.T_final = c.take<float>(L.n_pixels);
     f.last = c.take<uint32_t>(L.n_pixels);
     f.queue = c.take<uint32_t>(4);
+    // the work space
+    f.work = c.take<char>((int64_t)align256(work));
+    f.work_bytes = align256(work);
+    Carver w{f.work, 0};
+    f.rec.rad = w.take<int32_t>(L.nr);
+    f.rec.ntiles = w.take<uint32_t>(L.nr);
+    f.rec.dkey = w.take<uint32_t>(L.nr);
+    f.rec.order0 = nullptr;
+    f.rec.order_idb = 0;
+    f.dkey_alt = w.take<uint32_t>(L.nr);
+    f.order = w.take<uint32_t>(L.nr);
+    f.order_alt = w.take<uint32_t>(L.nr);
+    f.offs = w.take<uint32_t>(L.nr);
+    f.scan_scratch = w.take<char>((int64_t)scan_scratch_bytes(L.nr));
+    f.rs_scratch = w.take<char>((int64_t)radix_scratch_bytes(L.nr));
     return f;
 }
 
@@ -307,38 +368,44 @@ struct Pairs {
     uint64_t *k64, *k64_alt;
     uint32_t *rec_emit, *inv;  // deterministic mode: record per emission position, sorted position per emission
     void* rs_scratch;
+    bool alt_in_work;  // the alternate buffers and scratch are in the frame's work space
 };
 
-size_t pairs_bytes(int64_t cap, bool one_stage, bool det) {
+// The pair block: keys and values, and, unless they go to the frame's work space, the sort's
+// alternate buffers and scratch; deterministic mode adds two permutations.
+size_t pairs_bytes(int64_t cap, bool one_stage, bool det, bool alt_elsewhere) {
     const int64_t c = cap > 0 ? cap : 1;
-    size_t b = 2 * align256(sizeof(uint32_t) * c);
-    b += one_stage ? 2 * align256(sizeof(uint64_t) * c) : 2 * align256(sizeof(uint32_t) * c);
+    size_t b = align256(sizeof(uint32_t) * c) + align256((one_stage ? sizeof(uint64_t) : sizeof(uint32_t)) * c);
+    if (!alt_elsewhere) b += pairs_alt_bytes(cap, one_stage);
     if (det) b += 2 * align256(sizeof(uint32_t) * c);
-    b += align256(radix_scratch_bytes(c));
     return b + 256;
 }
 
-Pairs carve_pairs(void* mem, int64_t cap, bool one_stage, bool det) {
+// alt: the frame's work space when the alternate buffers go there, else null.
+Pairs carve_pairs(void* mem, int64_t cap, bool one_stage, bool det, char* alt) {
     Carver c{static_cast<char*>(mem), 0};
+    Carver a{alt, 0};
+    Carver& ca = alt ? a : c;
     Pairs p;
     p.capacity = cap;
-    p.vals = c.take<uint32_t>(cap);
-    p.vals_alt = c.take<uint32_t>(cap);
+    p.alt_in_work = alt != nullptr;
     p.tkeys = p.tkeys_alt = nullptr;
     p.k64 = p.k64_alt = nullptr;
     p.rec_emit = p.inv = nullptr;
+    p.vals = c.take<uint32_t>(cap);
+    p.vals_alt = ca.take<uint32_t>(cap);
     if (one_stage) {
         p.k64 = c.take<uint64_t>(cap);
-        p.k64_alt = c.take<uint64_t>(cap);
+        p.k64_alt = ca.take<uint64_t>(cap);
     } else {
         p.tkeys = c.take<uint32_t>(cap);
-        p.tkeys_alt = c.take<uint32_t>(cap);
+        p.tkeys_alt = ca.take<uint32_t>(cap);
     }
+    p.rs_scratch = ca.take<char>((int64_t)radix_scratch_bytes(cap > 0 ? cap : 1));
     if (det) {
         p.rec_emit = c.take<uint32_t>(cap);
         p.inv = c.take<uint32_t>(cap);
     }
-    p.rs_scratch = c.take<char>((int64_t)radix_scratch_bytes(cap > 0 ? cap : 1));
     return p;
 }
 
@@ -409,7 +476,8 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     {
         StageTimer t(MEGS_STAGE_EMIT, s);
         HIP_TRY(launch_clamp_count(f.counters + 0, p.capacity, f.counters + 1, f.status, s));
-        HIP_TRY(launch_emit(f.rec, f.views, L.nv, L.n, L.tile, one_stage ? nullptr : f.order, f.offs, L.nr, p.tkeys,
+        HIP_TRY(launch_emit(f.rec, f.views, L.nv, L.n, L.tile, one_stage ? nullptr : f.order, f.offs, f.counters + 0,
+                            L.nr, p.tkeys,
                             p.k64, p.vals, p.capacity, f.status, s, sub_masks(cfg, L) ? 8 : 0));
     }
     const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
@@ -433,6 +501,8 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
             sorted_t = alt ? p.tkeys_alt : p.tkeys;
         }
     }
+    // the work space is reused after the forward: the sorted pairs must not end there
+    if (alt && p.alt_in_work) return fail(MEGS_ERR_HIP, "the pair sort ended in the work space");
     sorted_v = alt ? p.vals_alt : p.vals;
     if (det) {
         uint32_t* rec_sorted = alt ? p.vals : p.vals_alt;  // the ping-pong buffer the sort left free
@@ -493,15 +563,9 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     state->det_order = one_stage ? nullptr : f.order;
     state->det_offsets = f.offs;
     state->det_count = f.counters + 1;
+    state->work = work_reusable(cfg) ? f.work : nullptr;
+    state->work_bytes = work_reusable(cfg) ? (int64_t)f.work_bytes : 0;
     return MEGS_OK;
-}
-
-// Backward scratch: the per-record sums of the blend backward [NR][9] (grad2d_index), the
-// persistent-queue word, and in deterministic mode the per-pair slots [P][9].
-size_t backward_bytes(const Layout& L, const megs_config* cfg, int64_t cap) {
-    size_t b = align256(sizeof(float) * 9 * (L.nr ? L.nr : 1)) + 256;
-    if (cfg->flags & MEGS_FLAG_DETERMINISTIC) b += align256(sizeof(float) * 9 * (cap > 0 ? cap : 1));
-    return b;
 }
 
 megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_config* cfg, const megs_state* st,
@@ -570,18 +634,27 @@ megs_status check_grads(const megs_scene* sc, const megs_scene_grad* g) {
     return MEGS_OK;
 }
 
+bool backward_reuses(const megs_config* cfg, const megs_state* st, size_t gbytes) {
+    return work_reusable(cfg) && st->work && st->work_bytes >= (int64_t)gbytes;
+}
+
+// reserve_backward: size the frame's work space to take the backward's scratch as well (a backward
+// may follow); the pair sort's alternate buffers then also go there when they fit.
 megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t nv, const megs_config* cfg,
                          megs_alloc_fn alloc, void* ctx, float* images, megs_state* state, hipStream_t s,
-                         float* importance = nullptr) {
+                         float* importance = nullptr, bool reserve_backward = true) {
     megs_status st = check_args(sc, cams, nv, cfg);
     if (st != MEGS_OK) return st;
     if (!alloc || !images || !state) return fail(MEGS_ERR_ARG, "null allocator, image or state");
     const Layout L = make_layout(sc, cams, nv, cfg);
     const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
     memset(state, 0, sizeof(*state));
-    void* fm = alloc(ctx, frame_bytes(L));
-    if (bad_alloc(fm)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", frame_bytes(L));
-    Frame f = carve_frame(fm, L);
+    const size_t work = work_bytes(L, cfg, cfg->pair_capacity, reserve_backward);
+    void* fm = alloc(ctx, frame_bytes(L, work));
+    if (bad_alloc(fm))
+        return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", frame_bytes(L, work));
+    Frame f = carve_frame(fm, L, work);
     st = enqueue_front(sc, L, cfg, f, s);
     if (st != MEGS_OK) return st;
     int64_t cap = cfg->pair_capacity;
@@ -599,10 +672,11 @@ megs_status forward_impl(const megs_scene* sc, const megs_camera* cams, int32_t 
         counted = total;
         cap = total;
     }
-    const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
-    void* pm = alloc(ctx, pairs_bytes(cap, one_stage, det));
-    if (bad_alloc(pm)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", pairs_bytes(cap, one_stage, det));
-    Pairs p = carve_pairs(pm, cap, one_stage, det);
+    const bool alt = alt_in_work(L, cfg, cap, f.work_bytes);
+    const size_t pbytes = pairs_bytes(cap, one_stage, det, alt);
+    void* pm = alloc(ctx, pbytes);
+    if (bad_alloc(pm)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", pbytes);
+    Pairs p = carve_pairs(pm, cap, one_stage, det, alt ? f.work : nullptr);
     st = enqueue_back(sc, L, cfg, f, p, images, state, s, importance);
     state->n_pairs = counted >= 0 ? counted : cap;
     return st;
@@ -648,11 +722,12 @@ void* scratch_take(void* ctx, size_t bytes) {
 }
 
 // Working memory of the autotuner's sweep. Every forward+backward asks for the same sequence of blocks
-// (frame, pair table, backward scratch), so the k-th request of a run reuses the pool's k-th block and
-// asks the caller for a larger one only when a candidate needs more (the caller's allocator never frees:
-// the smaller block stays with it). The sweep runs the largest candidate first, so the pool's size is
-// one candidate's working memory, not the sum over the sweep. All runs go to one stream, so a block is
-// reused only after the run before has finished with it.
+// (frame, pair table, and the backward scratch when the frame's work space cannot take it), so the k-th
+// request of a run reuses the pool's k-th block. The sweep sizes the blocks for its largest candidate
+// before it starts, so the pool holds one candidate's working memory, not the sum over the sweep; a
+// larger request would still get a new block (the caller's allocator never frees: the smaller block
+// stays with it). All runs go to one stream, so a block is reused only after the run before has
+// finished with it.
 struct SweepPool {
     megs_alloc_fn alloc;
     void* ctx;
@@ -741,8 +816,11 @@ megs_status megs_render_forward_noalloc(const megs_scene* scene, const megs_came
     const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
     const size_t cap = MEGS_NOALLOC_SCRATCH_BYTES;
     // what is known before any launch: the frame, and the pair table when its capacity is fixed
-    size_t need = align256(frame_bytes(L));
-    if (cfg->pair_capacity > 0) need += align256(pairs_bytes(cfg->pair_capacity, one_stage, det));
+    const size_t work = work_bytes(L, cfg, cfg->pair_capacity, false);
+    size_t need = align256(frame_bytes(L, work));
+    if (cfg->pair_capacity > 0)
+        need += align256(pairs_bytes(cfg->pair_capacity, one_stage, det,
+                                     alt_in_work(L, cfg, cfg->pair_capacity, align256(work))));
     if (need > cap)
         return fail(MEGS_ERR_CAPACITY, "this forward needs %zu bytes of working memory; the static scratch holds %zu",
                     need, cap);
@@ -750,7 +828,8 @@ megs_status megs_render_forward_noalloc(const megs_scene* scene, const megs_came
     st = scratch_of_current_device(&base);
     if (st != MEGS_OK) return st;
     ScratchBump b{static_cast<char*>(base), 0, cap, 0};
-    st = forward_impl(scene, cams, n_views, cfg, scratch_take, &b, images, state, static_cast<hipStream_t>(stream));
+    st = forward_impl(scene, cams, n_views, cfg, scratch_take, &b, images, state, static_cast<hipStream_t>(stream),
+                      nullptr, false);
     if (st == MEGS_ERR_ALLOC && b.needed)
         return fail(MEGS_ERR_CAPACITY,
                     "the counted pairs need %zu bytes of working memory in all; the static scratch holds %zu",
@@ -771,7 +850,8 @@ megs_status megs_render_backward(const megs_scene* scene, const megs_camera* cam
     if (state->n_records != L.nr || state->n_views != n_views || state->tile != cfg->tile || !state->internal)
         return fail(MEGS_ERR_ARG, "state does not belong to this scene, view set and tile size");
     const size_t gbytes = backward_bytes(L, cfg, state->pair_capacity);
-    void* gm = alloc(alloc_ctx, gbytes);
+    // the forward's work space when it is free and large enough, else new memory
+    void* gm = backward_reuses(cfg, state, gbytes) ? state->work : alloc(alloc_ctx, gbytes);
     if (bad_alloc(gm)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", gbytes);
     return enqueue_backward(scene, L, cfg, state, dl_dimages, gm, grads, static_cast<hipStream_t>(stream));
 }
@@ -987,6 +1067,27 @@ megs_status megs_state_status(const megs_state* state, int64_t* pairs_needed, vo
     return MEGS_OK;
 }
 
+megs_status megs_state_bytes(const megs_scene* scene, const megs_camera* cams, int32_t n_views,
+                             const megs_config* cfg, int64_t n_pairs, megs_memory* out) {
+    g_err[0] = 0;
+    megs_status st = check_args(scene, cams, n_views, cfg);
+    if (st != MEGS_OK) return st;
+    if (!out) return fail(MEGS_ERR_ARG, "null output");
+    if (cfg->pair_capacity == 0 && (n_pairs < 0 || n_pairs > (int64_t)kMaxPairs))
+        return fail(MEGS_ERR_ARG, "n_pairs = %lld outside [0, 2^31 - 1]", (long long)n_pairs);
+    const Layout L = make_layout(scene, cams, n_views, cfg);
+    const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
+    const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
+    const int64_t cap = cfg->pair_capacity > 0 ? cfg->pair_capacity : n_pairs;
+    const size_t work = align256(work_bytes(L, cfg, cfg->pair_capacity, true));
+    out->work = work;
+    out->frame = frame_bytes(L, work);
+    out->pairs = pairs_bytes(cap, one_stage, det, alt_in_work(L, cfg, cap, work));
+    const size_t gbytes = backward_bytes(L, cfg, cap);
+    out->backward = work_reusable(cfg) && work >= gbytes ? 0 : gbytes;
+    return MEGS_OK;
+}
+
 megs_status megs_state_counts(const megs_state* state, megs_counts* out, void* stream) {
     g_err[0] = 0;
     if (!state || !state->device_status || !out) return fail(MEGS_ERR_ARG, "null state or output");
@@ -1020,16 +1121,22 @@ megs_status megs_graph_create(const megs_scene* scene, const megs_camera* cams, 
     const Layout L = make_layout(scene, cams, n_views, cfg);
     const bool one_stage = cfg->flags & MEGS_FLAG_ONE_STAGE_SORT;
     const bool det = cfg->flags & MEGS_FLAG_DETERMINISTIC;
-    void* fm = alloc(alloc_ctx, frame_bytes(L));
-    void* pm = alloc(alloc_ctx, pairs_bytes(cfg->pair_capacity, one_stage, det));
-    const size_t gbytes = backward_bytes(L, cfg, cfg->pair_capacity);
-    void* gm = with_backward ? alloc(alloc_ctx, gbytes) : nullptr;
-    if (bad_alloc(fm) || bad_alloc(pm) || (with_backward && bad_alloc(gm)))
-        return fail(MEGS_ERR_ALLOC, "allocation failed or not 256-byte aligned");
+    const int64_t cap = cfg->pair_capacity;
+    const size_t work = work_bytes(L, cfg, cap, with_backward);
+    const bool alt = alt_in_work(L, cfg, cap, align256(work));
+    void* fm = alloc(alloc_ctx, frame_bytes(L, work));
+    void* pm = alloc(alloc_ctx, pairs_bytes(cap, one_stage, det, alt));
+    if (bad_alloc(fm) || bad_alloc(pm)) return fail(MEGS_ERR_ALLOC, "allocation failed or not 256-byte aligned");
+    Frame f = carve_frame(fm, L, work);
+    const size_t gbytes = backward_bytes(L, cfg, cap);
+    void* gm = nullptr;
+    if (with_backward) {
+        gm = work_reusable(cfg) && f.work_bytes >= gbytes ? static_cast<void*>(f.work) : alloc(alloc_ctx, gbytes);
+        if (bad_alloc(gm)) return fail(MEGS_ERR_ALLOC, "allocation failed or not 256-byte aligned");
+    }
     megs_graph* G = new (std::nothrow) megs_graph();
     if (!G) return fail(MEGS_ERR_ALLOC, "host allocation failed");
-    Frame f = carve_frame(fm, L);
-    Pairs p = carve_pairs(pm, cfg->pair_capacity, one_stage, det);
+    Pairs p = carve_pairs(pm, cap, one_stage, det, alt ? f.work : nullptr);
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { delete G; return fail(MEGS_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e)); }
     st = enqueue_front(scene, L, cfg, f, s);
@@ -1079,12 +1186,55 @@ megs_status megs_autotune(const megs_scene* scene, const megs_camera* cams, int3
     if (!base || !best || !dl_dimages || !alloc) return fail(MEGS_ERR_ARG, "null base config, best, dL/dimage or allocator");
     if (reps < 1) reps = 1;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // 8x8 tiles first: they list the most pairs and tiles, so the working memory they take is reused by
-    // every later candidate (SweepPool)
     const int combos[9][3] = {{8, 1, 0},  {16, 1, 0}, {16, 2, 0}, {16, 4, 0}, {32, 1, 0},
                               {32, 2, 0}, {32, 4, 0}, {16, 1, 8}, {32, 1, 8}};
     const int batches[4] = {32, 64, 128, 256};
     SweepPool pool{alloc, alloc_ctx, {}, 0, false};
+    {
+        // Sizing pass: each candidate's blocks are known before the sweep (the frame from its layout, the
+        // pair table from the pairs its front end counts), so the pool takes the largest of each at once
+        // and every run of the sweep reuses them.
+        size_t need[3] = {0, 0, 0};
+        for (int ci = 0; ci < 9; ++ci) {
+            megs_config c = *base;
+            c.tile = combos[ci][0]; c.waves = combos[ci][1]; c.subtile = combos[ci][2]; c.batch = 64;
+            megs_status st = check_args(scene, cams, n_views, &c);
+            if (st != MEGS_OK) return st;
+            const Layout L = make_layout(scene, cams, n_views, &c);
+            need[0] = std::max(need[0], frame_bytes(L, work_bytes(L, &c, c.pair_capacity, true)));
+        }
+        void* fm = alloc(alloc_ctx, need[0]);
+        if (bad_alloc(fm)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", need[0]);
+        for (int ci = 0; ci < 9; ++ci) {
+            megs_config c = *base;
+            c.tile = combos[ci][0]; c.waves = combos[ci][1]; c.subtile = combos[ci][2]; c.batch = 64;
+            const Layout L = make_layout(scene, cams, n_views, &c);
+            const size_t work = work_bytes(L, &c, c.pair_capacity, true);
+            Frame f = carve_frame(fm, L, work);
+            megs_status st = enqueue_front(scene, L, &c, f, s);
+            if (st != MEGS_OK) return st;
+            int64_t cap = c.pair_capacity;
+            if (cap == 0) {
+                uint32_t total = 0;
+                HIP_TRY(hipMemcpyAsync(&total, f.counters, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                if (total > kMaxPairs)
+                    return fail(MEGS_ERR_CAPACITY, "a candidate lists more than %u tile pairs", kMaxPairs);
+                cap = total;
+            }
+            const bool one_stage = c.flags & MEGS_FLAG_ONE_STAGE_SORT;
+            const bool det = c.flags & MEGS_FLAG_DETERMINISTIC;
+            need[1] = std::max(need[1], pairs_bytes(cap, one_stage, det, alt_in_work(L, &c, cap, f.work_bytes)));
+            const size_t gbytes = backward_bytes(L, &c, cap);
+            if (!(work_reusable(&c) && f.work_bytes >= gbytes)) need[2] = std::max(need[2], gbytes);
+        }
+        pool.blocks.push_back({fm, need[0]});
+        for (int k = 1; k < 3 && need[k]; ++k) {
+            void* m = alloc(alloc_ctx, need[k]);
+            if (bad_alloc(m)) return fail(MEGS_ERR_ALLOC, "allocation of %zu bytes failed or not 256-byte aligned", need[k]);
+            pool.blocks.push_back({m, need[k]});
+        }
+    }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));

@@ -86,10 +86,15 @@ struct Layout {
 
 // Stages record g for the frame with origin (x0, y0) (pixel coordinates of its top-left corner). Only
 // t = (X0 - u) + r (Y0 - v), which cancels along a thin footprint, needs FP64; it is rounded once, and
-// c1 = ax t and c2 = by (Y0 - v) then err by about one FP32 rounding of their own size.
-__device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0, double y0, Staged* dst) {
-    const float4* q = reinterpret_cast<const float4*>(a.rec + g);  // the record's 64-byte line
-    const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+// c1 = ax t and c2 = by (Y0 - v) then err by about one FP32 rounding of their own size. With box set,
+// also the frame-relative box of the cutoff ellipse {d' Q d <= k}: its half-extents are sqrt(k A) and
+// sqrt(k C) for the covariance Q^-1 = [[A, B], [B, C]], which the factors give without cancellation as
+// A = (r / l22)^2 + 1 / l11^2 and C = 1 / l22^2; widened by 1e-3 relative and 1e-2 px, far more than
+// FP32 rounding moves them, so every pixel with alpha >= 1/255 lies inside.
+__device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0, double y0, Staged* dst,
+                                      bool box = true) {
+    const float4* q = reinterpret_cast<const float4*>(a.rec + g);  // the record's three vectors
+    const float4 q0 = q[0], q1 = q[1], q2 = q[2];
     const double mx = __hiloint2double(__float_as_int(q0.y), __float_as_int(q0.x));
     const double my = __hiloint2double(__float_as_int(q0.w), __float_as_int(q0.z));
     const double r = __hiloint2double(__float_as_int(q1.y), __float_as_int(q1.x));
@@ -100,7 +105,14 @@ __device__ __forceinline__ void stage(const BlendArgs& a, uint32_t g, double x0,
     s.p0 = make_float4(ax, ax * (float)r, ax * t, q2.x);
     s.p1 = make_float4(by, by * dyf, q2.y, q2.z);
     s.b = q2.w;
-    s.box = make_float4(-dxf - q3.x, -dxf + q3.x, -dyf - q3.y, -dyf + q3.y);
+    s.box = make_float4(0.f, -1.f, 0.f, -1.f);
+    if (box) {
+        const float cut = cutoff_of(q2.x);
+        const float il22 = __builtin_amdgcn_rcpf(q1.w), ra = (float)r * il22, il11 = __builtin_amdgcn_rcpf(q1.z);
+        const float rx = __builtin_amdgcn_sqrtf(cut * __fmaf_rn(ra, ra, il11 * il11)) * 1.001f + 0.01f;
+        const float ry = __builtin_amdgcn_sqrtf(cut) * il22 * 1.001f + 0.01f;
+        s.box = make_float4(-dxf - rx, -dxf + rx, -dyf - ry, -dyf + ry);
+    }
     *dst = s;
 }
 
@@ -596,7 +608,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
                 g = gid;
                 const bool flagged = !a.tkeys || ((key >> (16 + q.sidx)) & 1u);
                 if (flagged) {
-                    stage(a, g, fx0, fy0, &st);
+                    stage(a, g, fx0, fy0, &st, !a.tkeys);
                     // the flags already test the ellipse against the sub-tile; without them, its box
                     hit = a.tkeys ? true : box_meets(st.box, 0, SUB - 1, 0, SUB - 1);
                 }
@@ -738,7 +750,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 g = gid;
                 const bool flagged = !a.tkeys || ((key >> (16 + q.sidx)) & 1u);
                 if (flagged) {
-                    stage(a, g, fx0, fy0, &st);
+                    stage(a, g, fx0, fy0, &st, !a.tkeys);
                     // the flags already test the ellipse against the sub-tile; without them, its box
                     hit = a.tkeys ? true : box_meets(st.box, 0, SUB - 1, 0, SUB - 1);
                 }

@@ -97,28 +97,29 @@ __device__ __forceinline__ Shape shape_of(float l11, double r, float l22) {
     return s;
 }
 
-// One record in a single 64-byte line, for the consumers that gather records in depth or tile
-// order (key emission, blend staging): one line per gathered record instead of one per plane.
-struct __align__(64) PackedRec {
+// One record in 48 bytes: what the blend and the projection backward read of it, gathered in
+// depth and tile order (three 16-byte loads per gathered record instead of one per plane). The
+// key emission's extra fields (footprint radius, tile count) are separate planes that live only
+// through the forward's sorting work space.
+struct __align__(16) PackedRec {
     double2 mean;     // pixel-space mean
     double r;         // the conic's factor ratio (Shape)
-    float l11, l22;   // the conic's diagonal factors (Shape)
+    float l11, l22;   // the conic's diagonal factors (Shape); l22 = 0 when culled
     float o;          // effective opacity
     float rgb[3];     // colour
-    float rx, ry;     // half-extents of the cutoff ellipse in x and y (widened; see the projection)
-    int32_t radius;   // -1 when culled
-    uint32_t ntiles;
 };
-static_assert(sizeof(PackedRec) == 64, "one record per 64-byte line");
+static_assert(sizeof(PackedRec) == 48, "three 16-byte vectors per record");
 
 // Record planes written by the projection (record r = view * n + i).
 struct Records {
-    PackedRec* packed;  // the same records, one line each
+    PackedRec* packed;  // the records, 48 bytes each
     // per-field planes (null unless MEGS_FLAG_RECORD_PLANES): mean .. radius, cutoff, chol
     double2* mean;      // pixel-space mean
     float4* conic_o;    // conic a, b, c (FP32 roundings of the factors' products) and effective opacity
     float4* rgbd;       // colour and camera depth
     int32_t* radius;    // -1 when culled
+    // the forward's own planes, in its sorting work space
+    int32_t* rad;       // footprint radius, -1 when culled (read by the key emission)
     uint32_t* ntiles;   // tiles of the rectangle the footprint ellipse reaches
     uint32_t* dkey;     // depth sort key: float bits of depth, 0xffffffff when no tiles
     // initial values of the depth sort when non-null: record id r in the low order_idb bits and
@@ -313,6 +314,7 @@ hipError_t launch_scan(const uint32_t* x, const uint32_t* idx, int64_t n, uint32
 // read on device from *d_count (capped at max_count). Sorted output ends in keys/vals when
 // the return flag `in_alt` is false, else in keys_alt/vals_alt.
 size_t radix_scratch_bytes(int64_t max_count);
+int radix_passes(int begin_bit, int end_bit);
 hipError_t launch_radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                                  const uint32_t* d_count, int64_t max_count, int begin_bit, int end_bit,
                                  void* scratch, hipStream_t stream, bool* in_alt);
@@ -321,11 +323,11 @@ hipError_t launch_radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_
                                  void* scratch, hipStream_t stream, bool* in_alt);
 
 // Key emission: for every record (in `order`, or index order when order is null) write its
-// tiles' keys at offsets[pos]. Two-stage: u32 global tile ids; one-stage: u64 tile|depth keys.
-// sub = 8: the upper 16 bits of each 32-bit tile key flag the 8 x 8 sub-tiles the record reaches
-// (two-stage sort, tile ids below 2^16); sub = 0: plain tile ids.
+// tiles' keys at offsets[pos]; total: the scan's grand total (device). Two-stage: u32 global tile ids;
+// one-stage: u64 tile|depth keys. sub = 8: the upper 16 bits of each 32-bit tile key flag the 8 x 8
+// sub-tiles the record reaches (two-stage sort, tile ids below 2^16); sub = 0: plain tile ids.
 hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_t n, int tile,
-                       const uint32_t* order, const uint32_t* offsets, int64_t n_records,
+                       const uint32_t* order, const uint32_t* offsets, const uint32_t* total, int64_t n_records,
                        uint32_t* tile_keys, uint64_t* keys64, uint32_t* vals, int64_t capacity,
                        int32_t* status, hipStream_t stream, int sub);
 hipError_t launch_ranges_u32(const uint32_t* tile_keys, const uint32_t* d_count, int64_t max_count,
@@ -339,7 +341,7 @@ struct BlendArgs {
     const ViewInfo* views;
     int nv;
     int64_t n_tiles;
-    const PackedRec* rec;  // the projection's records, one line each
+    const PackedRec* rec;  // the projection's records, 48 bytes each
     const uint32_t* tkeys; // sorted tile keys carrying sub-tile flags in bits 16-31 (null: none)
     const uint32_t* vals;
     const uint2* ranges;

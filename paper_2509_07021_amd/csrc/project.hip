@@ -398,9 +398,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
             rec.cutoff[r] = ok ? cut : 0.f;
             rec.chol[r] = ok ? make_double4((double)p.l11, p.r, (double)p.l22, 0.0) : make_double4(0.0, 0.0, 0.0, 0.0);
         }
-        // the packed line, written in two parts: the record's values now, the tile count after the
-        // row loop below (fewer values live through it)
-        float4* dst = reinterpret_cast<float4*>(rec.packed + r);
+        // the packed record (what the blend and the projection backward read)
         {
             PackedRec pr;
             pr.mean = ok ? make_double2(p.u, p.v) : make_double2(0.0, 0.0);
@@ -412,14 +410,9 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
             pr.rgb[1] = ok ? rgb[1] : 0.f;
             pr.rgb[2] = ok ? rgb[2] : 0.f;
             const float4* src = reinterpret_cast<const float4*>(&pr);
+            float4* dst = reinterpret_cast<float4*>(rec.packed + r);
             dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2];
         }
-        // the half-extents of the cutoff ellipse {q <= k} are sqrt(k A) and sqrt(k C) for the dilated
-        // covariance (A, C its diagonal), widened by 1e-3 relative and 1e-2 px, far more than FP32
-        // rounding of the stored factors moves the blend's ellipse: every pixel with alpha >= 1/255
-        // lies inside the box
-        const float rx = ok ? __builtin_amdgcn_sqrtf(cut * (float)p.A) * 1.001f + 0.01f : 0.f;
-        const float ry = ok ? __builtin_amdgcn_sqrtf(cut * (float)p.C) * 1.001f + 0.01f : 0.f;
         uint32_t nt = 0;
         if (ok) {
             int x0, x1, y0, y1;
@@ -433,12 +426,12 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
             }
         }
         rec.ntiles[r] = nt;
+        rec.rad[r] = ok ? p.radius : -1;
         if (sc.status) {  // culled records, one atomic per wave (the lanes here are the wave's Gaussians)
             const uint64_t culled = __ballot(!ok);
             if (culled && __lane_id() == (unsigned)__builtin_ctzll(__ballot(true)))
                 atomicAdd(&sc.status[kStatusCulled], (int32_t)__popcll(culled));
         }
-        dst[3] = make_float4(rx, ry, __int_as_float(ok ? p.radius : -1), __uint_as_float(nt));
         rec.dkey[r] = nt ? __float_as_uint(p.tzf) : 0xffffffffu;
         if (rec.order0) {
             const uint32_t cap = (1u << (32 - rec.order_idb)) - 1u;

@@ -440,7 +440,7 @@ hipError_t radix_sort(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, 
     K* dst_k = keys_alt; uint32_t* dst_v = vals_alt;
     // the fewest passes of at most 8 bits, with the bits spread evenly over them (14 tile bits sort
     // as 7 + 7: fewer digits per pass give each digit longer runs in the scatter)
-    const int passes = (end_bit - begin_bit + 7) / 8;
+    const int passes = radix_passes(begin_bit, end_bit);
     const int width = (end_bit - begin_bit + passes - 1) / passes;
     for (int shift = begin_bit; shift < end_bit; shift += width) {
         const int bits = end_bit - shift < width ? end_bit - shift : width;
@@ -539,7 +539,8 @@ __device__ __forceinline__ uint64_t band_mask(int c0, int c1, int first, int nbi
 template <int S>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewInfo* __restrict__ views, int64_t n,
                                                        int tile, const uint32_t* __restrict__ order,
-                                                       const uint32_t* __restrict__ offsets, int64_t n_records,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ total, int64_t n_records,
                                                        uint32_t* __restrict__ tile_keys, uint64_t* __restrict__ keys64,
                                                        uint32_t* __restrict__ vals, int64_t capacity, int32_t* status) {
     constexpr int SUB = 8;
@@ -549,22 +550,25 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     __shared__ uint32_t range[2];
     __shared__ uint32_t bucket[kBuckets];
     __shared__ uint16_t perm[kEmitThreads];
+    __shared__ uint32_t s_nt[kEmitThreads];
     const int64_t kb = (int64_t)blockIdx.x * kEmitThreads;
     const int64_t k_last = min(kb + kEmitThreads, n_records) - 1;
     {
         // A lane's time is set by the record with the most rows and tiles in its wave, so the
         // workgroup's records are dealt to lanes grouped by tile count (a counting sort in LDS).
         // Which lane handles a record does not change what is written where.
+        // A record's tile count is the step of the exclusive scan to the next record (modulo 2^32,
+        // exact while the counts fit), read in emission order instead of gathered per record.
         const int64_t k0 = kb + threadIdx.x;
         uint32_t nt0 = 0;
         if (k0 < n_records) {
-            const uint32_t g0 = order ? order[k0] : (uint32_t)k0;
-            nt0 = rec.packed[g0].ntiles;
+            nt0 = (k0 + 1 < n_records ? offsets[k0 + 1] : *total) - offsets[k0];
             if (k0 == k_last) {
                 range[0] = offsets[kb];
                 range[1] = (uint32_t)((int64_t)offsets[k0] + nt0);
             }
         }
+        s_nt[threadIdx.x] = nt0;
         if (threadIdx.x < kBuckets) bucket[threadIdx.x] = 0u;
         __syncthreads();
         const uint32_t key = min(nt0, (uint32_t)kBuckets - 1u);
@@ -581,14 +585,18 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     const int64_t k = kb + perm[threadIdx.x];
     const bool has = k < n_records;
     const uint32_t g = has ? (order ? order[k] : (uint32_t)k) : 0u;
-    // the record's 64-byte line: mean | factor ratio, diagonal factors | opacity, colour |
-    // half-extents, radius, ntiles
-    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
-    if (has) {
+    // the record: mean | factor ratio, diagonal factors | opacity (the colour is not needed here),
+    // and its footprint radius; records without tiles are not read
+    const uint32_t nt = has ? s_nt[perm[threadIdx.x]] : 0u;
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;
+    float o = 0.f;
+    int32_t rad = -1;
+    if (nt) {
         const float4* q = reinterpret_cast<const float4*>(rec.packed + g);
-        q0 = q[0]; q1 = q[1]; q2 = q[2]; q3 = q[3];
+        q0 = q[0]; q1 = q[1];
+        o = reinterpret_cast<const float*>(q + 2)[0];
+        rad = rec.rad[g];
     }
-    const uint32_t nt = has ? __float_as_uint(q3.w) : 0u;
     const int64_t off = has ? (int64_t)offsets[k] : 0;
     // windows past the table's capacity hold nothing that is written (an overflowed table)
     const int64_t lo = range[0], hi = min((int64_t)range[1], capacity);
@@ -607,8 +615,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
         const double mx = __hiloint2double(__float_as_int(q0.y), __float_as_int(q0.x));
         const double my = __hiloint2double(__float_as_int(q0.w), __float_as_int(q0.z));
         const double rr = __hiloint2double(__float_as_int(q1.y), __float_as_int(q1.x));
-        tile_rect(mx, my, __float_as_int(q3.z), vw, tile, x0, x1, y0, y1);
-        ellipse_rows(mx, my, shape_of(q1.z, rr, q1.w), cutoff_of(q2.x), er);
+        tile_rect(mx, my, rad, vw, tile, x0, x1, y0, y1);
+        ellipse_rows(mx, my, shape_of(q1.z, rr, q1.w), cutoff_of(o), er);
     }
     for (int64_t w0 = lo; w0 < hi; w0 += kEmitWindow) {
         const int64_t w1 = w0 + kEmitWindow < hi ? w0 + kEmitWindow : hi;
@@ -832,6 +840,10 @@ hipError_t launch_scan_packed(uint32_t* order, const uint32_t* ntiles, int64_t n
     return hipGetLastError();
 }
 
+// The fewest passes of at most 8 bits over [begin_bit, end_bit); the sorted data ends in the
+// alternate buffers exactly when this is odd.
+int radix_passes(int begin_bit, int end_bit) { return end_bit > begin_bit ? (end_bit - begin_bit + 7) / 8 : 0; }
+
 size_t radix_scratch_bytes(int64_t max_count) {
     const int64_t tiles = (max_count + kRsTile - 1) / kRsTile;
     const int64_t G = tiles < kRsMaxBlocks ? (tiles > 0 ? tiles : 1) : kRsMaxBlocks;
@@ -853,7 +865,7 @@ hipError_t launch_radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_
 }
 
 hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_t n, int tile,
-                       const uint32_t* order, const uint32_t* offsets, int64_t n_records,
+                       const uint32_t* order, const uint32_t* offsets, const uint32_t* total, int64_t n_records,
                        uint32_t* tile_keys, uint64_t* keys64, uint32_t* vals, int64_t capacity,
                        int32_t* status, hipStream_t stream, int sub) {
     (void)nv;
@@ -862,13 +874,13 @@ hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_
     const dim3 grid((unsigned)((n_records + kEmitThreads - 1) / kEmitThreads));
     if (!sub)
         hipLaunchKernelGGL(k_emit<0>, grid, dim3(kEmitThreads), 0, stream, rec, views, n, tile, order, offsets,
-                           n_records, tile_keys, keys64, vals, capacity, status);
+                           total, n_records, tile_keys, keys64, vals, capacity, status);
     else if (tile == 16)
         hipLaunchKernelGGL(k_emit<2>, grid, dim3(kEmitThreads), 0, stream, rec, views, n, tile, order, offsets,
-                           n_records, tile_keys, keys64, vals, capacity, status);
+                           total, n_records, tile_keys, keys64, vals, capacity, status);
     else
         hipLaunchKernelGGL(k_emit<4>, grid, dim3(kEmitThreads), 0, stream, rec, views, n, tile, order, offsets,
-                           n_records, tile_keys, keys64, vals, capacity, status);
+                           total, n_records, tile_keys, keys64, vals, capacity, status);
     return hipGetLastError();
 }
 

@@ -63,7 +63,7 @@ def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
         grads = R.backward(ds, fr, flat_weights(weights))
         torch.cuda.synchronize()
         out["grads"] = {p: (None if g is None else g.cpu().numpy().astype(np.float64)) for p, g in grads.items()}
-        moments = grad2d_buffer(fr.alloc.blocks[nblocks], nr)
+        moments = backward_sums(fr.alloc, fr.state, nblocks, nr)
         out["grad2d_moments"] = moments
         nr0 = out["conic_o"] if nr else np.zeros((0, 4))
         out["grad2d"] = grad2d_from_moments(moments, out["chol"] if nr else np.zeros((0, 4)),
@@ -74,6 +74,17 @@ def gpu_run(scene: S.Scene, cams, cfg: R.Config, weights=None) -> dict:
 def grad2d_buffer(block: torch.Tensor, nr: int) -> np.ndarray:
     """The backward's per-record sums [nr][9] from the start of its scratch block (FP64 copy)."""
     return block[: nr * 9 * 4].view(torch.float32).view(nr, 9).cpu().numpy().astype(np.float64)
+
+
+def backward_sums(alloc, state, nblocks: int, nr: int) -> np.ndarray:
+    """The backward's per-record sums: at the start of its scratch, which is the forward's work space
+    when that was large enough (no new block), else the first block allocated after the nblocks the
+    forward took."""
+    if len(alloc.blocks) > nblocks:
+        return grad2d_buffer(alloc.blocks[nblocks], nr)
+    assert state.work and state.work_bytes >= 36 * nr
+    return alloc.view(state.work, 9 * max(nr, 1), torch.float32)[: 9 * nr].view(nr, 9).cpu().numpy().astype(
+        np.float64)
 
 
 # The blend's exponent scale: its exponent in log2 units is -(w1^2 + w2^2), w = KQ2 (l11 (dx + r dy), l22 dy),

@@ -203,3 +203,42 @@ def test_noalloc_forward_rejects_what_does_not_fit():
     status = lib.megs_render_forward_noalloc(ctypes.byref(sc), cams, 1, ctypes.byref(cfg), ctypes.c_void_p(16),
                                              ctypes.byref(st), None)
     assert status == L.MEGS_ERR_ARG
+
+
+def _sized(n, nv, w, h, tile, sub, flags, cap, n_pairs):
+    """megs_state_bytes for a scene of n Gaussians (plane pointers are placeholders: nothing is
+    launched or read)."""
+    lib = L.load()
+    sc, cams, cfg = _args(tile=tile, nv=nv, width=w, height=h, n=n, k=4, flags=flags, cap=cap, subtile=sub)
+    for p in L.PLANES:
+        setattr(sc, p, 1 << 20)
+    mem = L.MegsMemory()
+    status = lib.megs_state_bytes(ctypes.byref(sc), cams, nv, ctypes.byref(cfg), n_pairs, ctypes.byref(mem))
+    assert status == L.MEGS_OK, lib.megs_last_error().decode()
+    return mem
+
+
+def test_state_bytes_sizes_the_forward_and_backward():
+    """The memory of a forward and backward (host only). The backward's per-record sums (36 bytes per
+    record) and, when they fit, the pair sort's alternate buffers (8 bytes per pair) live in the
+    forward's work space, which is free after the key emission; the deterministic mode keeps its
+    work space and allocates both."""
+    n, nv, P = 1_000_000, 8, 32_000_000
+    nr = n * nv
+    npix = nv * 1920 * 1080
+    m = _sized(n, nv, 1920, 1080, 32, 8, 0, 0, P)
+    assert m.backward == 0 and m.work >= 36 * nr
+    assert 48 * nr + 8 * npix + m.work <= m.frame <= 48 * nr + 8 * npix + m.work + (1 << 20)
+    assert 8 * P <= m.pairs <= 8 * P + (1 << 20)            # sorted keys and values only
+    few = _sized(n, nv, 1920, 1080, 32, 8, 0, 0, 4_000_000)  # the alternates fit with room to spare
+    assert few.work == m.work and few.pairs <= 8 * 4_000_000 + (1 << 20)
+    many = _sized(n, nv, 1920, 1080, 32, 8, 0, 0, 60_000_000)  # they do not fit: the pair block holds them
+    assert many.work == m.work and many.pairs >= 16 * 60_000_000
+    fixed = _sized(n, nv, 1920, 1080, 32, 8, 0, 60_000_000, 0)  # a known capacity sizes the work space for them
+    assert fixed.work >= 8 * 60_000_000 and fixed.pairs <= 8 * 60_000_000 + (1 << 20) and fixed.backward == 0
+    det = _sized(n, nv, 1920, 1080, 32, 0, L.MEGS_FLAG_DETERMINISTIC, 0, P)
+    assert det.work < 36 * nr and det.pairs >= 24 * P and det.backward >= 36 * nr + 36 * P
+    lib = L.load()
+    sc, cams, cfg = _args()
+    assert lib.megs_state_bytes(ctypes.byref(sc), cams, 1, ctypes.byref(cfg), -1, ctypes.byref(L.MegsMemory())) \
+        == L.MEGS_ERR_ARG

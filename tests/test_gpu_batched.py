@@ -1,5 +1,6 @@
 """GPU tests of the batched form (hipGraph capture and replay, persistent work queue, autotuner,
 capacity overflow) and of the full-size workloads on sampled outputs."""
+import ctypes
 import dataclasses
 
 import numpy as np
@@ -10,7 +11,7 @@ from paper_2509_07021_amd import _lib as L
 from paper_2509_07021_amd import render as R
 from paper_2509_07021_amd import scenes as S
 
-from gpu_util import (IMG_TOL, check_key_table, check_records, grad2d_buffer, grad2d_from_moments, grad_close,
+from gpu_util import (IMG_TOL, backward_sums, check_key_table, check_records, grad2d_from_moments, grad_close,
                       gpu_records, gpu_run, log)
 
 pytestmark = pytest.mark.gpu
@@ -110,12 +111,17 @@ def test_autotuner_picks_a_valid_config_with_the_same_images(tmp_path):
     for i, combo in enumerate(L.AUTOTUNE_COMBOS):
         if combo[2]:
             assert np.all(table[i] == table[i, 0])
-    # the sweep reuses one forward+backward's memory (its largest candidate, 8x8 tiles), not 36 x 2 of them
-    fr = R.forward(ds, cams, R.Config(8, 64))
-    npix = sum(c.width * c.height for c in cams)
-    R.backward(ds, fr, torch.ones(3 * npix, device="cuda"))
-    torch.cuda.synchronize()
-    assert stats["sweep_bytes"] <= 1.01 * fr.alloc.nbytes(), (stats["sweep_bytes"], fr.alloc.nbytes())
+    # the sweep holds one block of each kind at its largest size over the candidates (as megs_state_bytes
+    # sizes them from each candidate's pair count), not 36 x 2 forward+backward's memory
+    most = np.zeros(3, np.int64)
+    for tile, waves, sub in L.AUTOTUNE_COMBOS:
+        c = R.Config(tile, 64, waves=waves, subtile=sub)
+        P = int(R.forward(ds, cams, c).state.n_pairs)
+        m = L.MegsMemory()
+        L.check(L.load().megs_state_bytes(ctypes.byref(ds.struct()), R.cameras_struct(cams), len(cams),
+                                          ctypes.byref(c.struct()), P, ctypes.byref(m)))
+        most = np.maximum(most, [m.frame, m.pairs, m.backward])
+    assert stats["sweep_bytes"] == int(most.sum()), (stats["sweep_bytes"], most)
     # a second call finds the result in the cache (keyed by architecture and work) and times nothing
     cached, t2 = R.autotune(ds, cams, R.Config(16, 64), reps=1, cache=cache)
     assert t2 is None and (cached.tile, cached.batch, cached.waves, cached.subtile) == \
@@ -222,12 +228,12 @@ def _full_size_sampled(scene, cams, cfg, frac, seed, graph=False, record_sample=
         G.launch()
         G.stream.synchronize()
         grads = G.grads
-        g2 = grad2d_from_moments(grad2d_buffer(G.alloc.blocks[2], nr), g["chol"], rec["o"])
+        g2 = grad2d_from_moments(backward_sums(G.alloc, G.state, 2, nr), g["chol"], rec["o"])
     else:
         nb = len(fr.alloc.blocks)
         grads = R.backward(ds, fr, dl)
         torch.cuda.synchronize()
-        g2 = grad2d_from_moments(grad2d_buffer(fr.alloc.blocks[nb], nr), g["chol"], rec["o"])
+        g2 = grad2d_from_moments(backward_sums(fr.alloc, fr.state, nb, nr), g["chol"], rec["o"])
     ref = np.zeros_like(g2)
     ref_abs = np.zeros_like(g2)
     for vi, cam in enumerate(cams):

@@ -4,6 +4,8 @@ per-element guard scaled by each element's absolute contribution sum (see gpu_ut
 keys, order and ranges bit-exact given the same record means, depths and radii. Pixels whose oracle decisions lie within the threshold
 bands are excluded from image comparisons and get zero loss weight in gradient comparisons.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -281,6 +283,56 @@ def test_pair_count_beyond_32_bits():
     assert rc == L.MEGS_ERR_CAPACITY and need.value == (1 << 31) - 1
     nt = fr.alloc.view(fr.state.ntiles, scene.n, torch.int32).cpu().numpy()
     assert (nt == 2048 * 2048).all()   # every record reaches every tile
+
+
+@pytest.mark.parametrize("tile,sub,flags", [(16, 0, 0), (32, 8, 0), (8, 0, 1), (16, 0, 8)])
+def test_state_bytes_match_the_allocations(tile, sub, flags):
+    """megs_state_bytes predicts the blocks the forward and the backward ask for (eager, then as one
+    graph with a fixed capacity), and a backward that takes the forward's work space allocates nothing
+    and computes the same gradients as one with memory of its own (the deterministic mode's)."""
+    import ctypes
+    from paper_2509_07021_amd import _lib as L
+    scene, cams = S.make_workload("small_2k_128px")
+    ds = R.DeviceScene.from_scene(scene)
+    cfg = R.Config(tile, 64, flags, subtile=sub)
+    lib = L.load()
+
+    def predicted(c, n_pairs):
+        m = L.MegsMemory()
+        L.check(lib.megs_state_bytes(ctypes.byref(ds.struct()), R.cameras_struct(cams), len(cams),
+                                     ctypes.byref(c.struct()), n_pairs, ctypes.byref(m)))
+        return m
+
+    fr = R.forward(ds, cams, cfg)
+    P = int(fr.state.n_pairs)
+    m = predicted(cfg, P)
+    sizes = [b.numel() for b in fr.alloc.blocks]
+    assert sizes == [m.frame, m.pairs], (sizes, m.frame, m.pairs)
+    npix = sum(c.width * c.height for c in cams)
+    dl = torch.from_numpy(np.concatenate([w.reshape(-1) for w in S.loss_weights(cams, 4)])).cuda()
+    grads = R.backward(ds, fr, dl)
+    torch.cuda.synchronize()
+    sizes = [b.numel() for b in fr.alloc.blocks]
+    assert sizes == [m.frame, m.pairs] + ([m.backward] if m.backward else []), (sizes, m.backward)
+    log(f"tile {tile} sub {sub} flags {flags}: frame {m.frame} (work {m.work}), pairs {m.pairs}, "
+        f"backward {m.backward}")
+    if not flags & L.MEGS_FLAG_DETERMINISTIC:
+        assert m.backward == 0 and fr.state.work
+    fixed = dataclasses.replace(cfg, pair_capacity=P + 100)
+    G = R.Graph(ds, cams, fixed, with_backward=True, dl_images=dl)
+    G.launch()
+    G.stream.synchronize()
+    mg = predicted(fixed, 0)
+    sizes = [b.numel() for b in G.alloc.blocks]
+    assert sizes == [mg.frame, mg.pairs] + ([mg.backward] if mg.backward else []), (sizes, mg.frame, mg.pairs)
+    for p, g in grads.items():   # the same sums (bit for bit in the deterministic mode)
+        if g is not None:
+            ref, got = g.cpu().numpy(), G.grads[p].cpu().numpy()
+            if flags & L.MEGS_FLAG_DETERMINISTIC:
+                np.testing.assert_array_equal(got, ref)
+            else:
+                assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), p
+    G.close()
 
 
 def test_zero_lobes_and_single_gaussian():
