@@ -246,7 +246,7 @@ struct Frame {
     uint2* ranges;
     float* T_final;
     uint32_t* last;
-    uint32_t* queue;     // [0] forward, [1] backward work counters
+    uint32_t* queue;     // the forward's work counters (persistent launch): [0] per-tile, [0..7] sub-tile
     char* work;          // the work space and its size
     size_t work_bytes;
 };
@@ -267,7 +267,7 @@ size_t frame_main_bytes(const Layout& L) {
     b += align256(sizeof(uint32_t) * 8) + align256(sizeof(int32_t) * 8);
     b += align256(sizeof(uint2) * L.n_tiles);
     b += 2 * align256(sizeof(float) * L.n_pixels);
-    b += align256(sizeof(uint32_t) * 4);
+    b += align256(sizeof(uint32_t) * kQueueWords);
     return b;
 }
 
@@ -279,9 +279,9 @@ size_t work_fwd_bytes(const Layout& L) {
 }
 
 // The backward's scratch: the per-record sums of the blend backward [NR][9] (grad2d_index), the
-// persistent-queue word, and in deterministic mode the per-pair slots [P][9].
+// persistent launch's work counters, and in deterministic mode the per-pair slots [P][9].
 size_t backward_bytes(const Layout& L, const megs_config* cfg, int64_t cap) {
-    size_t b = align256(sizeof(float) * 9 * nr1(L)) + 256;
+    size_t b = align256(sizeof(float) * 9 * nr1(L)) + align256(sizeof(uint32_t) * kQueueWords);
     if (cfg->flags & MEGS_FLAG_DETERMINISTIC) b += align256(sizeof(float) * 9 * (cap > 0 ? cap : 1));
     return b;
 }
@@ -343,7 +343,7 @@ Frame carve_frame(void* mem, const Layout& L, size_t work) {
     f.ranges = c.take<uint2>(L.n_tiles);
     f.T_final = c.take<float>(L.n_pixels);
     f.last = c.take<uint32_t>(L.n_pixels);
-    f.queue = c.take<uint32_t>(4);
+    f.queue = c.take<uint32_t>(kQueueWords);
     // the work space
     f.work = c.take<char>((int64_t)align256(work));
     f.work_bytes = align256(work);
@@ -530,7 +530,7 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     a.stats = (cfg->flags & MEGS_FLAG_STATS) ? reinterpret_cast<unsigned long long*>(f.status + 4) : nullptr;
     a.importance = importance;
     a.n = L.n;
-    if (persistent) HIP_TRY(launch_fill_u32(f.queue, 0u, 4, s));
+    if (persistent) HIP_TRY(launch_fill_u32(f.queue, 0u, kQueueWords, s));
     {
         StageTimer t(MEGS_STAGE_BLEND_FWD, s);
         HIP_TRY(launch_blend_fwd(a, L.tile, waves_of(cfg), cfg->batch, persistent, s, cfg->subtile));
@@ -572,7 +572,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
                              const float* dl, void* scratch, const megs_scene_grad* gr, hipStream_t s) {
     Carver c{static_cast<char*>(scratch), 0};
     float* grad2d = c.take<float>(9 * L.nr);
-    uint32_t* queue = c.take<uint32_t>(4);
+    uint32_t* queue = c.take<uint32_t>(kQueueWords);
     float* grad_pair = nullptr;
     if (cfg->flags & MEGS_FLAG_DETERMINISTIC) {
         if (!st->det_inv) return fail(MEGS_ERR_ARG, "deterministic backward needs a deterministic forward state");
@@ -598,7 +598,7 @@ megs_status enqueue_backward(const megs_scene* sc, const Layout& L, const megs_c
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad_pair), 0u, 9 * st->pair_capacity, s));
     else
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, 9 * L.nr, s));
-    if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, 1, s));
+    if (persistent) HIP_TRY(launch_fill_u32(queue, 0u, kQueueWords, s));
     {
         StageTimer t(MEGS_STAGE_BLEND_BWD, s);
         HIP_TRY(launch_blend_bwd(a, L.tile, waves_of(cfg), cfg->batch, persistent, s, cfg->subtile));

@@ -530,17 +530,71 @@ __device__ __forceinline__ void wave_sync() {
 // Without the work queue, the forward's workgroup b runs item xcd_item(b): each XCD takes one
 // contiguous eighth of the sub-tiles (with 8 views, one view each), so the records an XCD gathers
 // stay in its own L2. The backward keeps identity order, which measured faster for it.
+//
+// With the work queue (persistent launch) the items are split into kSlices contiguous slices, one per
+// XCD (the same eighths as above), with one counter each (queue[s * kQueueStride], one per 256 bytes).
+// A wave pulls kPull consecutive items at a time from the slice of the XCD it runs on (the XCC_ID
+// hardware register), so a tile's sub-tiles and its list stay in one L2. Once its slice is drained it
+// reads all the counters at once (one lane each) and moves to the first slice with items left, its
+// own XCD's first. Every pull advances a counter, so every item is handed out exactly once, and a wave
+// ends when every counter has passed its slice's end. The register only steers locality: any value in
+// it gives the same result. Measured on the 8-view 1080p workload (forward / backward blend): with the
+// eight counters in one cache line, pulls serialised on it and the blends took 3.7 / 4.3 ms instead of
+// 0.99 / 2.24 ms for one workgroup per item; a line per counter brings them to 1.35 / 2.48 ms. More
+// slices per XCD (32, 64) lost L2 locality, and several items per pull lost balance (both slower).
+// What remains is the pull's round trip, which a wave waits for between items.
+constexpr int kSlices = kXcds;
+constexpr int kPull = 1;
+static_assert(kSlices % kXcds == 0 && kSlices <= 64 && kSlices * kQueueStride <= kQueueWords, "slice counters");
+
+struct Pull {
+    int slice = -1;            // the slice the wave pulls from (-1 before its first pull)
+    int64_t cur = 0, end = 0;  // items [cur, end) pulled and not yet run
+};
+
+__device__ __forceinline__ void slice_of(int64_t n_items, int s, int64_t& base, int64_t& cnt) {
+    const int64_t per = n_items / kSlices, rem = n_items % kSlices;
+    base = s * per + (s < rem ? s : rem);
+    cnt = per + (s < rem ? 1 : 0);
+}
 
 __device__ __forceinline__ int64_t next_item(const BlendArgs& a, int64_t prev, bool persistent, int64_t n_items,
-                                             uint32_t* slot, bool by_xcd) {
+                                             Pull& q, bool by_xcd) {
     if (!persistent) {
         if (prev >= 0) return n_items;
         return by_xcd ? xcd_item((int64_t)blockIdx.x, n_items) : (int64_t)blockIdx.x;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) *slot = atomicAdd(a.queue, 1u);
-    __syncthreads();
-    return (int64_t)*slot;
+    if (q.cur < q.end) return q.cur++;
+    const int lane = __lane_id();
+    constexpr int kPer = kSlices / kXcds;
+    const int xcc = (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcds - 1));  // XCC_ID
+    if (q.slice < 0) q.slice = xcc * kPer + (int)((blockIdx.x / kXcds) % kPer);
+    for (;;) {
+        int64_t base, cnt;
+        slice_of(n_items, q.slice, base, cnt);
+        uint32_t j = 0;
+        if (lane == 0) j = atomicAdd(a.queue + q.slice * kQueueStride, (uint32_t)kPull);
+        j = (uint32_t)__builtin_amdgcn_readfirstlane((int)j);
+        if ((int64_t)j < cnt) {
+            q.cur = base + j + 1;
+            q.end = base + min((int64_t)j + kPull, cnt);
+            return base + j;
+        }
+        // this slice is drained: the slices with items left, one lane each, this XCD's first
+        bool left = false;
+        if (lane < kSlices) {
+            int64_t b2, c2;
+            slice_of(n_items, lane, b2, c2);
+            left = (int64_t)__hip_atomic_load(a.queue + lane * kQueueStride, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) < c2;
+        }
+        uint64_t m = __ballot(left);
+        if (!m) return n_items;
+        const int r = xcc * kPer;  // rotate so that this XCD's slices come first
+        m = (m >> r) | (r ? m << (kSlices - r) : 0ull);
+        m &= (kSlices == 64 ? ~0ull : ((1ull << kSlices) - 1ull));
+        q.slice = (__builtin_ctzll(m) + r) % kSlices;
+    }
 }
 
 // Rank of this lane among the lanes set in mask (lanes below it).
@@ -572,12 +626,12 @@ template <bool STATS, bool IMP>
 __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int persistent) {
     constexpr int SUB = 8;
     __shared__ Kept lds[64];
-    __shared__ uint32_t work_slot;
     const int lane = __lane_id();
     const int64_t n_items = a.n_tiles * (int64_t)(tile / SUB) * (tile / SUB);
     uint32_t n_blended = 0, n_evaluated = 0;
-    for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot, true); w < n_items;
-         w = next_item(a, w, persistent, n_items, &work_slot, true)) {
+    Pull pull;
+    for (int64_t w = next_item(a, -1, persistent, n_items, pull, true); w < n_items;
+         w = next_item(a, w, persistent, n_items, pull, true)) {
         const SubCtx q = sub_ctx(a, w, tile);
         const TileCtx& c = q.c;
         const int lx = q.sx + (lane & 7), ly = q.sy + (lane >> 3);
@@ -695,14 +749,14 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
 __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int persistent) {
     constexpr int SUB = 8;
     __shared__ Kept lds[64];
-    __shared__ uint32_t work_slot;
     const int lane = __lane_id();
     // the 9 sums leave through one 9-lane atomic: lanes 0, 8, .., 56 hold sums 0..7, lane 63 sum 8
     const bool adds = (lane & 7) == 0 || lane == kLaneSum8;
     const int comp = lane == kLaneSum8 ? 8 : lane >> 3;
     const int64_t n_items = a.n_tiles * (int64_t)(tile / SUB) * (tile / SUB);
-    for (int64_t w = next_item(a, -1, persistent, n_items, &work_slot, false); w < n_items;
-         w = next_item(a, w, persistent, n_items, &work_slot, false)) {
+    Pull pull;
+    for (int64_t w = next_item(a, -1, persistent, n_items, pull, false); w < n_items;
+         w = next_item(a, w, persistent, n_items, pull, false)) {
         const SubCtx q = sub_ctx(a, w, tile);
         const TileCtx& c = q.c;
         const int lx = q.sx + (lane & 7), ly = q.sy + (lane >> 3);

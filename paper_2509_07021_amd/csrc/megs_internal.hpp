@@ -55,6 +55,11 @@ constexpr int kStatusPairs = 0;     // pairs counted
 constexpr int kStatusOverflow = 1;  // pair table overflowed its capacity
 constexpr int kStatusBadLobes = 2;  // some compressed-row lobe offsets were malformed
 constexpr int kStatusCulled = 3;    // records the projection culled (not rendered in their view)
+// Work counters of a persistent launch: [0] for the per-tile kernels, one per slice of the items
+// for the sub-tile kernels, each in its own 256 bytes (kQueueStride words apart: counters that share
+// a cache line serialise each other's atomics); zeroed before each launch.
+constexpr int kQueueStride = 64;
+constexpr int kQueueWords = 8 * kQueueStride;
 
 struct SceneDev {
     int64_t n;
@@ -354,7 +359,7 @@ struct BlendArgs {
                           // fragment, whose exponent gradient is o_eff e; w1, w2 the exponent's
                           // factors kQ2 L' d of the pixel offset d, Shape), then dL/dRGB
     float* grad_pair;     // deterministic backward: per list position [P][9] (null: atomics into grad2d)
-    uint32_t* queue;      // persistent mode work counter (null: one workgroup per tile)
+    uint32_t* queue;      // persistent mode work counters (kQueueWords)
     unsigned long long* stats;  // forward fragment counters [blended, evaluated] (null: not counted)
     float* importance;          // forward: per-Gaussian sum of blending weights (null: not computed)
     int64_t n;                  // Gaussians per view (record r of view v is Gaussian r - v n)
