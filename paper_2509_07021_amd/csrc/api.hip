@@ -11,6 +11,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "megs_internal.hpp"
 
 using namespace megs;
@@ -37,7 +39,14 @@ thread_local Profiler g_prof;
 
 namespace megs {
 
+// Every stage's enqueue is also a named ROCTX range ("megs:project", ...), so a trace taken with
+// rocprofv3 --marker-trace attributes each kernel to its stage (a no-op without a profiler).
+const char* const kStageRange[MEGS_STAGE_COUNT] = {"megs:project", "megs:depth_sort", "megs:scan", "megs:emit",
+                                                   "megs:pair_sort", "megs:ranges", "megs:blend_fwd",
+                                                   "megs:blend_bwd", "megs:project_bwd"};
+
 StageTimer::StageTimer(int st, hipStream_t s) : stage(st), stream(s), start(nullptr) {
+    roctxRangePushA(kStageRange[st]);
     if (!g_prof.on) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
@@ -46,6 +55,7 @@ StageTimer::StageTimer(int st, hipStream_t s) : stage(st), stream(s), start(null
 }
 
 StageTimer::~StageTimer() {
+    roctxRangePop();
     if (!start) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;

@@ -637,33 +637,54 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
                     band_extent(bf, SUB, ty * S + r, vh, xmin, xmax);
                     band_columns(xmin, xmax, SUB, bc0[r], bc1[r]);
                 }
-                const uint32_t row_key = (uint32_t)(tile_off + (int64_t)ty * tiles_x);
-                // a row of at most 64 / S tiles takes each sub-row's flags from one 64-bit mask of
-                // its sub-columns (a shift per tile); wider rows form them per tile
-                const bool narrow = (ch - cl + 1) * S <= 64;
-                uint64_t rmask[S > 0 ? S : 1];
-                if (S && narrow) {
-#pragma unroll
-                    for (int r = 0; r < S; ++r) rmask[r] = band_mask(bc0[r], bc1[r], cl * S, (ch - cl + 1) * S);
-                }
-                for (int tx = cl; tx <= ch && pos < w1; ++tx, ++pos) {
-                    if (pos < w0) continue;
-                    uint32_t key = row_key + (uint32_t)tx;
-                    if (S) {
-                        uint32_t m = 0;
-                        if (narrow) {
-                            const int sh = (tx - cl) * S;
-#pragma unroll
-                            for (int r = 0; r < S; ++r)
-                                m |= ((uint32_t)(rmask[r] >> sh) & ((1u << S) - 1u)) << (r * S);
-                        } else {
-#pragma unroll
-                            for (int r = 0; r < S; ++r) m |= band_bits(bc0[r], bc1[r], tx, S) << (r * S);
-                        }
-                        key |= m << 16;
+                const uint32_t row_key = (uint32_t)(tile_off + (int64_t)ty * tiles_x) + (uint32_t)cl;
+                // the row's tiles k = 0 .. nrow - 1 at positions pos + k; those inside this window (the
+                // row reaches into it: w0 - nrow < pos < w1, so base lies in (-nrow, kEmitWindow))
+                const int nrow = ch - cl + 1;
+                const int base = (int)(pos - w0);
+                const int k0 = max(0, -base), k1 = min(nrow, (int)(w1 - w0) - base);
+                uint32_t* wt = w_tile + base;
+                uint32_t* wv = w_val + base;
+                pos += nrow;
+                if (!S) {
+                    for (int k = k0; k < k1; ++k) {
+                        wt[k] = row_key + (uint32_t)k;
+                        wv[k] = g;
                     }
-                    w_tile[pos - w0] = key;
-                    w_val[pos - w0] = g;
+                } else if (nrow * S <= 32) {
+                    // each sub-row's flags over the row's sub-columns in one 32-bit mask; a tile's S
+                    // bits are a bit-field extract from each
+                    uint32_t rm[S > 0 ? S : 1];
+#pragma unroll
+                    for (int r = 0; r < S; ++r) rm[r] = (uint32_t)band_mask(bc0[r], bc1[r], cl * S, nrow * S);
+                    for (int k = k0; k < k1; ++k) {
+                        uint32_t m = __builtin_amdgcn_ubfe(rm[0], (uint32_t)(k * S), (uint32_t)S);
+#pragma unroll
+                        for (int r = 1; r < S; ++r)
+                            m |= __builtin_amdgcn_ubfe(rm[r], (uint32_t)(k * S), (uint32_t)S) << (r * S);
+                        wt[k] = (row_key + (uint32_t)k) | (m << 16);
+                        wv[k] = g;
+                    }
+                } else if (nrow * S <= 64) {
+                    uint64_t rm[S > 0 ? S : 1];
+#pragma unroll
+                    for (int r = 0; r < S; ++r) rm[r] = band_mask(bc0[r], bc1[r], cl * S, nrow * S);
+                    for (int k = k0; k < k1; ++k) {
+                        uint32_t m = 0;
+#pragma unroll
+                        for (int r = 0; r < S; ++r)
+                            m |= ((uint32_t)(rm[r] >> (k * S)) & ((1u << S) - 1u)) << (r * S);
+                        wt[k] = (row_key + (uint32_t)k) | (m << 16);
+                        wv[k] = g;
+                    }
+                } else {  // wider rows form each tile's flags from the sub-rows' column ranges
+                    for (int k = k0; k < k1; ++k) {
+                        uint32_t m = 0;
+#pragma unroll
+                        for (int r = 0; r < S; ++r) m |= band_bits(bc0[r], bc1[r], cl + k, S) << (r * S);
+                        wt[k] = (row_key + (uint32_t)k) | (m << 16);
+                        wv[k] = g;
+                    }
                 }
             }
         }

@@ -242,3 +242,14 @@ def test_state_bytes_sizes_the_forward_and_backward():
     sc, cams, cfg = _args()
     assert lib.megs_state_bytes(ctypes.byref(sc), cams, 1, ctypes.byref(cfg), -1, ctypes.byref(L.MegsMemory())) \
         == L.MEGS_ERR_ARG
+
+
+def test_stages_are_roctx_ranges():
+    """Every stage's enqueue is a named ROCTX range (for rocprofv3 --marker-trace): the library imports
+    the range calls and holds one name per stage."""
+    import subprocess
+    syms = subprocess.run(["nm", "-D", L.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    assert "roctxRangePushA" in syms and "roctxRangePop" in syms
+    data = open(L.LIB_PATH, "rb").read()
+    for stage in L.STAGES:
+        assert f"megs:{stage}".encode() + b"\0" in data, stage
