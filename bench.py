@@ -7,8 +7,10 @@ masks. Two forms are measured:
     ring of radius 6, forward+backward of all views captured once in a hipGraph and replayed;
   * `plain_fp32`: the same scene in FP32, one 1920x1080 view, eager launches.
 A step is one whole forward+backward of the workload's views. Inputs are resident in HBM before
-the timed region. Default launch configuration: 32x32 tiles for the key table, blending per 8x8
-sub-tile. Each stage's kernels are also timed live with HIP events (eager calls of the same
+the timed region. Launch configuration: the library's autotuner run on the headline workload itself
+(tile size, waves per tile, sub-tile blending and batch depth; reported under config.autotune), or with
+--no-autotune the given one (default 32x32 tiles for the key table, blending per 8x8 sub-tile); the
+plain form uses the same launch. Each stage's kernels are also timed live with HIP events (eager calls of the same
 workload); the slowest stage gives the roofline line, and every stage is set against its own bound
 (`stage_roofline`: algorithmic HBM bytes at 8 TB/s, or blend FLOPs at the FP32 peak), the whole
 path against the sum of those bounds (`path_roofline`). Per-step p10/p50/p90 times of the graph
@@ -18,7 +20,7 @@ timed on the headline workload's views (all 8 by default), and beside it on the 
 on the 2,000-Gaussian 128x128 case. Also reported: the post-processing of a post-ADMM scene and an
 SG-versus-SH colour comparison on the same renderer (skip with --no-post).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-post]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-post] [--no-workloads] [--no-autotune]
 """
 from __future__ import annotations
 
@@ -113,7 +115,8 @@ def parse():
     ap.add_argument("--waves", type=int, default=0, help="wave64s per tile workgroup (0: library default)")
     ap.add_argument("--subtile", type=int, default=8,
                     help="8: blend per 8x8 sub-tile (16x16 / 32x32 tiles); 0: per tile")
-    ap.add_argument("--autotune", action="store_true", help="pick tile/batch with the library's autotuner")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use --tile/--batch/--waves/--subtile instead of the autotuner's choice for the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=8, help="views of the workload the oracle renders")
     ap.add_argument("--no-post", action="store_true",
@@ -514,14 +517,27 @@ def main():
     cams8 = S.ring_cameras(args.views, seed=5)
     log(f"scenes ready in {time.perf_counter() - t_start:.1f}s: n={scene.n} k={scene.k}")
     cfg = R.Config(args.tile, args.batch, waves=args.waves, subtile=args.subtile)
+    tuned = None
+    if not args.no_autotune:
+        # the launch configuration: the library's autotuner on the headline workload itself (every
+        # tile size, waves per tile and sub-tile blending x batch depth, timed forward+backward)
+        ds16 = R.DeviceScene.from_scene(scene16)
+        dl8 = torch.randn(3 * sum(c.width * c.height for c in cams8), device="cuda")
+        stats = {}
+        t0 = time.perf_counter()
+        cfg, table = R.autotune(ds16, cams8, R.Config(16, 64), reps=1, dl_images=dl8, stats=stats)
+        tuned = {"tile": cfg.tile, "waves": cfg.waves, "subtile": cfg.subtile, "batch": cfg.batch,
+                 "best_ms": round(float(table.min()), 4), "sweep_s": round(time.perf_counter() - t0, 2),
+                 "sweep_vram_mb": round(stats["sweep_bytes"] / 1e6, 1)}
+        log(f"autotune: tile {cfg.tile} waves {cfg.waves} subtile {cfg.subtile} batch {cfg.batch} "
+            f"in {tuned['sweep_s']} s; ms per (tile, waves, subtile) x batch:\n{table}")
+        del ds16, dl8
+        torch.cuda.empty_cache()
 
-    # ---------------------------------------------------------------- plain FP32, 1 view
+    # ---------------------------------------------------------------- plain FP32, 1 view (same launch)
     ds = R.DeviceScene.from_scene(scene)
     npix1 = sum(c.width * c.height for c in cams1)
     dl1 = torch.randn(3 * npix1, device="cuda")
-    if args.autotune:
-        cfg, table = R.autotune(ds, cams1, R.Config(16, 64), reps=2, dl_images=dl1)
-        log(f"autotune: tile {cfg.tile} waves {cfg.waves} batch {cfg.batch}; ms per (tile, waves) x batch:\n{table}")
     stream = torch.cuda.current_stream()
 
     def step_plain():
@@ -606,7 +622,7 @@ def main():
                                 f"(BF16 amplitudes), {len(cams8)} views 1920x1080, forward+backward in one hipGraph"),
                    "gaussians": scene.n, "views": len(cams8), "resolution": "1920x1080", "tile": cfg.tile,
                    "batch": cfg.batch, "waves": cfg.waves, "subtile": cfg.subtile, "storage": "f16/f16/bf16",
-                   "pairs": pairs8},
+                   "pairs": pairs8, "autotune": tuned},
         "peak_vram_mb": {"forward": round(batched_fwd_peak / 1e6, 1), "forward_backward": round(batched_fb_peak / 1e6, 1),
                          "static_params": round(static16 / 1e6, 1), "resident_before": round(before / 1e6, 1),
                          "dynamic_per_view": round(dyn_per_view / 1e6, 1)},
