@@ -300,8 +300,11 @@ class Graph:
         self.stream = stream or torch.cuda.Stream()
         npix = sum(h * w for h, w in image_sizes(cams))
         self.images = torch.zeros(3 * npix, dtype=torch.float32, device="cuda")
-        self.dl = (dl_images.contiguous().to(torch.float32) if dl_images is not None else
-                   torch.zeros(3 * npix, dtype=torch.float32, device="cuda"))
+        # dL/dimage is read in place at every replay (a forward-only graph has none)
+        self.dl = None
+        if with_backward:
+            self.dl = (dl_images.contiguous().to(torch.float32) if dl_images is not None else
+                       torch.zeros(3 * npix, dtype=torch.float32, device="cuda"))
         self.grads = zero_grads_like(dscene) if with_backward else {}
         self.alloc = TorchAllocator()
         self._sc = dscene.struct()
