@@ -223,15 +223,18 @@ def post_processing(args, cfg):
     scene, cams = S.make_workload("post_admm_1600k_1080p")
     ds = R.DeviceScene.from_scene(scene)
     torch.cuda.synchronize()
-    for _ in range(2):
+    for _ in range(3):
         P.compact(ds, 0.01, 1.0)
     torch.cuda.synchronize()
-    reps = 5
-    t0 = time.perf_counter()
-    for _ in range(reps):
+    # the median call: a call that has to grow torch's cached device memory first (hipMalloc) takes
+    # milliseconds more, which is the allocator's cost, not the compaction's
+    times = []
+    for _ in range(9):
+        t0 = time.perf_counter()
         cds, kept, lsrc = P.compact(ds, 0.01, 1.0)
-    torch.cuda.synchronize()
-    ms_compact = (time.perf_counter() - t0) * 1e3 / reps
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ms_compact = sorted(times)[len(times) // 2]
     by = compact_bytes(scene, cds.n, cds.n_lobes)
     npix = sum(c.width * c.height for c in cams)
     dl = torch.randn(3 * npix, device="cuda")
@@ -251,7 +254,7 @@ def post_processing(args, cfg):
             "gaussians_in": scene.n, "gaussians_out": cds.n, "lobes_out": cds.n_lobes,
             "lobes_per_gaussian": round(lobes_per, 4), "colour_floats_per_gaussian": round(3 + 7 * lobes_per, 3),
             "compact_ms": round(ms_compact, 4),
-            "compact_note": "wall time of the call, including its one host synchronisation",
+            "compact_note": "median wall time of 9 calls, each including its one host synchronisation",
             "compact_algorithmic_bytes": by, "compact_GBps": round(by / (ms_compact * 1e-3) / 1e9, 1),
             "render": rates}
 
