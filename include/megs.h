@@ -297,6 +297,11 @@ megs_status megs_graph_create(const megs_scene *scene, const megs_camera *cams, 
                               const megs_config *cfg, megs_alloc_fn alloc, void *alloc_ctx,
                               float *images, const float *dl_dimages, megs_scene_grad *grads,
                               int32_t with_backward, void *stream, megs_graph **out);
+/* The same call under the name of the capture step (identical arguments and behaviour). */
+megs_status megs_graph_capture(const megs_scene *scene, const megs_camera *cams, int32_t n_views,
+                               const megs_config *cfg, megs_alloc_fn alloc, void *alloc_ctx,
+                               float *images, const float *dl_dimages, megs_scene_grad *grads,
+                               int32_t with_backward, void *stream, megs_graph **out);
 megs_status megs_graph_launch(megs_graph *graph, void *stream);
 megs_status megs_graph_status(megs_graph *graph, int64_t *pairs_needed, void *stream);
 const megs_state *megs_graph_state(const megs_graph *graph);

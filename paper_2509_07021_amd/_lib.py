@@ -31,7 +31,7 @@ EXPORTED = ("megs_render_forward", "megs_render_backward", "megs_state_status", 
             "megs_autotune", "megs_profile_begin", "megs_profile_end", "megs_last_error", "megs_version",
             "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply", "megs_dual_update",
             "megs_penalty_grad", "megs_compact", "megs_photometric_loss", "megs_adam_step",
-            "megs_render_forward_noalloc", "megs_state_counts", "megs_state_bytes")
+            "megs_render_forward_noalloc", "megs_state_counts", "megs_state_bytes", "megs_graph_capture")
 
 PLANES = ("pos", "logscale", "quat", "op_logit", "pmask_logit",
           "base", "axis", "sharp", "amp", "lmask_logit")
@@ -125,6 +125,7 @@ def load():
                                    P(MegsMemory)]
     L.megs_graph_create.argtypes = [P(MegsScene), P(MegsCamera), ctypes.c_int32, P(MegsConfig), ALLOC_FN, _vp,
                                     _vp, _vp, P(MegsSceneGrad), ctypes.c_int32, _vp, P(_vp)]
+    L.megs_graph_capture.argtypes = L.megs_graph_create.argtypes
     L.megs_graph_launch.argtypes = [_vp, _vp]
     L.megs_graph_status.argtypes = [_vp, P(ctypes.c_int64), _vp]
     L.megs_graph_state.argtypes = [_vp]
@@ -150,7 +151,7 @@ def load():
     L.megs_profile_end.argtypes = [P(MegsProfile)]
     for f in ("megs_render_forward", "megs_render_forward_noalloc", "megs_state_counts", "megs_state_bytes",
               "megs_render_backward",
-              "megs_state_status", "megs_graph_create",
+              "megs_state_status", "megs_graph_create", "megs_graph_capture",
               "megs_graph_launch", "megs_graph_status", "megs_autotune", "megs_profile_begin", "megs_profile_end",
               "megs_render_importance", "megs_lobe_range", "megs_select_topk", "megs_prox_apply",
               "megs_dual_update", "megs_penalty_grad", "megs_compact", "megs_photometric_loss",

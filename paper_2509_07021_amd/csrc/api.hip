@@ -1168,6 +1168,14 @@ megs_status megs_graph_create(const megs_scene* scene, const megs_camera* cams, 
     return MEGS_OK;
 }
 
+megs_status megs_graph_capture(const megs_scene* scene, const megs_camera* cams, int32_t n_views,
+                               const megs_config* cfg, megs_alloc_fn alloc, void* alloc_ctx, float* images,
+                               const float* dl_dimages, megs_scene_grad* grads, int32_t with_backward, void* stream,
+                               megs_graph** out) {
+    return megs_graph_create(scene, cams, n_views, cfg, alloc, alloc_ctx, images, dl_dimages, grads, with_backward,
+                             stream, out);
+}
+
 megs_status megs_graph_launch(megs_graph* graph, void* stream) {
     g_err[0] = 0;
     if (!graph) return fail(MEGS_ERR_ARG, "null graph");

@@ -61,6 +61,23 @@ def test_graph_replays_match_eager():
     graph.close()
 
 
+def test_graph_capture_is_the_same_call(monkeypatch):
+    """megs_graph_capture (the capture step's name for megs_graph_create) builds the same graph: its
+    replays give the eager forward's images bit for bit."""
+    scene, cams = _uneven()
+    ds = R.DeviceScene.from_scene(scene)
+    fr = R.forward(ds, cams, R.Config(16, 64))
+    torch.cuda.synchronize()
+    lib = L.load()
+    monkeypatch.setattr(lib, "megs_graph_create", lib.megs_graph_capture)
+    graph = R.Graph(ds, cams, R.Config(16, 64, 0, int(fr.state.n_pairs) + 1000), with_backward=False)
+    for _ in range(2):
+        graph.launch()
+        graph.stream.synchronize()
+        np.testing.assert_array_equal(graph.images.cpu().numpy(), fr.images.cpu().numpy())
+    graph.close()
+
+
 def test_graph_forward_only_and_capacity_overflow():
     scene, cams = _uneven()
     ds = R.DeviceScene.from_scene(scene)
