@@ -201,7 +201,8 @@ typedef struct {
     /* the forward's work space (device, work_bytes bytes; NULL in deterministic mode): it holds the
      * depth sort, the scan, the key emission's planes (ntiles above, the footprint radius) and, when
      * they fit, the pair sort's alternate buffers; megs_render_backward takes its scratch from it
-     * when it is large enough, so ntiles and the sort's intermediates are valid only until then */
+     * when it is large enough, so ntiles and the sort's intermediates are valid only until then, and
+     * two backward calls on one state must not overlap (they would share that scratch) */
     void *work;
     int64_t work_bytes;
 } megs_state;
