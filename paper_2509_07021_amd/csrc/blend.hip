@@ -533,23 +533,21 @@ __device__ __forceinline__ void wave_sync() {
 //
 // With the work queue (persistent launch) the items are split into kSlices contiguous slices, one per
 // XCD (the same eighths as above), with one counter each (queue[s * kQueueStride], one per 256 bytes).
-// A wave pulls kPull consecutive items at a time from the slice of the XCD it runs on (the XCC_ID
-// hardware register), so a tile's sub-tiles and its list stay in one L2. Once its slice is drained it
-// reads all the counters at once (one lane each) and moves to the first slice with items left, its
-// own XCD's first. Every pull advances a counter, so every item is handed out exactly once, and a wave
+// A wave pulls one item at a time from the slice of the XCD it runs on (the XCC_ID hardware register),
+// so a tile's sub-tiles and its list stay in one L2. Once its slice is drained it reads all the
+// counters at once (one lane each) and moves to the first slice with items left, its own XCD's first. Every pull advances a counter, so every item is handed out exactly once, and a wave
 // ends when every counter has passed its slice's end. The register only steers locality: any value in
 // it gives the same result. Measured on the 8-view 1080p workload (forward / backward blend): with the
 // eight counters in one cache line, pulls serialised on it and the blends took 3.7 / 4.3 ms instead of
 // 0.99 / 2.24 ms for one workgroup per item; a line per counter brings them to 1.35 / 2.48 ms. More
 // slices per XCD (32, 64) lost L2 locality, and several items per pull lost balance (both slower).
-// What remains is the pull's round trip, which a wave waits for between items.
+// What remains is not the queue: issuing each next pull ahead of its item (its round trip overlapping
+// the item's work) changed nothing, and a static assignment without atomics took as long (1.32 ms).
 constexpr int kSlices = kXcds;
-constexpr int kPull = 1;
 static_assert(kSlices % kXcds == 0 && kSlices <= 64 && kSlices * kQueueStride <= kQueueWords, "slice counters");
 
 struct Pull {
-    int slice = -1;            // the slice the wave pulls from (-1 before its first pull)
-    int64_t cur = 0, end = 0;  // items [cur, end) pulled and not yet run
+    int slice = -1;  // the slice the wave pulls from (-1 before its first pull)
 };
 
 __device__ __forceinline__ void slice_of(int64_t n_items, int s, int64_t& base, int64_t& cnt) {
@@ -564,7 +562,6 @@ __device__ __forceinline__ int64_t next_item(const BlendArgs& a, int64_t prev, b
         if (prev >= 0) return n_items;
         return by_xcd ? xcd_item((int64_t)blockIdx.x, n_items) : (int64_t)blockIdx.x;
     }
-    if (q.cur < q.end) return q.cur++;
     const int lane = __lane_id();
     constexpr int kPer = kSlices / kXcds;
     const int xcc = (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcds - 1));  // XCC_ID
@@ -573,13 +570,9 @@ __device__ __forceinline__ int64_t next_item(const BlendArgs& a, int64_t prev, b
         int64_t base, cnt;
         slice_of(n_items, q.slice, base, cnt);
         uint32_t j = 0;
-        if (lane == 0) j = atomicAdd(a.queue + q.slice * kQueueStride, (uint32_t)kPull);
+        if (lane == 0) j = atomicAdd(a.queue + q.slice * kQueueStride, 1u);
         j = (uint32_t)__builtin_amdgcn_readfirstlane((int)j);
-        if ((int64_t)j < cnt) {
-            q.cur = base + j + 1;
-            q.end = base + min((int64_t)j + kPull, cnt);
-            return base + j;
-        }
+        if ((int64_t)j < cnt) return base + j;
         // this slice is drained: the slices with items left, one lane each, this XCD's first
         bool left = false;
         if (lane < kSlices) {
