@@ -286,6 +286,22 @@ def test_full_size_headline_in_bench_configuration():
     _full_size_sampled(scene16, cams, R.Config(32, 64, subtile=8), 0.01, 6)
 
 
+def test_full_size_clustered_200k_720p():
+    """The 200k-Gaussian 720p workload at full size, in the benchmark's launch configuration."""
+    scene, cams = S.make_workload("clustered_200k_720p")
+    log("full-size clustered 200k 720p, 32x32 tiles, 8x8 sub-tiles")
+    _full_size_sampled(scene, cams, R.Config(32, 64, subtile=8), 0.05, 7)
+
+
+def test_full_size_fp16_3m_8x1080p_graph():
+    """The 3M FP16/BF16 workload at full size: 8 views at 1920x1080 in one captured hipGraph, in the
+    benchmark's launch configuration (sampled records, the whole key table, sampled blend and
+    gradients)."""
+    scene, cams = S.make_workload("fp16_3m_8x1080p")
+    log("full-size fp16 3M x 8 x 1080p graph, 32x32 tiles, 8x8 sub-tiles")
+    _full_size_sampled(scene, cams, R.Config(32, 64, subtile=8), 0.004, 9, graph=True)
+
+
 def test_fp16_3m_subsample_all_views():
     """The 3M FP16/BF16 workload: a seeded 20k subsample, all 8 views at 1920x1080, end to end
     against the FP64 oracle reading the exact stored values."""
