@@ -127,9 +127,9 @@ typedef struct {
                                        every record adds its slots in a fixed order; no float atomics.
                                        Set it on the forward and the backward alike. */
 #define MEGS_FLAG_RECORD_PLANES 16u /* also write the per-field record planes of megs_state (mean,
-                                       conic_o, rgbd, radius, cutoff) for inspection; without it
-                                       those pointers are NULL (the packed lines hold the same
-                                       records, and ntiles is always written) */
+                                       conic_o, rgbd, radius, cutoff, chol, ntiles) for inspection;
+                                       without it those pointers are NULL (the packed records hold
+                                       the same records) */
 
 typedef struct {
     int32_t tile;          /* tile edge in pixels: 8, 16 or 32 */
@@ -160,8 +160,10 @@ typedef void *(*megs_alloc_fn)(void *ctx, size_t bytes);
  *   conic_o   float[NR][4]   conic (a, b, c) of q = -(a dx^2 + c dy^2)/2 - b dx dy, and o_eff
  *   rgbd      float[NR][4]   SG colour (r, g, b) and camera depth z
  *   radius    int32[NR]      footprint radius in pixels, -1 when culled
- *   ntiles    uint32[NR]     tiles of the record's rectangle that its footprint ellipse reaches (in
- *                            the work space below: valid until a backward takes it over)
+ *   ntiles    uint32[NR]     tiles of the record's rectangle that its footprint ellipse reaches
+ *                            (MEGS_FLAG_RECORD_PLANES, or the deterministic mode; NULL otherwise: the
+ *                            forward's own counts live in the work space below, which its pair sort
+ *                            and the backward reuse)
  *   cutoff    float[NR]      k of that ellipse, {d : d' conic d <= k}; k bounds 2 ln(255 o_eff)
  *   chol      double[NR][4]  (l11, r, l22, 0): the conic as the key emission and the blend use it,
  *                            conic = L L', L = [[l11, 0], [l11 r, l22]], so that
@@ -199,10 +201,9 @@ typedef struct {
     const void *packed;
     const void *chol; /* see above (MEGS_FLAG_RECORD_PLANES only) */
     /* the forward's work space (device, work_bytes bytes; NULL in deterministic mode): it holds the
-     * depth sort, the scan, the key emission's planes (ntiles above, the footprint radius) and, when
-     * they fit, the pair sort's alternate buffers; megs_render_backward takes its scratch from it
-     * when it is large enough, so ntiles and the sort's intermediates are valid only until then, and
-     * two backward calls on one state must not overlap (they would share that scratch) */
+     * depth sort, the scan, the key emission's planes (tile counts, footprint radius) and, when they
+     * fit, the pair sort's alternate buffers; megs_render_backward takes its scratch from it when it is
+     * large enough, so two backward calls on one state must not overlap (they would share it) */
     void *work;
     int64_t work_bytes;
 } megs_state;

@@ -271,7 +271,7 @@ size_t frame_main_bytes(const Layout& L) {
     if (L.planes) {
         b += align256(sizeof(double2) * nr1(L));
         b += 2 * align256(sizeof(float4) * nr1(L));
-        b += 2 * align256(sizeof(uint32_t) * nr1(L));
+        b += 3 * align256(sizeof(uint32_t) * nr1(L));
         b += align256(sizeof(double4) * nr1(L));
     }
     b += align256(sizeof(uint32_t) * 8) + align256(sizeof(int32_t) * 8);
@@ -341,12 +341,14 @@ Frame carve_frame(void* mem, const Layout& L, size_t work) {
         f.rec.radius = c.take<int32_t>(L.nr);
         f.rec.cutoff = c.take<float>(L.nr);
         f.rec.chol = c.take<double4>(L.nr);
+        f.rec.ntiles_plane = c.take<uint32_t>(L.nr);
     } else {
         f.rec.mean = nullptr;
         f.rec.conic_o = f.rec.rgbd = nullptr;
         f.rec.radius = nullptr;
         f.rec.cutoff = nullptr;
         f.rec.chol = nullptr;
+        f.rec.ntiles_plane = nullptr;
     }
     f.counters = c.take<uint32_t>(8);
     f.status = c.take<int32_t>(8);
@@ -557,7 +559,9 @@ megs_status enqueue_back(const megs_scene* sc, const Layout& L, const megs_confi
     state->conic_o = f.rec.conic_o;
     state->rgbd = f.rec.rgbd;
     state->radius = f.rec.radius;
-    state->ntiles = f.rec.ntiles;
+    // the work space's tile counts are the forward's own (the pair sort may reuse their memory): the
+    // caller sees the copy in the record planes, or, in deterministic mode, the counts themselves
+    state->ntiles = L.planes ? f.rec.ntiles_plane : (work_reusable(cfg) ? nullptr : f.rec.ntiles);
     state->cutoff = f.rec.cutoff;
     state->packed = f.rec.packed;
     state->chol = f.rec.chol;

@@ -123,6 +123,7 @@ struct Records {
     float4* conic_o;    // conic a, b, c (FP32 roundings of the factors' products) and effective opacity
     float4* rgbd;       // colour and camera depth
     int32_t* radius;    // -1 when culled
+    uint32_t* ntiles_plane;  // copy of ntiles for the caller
     // the forward's own planes, in its sorting work space
     int32_t* rad;       // footprint radius, -1 when culled (read by the key emission)
     uint32_t* ntiles;   // tiles of the rectangle the footprint ellipse reaches

@@ -426,6 +426,7 @@ __global__ __launch_bounds__(256) void k_project(SceneDev sc, const ViewInfo* __
             }
         }
         rec.ntiles[r] = nt;
+        if (rec.ntiles_plane) rec.ntiles_plane[r] = nt;
         rec.rad[r] = ok ? p.radius : -1;
         if (sc.status) {  // culled records, one atomic per wave (the lanes here are the wave's Gaussians)
             const uint64_t culled = __ballot(!ok);

@@ -338,7 +338,7 @@ def test_packed_depth_order_with_escaped_counts_full_size():
     idb = max(1, int(np.ceil(np.log2(nr))))
     cap = (1 << (32 - idb)) - 1
     log(f"packed depth order: {nr} records, {idb} id bits, count cap {cap}")
-    two = R.forward(ds, cams, R.Config(8, 64))
+    two = R.forward(ds, cams, R.Config(8, 64, L.MEGS_FLAG_RECORD_PLANES))
     torch.cuda.synchronize()
     nt = two.buffer("ntiles", nr, torch.int32).cpu().numpy()
     assert int(nt.max()) >= cap, (int(nt.max()), cap)   # the escape path is taken

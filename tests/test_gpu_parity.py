@@ -275,7 +275,7 @@ def test_pair_count_beyond_32_bits():
         R.forward(ds, cams, R.Config(8, 64))
     assert e.value.status == L.MEGS_ERR_CAPACITY and "at least 4294967295" in str(e.value), str(e.value)
     log("pair count beyond 32 bits: fixed capacity")
-    fr = R.forward(ds, cams, R.Config(8, 64, pair_capacity=1 << 16))
+    fr = R.forward(ds, cams, R.Config(8, 64, L.MEGS_FLAG_RECORD_PLANES, pair_capacity=1 << 16))
     c = fr.counts()
     assert c["overflow"] and c["pairs_needed"] == (1 << 31) - 1 and c["culled"] == 0, c
     need = ctypes.c_int64(0)
