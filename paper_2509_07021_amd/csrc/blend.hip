@@ -820,17 +820,19 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 const bool incl = frag(s, px, py, w1, w2, G, alpha, clamped) & (s.pos1 <= lst);
                 if (!__any(incl)) continue;
                 float acc[9];
+                // a lane the entry does not include takes alpha = 0: its T is then multiplied by the
+                // reciprocal of 1.0, which is exactly 1.0, and its P by nothing, so it needs no select
                 const float al = incl ? alpha : 0.0f;
                 const float Ti = T * __builtin_amdgcn_rcpf(1.0f - al);
                 const float wgt = al * Ti;
                 // (c - S) . dL/dC, from c . dL/dC and the carried P
-                const float dcs = __fmaf_rn(s.p1.z, dl0, __fmaf_rn(s.p1.w, dl1, s.b * dl2)) - P;
+                const float dcs = __fmaf_rn(s.p1.z, dl0, __fmaf_rn(s.p1.w, dl1, __fmaf_rn(s.b, dl2, -P)));
                 acc[6] = wgt * dl0;
                 acc[7] = wgt * dl1;
                 acc[8] = wgt * dl2;
                 const float dal = Ti * dcs;
                 P = __fmaf_rn(al, dcs, P);
-                T = incl ? Ti : T;
+                T = Ti;
                 const bool live = incl & !clamped;
                 acc[5] = live ? G * dal : 0.0f;  // dL/do_eff; the exponent gradient is o_eff times this
                 acc[0] = acc[5] * w1;
