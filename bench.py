@@ -470,8 +470,9 @@ def workload_line(args, name, cfg, graph, hbm_copy, autotune=False):
     static = ds.static_bytes()
     _, roof, _, path_roof = stage_rooflines(R, L, ds, cams, cfg, scene, static // scene.n, pairs, hbm_copy,
                                             args.steps)
-    # the traffic figure is the headline workload's (measured offline on its source): not this one's
+    # the traffic and VALU counts are the headline workload's (measured offline on its source): not this one's
     roof["traffic"] = None
+    roof["valu"] = None
     mpix = npix / ms / 1e3
     res = sorted({f"{c.width}x{c.height}" for c in cams})
     log(f"{name}: {ms:.3f} ms/step, {mpix:.1f} Mpixel/s, pairs {pairs}, fwd+bwd peak {fb_peak / 1e6:.0f} MB "
