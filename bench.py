@@ -52,9 +52,9 @@ FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 30
 # when the counters were taken; a changed source reports traffic as null.
 TRAFFIC = {
     # 1M masked Gaussians, FP16, 8 x 1920x1080, 32x32 tiles, 8x8 sub-tile blending: FETCH_SIZE
-    # 2,172,192 KiB x 1.9998 (a 512 MiB copy read 262,167 KiB) + WRITE_SIZE 1,187,047 KiB x 1.0000
-    "blend_bwd": {"bytes": 5663795888,
-                  "source_sha256": "b1f1fa85065a3ef2b508b855fb20363370a7c0326dbe4486bf0699c6991499e6"},
+    # 2,172,586 KiB x 1.9998 (a 512 MiB copy read 262,167 KiB) + WRITE_SIZE 1,187,047 KiB x 1.0000
+    "blend_bwd": {"bytes": 5664606479,
+                  "source_sha256": "832e5079219fddd4167546ae17eb4345f372b8f130fae3afb8d91c7be652b371"},
 }
 # VALU instructions per launch of the blend kernels on the same workload, from a rocprofv3 --pmc
 # SQ_INSTS_VALU run (per dispatch, averaged), with the SHA-256 of the source they were taken on (a
@@ -63,9 +63,9 @@ TRAFFIC = {
 # VALU utilisation.
 VALU = {
     "blend_fwd": {"instructions": 519785357,
-                  "source_sha256": "b1f1fa85065a3ef2b508b855fb20363370a7c0326dbe4486bf0699c6991499e6"},
-    "blend_bwd": {"instructions": 1222382510,
-                  "source_sha256": "b1f1fa85065a3ef2b508b855fb20363370a7c0326dbe4486bf0699c6991499e6"},
+                  "source_sha256": "832e5079219fddd4167546ae17eb4345f372b8f130fae3afb8d91c7be652b371"},
+    "blend_bwd": {"instructions": 1203389756,
+                  "source_sha256": "832e5079219fddd4167546ae17eb4345f372b8f130fae3afb8d91c7be652b371"},
 }
 SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4
 STAGE_SOURCE = {"project": "project.hip", "project_bwd": "project.hip", "blend_fwd": "blend.hip",

@@ -317,7 +317,6 @@ __device__ __forceinline__ float dpp(float v) {  // lanes whose source lane is i
 }
 constexpr int kQuadXor1 = 0xb1, kQuadXor2 = 0x4e, kRowMirror = 0x140, kRowHalfMirror = 0x141;
 constexpr int kRowBcast15 = 0x142;  // lane 15 of the previous 16-lane row (rows 1-3)
-constexpr int kRowBcast31 = 0x143;  // lane 31 (rows 2 and 3)
 constexpr int kLaneSum8 = 63;       // the lane that ends with the wave total of v[8] in wave_sum9
 
 // Sum over one 8-lane group (every lane of the group ends with the total).
@@ -330,10 +329,11 @@ __device__ __forceinline__ float sum8(float y) {
 
 // Sum of v[0..8] over the wave: a transposed butterfly. After the swaps, lane group (b5 b4 b3) of
 // the lane index holds partial sums of v[4 b5 + 2 b4 + b3] only; the last three steps finish
-// them within each 8-lane group. Afterwards every lane of group m (lanes 8m..8m+7) holds the total
-// of v[m] in out. v[8] is summed within each 16-lane row, then across rows with the two row
-// broadcasts: lane kLaneSum8 (63) holds its wave total in v8.
-__device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
+// them within each 8-lane group, so every lane of group m (lanes 8m..8m+7) holds the total of v[m].
+// v[8] is summed within each 16-lane row, then across rows with the two row broadcasts, the last of
+// which writes only lanes 60-63: on return lanes 8m (m < 8) hold the total of v[m] and lane
+// kLaneSum8 (63) the total of v[8].
+__device__ __forceinline__ float wave_sum9(const float v[9]) {
     const int lane = __lane_id();
     float w4[4];
 #pragma unroll
@@ -351,13 +351,21 @@ __device__ __forceinline__ void wave_sum9(float v[9], float& out, float& v8) {
     }
     const bool b3 = lane & 8;      // lanes 0-7 of a row pair with lanes 15..8 through the mirror
     const float y = (b3 ? w2[1] : w2[0]) + dpp<kRowMirror>(b3 ? w2[0] : w2[1]);
-    out = sum8(y);
-    // (all rows take part in both broadcasts so each folds into one DPP add; only row 3's result,
-    // which reads valid lanes in both steps, is used)
+    float out = sum8(y);
+    // (all rows take part in the first broadcast so it folds into one DPP add; only row 3's result,
+    // which reads a valid lane, is used)
     float z = sum8(v[8]);
-    z += dpp<kRowMirror>(z);      // row sums R0..R3 in every lane of their row
-    z += dpp<kRowBcast15>(z);     // row 1: R0 + R1, row 3: R2 + R3
-    v8 = z + dpp<kRowBcast31>(z);  // row 3: R2 + R3 + (R0 + R1)
+    z += dpp<kRowMirror>(z);   // row sums R0..R3 in every lane of their row
+    z += dpp<kRowBcast15>(z);  // row 1: R0 + R1, row 3: R2 + R3
+    // Lanes 60-63 (row mask 8: row 3; bank mask 8: its lanes 12-15) take R2 + R3 + lane 31's
+    // R0 + R1 in place of the total of v[7], which lane 56 also holds; every other lane keeps out.
+    // This masked DPP add has no builtin form (a masked DPP move keeps the old value in the move,
+    // not in the sum), so it is written out, after the two wait states a DPP read of a VGPR that
+    // the previous VALU instruction wrote needs.
+    asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 row_bcast:31 row_mask:0x8 bank_mask:0x8"
+                 : "+v"(out)
+                 : "v"(z));
+    return out;
 }
 
 // DET: instead of float atomics into the record's gradient, the tile's 9 sums for each list
@@ -470,25 +478,23 @@ __global__ __launch_bounds__(64 * WAVES) void k_blend_bwd(BlendArgs a, int batch
                 }
                 if (WAVES == 1) {
                     if (!any_incl) continue;
-                    float tot, tot8;
-                    wave_sum9(acc, tot, tot8);
+                    const float tot = wave_sum9(acc);
                     if (DET) {
                         float* slot = a.grad_pair + 9 * (int64_t)(end - 1 - jj);
                         if ((lane & 7) == 0) slot[lane >> 3] = tot;
-                        if (lane == kLaneSum8) slot[8] = tot8;
+                        if (lane == kLaneSum8) slot[8] = tot;
                         continue;
                     }
                     // one 9-lane atomic: lanes 0, 8, .., 56 add sums 0..7, lane 63 adds sum 8
                     if ((lane & 7) == 0 || lane == kLaneSum8)
-                        unsafeAtomicAdd(a.grad2d + grad2d_index(lds_id[jj], lane == kLaneSum8 ? 8 : lane >> 3),
-                                        lane == kLaneSum8 ? tot8 : tot);
+                        unsafeAtomicAdd(a.grad2d + grad2d_index(lds_id[jj], lane == kLaneSum8 ? 8 : lane >> 3), tot);
                 } else {
                     // per-wave partial sums to LDS; summed across waves after the batch
-                    float tot = 0.f, tot8 = 0.f;
-                    if (any_incl) wave_sum9(acc, tot, tot8);
+                    float tot = 0.f;
+                    if (any_incl) tot = wave_sum9(acc);
                     float* part = lds_part + ((int64_t)jj * WAVES + wv) * 9;
                     if ((lane & 7) == 0) part[lane >> 3] = tot;
-                    if (lane == kLaneSum8) part[8] = tot8;
+                    if (lane == kLaneSum8) part[8] = tot;
                 }
             }
             __syncthreads();
@@ -840,12 +846,10 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
                 acc[2] = acc[0] * w1;
                 acc[3] = acc[0] * w2;
                 acc[4] = acc[1] * w2;
-                float tot, tot8;
-                wave_sum9(acc, tot, tot8);
-                float val = lane == kLaneSum8 ? tot8 : tot;
-                // keeps the sums' last DPP adds in front of the branch: sunk into it (where only the
-                // adding lanes run), each would split into a DPP move and a separate add
-                asm volatile("" : "+v"(val));
+                // (the sums' last add is a volatile statement, so their DPP adds stay in front of the
+                // branch: sunk into it, where only the adding lanes run, each would split into a DPP
+                // move and a separate add)
+                const float val = wave_sum9(acc);
                 if (adds) unsafeAtomicAdd(a.grad2d + (s.slot + comp), val);
             }
             wave_sync();
