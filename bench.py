@@ -52,8 +52,8 @@ FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 30
 # when the counters were taken; a changed source reports traffic as null.
 TRAFFIC = {
     # 1M masked Gaussians, FP16, 8 x 1920x1080, 32x32 tiles, 8x8 sub-tile blending: FETCH_SIZE
-    # 2,172,586 KiB x 1.9998 (a 512 MiB copy read 262,167 KiB) + WRITE_SIZE 1,187,047 KiB x 1.0000
-    "blend_bwd": {"bytes": 5664606479,
+    # 2,173,003 KiB x 1.9998 (a 512 MiB copy read 262,167 KiB) + WRITE_SIZE 1,187,047 KiB x 1.0000
+    "blend_bwd": {"bytes": 5665450152,
                   "source_sha256": "832e5079219fddd4167546ae17eb4345f372b8f130fae3afb8d91c7be652b371"},
 }
 # VALU instructions per launch of the blend kernels on the same workload, from a rocprofv3 --pmc
