@@ -220,6 +220,19 @@ def test_needle_footprints(tile, sub):
     assert conic_condition(rec["conic"][rec["valid"].astype(bool)]).max() > 1e3  # thin ellipses reached
 
 
+@pytest.mark.parametrize("tile,sub,min_pairs", [(8, 0, 16 * 2048), (32, 8, 2 * 2048)])
+def test_emission_spans_many_windows(tile, sub, min_pairs):
+    """Large footprints (400 Gaussians of tens of pixels radius in one 320x240 view): the key
+    emission's two workgroups of up to 256 records each emit several times its LDS window of 2048
+    pairs, so records' tile runs straddle window boundaries (about 18 windows per workgroup with 8x8
+    tiles, 2-3 with 32x32 tiles and sub-tile flags); keys, order and ranges bit-exact against the
+    oracle's plain tile definition, and every later stage at the standard tolerances."""
+    scene = S.random_scene(np.random.default_rng(21), 400, 2, masks=True, spread=1.0, logscale_mu=-1.2)
+    cams = [S.look_at((0, -4, 0.3), 320, 240, bg=(0.2, 0.1, 0.3))]
+    g, _, _ = _run_all_stages(scene, cams, R.Config(tile, 64, subtile=sub), seed=9)
+    assert g["n_pairs"] > min_pairs, g["n_pairs"]
+
+
 def test_misaligned_allocation_is_rejected():
     """The allocation callback must return 256-byte aligned memory: a pointer that is not (here 16
     bytes past an aligned block) fails with MEGS_ERR_ALLOC before anything is launched, and the
