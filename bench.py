@@ -52,8 +52,8 @@ FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 30
 # when the counters were taken; a changed source reports traffic as null.
 TRAFFIC = {
     # 1M masked Gaussians, FP16, 8 x 1920x1080, 32x32 tiles, 8x8 sub-tile blending: FETCH_SIZE
-    # 2,173,003 KiB x 1.9998 (a 512 MiB copy read 262,167 KiB) + WRITE_SIZE 1,187,047 KiB x 1.0000
-    "blend_bwd": {"bytes": 5665450152,
+    # 2,172,908 KiB x 1.9998 (a 512 MiB copy read 262,167 KiB) + WRITE_SIZE 1,187,047 KiB x 1.0000
+    "blend_bwd": {"bytes": 5665256675,
                   "source_sha256": "832e5079219fddd4167546ae17eb4345f372b8f130fae3afb8d91c7be652b371"},
 }
 # VALU instructions per launch of the blend kernels on the same workload, from a rocprofv3 --pmc
@@ -174,7 +174,7 @@ def fragment_counts(R, ds, cams, cfg):
 def stage_bytes(stage, n, nv, pairs, npix, ntiles, geom_bytes, k, tile_bits=14):
     """Algorithmic HBM bytes of one launch of an HBM-bound stage (two-stage sort, default flags)."""
     nr = n * nv
-    rec = 48 + 4 + 4 + 4 + 4                # packed record, radius, tile count, depth key, sort value
+    rec = 48 + 4 + 4 + 4                    # packed record, tile count, depth key, sort value
     if stage == "project":
         return n * geom_bytes + nr * rec
     if stage == "depth_sort":
@@ -182,8 +182,8 @@ def stage_bytes(stage, n, nv, pairs, npix, ntiles, geom_bytes, k, tile_bits=14):
     if stage == "scan":
         return nr * (4 + 4 + 4 + 4)         # sorted values read twice, rewritten as ids, offsets written
     if stage == "emit":
-        # order and offset per record, the record's mean, factors and opacity and its radius; key+value per pair
-        return nr * (4 + 4 + 36 + 4) + pairs * 8
+        # order and offset per record, the record's mean, factors and opacity; key+value per pair
+        return nr * (4 + 4 + 36) + pairs * 8
     if stage == "pair_sort":
         passes = (tile_bits + 7) // 8
         return passes * pairs * (4 + 8 + 8)

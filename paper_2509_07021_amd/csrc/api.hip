@@ -281,10 +281,10 @@ size_t frame_main_bytes(const Layout& L) {
     return b;
 }
 
-// What the forward itself needs of the work space: radius, tile count, depth keys and order (each
+// What the forward itself needs of the work space: tile count, depth keys and order (each
 // double-buffered), offsets, scan and sort scratch.
 size_t work_fwd_bytes(const Layout& L) {
-    return 7 * align256(sizeof(uint32_t) * nr1(L)) + align256(scan_scratch_bytes(L.nr)) +
+    return 6 * align256(sizeof(uint32_t) * nr1(L)) + align256(scan_scratch_bytes(L.nr)) +
            align256(radix_scratch_bytes(L.nr));
 }
 
@@ -360,7 +360,6 @@ Frame carve_frame(void* mem, const Layout& L, size_t work) {
     f.work = c.take<char>((int64_t)align256(work));
     f.work_bytes = align256(work);
     Carver w{f.work, 0};
-    f.rec.rad = w.take<int32_t>(L.nr);
     f.rec.ntiles = w.take<uint32_t>(L.nr);
     f.rec.dkey = w.take<uint32_t>(L.nr);
     f.rec.order0 = nullptr;

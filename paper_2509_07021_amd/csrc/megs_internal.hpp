@@ -104,8 +104,8 @@ __device__ __forceinline__ Shape shape_of(float l11, double r, float l22) {
 
 // One record in 48 bytes: what the blend and the projection backward read of it, gathered in
 // depth and tile order (three 16-byte loads per gathered record instead of one per plane). The
-// key emission's extra fields (footprint radius, tile count) are separate planes that live only
-// through the forward's sorting work space.
+// key emission forms the footprint radius from it (footprint_rho); its tile count is the step of
+// the offsets' scan.
 struct __align__(16) PackedRec {
     double2 mean;     // pixel-space mean
     double r;         // the conic's factor ratio (Shape)
@@ -125,7 +125,6 @@ struct Records {
     int32_t* radius;    // -1 when culled
     uint32_t* ntiles_plane;  // copy of ntiles for the caller
     // the forward's own planes, in its sorting work space
-    int32_t* rad;       // footprint radius, -1 when culled (read by the key emission)
     uint32_t* ntiles;   // tiles of the rectangle the footprint ellipse reaches
     uint32_t* dkey;     // depth sort key: float bits of depth, 0xffffffff when no tiles
     // initial values of the depth sort when non-null: record id r in the low order_idb bits and
@@ -140,6 +139,21 @@ struct Records {
 // 1e-4 absolute) so that FP32 rounding in the blend never reaches past a culled tile.
 __device__ __forceinline__ float cutoff_of(float o_eff) {
     return 2.004f * __logf(255.0f * o_eff) + 1e-4f;
+}
+
+// Footprint radius before rounding up: every pixel with alpha >= 1/255 lies within
+// rho = sqrt(2 ln(255 o) lmax) of the mean, lmax the larger eigenvalue of the 2D covariance. The
+// covariance is taken from the stored factors of its inverse (Shape): S_xx = (r / l22)^2 + 1 / l11^2,
+// S_yy = 1 / l22^2, det S = 1 / (l11 l22)^2, so the projection (which stores ceil(rho)) and the key
+// emission (which needs it for the tile rectangle) form the same radius from the same record, and
+// the emission need not gather a radius plane. Non-finite for a degenerate shape.
+__device__ __forceinline__ float footprint_rho(float l11, double r, float l22, float o_eff) {
+    const float il11 = 1.0f / l11, il22 = 1.0f / l22;
+    const float rq = (float)r * il22, d = il11 * il22;
+    const float sxx = __fmaf_rn(rq, rq, il11 * il11), syy = il22 * il22, det = d * d;
+    const float mid = 0.5f * (sxx + syy);
+    const float lmax = mid + sqrtf(fmaxf(__fmaf_rn(mid, mid, -det), 0.0f));
+    return sqrtf(2.0f * __logf(255.0f * o_eff) * lmax);
 }
 
 __device__ __forceinline__ float load_elem(const void* p, int dt, int64_t idx) {

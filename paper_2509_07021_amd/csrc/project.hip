@@ -218,11 +218,7 @@ __device__ __forceinline__ void project_view(const Geo& g, const Cov64& cv, cons
     const float Cf = (float)p.C, detf = (float)p.det;
     p.l11 = __builtin_amdgcn_sqrtf(Cf / detf);
     p.l22 = __builtin_amdgcn_rsqf(Cf);
-    const float Af = (float)p.A;
-    const float mid = 0.5f * (Af + Cf);
-    const float lmax = mid + sqrtf(fmaxf(mid * mid - detf, 0.0f));
-    const float rho = sqrtf(2.0f * __logf(255.0f * g.o_eff) * lmax);
-    const float rr = ceilf(rho);
+    const float rr = ceilf(footprint_rho(p.l11, p.r, p.l22, g.o_eff));
     if (!(isfinite(p.u) && isfinite(p.v) && isfinite(rr)) || fabs(p.u) > kMaxCoord || fabs(p.v) > kMaxCoord ||
         rr > (float)kMaxCoord)
         p.ok = false;
@@ -435,7 +431,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kProjectWav
         }
         rec.ntiles[r] = nt;
         if (rec.ntiles_plane) rec.ntiles_plane[r] = nt;
-        rec.rad[r] = ok ? p.radius : -1;
         if (sc.status) {  // culled records, one atomic per wave (the lanes here are the wave's Gaussians)
             const uint64_t culled = __ballot(!ok);
             if (culled && __lane_id() == (unsigned)__builtin_ctzll(__ballot(true)))

@@ -588,17 +588,15 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     const int64_t k = kb + perm[threadIdx.x];
     const bool has = k < n_records;
     const uint32_t g = has ? (order ? order[k] : (uint32_t)k) : 0u;
-    // the record: mean | factor ratio, diagonal factors | opacity (the colour is not needed here),
-    // and its footprint radius; records without tiles are not read
+    // the record: mean | factor ratio, diagonal factors | opacity (the colour is not needed here);
+    // records without tiles are not read
     const uint32_t nt = has ? s_nt[perm[threadIdx.x]] : 0u;
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;
     float o = 0.f;
-    int32_t rad = -1;
     if (nt) {
         const float4* q = reinterpret_cast<const float4*>(rec.packed + g);
         q0 = q[0]; q1 = q[1];
         o = reinterpret_cast<const float*>(q + 2)[0];
-        rad = rec.rad[g];
     }
     const int64_t off = has ? (int64_t)offsets[k] : 0;
     // windows past the table's capacity hold nothing that is written (an overflowed table)
@@ -618,6 +616,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
         const double mx = __hiloint2double(__float_as_int(q0.y), __float_as_int(q0.x));
         const double my = __hiloint2double(__float_as_int(q0.w), __float_as_int(q0.z));
         const double rr = __hiloint2double(__float_as_int(q1.y), __float_as_int(q1.x));
+        // the radius the projection stored for this record (a record with tiles has a finite one)
+        const int32_t rad = (int32_t)ceilf(footprint_rho(q1.z, rr, q1.w, o));
         tile_rect(mx, my, rad, vw, tile, x0, x1, y0, y1);
         ellipse_rows(mx, my, shape_of(q1.z, rr, q1.w), cutoff_of(o), er);
     }

@@ -50,10 +50,10 @@ def test_stage_bytes_follow_the_per_unit_counts():
     for st in STAGES_HBM:
         assert bench.stage_bytes(st, *args) > 0, st
     assert bench.stage_bytes("blend_bwd", *args) == 0  # the blends are counted in FLOPs
-    # parameters read once, per view a 48-byte record, its radius, tile count, depth key and sort value
-    assert bench.stage_bytes("project", *args) == n * gb + nr * 64
-    # order, offset, 36 bytes of the record and its radius per record; key and value per pair
-    assert bench.stage_bytes("emit", *args) == nr * 48 + pairs * 8
+    # parameters read once, per view a 48-byte record, its tile count, depth key and sort value
+    assert bench.stage_bytes("project", *args) == n * gb + nr * 60
+    # order, offset and 36 bytes of the record per record; key and value per pair
+    assert bench.stage_bytes("emit", *args) == nr * 44 + pairs * 8
     # one radix pass per 8 tile bits, each reading the keys twice and the values once, writing both
     assert bench.stage_bytes("pair_sort", *args, tile_bits=14) == 2 * pairs * 20
     assert bench.stage_bytes("pair_sort", *args, tile_bits=8) == pairs * 20
