@@ -52,9 +52,9 @@ FLOP_TEST, FLOP_FWD_BLEND, FLOP_BWD_BLEND = 15, 10, 30
 # when the counters were taken; a changed source reports traffic as null.
 TRAFFIC = {
     # 1M masked Gaussians, FP16, 8 x 1920x1080, 32x32 tiles, 8x8 sub-tile blending: FETCH_SIZE
-    # 2,172,908 KiB x 1.9998 (a 512 MiB copy read 262,167 KiB) + WRITE_SIZE 1,187,047 KiB x 1.0000
-    "blend_bwd": {"bytes": 5665256675,
-                  "source_sha256": "832e5079219fddd4167546ae17eb4345f372b8f130fae3afb8d91c7be652b371"},
+    # 2,173,395 KiB x 1.9998 (a 512 MiB copy read 262,167 KiB) + WRITE_SIZE 1,187,047 KiB x 1.0000
+    "blend_bwd": {"bytes": 5666252128,
+                  "source_sha256": "7c9dbb326179f52600e406b28a064c01c7630fbd32e397db7d3ae56f4519ed07"},
 }
 # VALU instructions per launch of the blend kernels on the same workload, from a rocprofv3 --pmc
 # SQ_INSTS_VALU run (per dispatch, averaged), with the SHA-256 of the source they were taken on (a
@@ -62,10 +62,10 @@ TRAFFIC = {
 # 1024 SIMDs at 2.4 GHz they give the issue time; set against the measured time it is the kernel's
 # VALU utilisation.
 VALU = {
-    "blend_fwd": {"instructions": 519785357,
-                  "source_sha256": "832e5079219fddd4167546ae17eb4345f372b8f130fae3afb8d91c7be652b371"},
-    "blend_bwd": {"instructions": 1203389756,
-                  "source_sha256": "832e5079219fddd4167546ae17eb4345f372b8f130fae3afb8d91c7be652b371"},
+    "blend_fwd": {"instructions": 512547725,
+                  "source_sha256": "7c9dbb326179f52600e406b28a064c01c7630fbd32e397db7d3ae56f4519ed07"},
+    "blend_bwd": {"instructions": 1196378670,
+                  "source_sha256": "7c9dbb326179f52600e406b28a064c01c7630fbd32e397db7d3ae56f4519ed07"},
 }
 SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4
 STAGE_SOURCE = {"project": "project.hip", "project_bwd": "project.hip", "blend_fwd": "blend.hip",

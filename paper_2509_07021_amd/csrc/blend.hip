@@ -621,7 +621,10 @@ __device__ __forceinline__ SubCtx sub_ctx(const BlendArgs& a, int64_t w, int til
     return q;
 }
 
-template <bool STATS, bool IMP>
+// FLAGS: the tile keys carry sub-tile flags (a.tkeys non-null), which decide which entries a
+// sub-tile keeps; without them each entry's footprint box is tested instead. A template argument, so
+// the flagged form (the default) carries no box code and no runtime test of the key pointer.
+template <bool STATS, bool IMP, bool FLAGS>
 __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int persistent) {
     constexpr int SUB = 8;
     __shared__ Kept lds[64];
@@ -647,7 +650,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
         uint32_t key_n = 0, id_n = 0;
         if (rg.x + lane < rg.y) {
             id_n = a.vals[rg.x + lane];
-            key_n = a.tkeys ? a.tkeys[rg.x + lane] : 0u;
+            key_n = FLAGS ? a.tkeys[rg.x + lane] : 0u;
         }
         for (uint32_t base = rg.x; base < rg.y; base += 64) {
             if (!__any(T > 0.0f)) break;
@@ -659,11 +662,11 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
             if (idx < rg.y) {
                 // the key's sub-tile flags, when present, decide before the record is gathered
                 g = gid;
-                const bool flagged = !a.tkeys || ((key >> (16 + q.sidx)) & 1u);
+                const bool flagged = !FLAGS || ((key >> (16 + q.sidx)) & 1u);
                 if (flagged) {
-                    stage(a, g, fx0, fy0, &st, !a.tkeys);
+                    stage(a, g, fx0, fy0, &st, !FLAGS);
                     // the flags already test the ellipse against the sub-tile; without them, its box
-                    hit = a.tkeys ? true : box_meets(st.box, 0, SUB - 1, 0, SUB - 1);
+                    hit = FLAGS ? true : box_meets(st.box, 0, SUB - 1, 0, SUB - 1);
                 }
             }
             const uint64_t m = __ballot(hit);
@@ -674,7 +677,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
             }
             if (idx + 64u < rg.y) {
                 id_n = a.vals[idx + 64u];
-                key_n = a.tkeys ? a.tkeys[idx + 64u] : 0u;
+                key_n = FLAGS ? a.tkeys[idx + 64u] : 0u;
             }
             wave_sync();
             for (int k0 = 0; k0 < nhit; k0 += 4) {
@@ -745,6 +748,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_sub(BlendArgs a, int tile, int
     }
 }
 
+template <bool FLAGS>  // as in k_blend_fwd_sub
 __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int persistent) {
     constexpr int SUB = 8;
     __shared__ Kept lds[64];
@@ -789,7 +793,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
         if ((uint32_t)lane < wave_last) {
             const uint32_t i0 = rg.x + wave_last - 1u - (uint32_t)lane;
             id_n = a.vals[i0];
-            key_n = a.tkeys ? a.tkeys[i0] : 0u;
+            key_n = FLAGS ? a.tkeys[i0] : 0u;
         }
         for (uint32_t end = rg.x + wave_last; end > rg.x;) {
             const uint32_t beg = end - rg.x > 64u ? end - 64u : rg.x;
@@ -801,11 +805,11 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             uint32_t g = 0;
             if ((uint32_t)lane < cnt) {
                 g = gid;
-                const bool flagged = !a.tkeys || ((key >> (16 + q.sidx)) & 1u);
+                const bool flagged = !FLAGS || ((key >> (16 + q.sidx)) & 1u);
                 if (flagged) {
-                    stage(a, g, fx0, fy0, &st, !a.tkeys);
+                    stage(a, g, fx0, fy0, &st, !FLAGS);
                     // the flags already test the ellipse against the sub-tile; without them, its box
-                    hit = a.tkeys ? true : box_meets(st.box, 0, SUB - 1, 0, SUB - 1);
+                    hit = FLAGS ? true : box_meets(st.box, 0, SUB - 1, 0, SUB - 1);
                 }
             }
             const uint64_t m = __ballot(hit);
@@ -816,7 +820,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_sub(BlendArgs a, int tile, int
             }
             if ((uint32_t)lane < beg - rg.x) {  // the next chunk: positions beg - 1 - lane downwards
                 id_n = a.vals[beg - 1u - (uint32_t)lane];
-                key_n = a.tkeys ? a.tkeys[beg - 1u - (uint32_t)lane] : 0u;
+                key_n = FLAGS ? a.tkeys[beg - 1u - (uint32_t)lane] : 0u;
             }
             wave_sync();
             for (int k = 0; k < nhit; ++k) {
@@ -893,16 +897,27 @@ hipError_t launch_bwd_t(const BlendArgs& a, int batch, bool persistent, hipStrea
     return hipGetLastError();
 }
 
+// The sub-tile flags' presence is a template argument, so the flagged form (the default) carries no
+// footprint-box code.
+template <bool STATS, bool IMP>
+void launch_fwd_sub_t(const BlendArgs& a, unsigned grid, int tile, bool persistent, hipStream_t stream) {
+    if (a.tkeys)
+        hipLaunchKernelGGL((k_blend_fwd_sub<STATS, IMP, true>), dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+    else
+        hipLaunchKernelGGL((k_blend_fwd_sub<STATS, IMP, false>), dim3(grid), dim3(64), 0, stream, a, tile,
+                           (int)persistent);
+}
+
 hipError_t launch_fwd_sub(const BlendArgs& a, int tile, bool persistent, hipStream_t stream) {
     const int64_t items = a.n_tiles * (int64_t)(tile / 8) * (tile / 8);
     const int64_t groups = persistent ? kPersistentGroups : items;
     const unsigned grid = (unsigned)(groups < items ? groups : items);
     if (a.importance)
-        hipLaunchKernelGGL((k_blend_fwd_sub<false, true>), dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+        launch_fwd_sub_t<false, true>(a, grid, tile, persistent, stream);
     else if (a.stats)
-        hipLaunchKernelGGL((k_blend_fwd_sub<true, false>), dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+        launch_fwd_sub_t<true, false>(a, grid, tile, persistent, stream);
     else
-        hipLaunchKernelGGL((k_blend_fwd_sub<false, false>), dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+        launch_fwd_sub_t<false, false>(a, grid, tile, persistent, stream);
     return hipGetLastError();
 }
 
@@ -910,7 +925,10 @@ hipError_t launch_bwd_sub(const BlendArgs& a, int tile, bool persistent, hipStre
     const int64_t items = a.n_tiles * (int64_t)(tile / 8) * (tile / 8);
     const int64_t groups = persistent ? kPersistentGroups : items;
     const unsigned grid = (unsigned)(groups < items ? groups : items);
-    hipLaunchKernelGGL(k_blend_bwd_sub, dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+    if (a.tkeys)
+        hipLaunchKernelGGL((k_blend_bwd_sub<true>), dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
+    else
+        hipLaunchKernelGGL((k_blend_bwd_sub<false>), dim3(grid), dim3(64), 0, stream, a, tile, (int)persistent);
     return hipGetLastError();
 }
 
