@@ -490,10 +490,18 @@ __device__ __forceinline__ void project_bwd_colour(const SceneDev& sc, const Vie
         glam[l] = 0.f; glm[l] = 0.f;
         gamp[l][0] = gamp[l][1] = gamp[l][2] = 0.f;
     }
+    // each view's three colour sums are loaded one view ahead, so their round trip overlaps the
+    // previous view's arithmetic
+    float gnext[3] = {0.f, 0.f, 0.f};
+    if (nv > 0 && lobes_ok)
+        for (int c = 0; c < 3; ++c) gnext[c] = sums_col[9 * i + c];
     for (int v = 0; v < nv && lobes_ok; ++v) {
         const ViewInfo& vw = views[v];
-        const int64_t r = (int64_t)v * n + i;
-        const float gcol[3] = {sums_col[9 * r], sums_col[9 * r + 1], sums_col[9 * r + 2]};
+        const float gcol[3] = {gnext[0], gnext[1], gnext[2]};
+        if (v + 1 < nv) {
+            const int64_t rn = (int64_t)(v + 1) * n + i;
+            for (int c = 0; c < 3; ++c) gnext[c] = sums_col[9 * rn + c];
+        }
         if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
         float d[3], dlen, rgb[3], e[KK], muh[KK][3], dd2[KK];
         bool clamped[3] = {false, false, false};
@@ -578,11 +586,25 @@ __device__ __forceinline__ void project_bwd_geometry(const SceneDev& sc, const V
     // yz, zz; full-matrix convention)
     float gpos[3] = {0.f, 0.f, 0.f}, H[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float gop = 0.f, gpm = 0.f;
+    // each view's record factors and six exponent sums are loaded one view ahead (all of them, a
+    // culled record's included: its sums are zero), so their round trip overlaps the previous view's
+    // arithmetic
+    float4 fq_next = make_float4(0.f, 0.f, 0.f, 0.f);
+    float gr_next[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (nv > 0) {
+        fq_next = reinterpret_cast<const float4*>(rec + i)[1];
+        for (int c = 0; c < 6; ++c) gr_next[c] = sums_exp[9 * i + c];
+    }
     for (int v = 0; v < nv; ++v) {
         const ViewInfo& vw = views[v];
-        const int64_t r = (int64_t)v * n + i;
         // the record's conic factors as the forward stored them (zero when the forward culled it)
-        const float4 fq = reinterpret_cast<const float4*>(rec + r)[1];
+        const float4 fq = fq_next;
+        const float gr[6] = {gr_next[0], gr_next[1], gr_next[2], gr_next[3], gr_next[4], gr_next[5]};
+        if (v + 1 < nv) {
+            const int64_t rn = (int64_t)(v + 1) * n + i;
+            fq_next = reinterpret_cast<const float4*>(rec + rn)[1];
+            for (int c = 0; c < 6; ++c) gr_next[c] = sums_exp[9 * rn + c];
+        }
         if (!(fq.w > 0.0f)) continue;
         ViewProj p;
         double T0d[3], T1d[3];
@@ -599,7 +621,6 @@ __device__ __forceinline__ void project_bwd_geometry(const SceneDev& sc, const V
         //   dL/dmean = (o_eff / kQ2) L S,  dL/dSigma = (o_eff / (2 kQ2^2)) L M L',
         // products of the factors only: no inverse, no determinant, nothing that cancels for a thin
         // footprint.
-        const float* gr = sums_exp + 9 * r;
         const float oe = g.o_eff;
         const float s1 = oe * (1.0f / kQ2), s2 = oe * (0.5f / (kQ2 * kQ2));
         const float gu = s1 * (l11 * gr[0]);
