@@ -156,6 +156,31 @@ __device__ __forceinline__ float footprint_rho(float l11, double r, float l22, f
     return sqrtf(2.0f * __logf(255.0f * o_eff) * lmax);
 }
 
+// N parameter elements of one storage type (element j: plane p[j], index idx[j]; 0 where live[j] is
+// false, and then not read), under one branch on the uniform storage type. FP32 elements are loaded
+// straight into out. FP16 and BF16 ones are all loaded as 16-bit words before any is converted:
+// converting each inside its load's branch (as load_elem does) makes the compiler wait for every
+// 16-bit load before it issues the next.
+template <int N>
+__device__ __forceinline__ void load_n(int dt, const void* const (&p)[N], const int64_t (&idx)[N],
+                                       const bool (&live)[N], float (&out)[N]) {
+    if (dt == MEGS_F32) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) out[j] = live[j] ? static_cast<const float*>(p[j])[idx[j]] : 0.0f;
+        return;
+    }
+    uint32_t h[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) h[j] = live[j] ? static_cast<const uint16_t*>(p[j])[idx[j]] : 0u;
+    if (dt == MEGS_F16) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) out[j] = __half2float(__ushort_as_half((unsigned short)h[j]));
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) out[j] = __uint_as_float(h[j] << 16);
+    }
+}
+
 __device__ __forceinline__ float load_elem(const void* p, int dt, int64_t idx) {
     if (dt == MEGS_F32) return static_cast<const float*>(p)[idx];
     if (dt == MEGS_F16) return __half2float(static_cast<const __half*>(p)[idx]);

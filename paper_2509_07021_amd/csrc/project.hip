@@ -6,8 +6,8 @@
 // every view are written. View-independent values (activations, 3D covariance, unit lobe axes,
 // base colour) are formed once per Gaussian. The camera-space position, the pixel mean and the
 // tile count (the row-interval test of the key emission) are computed in FP64, everything else in
-// FP32. The kernels are bound by the latency of their dependent arithmetic at the occupancy their
-// registers allow (four and three waves per SIMD). The forward with SG colour of up to four lobes is
+// FP32. Each group of parameter loads is issued together (load_n), and the kernels are bound by the
+// latency of their dependent arithmetic at the occupancy their registers allow (four waves per SIMD). The forward with SG colour of up to four lobes is
 // held to four waves per SIMD (128 registers): left to itself it takes 132 and runs three.
 //
 // Colour: c(d) = c0 + sum_k m_k a_k exp(lambda_k (mu_k . d - 1)) (SG lobe and colour equations,
@@ -46,13 +46,25 @@ __device__ __forceinline__ void rot_from_quat(const float q[4], float R[9]) {
     R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
 }
 
-// View-independent part: activations and the 3D covariance.
-__device__ __forceinline__ void load_geo(const SceneDev& sc, int64_t i, float pos[3], Geo& g) {
+// View-independent part: activations and the 3D covariance. The raw quaternion is returned in
+// q_raw for load_cov64. The twelve loads are one group (load_n).
+__device__ __forceinline__ void load_geo(const SceneDev& sc, int64_t i, float pos[3], Geo& g, float q_raw[4]) {
     const int64_t n = sc.n;
-    for (int j = 0; j < 3; ++j) pos[j] = load_elem(sc.pos, sc.dt_geom, j * n + i);
-    for (int j = 0; j < 3; ++j) g.s[j] = __expf(load_elem(sc.logscale, sc.dt_geom, j * n + i));
-    float q[4];
-    for (int j = 0; j < 4; ++j) q[j] = load_elem(sc.quat, sc.dt_geom, j * n + i);
+    const void* pl[12];
+    int64_t ix[12];
+    bool lv[12];
+    for (int j = 0; j < 12; ++j) lv[j] = true;
+    for (int j = 0; j < 3; ++j) { pl[j] = sc.pos; ix[j] = j * n + i; }
+    for (int j = 0; j < 3; ++j) { pl[3 + j] = sc.logscale; ix[3 + j] = j * n + i; }
+    for (int j = 0; j < 4; ++j) { pl[6 + j] = sc.quat; ix[6 + j] = j * n + i; }
+    pl[10] = sc.op_logit; ix[10] = i;
+    pl[11] = sc.pmask_logit; ix[11] = i; lv[11] = sc.pmask_logit != nullptr;
+    float f[12];
+    load_n(sc.dt_geom, pl, ix, lv, f);
+    for (int j = 0; j < 3; ++j) pos[j] = f[j];
+    for (int j = 0; j < 3; ++j) g.s[j] = __expf(f[3 + j]);
+    float* q = q_raw;
+    for (int j = 0; j < 4; ++j) q[j] = f[6 + j];
     float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     g.ok = (qq > 0.0f) && isfinite(qq);
     g.qnorm = sqrtf(qq);
@@ -68,8 +80,8 @@ __device__ __forceinline__ void load_geo(const SceneDev& sc, int64_t i, float po
     g.S3[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
     g.S3[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
     g.S3[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
-    g.o = sigmoidf(load_elem(sc.op_logit, sc.dt_geom, i));
-    g.mp = sc.pmask_logit ? sigmoidf(load_elem(sc.pmask_logit, sc.dt_geom, i)) : 1.0f;
+    g.o = sigmoidf(f[10]);
+    g.mp = sc.pmask_logit ? sigmoidf(f[11]) : 1.0f;
     g.o_eff = g.o * g.mp;
 }
 
@@ -82,21 +94,43 @@ struct Cov64 {
     float s[3];
 };
 
-__device__ __forceinline__ void load_cov64(const SceneDev& sc, int64_t i, Cov64& cv) {
-    const int64_t n = sc.n;
+// From the raw quaternion and the scales load_geo formed (the same values it would load again).
+__device__ __forceinline__ void load_cov64(const float q_raw[4], const float s[3], Cov64& cv) {
     double q[4], qq = 0.0;
     for (int j = 0; j < 4; ++j) {
-        q[j] = (double)load_elem(sc.quat, sc.dt_geom, j * n + i);
+        q[j] = (double)q_raw[j];
         qq = fma(q[j], q[j], qq);
     }
     const double inv = 1.0 / sqrt(qq);
     cv.w = q[0] * inv; cv.x = q[1] * inv; cv.y = q[2] * inv; cv.z = q[3] * inv;
-    for (int j = 0; j < 3; ++j) cv.s[j] = __expf(load_elem(sc.logscale, sc.dt_geom, j * n + i));
+    for (int j = 0; j < 3; ++j) cv.s[j] = s[j];
 }
 
 // Lobe slots at or past the Gaussian's count get zero mask and amplitude, so they add exactly +0.
+// Every lobe's loads are issued before any is converted.
 template <int K, bool RAGGED>
 __device__ __forceinline__ bool load_lobes(const SceneDev& sc, const LobeRef<RAGGED>& r, Lobes<K>& L) {
+    // per lobe: axis (3), sharpness and mask logit in the colour storage type; amplitude (3) in its own.
+    // A ragged Gaussian's slots past its count are not read.
+    constexpr int KK = K > 0 ? K : 1;
+    const void* pc[KK * 5];
+    const void* pm[KK * 3];
+    int64_t ic[KK * 5], im[KK * 3];
+    bool lc[KK * 5], lm[KK * 3];
+#pragma unroll
+    for (int l = 0; l < KK; ++l) {
+        const bool live = l < K && !(RAGGED && l >= r.cnt);
+        for (int c = 0; c < 3; ++c) {
+            pc[5 * l + c] = sc.axis; ic[5 * l + c] = live ? r.at3(l, c) : 0; lc[5 * l + c] = live;
+            pm[3 * l + c] = sc.amp; im[3 * l + c] = live ? r.at3(l, c) : 0; lm[3 * l + c] = live;
+        }
+        pc[5 * l + 3] = sc.sharp; ic[5 * l + 3] = live ? r.at1(l) : 0; lc[5 * l + 3] = live;
+        pc[5 * l + 4] = sc.lmask_logit; ic[5 * l + 4] = live ? r.at1(l) : 0;
+        lc[5 * l + 4] = live && sc.lmask_logit != nullptr;
+    }
+    float fc[KK * 5], fm[KK * 3];
+    load_n(sc.dt_color, pc, ic, lc, fc);
+    load_n(sc.dt_amp, pm, im, lm, fm);
     bool ok = true;
 #pragma unroll
     for (int l = 0; l < K; ++l) {
@@ -107,18 +141,16 @@ __device__ __forceinline__ bool load_lobes(const SceneDev& sc, const LobeRef<RAG
             L.amp[l][0] = L.amp[l][1] = L.amp[l][2] = 0.0f;
             continue;
         }
-        float a0 = load_elem(sc.axis, sc.dt_color, r.at3(l, 0));
-        float a1 = load_elem(sc.axis, sc.dt_color, r.at3(l, 1));
-        float a2 = load_elem(sc.axis, sc.dt_color, r.at3(l, 2));
+        const float a0 = fc[5 * l], a1 = fc[5 * l + 1], a2 = fc[5 * l + 2];
         float al2 = a0 * a0 + a1 * a1 + a2 * a2;
         const float ia = rsqrtf(al2);
         L.ia[l] = ia;
         L.mu[l][0] = a0 * ia; L.mu[l][1] = a1 * ia; L.mu[l][2] = a2 * ia;
         ok = ok && (al2 > 0.0f) && isfinite(al2);
-        L.lam[l] = load_elem(sc.sharp, sc.dt_color, r.at1(l));
+        L.lam[l] = fc[5 * l + 3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) L.amp[l][c] = load_elem(sc.amp, sc.dt_amp, r.at3(l, c));
-        L.m[l] = sc.lmask_logit ? sigmoidf(load_elem(sc.lmask_logit, sc.dt_color, r.at1(l))) : 1.0f;
+        for (int c = 0; c < 3; ++c) L.amp[l][c] = fm[3 * l + c];
+        L.m[l] = sc.lmask_logit ? sigmoidf(fc[5 * l + 4]) : 1.0f;
     }
     return ok;
 }
@@ -235,7 +267,12 @@ __device__ __forceinline__ void view_dir(const float pos[3], const ViewInfo& vw,
 
 // The base colour c0 of Gaussian i (view-independent; read once, before the view loop).
 __device__ __forceinline__ void load_base(const SceneDev& sc, int64_t i, float base[3]) {
-    for (int c = 0; c < 3; ++c) base[c] = load_elem(sc.base, sc.dt_color, c * sc.n + i);
+    const void* pl[3] = {sc.base, sc.base, sc.base};
+    const int64_t ix[3] = {i, sc.n + i, 2 * sc.n + i};
+    const bool lv[3] = {true, true, true};
+    float f[3];
+    load_n(sc.dt_color, pl, ix, lv, f);
+    for (int c = 0; c < 3; ++c) base[c] = f[c];
 }
 
 // The SG colour at d; returns false if not finite.
@@ -338,9 +375,16 @@ __device__ __forceinline__ bool sh_colour(const SceneDev& sc, int64_t i, const f
     sh_basis<D, false>(d, Y, dY);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+        const void* pl[M];
+        int64_t ix[M];
+        bool lv[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) { pl[m] = sc.sh; ix[m] = ((int64_t)m * 3 + c) * n + i; lv[m] = true; }
+        float f[M];  // the channel's coefficients, one group
+        load_n(sc.dt_color, pl, ix, lv, f);
         float acc = 0.5f;
 #pragma unroll
-        for (int m = 0; m < M; ++m) acc = __fmaf_rn(Y[m], load_elem(sc.sh, sc.dt_color, ((int64_t)m * 3 + c) * n + i), acc);
+        for (int m = 0; m < M; ++m) acc = __fmaf_rn(Y[m], f[m], acc);
         clamped[c] = acc < 0.0f;
         rgb[c] = clamped[c] ? 0.0f : acc;
     }
@@ -348,9 +392,9 @@ __device__ __forceinline__ bool sh_colour(const SceneDev& sc, int64_t i, const f
 }
 
 // Waves per SIMD the forward projection is compiled for: four with SG colour of up to four lobes
-// (four lobes fit in 128 registers with 12 bytes of spills, and ran 9% faster than at three waves
-// in 132 registers: 0.369 -> 0.336 ms on the 8-view 1080p workload), else what its registers give
-// (more lobes and the SH forms would spill far more).
+// (four lobes fit in 128 registers, and ran 9% faster than at three waves in 132 registers: 0.369 ->
+// 0.336 ms on the 8-view 1080p workload), else what its registers give (more lobes and the SH forms
+// would spill far more).
 template <int K, int SHD>
 constexpr int kProjectWaves = (SHD < 0 && K <= 4) ? 4 : 1;
 
@@ -361,9 +405,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kProjectWav
     if (i >= sc.n) return;
     float pos[3];
     Geo g;
-    load_geo(sc, i, pos, g);
+    float q_raw[4];
+    load_geo(sc, i, pos, g, q_raw);
     Cov64 cv;
-    load_cov64(sc, i, cv);
+    load_cov64(q_raw, g.s, cv);
     Lobes<K> L;
     LobeRef<RAGGED> lr;
     const bool lobes_ok = lobe_ref<RAGGED>(sc, i, K, lr) && load_lobes<K, RAGGED>(sc, lr, L);
@@ -475,7 +520,12 @@ __device__ __forceinline__ void project_bwd_colour(const SceneDev& sc, const Vie
     if (i >= sc.n) return;
     const int64_t n = sc.n;
     float pos[3];
-    for (int j = 0; j < 3; ++j) pos[j] = load_elem(sc.pos, sc.dt_geom, j * n + i);
+    {
+        const void* pl[3] = {sc.pos, sc.pos, sc.pos};
+        const int64_t ix[3] = {i, n + i, 2 * n + i};
+        const bool lv[3] = {true, true, true};
+        load_n(sc.dt_geom, pl, ix, lv, pos);
+    }
     Lobes<K> L;
     LobeRef<RAGGED> lr;
     const bool lobes_ok = lobe_ref<RAGGED>(sc, i, K, lr) && load_lobes<K, RAGGED>(sc, lr, L);
@@ -516,10 +566,17 @@ __device__ __forceinline__ void project_bwd_colour(const SceneDev& sc, const Vie
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float gc = clamped[c] ? 0.f : gcol[c];
+                const void* pl[SHM];
+                int64_t ix[SHM];
+                bool lv[SHM];
+#pragma unroll
+                for (int m = 0; m < SHM; ++m) { pl[m] = sc.sh; ix[m] = ((int64_t)m * 3 + c) * n + i; lv[m] = true; }
+                float fsh[SHM];  // the channel's coefficients, one group
+                load_n(sc.dt_color, pl, ix, lv, fsh);
 #pragma unroll
                 for (int m = 0; m < SHM; ++m) {
                     gsh[m][c] = __fmaf_rn(Y[m], gc, gsh[m][c]);
-                    const float w = gc * load_elem(sc.sh, sc.dt_color, ((int64_t)m * 3 + c) * n + i);
+                    const float w = gc * fsh[m];
                     gd[0] = __fmaf_rn(w, dY[m][0], gd[0]);
                     gd[1] = __fmaf_rn(w, dY[m][1], gd[1]);
                     gd[2] = __fmaf_rn(w, dY[m][2], gd[2]);
@@ -579,9 +636,10 @@ __device__ __forceinline__ void project_bwd_geometry(const SceneDev& sc, const V
     const int64_t n = sc.n;
     float pos[3];
     Geo g;
-    load_geo(sc, i, pos, g);
+    float q_raw[4];
+    load_geo(sc, i, pos, g, q_raw);
     Cov64 cv;
-    load_cov64(sc, i, cv);
+    load_cov64(q_raw, g.s, cv);
     // H = R' (dL/dSigma3) R, the 3D covariance's gradient in the Gaussian's own axes (xx, xy, xz, yy,
     // yz, zz; full-matrix convention)
     float gpos[3] = {0.f, 0.f, 0.f}, H[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -741,7 +799,9 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(SceneDev sc, const ViewI
     project_bwd_colour<0, false, SHD>(sc, views, nv, sums_col, G);
 }
 
-__global__ __launch_bounds__(256) void k_project_bwd_geo(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
+// held to four waves per SIMD: it fits in 128 registers without spills, where left to itself it takes
+// 130 and runs three
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_project_bwd_geo(SceneDev sc, const ViewInfo* __restrict__ views, int nv,
                                                          const float* __restrict__ sums_exp,
                                                          const PackedRec* __restrict__ rec, GradDev G) {
     project_bwd_geometry(sc, views, nv, sums_exp, rec, G);
