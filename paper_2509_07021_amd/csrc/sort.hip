@@ -166,10 +166,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce_packed(const uint3
                                                                      int64_t n, int idb, uint32_t* partial) {
     __shared__ uint64_t lds[4];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    uint64_t s = 0;
+    // every load first (lanes past the end read item 0, n >= 1), so they are in flight together
+    uint32_t w[kScanIpt];
+#pragma unroll
     for (int j = 0; j < kScanIpt; ++j) {
         const int64_t i = base + j * kScanThreads + threadIdx.x;
-        if (i < n) s += packed_count(order[i], ntiles, idb);
+        w[j] = order[i < n ? i : 0];
+    }
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanIpt; ++j) {
+        const int64_t i = base + j * kScanThreads + threadIdx.x;
+        if (i < n) s += packed_count(w[j], ntiles, idb);
     }
     const uint64_t total = block_sum64(s, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = sat32(total);
@@ -280,11 +288,19 @@ __global__ __launch_bounds__(kRsThreads) void k_radix_upsweep(const K* __restric
     const Chunk c = chunk_of(d_count, max_count);
     const int64_t i1 = c.t1 * kRsTile < c.n ? c.t1 * kRsTile : c.n;
     for (int64_t base = c.t0 * kRsTile + (int64_t)w * kWave * U; base < i1; base += (int64_t)kRsThreads * U) {
+        // every key load first (lanes past the end read the chunk's last key), so the U loads are in
+        // flight together; the digits after
+        K kv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t idx = base + u * kWave + lane;
+            kv[u] = keys[idx < i1 ? idx : i1 - 1];
+        }
         uint32_t d[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t idx = base + u * kWave + lane;
-            d[u] = idx < i1 ? digit_of(keys[idx], shift, mask) : 0xffffffffu;
+            d[u] = idx < i1 ? digit_of(kv[u], shift, mask) : 0xffffffffu;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
