@@ -18,7 +18,9 @@
  *   would drop below 1e-4 (that fragment is not blended); near plane from the camera; the
  *   Jacobian is evaluated at the direction clamped to 1.3x the half field of view; the
  *   footprint radius is ceil(sqrt(2 ln(255 o) lambda_max)) so that every pixel with
- *   alpha >= 1/255 lies inside the tile rectangle, and of that rectangle exactly the tiles are
+ *   alpha >= 1/255 lies inside the tile rectangle (lambda_max in FP32 from the record's stored
+ *   conic factors, so a radius can differ by one pixel from an FP64 evaluation where the root lies
+ *   within rounding of an integer), and of that rectangle exactly the tiles are
  *   listed whose pixel-centre box (the centres of the tile's pixels inside the image) the ellipse
  *   (p - m)' conic (p - m) <= k reaches, k = 2.004 ln(255 o) + 1e-4, slightly above the level
  *   2 ln(255 o) of alpha = 1/255 (see megs_state.cutoff); depth ties are ordered by record index.
@@ -201,7 +203,7 @@ typedef struct {
     const void *packed;
     const void *chol; /* see above (MEGS_FLAG_RECORD_PLANES only) */
     /* the forward's work space (device, work_bytes bytes; NULL in deterministic mode): it holds the
-     * depth sort, the scan, the key emission's planes (tile counts, footprint radius) and, when they
+     * depth sort, the scan, the key emission's tile counts and, when they
      * fit, the pair sort's alternate buffers; megs_render_backward takes its scratch from it when it is
      * large enough, so two backward calls on one state must not overlap (they would share it) */
     void *work;
