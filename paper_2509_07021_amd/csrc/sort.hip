@@ -782,44 +782,55 @@ __global__ void k_ranges(const K* __restrict__ keys, int shift, uint32_t tmask, 
     }
 }
 
-// The same for 32-bit keys, four consecutive keys per thread through one 16-byte load (the key
-// arrays are 256-byte aligned), plus the keys just before and after them: those are the
-// neighbouring lanes' last and first keys, taken by shuffles, and loaded only at the wave's ends.
+// The same for 32-bit keys, 4 V consecutive keys per thread through V 16-byte loads (the key arrays
+// are 256-byte aligned), all issued before any key is compared, plus the keys just before and after
+// them: those are the neighbouring lanes' last and first keys, taken by shuffles, and loaded only at
+// the wave's ends.
+template <int V>
 __global__ void k_ranges_u32x4(const uint32_t* __restrict__ keys, uint32_t tmask, const uint32_t* d_count,
                                int64_t max_count, uint2* __restrict__ ranges) {
+    constexpr int KPT = 4 * V;  // keys per thread
     int64_t n = (int64_t)*d_count;
     if (n > max_count) n = max_count;
-    const int64_t nq = (n + 3) / 4;
+    const int64_t nq = (n + KPT - 1) / KPT;
     const int lane = __lane_id();
     // whole waves take part in every iteration (the shuffles read the neighbouring lanes), lanes
     // past the end with no keys
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q - lane < nq; q += stride) {
-        const int64_t i0 = 4 * q;
-        uint32_t t[4] = {0u, 0u, 0u, 0u};
-        if (i0 + 4 <= n) {
-            const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
-            t[0] = v.x & tmask; t[1] = v.y & tmask; t[2] = v.z & tmask; t[3] = v.w & tmask;
+        const int64_t i0 = KPT * q;
+        uint32_t t[KPT];
+        if (i0 + KPT <= n) {
+            uint4 v[V];
+#pragma unroll
+            for (int u = 0; u < V; ++u) v[u] = reinterpret_cast<const uint4*>(keys + i0)[u];
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                t[4 * u] = v[u].x & tmask; t[4 * u + 1] = v[u].y & tmask;
+                t[4 * u + 2] = v[u].z & tmask; t[4 * u + 3] = v[u].w & tmask;
+            }
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) t[j] = i0 + j < n ? keys[i0 + j] & tmask : 0u;
+            for (int j = 0; j < KPT; ++j) t[j] = i0 + j < n ? keys[i0 + j] & tmask : 0u;
         }
-        uint32_t before = (uint32_t)__shfl_up((int)t[3], 1);
+        uint32_t before = (uint32_t)__shfl_up((int)t[KPT - 1], 1);
         uint32_t after = (uint32_t)__shfl_down((int)t[0], 1);
         if (lane == 0) before = i0 > 0 && i0 - 1 < n ? keys[i0 - 1] & tmask : 0u;
-        if (lane == kWave - 1) after = i0 + 4 < n ? keys[i0 + 4] & tmask : 0u;
+        if (lane == kWave - 1) after = i0 + KPT < n ? keys[i0 + KPT] & tmask : 0u;
         if (q >= nq) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < KPT; ++j) {
             const int64_t i = i0 + j;
             if (i >= n) break;
             const bool first = i == 0 || (j == 0 ? before : t[j - 1]) != t[j];
-            const bool last = i == n - 1 || (j == 3 ? after : t[j + 1]) != t[j];
+            const bool last = i == n - 1 || (j == KPT - 1 ? after : t[j + 1]) != t[j];
             if (first) ranges[t[j]].x = (uint32_t)i;
             if (last) ranges[t[j]].y = (uint32_t)(i + 1);
         }
     }
 }
+
+constexpr int kRangeVecs = 4;  // 16-byte vectors of tile keys per thread
 
 inline unsigned grid_for(int64_t count, int threads, int64_t cap = 65536) {
     int64_t b = (count + threads - 1) / threads;
@@ -927,8 +938,8 @@ hipError_t launch_emit(const Records& rec, const ViewInfo* views, int nv, int64_
 hipError_t launch_ranges_u32(const uint32_t* tile_keys, const uint32_t* d_count, int64_t max_count, uint2* ranges,
                              hipStream_t stream, uint32_t tmask) {
     if (max_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges_u32x4, dim3(grid_for((max_count + 3) / 4, 256)), dim3(256), 0, stream, tile_keys, tmask,
-                       d_count, max_count, ranges);
+    hipLaunchKernelGGL(k_ranges_u32x4<kRangeVecs>, dim3(grid_for((max_count + 4 * kRangeVecs - 1) / (4 * kRangeVecs), 256)),
+                       dim3(256), 0, stream, tile_keys, tmask, d_count, max_count, ranges);
     return hipGetLastError();
 }
 
