@@ -569,28 +569,48 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
     __shared__ uint32_t range[2];
     __shared__ uint32_t bucket[kBuckets];
     __shared__ uint16_t perm[kEmitThreads];
-    __shared__ uint32_t s_nt[kEmitThreads];
+    // per record of the workgroup (slot = its position in emission order): what the emission reads of
+    // it, gathered by the slot's own thread and taken by the thread that emits the record
+    __shared__ float4 s_q0[kEmitThreads], s_q1[kEmitThreads];
+    __shared__ uint4 s_meta[kEmitThreads];  // opacity bits, record id, tile count, offset
     const int64_t kb = (int64_t)blockIdx.x * kEmitThreads;
     const int64_t k_last = min(kb + kEmitThreads, n_records) - 1;
     {
-        // A lane's time is set by the record with the most rows and tiles in its wave, so the
-        // workgroup's records are dealt to lanes grouped by tile count (a counting sort in LDS).
-        // Which lane handles a record does not change what is written where.
-        // A record's tile count is the step of the exclusive scan to the next record (modulo 2^32,
-        // exact while the counts fit), read in emission order instead of gathered per record.
+        // A lane's time is set by the record with the most work in its wave, so the workgroup's
+        // records are dealt to lanes grouped by an estimate of their work (a counting sort in LDS):
+        // the tile rows the footprint's vertical extent spans (each costs a row test and, where the
+        // row lists tiles, four sub-row bands) and the tiles. Which lane handles a record does not
+        // change what is written where. A record's tile count is the step of the exclusive scan to the
+        // next record (modulo 2^32, exact while the counts fit), read in emission order.
         const int64_t k0 = kb + threadIdx.x;
-        uint32_t nt0 = 0;
+        uint32_t nt0 = 0, off0 = 0, g0 = 0, key = 0;
+        float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+        float ao = 0.f;
         if (k0 < n_records) {
-            nt0 = (k0 + 1 < n_records ? offsets[k0 + 1] : *total) - offsets[k0];
+            off0 = offsets[k0];
+            nt0 = (k0 + 1 < n_records ? offsets[k0 + 1] : *total) - off0;
             if (k0 == k_last) {
                 range[0] = offsets[kb];
-                range[1] = (uint32_t)((int64_t)offsets[k0] + nt0);
+                range[1] = (uint32_t)((int64_t)off0 + nt0);
+            }
+            if (nt0) {  // the record: mean | factor ratio, diagonal factors | opacity; without tiles not read
+                g0 = order ? order[k0] : (uint32_t)k0;
+                const float4* q = reinterpret_cast<const float4*>(rec.packed + g0);
+                a0 = q[0]; a1 = q[1];
+                ao = reinterpret_cast<const float*>(q + 2)[0];
+                const float my = (float)__hiloint2double(__float_as_int(a0.w), __float_as_int(a0.z));
+                const double rr = __hiloint2double(__float_as_int(a1.y), __float_as_int(a1.x));
+                const float rho = ceilf(footprint_rho(a1.z, rr, a1.w, ao)), it = 1.0f / (float)tile;
+                const int rows = (int)(floorf((my + rho) * it) - floorf((my - rho) * it)) + 1;
+                const uint32_t ur = (uint32_t)min(max(rows, 1), 64), ut = min(nt0, 64u);
+                key = min((60u * ur + 150u * min(ur, ut) + 12u * ut) / 24u, (uint32_t)kBuckets - 1u);
             }
         }
-        s_nt[threadIdx.x] = nt0;
+        s_q0[threadIdx.x] = a0;
+        s_q1[threadIdx.x] = a1;
+        s_meta[threadIdx.x] = make_uint4(__float_as_uint(ao), g0, nt0, off0);
         if (threadIdx.x < kBuckets) bucket[threadIdx.x] = 0u;
         __syncthreads();
-        const uint32_t key = min(nt0, (uint32_t)kBuckets - 1u);
         const uint32_t rank = atomicAdd(&bucket[key], 1u);
         __syncthreads();
         if (threadIdx.x < kBuckets) {  // one wave: exclusive scan of the bucket sizes
@@ -601,20 +621,14 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Records rec, const ViewIn
         perm[bucket[key] + rank] = (uint16_t)threadIdx.x;
         __syncthreads();
     }
-    const int64_t k = kb + perm[threadIdx.x];
+    const int slot = perm[threadIdx.x];
+    const int64_t k = kb + slot;
     const bool has = k < n_records;
-    const uint32_t g = has ? (order ? order[k] : (uint32_t)k) : 0u;
-    // the record: mean | factor ratio, diagonal factors | opacity (the colour is not needed here);
-    // records without tiles are not read
-    const uint32_t nt = has ? s_nt[perm[threadIdx.x]] : 0u;
-    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;
-    float o = 0.f;
-    if (nt) {
-        const float4* q = reinterpret_cast<const float4*>(rec.packed + g);
-        q0 = q[0]; q1 = q[1];
-        o = reinterpret_cast<const float*>(q + 2)[0];
-    }
-    const int64_t off = has ? (int64_t)offsets[k] : 0;
+    const uint4 meta = s_meta[slot];
+    const uint32_t g = meta.y, nt = has ? meta.z : 0u;
+    const float4 q0 = s_q0[slot], q1 = s_q1[slot];
+    const float o = __uint_as_float(meta.x);
+    const int64_t off = has ? (int64_t)meta.w : 0;
     // windows past the table's capacity hold nothing that is written (an overflowed table)
     const int64_t lo = range[0], hi = min((int64_t)range[1], capacity);
     if (has && nt && off + (int64_t)nt > capacity) status[1] = 1;
