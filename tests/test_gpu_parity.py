@@ -177,6 +177,16 @@ def test_reduced_precision_storage():
     _run_all_stages(scene, cams, R.Config(16, 64))
 
 
+def test_bf16_geometry_and_colour_storage():
+    """The other storage combination: geometry and colour planes in BF16, amplitudes in FP16 (each
+    parameter group is loaded and widened under its own type), in the benchmark's launch
+    configuration; the oracle reads the exact stored values."""
+    scene, cams = S.make_workload("clustered_200k_720p", n=20_000)
+    scene = scene.stored("bf16", "bf16", "f16")
+    cams = [S.crop_camera(cams[0], 320, 180)]
+    _run_all_stages(scene, cams, R.Config(32, 64, subtile=8), seed=4)
+
+
 def test_forward_is_deterministic():
     scene, cams = S.make_workload("small_2k_128px")
     a = gpu_run(scene, cams, R.Config(16, 64))
